@@ -1,0 +1,297 @@
+"""Recursive strong skeletonization with dense bookkeeping (oracle; test infrastructure).
+
+The whole scaled matrix A~ is kept as a dense array; every Schur-complement update is
+applied to it in place, so that any entry can be inspected at any time. This is the
+plainest possible form of the method of Sections 4.1-4.4 and 5.1-5.2:
+
+  for each level l = L, L-1, ..., 2 (finest first, Section 4.2):
+    for each level-l box B holding active DOFs, in the schedule below:
+      classify every other active DOF by the box that owns it (near N, far F = Q u P);
+      ID of the stacked matrix [A_QB ; A_BQ^T ; proxy outgoing ; proxy incoming]
+        (Section 5.1.3, simultaneous skeletonization) -> S, R, T;
+      elimination E, F with T, then L, U with the pivot block X_RR (Section 4.1,
+        eq. strong-skel-elim); the Schur complement is subtracted from A_{(S u N)(S u N)};
+      the redundant DOFs R become inactive.
+  the remaining active DOFs B_t form the top block, factored by dense LU (Section 4.2).
+
+Readings where the paper is silent (each is also listed in the design notes):
+  * Owners. At level l every active DOF is owned either by its level-l ancestor box or,
+    when its leaf is coarser than l, by that leaf (coarse leaves keep their points
+    active until their own level).
+  * Near/far split (Section 4.4, radius 5R/2 around B). With g the L-infinity gap
+    between B (side R) and the owner box, in units of R: N if g = 0 (touching),
+    Q if 0 < g < 2 (the owner meets the open cube of side 5R centred on B), P if
+    g >= 2. Every P point is then at distance >= 2.5R from the centre of B, on or
+    outside the proxy sphere. The cube is the sphere's bounding cube: it puts every box
+    that meets the sphere into Q.
+  * Boxes without far-field DOFs (Q and P empty) are not skeletonized at that level.
+  * Schedule within a level: by colour (ix mod 2) + 2 (iy mod 2) + 4 (iz mod 2), then by
+    Morton key. Same-colour boxes never touch, so none of them reads what another one
+    writes; their updates only add into shared near-near blocks.
+  * Proxy surface (Section 5.1, 5.2): sphere of radius rho = 2.5R about the centre of B,
+    n_gamma Fibonacci points, n_gamma = max(64, 2 (p+1)^2) with
+    p = ceil(log(1/eps) / log(rho/r_B)) + ceil(k 2 r_B), r_B = (sqrt 3 / 2) R. Proxy rows
+    carry the L2 weight s = sqrt(4 pi rho^2 / n_gamma).
+  * Outgoing proxy rows s K(y_l, x_j) sqrt(w_j) (source normal n_j); incoming proxy rows
+    s G(x_j, y_l) sqrt(w_j) (single layer only, Section 5.1.2). Transposes are plain,
+    not conjugate (Section 4.1, eq. proxy-split-1).
+  * DOF order inside a box: tree order (the octree's point order); near DOFs listed
+    owner by owner in tree order.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import dense, kernel
+from .idqr import interp_decomp
+from .tree import Tree, morton
+
+PROXY_RADIUS = 2.5
+
+
+def fibonacci_dirs(n):
+    """Unit vectors z_i = 1 - (2i+1)/n, phi_i = i pi (3 - sqrt 5)."""
+    i = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * i + 1.0) / n
+    phi = i * (math.pi * (3.0 - math.sqrt(5.0)))
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z])
+
+
+def proxy_count(side, k, eps):
+    """n_gamma for a box of side R (reading of Section 5.2's multipole estimate)."""
+    ratio = PROXY_RADIUS / (math.sqrt(3.0) / 2.0)
+    p = math.ceil(math.log(1.0 / eps) / math.log(ratio)) + math.ceil(k * math.sqrt(3.0) * side)
+    return max(64, 2 * (p + 1) ** 2)
+
+
+def colour(c):
+    return int(c[0] & 1) + 2 * int(c[1] & 1) + 4 * int(c[2] & 1)
+
+
+@dataclass
+class BoxFactor:
+    level: int
+    box: int
+    coord: tuple
+    R: np.ndarray      # redundant DOFs (global indices), in ID pivot order
+    S: np.ndarray      # skeleton DOFs, in ID pivot order
+    N: np.ndarray      # near DOFs
+    T: np.ndarray      # s x r interpolation matrix
+    XRR: np.ndarray    # pivot block
+    lu: tuple          # LU of XRR (scipy lu_factor)
+    Lp: np.ndarray     # X_{(S u N) R} X_RR^{-1}
+    Up: np.ndarray     # X_RR^{-1} X_{R (S u N)}
+    m: int
+    nq: int
+    ngamma: int
+
+    @property
+    def SN(self):
+        return np.concatenate([self.S, self.N])
+
+
+class RSSFactor:
+    """Dense-bookkeeping RS-S factorization of A~ (see module docstring)."""
+
+    def __init__(self, x, nrm, w, k, eta, eps, leaf_size=64, check_invariant=False,
+                 brute_force_check=False, use_proxy=True):
+        self.x = np.asarray(x, dtype=np.float64)
+        self.nrm = np.asarray(nrm, dtype=np.float64)
+        self.w = np.asarray(w, dtype=np.float64)
+        self.k, self.eta, self.eps = float(k), float(eta), float(eps)
+        self.n = self.x.shape[1]
+        self.tree = Tree(self.x, leaf_size)
+        A = dense.system_matrix(self.x, self.nrm, self.w, k, eta)
+        self.A0 = A.copy() if (check_invariant or brute_force_check) else None
+        self.factors: list[BoxFactor] = []
+        self.level_stats = []
+        self.bf_errors = []
+        self.invariant_checked = 0
+        active = np.ones(self.n, dtype=bool)
+        t = self.tree
+        rank = t.rank
+        for lev in range(t.nlevels - 1, 1, -1):
+            anc = self._owner_map(lev)
+            owner = anc[t.point_leaf]
+            processed = sorted(
+                {int(owner[i]) for i in np.nonzero(active)[0] if t.level[owner[i]] == lev},
+                key=lambda b: (colour(t.coord[b]), int(morton(*t.coord[b]))))
+            nproc = 0
+            for B in processed:
+                act = np.nonzero(active)[0]
+                own = owner[act]
+                ob = np.unique(own)
+                gaps = self._gaps(lev, t.coord[B], ob)
+                idxB = self._sorted(act[own == B], rank)
+                near_owners = [int(o) for o, g in zip(ob, gaps) if g == 0 and o != B]
+                q_owners = [int(o) for o, g in zip(ob, gaps) if g == 1]
+                p_any = any(g >= 2 for g in gaps)
+                near_owners.sort(key=lambda o: rank[t.pts[o]].min() if t.pts[o].size else 0)
+                q_owners.sort(key=lambda o: rank[t.pts[o]].min() if t.pts[o].size else 0)
+                idxN = np.concatenate([self._sorted(act[own == o], rank) for o in near_owners]
+                                      ) if near_owners else np.zeros(0, np.int64)
+                idxQ = np.concatenate([self._sorted(act[own == o], rank) for o in q_owners]
+                                      ) if q_owners else np.zeros(0, np.int64)
+                idxP = act[np.isin(own, [o for o, g in zip(ob, gaps) if g >= 2])]
+                if idxQ.size == 0 and not p_any:
+                    continue
+                if check_invariant and idxP.size:
+                    ok = (np.array_equal(A[np.ix_(idxP, idxB)], self.A0[np.ix_(idxP, idxB)])
+                          and np.array_equal(A[np.ix_(idxB, idxP)], self.A0[np.ix_(idxB, idxP)]))
+                    if not ok:
+                        raise AssertionError(f"far-field block of box {B} was modified")
+                    self.invariant_checked += 1
+                blocks = []
+                if idxQ.size:
+                    blocks.append(A[np.ix_(idxQ, idxB)])
+                    blocks.append(A[np.ix_(idxB, idxQ)].T)
+                ng = 0
+                if p_any and use_proxy:
+                    pout, pin, ng = self.proxy_rows(B, idxB)
+                    blocks += [pout, pin]
+                elif p_any:
+                    blocks.append(A[np.ix_(idxP, idxB)])
+                    blocks.append(A[np.ix_(idxB, idxP)].T)
+                M = np.vstack(blocks)
+                Spos, Rpos, T = interp_decomp(M, self.eps)
+                if brute_force_check and idxP.size:
+                    F = np.concatenate([idxQ, idxP])
+                    full = np.vstack([A[np.ix_(F, idxB)], A[np.ix_(idxB, F)].T])
+                    err = np.linalg.norm(full[:, Rpos] - full[:, Spos] @ T, 2) if Rpos.size else 0.0
+                    self.bf_errors.append((B, err / np.linalg.norm(full, 2), Spos.size, idxB.size))
+                nproc += 1
+                if Rpos.size == 0:
+                    continue
+                f = self._eliminate(A, lev, B, idxB[Rpos], idxB[Spos], idxN, T, M.shape[0], ng)
+                f.nq = int(idxQ.size)
+                self.factors.append(f)
+                active[f.R] = False
+            self.level_stats.append((lev, nproc, int(active.sum())))
+        self.top = self._sorted(np.nonzero(active)[0], rank)
+        self.Att = A[np.ix_(self.top, self.top)].copy()
+        self.top_lu = sla.lu_factor(self.Att, check_finite=False)
+        self.A = A
+
+    # -- helpers ----------------------------------------------------------------------
+    @staticmethod
+    def _sorted(idx, rank):
+        return idx[np.argsort(rank[idx], kind="stable")]
+
+    def _owner_map(self, lev):
+        """For every box id: the level-`lev` ancestor of a box at level >= lev; itself
+        otherwise (used on leaves only)."""
+        t = self.tree
+        nb = len(t.level)
+        anc = np.arange(nb)
+        for b in range(nb):
+            a = b
+            while t.level[a] > lev:
+                a = t.parent[a]
+            anc[b] = a
+        return anc
+
+    def _gaps(self, lev, c, owners):
+        t = self.tree
+        lv = t.level[owners]
+        sh = (lev - lv)
+        lo = t.coord[owners] << sh[:, None]
+        hi = (t.coord[owners] + 1) << sh[:, None]
+        c = np.asarray(c)
+        g = np.maximum(lo - (c + 1), c - hi).max(axis=1)
+        return np.maximum(g, 0)
+
+    def proxy_rows(self, B, idxB):
+        """Outgoing and incoming proxy blocks (Section 5.1.1-5.1.3)."""
+        t = self.tree
+        side = t.box_side(B)
+        ctr = t.box_centre(B)
+        rho = PROXY_RADIUS * side
+        ng = proxy_count(side, self.k, self.eps)
+        y = ctr[:, None] + rho * fibonacci_dirs(ng)
+        sg = math.sqrt(4.0 * math.pi * rho * rho / ng)
+        xb, nb, swb = self.x[:, idxB], self.nrm[:, idxB], np.sqrt(self.w[idxB])
+        pout = sg * kernel.cfie(y, xb, nb, self.k, self.eta) * swb[None, :]
+        pin = sg * kernel.green(y, xb, self.k) * swb[None, :]
+        return pout, pin, ng
+
+    def _eliminate(self, A, lev, B, R, S, N, T, mrows, ng):
+        """Section 4.1: E, F from T, then L, U from X_RR; Schur update in place."""
+        ARR, ARS, ASR, ASS = (A[np.ix_(R, R)], A[np.ix_(R, S)], A[np.ix_(S, R)], A[np.ix_(S, S)])
+        ARN, ANR, ASN, ANS = (A[np.ix_(R, N)], A[np.ix_(N, R)], A[np.ix_(S, N)], A[np.ix_(N, S)])
+        Tt = T.T
+        XRR = ARR - Tt @ ASR - ARS @ T + Tt @ ASS @ T
+        XRS = ARS - Tt @ ASS
+        XSR = ASR - ASS @ T
+        XRN = ARN - Tt @ ASN
+        XNR = ANR - ANS @ T
+        XR_SN = np.hstack([XRS, XRN])
+        XSN_R = np.vstack([XSR, XNR])
+        lu = sla.lu_factor(XRR, check_finite=False)
+        if np.any(np.diag(lu[0]) == 0):
+            raise np.linalg.LinAlgError(f"singular pivot block at box {B}")
+        Up = sla.lu_solve(lu, XR_SN, check_finite=False)
+        Lp = sla.lu_solve(lu, XSN_R.T, trans=1, check_finite=False).T
+        SN = np.concatenate([S, N])
+        A[np.ix_(SN, SN)] -= XSN_R @ Up
+        return BoxFactor(lev, B, tuple(int(v) for v in self.tree.coord[B]), R, S, N, T, XRR, lu,
+                         Lp, Up, R.size + S.size, 0, ng)
+
+    # -- application of the factors (Section 4.2) ----------------------------------------
+    def solve(self, b):
+        """x = A_f^{-1} b: V_1^{-1} ... V_M^{-1} in box order (E then L), D^{-1},
+        then W_M^{-1} ... W_1^{-1} in reverse order (U then F)."""
+        x = np.array(b, dtype=np.complex128, copy=True)
+        for f in self.factors:
+            x[f.R] -= f.T.T @ x[f.S]
+            x[f.SN] -= f.Lp @ x[f.R]
+        for f in self.factors:
+            x[f.R] = sla.lu_solve(f.lu, x[f.R], check_finite=False)
+        x[self.top] = sla.lu_solve(self.top_lu, x[self.top], check_finite=False)
+        for f in reversed(self.factors):
+            x[f.R] -= f.Up @ x[f.SN]
+            x[f.S] -= f.T @ x[f.R]
+        return x
+
+    def solve_adjoint(self, b):
+        """x = A_f^{-H} b = V_1^{-H} ... V_M^{-H} D^{-H} W_M^{-H} ... W_1^{-H} b."""
+        x = np.array(b, dtype=np.complex128, copy=True)
+        for f in self.factors:
+            x[f.R] -= f.T.conj().T @ x[f.S]
+            x[f.SN] -= f.Up.conj().T @ x[f.R]
+        for f in self.factors:
+            x[f.R] = sla.lu_solve(f.lu, x[f.R], trans=2, check_finite=False)
+        x[self.top] = sla.lu_solve(self.top_lu, x[self.top], trans=2, check_finite=False)
+        for f in reversed(self.factors):
+            x[f.R] -= f.Lp.conj().T @ x[f.SN]
+            x[f.S] -= f.T.conj() @ x[f.R]
+        return x
+
+    def apply(self, v):
+        """A_f v = V_1 ... V_M D W_M ... W_1 v (the factored approximation of A~)."""
+        x = np.array(v, dtype=np.complex128, copy=True)
+        for f in self.factors:
+            x[f.S] += f.T @ x[f.R]
+            x[f.R] += f.Up @ x[f.SN]
+        for f in self.factors:
+            x[f.R] = f.XRR @ x[f.R]
+        x[self.top] = self.Att @ x[self.top]
+        for f in reversed(self.factors):
+            x[f.SN] += f.Lp @ x[f.R]
+            x[f.R] += f.T.T @ x[f.S]
+        return x
+
+    @property
+    def n0(self):
+        return int(self.top.size)
+
+    def factor_entries(self):
+        """Stored complex entries (T, X_RR, L and U panels, top block)."""
+        tot = self.top.size ** 2
+        for f in self.factors:
+            tot += f.T.size + f.XRR.size + f.Lp.size + f.Up.size
+        return tot

@@ -1,0 +1,102 @@
+"""Pins of the oracle's recursive strong skeletonization (CPU only).
+
+Checked against what the paper fixes rather than against itself:
+  * whole solve vs dense partial-pivoting LU, relative error <= 10 eps (Section 4.2's
+    factored inverse is eps-accurate);
+  * the factored operator A_f = V_1..V_M D W_M..W_1 reproduces A~ to O(eps);
+  * adjoint solve: <A_f^{-1} b, c> = <b, A_f^{-H} c> to rounding, and vs dense A~^{-H};
+  * Section 4.4's invariant: the P-blocks A_PB, A_BP hold unmodified kernel entries when
+    B is compressed;
+  * Section 4.3/5.1: the proxy ID is as accurate for the full far-field block
+    [A_FB ; A_BF^T] as the requested tolerance (brute force against all of F);
+  * special cases: a single leaf (no compression) and a tolerance near machine
+    precision reduce to dense LU.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, rss
+
+
+def _rhs(s):
+    return np.sqrt(s.weights) * synth.point_source_data(s.points, s.k)
+
+
+def test_solve_matches_dense_lu(sphere3k, sphere3k_dense, sphere3k_rss):
+    s = sphere3k
+    _, lu = sphere3k_dense
+    b = _rhs(s)
+    xs = lu.solve(b)
+    x = sphere3k_rss.solve(b)
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 10 * s.eps
+
+
+def test_structure(sphere3k_rss):
+    f = sphere3k_rss
+    assert f.tree.nlevels >= 3
+    assert len(f.factors) > 0
+    assert f.n0 < f.n
+    for fa in f.factors:
+        assert fa.R.size + fa.S.size == fa.m
+        assert np.intersect1d(fa.R, fa.N).size == 0
+        assert fa.T.shape == (fa.S.size, fa.R.size)
+
+
+def test_factored_operator_reproduces_matrix(sphere3k, sphere3k_dense, sphere3k_rss):
+    a, _ = sphere3k_dense
+    v = np.random.default_rng(3).standard_normal(sphere3k.n) * (1 - 2j)
+    av = a @ v
+    assert np.linalg.norm(sphere3k_rss.apply(v) - av) / np.linalg.norm(av) <= 10 * sphere3k.eps
+
+
+def test_adjoint(sphere3k, sphere3k_dense, sphere3k_rss):
+    _, lu = sphere3k_dense
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(sphere3k.n) + 1j * rng.standard_normal(sphere3k.n)
+    c = rng.standard_normal(sphere3k.n) + 1j * rng.standard_normal(sphere3k.n)
+    f = sphere3k_rss
+    lhs = np.vdot(c, f.solve(b))
+    rhs = np.vdot(f.solve_adjoint(c), b)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    xa = f.solve_adjoint(c)
+    xs = lu.solve_adjoint(c)
+    assert np.linalg.norm(xa - xs) / np.linalg.norm(xs) <= 10 * sphere3k.eps
+
+
+def test_far_field_invariant_and_proxy_accuracy(sphere3k_rss):
+    f = sphere3k_rss
+    assert f.invariant_checked > 50
+    errs = np.array([e[1] for e in f.bf_errors])
+    assert errs.size > 50
+    assert errs.max() <= 3 * f.eps
+
+
+def test_single_leaf_is_dense_lu():
+    s = synth.unit_sphere(60)
+    f = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps)
+    assert len(f.factors) == 0 and f.n0 == 60
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    b = _rhs(s)
+    xs = np.linalg.solve(a, b)
+    assert np.linalg.norm(f.solve(b) - xs) / np.linalg.norm(xs) < 1e-13
+
+
+def test_tight_tolerance_is_nearly_exact():
+    s = synth.unit_sphere(800, eps=1e-13)
+    f = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, 1e-13, leaf_size=16)
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    b = _rhs(s)
+    xs = np.linalg.solve(a, b)
+    assert np.linalg.norm(f.solve(b) - xs) / np.linalg.norm(xs) < 1e-11
+
+
+def test_graded_ellipsoid_small():
+    s = synth.graded_ellipsoid(2500, seed=2, k=3.0, eps=1e-6)
+    f = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, leaf_size=32,
+                      check_invariant=True)
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    b = _rhs(s)
+    xs = np.linalg.solve(a, b)
+    assert len(f.factors) > 20
+    assert np.linalg.norm(f.solve(b) - xs) / np.linalg.norm(xs) <= 10 * s.eps
