@@ -1,0 +1,186 @@
+/*
+ * fmmlu.h -- C ABI of the MI355X (gfx950) FMM-LU library.
+ *
+ * FMM-LU (Sushnikova, Greengard, O'Neil, Rachh) factors the dense Nystrom matrix of the
+ * 3-D Helmholtz combined-field integral equation by recursive strong skeletonization over
+ * a level-restricted adaptive octree (Sections 4.1-4.4), with far fields compressed
+ * against proxy spheres (Sections 5.1-5.2). The system solved is the square-root-weighted
+ * one of Section 3, eq. (disc3), with plain smooth weights w_j and alpha = 1/2:
+ *
+ *     A~_ii = 1/2,   A~_ij = sqrt(w_i) K(x_i, x_j) sqrt(w_j)  (i != j),
+ *     K(x, y) = n(y) . grad_y G(x, y) - i eta G(x, y),   G = e^{ik|x-y|} / (4 pi |x-y|)
+ *
+ * (eq. comb_ref with the single-layer coupling k generalised to eta), acting on
+ * sigma~ = sqrt(w) sigma with right-hand side b~ = sqrt(w) f.
+ *
+ * Conventions for every entry point:
+ *   - Return value is an fmmlu_status; 0 means success. No function throws, aborts or
+ *     exits across this boundary. On failure fmmlu_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Geometry (points, normals, weights) is HOST memory, structure-of-arrays float64:
+ *     xyz[0..n) = x, xyz[n..2n) = y, xyz[2n..3n) = z. The library copies what it keeps;
+ *     the caller keeps ownership.
+ *   - Vectors passed to solve / matvec are DEVICE memory, complex128 interleaved
+ *     (re, im), column-major n x nrhs, in the caller's original point order. They are
+ *     read and written on the caller's HIP stream (hip_stream == NULL means the null
+ *     stream); calls return once the work is enqueued unless stated otherwise.
+ *   - Handles are opaque and owned by the caller; destroy functions accept NULL.
+ *   - A GPU runtime error is reported as FMMLU_EHIP with the HIP error string.
+ */
+#ifndef FMMLU_H
+#define FMMLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FMMLU_OK = 0,
+  FMMLU_EINVAL = -1,     /* invalid argument: sizes, NaN/Inf, non-positive weight, duplicate point, ... */
+  FMMLU_ENOMEM = -2,     /* device or host allocation failed, or the configured memory cap was exceeded */
+  FMMLU_EHIP = -3,       /* HIP runtime error */
+  FMMLU_ESINGULAR = -4,  /* a pivot block X_RR or the top block is numerically singular */
+  FMMLU_ENOCONV = -5,    /* iterative refinement did not reach the tolerance */
+  FMMLU_ESTATE = -6      /* handle in the wrong state (e.g. NULL factor) */
+} fmmlu_status;
+
+typedef enum {
+  FMMLU_FP64 = 0,  /* complex float64 tiles, factors and solves */
+  FMMLU_FP32 = 1   /* complex float32 tiles and factors; ID and pivot blocks in float64 */
+} fmmlu_precision;
+
+typedef struct fmmlu_tree_s* fmmlu_tree_h;
+typedef struct fmmlu_factor_s* fmmlu_factor_h;
+
+/* Options of fmmlu_factor. Fill with fmmlu_default_opts() first. */
+typedef struct {
+  double eps;                 /* ID tolerance, relative (Section 4.1 Definition); in (0, 0.1] */
+  double proxy_radius;        /* proxy sphere radius in units of the box side (Section 4.4: 2.5) */
+  int32_t proxy_min_points;   /* floor on proxy points per sphere (64) */
+  int32_t precision;          /* fmmlu_precision */
+  int64_t device_mem_cap;     /* bytes of device memory the factorization may hold; 0 = no cap */
+  int32_t verbose;            /* 0 silent, 1 per-level summary on stderr */
+  int32_t reserved[7];
+} fmmlu_opts;
+
+/* Per-factorization statistics. */
+typedef struct {
+  int64_t n;                  /* unknowns */
+  int64_t n0;                 /* size of the top block B_t (Section 4.2) */
+  int32_t nlevels;            /* octree levels, root = 0 */
+  int32_t nboxes_factored;    /* boxes whose redundant DOFs were eliminated */
+  int64_t factor_bytes;       /* device bytes held by the factors */
+  int64_t peak_bytes;         /* peak device bytes during the factorization */
+  int32_t max_rank;           /* largest skeleton size |S| */
+  int32_t max_block;          /* largest active DOF count m of a box */
+  double t_tree, t_factor;    /* seconds (host wall clock, device synchronised) */
+  double flops_id, flops_elim, flops_schur, flops_top;  /* algorithmic flop counts */
+  double bytes_tiles;         /* bytes of pair tiles generated or merged */
+  int32_t precision;
+  int32_t reserved[7];
+} fmmlu_info;
+
+/* Fill *opts with defaults: eps 1e-6, proxy_radius 2.5, proxy_min_points 64, FP64. */
+fmmlu_status fmmlu_default_opts(fmmlu_opts* opts);
+
+/*
+ * Build the level-restricted adaptive octree (Section 4, opening): root cube centred on
+ * the points' bounding box with side (largest extent)*(1 + 1e-12); a box is split into
+ * eight while it holds more than leaf_size points; leaves that share a boundary point
+ * are then brought to within one level of each other by splitting the coarser one.
+ * xyz: host, 3*n doubles (SoA). n >= 1, leaf_size >= 1. Points must be finite and
+ * pairwise distinct (FMMLU_EINVAL otherwise). Host-only work.
+ */
+fmmlu_status fmmlu_build_tree(const double* xyz, int64_t n, int32_t leaf_size, fmmlu_tree_h* out);
+
+/* Tree description for inspection: number of boxes, levels and leaves. Any output
+ * pointer may be NULL. */
+fmmlu_status fmmlu_tree_info(fmmlu_tree_h t, int64_t* nboxes, int32_t* nlevels, int64_t* nleaves);
+
+/* Export the boxes: for box b, level[b], coord[3b..3b+2] (integer coordinates at its level),
+ * npts[b] and is_leaf[b]; and the tree order of the points: order[i] = original index of
+ * the i-th point in tree order (leaves by the Morton key of their lower corner, then by
+ * original index). Host arrays sized by fmmlu_tree_info. Any pointer may be NULL. */
+fmmlu_status fmmlu_tree_export(fmmlu_tree_h t, int32_t* level, int32_t* coord, int32_t* npts,
+                               int8_t* is_leaf, int64_t* order);
+
+void fmmlu_tree_destroy(fmmlu_tree_h t);
+
+/*
+ * Factor A~ by recursive strong skeletonization (Sections 4.1-4.4, 5.1-5.3 without
+ * quadrature corrections) on the GPU of the calling thread's current HIP device.
+ * The tree must have been built from the same points. normals: host 3*n unit vectors
+ * (outward), weights: host n positive doubles. k >= 0 (k = 0 is the Laplace limit),
+ * eta any finite real. The factor keeps its own device copy of the geometry and does
+ * not reference the tree afterwards. Synchronises hip_stream before returning.
+ * Errors: EINVAL (bad sizes/values), ENOMEM, EHIP, ESINGULAR.
+ */
+fmmlu_status fmmlu_factor(fmmlu_tree_h t, const double* xyz, const double* normals,
+                          const double* weights, double k, double eta, const fmmlu_opts* opts,
+                          void* hip_stream, fmmlu_factor_h* out);
+
+/*
+ * x = A_f^{-1} b with the factored inverse of Section 4.2:
+ * A^{-1} ~ (W_1^{-1} ... W_M^{-1}) P_t D^{-1} P_t^T (V_M^{-1} ... V_1^{-1}).
+ * b, x: device complex128, n x nrhs column-major (may alias: in-place is allowed).
+ */
+fmmlu_status fmmlu_solve(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs, void* hip_stream);
+
+/* x = A_f^{-H} b (conjugate transpose of the factored inverse; same layout as fmmlu_solve). */
+fmmlu_status fmmlu_solve_adjoint(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs,
+                                 void* hip_stream);
+
+/*
+ * Exact float64 product with the scaled system matrix, entries generated on the fly
+ * (Section 3, eq. disc3): op 0: y = A~ x; 1: y = A~^H x; 2: y = (dA~/dk) x; 3: y = (dA~/deta) x.
+ * x, y: device complex128 vectors of length n, original point order; must not alias.
+ */
+fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, void* hip_stream);
+
+/*
+ * Iterative refinement (Section 7's use of a low-precision direct solver as a
+ * preconditioner): right-preconditioned restarted GMRES in float64 on A~ (adjoint != 0:
+ * on A~^H) with the exact matvec above, preconditioned by fmmlu_solve (fmmlu_solve_adjoint).
+ * b, x: device complex128 vectors of length n. x is overwritten. Stops when
+ * ||b - A~ x|| <= tol ||b|| or after maxit iterations (FMMLU_ENOCONV; *relres and *iters
+ * still reported). Synchronises the stream.
+ */
+fmmlu_status fmmlu_solve_refined(fmmlu_factor_h f, const void* b, void* x, int32_t adjoint,
+                                 double tol, int32_t maxit, int32_t* iters, double* relres,
+                                 void* hip_stream);
+
+/* Statistics of a finished factorization. */
+fmmlu_status fmmlu_factor_info(fmmlu_factor_h f, fmmlu_info* out);
+
+/*
+ * Per-box record of the factorization for inspection, in elimination order.
+ * fmmlu_factor_boxes(f, &count, NULL, ...) returns the count in *count. Otherwise, for record r:
+ * level[r], coord[3r..3r+2], m[r] (active DOFs), s[r] (skeleton size). skel, when not
+ * NULL, receives for all records the skeleton DOFs as original point indices, sorted,
+ * concatenated in record order (sum of s entries).
+ */
+fmmlu_status fmmlu_factor_boxes(fmmlu_factor_h f, int64_t* count, int32_t* level, int32_t* coord,
+                                int32_t* m, int32_t* s, int64_t* skel);
+
+void fmmlu_factor_destroy(fmmlu_factor_h f);
+
+/*
+ * Kernel-block generation on the device (the entry generator the factorization uses):
+ * out[i + j*nr] = A~[rows[i], cols[j]] for i < nr, j < nc, complex128, with the diagonal
+ * value 1/2 where rows[i] == cols[j]. xyz, nrm: device SoA 3*n doubles; w: device n
+ * doubles; rows, cols, out: device. For testing and for callers that assemble blocks.
+ */
+fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const double* w, int64_t n,
+                                double k, double eta, const int64_t* rows, int64_t nr,
+                                const int64_t* cols, int64_t nc, void* out, void* hip_stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* fmmlu_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMMLU_H */

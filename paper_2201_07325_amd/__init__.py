@@ -1,0 +1,267 @@
+"""MI355X (gfx950) FMM-LU: recursive strong skeletonization of the Helmholtz CFIE.
+
+Thin ctypes binding of the C ABI declared in include/fmmlu.h. Every step of the
+factorization and of the solves runs in the HIP library libfmmlu.so; this module only
+marshals arguments. PyTorch provides device memory and the current HIP stream.
+
+The library is required: importing works without it, but every call raises
+RuntimeError if libfmmlu.so has not been built (python -m paper_2201_07325_amd.build).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+__all__ = ["lib", "Tree", "Factor", "kernel_block", "FmmluError", "STATUS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmmlu.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "fmmlu.h")
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENOCONV", -6: "ESTATE"}
+
+
+class FmmluError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+
+
+class Opts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("proxy_radius", C.c_double), ("proxy_min_points", C.c_int32),
+                ("precision", C.c_int32), ("device_mem_cap", C.c_int64), ("verbose", C.c_int32),
+                ("reserved", C.c_int32 * 7)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n0", C.c_int64), ("nlevels", C.c_int32),
+                ("nboxes_factored", C.c_int32), ("factor_bytes", C.c_int64), ("peak_bytes", C.c_int64),
+                ("max_rank", C.c_int32), ("max_block", C.c_int32), ("t_tree", C.c_double),
+                ("t_factor", C.c_double), ("flops_id", C.c_double), ("flops_elim", C.c_double),
+                ("flops_schur", C.c_double), ("flops_top", C.c_double), ("bytes_tiles", C.c_double),
+                ("precision", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+P = C.c_void_p
+I64 = C.c_int64
+I32 = C.c_int32
+D = C.c_double
+PD = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load libfmmlu.so (raises RuntimeError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2201_07325_amd.build")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "fmmlu_default_opts": (I32, [C.POINTER(Opts)]),
+        "fmmlu_build_tree": (I32, [PD, I64, I32, C.POINTER(P)]),
+        "fmmlu_tree_info": (I32, [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I64)]),
+        "fmmlu_tree_export": (I32, [P, P, P, P, P, P]),
+        "fmmlu_tree_destroy": (None, [P]),
+        "fmmlu_factor": (I32, [P, PD, PD, PD, D, D, C.POINTER(Opts), P, C.POINTER(P)]),
+        "fmmlu_solve": (I32, [P, P, P, I64, P]),
+        "fmmlu_solve_adjoint": (I32, [P, P, P, I64, P]),
+        "fmmlu_matvec": (I32, [P, I32, P, P, P]),
+        "fmmlu_solve_refined": (I32, [P, P, P, I32, D, I32, C.POINTER(I32), PD, P]),
+        "fmmlu_factor_info": (I32, [P, C.POINTER(Info)]),
+        "fmmlu_factor_boxes": (I32, [P, C.POINTER(I64), P, P, P, P, P]),
+        "fmmlu_factor_destroy": (None, [P]),
+        "fmmlu_kernel_block": (I32, [P, P, P, I64, D, D, P, I64, P, I64, P, P]),
+        "fmmlu_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions declared in include/fmmlu.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmmlu_[a-z_]+)\s*\(", txt)))
+
+
+def _check(status):
+    if status != 0:
+        msg = lib().fmmlu_last_error().decode(errors="replace")
+        raise FmmluError(status, msg)
+
+
+def _soa(a, n=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.ndim == 2 and a.shape[0] != 3 and a.shape[1] == 3:
+        a = np.ascontiguousarray(a.T)
+    if n is not None and a.size != 3 * n:
+        raise ValueError("expected 3*n values")
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(PD)
+
+
+class Tree:
+    """Level-restricted adaptive octree (host). points: (3, n) float64."""
+
+    def __init__(self, points, leaf_size=64):
+        self.points = _soa(points)
+        self.n = self.points.shape[-1] if self.points.ndim == 2 else self.points.size // 3
+        h = P()
+        _check(lib().fmmlu_build_tree(_ptr(self.points), self.n, int(leaf_size), C.byref(h)))
+        self.h = h
+        self.leaf_size = int(leaf_size)
+
+    def info(self):
+        nb, nl, nleaf = I64(), I32(), I64()
+        _check(lib().fmmlu_tree_info(self.h, C.byref(nb), C.byref(nl), C.byref(nleaf)))
+        return int(nb.value), int(nl.value), int(nleaf.value)
+
+    def export(self):
+        nb, nl, _ = self.info()
+        level = np.zeros(nb, np.int32)
+        coord = np.zeros((nb, 3), np.int32)
+        npts = np.zeros(nb, np.int32)
+        leaf = np.zeros(nb, np.int8)
+        order = np.zeros(self.n, np.int64)
+        _check(lib().fmmlu_tree_export(self.h, level.ctypes.data, coord.ctypes.data, npts.ctypes.data,
+                                       leaf.ctypes.data, order.ctypes.data))
+        return {"level": level, "coord": coord, "npts": npts, "is_leaf": leaf.astype(bool),
+                "order": order, "nlevels": nl}
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.fmmlu_tree_destroy(h)
+            self.h = None
+
+
+def _stream():
+    import torch
+    return P(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_c128(x, n):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex128):
+        raise TypeError("expected a complex128 CUDA tensor")
+    if x.shape[0] != n:
+        raise ValueError(f"leading dimension {x.shape[0]} != n = {n}")
+    return x
+
+
+class Factor:
+    """FMM-LU factorization of the scaled CFIE matrix on the current GPU.
+
+    points, normals: (3, n) float64; weights: (n,) positive. Solves take and return
+    complex128 CUDA tensors of shape (n,) or (n, nrhs) in the original point order.
+    """
+
+    def __init__(self, points, normals, weights, k, eta, eps=1e-6, leaf_size=64, tree=None,
+                 proxy_radius=2.5, proxy_min_points=64, precision=0, verbose=0, mem_cap=0):
+        L = lib()
+        self.points = _soa(points)
+        self.n = self.points.size // 3
+        self.normals = _soa(normals, self.n)
+        self.weights = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        if self.weights.size != self.n:
+            raise ValueError("weights must have n entries")
+        self.k, self.eta, self.eps = float(k), float(eta), float(eps)
+        self.tree = tree if tree is not None else Tree(self.points, leaf_size)
+        o = Opts()
+        _check(L.fmmlu_default_opts(C.byref(o)))
+        o.eps = self.eps
+        o.proxy_radius = float(proxy_radius)
+        o.proxy_min_points = int(proxy_min_points)
+        o.precision = int(precision)
+        o.verbose = int(verbose)
+        o.device_mem_cap = int(mem_cap)
+        h = P()
+        _check(L.fmmlu_factor(self.tree.h, _ptr(self.points), _ptr(self.normals), _ptr(self.weights),
+                              self.k, self.eta, C.byref(o), _stream(), C.byref(h)))
+        self.h = h
+
+    def _apply(self, fn, b, out=None):
+        import torch
+        b = _dev_c128(b, self.n)
+        squeeze = b.dim() == 1
+        bb = b.reshape(self.n, -1)
+        nrhs = bb.shape[1]
+        # column-major n x nrhs: column c contiguous
+        bcol = bb.t().contiguous()
+        x = torch.empty_like(bcol)
+        _check(fn(self.h, P(bcol.data_ptr()), P(x.data_ptr()), nrhs, _stream()))
+        x = x.t()
+        return x.reshape(self.n) if squeeze else x.contiguous()
+
+    def solve(self, b):
+        """x = A_f^{-1} b."""
+        return self._apply(lib().fmmlu_solve, b)
+
+    def solve_adjoint(self, b):
+        """x = A_f^{-H} b."""
+        return self._apply(lib().fmmlu_solve_adjoint, b)
+
+    def matvec(self, x, op=0):
+        """Exact float64 product: op 0 A~, 1 A~^H, 2 dA~/dk, 3 dA~/deta."""
+        import torch
+        x = _dev_c128(x, self.n).contiguous()
+        y = torch.empty_like(x)
+        _check(lib().fmmlu_matvec(self.h, int(op), P(x.data_ptr()), P(y.data_ptr()), _stream()))
+        return y
+
+    def info(self):
+        inf = Info()
+        _check(lib().fmmlu_factor_info(self.h, C.byref(inf)))
+        return inf.as_dict()
+
+    def boxes(self):
+        cnt = I64()
+        _check(lib().fmmlu_factor_boxes(self.h, C.byref(cnt), None, None, None, None, None))
+        c = int(cnt.value)
+        level = np.zeros(c, np.int32)
+        coord = np.zeros((c, 3), np.int32)
+        m = np.zeros(c, np.int32)
+        s = np.zeros(c, np.int32)
+        _check(lib().fmmlu_factor_boxes(self.h, C.byref(cnt), level.ctypes.data, coord.ctypes.data,
+                                        m.ctypes.data, s.ctypes.data, None))
+        skel = np.zeros(int(s.sum()), np.int64)
+        _check(lib().fmmlu_factor_boxes(self.h, C.byref(cnt), None, None, None, None, skel.ctypes.data))
+        return {"level": level, "coord": coord, "m": m, "s": s, "skel": skel}
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.fmmlu_factor_destroy(h)
+            self.h = None
+
+
+def kernel_block(points, normals, weights, k, eta, rows, cols):
+    """A~[rows, cols] generated on the device; returns a complex128 CUDA tensor (nr, nc)."""
+    import torch
+    pts = torch.as_tensor(_soa(points)).reshape(-1).cuda()
+    n = pts.numel() // 3
+    nrm = torch.as_tensor(_soa(normals, n)).reshape(-1).cuda()
+    w = torch.as_tensor(np.asarray(weights, np.float64)).cuda()
+    r = torch.as_tensor(np.asarray(rows, np.int64)).cuda()
+    c = torch.as_tensor(np.asarray(cols, np.int64)).cuda()
+    out = torch.empty((c.numel(), r.numel()), dtype=torch.complex128, device="cuda")
+    _check(lib().fmmlu_kernel_block(P(pts.data_ptr()), P(nrm.data_ptr()), P(w.data_ptr()), n, float(k),
+                                    float(eta), P(r.data_ptr()), r.numel(), P(c.data_ptr()), c.numel(),
+                                    P(out.data_ptr()), _stream()))
+    return out.t()

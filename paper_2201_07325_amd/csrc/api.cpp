@@ -1,0 +1,311 @@
+// C ABI of the library: argument validation, handle management, error translation.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmlu.h"
+#include "common.hpp"
+#include "factor.hpp"
+#include "kernels.hpp"
+#include "tree.hpp"
+
+using namespace fmmlu;
+
+struct fmmlu_tree_s {
+  Octree t;
+  std::vector<double> xyz;  // copy of the points (for consistency checks in factor)
+  double t_build = 0;
+};
+
+struct fmmlu_factor_s {
+  FactorImpl f;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fmmlu_status fail(fmmlu_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+template <class F>
+fmmlu_status guarded(F&& fn) {
+  try {
+    g_last_error.clear();
+    fn();
+    return FMMLU_OK;
+  } catch (const Error& e) {
+    return fail(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(FMMLU_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FMMLU_EINVAL, e.what());
+  } catch (...) {
+    return fail(FMMLU_EINVAL, "unknown error");
+  }
+}
+
+void check_finite(const double* v, int64_t cnt, const char* what) {
+  for (int64_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(v[i])) throw Error(FMMLU_EINVAL, std::string(what) + " contains NaN or Inf");
+}
+
+}  // namespace
+
+extern "C" {
+
+fmmlu_status fmmlu_default_opts(fmmlu_opts* opts) {
+  if (!opts) return fail(FMMLU_EINVAL, "opts is NULL");
+  std::memset(opts, 0, sizeof(*opts));
+  opts->eps = 1e-6;
+  opts->proxy_radius = 2.5;
+  opts->proxy_min_points = 64;
+  opts->precision = FMMLU_FP64;
+  opts->device_mem_cap = 0;
+  opts->verbose = 0;
+  return FMMLU_OK;
+}
+
+fmmlu_status fmmlu_build_tree(const double* xyz, int64_t n, int32_t leaf_size, fmmlu_tree_h* out) {
+  if (!out) return fail(FMMLU_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!xyz) return fail(FMMLU_EINVAL, "xyz is NULL");
+  if (n < 1) return fail(FMMLU_EINVAL, "n must be >= 1");
+  if (n > INT32_MAX) return fail(FMMLU_EINVAL, "n must fit in int32");
+  if (leaf_size < 1) return fail(FMMLU_EINVAL, "leaf_size must be >= 1");
+  return guarded([&] {
+    check_finite(xyz, 3 * n, "points");
+    auto t0 = std::chrono::steady_clock::now();
+    auto* h = new fmmlu_tree_s;
+    try {
+      h->t.build(xyz, n, leaf_size);
+      // duplicate points share a full-depth key; compare coordinates within equal keys
+      const auto& ms = h->t.msort;
+      for (int64_t i = 1; i < n; ++i) {
+        if (h->t.key[ms[i]] != h->t.key[ms[i - 1]]) continue;
+        for (int64_t j = i - 1; j >= 0 && h->t.key[ms[j]] == h->t.key[ms[i]]; --j) {
+          const int64_t a = ms[i], b = ms[j];
+          if (xyz[a] == xyz[b] && xyz[n + a] == xyz[n + b] && xyz[2 * n + a] == xyz[2 * n + b])
+            throw Error(FMMLU_EINVAL, "duplicate points " + std::to_string(b) + " and " + std::to_string(a));
+        }
+      }
+      h->xyz.assign(xyz, xyz + 3 * n);
+      h->t_build = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+fmmlu_status fmmlu_tree_info(fmmlu_tree_h t, int64_t* nboxes, int32_t* nlevels, int64_t* nleaves) {
+  if (!t) return fail(FMMLU_ESTATE, "tree is NULL");
+  if (nboxes) *nboxes = t->t.nboxes();
+  if (nlevels) *nlevels = t->t.nlevels;
+  if (nleaves) {
+    int64_t c = 0;
+    for (int64_t b = 0; b < t->t.nboxes(); ++b) c += t->t.is_leaf((int)b);
+    *nleaves = c;
+  }
+  return FMMLU_OK;
+}
+
+fmmlu_status fmmlu_tree_export(fmmlu_tree_h t, int32_t* level, int32_t* coord, int32_t* npts,
+                               int8_t* is_leaf, int64_t* order) {
+  if (!t) return fail(FMMLU_ESTATE, "tree is NULL");
+  const Octree& o = t->t;
+  for (int64_t b = 0; b < o.nboxes(); ++b) {
+    if (level) level[b] = o.level[b];
+    if (coord) {
+      coord[3 * b] = o.cx[b];
+      coord[3 * b + 1] = o.cy[b];
+      coord[3 * b + 2] = o.cz[b];
+    }
+    if (npts) npts[b] = (int32_t)o.npts((int)b);
+    if (is_leaf) is_leaf[b] = o.is_leaf((int)b) ? 1 : 0;
+  }
+  if (order)
+    for (int64_t i = 0; i < o.n; ++i) order[i] = o.order[i];
+  return FMMLU_OK;
+}
+
+void fmmlu_tree_destroy(fmmlu_tree_h t) { delete t; }
+
+fmmlu_status fmmlu_factor(fmmlu_tree_h t, const double* xyz, const double* normals,
+                          const double* weights, double k, double eta, const fmmlu_opts* opts,
+                          void* hip_stream, fmmlu_factor_h* out) {
+  if (!out) return fail(FMMLU_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!t) return fail(FMMLU_ESTATE, "tree is NULL");
+  if (!xyz || !normals || !weights) return fail(FMMLU_EINVAL, "geometry pointer is NULL");
+  fmmlu_opts o;
+  if (opts)
+    o = *opts;
+  else
+    fmmlu_default_opts(&o);
+  if (!(o.eps > 0.0 && o.eps <= 0.1)) return fail(FMMLU_EINVAL, "eps must be in (0, 0.1]");
+  if (!(k >= 0.0) || !std::isfinite(k)) return fail(FMMLU_EINVAL, "k must be finite and >= 0");
+  if (!std::isfinite(eta)) return fail(FMMLU_EINVAL, "eta must be finite");
+  if (!(o.proxy_radius >= 1.5 && o.proxy_radius <= 10.0))
+    return fail(FMMLU_EINVAL, "proxy_radius must be in [1.5, 10]");
+  if (o.proxy_min_points < 1) return fail(FMMLU_EINVAL, "proxy_min_points must be >= 1");
+  if (o.precision != FMMLU_FP64) return fail(FMMLU_EINVAL, "only FMMLU_FP64 is available in this build");
+  const int64_t n = t->t.n;
+  return guarded([&] {
+    check_finite(xyz, 3 * n, "points");
+    check_finite(normals, 3 * n, "normals");
+    check_finite(weights, n, "weights");
+    if (std::memcmp(xyz, t->xyz.data(), sizeof(double) * 3 * n) != 0)
+      throw Error(FMMLU_EINVAL, "points differ from those the tree was built from");
+    for (int64_t i = 0; i < n; ++i) {
+      if (!(weights[i] > 0.0)) throw Error(FMMLU_EINVAL, "weights must be positive");
+      const double nn = normals[i] * normals[i] + normals[n + i] * normals[n + i] +
+                        normals[2 * n + i] * normals[2 * n + i];
+      if (std::fabs(nn - 1.0) > 1e-6) throw Error(FMMLU_EINVAL, "normals must be unit vectors");
+    }
+    auto* h = new fmmlu_factor_s;
+    try {
+      FMMLU_HIP(hipGetDevice(&h->f.device));
+      h->f.k = k;
+      h->f.eta = eta;
+      h->f.opts = o;
+      h->f.factor(t->t, xyz, normals, weights, static_cast<hipStream_t>(hip_stream));
+      h->f.info.t_tree = t->t_build;
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+fmmlu_status fmmlu_solve(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs, void* hip_stream) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  if (!b || !x) return fail(FMMLU_EINVAL, "vector pointer is NULL");
+  if (nrhs < 1) return fail(FMMLU_EINVAL, "nrhs must be >= 1");
+  return guarded([&] {
+    f->f.solve(static_cast<const zd*>(b), static_cast<zd*>(x), nrhs, false,
+               static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+fmmlu_status fmmlu_solve_adjoint(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs,
+                                 void* hip_stream) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  if (!b || !x) return fail(FMMLU_EINVAL, "vector pointer is NULL");
+  if (nrhs < 1) return fail(FMMLU_EINVAL, "nrhs must be >= 1");
+  return guarded([&] {
+    f->f.solve(static_cast<const zd*>(b), static_cast<zd*>(x), nrhs, true,
+               static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, void* hip_stream) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  if (!x || !y) return fail(FMMLU_EINVAL, "vector pointer is NULL");
+  if (x == y) return fail(FMMLU_EINVAL, "x and y must not alias");
+  if (op < 0 || op > 3) return fail(FMMLU_EINVAL, "op must be 0..3");
+  return guarded([&] {
+    FactorImpl& F = f->f;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (!F.wx) {
+      F.wx = F.arena.alloc_n<zd>((size_t)F.n);
+      F.wy = F.arena.alloc_n<zd>((size_t)std::max<int64_t>(F.ymax, 1));
+      F.wtop = F.arena.alloc_n<zd>((size_t)std::max(F.n0, 1));
+    }
+    if (!F.wmv) F.wmv = F.arena.alloc_n<zd>((size_t)F.n);
+    zd* tin = F.wmv;
+    // permute in, apply, permute out (tree order inside)
+    launch_permute(static_cast<const zd*>(x), tin, F.order_dev, F.n, 1, st);
+    launch_matvec(F.g, op, tin, F.wx, st);
+    launch_permute(F.wx, static_cast<zd*>(y), F.order_dev, F.n, 0, st);
+    FMMLU_HIP(hipStreamSynchronize(st));
+  });
+}
+
+fmmlu_status fmmlu_solve_refined(fmmlu_factor_h f, const void* b, void* x, int32_t adjoint, double tol,
+                                 int32_t maxit, int32_t* iters, double* relres, void* hip_stream) {
+  (void)b;
+  (void)x;
+  (void)adjoint;
+  (void)tol;
+  (void)maxit;
+  (void)iters;
+  (void)relres;
+  (void)hip_stream;
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  return fail(FMMLU_EINVAL, "fmmlu_solve_refined is not available in this build");
+}
+
+fmmlu_status fmmlu_factor_info(fmmlu_factor_h f, fmmlu_info* out) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  if (!out) return fail(FMMLU_EINVAL, "out is NULL");
+  *out = f->f.info;
+  return FMMLU_OK;
+}
+
+fmmlu_status fmmlu_factor_boxes(fmmlu_factor_h f, int64_t* count, int32_t* level, int32_t* coord,
+                                int32_t* m, int32_t* s, int64_t* skel) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  const auto& bx = f->f.boxes;
+  if (count) *count = (int64_t)bx.size();
+  int64_t pos = 0;
+  for (size_t r = 0; r < bx.size(); ++r) {
+    if (level) level[r] = bx[r].level;
+    if (coord)
+      for (int a = 0; a < 3; ++a) coord[3 * r + a] = bx[r].coord[a];
+    if (m) m[r] = bx[r].m;
+    if (s) s[r] = bx[r].s;
+    if (skel)
+      for (int64_t v : bx[r].skel_orig) skel[pos++] = v;
+  }
+  return FMMLU_OK;
+}
+
+void fmmlu_factor_destroy(fmmlu_factor_h f) { delete f; }
+
+fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const double* w, int64_t n,
+                                double k, double eta, const int64_t* rows, int64_t nr,
+                                const int64_t* cols, int64_t nc, void* out, void* hip_stream) {
+  if (!xyz || !nrm || !w || !rows || !cols || !out) return fail(FMMLU_EINVAL, "NULL pointer");
+  if (n < 1 || nr < 0 || nc < 0) return fail(FMMLU_EINVAL, "bad sizes");
+  return guarded([&] {
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // pack SoA geometry with sqrt(w) on the device (original order)
+    DeviceArena a(size_t(8) << 20);
+    double* p = a.alloc_n<double>(7 * (size_t)n);
+    FMMLU_HIP(hipMemcpyAsync(p, xyz, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+    FMMLU_HIP(hipMemcpyAsync(p + 3 * n, nrm, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+    std::vector<double> hw(n), hs(n);
+    FMMLU_HIP(hipMemcpyAsync(hw.data(), w, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    FMMLU_HIP(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < n; ++i) {
+      if (!(hw[i] > 0.0)) throw Error(FMMLU_EINVAL, "weights must be positive");
+      hs[i] = std::sqrt(hw[i]);
+    }
+    FMMLU_HIP(hipMemcpyAsync(p + 6 * n, hs.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    // indices must address the geometry: checked on the host before any kernel reads them
+    std::vector<int64_t> hr(nr), hc(nc);
+    if (nr) FMMLU_HIP(hipMemcpyAsync(hr.data(), rows, sizeof(int64_t) * nr, hipMemcpyDeviceToHost, st));
+    if (nc) FMMLU_HIP(hipMemcpyAsync(hc.data(), cols, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, st));
+    FMMLU_HIP(hipStreamSynchronize(st));
+    for (int64_t v : hr)
+      if (v < 0 || v >= n) throw Error(FMMLU_EINVAL, "row index out of range");
+    for (int64_t v : hc)
+      if (v < 0 || v >= n) throw Error(FMMLU_EINVAL, "column index out of range");
+    DevGeom g{p, n, k, eta};
+    launch_block(g, rows, nr, cols, nc, static_cast<zd*>(out), st);
+    FMMLU_HIP(hipStreamSynchronize(st));
+  });
+}
+
+const char* fmmlu_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

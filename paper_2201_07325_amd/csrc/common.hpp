@@ -1,0 +1,147 @@
+// Shared host/device definitions of the FMM-LU library: complex arithmetic, error
+// handling, and a bump-pointer device arena.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fmmlu.h"
+
+namespace fmmlu {
+
+// ---------------------------------------------------------------------------------
+// complex float64 (interleaved, 16-byte aligned; same layout as std::complex<double>)
+struct alignas(16) zd {
+  double re, im;
+};
+struct alignas(8) zf {
+  float re, im;
+};
+
+__host__ __device__ inline zd zmake(double r, double i) { return zd{r, i}; }
+__host__ __device__ inline zd zadd(zd a, zd b) { return zd{a.re + b.re, a.im + b.im}; }
+__host__ __device__ inline zd zsub(zd a, zd b) { return zd{a.re - b.re, a.im - b.im}; }
+__host__ __device__ inline zd zmul(zd a, zd b) {
+  return zd{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__host__ __device__ inline zd zconj(zd a) { return zd{a.re, -a.im}; }
+__host__ __device__ inline zd zscale(zd a, double s) { return zd{a.re * s, a.im * s}; }
+__host__ __device__ inline double zabs2(zd a) { return a.re * a.re + a.im * a.im; }
+// acc += a * b
+__host__ __device__ inline void zfma(zd& acc, zd a, zd b) {
+  acc.re += a.re * b.re - a.im * b.im;
+  acc.im += a.re * b.im + a.im * b.re;
+}
+// acc += conj(a) * b
+__host__ __device__ inline void zfmac(zd& acc, zd a, zd b) {
+  acc.re += a.re * b.re + a.im * b.im;
+  acc.im += a.re * b.im - a.im * b.re;
+}
+__host__ __device__ inline zd zdiv(zd a, zd b) {
+  // Smith's algorithm
+  if (fabs(b.re) >= fabs(b.im)) {
+    double r = b.im / b.re, d = b.re + b.im * r;
+    return zd{(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  } else {
+    double r = b.re / b.im, d = b.im + b.re * r;
+    return zd{(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// errors: thrown inside the library, converted to fmmlu_status at the C boundary
+struct Error : std::runtime_error {
+  fmmlu_status status;
+  Error(fmmlu_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define FMMLU_HIP(call)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::fmmlu::Error(FMMLU_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define FMMLU_REQUIRE(cond, status, msg)                        \
+  do {                                                          \
+    if (!(cond)) throw ::fmmlu::Error(status, std::string(msg)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------------
+// Device arena: large chunks, bump allocation, 256-byte alignment, freed together.
+class DeviceArena {
+ public:
+  explicit DeviceArena(size_t chunk = size_t(256) << 20) : chunk_(chunk) {}
+  ~DeviceArena() { release(); }
+  DeviceArena(const DeviceArena&) = delete;
+  DeviceArena& operator=(const DeviceArena&) = delete;
+
+  void* alloc(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (cur_ < chunks_.size() && used_ + bytes <= sizes_[cur_]) {
+      void* p = static_cast<char*>(chunks_[cur_]) + used_;
+      used_ += bytes;
+      total_ += bytes;
+      return p;
+    }
+    // advance to the next existing chunk that fits, else allocate a new one
+    while (cur_ + 1 < chunks_.size()) {
+      ++cur_;
+      used_ = 0;
+      if (bytes <= sizes_[cur_]) return alloc(bytes);
+    }
+    size_t sz = bytes > chunk_ ? bytes : chunk_;
+    if (cap_ && held_ + sz > cap_)
+      throw Error(FMMLU_ENOMEM, "device memory cap exceeded (" + std::to_string(held_ + sz) +
+                                    " > " + std::to_string(cap_) + " bytes)");
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(FMMLU_ENOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed");
+    }
+    chunks_.push_back(p);
+    sizes_.push_back(sz);
+    held_ += sz;
+    cur_ = chunks_.size() - 1;
+    used_ = 0;
+    return alloc(bytes);
+  }
+  template <class T>
+  T* alloc_n(size_t n) {
+    return static_cast<T*>(alloc(n * sizeof(T)));
+  }
+  // forget all allocations but keep the chunks for reuse
+  void reset() {
+    cur_ = 0;
+    used_ = 0;
+    total_ = 0;
+  }
+  void release() {
+    for (void* p : chunks_) (void)hipFree(p);
+    chunks_.clear();
+    sizes_.clear();
+    cur_ = 0;
+    used_ = 0;
+    held_ = 0;
+    total_ = 0;
+  }
+  size_t held() const { return held_; }
+  void set_cap(size_t cap) { cap_ = cap; }
+  void set_chunk(size_t c) { chunk_ = c; }
+
+ private:
+  size_t chunk_;
+  size_t cap_ = 0;
+  std::vector<void*> chunks_;
+  std::vector<size_t> sizes_;
+  size_t cur_ = 0, used_ = 0, held_ = 0, total_ = 0;
+};
+
+}  // namespace fmmlu

@@ -1,0 +1,1074 @@
+// Recursive strong skeletonization (Sections 4.1-4.4, 5.1-5.2), driven level by level.
+//
+// Storage ("pair tiles"). At level l every active DOF is owned by its level-l box or, when
+// its leaf is coarser, by that leaf. For every ordered pair of owners whose L-infinity gap
+// is at most one side of the finer of the two, the block A[act(o1), act(o2)] is kept as a
+// dense column-major tile. Schur-complement updates only ever touch such pairs (two boxes
+// that both touch the box being eliminated are at most one box apart), and every other
+// entry is still a pure kernel value (Section 4.4's invariant), so it is regenerated on
+// demand instead of stored.
+//
+// Per level: tiles are assembled (copied from the previous level's tiles restricted to the
+// surviving skeletons, or generated), then the level's boxes are processed in eight colour
+// phases (parity of the integer box coordinates). Same-colour boxes never touch, so within
+// a phase nothing one box writes is read by another; their Schur updates to shared
+// near-near tiles are summed by one output-stationary GEMM task per destination tile.
+// Within a phase:
+//   1. ID matrix M = [A_QB ; A_BQ^T ; proxy outgoing ; proxy incoming]  (Section 5.1.3)
+//   2. blocked Householder QR of M -> R;  greedy CPQR of R -> S, R, T  (Section 4.1)
+//   3. gathers and GEMMs for X_RR, X_{(S u N) R}, X_{R (S u N)}       (Section 4.1)
+//   4. Gauss-Jordan inversion of X_RR, panels L = X_{.R} X_RR^{-1}, U = X_RR^{-1} X_{R.}
+//   5. Schur update of the near-near tiles with X_{.R} U
+// The host only plans (index lists, task descriptors) and reads back ranks and pivots.
+#include "factor.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <unordered_map>
+
+namespace fmmlu {
+
+// ------------------------------------------------------------------------------------------
+HostStage::~HostStage() {
+  for (void* p : chunks_) (void)hipHostFree(p);
+}
+
+void* HostStage::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (cur_ < chunks_.size()) {
+    if (used_ + bytes <= sizes_[cur_]) {
+      void* p = static_cast<char*>(chunks_[cur_]) + used_;
+      used_ += bytes;
+      return p;
+    }
+    ++cur_;
+    used_ = 0;
+  }
+  size_t sz = std::max(bytes, size_t(64) << 20);
+  void* p = nullptr;
+  FMMLU_HIP(hipHostMalloc(&p, sz, hipHostMallocDefault));
+  chunks_.push_back(p);
+  sizes_.push_back(sz);
+  cur_ = chunks_.size() - 1;
+  used_ = bytes;
+  return p;
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Owner {
+  int box = -1;
+  int level = 0;
+  int64_t c[3] = {0, 0, 0};
+  int64_t first_pos = 0;        // first tree position of the box (ordering key)
+  std::vector<int64_t> act;     // tree positions of the tile rows at this level
+  std::vector<int32_t> live;    // positions in act still active (ascending)
+  int32_t* live_dev = nullptr;  // device copy of live
+  int32_t* perm_dev = nullptr;  // pivot order when processed at this level
+  std::vector<int> sub;         // previous-level owners merged into this one
+  std::vector<int64_t> sub_rowbase;
+};
+
+int64_t gap_units(const Owner& a, const Owner& b) {
+  const int L = std::max(a.level, b.level);
+  const int64_t sa = int64_t(1) << (L - a.level), sb = int64_t(1) << (L - b.level);
+  int64_t g = 0;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int64_t alo = a.c[ax] * sa, ahi = (a.c[ax] + 1) * sa;
+    const int64_t blo = b.c[ax] * sb, bhi = (b.c[ax] + 1) * sb;
+    g = std::max(g, std::max(blo - ahi, alo - bhi));
+  }
+  return std::max<int64_t>(g, 0);
+}
+
+struct Stage {
+  // device scratch for one phase / assembly, reset after each synchronisation
+  DeviceArena dev{size_t(512) << 20};
+  HostStage host;
+  hipStream_t st = nullptr;
+
+  template <class T>
+  T* up(const std::vector<T>& v) {
+    if (v.empty()) return nullptr;
+    size_t b = v.size() * sizeof(T);
+    void* h = host.alloc(b);
+    std::memcpy(h, v.data(), b);
+    T* d = static_cast<T*>(dev.alloc(b));
+    FMMLU_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, st));
+    return d;
+  }
+  // persistent upload into another arena
+  template <class T>
+  T* up_to(DeviceArena& a, const std::vector<T>& v) {
+    if (v.empty()) return nullptr;
+    size_t b = v.size() * sizeof(T);
+    void* h = host.alloc(b);
+    std::memcpy(h, v.data(), b);
+    T* d = static_cast<T*>(a.alloc(b));
+    FMMLU_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, st));
+    return d;
+  }
+  void sync_reset() {
+    FMMLU_HIP(hipStreamSynchronize(st));
+    dev.reset();
+    host.reset();
+  }
+};
+
+// Units of a GEMM task with 32 x 32 output blocks
+inline int64_t gemm_units(int M, int N) { return int64_t((M + 31) / 32) * ((N + 31) / 32); }
+inline int64_t units64(int r, int c) { return int64_t((r + 63) / 64) * ((c + 63) / 64); }
+
+struct GemmBatch {
+  std::vector<GemmTask> tasks;
+  std::vector<GemmSeg> segs;
+  int64_t units = 0;
+  void add(zd* C, int ldc, int M, int N, const int32_t* rmap, const int32_t* cmap,
+           const std::vector<GemmSeg>& s, double are, double aim, double beta) {
+    if (M <= 0 || N <= 0) return;
+    GemmTask t{};
+    t.C = C;
+    t.rmap = rmap;
+    t.cmap = cmap;
+    t.M = M;
+    t.N = N;
+    t.ldc = ldc;
+    t.seg_begin = (int32_t)segs.size();
+    t.nseg = (int32_t)s.size();
+    t.alpha_re = are;
+    t.alpha_im = aim;
+    t.beta = beta;
+    t.unit_begin = units;
+    units += gemm_units(M, N);
+    for (auto& g : s) segs.push_back(g);
+    tasks.push_back(t);
+  }
+  void add1(zd* C, int ldc, int M, int N, const zd* A, int lda, const zd* B, int ldb, int K,
+            double are, double beta) {
+    if (K <= 0) {
+      if (beta == 1.0) return;
+    }
+    std::vector<GemmSeg> s;
+    if (K > 0) s.push_back(GemmSeg{A, B, lda, ldb, K, 0});
+    add(C, ldc, M, N, nullptr, nullptr, s, are, 0.0, beta);
+  }
+  void run(Stage& sg, int opA) {
+    if (tasks.empty()) return;
+    GemmTask* dt = sg.up(tasks);
+    GemmSeg* ds = sg.up(segs);
+    launch_gemm(opA, dt, (int)tasks.size(), units, ds, sg.st);
+  }
+};
+
+// Batched Gauss-Jordan inversion of matrices A_b (n_b x n_b, lda_b) into out_b (ld n_b).
+void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd*>& outs,
+                     int32_t* info_dev) {
+  if (tasks.empty()) return;
+  int nmax = 0;
+  for (auto& t : tasks) nmax = std::max(nmax, t.n);
+  const int nt = (int)tasks.size();
+  std::vector<zd*> W(nt);
+  std::vector<int32_t*> work(nt);
+  for (int i = 0; i < nt; ++i) {
+    tasks[i].piv = sg.dev.alloc_n<int32_t>(tasks[i].n);
+    tasks[i].info = info_dev;
+    W[i] = sg.dev.alloc_n<zd>((size_t)kGjBlock * tasks[i].n);
+    work[i] = sg.dev.alloc_n<int32_t>(tasks[i].n);
+  }
+  GjTask* dt = sg.up(tasks);
+  zd** dW = sg.up(W);
+  int32_t** dwork = sg.up(work);
+  zd** dout = sg.up(outs);
+  for (int j0 = 0; j0 < nmax; j0 += kGjBlock) {
+    launch_gj_panel(dt, nt, j0, sg.st);
+    launch_gj_swaps(dt, nt, j0, nmax, sg.st);
+    launch_gj_copyrow(dt, nt, j0, nmax, dW, sg.st);
+    GemmBatch gb;
+    for (int i = 0; i < nt; ++i) {
+      const GjTask& t = tasks[i];
+      if (j0 >= t.n) continue;
+      const int nb = std::min(kGjBlock, t.n - j0);
+      // A[:, c] += A[:, J] W[:, c] for c outside J (two column ranges)
+      if (j0 > 0)
+        gb.add1(t.A, t.lda, t.n, j0, t.A + (int64_t)j0 * t.lda, t.lda, W[i], nb, nb, 1.0, 1.0);
+      const int c1 = j0 + nb;
+      if (c1 < t.n)
+        gb.add1(t.A + (int64_t)c1 * t.lda, t.lda, t.n, t.n - c1, t.A + (int64_t)j0 * t.lda, t.lda,
+                W[i] + (int64_t)c1 * nb, nb, nb, 1.0, 1.0);
+    }
+    gb.run(sg, 0);
+    launch_gj_fixrow(dt, nt, j0, nmax, dW, sg.st);
+  }
+  launch_gj_unpermute(dt, nt, nmax, dout, dwork, sg.st);
+}
+
+// Blocked Householder QR (no pivoting) of M_b (rows_b x m_b, ld rows_b), in place; the R
+// factor is left in the upper triangle.
+void batched_qr(Stage& sg, const std::vector<zd*>& Ms, const std::vector<int>& rows,
+                const std::vector<int>& ms) {
+  const int nt = (int)Ms.size();
+  if (nt == 0) return;
+  constexpr int NB = 16;
+  int kmax = 0;
+  for (int i = 0; i < nt; ++i) kmax = std::max(kmax, std::min(rows[i], ms[i]));
+  // per task V buffer (rows x NB) and Tw (NB x NB), W (NB x m)
+  std::vector<zd*> V(nt), Tw(nt), W(nt), W2(nt);
+  for (int i = 0; i < nt; ++i) {
+    V[i] = sg.dev.alloc_n<zd>((size_t)rows[i] * NB);
+    Tw[i] = sg.dev.alloc_n<zd>(NB * NB);
+    W[i] = sg.dev.alloc_n<zd>((size_t)NB * ms[i]);
+    W2[i] = sg.dev.alloc_n<zd>((size_t)NB * ms[i]);
+  }
+  for (int j0 = 0; j0 < kmax; j0 += NB) {
+    std::vector<QrTask> qt;
+    std::vector<int> who;
+    for (int i = 0; i < nt; ++i) {
+      const int k = std::min(rows[i], ms[i]);
+      if (j0 >= k) continue;
+      QrTask t{};
+      t.A = Ms[i];
+      t.V = V[i];
+      t.Tw = Tw[i];
+      t.rows = rows[i];
+      t.lda = rows[i];
+      t.j0 = j0;
+      t.nb = std::min(NB, k - j0);
+      qt.push_back(t);
+      who.push_back(i);
+    }
+    if (qt.empty()) break;
+    launch_qr_panel(sg.up(qt), (int)qt.size(), sg.st);
+    // trailing update: A2 = A[j0:, j0+nb:m];  A2 -= V (Tw^H (V^H A2))
+    GemmBatch g1, g2, g3;
+    for (size_t q = 0; q < qt.size(); ++q) {
+      const int i = who[q];
+      const int nb = qt[q].nb;
+      const int c0 = j0 + nb;
+      const int ncols = ms[i] - c0;
+      if (ncols <= 0) continue;
+      const int L = rows[i] - j0;
+      zd* A2 = Ms[i] + j0 + (int64_t)c0 * rows[i];
+      // W = V^H A2  (nb x ncols), K = L
+      g1.add1(W[i], nb, nb, ncols, V[i], L, A2, rows[i], L, 1.0, 0.0);
+      // W2 = Tw^H W  (nb x ncols), K = nb
+      g2.add1(W2[i], nb, nb, ncols, Tw[i], nb, W[i], nb, nb, 1.0, 0.0);
+      // A2 -= V W2  (L x ncols), K = nb
+      g3.add1(A2, rows[i], L, ncols, V[i], L, W2[i], nb, nb, -1.0, 1.0);
+    }
+    g1.run(sg, 2);
+    g2.run(sg, 2);
+    g3.run(sg, 0);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
+                        hipStream_t st) {
+  auto t0 = Clock::now();
+  n = tree.n;
+  info = fmmlu_info{};
+  info.n = n;
+  info.nlevels = tree.nlevels;
+  info.precision = opts.precision;
+  if (opts.device_mem_cap > 0) arena.set_cap((size_t)opts.device_mem_cap);
+  Stage sg;
+  sg.st = st;
+  // ---- geometry in tree order: x, y, z, nx, ny, nz, sqrt(w)
+  order = tree.order;
+  {
+    std::vector<double> gp(7 * (size_t)n);
+    for (int64_t p = 0; p < n; ++p) {
+      const int64_t o = order[p];
+      for (int a = 0; a < 3; ++a) {
+        gp[a * n + p] = xyz[a * n + o];
+        gp[(3 + a) * n + p] = nrm[a * n + o];
+      }
+      gp[6 * n + p] = std::sqrt(w[o]);
+    }
+    geom = sg.up_to(arena, gp);
+    order_dev = sg.up_to(arena, order);
+  }
+  g = DevGeom{geom, n, k, eta};
+  const double eps = opts.eps;
+  const double prad = opts.proxy_radius;
+
+  // ---- initial owners: every non-empty leaf, points in tree order (contiguous)
+  std::vector<Owner> own;
+  std::unordered_map<int, int> by_box;
+  for (int b = 0; b < (int)tree.nboxes(); ++b) {
+    if (!tree.is_leaf(b) || tree.npts(b) == 0) continue;
+    Owner o;
+    o.box = b;
+    o.level = tree.level[b];
+    o.c[0] = tree.cx[b];
+    o.c[1] = tree.cy[b];
+    o.c[2] = tree.cz[b];
+    o.first_pos = tree.first_pos(b);
+    o.act.resize(tree.npts(b));
+    std::iota(o.act.begin(), o.act.end(), o.first_pos);
+    own.push_back(std::move(o));
+  }
+  std::sort(own.begin(), own.end(), [](const Owner& a, const Owner& b) { return a.first_pos < b.first_pos; });
+  int64_t live_total = n;
+
+  // tiles of the previous level (for assembly)
+  zd* prev_pool = nullptr;
+  std::unordered_map<int64_t, int64_t> prev_pair;  // key o1*nprev+o2 -> offset
+  std::vector<Owner> prev_own;
+  bool first_level = true;
+  int32_t* info_dev = arena.alloc_n<int32_t>(1);
+  FMMLU_HIP(hipMemsetAsync(info_dev, 0, sizeof(int32_t), st));
+
+  auto owner_lookup = [&](int lev, int64_t x, int64_t y, int64_t z) -> int {
+    // owner containing level-lev cell (x,y,z) with level <= lev; -1 if none
+    const int64_t lim = int64_t(1) << lev;
+    if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
+    for (int l = lev; l >= 0; --l) {
+      const int sh = lev - l;
+      const int b = tree.find(l, x >> sh, y >> sh, z >> sh);
+      if (b < 0) continue;
+      auto it = by_box.find(b);
+      return it == by_box.end() ? -1 : it->second;
+    }
+    return -1;
+  };
+
+  for (int lev = tree.nlevels - 1; lev >= 2; --lev) {
+    const int nown = (int)own.size();
+    by_box.clear();
+    for (int i = 0; i < nown; ++i) by_box[own[i].box] = i;
+    // ---- close pairs of owners and their tiles
+    std::vector<std::vector<int>> close(nown);
+    for (int i = 0; i < nown; ++i) {
+      const Owner& o = own[i];
+      for (int dz = -2; dz <= 2; ++dz)
+        for (int dy = -2; dy <= 2; ++dy)
+          for (int dx = -2; dx <= 2; ++dx) {
+            const int p = owner_lookup(o.level, o.c[0] + dx, o.c[1] + dy, o.c[2] + dz);
+            if (p < 0) continue;
+            close[i].push_back(p);
+            close[p].push_back(i);
+          }
+    }
+    std::unordered_map<int64_t, int64_t> pair_off;
+    int64_t pool_elems = 0;
+    std::vector<std::pair<int, int>> pairs;
+    for (int i = 0; i < nown; ++i) {
+      auto& v = close[i];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+      for (int p : v) {
+        if (gap_units(own[i], own[p]) > 1) continue;
+        pair_off[(int64_t)i * nown + p] = pool_elems;
+        pairs.emplace_back(i, p);
+        pool_elems += (int64_t)own[i].act.size() * own[p].act.size();
+      }
+    }
+    zd* pool = nullptr;
+    {
+      size_t bytes = std::max<size_t>(1, (size_t)pool_elems) * sizeof(zd);
+      hipError_t e = hipMalloc(&pool, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(FMMLU_ENOMEM, "tile pool allocation failed (" + std::to_string(bytes) + " bytes)");
+      }
+    }
+    info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)(arena.held() + pool_elems * 16));
+    info.bytes_tiles += (double)pool_elems * 16.0;
+    // ---- assemble: slot/idx maps, dof lists, source tables
+    {
+      std::vector<int32_t> slot, idx;
+      std::vector<int64_t> dof;
+      std::vector<int64_t> map_off(nown);
+      for (int i = 0; i < nown; ++i) {
+        Owner& o = own[i];
+        map_off[i] = (int64_t)slot.size();
+        if (first_level) {
+          for (size_t r = 0; r < o.act.size(); ++r) {
+            slot.push_back(0);
+            idx.push_back((int32_t)r);
+          }
+        } else {
+          for (size_t q = 0; q < o.sub.size(); ++q) {
+            const Owner& so = prev_own[o.sub[q]];
+            for (int32_t l : so.live) {
+              slot.push_back((int32_t)q);
+              idx.push_back(l);
+            }
+          }
+        }
+        for (int64_t a : o.act) dof.push_back(a);
+      }
+      std::vector<AsmTask> tasks;
+      std::vector<AsmSrc> table;
+      int64_t units = 0;
+      for (auto& pr : pairs) {
+        const Owner& a = own[pr.first];
+        const Owner& b = own[pr.second];
+        AsmTask t{};
+        t.out_off = pair_off[(int64_t)pr.first * nown + pr.second];
+        t.nr = (int)a.act.size();
+        t.nc = (int)b.act.size();
+        t.ld = t.nr;
+        t.rmap_off = map_off[pr.first];
+        t.cmap_off = map_off[pr.second];
+        t.rdof_off = map_off[pr.first];
+        t.cdof_off = map_off[pr.second];
+        t.tab_off = (int64_t)table.size();
+        if (first_level) {
+          t.nsc = 1;
+          table.push_back(AsmSrc{-1, 0, 0});
+        } else {
+          t.nsc = (int)b.sub.size();
+          const int64_t nprev = (int64_t)prev_own.size();
+          for (int sa : a.sub)
+            for (int sb : b.sub) {
+              auto it = prev_pair.find((int64_t)sa * nprev + sb);
+              if (it == prev_pair.end())
+                table.push_back(AsmSrc{-1, 0, 0});
+              else
+                table.push_back(AsmSrc{it->second, (int32_t)prev_own[sa].act.size(), 0});
+            }
+        }
+        t.unit_begin = units;
+        units += units64(t.nr, t.nc);
+        if (t.nr > 0 && t.nc > 0) tasks.push_back(t);
+        else units = t.unit_begin;
+      }
+      launch_assemble(g, sg.up(tasks), (int)tasks.size(), units, sg.up(slot), sg.up(idx), sg.up(dof),
+                      sg.up(table), prev_pool, pool, st);
+      sg.sync_reset();
+      if (prev_pool) FMMLU_HIP(hipFree(prev_pool));
+      prev_pool = nullptr;
+    }
+    // every owner starts the level fully live; device copies of act positions as int32 tree
+    // positions are kept per owner for the factor records
+    for (auto& o : own) {
+      o.live.resize(o.act.size());
+      std::iota(o.live.begin(), o.live.end(), 0);
+    }
+    // device live lists: identity for all owners at level start
+    {
+      std::vector<int32_t> ident;
+      int maxc = 0;
+      for (auto& o : own) maxc = std::max<int>(maxc, (int)o.act.size());
+      ident.resize(maxc);
+      std::iota(ident.begin(), ident.end(), 0);
+      int32_t* dident = sg.up_to(arena, ident);  // persistent for the level (small)
+      for (auto& o : own) o.live_dev = dident;
+      FMMLU_HIP(hipStreamSynchronize(st));
+      sg.host.reset();
+    }
+    // device copy of all act lists (int64 tree positions) for the ID matrix proxy rows
+    std::vector<int64_t> act_cat;
+    std::vector<int64_t> act_off(nown);
+    for (int i = 0; i < nown; ++i) {
+      act_off[i] = (int64_t)act_cat.size();
+      act_cat.insert(act_cat.end(), own[i].act.begin(), own[i].act.end());
+    }
+    DeviceArena level_arena(size_t(64) << 20);
+    int64_t* act_dev = sg.up_to(level_arena, act_cat);
+
+    // ---- processed boxes by colour, Morton order within a colour
+    std::vector<std::vector<int>> colours(8);
+    for (int i = 0; i < nown; ++i) {
+      const Owner& o = own[i];
+      if (o.level != lev) continue;
+      const int col = int(o.c[0] & 1) + 2 * int(o.c[1] & 1) + 4 * int(o.c[2] & 1);
+      colours[col].push_back(i);
+    }
+    for (auto& v : colours)
+      std::sort(v.begin(), v.end(), [&](int a, int b) {
+        return morton3((uint32_t)own[a].c[0], (uint32_t)own[a].c[1], (uint32_t)own[a].c[2]) <
+               morton3((uint32_t)own[b].c[0], (uint32_t)own[b].c[1], (uint32_t)own[b].c[2]);
+      });
+
+    for (int colour = 0; colour < 8; ++colour) {
+      // ---- plan the phase
+      struct BoxPlan {
+        int oi;
+        int m;
+        std::vector<int> nown_, qown;  // near and Q owners (with live DOFs)
+        int nN = 0, nQ = 0;
+        bool far_p = false;
+        int ngamma = 0;
+        double ctr[3], radius = 0, wgamma = 0;
+        int rows = 0;
+        zd* M = nullptr;
+        zd* R = nullptr;
+        int32_t* perm = nullptr;
+        int32_t* rank = nullptr;
+        zd* T = nullptr;
+      };
+      std::vector<BoxPlan> plan;
+      for (int oi : colours[colour]) {
+        Owner& B = own[oi];
+        if (B.live.empty()) continue;
+        BoxPlan bp;
+        bp.oi = oi;
+        bp.m = (int)B.act.size();
+        int64_t near_live = 0;
+        for (int p : close[oi]) {
+          if (p == oi) continue;
+          const int64_t gu = gap_units(B, own[p]);
+          if (own[p].live.empty()) continue;
+          if (gu == 0) {
+            bp.nown_.push_back(p);
+            bp.nN += (int)own[p].live.size();
+          } else if (gu == 1) {
+            bp.qown.push_back(p);
+            bp.nQ += (int)own[p].live.size();
+          }
+        }
+        near_live = (int64_t)bp.nN + bp.nQ + (int64_t)B.live.size();
+        bp.far_p = live_total - near_live > 0;
+        if (bp.nQ == 0 && !bp.far_p) continue;
+        // owners are already in tree order (index order == first_pos order)
+        std::sort(bp.nown_.begin(), bp.nown_.end());
+        std::sort(bp.qown.begin(), bp.qown.end());
+        const double side = tree.box_side(B.box);
+        tree.box_centre(B.box, bp.ctr);
+        if (bp.far_p) {
+          const double ratio = prad / (std::sqrt(3.0) / 2.0);
+          const int p = (int)std::ceil(std::log(1.0 / eps) / std::log(ratio)) +
+                        (int)std::ceil(k * std::sqrt(3.0) * side);
+          bp.ngamma = std::max(opts.proxy_min_points, 2 * (p + 1) * (p + 1));
+          bp.radius = prad * side;
+          bp.wgamma = std::sqrt(4.0 * M_PI * bp.radius * bp.radius / bp.ngamma);
+        }
+        bp.rows = 2 * bp.nQ + 2 * bp.ngamma;
+        plan.push_back(std::move(bp));
+      }
+      if (plan.empty()) continue;
+      const int nb = (int)plan.size();
+      // ---- 1. ID matrices
+      std::vector<IdTask> idt;
+      std::vector<QSeg> qsegs;
+      int64_t units = 0;
+      for (auto& bp : plan) {
+        Owner& B = own[bp.oi];
+        bp.M = sg.dev.alloc_n<zd>((size_t)bp.rows * bp.m);
+        IdTask t{};
+        t.M = bp.M;
+        t.rows = bp.rows;
+        t.m = bp.m;
+        t.nq = bp.nQ;
+        t.ngamma = bp.ngamma;
+        t.seg_off = (int64_t)qsegs.size();
+        int row0 = 0;
+        for (int q : bp.qown) {
+          QSeg s{};
+          s.tile_qb = pair_off.at((int64_t)q * nown + bp.oi);
+          s.tile_bq = pair_off.at((int64_t)bp.oi * nown + q);
+          s.live = own[q].live_dev;
+          s.ld = (int)own[q].act.size();
+          s.row0 = row0;
+          row0 += (int)own[q].live.size();
+          qsegs.push_back(s);
+        }
+        t.nseg = (int)bp.qown.size();
+        t.dof_off = act_off[bp.oi];
+        t.cx = bp.ctr[0];
+        t.cy = bp.ctr[1];
+        t.cz = bp.ctr[2];
+        t.radius = bp.radius;
+        t.wgamma = bp.wgamma;
+        t.unit_begin = units;
+        units += units64(t.rows, t.m);
+        idt.push_back(t);
+        (void)B;
+      }
+      launch_build_idmatrix(g, sg.up(idt), nb, units, qsegs.empty() ? nullptr : sg.up(qsegs), act_dev,
+                            pool, st);
+      // ---- 2. QR of M, extract R, CPQR
+      {
+        std::vector<zd*> Ms;
+        std::vector<int> rws, mms;
+        for (auto& bp : plan) {
+          Ms.push_back(bp.M);
+          rws.push_back(bp.rows);
+          mms.push_back(bp.m);
+        }
+        batched_qr(sg, Ms, rws, mms);
+        std::vector<ExtractTask> et;
+        std::vector<CpqrTask> ct;
+        int mmax = 0;
+        for (auto& bp : plan) {
+          bp.R = sg.dev.alloc_n<zd>((size_t)bp.m * bp.m);
+          bp.perm = sg.dev.alloc_n<int32_t>(bp.m);
+          bp.rank = sg.dev.alloc_n<int32_t>(1);
+          bp.T = sg.dev.alloc_n<zd>((size_t)bp.m * bp.m);
+          et.push_back(ExtractTask{bp.M, bp.R, bp.rows, bp.m});
+          ct.push_back(CpqrTask{bp.R, bp.perm, bp.rank, bp.T, bp.m, bp.m});
+          mmax = std::max(mmax, bp.m);
+        }
+        launch_extract_r(sg.up(et), nb, mmax, st);
+        launch_cpqr(sg.up(ct), nb, eps, st);
+      }
+      // ---- read back ranks and pivots
+      std::vector<int32_t> ranks(nb);
+      std::vector<std::vector<int32_t>> perms(nb);
+      for (int i = 0; i < nb; ++i) {
+        perms[i].resize(plan[i].m);
+        FMMLU_HIP(hipMemcpyAsync(&ranks[i], plan[i].rank, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        FMMLU_HIP(hipMemcpyAsync(perms[i].data(), plan[i].perm, sizeof(int32_t) * plan[i].m,
+                                 hipMemcpyDeviceToHost, st));
+      }
+      FMMLU_HIP(hipStreamSynchronize(st));
+      // ---- 3. elimination plan
+      struct ElimPlan {
+        int pi;  // index into plan
+        int s, r, nsn;
+        zd *Ccol, *Crow;
+        FactorBox* fb;
+      };
+      std::vector<ElimPlan> ep;
+      const size_t box_base = boxes.size();
+      for (int i = 0; i < nb; ++i) {
+        const int s = ranks[i], m = plan[i].m;
+        if (s >= m) continue;  // nothing redundant
+        ElimPlan e{};
+        e.pi = i;
+        e.s = s;
+        e.r = m - s;
+        e.nsn = s + plan[i].nN;
+        ep.push_back(e);
+      }
+      const int ne = (int)ep.size();
+      if (ne > 0) {
+        boxes.resize(box_base + ne);
+        // factor storage and index lists
+        std::vector<CrossTask> cross;
+        std::vector<NSeg> nsegs;
+        int64_t cunits = 0;
+        for (int q = 0; q < ne; ++q) {
+          ElimPlan& e = ep[q];
+          BoxPlan& bp = plan[e.pi];
+          Owner& B = own[bp.oi];
+          FactorBox& fb = boxes[box_base + q];
+          e.fb = &fb;
+          fb.level = lev;
+          fb.box = B.box;
+          fb.coord[0] = (int)B.c[0];
+          fb.coord[1] = (int)B.c[1];
+          fb.coord[2] = (int)B.c[2];
+          fb.m = bp.m;
+          fb.s = e.s;
+          fb.r = e.r;
+          fb.nsn = e.nsn;
+          const std::vector<int32_t>& pv = perms[e.pi];
+          std::vector<int32_t> Ridx(e.r), Sidx(e.s), SNidx;
+          for (int j = 0; j < e.s; ++j) Sidx[j] = (int32_t)B.act[pv[j]];
+          for (int j = 0; j < e.r; ++j) Ridx[j] = (int32_t)B.act[pv[e.s + j]];
+          SNidx = Sidx;
+          for (int o : bp.nown_)
+            for (int32_t l : own[o].live) SNidx.push_back((int32_t)own[o].act[l]);
+          fb.skel_orig.resize(e.s);
+          for (int j = 0; j < e.s; ++j) fb.skel_orig[j] = order[Sidx[j]];
+          std::sort(fb.skel_orig.begin(), fb.skel_orig.end());
+          SolveBox& d = fb.dev;
+          d.R = sg.up_to(arena, Ridx);
+          d.S = e.s ? sg.up_to(arena, Sidx) : nullptr;
+          d.SN = e.nsn ? sg.up_to(arena, SNidx) : nullptr;
+          d.T = e.s ? arena.alloc_n<zd>((size_t)e.s * e.r) : nullptr;
+          d.Xi = arena.alloc_n<zd>((size_t)e.r * e.r);
+          d.Lp = e.nsn ? arena.alloc_n<zd>((size_t)e.nsn * e.r) : nullptr;
+          d.Up = e.nsn ? arena.alloc_n<zd>((size_t)e.r * e.nsn) : nullptr;
+          d.r = e.r;
+          d.s = e.s;
+          d.nsn = e.nsn;
+          info.factor_bytes += 16 * ((int64_t)e.s * e.r + (int64_t)e.r * e.r + 2 * (int64_t)e.nsn * e.r);
+          // cross gathers
+          const int mn = bp.m + bp.nN;
+          e.Ccol = sg.dev.alloc_n<zd>((size_t)mn * bp.m);
+          e.Crow = sg.dev.alloc_n<zd>((size_t)bp.m * mn);
+          CrossTask ct{};
+          ct.Ccol = e.Ccol;
+          ct.Crow = e.Crow;
+          ct.tile_bb = pair_off.at((int64_t)bp.oi * nown + bp.oi);
+          ct.perm = bp.perm;
+          ct.m = bp.m;
+          ct.nN = bp.nN;
+          ct.s = e.s;
+          ct.seg_off = (int64_t)nsegs.size();
+          int off = 0;
+          for (int o : bp.nown_) {
+            NSeg s{};
+            s.tile_nb = pair_off.at((int64_t)o * nown + bp.oi);
+            s.tile_bn = pair_off.at((int64_t)bp.oi * nown + o);
+            s.live = own[o].live_dev;
+            s.ld = (int)own[o].act.size();
+            s.off = off;
+            off += (int)own[o].live.size();
+            nsegs.push_back(s);
+          }
+          ct.nseg = (int)bp.nown_.size();
+          ct.unit_begin = cunits;
+          cunits += units64(mn, bp.m) + units64(bp.m, mn);
+          cross.push_back(ct);
+          info.max_rank = std::max(info.max_rank, e.s);
+        }
+        launch_gather_cross(sg.up(cross), ne, cunits, nsegs.empty() ? nullptr : sg.up(nsegs), pool, st);
+        // E/F transforms (Section 4.1). Ccol = A[(R,S,N),(S,R)], Crow = A[(S,R),(R,S,N)]:
+        //   Ccol[:, s:m]      -= Ccol[:, 0:s] T        (A_{.R} - A_{.S} T)
+        //   Ccol[0:r, s:m]    -= T^T Ccol[r:m, s:m]    -> X_RR;  Ccol[r:, s:m] = X_{(S u N) R}
+        //   Crow[s:m, r:]     -= T^T Crow[0:s, r:]     -> X_{R (S u N)}
+        {
+          GemmBatch ga, gb, gc;
+          for (auto& e : ep) {
+            BoxPlan& bp = plan[e.pi];
+            const int m = bp.m, mn = bp.m + bp.nN;
+            zd* CcR = e.Ccol + (int64_t)e.s * mn;
+            ga.add1(CcR, mn, mn, e.r, e.Ccol, mn, bp.T, m, e.s, -1.0, 1.0);
+            gc.add1(e.Crow + e.s + (int64_t)e.r * m, m, e.r, mn - e.r, bp.T, m, e.Crow + (int64_t)e.r * m, m,
+                    e.s, -1.0, 1.0);
+          }
+          ga.run(sg, 0);
+          gc.run(sg, 1);
+          for (auto& e : ep) {
+            BoxPlan& bp = plan[e.pi];
+            const int m = bp.m, mn = bp.m + bp.nN;
+            zd* CcR = e.Ccol + (int64_t)e.s * mn;
+            gb.add1(CcR, mn, e.r, e.r, bp.T, m, CcR + e.r, mn, e.s, -1.0, 1.0);
+          }
+          gb.run(sg, 1);
+        }
+        // 4. inverse of X_RR (in place in Ccol[0:r, 0:r]) -> Xi
+        {
+          std::vector<GjTask> gt;
+          std::vector<zd*> outs;
+          for (auto& e : ep) {
+            GjTask t{};
+            t.A = e.Ccol + (int64_t)e.s * (plan[e.pi].m + plan[e.pi].nN);
+            t.n = e.r;
+            t.lda = plan[e.pi].m + plan[e.pi].nN;
+            gt.push_back(t);
+            outs.push_back(const_cast<zd*>(e.fb->dev.Xi));
+          }
+          batched_inverse(sg, gt, outs, info_dev);
+        }
+        // panels: Lp = X_{SN,R} Xi ; Up = Xi X_{R,SN}; T compacted into the factor
+        {
+          GemmBatch gp;
+          std::vector<CopyTask> cps;
+          int64_t cu = 0;
+          for (auto& e : ep) {
+            BoxPlan& bp = plan[e.pi];
+            const int m = bp.m, mn = bp.m + bp.nN;
+            SolveBox& d = e.fb->dev;
+            if (e.nsn > 0) {
+              const zd* XsnR = e.Ccol + (int64_t)e.s * mn + e.r;         // X_{(S u N) R}
+              const zd* XRsn = e.Crow + e.s + (int64_t)e.r * m;          // X_{R (S u N)}
+              gp.add1(const_cast<zd*>(d.Lp), e.nsn, e.nsn, e.r, XsnR, mn, d.Xi, e.r, e.r, 1.0, 0.0);
+              gp.add1(const_cast<zd*>(d.Up), e.r, e.r, e.nsn, d.Xi, e.r, XRsn, m, e.r, 1.0, 0.0);
+            }
+            if (e.s > 0) {
+              CopyTask c{bp.T, const_cast<zd*>(d.T), e.s, e.r, m, e.s, cu};
+              cu += units64(e.s, e.r);
+              cps.push_back(c);
+            }
+          }
+          gp.run(sg, 0);
+          if (!cps.empty()) launch_copy(sg.up(cps), (int)cps.size(), cu, st);
+        }
+        // 5. Schur update of near-near tiles: A[SN, SN] -= X_{SN,R} Up
+        {
+          GemmBatch gs;
+          std::map<int64_t, int> dest;  // tile offset -> task index (ordered for determinism)
+          struct Dst {
+            zd* C;
+            int ldc, M, N;
+            const int32_t *rmap, *cmap;
+            std::vector<GemmSeg> segs;
+          };
+          std::vector<Dst> dsts;
+          for (auto& e : ep) {
+            BoxPlan& bp = plan[e.pi];
+            const int mn = bp.m + bp.nN;
+            SolveBox& d = e.fb->dev;
+            // owners of the S u N rows: B itself then its near owners
+            std::vector<int> grp;
+            std::vector<int> goff;
+            grp.push_back(bp.oi);
+            goff.push_back(0);
+            int off = e.s;
+            for (int o : bp.nown_) {
+              grp.push_back(o);
+              goff.push_back(off);
+              off += (int)own[o].live.size();
+            }
+            for (size_t a = 0; a < grp.size(); ++a)
+              for (size_t b = 0; b < grp.size(); ++b) {
+                const int o1 = grp[a], o2 = grp[b];
+                const int M = (a == 0) ? e.s : (int)own[o1].live.size();
+                const int N = (b == 0) ? e.s : (int)own[o2].live.size();
+                if (M == 0 || N == 0) continue;
+                const int64_t toff = pair_off.at((int64_t)o1 * nown + o2);
+                auto it = dest.find(toff);
+                int di;
+                if (it == dest.end()) {
+                  di = (int)dsts.size();
+                  dest[toff] = di;
+                  Dst ds;
+                  ds.C = pool + toff;
+                  ds.ldc = (int)own[o1].act.size();
+                  ds.M = M;
+                  ds.N = N;
+                  ds.rmap = (a == 0) ? bp.perm : own[o1].live_dev;
+                  ds.cmap = (b == 0) ? bp.perm : own[o2].live_dev;
+                  dsts.push_back(ds);
+                } else {
+                  di = it->second;
+                }
+                dsts[di].segs.push_back(GemmSeg{e.Ccol + (int64_t)e.s * mn + e.r + goff[a],
+                                                d.Up + (int64_t)goff[b] * e.r, mn, e.r, e.r, 0});
+              }
+          }
+          for (auto& kv : dest) {
+            Dst& ds = dsts[kv.second];
+            gs.add(ds.C, ds.ldc, ds.M, ds.N, ds.rmap, ds.cmap, ds.segs, -1.0, 0.0, 1.0);
+          }
+          gs.run(sg, 0);
+        }
+        // flops of this phase
+        for (auto& e : ep) {
+          BoxPlan& bp = plan[e.pi];
+          info.flops_schur += 8.0 * (double)e.nsn * e.nsn * e.r;
+          info.flops_elim += 8.0 * ((double)(bp.m + bp.nN) * e.r * e.s * 2 + 2.0 * e.r * e.r * e.r +
+                                   2.0 * e.nsn * e.r * e.r);
+        }
+      }
+      for (auto& bp : plan) {
+        const double L = bp.rows, m = bp.m;
+        info.flops_id += 8.0 * (2.0 * L * m * std::min(L, m)) + 8.0 * m * m * m;
+      }
+      // ---- update live lists of eliminated boxes (skeletons in tree order)
+      for (int q = 0; q < ne; ++q) {
+        ElimPlan& e = ep[q];
+        Owner& B = own[plan[e.pi].oi];
+        const std::vector<int32_t>& pv = perms[e.pi];
+        std::vector<int32_t> nl(pv.begin(), pv.begin() + e.s);
+        std::sort(nl.begin(), nl.end());
+        B.live = nl;
+        live_total -= e.r;
+        info.nboxes_factored++;
+      }
+      // build the solve phase record (needs the live lists of boxes only for SN: done above)
+      if (ne > 0) {
+        SolvePhase ph;
+        ph.box_begin = (int)box_base;
+        ph.box_end = (int)boxes.size();
+        int64_t yo = 0;
+        std::map<int32_t, std::vector<int64_t>> contrib;
+        std::vector<SolveBox> db;
+        for (int b = ph.box_begin; b < ph.box_end; ++b) {
+          FactorBox& fb = boxes[b];
+          fb.y_off = yo;
+          fb.dev.y_off = yo;
+          ph.rmax = std::max(ph.rmax, fb.r);
+          db.push_back(fb.dev);
+          yo += fb.nsn;
+        }
+        // host copies of SN lists for the scatter CSR: rebuild from the plan
+        for (int q = 0; q < ne; ++q) {
+          ElimPlan& e = ep[q];
+          BoxPlan& bp = plan[e.pi];
+          Owner& B = own[bp.oi];
+          const std::vector<int32_t>& pv = perms[e.pi];
+          FactorBox& fb = boxes[box_base + q];
+          int c = 0;
+          for (int j = 0; j < e.s; ++j) contrib[(int32_t)B.act[pv[j]]].push_back(fb.y_off + c++);
+          for (int o : bp.nown_)
+            for (int32_t l : own[o].live) contrib[(int32_t)own[o].act[l]].push_back(fb.y_off + c++);
+        }
+        std::vector<int32_t> dst;
+        std::vector<int64_t> ptr{0}, src;
+        for (auto& kv : contrib) {
+          dst.push_back(kv.first);
+          for (int64_t v : kv.second) src.push_back(v);
+          ptr.push_back((int64_t)src.size());
+        }
+        if ((size_t)ph.rmax * sizeof(zd) > 65536)
+          throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(ph.rmax) +
+                                        " DOFs exceeds the solve kernels' LDS bound (4096)");
+        ph.ylen = yo;
+        ph.nd = (int64_t)dst.size();
+        ph.dboxes = sg.up_to(arena, db);
+        ph.sc_dst = sg.up_to(arena, dst);
+        ph.sc_ptr = sg.up_to(arena, ptr);
+        ph.sc_src = sg.up_to(arena, src);
+        ymax = std::max(ymax, yo);
+        phases.push_back(ph);
+      }
+      // live lists of eliminated boxes to the device (persistent for the level)
+      for (int q = 0; q < ne; ++q) {
+        Owner& B = own[plan[ep[q].pi].oi];
+        B.live_dev = B.live.empty() ? nullptr : sg.up_to(level_arena, B.live);
+      }
+      sg.sync_reset();
+      {
+        int32_t hinfo = 0;
+        FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+        if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block X_RR at level " + std::to_string(lev));
+      }
+      for (auto& bp : plan) info.max_block = std::max(info.max_block, bp.m);
+    }
+    if (opts.verbose)
+      fprintf(stderr, "[fmmlu] level %d: owners %d pairs %zu tiles %.1f MB live %lld\n", lev, nown,
+              pairs.size(), pool_elems * 16.0 / 1e6, (long long)live_total);
+
+    // ---- next level's owners: merge live DOFs of level-lev owners into parents
+    std::vector<Owner> next;
+    std::unordered_map<int, int> next_by_box;
+    for (int i = 0; i < nown; ++i) {
+      Owner& o = own[i];
+      if (o.live.empty()) continue;
+      int target_box = o.level == lev ? tree.parent[o.box] : o.box;
+      auto it = next_by_box.find(target_box);
+      int ni;
+      if (it == next_by_box.end()) {
+        ni = (int)next.size();
+        next_by_box[target_box] = ni;
+        Owner no;
+        no.box = target_box;
+        no.level = tree.level[target_box];
+        no.c[0] = tree.cx[target_box];
+        no.c[1] = tree.cy[target_box];
+        no.c[2] = tree.cz[target_box];
+        no.first_pos = o.act[o.live[0]];
+        next.push_back(std::move(no));
+      } else {
+        ni = it->second;
+      }
+      Owner& no = next[ni];
+      no.sub.push_back(i);
+      for (int32_t l : o.live) no.act.push_back(o.act[l]);
+    }
+    for (auto& no : next) {
+      // sub-owners are visited in tree order, so act is sorted; first_pos = act[0]
+      no.first_pos = no.act.front();
+    }
+    std::sort(next.begin(), next.end(), [](const Owner& a, const Owner& b) { return a.first_pos < b.first_pos; });
+    prev_own = std::move(own);
+    prev_pair = std::move(pair_off);
+    prev_pool = pool;
+    own = std::move(next);
+    first_level = false;
+    FMMLU_HIP(hipStreamSynchronize(st));
+  }
+
+  // ---- top block: all remaining live DOFs (tree order)
+  {
+    // own holds the owners after the last merge; their act lists are all live.
+    std::vector<int32_t> slot, idx;
+    std::vector<int64_t> dof;
+    std::vector<int32_t> top;
+    int nsub = 0;
+    if (first_level) {
+      // no level was processed (tree with fewer than 3 levels): the top block is A~ itself
+      for (auto& o : own) {
+        for (int64_t a : o.act) {
+          slot.push_back(0);
+          idx.push_back(0);
+          dof.push_back(a);
+        }
+      }
+      nsub = 1;
+    } else {
+      nsub = (int)prev_own.size();
+      for (size_t q = 0; q < prev_own.size(); ++q) {
+        const Owner& so = prev_own[q];
+        for (int32_t l : so.live) {
+          slot.push_back((int32_t)q);
+          idx.push_back(l);
+          dof.push_back(so.act[l]);
+        }
+      }
+    }
+    n0 = (int)dof.size();
+    info.n0 = n0;
+    for (int64_t d : dof) top.push_back((int32_t)d);
+    if (n0 > 0) {
+      std::vector<AsmSrc> table;
+      if (first_level) {
+        table.push_back(AsmSrc{-1, 0, 0});
+      } else {
+        const int64_t np = (int64_t)prev_own.size();
+        table.resize((size_t)np * np, AsmSrc{-1, 0, 0});
+        for (auto& kv : prev_pair) {
+          const int64_t a = kv.first / np, b = kv.first % np;
+          table[a * np + b] = AsmSrc{kv.second, (int32_t)prev_own[a].act.size(), 0};
+        }
+      }
+      zd* Att = sg.dev.alloc_n<zd>((size_t)n0 * n0);
+      AsmTask t{};
+      t.out_off = 0;
+      t.nr = n0;
+      t.nc = n0;
+      t.ld = n0;
+      t.nsc = first_level ? 1 : nsub;
+      t.rmap_off = 0;
+      t.cmap_off = 0;
+      t.rdof_off = 0;
+      t.cdof_off = 0;
+      t.tab_off = 0;
+      t.unit_begin = 0;
+      std::vector<AsmTask> tv{t};
+      launch_assemble(g, sg.up(tv), 1, units64(n0, n0), sg.up(slot), sg.up(idx), sg.up(dof), sg.up(table),
+                      prev_pool, Att, st);
+      Ainv = arena.alloc_n<zd>((size_t)n0 * n0);
+      std::vector<GjTask> gt(1);
+      gt[0].A = Att;
+      gt[0].n = n0;
+      gt[0].lda = n0;
+      std::vector<zd*> outs{Ainv};
+      batched_inverse(sg, gt, outs, info_dev);
+      top_dev = sg.up_to(arena, top);
+      info.flops_top = 8.0 * (double)n0 * n0 * n0;
+      info.factor_bytes += 16 * (int64_t)n0 * n0;
+    }
+    sg.sync_reset();
+    if (prev_pool) FMMLU_HIP(hipFree(prev_pool));
+    prev_pool = nullptr;
+    int32_t hinfo = 0;
+    FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular top block");
+  }
+  info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)arena.held());
+  info.t_factor = std::chrono::duration<double>(Clock::now() - t0).count();
+}
+
+// ------------------------------------------------------------------------------------------
+void FactorImpl::solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st) {
+  if (!wx) {
+    wx = arena.alloc_n<zd>((size_t)n);
+    wy = arena.alloc_n<zd>((size_t)std::max<int64_t>(ymax, 1));
+    wtop = arena.alloc_n<zd>((size_t)std::max(n0, 1));
+  }
+  const int adj = adjoint ? 1 : 0;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    const zd* bc = b + c * n;
+    zd* xc = x + c * n;
+    launch_permute(bc, wx, order_dev, n, 1, st);
+    for (auto& ph : phases) {
+      launch_solve_fwd(ph.dboxes, ph.box_end - ph.box_begin, ph.rmax, wx, wy, adj, st);
+      launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
+    }
+    for (auto& ph : phases) launch_solve_diag(ph.dboxes, ph.box_end - ph.box_begin, ph.rmax, wx, adj, st);
+    launch_solve_top(Ainv, n0, top_dev, wx, wtop, adj, st);
+    for (auto it = phases.rbegin(); it != phases.rend(); ++it)
+      launch_solve_bwd(it->dboxes, it->box_end - it->box_begin, it->rmax, wx, adj, st);
+    launch_permute(wx, xc, order_dev, n, 0, st);
+  }
+}
+
+}  // namespace fmmlu

@@ -1,0 +1,81 @@
+// Factorization object: recursive strong skeletonization driven level by level from the
+// host, every arithmetic step in device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "tree.hpp"
+
+namespace fmmlu {
+
+// Pinned host staging memory for task descriptors; bump allocation, reset after a sync.
+class HostStage {
+ public:
+  ~HostStage();
+  void* alloc(size_t bytes);
+  void reset() {
+    cur_ = 0;
+    used_ = 0;
+  }
+
+ private:
+  std::vector<void*> chunks_;
+  std::vector<size_t> sizes_;
+  size_t cur_ = 0, used_ = 0;
+};
+
+struct FactorBox {
+  int level, box;
+  int coord[3];
+  int m, s, r, nsn;
+  int64_t y_off;
+  std::vector<int64_t> skel_orig;  // skeleton DOFs as original indices (sorted)
+  SolveBox dev;                    // device pointers and sizes
+};
+
+struct SolvePhase {
+  int box_begin = 0, box_end = 0;  // range in boxes
+  SolveBox* dboxes = nullptr;      // device array
+  int32_t* sc_dst = nullptr;       // scatter CSR: destination tree positions
+  int64_t* sc_ptr = nullptr;
+  int64_t* sc_src = nullptr;
+  int64_t nd = 0;
+  int64_t ylen = 0;
+  int rmax = 0;
+};
+
+struct FactorImpl {
+  int64_t n = 0;
+  double k = 0, eta = 0;
+  fmmlu_opts opts{};
+  int device = 0;
+  DeviceArena arena;  // persistent: geometry, factors, top
+  double* geom = nullptr;
+  int64_t* order_dev = nullptr;  // tree position -> original index
+  DevGeom g{};
+  std::vector<int64_t> order;  // host copy
+  std::vector<FactorBox> boxes;
+  std::vector<SolvePhase> phases;
+  int64_t ymax = 0;
+  int n0 = 0;
+  int32_t* top_dev = nullptr;
+  zd* Ainv = nullptr;
+  fmmlu_info info{};
+  // solve workspace (allocated lazily)
+  zd* wx = nullptr;
+  zd* wy = nullptr;
+  zd* wtop = nullptr;
+  zd* wmv = nullptr;
+
+  void factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
+              hipStream_t st);
+  void solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st);
+};
+
+}  // namespace fmmlu

@@ -1,0 +1,207 @@
+// Task descriptors and launchers of the device kernels. Every kernel is batched over a
+// list of independent tasks of uneven size; the host fills the task arrays, copies them
+// to the device once per launch group, and a workgroup finds its task by binary search
+// over the tasks' prefix sums of work units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace fmmlu {
+
+// Geometry on the device, structure of arrays in tree order: x, y, z, nx, ny, nz, sqrt(w).
+struct DevGeom {
+  const double* p;  // 7 * n doubles
+  int64_t n;
+  double k, eta;
+};
+
+// ---- tile assembly: out block = copy from old tiles where stored, else kernel entries ----
+// Rows of the output are described by (slot, index) pairs: slot selects a source row group
+// (a sub-owner) and index the row inside that group's source tile. Columns likewise. The
+// source table holds, per (row slot, column slot), the source tile offset (-1: generate
+// from the kernel) and its leading dimension.
+struct AsmTask {
+  int64_t out_off;      // destination offset (elements)
+  int32_t nr, nc, ld;   // block size and destination leading dimension
+  int32_t nsc;          // number of column slots (table row stride)
+  int64_t rmap_off;     // offset into map arrays: rslot/ridx for rows
+  int64_t cmap_off;     // ... cslot/cidx for columns
+  int64_t rdof_off;     // offset into dof array: tree position of each output row
+  int64_t cdof_off;     // ... of each output column
+  int64_t tab_off;      // offset into the source table
+  int64_t unit_begin;   // prefix sum of 64x64 work units
+};
+struct AsmSrc {
+  int64_t off;  // source offset, -1 to generate
+  int32_t ld;
+  int32_t pad;
+};
+
+void launch_assemble(const DevGeom& g, const AsmTask* tasks, int ntasks, int64_t nunits,
+                     const int32_t* slot, const int32_t* idx, const int64_t* dof,
+                     const AsmSrc* table, const zd* src_pool, zd* dst_pool, hipStream_t st);
+
+// ---- ID matrix [A_QB ; A_BQ^T ; proxy outgoing ; proxy incoming] (column-major) ----
+struct QSeg {
+  int64_t tile_qb;      // offset of tile (q, B): rows = act(q), cols = act(B)
+  int64_t tile_bq;      // offset of tile (B, q): rows = act(B), cols = act(q)
+  const int32_t* live;  // live rows of q (positions in act(q))
+  int32_t ld;           // |act(q)|, leading dimension of tile (q, B)
+  int32_t row0;         // first row of this segment inside the A_QB block
+};
+struct IdTask {
+  zd* M;             // output matrix
+  int32_t rows, m;   // M is rows x m, ld = rows
+  int32_t nq;        // sum of Q counts
+  int32_t ngamma;    // proxy points (0: no proxy rows)
+  int32_t nseg;      // number of Q segments
+  int32_t pad;
+  int64_t seg_off;   // offset into QSeg array
+  int64_t dof_off;   // tree positions of B's active DOFs (m)
+  double cx, cy, cz, radius, wgamma;  // proxy sphere centre, radius, row weight
+  int64_t unit_begin;
+};
+void launch_build_idmatrix(const DevGeom& g, const IdTask* tasks, int ntasks, int64_t nunits,
+                           const QSeg* segs, const int64_t* dof, const zd* pool, hipStream_t st);
+
+// ---- batched complex GEMM with segments and scatter maps ----
+// C[rmap[i], cmap[j]] = beta * C[...] + alpha * sum_s opA(A_s)[i, :] * B_s[:, j]
+// opA: 0 = N (A is M x K, lda), 1 = T (A stored K x M), 2 = C (conjugate transpose).
+struct GemmSeg {
+  const zd* A;
+  const zd* B;
+  int32_t lda, ldb, K, pad;
+};
+struct GemmTask {
+  zd* C;
+  const int32_t* rmap;  // may be null (identity)
+  const int32_t* cmap;  // may be null (identity)
+  int32_t M, N, ldc;
+  int32_t seg_begin, nseg;
+  int32_t pad;
+  double alpha_re, alpha_im, beta;  // beta real
+  int64_t unit_begin;              // prefix sum of 32x32 output blocks
+};
+void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
+                 hipStream_t st);
+
+// ---- Householder panel factorization (unpivoted QR) ----
+struct QrTask {
+  zd* A;          // matrix, column-major, lda
+  zd* V;          // output: explicit reflectors (rows - j0) x nb, ld = rows - j0
+  zd* Tw;         // output: nb x nb triangular factor of the compact WY form
+  int32_t rows, lda, j0, nb;
+};
+void launch_qr_panel(const QrTask* tasks, int ntasks, hipStream_t st);
+
+// ---- greedy CPQR on an m x m matrix (in place) + T = R11^{-1} R12 ----
+struct CpqrTask {
+  zd* R;           // m x m, ld = lda (in place)
+  int32_t* perm;   // output m
+  int32_t* rank;   // output (device scalar)
+  zd* T;           // output s x (m - s), ld = m (room for s <= m)
+  int32_t m, lda;
+};
+void launch_cpqr(const CpqrTask* tasks, int ntasks, double eps, hipStream_t st);
+
+// ---- gathers of the cross of B ----
+// With perm the ID pivot order (skeletons S = perm[0:s], redundant R = perm[s:m]):
+//   Ccol = A[(R, S, N), (S, R)]   ((m + nN) x m, ld m + nN)
+//   Crow = A[(S, R), (R, S, N)]   (m x (m + nN), ld m)
+// so that after the E/F transforms X_RR, X_{(S u N) R} and X_{R (S u N)} are contiguous.
+struct NSeg {
+  int64_t tile_nb;      // tile (o, B): rows act(o), ld = ld
+  int64_t tile_bn;      // tile (B, o): rows act(B), ld = m
+  const int32_t* live;  // live rows of o
+  int32_t ld, off;      // |act(o)| and position of its first live DOF in the N list
+};
+struct CrossTask {
+  zd* Ccol;  // (m + nN) x m, ld = m + nN
+  zd* Crow;  // m x (m + nN), ld = m
+  int64_t tile_bb;   // tile (B, B), ld = m
+  const int32_t* perm;
+  int32_t m, nN, nseg, s;
+  int64_t seg_off;
+  int64_t unit_begin;
+};
+void launch_gather_cross(const CrossTask* tasks, int ntasks, int64_t nunits, const NSeg* segs,
+                         const zd* pool, hipStream_t st);
+
+// ---- Gauss-Jordan inversion with partial pivoting, blocked ----
+struct GjTask {
+  zd* A;      // n x n, ld = lda
+  int32_t* piv;
+  int32_t n, lda;
+  int32_t* info;  // set to 1 + column on a zero pivot
+};
+void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, hipStream_t st);
+void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st);
+// W (nb x n) = A[J, :] with J = [j0, j0+nb)
+void launch_gj_copyrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,
+                       hipStream_t st);
+// A[J, c] -= W[:, c] for c outside J
+void launch_gj_fixrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,
+                      hipStream_t st);
+// undo the column permutation: Out = A * P (gather columns)
+void launch_gj_unpermute(const GjTask* tasks, int ntasks, int nmax, zd* const* out,
+                         int32_t* const* work, hipStream_t st);
+constexpr int kGjBlock = 16;  // Gauss-Jordan panel width
+
+// ---- R factor extraction: R = triu(M[0:min(rows,m), 0:m]) padded to m x m ----
+struct ExtractTask {
+  const zd* M;
+  zd* R;
+  int32_t rows, m;
+};
+void launch_extract_r(const ExtractTask* tasks, int ntasks, int mmax, hipStream_t st);
+
+// ---- copy a sub-block (column-major) ----
+struct CopyTask {
+  const zd* src;
+  zd* dst;
+  int32_t rows, cols, lds, ldd;
+  int64_t unit_begin;
+};
+void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
+
+// ---- solve sweeps ----
+struct SolveBox {
+  const int32_t* R;   // tree positions, r
+  const int32_t* S;   // s
+  const int32_t* SN;  // s + nN (S first)
+  const zd* T;        // s x r, ld = s
+  const zd* Xi;       // r x r inverse pivot block
+  const zd* Lp;       // (s+nN) x r, ld = s+nN
+  const zd* Up;       // r x (s+nN), ld = r
+  int32_t r, s, nsn, pad;
+  int64_t y_off;      // offset of this box's output in the scatter buffer
+};
+// forward sweep part 1 (per box): xR -= op(T) xS; y = op(P) xR (adjoint: T^H, Up^H)
+void launch_solve_fwd(const SolveBox* boxes, int nb, int rmax, zd* x, zd* y, int adjoint,
+                      hipStream_t st);
+// scatter: x[dst[d]] -= sum_{q in [ptr[d], ptr[d+1])} y[src[q]]
+void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
+                        const zd* y, zd* x, hipStream_t st);
+// diagonal: xR = Xi xR (adjoint: Xi^H xR), all boxes
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, hipStream_t st);
+// backward sweep (per box): xR -= op(P) x[SN]; xS -= op(T) xR
+void launch_solve_bwd(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, hipStream_t st);
+// top block: x[top] = Ainv x[top] (or Ainv^H)
+void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
+                      hipStream_t st);
+// permutations between original and tree order, scaled copy
+void launch_permute(const zd* src, zd* dst, const int64_t* map, int64_t n, int gather,
+                    hipStream_t st);
+
+// ---- stand-alone block of A~ (rows, cols: tree positions) ----
+void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64_t* cols,
+                  int64_t nc, zd* out, hipStream_t st);
+
+// ---- exact matvec on the fly ----
+void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, hipStream_t st);
+
+}  // namespace fmmlu

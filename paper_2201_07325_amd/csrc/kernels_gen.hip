@@ -1,0 +1,301 @@
+// Kernel-entry generation: pair-tile assembly, the ID matrix with its proxy rows, the
+// stand-alone block generator and the exact on-the-fly matvec.
+//
+// Entries follow Section 3 (eqs. disc1, disc3, comb_ref) with plain smooth weights:
+//   A~_ii = 1/2,  A~_ij = sqrt(w_i) K(x_i, x_j) sqrt(w_j),
+//   K(x, y) = e^{ik r} / (4 pi r^3) * [ (1 - ik r) (x - y).n(y) - i eta r^2 ],  r = |x - y|.
+// All generators are VALU-bound (one sincos, one sqrt and one division per entry); work is
+// split into 64x64 units so that a workgroup of 256 threads writes whole columns
+// (consecutive threads -> consecutive rows, coalesced stores).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace fmmlu {
+
+namespace {
+
+constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
+
+// A~[i, j] for tree positions i, j
+__device__ inline zd cfie_entry(const double* __restrict__ p, int64_t n, double k, double eta,
+                                int64_t i, int64_t j) {
+  if (i == j) return zd{0.5, 0.0};
+  double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double r = sqrt(r2);
+  double dn = dx * p[3 * n + j] + dy * p[4 * n + j] + dz * p[5 * n + j];
+  double s, c;
+  sincos(k * r, &s, &c);
+  double a = dn, b = k * r * dn + eta * r2;
+  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi / (r2 * r);
+  return zd{(c * a + s * b) * f, (s * a - c * b) * f};
+}
+
+// d/dk of A~[i, j] at fixed eta
+__device__ inline zd cfie_entry_dk(const double* __restrict__ p, int64_t n, double k, double eta,
+                                   int64_t i, int64_t j) {
+  if (i == j) return zd{0.0, 0.0};
+  double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double r = sqrt(r2);
+  double dn = dx * p[3 * n + j] + dy * p[4 * n + j] + dz * p[5 * n + j];
+  double s, c;
+  sincos(k * r, &s, &c);
+  // k e^{ikr} dn / (4 pi r)  +  eta r e^{ikr} / (4 pi r) = e^{ikr} (k dn + eta r) / (4 pi r)
+  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi / r;
+  double a = k * dn + eta * r;
+  return zd{c * a * f, s * a * f};
+}
+
+// d/deta of A~[i, j] = -i sqrt(w_i w_j) G
+__device__ inline zd cfie_entry_deta(const double* __restrict__ p, int64_t n, double k,
+                                     int64_t i, int64_t j) {
+  if (i == j) return zd{0.0, 0.0};
+  double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double s, c;
+  sincos(k * r, &s, &c);
+  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi / r;
+  return zd{s * f, -c * f};
+}
+
+template <class Task>
+__device__ inline int find_task(const Task* __restrict__ t, int n, int64_t u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (t[mid].unit_begin <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) assemble_kernel(DevGeom g, const AsmTask* __restrict__ tasks,
+                                                       int ntasks, const int32_t* __restrict__ slot,
+                                                       const int32_t* __restrict__ idx,
+                                                       const int64_t* __restrict__ dof,
+                                                       const AsmSrc* __restrict__ table,
+                                                       const zd* __restrict__ src, zd* __restrict__ dst) {
+  const int64_t u = blockIdx.x;
+  const int ti = find_task(tasks, ntasks, u);
+  const AsmTask t = tasks[ti];
+  const int64_t lu = u - t.unit_begin;
+  const int nbr = (t.nr + 63) >> 6;
+  const int bi = (int)(lu % nbr), bj = (int)(lu / nbr);
+  const int i = bi * 64 + (threadIdx.x & 63);
+  if (i >= t.nr) return;
+  const int rs = slot[t.rmap_off + i];
+  const int ri = idx[t.rmap_off + i];
+  const int64_t rd = dof[t.rdof_off + i];
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+    if (j >= t.nc) break;
+    const int cs = slot[t.cmap_off + j];
+    const AsmSrc sr = table[t.tab_off + (int64_t)rs * t.nsc + cs];
+    zd v;
+    if (sr.off >= 0) {
+      v = src[sr.off + ri + (int64_t)idx[t.cmap_off + j] * sr.ld];
+    } else {
+      v = cfie_entry(g.p, g.n, g.k, g.eta, rd, dof[t.cdof_off + j]);
+    }
+    dst[t.out_off + i + (int64_t)j * t.ld] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) idmatrix_kernel(DevGeom g, const IdTask* __restrict__ tasks,
+                                                       int ntasks, const QSeg* __restrict__ segs,
+                                                       const int64_t* __restrict__ dof,
+                                                       const zd* __restrict__ pool) {
+  const int64_t u = blockIdx.x;
+  const int ti = find_task(tasks, ntasks, u);
+  const IdTask t = tasks[ti];
+  const int64_t lu = u - t.unit_begin;
+  const int nbr = (t.rows + 63) >> 6;
+  const int bi = (int)(lu % nbr), bj = (int)(lu / nbr);
+  const int i = bi * 64 + (threadIdx.x & 63);
+  if (i >= t.rows) return;
+  const double* p = g.p;
+  const int64_t n = g.n;
+  zd* out = t.M;
+  if (i < 2 * t.nq) {
+    const bool transposed = i >= t.nq;
+    const int iq = transposed ? i - t.nq : i;
+    // segment containing row iq
+    int lo = 0, hi = t.nseg - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (segs[t.seg_off + mid].row0 <= iq)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const QSeg sg = segs[t.seg_off + lo];
+    const int li = sg.live[iq - sg.row0];
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+      if (j >= t.m) break;
+      zd v = transposed ? pool[sg.tile_bq + j + (int64_t)li * t.m]
+                        : pool[sg.tile_qb + li + (int64_t)j * sg.ld];
+      out[i + (int64_t)j * t.rows] = v;
+    }
+    return;
+  }
+  // proxy row: Fibonacci point l on the sphere of the given centre and radius
+  const bool incoming = i >= 2 * t.nq + t.ngamma;
+  const int l = incoming ? i - 2 * t.nq - t.ngamma : i - 2 * t.nq;
+  const double golden = M_PI * (3.0 - sqrt(5.0));
+  const double z = 1.0 - (2.0 * l + 1.0) / t.ngamma;
+  const double phi = l * golden;
+  const double rr = sqrt(fmax(0.0, 1.0 - z * z));
+  double sp, cp;
+  sincos(phi, &sp, &cp);
+  const double yx = t.cx + t.radius * (rr * cp);
+  const double yy = t.cy + t.radius * (rr * sp);
+  const double yz = t.cz + t.radius * z;
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+    if (j >= t.m) break;
+    const int64_t q = dof[t.dof_off + j];
+    const double dx = yx - p[q], dy = yy - p[n + q], dz = yz - p[2 * n + q];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double r = sqrt(r2);
+    double s, c;
+    sincos(g.k * r, &s, &c);
+    const double sw = p[6 * n + q] * t.wgamma;
+    zd v;
+    if (incoming) {
+      // G(x_j, y_l) sqrt(w_j)
+      const double f = sw * kInv4Pi / r;
+      v = zd{c * f, s * f};
+    } else {
+      // K(y_l, x_j) sqrt(w_j), source normal n_j
+      const double dn = dx * p[3 * n + q] + dy * p[4 * n + q] + dz * p[5 * n + q];
+      const double a = dn, b = g.k * r * dn + g.eta * r2;
+      const double f = sw * kInv4Pi / (r2 * r);
+      v = zd{(c * a + s * b) * f, (s * a - c * b) * f};
+    }
+    out[i + (int64_t)j * t.rows] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) block_kernel(DevGeom g, const int64_t* __restrict__ rows,
+                                                    int64_t nr, const int64_t* __restrict__ cols,
+                                                    int64_t nc, zd* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nr * nc) return;
+  const int64_t i = e % nr, j = e / nr;
+  out[e] = cfie_entry(g.p, g.n, g.k, g.eta, rows[i], cols[j]);
+}
+
+// ---------------------------------------------------------------------------------------
+// Exact matvec: each workgroup owns 256 target rows and streams all sources through LDS.
+// op 0: y = A~ x; 1: y = A~^H x; 2: y = dA~/dk x; 3: y = dA~/deta x. Vectors in tree order.
+__global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, int op, const zd* __restrict__ x,
+                                                     zd* __restrict__ y) {
+  __shared__ double sp[7][256];
+  __shared__ zd sx[256];
+  const int64_t n = g.n;
+  const double* p = g.p;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool live = i < n;
+  double xi[7];
+  for (int a = 0; a < 7; ++a) xi[a] = live ? p[a * n + i] : 0.0;
+  double are = 0.0, aim = 0.0;
+  for (int64_t j0 = 0; j0 < n; j0 += 256) {
+    __syncthreads();
+    const int64_t jl = j0 + threadIdx.x;
+    for (int a = 0; a < 7; ++a) sp[a][threadIdx.x] = jl < n ? p[a * n + jl] : 0.0;
+    sx[threadIdx.x] = jl < n ? x[jl] : zd{0.0, 0.0};
+    __syncthreads();
+    const int cnt = (int)min<int64_t>(256, n - j0);
+    if (!live) continue;
+    for (int jj = 0; jj < cnt; ++jj) {
+      const int64_t j = j0 + jj;
+      if (j == i) {
+        if (op <= 1) {
+          are += 0.5 * sx[jj].re;
+          aim += 0.5 * sx[jj].im;
+        }
+        continue;
+      }
+      double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
+      double r2 = dx * dx + dy * dy + dz * dz;
+      double r = sqrt(r2);
+      double s, c;
+      sincos(g.k * r, &s, &c);
+      double w = xi[6] * sp[6][jj] * kInv4Pi;
+      double vr, vi;
+      if (op == 0) {
+        double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
+        double a = dn, b = g.k * r * dn + g.eta * r2;
+        double f = w / (r2 * r);
+        vr = (c * a + s * b) * f;
+        vi = (s * a - c * b) * f;
+      } else if (op == 1) {
+        // conj(A~[j, i]): target j, source i with normal n_i; d = x_j - x_i = -(dx, dy, dz)
+        double dn = -(dx * xi[3] + dy * xi[4] + dz * xi[5]);
+        double a = dn, b = g.k * r * dn + g.eta * r2;
+        double f = w / (r2 * r);
+        vr = (c * a + s * b) * f;
+        vi = -(s * a - c * b) * f;
+      } else if (op == 2) {
+        double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
+        double a = g.k * dn + g.eta * r;
+        double f = w / r;
+        vr = c * a * f;
+        vi = s * a * f;
+      } else {
+        double f = w / r;
+        vr = s * f;
+        vi = -c * f;
+      }
+      const zd xv = sx[jj];
+      are += vr * xv.re - vi * xv.im;
+      aim += vr * xv.im + vi * xv.re;
+    }
+  }
+  if (live) y[i] = zd{are, aim};
+}
+
+}  // namespace
+
+void launch_assemble(const DevGeom& g, const AsmTask* tasks, int ntasks, int64_t nunits,
+                     const int32_t* slot, const int32_t* idx, const int64_t* dof,
+                     const AsmSrc* table, const zd* src_pool, zd* dst_pool, hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)nunits), dim3(256), 0, st, g, tasks, ntasks,
+                     slot, idx, dof, table, src_pool, dst_pool);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_build_idmatrix(const DevGeom& g, const IdTask* tasks, int ntasks, int64_t nunits,
+                           const QSeg* segs, const int64_t* dof, const zd* pool, hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  hipLaunchKernelGGL(idmatrix_kernel, dim3((unsigned)nunits), dim3(256), 0, st, g, tasks, ntasks,
+                     segs, dof, pool);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64_t* cols,
+                  int64_t nc, zd* out, hipStream_t st) {
+  int64_t tot = nr * nc;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(block_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g, rows,
+                     nr, cols, nc, out);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, hipStream_t st) {
+  if (g.n <= 0) return;
+  hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, g, op,
+                     x, y);
+  FMMLU_HIP(hipGetLastError());
+}
+
+}  // namespace fmmlu

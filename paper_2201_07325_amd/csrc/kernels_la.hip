@@ -1,0 +1,720 @@
+// Batched dense linear algebra on complex float64 for uneven sizes: GEMM with segments and
+// scatter maps, Householder panel QR (compact WY), greedy column-pivoted QR on a square
+// factor, Gauss-Jordan inversion with partial pivoting, and block gathers.
+//
+// All matrices are column-major. Workgroups are 256 threads (four 64-wide wavefronts);
+// reductions go through wavefront shuffles first and LDS second.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace fmmlu {
+
+namespace {
+
+template <class Task>
+__device__ inline int find_task(const Task* __restrict__ t, int n, int64_t u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (t[mid].unit_begin <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of a complex value over the 256-thread block; result broadcast to all threads.
+__device__ inline zd block_sum(zd v, zd* red /* >= 4 */) {
+  v.re = wave_sum(v.re);
+  v.im = wave_sum(v.im);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  zd s = red[0];
+  for (int i = 1; i < 4; ++i) s = zadd(s, red[i]);
+  __syncthreads();
+  return s;
+}
+
+__device__ inline double block_sum_d(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------
+// GEMM: 256 threads as 16 x 16, each thread a TM x TN micro-tile, block (16 TM) x (16 TN),
+// K staged through LDS in steps of 16.
+template <int OPA, int TM, int TN>
+__global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ tasks, int ntasks,
+                                                   const GemmSeg* __restrict__ segs) {
+  constexpr int BM = 16 * TM, BN = 16 * TN, BK = 16;
+  __shared__ zd As[BK][BM + 1];
+  __shared__ zd Bs[BK][BN + 1];
+  const int64_t u = blockIdx.x;
+  const int ti = find_task(tasks, ntasks, u);
+  const GemmTask t = tasks[ti];
+  const int64_t lu = u - t.unit_begin;
+  const int nbm = (t.M + BM - 1) / BM;
+  const int bm = (int)(lu % nbm), bn = (int)(lu / nbm);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  zd acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = zd{0.0, 0.0};
+  const int row0 = bm * BM, col0 = bn * BN;
+  for (int sidx = 0; sidx < t.nseg; ++sidx) {
+    const GemmSeg sg = segs[t.seg_begin + sidx];
+    for (int k0 = 0; k0 < sg.K; k0 += BK) {
+      // A tile: BM x BK
+      for (int e = threadIdx.x; e < BM * BK; e += 256) {
+        int i, kk;
+        if (OPA == 0) {
+          i = e % BM;
+          kk = e / BM;
+        } else {
+          kk = e % BK;
+          i = e / BK;
+        }
+        const int gi = row0 + i, gk = k0 + kk;
+        zd v{0.0, 0.0};
+        if (gi < t.M && gk < sg.K) {
+          if (OPA == 0)
+            v = sg.A[gi + (int64_t)gk * sg.lda];
+          else {
+            v = sg.A[gk + (int64_t)gi * sg.lda];
+            if (OPA == 2) v.im = -v.im;
+          }
+        }
+        As[kk][i] = v;
+      }
+      // B tile: BK x BN
+      for (int e = threadIdx.x; e < BK * BN; e += 256) {
+        const int kk = e % BK, j = e / BK;
+        const int gk = k0 + kk, gj = col0 + j;
+        zd v{0.0, 0.0};
+        if (gk < sg.K && gj < t.N) v = sg.B[gk + (int64_t)gj * sg.ldb];
+        Bs[kk][j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < BK; ++kk) {
+        zd a[TM], b[TN];
+#pragma unroll
+        for (int q = 0; q < TM; ++q) a[q] = As[kk][ty + 16 * q];
+#pragma unroll
+        for (int q = 0; q < TN; ++q) b[q] = Bs[kk][tx + 16 * q];
+#pragma unroll
+        for (int qa = 0; qa < TM; ++qa)
+#pragma unroll
+          for (int qb = 0; qb < TN; ++qb) zfma(acc[qa][qb], a[qa], b[qb]);
+      }
+      __syncthreads();
+    }
+  }
+  const zd alpha{t.alpha_re, t.alpha_im};
+#pragma unroll
+  for (int qa = 0; qa < TM; ++qa) {
+    const int i = row0 + ty + 16 * qa;
+    if (i >= t.M) continue;
+    const int ri = t.rmap ? t.rmap[i] : i;
+#pragma unroll
+    for (int qb = 0; qb < TN; ++qb) {
+      const int j = col0 + tx + 16 * qb;
+      if (j >= t.N) continue;
+      const int cj = t.cmap ? t.cmap[j] : j;
+      zd* c = t.C + ri + (int64_t)cj * t.ldc;
+      zd v = zmul(alpha, acc[qa][qb]);
+      if (t.beta != 0.0) v = zadd(v, zscale(*c, t.beta));
+      *c = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Householder QR of the panel A[j0:rows, j0:j0+nb]. Reflector H = I - tau v v^H with
+// v = x + e^{i arg x0} |x| e_1 and tau = 2 / |v|^2 (Hermitian, unitary); H x = -e^{i arg x0}|x| e_1.
+// The product H_1 ... H_nb = I - V Tw V^H (compact WY, forward). V is written explicitly.
+constexpr int kQrMaxNb = 32;
+__global__ void __launch_bounds__(256) qr_panel_kernel(const QrTask* __restrict__ tasks) {
+  const QrTask t = tasks[blockIdx.x];
+  __shared__ zd red[4];
+  __shared__ zd dots[2 * kQrMaxNb];
+  __shared__ zd sh_v0;
+  __shared__ double sh_tau;
+  __shared__ zd sh_beta;
+  const int L = t.rows - t.j0;  // panel height
+  const int nb = t.nb;
+  zd* A = t.A;
+  const int64_t lda = t.lda;
+  const int ldv = L;
+  // zero the Tw block
+  for (int e = threadIdx.x; e < nb * nb; e += 256) t.Tw[e] = zd{0.0, 0.0};
+  for (int j = 0; j < nb; ++j) {
+    const int col = t.j0 + j;
+    zd* x = A + col + (int64_t)col * lda;  // x[0 .. len)
+    const int len = t.rows - col;
+    // column of V (explicit; zeros above row j of the panel)
+    zd* vj = t.V + (int64_t)j * ldv;
+    if (len <= 0) {
+      for (int i = threadIdx.x; i < L; i += 256) vj[i] = zd{0.0, 0.0};
+      continue;
+    }
+    double ss = 0.0;
+    for (int i = threadIdx.x; i < len; i += 256) ss += zabs2(x[i]);
+    __shared__ double redd[4];
+    ss = block_sum_d(ss, redd);
+    if (threadIdx.x == 0) {
+      const zd a = x[0];
+      const double nrm = sqrt(ss);
+      const double aa = sqrt(zabs2(a));
+      const zd ph = aa > 0.0 ? zd{a.re / aa, a.im / aa} : zd{1.0, 0.0};
+      const zd v0 = zd{a.re + ph.re * nrm, a.im + ph.im * nrm};
+      const double vn2 = ss - zabs2(a) + zabs2(v0);
+      sh_v0 = v0;
+      sh_tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      sh_beta = zd{-ph.re * nrm, -ph.im * nrm};
+    }
+    __syncthreads();
+    const zd v0 = sh_v0;
+    const double tau = sh_tau;
+    // dots: with remaining panel columns c = j+1..nb-1 (index c) and with previous V
+    // columns l < j (index nb + l)
+    zd part[2 * kQrMaxNb];
+    const int nrem = nb - j - 1;
+    for (int c = 0; c < nrem + j; ++c) part[c] = zd{0.0, 0.0};
+    for (int i = threadIdx.x; i < len; i += 256) {
+      const zd vi = (i == 0) ? v0 : x[i];
+      for (int c = 0; c < nrem; ++c) zfmac(part[c], vi, x[i + (int64_t)(c + 1) * lda]);
+      for (int l = 0; l < j; ++l) zfmac(part[nrem + l], t.V[(int64_t)l * ldv + j + i], vi);
+    }
+    for (int c = 0; c < nrem + j; ++c) {
+      zd s = block_sum(part[c], red);
+      if (threadIdx.x == 0) dots[c] = s;
+    }
+    __syncthreads();
+    // update remaining panel columns: c -= tau v (v^H c)
+    for (int i = threadIdx.x; i < len; i += 256) {
+      const zd vi = (i == 0) ? v0 : x[i];
+      for (int c = 0; c < nrem; ++c) {
+        zd* p = x + i + (int64_t)(c + 1) * lda;
+        const zd f = zscale(zmul(vi, dots[c]), tau);
+        *p = zsub(*p, f);
+      }
+    }
+    // write V column j (explicit), then overwrite x with R's column
+    for (int i = threadIdx.x; i < L; i += 256) {
+      zd v;
+      if (i < j)
+        v = zd{0.0, 0.0};
+      else if (i == j)
+        v = v0;
+      else
+        v = x[i - j];
+      vj[i] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += 256) x[i] = (i == 0) ? sh_beta : zd{0.0, 0.0};
+    // Tw(0:j, j) = -tau Tw(0:j, 0:j) w,  w_l = V_l^H v ;  Tw(j, j) = tau
+    if (threadIdx.x == 0) {
+      for (int r = 0; r < j; ++r) {
+        zd s{0.0, 0.0};
+        for (int l = r; l < j; ++l) zfma(s, t.Tw[r + l * nb], dots[nrem + l]);
+        t.Tw[r + j * nb] = zscale(s, -tau);
+      }
+      t.Tw[j + j * nb] = zd{tau, 0.0};
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Greedy CPQR of an m x m matrix in place with exact column norms at every step, then
+// T = R11^{-1} R12 (ld m). Ties in the norm go to the lowest original column index.
+__global__ void __launch_bounds__(256) cpqr_kernel(const CpqrTask* __restrict__ tasks, double eps) {
+  const CpqrTask t = tasks[blockIdx.x];
+  const int m = t.m;
+  const int64_t lda = t.lda;
+  zd* R = t.R;
+  __shared__ double bestv[256];
+  __shared__ int besti[256];
+  __shared__ int bestp[256];
+  __shared__ int sh_piv, sh_stop;
+  __shared__ double sh_r00;
+  __shared__ zd sh_v0, sh_beta;
+  __shared__ double sh_tau;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = threadIdx.x; j < m; j += 256) t.perm[j] = j;
+  __syncthreads();
+  int s = m;
+  for (int k = 0; k < m; ++k) {
+    // exact norms^2 of columns k..m-1 over rows k..m-1; wave per column
+    double mybest = -1.0;
+    int myi = -1, myp = 0x7fffffff;
+    for (int c = k + wave; c < m; c += 4) {
+      double acc = 0.0;
+      const zd* col = R + (int64_t)c * lda;
+      for (int i = k + lane; i < m; i += 64) acc += zabs2(col[i]);
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        const int pc = t.perm[c];
+        if (acc > mybest || (acc == mybest && pc < myp)) {
+          mybest = acc;
+          myi = c;
+          myp = pc;
+        }
+      }
+    }
+    if (lane == 0) {
+      bestv[wave] = mybest;
+      besti[wave] = myi;
+      bestp[wave] = myp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double bv = -1.0;
+      int bi = -1, bp = 0x7fffffff;
+      for (int w = 0; w < 4; ++w) {
+        if (besti[w] < 0) continue;
+        if (bestv[w] > bv || (bestv[w] == bv && bestp[w] < bp)) {
+          bv = bestv[w];
+          bi = besti[w];
+          bp = bestp[w];
+        }
+      }
+      const double nk = sqrt(bv);
+      int stop = 0;
+      if (k == 0) {
+        sh_r00 = nk;
+        if (nk == 0.0) stop = 1;
+      } else if (nk <= eps * sh_r00) {
+        stop = 1;
+      }
+      sh_stop = stop;
+      sh_piv = bi;
+    }
+    __syncthreads();
+    if (sh_stop) {
+      s = k;
+      break;
+    }
+    const int p = sh_piv;
+    if (p != k) {
+      for (int i = threadIdx.x; i < m; i += 256) {
+        zd a = R[i + (int64_t)k * lda];
+        R[i + (int64_t)k * lda] = R[i + (int64_t)p * lda];
+        R[i + (int64_t)p * lda] = a;
+      }
+      if (threadIdx.x == 0) {
+        int q = t.perm[k];
+        t.perm[k] = t.perm[p];
+        t.perm[p] = q;
+      }
+    }
+    __syncthreads();
+    zd* x = R + k + (int64_t)k * lda;
+    const int len = m - k;
+    if (threadIdx.x == 0) {
+      double ss = 0.0;
+      for (int i = 0; i < len; ++i) ss += zabs2(x[i]);
+      const zd a = x[0];
+      const double nrm = sqrt(ss);
+      const double aa = sqrt(zabs2(a));
+      const zd ph = aa > 0.0 ? zd{a.re / aa, a.im / aa} : zd{1.0, 0.0};
+      const zd v0 = zd{a.re + ph.re * nrm, a.im + ph.im * nrm};
+      const double vn2 = ss - zabs2(a) + zabs2(v0);
+      sh_v0 = v0;
+      sh_tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      sh_beta = zd{-ph.re * nrm, -ph.im * nrm};
+    }
+    __syncthreads();
+    const zd v0 = sh_v0;
+    const double tau = sh_tau;
+    // apply to columns k+1..m-1, wave per column
+    for (int c = k + 1 + wave; c < m; c += 4) {
+      zd* col = R + k + (int64_t)c * lda;
+      zd d{0.0, 0.0};
+      for (int i = lane; i < len; i += 64) zfmac(d, (i == 0) ? v0 : x[i], col[i]);
+      d.re = wave_sum(d.re);
+      d.im = wave_sum(d.im);
+      const zd f = zscale(d, tau);
+      for (int i = lane; i < len; i += 64) col[i] = zsub(col[i], zmul((i == 0) ? v0 : x[i], f));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < len; i += 256) x[i] = (i == 0) ? sh_beta : zd{0.0, 0.0};
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *t.rank = s;
+  // T = R11^{-1} R12 (s x (m - s)): one thread per right-hand side column, back substitution
+  __syncthreads();
+  for (int c = threadIdx.x; c < m - s; c += 256) {
+    zd* tc = t.T + (int64_t)c * m;
+    const zd* rc = R + (int64_t)(s + c) * lda;
+    for (int i = 0; i < s; ++i) tc[i] = rc[i];
+    for (int i = s - 1; i >= 0; --i) {
+      const zd ti = zdiv(tc[i], R[i + (int64_t)i * lda]);
+      tc[i] = ti;
+      for (int r = 0; r < i; ++r) tc[r] = zsub(tc[r], zmul(R[r + (int64_t)i * lda], ti));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Gauss-Jordan inversion with partial pivoting, blocked by column panels of kGjNb.
+constexpr int kGjNb = 16;
+
+// Panel: columns J = [j0, j0+nb) of all n rows; pivot rows searched among rows >= column.
+__global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict__ tasks, int j0) {
+  const GjTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  if (j0 >= n) return;
+  const int nb = min(kGjNb, n - j0);
+  const int64_t lda = t.lda;
+  zd* A = t.A;
+  __shared__ double bv[4];
+  __shared__ int bi[4];
+  __shared__ zd rowg[kGjNb];
+  __shared__ zd sh_inv;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = 0; j < nb; ++j) {
+    const int gc = j0 + j;
+    // pivot search
+    double best = -1.0;
+    int besti = 0x7fffffff;
+    for (int i = gc + threadIdx.x; i < n; i += 256) {
+      const double v = zabs2(A[i + (int64_t)gc * lda]);
+      if (v > best) {
+        best = v;
+        besti = i;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(besti, o, 64);
+      if (ov > best || (ov == best && oi < besti)) {
+        best = ov;
+        besti = oi;
+      }
+    }
+    if (lane == 0) {
+      bv[wave] = best;
+      bi[wave] = besti;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double b = bv[0];
+      int p = bi[0];
+      for (int w = 1; w < 4; ++w)
+        if (bv[w] > b || (bv[w] == b && bi[w] < p)) {
+          b = bv[w];
+          p = bi[w];
+        }
+      if (p >= n) p = gc;
+      t.piv[gc] = p;
+      if (b <= 0.0 && *t.info == 0) *t.info = gc + 1;
+    }
+    __syncthreads();
+    const int p = t.piv[gc];
+    // swap rows gc and p inside the panel
+    if (p != gc && threadIdx.x < nb) {
+      const int c = j0 + threadIdx.x;
+      zd a = A[gc + (int64_t)c * lda];
+      A[gc + (int64_t)c * lda] = A[p + (int64_t)c * lda];
+      A[p + (int64_t)c * lda] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const zd piv = A[gc + (int64_t)gc * lda];
+      sh_inv = (zabs2(piv) > 0.0) ? zdiv(zd{1.0, 0.0}, piv) : zd{0.0, 0.0};
+    }
+    __syncthreads();
+    const zd inv = sh_inv;
+    // scale pivot row (panel columns other than gc)
+    if (threadIdx.x < nb) {
+      const int c = j0 + threadIdx.x;
+      zd v = A[gc + (int64_t)c * lda];
+      if (c != gc) v = zmul(v, inv);
+      rowg[threadIdx.x] = v;
+      if (c != gc) A[gc + (int64_t)c * lda] = v;
+    }
+    __syncthreads();
+    // eliminate column gc from the other rows
+    for (int i = threadIdx.x; i < n; i += 256) {
+      if (i == gc) continue;
+      zd* ai = A + i;
+      const zd f = ai[(int64_t)gc * lda];
+      for (int q = 0; q < nb; ++q) {
+        const int c = j0 + q;
+        if (c == gc) continue;
+        ai[(int64_t)c * lda] = zsub(ai[(int64_t)c * lda], zmul(f, rowg[q]));
+      }
+      ai[(int64_t)gc * lda] = zd{-(f.re * inv.re - f.im * inv.im), -(f.re * inv.im + f.im * inv.re)};
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A[gc + (int64_t)gc * lda] = inv;
+    __syncthreads();
+  }
+}
+
+// Row swaps of the panel applied to columns outside J. grid.x = task, grid.y = column chunk.
+__global__ void __launch_bounds__(256) gj_swaps_kernel(const GjTask* __restrict__ tasks, int j0) {
+  const GjTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  if (j0 >= n) return;
+  const int nb = min(kGjNb, n - j0);
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  if (c >= n || (c >= j0 && c < j0 + nb)) return;
+  zd* col = t.A + (int64_t)c * t.lda;
+  for (int q = 0; q < nb; ++q) {
+    const int gc = j0 + q, p = t.piv[gc];
+    if (p != gc) {
+      zd a = col[gc];
+      col[gc] = col[p];
+      col[p] = a;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) gj_copyrow_kernel(const GjTask* __restrict__ tasks, int j0,
+                                                         zd* const* __restrict__ W) {
+  const GjTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  if (j0 >= n) return;
+  const int nb = min(kGjNb, n - j0);
+  const int c = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int q = threadIdx.x & 15;
+  if (c >= n || q >= nb) return;
+  W[blockIdx.x][q + (int64_t)c * nb] = t.A[(j0 + q) + (int64_t)c * t.lda];
+}
+
+__global__ void __launch_bounds__(256) gj_fixrow_kernel(const GjTask* __restrict__ tasks, int j0,
+                                                        zd* const* __restrict__ W) {
+  const GjTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  if (j0 >= n) return;
+  const int nb = min(kGjNb, n - j0);
+  const int c = blockIdx.y * 16 + (threadIdx.x >> 4);
+  const int q = threadIdx.x & 15;
+  if (c >= n || q >= nb || (c >= j0 && c < j0 + nb)) return;
+  zd* a = t.A + (j0 + q) + (int64_t)c * t.lda;
+  *a = zsub(*a, W[blockIdx.x][q + (int64_t)c * nb]);
+}
+
+// Compose the column permutation (one thread per task) then gather columns into out.
+__global__ void gj_compose_kernel(const GjTask* __restrict__ tasks, int32_t* const* __restrict__ work) {
+  const GjTask t = tasks[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  int32_t* idx = work[blockIdx.x];
+  for (int j = 0; j < t.n; ++j) idx[j] = j;
+  for (int gc = t.n - 1; gc >= 0; --gc) {
+    const int p = t.piv[gc];
+    const int a = idx[gc];
+    idx[gc] = idx[p];
+    idx[p] = a;
+  }
+}
+__global__ void __launch_bounds__(256) gj_gather_kernel(const GjTask* __restrict__ tasks,
+                                                        zd* const* __restrict__ out,
+                                                        int32_t* const* __restrict__ work) {
+  const GjTask t = tasks[blockIdx.x];
+  const int j = blockIdx.y;
+  if (j >= t.n) return;
+  const int src = work[blockIdx.x][j];
+  const zd* a = t.A + (int64_t)src * t.lda;
+  zd* o = out[blockIdx.x] + (int64_t)j * t.n;
+  for (int i = threadIdx.x; i < t.n; i += 256) o[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------------------
+__device__ inline int seg_of(const NSeg* __restrict__ segs, int64_t base, int nseg, int pos) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (segs[base + mid].off <= pos)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(256) cross_kernel(const CrossTask* __restrict__ tasks, int ntasks,
+                                                    const NSeg* __restrict__ segs,
+                                                    const zd* __restrict__ pool) {
+  const int64_t u = blockIdx.x;
+  const int ti = find_task(tasks, ntasks, u);
+  const CrossTask t = tasks[ti];
+  int64_t lu = u - t.unit_begin;
+  const int m = t.m, mn = t.m + t.nN, s = t.s, r = t.m - t.s;
+  const int ucol_r = (mn + 63) >> 6, ucol_c = (m + 63) >> 6;
+  const int64_t ncol_units = (int64_t)ucol_r * ucol_c;
+  const zd* bb = pool + t.tile_bb;
+  if (lu < ncol_units) {
+    // Ccol: rows (R, S, N), cols (S, R) = perm order
+    const int bi = (int)(lu % ucol_r), bj = (int)(lu / ucol_r);
+    const int i = bi * 64 + (threadIdx.x & 63);
+    if (i >= mn) return;
+    int pi = 0;
+    const NSeg* sg = nullptr;
+    int li = 0;
+    if (i < m) {
+      pi = (i < r) ? t.perm[s + i] : t.perm[i - r];
+    } else {
+      sg = segs + t.seg_off + seg_of(segs, t.seg_off, t.nseg, i - m);
+      li = sg->live[i - m - sg->off];
+    }
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+      if (j >= m) break;
+      const int pj = t.perm[j];
+      zd v = (i < m) ? bb[pi + (int64_t)pj * m] : pool[sg->tile_nb + li + (int64_t)pj * sg->ld];
+      t.Ccol[i + (int64_t)j * mn] = v;
+    }
+  } else {
+    lu -= ncol_units;
+    // Crow: rows (S, R) = perm order, cols (R, S, N)
+    const int urow_r = (m + 63) >> 6;
+    const int bi = (int)(lu % urow_r), bj = (int)(lu / urow_r);
+    const int i = bi * 64 + (threadIdx.x & 63);
+    if (i >= m) return;
+    const int pi = t.perm[i];
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+      if (j >= mn) break;
+      zd v;
+      if (j < m) {
+        const int pj = (j < r) ? t.perm[s + j] : t.perm[j - r];
+        v = bb[pi + (int64_t)pj * m];
+      } else {
+        const NSeg& sg = segs[t.seg_off + seg_of(segs, t.seg_off, t.nseg, j - m)];
+        v = pool[sg.tile_bn + pi + (int64_t)sg.live[j - m - sg.off] * m];
+      }
+      t.Crow[i + (int64_t)j * m] = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) extract_r_kernel(const ExtractTask* __restrict__ tasks) {
+  const ExtractTask t = tasks[blockIdx.x];
+  const int j = blockIdx.y;
+  if (j >= t.m) return;
+  for (int i = threadIdx.x; i < t.m; i += 256) {
+    zd v{0.0, 0.0};
+    if (i <= j && i < t.rows) v = t.M[i + (int64_t)j * t.rows];
+    t.R[i + (int64_t)j * t.m] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) copy_kernel(const CopyTask* __restrict__ tasks, int ntasks) {
+  const int64_t u = blockIdx.x;
+  const int ti = find_task(tasks, ntasks, u);
+  const CopyTask t = tasks[ti];
+  const int64_t lu = u - t.unit_begin;
+  const int nbr = (t.rows + 63) >> 6;
+  const int bi = (int)(lu % nbr), bj = (int)(lu / nbr);
+  const int i = bi * 64 + (threadIdx.x & 63);
+  if (i >= t.rows) return;
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+    if (j >= t.cols) break;
+    t.dst[i + (int64_t)j * t.ldd] = t.src[i + (int64_t)j * t.lds];
+  }
+}
+
+}  // namespace
+
+void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
+                 hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  dim3 g((unsigned)nunits), b(256);
+  // 32 x 32 blocks (2 x 2 per thread); units must be counted with gemm_units(.., 32)
+  if (opA == 0)
+    hipLaunchKernelGGL((gemm_kernel<0, 2, 2>), g, b, 0, st, tasks, ntasks, segs);
+  else if (opA == 1)
+    hipLaunchKernelGGL((gemm_kernel<1, 2, 2>), g, b, 0, st, tasks, ntasks, segs);
+  else
+    hipLaunchKernelGGL((gemm_kernel<2, 2, 2>), g, b, 0, st, tasks, ntasks, segs);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_qr_panel(const QrTask* tasks, int ntasks, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(qr_panel_kernel, dim3(ntasks), dim3(256), 0, st, tasks);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_cpqr(const CpqrTask* tasks, int ntasks, double eps, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(cpqr_kernel, dim3(ntasks), dim3(256), 0, st, tasks, eps);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(gj_panel_kernel, dim3(ntasks), dim3(256), 0, st, tasks, j0);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(gj_swaps_kernel, dim3(ntasks, (nmax + 255) / 256), dim3(256), 0, st, tasks, j0);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gj_copyrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,
+                       hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(gj_copyrow_kernel, dim3(ntasks, (nmax + 15) / 16), dim3(256), 0, st, tasks, j0, W);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gj_fixrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,
+                      hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(gj_fixrow_kernel, dim3(ntasks, (nmax + 15) / 16), dim3(256), 0, st, tasks, j0, W);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gj_unpermute(const GjTask* tasks, int ntasks, int nmax, zd* const* out,
+                         int32_t* const* work, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(gj_compose_kernel, dim3(ntasks), dim3(64), 0, st, tasks, work);
+  FMMLU_HIP(hipGetLastError());
+  hipLaunchKernelGGL(gj_gather_kernel, dim3(ntasks, nmax), dim3(256), 0, st, tasks, out, work);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gather_cross(const CrossTask* tasks, int ntasks, int64_t nunits, const NSeg* segs,
+                         const zd* pool, hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  hipLaunchKernelGGL(cross_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks, segs, pool);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_extract_r(const ExtractTask* tasks, int ntasks, int mmax, hipStream_t st) {
+  if (ntasks <= 0 || mmax <= 0) return;
+  hipLaunchKernelGGL(extract_r_kernel, dim3(ntasks, mmax), dim3(256), 0, st, tasks);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
+  FMMLU_HIP(hipGetLastError());
+}
+
+}  // namespace fmmlu
