@@ -63,7 +63,10 @@ typedef struct {
   int32_t precision;          /* fmmlu_precision */
   int64_t device_mem_cap;     /* bytes of device memory the factorization may hold; 0 = no cap */
   int32_t verbose;            /* 0 silent, 1 per-level summary on stderr */
-  int32_t reserved[7];
+  int32_t profile;            /* 1: time each kernel class with HIP events (fmmlu_factor_profile) */
+  int32_t id_route;           /* greedy CPQR route: 0 auto (Gram matrix when eps >= 1e-7, else
+                                 Householder), 1 Gram matrix + pivoted Cholesky, 2 Householder QR */
+  int32_t reserved[5];
 } fmmlu_opts;
 
 /* Per-factorization statistics. */
@@ -164,6 +167,19 @@ fmmlu_status fmmlu_factor_info(fmmlu_factor_h f, fmmlu_info* out);
  */
 fmmlu_status fmmlu_factor_boxes(fmmlu_factor_h f, int64_t* count, int32_t* level, int32_t* coord,
                                 int32_t* m, int32_t* s, int64_t* skel);
+
+/*
+ * Kernel-class profile of the factorization (only when opts.profile was set): for each of
+ * the FMMLU_NKCLASS classes (0 tile assembly, 1 ID-matrix generation, 2 Householder QR,
+ * 3 pivoted QR, 4 elimination GEMMs and gathers, 5 pivot-block inversion, 6 Schur update,
+ * 7 top block), ms[c] is the GPU time summed over HIP-event-bracketed launches on the
+ * factorization stream, launches[c] the number of brackets, flops[c] and bytes[c] the
+ * algorithmic work (complex multiply-add = 8 flops). Host arrays of FMMLU_NKCLASS entries;
+ * any may be NULL.
+ */
+#define FMMLU_NKCLASS 8
+fmmlu_status fmmlu_factor_profile(fmmlu_factor_h f, double* ms, int64_t* launches, double* flops,
+                                  double* bytes);
 
 void fmmlu_factor_destroy(fmmlu_factor_h f);
 

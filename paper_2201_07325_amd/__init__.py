@@ -34,7 +34,7 @@ class FmmluError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("proxy_radius", C.c_double), ("proxy_min_points", C.c_int32),
                 ("precision", C.c_int32), ("device_mem_cap", C.c_int64), ("verbose", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("profile", C.c_int32), ("id_route", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 class Info(C.Structure):
@@ -79,6 +79,7 @@ def lib():
         "fmmlu_factor_info": (I32, [P, C.POINTER(Info)]),
         "fmmlu_factor_boxes": (I32, [P, C.POINTER(I64), P, P, P, P, P]),
         "fmmlu_factor_destroy": (None, [P]),
+        "fmmlu_factor_profile": (I32, [P, P, P, P, P]),
         "fmmlu_kernel_block": (I32, [P, P, P, I64, D, D, P, I64, P, I64, P, P]),
         "fmmlu_last_error": (C.c_char_p, []),
     }
@@ -173,7 +174,8 @@ class Factor:
     """
 
     def __init__(self, points, normals, weights, k, eta, eps=1e-6, leaf_size=64, tree=None,
-                 proxy_radius=2.5, proxy_min_points=64, precision=0, verbose=0, mem_cap=0):
+                 proxy_radius=2.5, proxy_min_points=64, precision=0, verbose=0, mem_cap=0, profile=False,
+                 id_route=0):
         L = lib()
         self.points = _soa(points)
         self.n = self.points.size // 3
@@ -191,6 +193,8 @@ class Factor:
         o.precision = int(precision)
         o.verbose = int(verbose)
         o.device_mem_cap = int(mem_cap)
+        o.profile = 1 if profile else 0
+        o.id_route = int(id_route)
         h = P()
         _check(L.fmmlu_factor(self.tree.h, _ptr(self.points), _ptr(self.normals), _ptr(self.weights),
                               self.k, self.eta, C.byref(o), _stream(), C.byref(h)))
@@ -229,6 +233,21 @@ class Factor:
         inf = Info()
         _check(lib().fmmlu_factor_info(self.h, C.byref(inf)))
         return inf.as_dict()
+
+    KCLASSES = ["assemble", "id_matrix", "householder_qr", "pivoted_qr", "elimination", "pivot_inverse",
+                "schur_update", "top_block"]
+
+    def profile(self):
+        """Per kernel class: GPU ms (HIP events), brackets, algorithmic flops and bytes."""
+        nk = len(self.KCLASSES)
+        ms = np.zeros(nk)
+        la = np.zeros(nk, np.int64)
+        fl = np.zeros(nk)
+        by = np.zeros(nk)
+        _check(lib().fmmlu_factor_profile(self.h, ms.ctypes.data, la.ctypes.data, fl.ctypes.data,
+                                          by.ctypes.data))
+        return {k: {"ms": float(ms[i]), "launches": int(la[i]), "flops": float(fl[i]), "bytes": float(by[i])}
+                for i, k in enumerate(self.KCLASSES)}
 
     def boxes(self):
         cnt = I64()

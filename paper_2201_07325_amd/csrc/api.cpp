@@ -69,6 +69,8 @@ fmmlu_status fmmlu_default_opts(fmmlu_opts* opts) {
   opts->precision = FMMLU_FP64;
   opts->device_mem_cap = 0;
   opts->verbose = 0;
+  opts->profile = 0;
+  opts->id_route = 0;
   return FMMLU_OK;
 }
 
@@ -156,6 +158,7 @@ fmmlu_status fmmlu_factor(fmmlu_tree_h t, const double* xyz, const double* norma
   if (!(o.proxy_radius >= 1.5 && o.proxy_radius <= 10.0))
     return fail(FMMLU_EINVAL, "proxy_radius must be in [1.5, 10]");
   if (o.proxy_min_points < 1) return fail(FMMLU_EINVAL, "proxy_min_points must be >= 1");
+  if (o.id_route < 0 || o.id_route > 2) return fail(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
   if (o.precision != FMMLU_FP64) return fail(FMMLU_EINVAL, "only FMMLU_FP64 is available in this build");
   const int64_t n = t->t.n;
   return guarded([&] {
@@ -215,12 +218,7 @@ fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, 
   return guarded([&] {
     FactorImpl& F = f->f;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    if (!F.wx) {
-      F.wx = F.arena.alloc_n<zd>((size_t)F.n);
-      F.wy = F.arena.alloc_n<zd>((size_t)std::max<int64_t>(F.ymax, 1));
-      F.wtop = F.arena.alloc_n<zd>((size_t)std::max(F.n0, 1));
-    }
-    if (!F.wmv) F.wmv = F.arena.alloc_n<zd>((size_t)F.n);
+    F.ensure_workspace();
     zd* tin = F.wmv;
     // permute in, apply, permute out (tree order inside)
     launch_permute(static_cast<const zd*>(x), tin, F.order_dev, F.n, 1, st);
@@ -265,6 +263,19 @@ fmmlu_status fmmlu_factor_boxes(fmmlu_factor_h f, int64_t* count, int32_t* level
     if (s) s[r] = bx[r].s;
     if (skel)
       for (int64_t v : bx[r].skel_orig) skel[pos++] = v;
+  }
+  return FMMLU_OK;
+}
+
+fmmlu_status fmmlu_factor_profile(fmmlu_factor_h f, double* ms, int64_t* launches, double* flops,
+                                  double* bytes) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  const Profiler& p = f->f.prof;
+  for (int c = 0; c < KC_COUNT; ++c) {
+    if (ms) ms[c] = p.ms[c];
+    if (launches) launches[c] = p.launches[c];
+    if (flops) flops[c] = p.flops[c];
+    if (bytes) bytes[c] = p.bytes[c];
   }
   return FMMLU_OK;
 }

@@ -59,9 +59,57 @@ void* HostStage::alloc(size_t bytes) {
   return p;
 }
 
+hipEvent_t Profiler::get() {
+  if (!free_ev.empty()) {
+    hipEvent_t e = free_ev.back();
+    free_ev.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  FMMLU_HIP(hipEventCreate(&e));
+  return e;
+}
+void Profiler::begin(int cls) {
+  if (!on) return;
+  cur = cls;
+  cur_a = get();
+  FMMLU_HIP(hipEventRecord(cur_a, st));
+}
+void Profiler::end() {
+  if (!on || cur < 0) return;
+  hipEvent_t b = get();
+  FMMLU_HIP(hipEventRecord(b, st));
+  open.push_back(Rec{cur, cur_a, b});
+  launches[cur]++;
+  cur = -1;
+}
+void Profiler::harvest() {
+  if (!on) return;
+  for (auto& r : open) {
+    float t = 0.f;
+    FMMLU_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cls] += t;
+    free_ev.push_back(r.a);
+    free_ev.push_back(r.b);
+  }
+  open.clear();
+}
+Profiler::~Profiler() {
+  for (auto& r : open) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : free_ev) (void)hipEventDestroy(e);
+}
+
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Tolerances at or above this use the Gram-matrix route to the greedy CPQR: pivoted
+// Cholesky of M^H M has the same pivots and R as CPQR of M in exact arithmetic, and in
+// float64 its error floor (~sqrt(u) relative to |M|) stays well below eps down to 1e-7.
+constexpr double kGramEps = 1e-7;
 
 struct Owner {
   int box = -1;
@@ -93,6 +141,7 @@ struct Stage {
   DeviceArena dev{size_t(512) << 20};
   HostStage host;
   hipStream_t st = nullptr;
+  Profiler* prof = nullptr;
 
   template <class T>
   T* up(const std::vector<T>& v) {
@@ -117,6 +166,7 @@ struct Stage {
   }
   void sync_reset() {
     FMMLU_HIP(hipStreamSynchronize(st));
+    if (prof) prof->harvest();
     dev.reset();
     host.reset();
   }
@@ -150,6 +200,27 @@ struct GemmBatch {
     for (auto& g : s) segs.push_back(g);
     tasks.push_back(t);
   }
+  // C_part[k] = alpha * A^op B over K chunk k (k < ceil(K / kchunk)); partials at stride pstride
+  void add_split(zd* Cpart, int ldc, int M, int N, const zd* A, int lda, const zd* B, int ldb, int K,
+                 int kchunk, int64_t pstride) {
+    if (M <= 0 || N <= 0 || K <= 0) return;
+    const int nsplit = (K + kchunk - 1) / kchunk;
+    GemmTask t{};
+    t.C = Cpart;
+    t.M = M;
+    t.N = N;
+    t.ldc = ldc;
+    t.seg_begin = (int32_t)segs.size();
+    t.nseg = 1;
+    t.kchunk = kchunk;
+    t.part_stride = pstride;
+    t.alpha_re = 1.0;
+    t.beta = 0.0;
+    t.unit_begin = units;
+    units += gemm_units(M, N) * nsplit;
+    segs.push_back(GemmSeg{A, B, lda, ldb, K, 0});
+    tasks.push_back(t);
+  }
   void add1(zd* C, int ldc, int M, int N, const zd* A, int lda, const zd* B, int ldb, int K,
             double are, double beta) {
     if (K <= 0) {
@@ -159,17 +230,27 @@ struct GemmBatch {
     if (K > 0) s.push_back(GemmSeg{A, B, lda, ldb, K, 0});
     add(C, ldc, M, N, nullptr, nullptr, s, are, 0.0, beta);
   }
-  void run(Stage& sg, int opA) {
+  GemmTask* dt = nullptr;
+  GemmSeg* ds = nullptr;
+  void prepare(Stage& sg) {
     if (tasks.empty()) return;
-    GemmTask* dt = sg.up(tasks);
-    GemmSeg* ds = sg.up(segs);
+    dt = sg.up(tasks);
+    ds = sg.up(segs);
+  }
+  void launch(Stage& sg, int opA) {
+    if (tasks.empty()) return;
     launch_gemm(opA, dt, (int)tasks.size(), units, ds, sg.st);
+  }
+  void run(Stage& sg, int opA) {
+    prepare(sg);
+    launch(sg, opA);
   }
 };
 
 // Batched Gauss-Jordan inversion of matrices A_b (n_b x n_b, lda_b) into out_b (ld n_b).
+// All descriptors are uploaded first; the launches are timed as class `cls`.
 void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd*>& outs,
-                     int32_t* info_dev) {
+                     int32_t* info_dev, int cls) {
   if (tasks.empty()) return;
   int nmax = 0;
   for (auto& t : tasks) nmax = std::max(nmax, t.n);
@@ -186,10 +267,8 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
   zd** dW = sg.up(W);
   int32_t** dwork = sg.up(work);
   zd** dout = sg.up(outs);
+  std::vector<GemmBatch> steps;
   for (int j0 = 0; j0 < nmax; j0 += kGjBlock) {
-    launch_gj_panel(dt, nt, j0, sg.st);
-    launch_gj_swaps(dt, nt, j0, nmax, sg.st);
-    launch_gj_copyrow(dt, nt, j0, nmax, dW, sg.st);
     GemmBatch gb;
     for (int i = 0; i < nt; ++i) {
       const GjTask& t = tasks[i];
@@ -203,29 +282,49 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
         gb.add1(t.A + (int64_t)c1 * t.lda, t.lda, t.n, t.n - c1, t.A + (int64_t)j0 * t.lda, t.lda,
                 W[i] + (int64_t)c1 * nb, nb, nb, 1.0, 1.0);
     }
-    gb.run(sg, 0);
+    gb.prepare(sg);
+    steps.push_back(std::move(gb));
+  }
+  ProfScope ps(*sg.prof, cls);
+  int step = 0;
+  for (int j0 = 0; j0 < nmax; j0 += kGjBlock, ++step) {
+    launch_gj_panel(dt, nt, j0, sg.st);
+    launch_gj_swaps(dt, nt, j0, nmax, sg.st);
+    launch_gj_copyrow(dt, nt, j0, nmax, dW, sg.st);
+    steps[step].launch(sg, 0);
     launch_gj_fixrow(dt, nt, j0, nmax, dW, sg.st);
   }
   launch_gj_unpermute(dt, nt, nmax, dout, dwork, sg.st);
+  for (auto& t : tasks) sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
 }
 
 // Blocked Householder QR (no pivoting) of M_b (rows_b x m_b, ld rows_b), in place; the R
-// factor is left in the upper triangle.
+// factor is left in the upper triangle. Per panel of kQrBlock columns: panel kernel, then the
+// trailing update A2 -= V (Tw^H (V^H A2)) with V^H A2 as a split-K GEMM (long K = panel height).
 void batched_qr(Stage& sg, const std::vector<zd*>& Ms, const std::vector<int>& rows,
                 const std::vector<int>& ms) {
   const int nt = (int)Ms.size();
   if (nt == 0) return;
-  constexpr int NB = 16;
+  constexpr int NB = kQrBlock;
+  constexpr int KCH = 512;
   int kmax = 0;
   for (int i = 0; i < nt; ++i) kmax = std::max(kmax, std::min(rows[i], ms[i]));
-  // per task V buffer (rows x NB) and Tw (NB x NB), W (NB x m)
-  std::vector<zd*> V(nt), Tw(nt), W(nt), W2(nt);
+  std::vector<zd*> V(nt), Tw(nt), W2(nt), part(nt);
   for (int i = 0; i < nt; ++i) {
     V[i] = sg.dev.alloc_n<zd>((size_t)rows[i] * NB);
     Tw[i] = sg.dev.alloc_n<zd>(NB * NB);
-    W[i] = sg.dev.alloc_n<zd>((size_t)NB * ms[i]);
     W2[i] = sg.dev.alloc_n<zd>((size_t)NB * ms[i]);
+    const int nsplit = (rows[i] + KCH - 1) / KCH;
+    part[i] = sg.dev.alloc_n<zd>((size_t)nsplit * NB * ms[i]);
   }
+  struct Step {
+    QrTask* dqt;
+    int nq;
+    GemmBatch g1, g3;
+    RedTwTask* drt;
+    int nrt, cmax;
+  };
+  std::vector<Step> steps;
   for (int j0 = 0; j0 < kmax; j0 += NB) {
     std::vector<QrTask> qt;
     std::vector<int> who;
@@ -244,9 +343,11 @@ void batched_qr(Stage& sg, const std::vector<zd*>& Ms, const std::vector<int>& r
       who.push_back(i);
     }
     if (qt.empty()) break;
-    launch_qr_panel(sg.up(qt), (int)qt.size(), sg.st);
-    // trailing update: A2 = A[j0:, j0+nb:m];  A2 -= V (Tw^H (V^H A2))
-    GemmBatch g1, g2, g3;
+    Step stp;
+    stp.dqt = sg.up(qt);
+    stp.nq = (int)qt.size();
+    std::vector<RedTwTask> rt;
+    stp.cmax = 0;
     for (size_t q = 0; q < qt.size(); ++q) {
       const int i = who[q];
       const int nb = qt[q].nb;
@@ -255,16 +356,31 @@ void batched_qr(Stage& sg, const std::vector<zd*>& Ms, const std::vector<int>& r
       if (ncols <= 0) continue;
       const int L = rows[i] - j0;
       zd* A2 = Ms[i] + j0 + (int64_t)c0 * rows[i];
-      // W = V^H A2  (nb x ncols), K = L
-      g1.add1(W[i], nb, nb, ncols, V[i], L, A2, rows[i], L, 1.0, 0.0);
-      // W2 = Tw^H W  (nb x ncols), K = nb
-      g2.add1(W2[i], nb, nb, ncols, Tw[i], nb, W[i], nb, nb, 1.0, 0.0);
-      // A2 -= V W2  (L x ncols), K = nb
-      g3.add1(A2, rows[i], L, ncols, V[i], L, W2[i], nb, nb, -1.0, 1.0);
+      const int64_t pstride = (int64_t)nb * ncols;
+      stp.g1.add_split(part[i], nb, nb, ncols, V[i], L, A2, rows[i], L, KCH, pstride);
+      rt.push_back(RedTwTask{part[i], Tw[i], W2[i], nb, ncols, (L + KCH - 1) / KCH, 0, pstride});
+      stp.cmax = std::max(stp.cmax, ncols);
+      stp.g3.add1(A2, rows[i], L, ncols, V[i], L, W2[i], nb, nb, -1.0, 1.0);
     }
-    g1.run(sg, 2);
-    g2.run(sg, 2);
-    g3.run(sg, 0);
+    stp.g1.prepare(sg);
+    stp.g3.prepare(sg);
+    stp.drt = sg.up(rt);
+    stp.nrt = (int)rt.size();
+    steps.push_back(std::move(stp));
+  }
+  {
+    ProfScope ps(*sg.prof, KC_QR);
+    for (auto& stp : steps) {
+      launch_qr_panel(stp.dqt, stp.nq, sg.st);
+      stp.g1.launch(sg, 2);
+      if (stp.nrt) launch_reduce_tw(stp.drt, stp.nrt, stp.cmax, sg.st);
+      stp.g3.launch(sg, 0);
+    }
+  }
+  for (int i = 0; i < nt; ++i) {
+    const double L = rows[i], m = std::min(rows[i], ms[i]), n = ms[i];
+    // complex Householder QR of an L x n matrix: ~ L n^2 - n^3/3 complex MACs
+    sg.prof->flops[KC_QR] += 8.0 * (L * n * m - m * m * m / 3.0);
   }
 }
 
@@ -282,6 +398,9 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   if (opts.device_mem_cap > 0) arena.set_cap((size_t)opts.device_mem_cap);
   Stage sg;
   sg.st = st;
+  prof.on = opts.profile != 0;
+  prof.st = st;
+  sg.prof = &prof;
   // ---- geometry in tree order: x, y, z, nx, ny, nz, sqrt(w)
   order = tree.order;
   {
@@ -444,8 +563,16 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         if (t.nr > 0 && t.nc > 0) tasks.push_back(t);
         else units = t.unit_begin;
       }
-      launch_assemble(g, sg.up(tasks), (int)tasks.size(), units, sg.up(slot), sg.up(idx), sg.up(dof),
-                      sg.up(table), prev_pool, pool, st);
+      {
+        AsmTask* dt = sg.up(tasks);
+        int32_t* dslot = sg.up(slot);
+        int32_t* didx = sg.up(idx);
+        int64_t* ddof = sg.up(dof);
+        AsmSrc* dtab = sg.up(table);
+        ProfScope ps(prof, KC_ASSEMBLE);
+        launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, pool, st);
+      }
+      prof.bytes[KC_ASSEMBLE] += 16.0 * (double)pool_elems * (first_level ? 1.0 : 2.0);
       sg.sync_reset();
       if (prev_pool) FMMLU_HIP(hipFree(prev_pool));
       prev_pool = nullptr;
@@ -587,10 +714,54 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         idt.push_back(t);
         (void)B;
       }
-      launch_build_idmatrix(g, sg.up(idt), nb, units, qsegs.empty() ? nullptr : sg.up(qsegs), act_dev,
-                            pool, st);
-      // ---- 2. QR of M, extract R, CPQR
       {
+        IdTask* didt = sg.up(idt);
+        QSeg* dq = qsegs.empty() ? nullptr : sg.up(qsegs);
+        ProfScope ps(prof, KC_IDMAT);
+        launch_build_idmatrix(g, didt, nb, units, dq, act_dev, pool, st);
+      }
+      for (auto& bp : plan) prof.bytes[KC_IDMAT] += 16.0 * (double)bp.rows * bp.m;
+      // ---- 2. greedy CPQR of M: through the Gram matrix (pivoted Cholesky of M^H M) when
+      //      eps >= kGramEps, else Householder QR of M followed by CPQR of its R factor
+      const bool gram = opts.id_route == 1 || (opts.id_route == 0 && eps >= kGramEps);
+      if (gram) {
+        constexpr int KCH = 512;
+        GemmBatch gg;
+        std::vector<SumTask> st_;
+        std::vector<PcholTask> pt;
+        int64_t su = 0;
+        int mmax = 0;
+        for (auto& bp : plan) {
+          const int nsplit = (bp.rows + KCH - 1) / KCH;
+          const int64_t mm = (int64_t)bp.m * bp.m;
+          zd* part = sg.dev.alloc_n<zd>((size_t)nsplit * mm);
+          zd* G = sg.dev.alloc_n<zd>((size_t)mm);
+          bp.R = sg.dev.alloc_n<zd>((size_t)mm);
+          bp.perm = sg.dev.alloc_n<int32_t>(bp.m);
+          bp.rank = sg.dev.alloc_n<int32_t>(1);
+          bp.T = sg.dev.alloc_n<zd>((size_t)mm);
+          gg.add_split(part, bp.m, bp.m, bp.m, bp.M, bp.rows, bp.M, bp.rows, bp.rows, KCH, mm);
+          SumTask sm{part, G, mm, mm, nsplit, 0, su};
+          su += (mm + 255) / 256;
+          st_.push_back(sm);
+          zd* W = sg.dev.alloc_n<zd>((size_t)mm / 4 + bp.m + 1);
+          pt.push_back(PcholTask{G, bp.R, bp.perm, bp.rank, bp.T, W, bp.m, 0});
+          mmax = std::max(mmax, bp.m);
+          prof.flops[KC_QR] += 8.0 * (double)bp.rows * bp.m * bp.m;
+        }
+        gg.prepare(sg);
+        SumTask* dst_ = sg.up(st_);
+        PcholTask* dpt = sg.up(pt);
+        {
+          ProfScope ps(prof, KC_QR);
+          gg.launch(sg, 2);
+          launch_sum_parts(dst_, (int)st_.size(), su, st);
+        }
+        {
+          ProfScope ps(prof, KC_CPQR);
+          launch_pchol(dpt, nb, mmax, eps, st);
+        }
+      } else {
         std::vector<zd*> Ms;
         std::vector<int> rws, mms;
         for (auto& bp : plan) {
@@ -608,11 +779,17 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           bp.rank = sg.dev.alloc_n<int32_t>(1);
           bp.T = sg.dev.alloc_n<zd>((size_t)bp.m * bp.m);
           et.push_back(ExtractTask{bp.M, bp.R, bp.rows, bp.m});
-          ct.push_back(CpqrTask{bp.R, bp.perm, bp.rank, bp.T, bp.m, bp.m});
+          zd* W = sg.dev.alloc_n<zd>((size_t)bp.m * bp.m / 4 + bp.m + 1);
+          ct.push_back(CpqrTask{bp.R, bp.perm, bp.rank, bp.T, W, bp.m, bp.m});
           mmax = std::max(mmax, bp.m);
         }
-        launch_extract_r(sg.up(et), nb, mmax, st);
-        launch_cpqr(sg.up(ct), nb, eps, st);
+        ExtractTask* det = sg.up(et);
+        CpqrTask* dct = sg.up(ct);
+        {
+          ProfScope ps(prof, KC_CPQR);
+          launch_extract_r(det, nb, mmax, st);
+          launch_cpqr(dct, nb, mmax, eps, st);
+        }
       }
       // ---- read back ranks and pivots
       std::vector<int32_t> ranks(nb);
@@ -624,6 +801,11 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
                                  hipMemcpyDeviceToHost, st));
       }
       FMMLU_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i < nb; ++i) {
+        double f = 0;
+        for (int kk = 0; kk < ranks[i]; ++kk) f += 2.0 * (double)(plan[i].m - kk) * (plan[i].m - kk);
+        prof.flops[KC_CPQR] += 8.0 * f;
+      }
       // ---- 3. elimination plan
       struct ElimPlan {
         int pi;  // index into plan
@@ -717,7 +899,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           cross.push_back(ct);
           info.max_rank = std::max(info.max_rank, e.s);
         }
-        launch_gather_cross(sg.up(cross), ne, cunits, nsegs.empty() ? nullptr : sg.up(nsegs), pool, st);
+        CrossTask* dcross = sg.up(cross);
+        NSeg* dns = nsegs.empty() ? nullptr : sg.up(nsegs);
+        {
+          ProfScope ps(prof, KC_ELIM);
+          launch_gather_cross(dcross, ne, cunits, dns, pool, st);
+        }
         // E/F transforms (Section 4.1). Ccol = A[(R,S,N),(S,R)], Crow = A[(S,R),(R,S,N)]:
         //   Ccol[:, s:m]      -= Ccol[:, 0:s] T        (A_{.R} - A_{.S} T)
         //   Ccol[0:r, s:m]    -= T^T Ccol[r:m, s:m]    -> X_RR;  Ccol[r:, s:m] = X_{(S u N) R}
@@ -732,15 +919,21 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             gc.add1(e.Crow + e.s + (int64_t)e.r * m, m, e.r, mn - e.r, bp.T, m, e.Crow + (int64_t)e.r * m, m,
                     e.s, -1.0, 1.0);
           }
-          ga.run(sg, 0);
-          gc.run(sg, 1);
           for (auto& e : ep) {
             BoxPlan& bp = plan[e.pi];
             const int m = bp.m, mn = bp.m + bp.nN;
             zd* CcR = e.Ccol + (int64_t)e.s * mn;
             gb.add1(CcR, mn, e.r, e.r, bp.T, m, CcR + e.r, mn, e.s, -1.0, 1.0);
+            prof.flops[KC_ELIM] += 8.0 * ((double)mn * e.r * e.s + (double)e.r * (mn - e.r) * e.s +
+                                          (double)e.r * e.r * e.s);
           }
-          gb.run(sg, 1);
+          ga.prepare(sg);
+          gb.prepare(sg);
+          gc.prepare(sg);
+          ProfScope ps(prof, KC_ELIM);
+          ga.launch(sg, 0);
+          gc.launch(sg, 1);
+          gb.launch(sg, 1);
         }
         // 4. inverse of X_RR (in place in Ccol[0:r, 0:r]) -> Xi
         {
@@ -754,7 +947,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             gt.push_back(t);
             outs.push_back(const_cast<zd*>(e.fb->dev.Xi));
           }
-          batched_inverse(sg, gt, outs, info_dev);
+          batched_inverse(sg, gt, outs, info_dev, KC_INV);
         }
         // panels: Lp = X_{SN,R} Xi ; Up = Xi X_{R,SN}; T compacted into the factor
         {
@@ -777,8 +970,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
               cps.push_back(c);
             }
           }
-          gp.run(sg, 0);
-          if (!cps.empty()) launch_copy(sg.up(cps), (int)cps.size(), cu, st);
+          gp.prepare(sg);
+          CopyTask* dcp = cps.empty() ? nullptr : sg.up(cps);
+          ProfScope ps(prof, KC_ELIM);
+          gp.launch(sg, 0);
+          if (dcp) launch_copy(dcp, (int)cps.size(), cu, st);
+          for (auto& e : ep) prof.flops[KC_ELIM] += 8.0 * 2.0 * (double)e.nsn * e.r * e.r;
         }
         // 5. Schur update of near-near tiles: A[SN, SN] -= X_{SN,R} Up
         {
@@ -836,8 +1033,15 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           for (auto& kv : dest) {
             Dst& ds = dsts[kv.second];
             gs.add(ds.C, ds.ldc, ds.M, ds.N, ds.rmap, ds.cmap, ds.segs, -1.0, 0.0, 1.0);
+            double kk = 0;
+            for (auto& sgm : ds.segs) kk += sgm.K;
+            prof.flops[KC_SCHUR] += 8.0 * ds.M * ds.N * kk;
+            prof.bytes[KC_SCHUR] += 32.0 * ds.M * ds.N;
           }
-          gs.run(sg, 0);
+          for (auto& e : ep) prof.bytes[KC_SCHUR] += 32.0 * (double)e.nsn * e.r;
+          gs.prepare(sg);
+          ProfScope ps(prof, KC_SCHUR);
+          gs.launch(sg, 0);
         }
         // flops of this phase
         for (auto& e : ep) {
@@ -862,23 +1066,34 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         live_total -= e.r;
         info.nboxes_factored++;
       }
-      // build the solve phase record (needs the live lists of boxes only for SN: done above)
+      // build the solve phase record
       if (ne > 0) {
         SolvePhase ph;
         ph.box_begin = (int)box_base;
         ph.box_end = (int)boxes.size();
-        int64_t yo = 0;
+        int64_t yo = 0, xo = 0, po = 0;
         std::map<int32_t, std::vector<int64_t>> contrib;
         std::vector<SolveBox> db;
+        std::vector<SweepTask> ty, tp;
         for (int b = ph.box_begin; b < ph.box_end; ++b) {
           FactorBox& fb = boxes[b];
+          const int lb = b - ph.box_begin;
           fb.y_off = yo;
           fb.dev.y_off = yo;
+          fb.dev.xr_off = xo;
+          fb.dev.p_off = po;
+          fb.dev.nchunk = (fb.nsn + kSweepCols - 1) / kSweepCols;
+          for (int k0 = 0; k0 < fb.nsn; k0 += kSweepRows)
+            ty.push_back(SweepTask{lb, k0, std::min(kSweepRows, fb.nsn - k0), 0});
+          for (int c = 0; c < fb.dev.nchunk; ++c)
+            tp.push_back(SweepTask{lb, c * kSweepCols, std::min(kSweepCols, fb.nsn - c * kSweepCols), c});
           ph.rmax = std::max(ph.rmax, fb.r);
           db.push_back(fb.dev);
           yo += fb.nsn;
+          xo += fb.r;
+          po += (int64_t)fb.dev.nchunk * fb.r;
         }
-        // host copies of SN lists for the scatter CSR: rebuild from the plan
+        // scatter lists: every S u N position of every box of the phase, summed in box order
         for (int q = 0; q < ne; ++q) {
           ElimPlan& e = ep[q];
           BoxPlan& bp = plan[e.pi];
@@ -901,12 +1116,20 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(ph.rmax) +
                                         " DOFs exceeds the solve kernels' LDS bound (4096)");
         ph.ylen = yo;
+        ph.xrlen = xo;
+        ph.plen = po;
         ph.nd = (int64_t)dst.size();
         ph.dboxes = sg.up_to(arena, db);
         ph.sc_dst = sg.up_to(arena, dst);
         ph.sc_ptr = sg.up_to(arena, ptr);
         ph.sc_src = sg.up_to(arena, src);
+        ph.dy = sg.up_to(arena, ty);
+        ph.dp = sg.up_to(arena, tp);
+        ph.ny = (int)ty.size();
+        ph.np = (int)tp.size();
         ymax = std::max(ymax, yo);
+        xrmax = std::max(xrmax, xo);
+        pmax = std::max(pmax, po);
         phases.push_back(ph);
       }
       // live lists of eliminated boxes to the device (persistent for the level)
@@ -1023,15 +1246,22 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       t.tab_off = 0;
       t.unit_begin = 0;
       std::vector<AsmTask> tv{t};
-      launch_assemble(g, sg.up(tv), 1, units64(n0, n0), sg.up(slot), sg.up(idx), sg.up(dof), sg.up(table),
-                      prev_pool, Att, st);
+      {
+        AsmTask* dt = sg.up(tv);
+        int32_t* dslot = sg.up(slot);
+        int32_t* didx = sg.up(idx);
+        int64_t* ddof = sg.up(dof);
+        AsmSrc* dtab = sg.up(table);
+        ProfScope ps(prof, KC_TOP);
+        launch_assemble(g, dt, 1, units64(n0, n0), dslot, didx, ddof, dtab, prev_pool, Att, st);
+      }
       Ainv = arena.alloc_n<zd>((size_t)n0 * n0);
       std::vector<GjTask> gt(1);
       gt[0].A = Att;
       gt[0].n = n0;
       gt[0].lda = n0;
       std::vector<zd*> outs{Ainv};
-      batched_inverse(sg, gt, outs, info_dev);
+      batched_inverse(sg, gt, outs, info_dev, KC_TOP);
       top_dev = sg.up_to(arena, top);
       info.flops_top = 8.0 * (double)n0 * n0 * n0;
       info.factor_bytes += 16 * (int64_t)n0 * n0;
@@ -1043,30 +1273,53 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
     if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular top block");
   }
+  {
+    std::vector<SolveBox> all;
+    for (auto& fb : boxes) {
+      all.push_back(fb.dev);
+      rmax_all = std::max(rmax_all, fb.r);
+    }
+    nall = (int)all.size();
+    all_boxes = sg.up_to(arena, all);
+    sg.sync_reset();
+  }
   info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)arena.held());
   info.t_factor = std::chrono::duration<double>(Clock::now() - t0).count();
 }
 
 // ------------------------------------------------------------------------------------------
+void FactorImpl::ensure_workspace() {
+  if (wx) return;
+  wx = arena.alloc_n<zd>((size_t)n);
+  wy = arena.alloc_n<zd>((size_t)std::max<int64_t>(ymax, 1));
+  wxr = arena.alloc_n<zd>((size_t)std::max<int64_t>(xrmax, 1));
+  wp = arena.alloc_n<zd>((size_t)std::max<int64_t>(pmax, 1));
+  const int64_t nblk = (n0 + 255) / 256;
+  wtop = arena.alloc_n<zd>((size_t)std::max<int64_t>((int64_t)n0 * (1 + nblk), 1));
+  wmv = arena.alloc_n<zd>((size_t)n);
+}
+
 void FactorImpl::solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st) {
-  if (!wx) {
-    wx = arena.alloc_n<zd>((size_t)n);
-    wy = arena.alloc_n<zd>((size_t)std::max<int64_t>(ymax, 1));
-    wtop = arena.alloc_n<zd>((size_t)std::max(n0, 1));
-  }
+  ensure_workspace();
   const int adj = adjoint ? 1 : 0;
   for (int64_t c = 0; c < nrhs; ++c) {
     const zd* bc = b + c * n;
     zd* xc = x + c * n;
     launch_permute(bc, wx, order_dev, n, 1, st);
+    // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
     for (auto& ph : phases) {
-      launch_solve_fwd(ph.dboxes, ph.box_end - ph.box_begin, ph.rmax, wx, wy, adj, st);
+      launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, wx, wxr, adj, st);
+      launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, st);
       launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
     }
-    for (auto& ph : phases) launch_solve_diag(ph.dboxes, ph.box_end - ph.box_begin, ph.rmax, wx, adj, st);
+    // D^{-1} (adjoint D^{-H}): all pivot blocks, then the top block
+    launch_solve_diag(all_boxes, nall, rmax_all, wx, adj, st);
     launch_solve_top(Ainv, n0, top_dev, wx, wtop, adj, st);
-    for (auto it = phases.rbegin(); it != phases.rend(); ++it)
-      launch_solve_bwd(it->dboxes, it->box_end - it->box_begin, it->rmax, wx, adj, st);
+    // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse
+    for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
+      launch_solve_bpart(it->dboxes, it->dp, it->np, wx, wp, adj, st);
+      launch_solve_bfin(it->dboxes, it->box_end - it->box_begin, it->rmax, wp, wx, adj, st);
+    }
     launch_permute(wx, xc, order_dev, n, 0, st);
   }
 }

@@ -30,6 +30,36 @@ class HostStage {
   size_t cur_ = 0, used_ = 0;
 };
 
+// Opt-in timing of kernel classes with HIP events on the launch stream. Algorithmic work
+// (flops or bytes, per class) is accumulated by the caller alongside.
+enum KClass { KC_ASSEMBLE = 0, KC_IDMAT, KC_QR, KC_CPQR, KC_ELIM, KC_INV, KC_SCHUR, KC_TOP, KC_COUNT };
+struct Profiler {
+  bool on = false;
+  hipStream_t st = nullptr;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> open;
+  std::vector<hipEvent_t> free_ev;
+  double ms[KC_COUNT] = {0};
+  int64_t launches[KC_COUNT] = {0};
+  double flops[KC_COUNT] = {0};
+  double bytes[KC_COUNT] = {0};
+  int cur = -1;
+  hipEvent_t cur_a = nullptr;
+  hipEvent_t get();
+  void begin(int cls);
+  void end();
+  void harvest();  // after a stream synchronisation
+  ~Profiler();
+};
+struct ProfScope {
+  Profiler& p;
+  ProfScope(Profiler& pr, int cls) : p(pr) { p.begin(cls); }
+  ~ProfScope() { p.end(); }
+};
+
 struct FactorBox {
   int level, box;
   int coord[3];
@@ -46,7 +76,10 @@ struct SolvePhase {
   int64_t* sc_ptr = nullptr;
   int64_t* sc_src = nullptr;
   int64_t nd = 0;
-  int64_t ylen = 0;
+  int64_t ylen = 0, xrlen = 0, plen = 0;
+  SweepTask* dy = nullptr;  // forward row chunks
+  SweepTask* dp = nullptr;  // backward column chunks
+  int ny = 0, np = 0;
   int rmax = 0;
 };
 
@@ -62,20 +95,26 @@ struct FactorImpl {
   std::vector<int64_t> order;  // host copy
   std::vector<FactorBox> boxes;
   std::vector<SolvePhase> phases;
-  int64_t ymax = 0;
+  int64_t ymax = 0, xrmax = 0, pmax = 0;
+  SolveBox* all_boxes = nullptr;  // every factored box, for the diagonal step
+  int nall = 0, rmax_all = 0;
   int n0 = 0;
   int32_t* top_dev = nullptr;
   zd* Ainv = nullptr;
   fmmlu_info info{};
+  Profiler prof;
   // solve workspace (allocated lazily)
   zd* wx = nullptr;
   zd* wy = nullptr;
   zd* wtop = nullptr;
   zd* wmv = nullptr;
+  zd* wxr = nullptr;
+  zd* wp = nullptr;
 
   void factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
               hipStream_t st);
   void solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st);
+  void ensure_workspace();
 };
 
 }  // namespace fmmlu

@@ -82,9 +82,10 @@ struct GemmTask {
   const int32_t* cmap;  // may be null (identity)
   int32_t M, N, ldc;
   int32_t seg_begin, nseg;
-  int32_t pad;
+  int32_t kchunk;                   // > 0: split K into chunks; chunk c writes C + c*part_stride
   double alpha_re, alpha_im, beta;  // beta real
-  int64_t unit_begin;              // prefix sum of 32x32 output blocks
+  int64_t part_stride;
+  int64_t unit_begin;              // prefix sum of 32x32 output blocks (times K chunks)
 };
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
                  hipStream_t st);
@@ -97,6 +98,16 @@ struct QrTask {
   int32_t rows, lda, j0, nb;
 };
 void launch_qr_panel(const QrTask* tasks, int ntasks, hipStream_t st);
+constexpr int kQrBlock = 16;  // panel width of the blocked Householder QR
+// W2 = Tw^H * sum_k part_k  (part_k: nb x ncols, ld nb, stride part_stride)
+struct RedTwTask {
+  const zd* part;
+  const zd* Tw;
+  zd* W2;
+  int32_t nb, ncols, nsplit, pad;
+  int64_t part_stride;
+};
+void launch_reduce_tw(const RedTwTask* tasks, int ntasks, int nmax, hipStream_t st);
 
 // ---- greedy CPQR on an m x m matrix (in place) + T = R11^{-1} R12 ----
 struct CpqrTask {
@@ -104,9 +115,10 @@ struct CpqrTask {
   int32_t* perm;   // output m
   int32_t* rank;   // output (device scalar)
   zd* T;           // output s x (m - s), ld = m (room for s <= m)
+  zd* W;           // scratch, m * m / 4 + m entries
   int32_t m, lda;
 };
-void launch_cpqr(const CpqrTask* tasks, int ntasks, double eps, hipStream_t st);
+void launch_cpqr(const CpqrTask* tasks, int ntasks, int mmax, double eps, hipStream_t st);
 
 // ---- gathers of the cross of B ----
 // With perm the ID pivot order (skeletons S = perm[0:s], redundant R = perm[s:m]):
@@ -130,6 +142,31 @@ struct CrossTask {
 };
 void launch_gather_cross(const CrossTask* tasks, int ntasks, int64_t nunits, const NSeg* segs,
                          const zd* pool, hipStream_t st);
+
+// ---- sum of split-K partials: out[e] = sum_k part[k*stride + e], e < count ----
+struct SumTask {
+  const zd* part;
+  zd* out;
+  int64_t count, stride;
+  int32_t nsplit, pad;
+  int64_t unit_begin;  // units of 256 elements
+};
+void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
+
+// ---- greedy CPQR through the Gram matrix: pivoted Cholesky of G = M^H M (m x m) ----
+// Left-looking: row k of R from G[perm[k], perm[.]] and the previous rows; the diagonal of
+// the Schur complement (the squared norms of the remaining columns after projection) is
+// updated exactly. Outputs as CpqrTask: perm, rank, T = R11^{-1} R12 (ld m).
+struct PcholTask {
+  const zd* G;     // m x m, ld m (not modified)
+  zd* R;           // m x m scratch, ld m
+  int32_t* perm;
+  int32_t* rank;
+  zd* T;
+  zd* W;           // scratch, m * m / 4 + m entries
+  int32_t m, pad;
+};
+void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st);
 
 // ---- Gauss-Jordan inversion with partial pivoting, blocked ----
 struct GjTask {
@@ -177,25 +214,39 @@ struct SolveBox {
   const zd* Xi;       // r x r inverse pivot block
   const zd* Lp;       // (s+nN) x r, ld = s+nN
   const zd* Up;       // r x (s+nN), ld = r
-  int32_t r, s, nsn, pad;
-  int64_t y_off;      // offset of this box's output in the scatter buffer
+  int32_t r, s, nsn, nchunk;  // nchunk: backward partial chunks
+  int64_t y_off;      // this box's outputs in the forward scatter buffer
+  int64_t xr_off;     // this box's x_R copy in the phase buffer
+  int64_t p_off;      // this box's backward partials (nchunk x r)
 };
-// forward sweep part 1 (per box): xR -= op(T) xS; y = op(P) xR (adjoint: T^H, Up^H)
-void launch_solve_fwd(const SolveBox* boxes, int nb, int rmax, zd* x, zd* y, int adjoint,
-                      hipStream_t st);
+// Work item of a box: rows [k0, k0 + kn) of its panel (forward), or columns (backward).
+struct SweepTask {
+  int32_t box, k0, kn, chunk;
+};
+// forward, per box: x_R -= op(T) x_S (T^T, adjoint T^H); copy to XR
+void launch_solve_xr(const SolveBox* boxes, int nb, zd* x, zd* XR, int adjoint, hipStream_t st);
+// forward, per task: y = op(P) x_R on a row chunk (Lp, adjoint Up^H)
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
+                    zd* y, int adjoint, hipStream_t st);
 // scatter: x[dst[d]] -= sum_{q in [ptr[d], ptr[d+1])} y[src[q]]
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st);
 // diagonal: xR = Xi xR (adjoint: Xi^H xR), all boxes
 void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, hipStream_t st);
-// backward sweep (per box): xR -= op(P) x[SN]; xS -= op(T) xR
-void launch_solve_bwd(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, hipStream_t st);
-// top block: x[top] = Ainv x[top] (or Ainv^H)
+// backward, per task: partial of op(P) x_SN over a column chunk (Up, adjoint Lp^H)
+void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
+                        int adjoint, hipStream_t st);
+// backward, per box: x_R -= sum of partials; x_S -= op(T) x_R (T, adjoint conj(T))
+void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint,
+                       hipStream_t st);
+// top block: x[top] = Ainv x[top] (or Ainv^H); tmp >= n0 * (1 + ceil(n0 / 256)) entries
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
                       hipStream_t st);
-// permutations between original and tree order, scaled copy
+// permutations between original and tree order
 void launch_permute(const zd* src, zd* dst, const int64_t* map, int64_t n, int gather,
                     hipStream_t st);
+constexpr int kSweepRows = 256;   // forward row chunk
+constexpr int kSweepCols = 512;   // backward column chunk
 
 // ---- stand-alone block of A~ (rows, cols: tree positions) ----
 void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64_t* cols,

@@ -67,8 +67,11 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ 
   const int64_t u = blockIdx.x;
   const int ti = find_task(tasks, ntasks, u);
   const GemmTask t = tasks[ti];
-  const int64_t lu = u - t.unit_begin;
+  int64_t lu = u - t.unit_begin;
   const int nbm = (t.M + BM - 1) / BM;
+  const int64_t ntiles = (int64_t)nbm * ((t.N + BN - 1) / BN);
+  const int kc = (int)(lu / ntiles);  // split-K chunk (0 without split)
+  lu -= (int64_t)kc * ntiles;
   const int bm = (int)(lu % nbm), bn = (int)(lu / nbm);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   zd acc[TM][TN];
@@ -79,7 +82,9 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ 
   const int row0 = bm * BM, col0 = bn * BN;
   for (int sidx = 0; sidx < t.nseg; ++sidx) {
     const GemmSeg sg = segs[t.seg_begin + sidx];
-    for (int k0 = 0; k0 < sg.K; k0 += BK) {
+    const int kbeg = t.kchunk > 0 ? kc * t.kchunk : 0;
+    const int kend = t.kchunk > 0 ? min(sg.K, kbeg + t.kchunk) : sg.K;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
       // A tile: BM x BK
       for (int e = threadIdx.x; e < BM * BK; e += 256) {
         int i, kk;
@@ -92,7 +97,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ 
         }
         const int gi = row0 + i, gk = k0 + kk;
         zd v{0.0, 0.0};
-        if (gi < t.M && gk < sg.K) {
+        if (gi < t.M && gk < kend) {
           if (OPA == 0)
             v = sg.A[gi + (int64_t)gk * sg.lda];
           else {
@@ -107,7 +112,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ 
         const int kk = e % BK, j = e / BK;
         const int gk = k0 + kk, gj = col0 + j;
         zd v{0.0, 0.0};
-        if (gk < sg.K && gj < t.N) v = sg.B[gk + (int64_t)gj * sg.ldb];
+        if (gk < kend && gj < t.N) v = sg.B[gk + (int64_t)gj * sg.ldb];
         Bs[kk][j] = v;
       }
       __syncthreads();
@@ -137,7 +142,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ 
       const int j = col0 + tx + 16 * qb;
       if (j >= t.N) continue;
       const int cj = t.cmap ? t.cmap[j] : j;
-      zd* c = t.C + ri + (int64_t)cj * t.ldc;
+      zd* c = t.C + (int64_t)kc * t.part_stride + ri + (int64_t)cj * t.ldc;
       zd v = zmul(alpha, acc[qa][qb]);
       if (t.beta != 0.0) v = zadd(v, zscale(*c, t.beta));
       *c = v;
@@ -146,95 +151,112 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------------------
-// Householder QR of the panel A[j0:rows, j0:j0+nb]. Reflector H = I - tau v v^H with
-// v = x + e^{i arg x0} |x| e_1 and tau = 2 / |v|^2 (Hermitian, unitary); H x = -e^{i arg x0}|x| e_1.
-// The product H_1 ... H_nb = I - V Tw V^H (compact WY, forward). V is written explicitly.
-constexpr int kQrMaxNb = 32;
+// Householder QR of the panel A[j0:rows, j0:j0+nb], nb <= kQrNb. Reflector H = I - tau v v^H
+// with v = x + e^{i arg x0} |x| e_1 and tau = 2/|v|^2 (Hermitian, unitary), so that
+// H x = -e^{i arg x0} |x| e_1. The product H_1 ... H_nb = I - V Tw V^H (compact WY, forward)
+// is returned with V written explicitly. One workgroup per panel; per column two passes over
+// the panel rows (dots, then update + next column's norm), each closed by one reduction.
+constexpr int kQrNb = 16;
+
+template <int N>
+__device__ inline void block_reduce_vec(zd (&v)[N], zd (*red)[N], zd* out) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double re = wave_sum(v[q].re), im = wave_sum(v[q].im);
+    if (lane == 0) red[w][q] = zd{re, im};
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    zd a = red[0][threadIdx.x];
+    for (int i = 1; i < 4; ++i) a = zadd(a, red[i][threadIdx.x]);
+    out[threadIdx.x] = a;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(256) qr_panel_kernel(const QrTask* __restrict__ tasks) {
+  constexpr int NB = kQrNb;
   const QrTask t = tasks[blockIdx.x];
-  __shared__ zd red[4];
-  __shared__ zd dots[2 * kQrMaxNb];
-  __shared__ zd sh_v0;
-  __shared__ double sh_tau;
-  __shared__ zd sh_beta;
+  __shared__ zd red[4][2 * NB];
+  __shared__ zd s_d[2 * NB];
+  __shared__ double redd[4];
+  __shared__ double s_ss;
+  __shared__ zd s_v0, s_beta;
+  __shared__ double s_tau;
   const int L = t.rows - t.j0;  // panel height
   const int nb = t.nb;
-  zd* A = t.A;
   const int64_t lda = t.lda;
-  const int ldv = L;
-  // zero the Tw block
+  zd* P = t.A + t.j0 + (int64_t)t.j0 * lda;  // P[i + c*lda], i < L, c < nb
+  zd* V = t.V;
+  const int64_t ldv = L;
   for (int e = threadIdx.x; e < nb * nb; e += 256) t.Tw[e] = zd{0.0, 0.0};
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < L; i += 256) ss += zabs2(P[i]);
+  ss = block_sum_d(ss, redd);
+  if (threadIdx.x == 0) s_ss = ss;
+  __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    const int col = t.j0 + j;
-    zd* x = A + col + (int64_t)col * lda;  // x[0 .. len)
-    const int len = t.rows - col;
-    // column of V (explicit; zeros above row j of the panel)
-    zd* vj = t.V + (int64_t)j * ldv;
-    if (len <= 0) {
-      for (int i = threadIdx.x; i < L; i += 256) vj[i] = zd{0.0, 0.0};
+    if (j >= L) {
+      for (int i = threadIdx.x; i < L; i += 256) V[i + j * ldv] = zd{0.0, 0.0};
       continue;
     }
-    double ss = 0.0;
-    for (int i = threadIdx.x; i < len; i += 256) ss += zabs2(x[i]);
-    __shared__ double redd[4];
-    ss = block_sum_d(ss, redd);
     if (threadIdx.x == 0) {
-      const zd a = x[0];
-      const double nrm = sqrt(ss);
+      const zd a = P[j + (int64_t)j * lda];
+      const double nrm = sqrt(s_ss);
       const double aa = sqrt(zabs2(a));
       const zd ph = aa > 0.0 ? zd{a.re / aa, a.im / aa} : zd{1.0, 0.0};
       const zd v0 = zd{a.re + ph.re * nrm, a.im + ph.im * nrm};
-      const double vn2 = ss - zabs2(a) + zabs2(v0);
-      sh_v0 = v0;
-      sh_tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-      sh_beta = zd{-ph.re * nrm, -ph.im * nrm};
+      const double vn2 = s_ss - zabs2(a) + zabs2(v0);
+      s_v0 = v0;
+      s_tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      s_beta = zd{-ph.re * nrm, -ph.im * nrm};
     }
     __syncthreads();
-    const zd v0 = sh_v0;
-    const double tau = sh_tau;
-    // dots: with remaining panel columns c = j+1..nb-1 (index c) and with previous V
-    // columns l < j (index nb + l)
-    zd part[2 * kQrMaxNb];
-    const int nrem = nb - j - 1;
-    for (int c = 0; c < nrem + j; ++c) part[c] = zd{0.0, 0.0};
-    for (int i = threadIdx.x; i < len; i += 256) {
-      const zd vi = (i == 0) ? v0 : x[i];
-      for (int c = 0; c < nrem; ++c) zfmac(part[c], vi, x[i + (int64_t)(c + 1) * lda]);
-      for (int l = 0; l < j; ++l) zfmac(part[nrem + l], t.V[(int64_t)l * ldv + j + i], vi);
+    const zd v0 = s_v0;
+    const double tau = s_tau;
+    // pass A: d_c = v^H P[:, c] (c > j) and w_l = V_l^H v (l < j)
+    zd acc[2 * NB];
+#pragma unroll
+    for (int q = 0; q < 2 * NB; ++q) acc[q] = zd{0.0, 0.0};
+    for (int i = j + threadIdx.x; i < L; i += 256) {
+      const zd vi = (i == j) ? v0 : P[i + (int64_t)j * lda];
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+        if (c > j && c < nb) zfmac(acc[c], vi, P[i + (int64_t)c * lda]);
+#pragma unroll
+      for (int l = 0; l < NB; ++l)
+        if (l < j) zfmac(acc[NB + l], V[i + l * ldv], vi);
     }
-    for (int c = 0; c < nrem + j; ++c) {
-      zd s = block_sum(part[c], red);
-      if (threadIdx.x == 0) dots[c] = s;
-    }
-    __syncthreads();
-    // update remaining panel columns: c -= tau v (v^H c)
-    for (int i = threadIdx.x; i < len; i += 256) {
-      const zd vi = (i == 0) ? v0 : x[i];
-      for (int c = 0; c < nrem; ++c) {
-        zd* p = x + i + (int64_t)(c + 1) * lda;
-        const zd f = zscale(zmul(vi, dots[c]), tau);
-        *p = zsub(*p, f);
-      }
-    }
-    // write V column j (explicit), then overwrite x with R's column
+    block_reduce_vec<2 * NB>(acc, red, s_d);
+    // pass B: update columns c > j; V column j; R column j; norm^2 of column j+1 below row j+1
+    double ss2 = 0.0;
     for (int i = threadIdx.x; i < L; i += 256) {
-      zd v;
-      if (i < j)
-        v = zd{0.0, 0.0};
-      else if (i == j)
-        v = v0;
-      else
-        v = x[i - j];
-      vj[i] = v;
+      if (i < j) {
+        V[i + j * ldv] = zd{0.0, 0.0};
+        continue;
+      }
+      const zd vi = (i == j) ? v0 : P[i + (int64_t)j * lda];
+      V[i + j * ldv] = vi;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        if (c > j && c < nb) {
+          zd* pc = P + i + (int64_t)c * lda;
+          const zd f = zscale(zmul(vi, s_d[c]), tau);
+          const zd nv = zsub(*pc, f);
+          *pc = nv;
+          if (c == j + 1 && i >= j + 1) ss2 += zabs2(nv);
+        }
+      }
+      P[i + (int64_t)j * lda] = (i == j) ? s_beta : zd{0.0, 0.0};
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < len; i += 256) x[i] = (i == 0) ? sh_beta : zd{0.0, 0.0};
-    // Tw(0:j, j) = -tau Tw(0:j, 0:j) w,  w_l = V_l^H v ;  Tw(j, j) = tau
+    ss2 = block_sum_d(ss2, redd);
     if (threadIdx.x == 0) {
+      s_ss = ss2;
       for (int r = 0; r < j; ++r) {
-        zd s{0.0, 0.0};
-        for (int l = r; l < j; ++l) zfma(s, t.Tw[r + l * nb], dots[nrem + l]);
-        t.Tw[r + j * nb] = zscale(s, -tau);
+        zd sacc{0.0, 0.0};
+        for (int l = r; l < j; ++l) zfma(sacc, t.Tw[r + l * nb], s_d[NB + l]);
+        t.Tw[r + j * nb] = zscale(sacc, -tau);
       }
       t.Tw[j + j * nb] = zd{tau, 0.0};
     }
@@ -242,47 +264,111 @@ __global__ void __launch_bounds__(256) qr_panel_kernel(const QrTask* __restrict_
   }
 }
 
+// Split-K partial sums of W = V^H A2 are reduced and multiplied by Tw^H in one pass:
+// W2[:, c] = Tw^H sum_k part_k[:, c]. One thread per column.
+__global__ void __launch_bounds__(256) reduce_tw_kernel(const RedTwTask* __restrict__ tasks) {
+  const RedTwTask t = tasks[blockIdx.x];
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  if (c >= t.ncols) return;
+  zd w[kQrNb];
+  for (int q = 0; q < t.nb; ++q) w[q] = zd{0.0, 0.0};
+  for (int k = 0; k < t.nsplit; ++k) {
+    const zd* p = t.part + (int64_t)k * t.part_stride + (int64_t)c * t.nb;
+    for (int q = 0; q < t.nb; ++q) w[q] = zadd(w[q], p[q]);
+  }
+  zd* o = t.W2 + (int64_t)c * t.nb;
+  for (int r = 0; r < t.nb; ++r) {
+    // (Tw^H w)_r = sum_q conj(Tw[q, r]) w_q, Tw upper triangular (q <= r)
+    zd a{0.0, 0.0};
+    for (int q = 0; q <= r; ++q) zfmac(a, t.Tw[q + r * t.nb], w[q]);
+    o[r] = a;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
-// Greedy CPQR of an m x m matrix in place with exact column norms at every step, then
-// T = R11^{-1} R12 (ld m). Ties in the norm go to the lowest original column index.
+// T = R11^{-1} R12 for R (m x m, ld lda) with rank s: T is s x (m - s), written with ld m.
+// The right-hand sides are processed transposed in scratch W (W[c + i*nc], nc = m - s) so
+// that the lanes of a wavefront, one right-hand side each, touch consecutive addresses;
+// R's column i is read as a broadcast. Call from all 256 threads after a barrier.
+__device__ inline void back_substitute(const zd* __restrict__ R, int64_t lda, int s, int m, zd* W,
+                                       zd* T, bool real_diag) {
+  const int nc = m - s;
+  for (int e = threadIdx.x; e < s * nc; e += 256) {
+    const int c = e % nc, i = e / nc;
+    W[c + (int64_t)i * nc] = R[i + (int64_t)(s + c) * lda];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < nc; c += 256) {
+    for (int i = s - 1; i >= 0; --i) {
+      const zd rii = R[i + (int64_t)i * lda];
+      const zd ti = real_diag ? zscale(W[c + (int64_t)i * nc], 1.0 / rii.re) : zdiv(W[c + (int64_t)i * nc], rii);
+      W[c + (int64_t)i * nc] = ti;
+      const zd* ri = R + (int64_t)i * lda;
+      for (int r = 0; r < i; ++r) W[c + (int64_t)r * nc] = zsub(W[c + (int64_t)r * nc], zmul(ri[r], ti));
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < s * nc; e += 256) {
+    const int i = e % s, c = e / s;
+    T[i + (int64_t)c * m] = W[c + (int64_t)i * nc];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Greedy CPQR of an m x m matrix in place, then T = R11^{-1} R12 (ld m). The squared norms
+// of the trailing columns are recomputed exactly at every step, fused into the reflector
+// pass (dynamic LDS holds them: m doubles). Ties go to the lowest original column index.
 __global__ void __launch_bounds__(256) cpqr_kernel(const CpqrTask* __restrict__ tasks, double eps) {
   const CpqrTask t = tasks[blockIdx.x];
   const int m = t.m;
   const int64_t lda = t.lda;
   zd* R = t.R;
-  __shared__ double bestv[256];
-  __shared__ int besti[256];
-  __shared__ int bestp[256];
+  extern __shared__ double nrm2[];
+  __shared__ double bestv[4];
+  __shared__ int besti[4];
+  __shared__ int bestp[4];
   __shared__ int sh_piv, sh_stop;
   __shared__ double sh_r00;
   __shared__ zd sh_v0, sh_beta;
   __shared__ double sh_tau;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int j = threadIdx.x; j < m; j += 256) t.perm[j] = j;
+  for (int c = wave; c < m; c += 4) {
+    double acc = 0.0;
+    const zd* col = R + (int64_t)c * lda;
+    for (int i = lane; i < m; i += 64) acc += zabs2(col[i]);
+    acc = wave_sum(acc);
+    if (lane == 0) nrm2[c] = acc;
+  }
   __syncthreads();
   int s = m;
   for (int k = 0; k < m; ++k) {
-    // exact norms^2 of columns k..m-1 over rows k..m-1; wave per column
-    double mybest = -1.0;
-    int myi = -1, myp = 0x7fffffff;
-    for (int c = k + wave; c < m; c += 4) {
-      double acc = 0.0;
-      const zd* col = R + (int64_t)c * lda;
-      for (int i = k + lane; i < m; i += 64) acc += zabs2(col[i]);
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        const int pc = t.perm[c];
-        if (acc > mybest || (acc == mybest && pc < myp)) {
-          mybest = acc;
-          myi = c;
-          myp = pc;
-        }
+    // argmax of nrm2[k..m), ties -> lowest original index
+    double mb = -1.0;
+    int mi = -1, mp = 0x7fffffff;
+    for (int c = k + threadIdx.x; c < m; c += 256) {
+      const double v = nrm2[c];
+      const int pc = t.perm[c];
+      if (v > mb || (v == mb && pc < mp)) {
+        mb = v;
+        mi = c;
+        mp = pc;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(mb, o, 64);
+      const int oi = __shfl_xor(mi, o, 64);
+      const int op = __shfl_xor(mp, o, 64);
+      if (oi >= 0 && (mi < 0 || ov > mb || (ov == mb && op < mp))) {
+        mb = ov;
+        mi = oi;
+        mp = op;
       }
     }
     if (lane == 0) {
-      bestv[wave] = mybest;
-      besti[wave] = myi;
-      bestp[wave] = myp;
+      bestv[wave] = mb;
+      besti[wave] = mi;
+      bestp[wave] = mp;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -290,13 +376,13 @@ __global__ void __launch_bounds__(256) cpqr_kernel(const CpqrTask* __restrict__ 
       int bi = -1, bp = 0x7fffffff;
       for (int w = 0; w < 4; ++w) {
         if (besti[w] < 0) continue;
-        if (bestv[w] > bv || (bestv[w] == bv && bestp[w] < bp)) {
+        if (bi < 0 || bestv[w] > bv || (bestv[w] == bv && bestp[w] < bp)) {
           bv = bestv[w];
           bi = besti[w];
           bp = bestp[w];
         }
       }
-      const double nk = sqrt(bv);
+      const double nk = sqrt(fmax(bv, 0.0));
       int stop = 0;
       if (k == 0) {
         sh_r00 = nk;
@@ -323,14 +409,16 @@ __global__ void __launch_bounds__(256) cpqr_kernel(const CpqrTask* __restrict__ 
         int q = t.perm[k];
         t.perm[k] = t.perm[p];
         t.perm[p] = q;
+        double d = nrm2[k];
+        nrm2[k] = nrm2[p];
+        nrm2[p] = d;
       }
     }
     __syncthreads();
     zd* x = R + k + (int64_t)k * lda;
     const int len = m - k;
     if (threadIdx.x == 0) {
-      double ss = 0.0;
-      for (int i = 0; i < len; ++i) ss += zabs2(x[i]);
+      const double ss = nrm2[k];
       const zd a = x[0];
       const double nrm = sqrt(ss);
       const double aa = sqrt(zabs2(a));
@@ -344,7 +432,7 @@ __global__ void __launch_bounds__(256) cpqr_kernel(const CpqrTask* __restrict__ 
     __syncthreads();
     const zd v0 = sh_v0;
     const double tau = sh_tau;
-    // apply to columns k+1..m-1, wave per column
+    // apply to columns k+1..m-1 (wave per column); new squared norm below row k
     for (int c = k + 1 + wave; c < m; c += 4) {
       zd* col = R + k + (int64_t)c * lda;
       zd d{0.0, 0.0};
@@ -352,25 +440,151 @@ __global__ void __launch_bounds__(256) cpqr_kernel(const CpqrTask* __restrict__ 
       d.re = wave_sum(d.re);
       d.im = wave_sum(d.im);
       const zd f = zscale(d, tau);
-      for (int i = lane; i < len; i += 64) col[i] = zsub(col[i], zmul((i == 0) ? v0 : x[i], f));
+      double nn = 0.0;
+      for (int i = lane; i < len; i += 64) {
+        const zd nv = zsub(col[i], zmul((i == 0) ? v0 : x[i], f));
+        col[i] = nv;
+        if (i > 0) nn += zabs2(nv);
+      }
+      nn = wave_sum(nn);
+      if (lane == 0) nrm2[c] = nn;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < len; i += 256) x[i] = (i == 0) ? sh_beta : zd{0.0, 0.0};
     __syncthreads();
   }
   if (threadIdx.x == 0) *t.rank = s;
-  // T = R11^{-1} R12 (s x (m - s)): one thread per right-hand side column, back substitution
   __syncthreads();
-  for (int c = threadIdx.x; c < m - s; c += 256) {
-    zd* tc = t.T + (int64_t)c * m;
-    const zd* rc = R + (int64_t)(s + c) * lda;
-    for (int i = 0; i < s; ++i) tc[i] = rc[i];
-    for (int i = s - 1; i >= 0; --i) {
-      const zd ti = zdiv(tc[i], R[i + (int64_t)i * lda]);
-      tc[i] = ti;
-      for (int r = 0; r < i; ++r) tc[r] = zsub(tc[r], zmul(R[r + (int64_t)i * lda], ti));
-    }
+  back_substitute(R, lda, s, m, t.W, t.T, false);
+}
+
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restrict__ tasks, int ntasks) {
+  const int64_t u = blockIdx.x;
+  const int ti = find_task(tasks, ntasks, u);
+  const SumTask t = tasks[ti];
+  const int64_t e = (u - t.unit_begin) * 256 + threadIdx.x;
+  if (e >= t.count) return;
+  zd a{0.0, 0.0};
+  for (int k = 0; k < t.nsplit; ++k) a = zadd(a, t.part[(int64_t)k * t.stride + e]);
+  t.out[e] = a;
+}
+
+// Left-looking pivoted Cholesky of the Gram matrix (greedy CPQR of M in exact arithmetic).
+__global__ void __launch_bounds__(256) pchol_kernel(const PcholTask* __restrict__ tasks, double eps) {
+  const PcholTask t = tasks[blockIdx.x];
+  const int m = t.m;
+  const zd* G = t.G;
+  zd* R = t.R;
+  extern __shared__ double dg[];
+  __shared__ double bestv[4];
+  __shared__ int besti[4];
+  __shared__ int bestp[4];
+  __shared__ int sh_piv, sh_stop;
+  __shared__ double sh_r00;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int j = threadIdx.x; j < m; j += 256) {
+    t.perm[j] = j;
+    dg[j] = G[j + (int64_t)j * m].re;
   }
+  __syncthreads();
+  int s = m;
+  for (int k = 0; k < m; ++k) {
+    double mb = -1.0;
+    int mi = -1, mp = 0x7fffffff;
+    for (int c = k + threadIdx.x; c < m; c += 256) {
+      const double v = dg[c];
+      const int pc = t.perm[c];
+      if (mi < 0 || v > mb || (v == mb && pc < mp)) {
+        mb = v;
+        mi = c;
+        mp = pc;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(mb, o, 64);
+      const int oi = __shfl_xor(mi, o, 64);
+      const int op = __shfl_xor(mp, o, 64);
+      if (oi >= 0 && (mi < 0 || ov > mb || (ov == mb && op < mp))) {
+        mb = ov;
+        mi = oi;
+        mp = op;
+      }
+    }
+    if (lane == 0) {
+      bestv[wave] = mb;
+      besti[wave] = mi;
+      bestp[wave] = mp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double bv = -1.0;
+      int bi = -1, bp = 0x7fffffff;
+      for (int w = 0; w < 4; ++w) {
+        if (besti[w] < 0) continue;
+        if (bi < 0 || bestv[w] > bv || (bestv[w] == bv && bestp[w] < bp)) {
+          bv = bestv[w];
+          bi = besti[w];
+          bp = bestp[w];
+        }
+      }
+      const double nk = sqrt(fmax(bv, 0.0));
+      int stop = 0;
+      if (k == 0) {
+        sh_r00 = nk;
+        if (nk == 0.0) stop = 1;
+      } else if (nk <= eps * sh_r00) {
+        stop = 1;
+      }
+      sh_stop = stop;
+      sh_piv = bi;
+    }
+    __syncthreads();
+    if (sh_stop) {
+      s = k;
+      break;
+    }
+    const int p = sh_piv;
+    if (p != k) {
+      // swap columns k and p of the rows computed so far
+      for (int l = threadIdx.x; l < k; l += 256) {
+        zd a = R[l + (int64_t)k * m];
+        R[l + (int64_t)k * m] = R[l + (int64_t)p * m];
+        R[l + (int64_t)p * m] = a;
+      }
+      if (threadIdx.x == 0) {
+        int q = t.perm[k];
+        t.perm[k] = t.perm[p];
+        t.perm[p] = q;
+        double d = dg[k];
+        dg[k] = dg[p];
+        dg[p] = d;
+      }
+    }
+    __syncthreads();
+    const double rkk = sqrt(fmax(dg[k], 0.0));
+    const double inv = rkk > 0.0 ? 1.0 / rkk : 0.0;
+    const int pk = t.perm[k];
+    const zd* rk = R + (int64_t)k * m;  // column k of R, rows l < k
+    for (int c = k + 1 + wave; c < m; c += 4) {
+      const zd* rc = R + (int64_t)c * m;
+      zd dot{0.0, 0.0};
+      for (int l = lane; l < k; l += 64) zfmac(dot, rk[l], rc[l]);
+      dot.re = wave_sum(dot.re);
+      dot.im = wave_sum(dot.im);
+      if (lane == 0) {
+        const zd gkc = G[pk + (int64_t)t.perm[c] * m];
+        const zd v = zscale(zsub(gkc, dot), inv);
+        R[k + (int64_t)c * m] = v;
+        dg[c] -= zabs2(v);
+      }
+    }
+    if (threadIdx.x == 0) R[k + (int64_t)k * m] = zd{rkk, 0.0};
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *t.rank = s;
+  __syncthreads();
+  back_substitute(R, m, s, m, t.W, t.T, true);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -651,15 +865,35 @@ void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, con
   FMMLU_HIP(hipGetLastError());
 }
 
+void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st) {
+  if (ntasks <= 0) return;
+  if ((size_t)mmax * sizeof(double) > 65536) throw Error(FMMLU_EINVAL, "ID block wider than 8192");
+  hipLaunchKernelGGL(pchol_kernel, dim3(ntasks), dim3(256), (size_t)mmax * sizeof(double), st, tasks, eps);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_reduce_tw(const RedTwTask* tasks, int ntasks, int nmax, hipStream_t st) {
+  if (ntasks <= 0 || nmax <= 0) return;
+  hipLaunchKernelGGL(reduce_tw_kernel, dim3(ntasks, (nmax + 255) / 256), dim3(256), 0, st, tasks);
+  FMMLU_HIP(hipGetLastError());
+}
+
 void launch_qr_panel(const QrTask* tasks, int ntasks, hipStream_t st) {
   if (ntasks <= 0) return;
   hipLaunchKernelGGL(qr_panel_kernel, dim3(ntasks), dim3(256), 0, st, tasks);
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_cpqr(const CpqrTask* tasks, int ntasks, double eps, hipStream_t st) {
+void launch_cpqr(const CpqrTask* tasks, int ntasks, int mmax, double eps, hipStream_t st) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(cpqr_kernel, dim3(ntasks), dim3(256), 0, st, tasks, eps);
+  if ((size_t)mmax * sizeof(double) > 65536) throw Error(FMMLU_EINVAL, "CPQR block wider than 8192");
+  hipLaunchKernelGGL(cpqr_kernel, dim3(ntasks), dim3(256), (size_t)mmax * sizeof(double), st, tasks, eps);
   FMMLU_HIP(hipGetLastError());
 }
 

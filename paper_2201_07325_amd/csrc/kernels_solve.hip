@@ -51,39 +51,93 @@ __device__ inline zd gemv_t_wave(const zd* __restrict__ A, int64_t lda, int i, i
   return acc;
 }
 
-__global__ void __launch_bounds__(256) solve_fwd_kernel(const SolveBox* __restrict__ boxes, zd* x,
-                                                        zd* y, int adjoint) {
-  const SolveBox b = boxes[blockIdx.x];
-  extern __shared__ zd xr[];
+// y[0:M] = op(A)[0:M, 0:K] v with A column-major (lda); v[k] = fetch(k). Lanes take rows,
+// the four wavefronts split k, partial sums meet in LDS (part: 4 x 64). Result handed to
+// emit(i, value) for i < M. Call from all 256 threads.
+template <class Fetch, class Emit>
+__device__ inline void block_gemv_n(const zd* __restrict__ A, int64_t lda, int M, int K, bool conjA,
+                                    Fetch fetch, Emit emit, zd (*part)[64]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // x_R -= T^T x_S  (adjoint: T^H x_S); T is s x r: output i is column i of T
-  for (int i = wave; i < b.r; i += 4) {
-    zd d{0.0, 0.0};
-    const zd* col = b.T + (int64_t)i * b.s;
-    for (int l = lane; l < b.s; l += 64) {
-      if (adjoint)
-        zfmac(d, col[l], x[b.S[l]]);
-      else
-        zfma(d, col[l], x[b.S[l]]);
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    const int i = i0 + lane;
+    zd acc{0.0, 0.0};
+    if (i < M) {
+      for (int k = wave; k < K; k += 4) {
+        zd a = A[i + (int64_t)k * lda];
+        if (conjA) a.im = -a.im;
+        zfma(acc, a, fetch(k));
+      }
     }
-    d.re = wave_sum(d.re);
-    d.im = wave_sum(d.im);
-    if (lane == 0) {
-      zd v = zsub(x[b.R[i]], d);
-      xr[i] = v;
-      x[b.R[i]] = v;
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && i < M) {
+      zd sum = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
+      emit(i, sum);
     }
+    __syncthreads();
   }
+}
+
+// y[i] = sum_k A[k, i]^(*) v[k] for i < M; wavefront per output, lanes over k (coalesced).
+template <class Fetch, class Emit>
+__device__ inline void block_gemv_t(const zd* __restrict__ A, int64_t lda, int M, int K, bool conjA,
+                                    Fetch fetch, Emit emit) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = wave; i < M; i += 4) {
+    zd acc{0.0, 0.0};
+    const zd* col = A + (int64_t)i * lda;
+    for (int k = lane; k < K; k += 64) {
+      if (conjA)
+        zfmac(acc, col[k], fetch(k));
+      else
+        zfma(acc, col[k], fetch(k));
+    }
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) emit(i, acc);
+  }
+}
+
+__global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restrict__ boxes, zd* x,
+                                                       zd* XR, int adjoint) {
+  const SolveBox b = boxes[blockIdx.x];
+  // x_R -= T^T x_S  (adjoint: T^H x_S); T is s x r: output i is column i of T
+  block_gemv_t(b.T, b.s, b.r, b.s, adjoint != 0, [&](int k) { return x[b.S[k]]; },
+               [&](int i, zd d) {
+                 const zd v = zsub(x[b.R[i]], d);
+                 x[b.R[i]] = v;
+                 XR[b.xr_off + i] = v;
+               });
+}
+
+__global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict__ boxes,
+                                                      const SweepTask* __restrict__ tasks,
+                                                      const zd* __restrict__ XR, zd* __restrict__ y,
+                                                      int adjoint) {
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
+  extern __shared__ zd xr[];
+  for (int k = threadIdx.x; k < b.r; k += 256) xr[k] = XR[b.xr_off + k];
   __syncthreads();
-  // y = Lp x_R  (adjoint: Up^H x_R)
   zd* yb = y + b.y_off;
   if (!adjoint) {
-    for (int i = threadIdx.x; i < b.nsn; i += 256) yb[i] = gemv_n_row(b.Lp, b.nsn, i, b.r, xr, false);
+    // y[i] = sum_k Lp[i, k] x_R[k]; thread per row, rows [k0, k0 + kn)
+    for (int i = t.k0 + threadIdx.x; i < t.k0 + t.kn; i += 256) {
+      zd acc{0.0, 0.0};
+      const zd* a = b.Lp + i;
+      for (int k = 0; k < b.r; ++k) zfma(acc, a[(int64_t)k * b.nsn], xr[k]);
+      yb[i] = acc;
+    }
   } else {
-    // Up is r x nsn: output i = sum_k conj(Up[k, i]) xr[k]
-    for (int i = wave; i < b.nsn; i += 4) {
-      zd d = gemv_t_wave(b.Up, b.r, i, b.r, xr, true, lane);
-      if (lane == 0) yb[i] = d;
+    // y[i] = sum_k conj(Up[k, i]) x_R[k]; wavefront per output, lanes over k
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = t.k0 + wave; i < t.k0 + t.kn; i += 4) {
+      const zd* col = b.Up + (int64_t)i * b.r;
+      zd acc{0.0, 0.0};
+      for (int k = lane; k < b.r; k += 64) zfmac(acc, col[k], xr[k]);
+      acc.re = wave_sum(acc.re);
+      acc.im = wave_sum(acc.im);
+      if (lane == 0) yb[i] = acc;
     }
   }
 }
@@ -105,50 +159,71 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
                                                          int adjoint) {
   const SolveBox b = boxes[blockIdx.x];
   extern __shared__ zd xr[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ zd part[4][64];
   for (int l = threadIdx.x; l < b.r; l += 256) xr[l] = x[b.R[l]];
   __syncthreads();
+  if (!adjoint)
+    block_gemv_n(b.Xi, b.r, b.r, b.r, false, [&](int k) { return xr[k]; },
+                 [&](int i, zd v) { x[b.R[i]] = v; }, part);
+  else
+    block_gemv_t(b.Xi, b.r, b.r, b.r, true, [&](int k) { return xr[k]; },
+                 [&](int i, zd v) { x[b.R[i]] = v; });
+}
+
+// Backward partials: P[chunk][i] = sum over the chunk of op(P)[i, k] x_SN[k], i < r.
+__global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __restrict__ boxes,
+                                                          const SweepTask* __restrict__ tasks,
+                                                          const zd* __restrict__ x, zd* __restrict__ Pbuf,
+                                                          int adjoint) {
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
+  __shared__ zd xsn[kSweepCols];
+  __shared__ zd part[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int q = threadIdx.x; q < t.kn; q += 256) xsn[q] = x[b.SN[t.k0 + q]];
+  __syncthreads();
+  zd* out = Pbuf + b.p_off + (int64_t)t.chunk * b.r;
   if (!adjoint) {
-    for (int i = threadIdx.x; i < b.r; i += 256) x[b.R[i]] = gemv_n_row(b.Xi, b.r, i, b.r, xr, false);
+    // Up: r x nsn; lanes take rows i, wavefronts split the chunk's columns
+    for (int i0 = 0; i0 < b.r; i0 += 64) {
+      const int i = i0 + lane;
+      zd acc{0.0, 0.0};
+      if (i < b.r)
+        for (int k = wave; k < t.kn; k += 4) zfma(acc, b.Up[i + (int64_t)(t.k0 + k) * b.r], xsn[k]);
+      part[wave][lane] = acc;
+      __syncthreads();
+      if (wave == 0 && i < b.r)
+        out[i] = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
+      __syncthreads();
+    }
   } else {
-    for (int i = wave; i < b.r; i += 4) {
-      zd d = gemv_t_wave(b.Xi, b.r, i, b.r, xr, true, lane);
-      if (lane == 0) x[b.R[i]] = d;
+    // Lp: nsn x r; output k = sum_{i in chunk} conj(Lp[i, k]) x_SN[i]
+    for (int k = wave; k < b.r; k += 4) {
+      const zd* col = b.Lp + (int64_t)k * b.nsn + t.k0;
+      zd acc{0.0, 0.0};
+      for (int i = lane; i < t.kn; i += 64) zfmac(acc, col[i], xsn[i]);
+      acc.re = wave_sum(acc.re);
+      acc.im = wave_sum(acc.im);
+      if (lane == 0) out[k] = acc;
     }
   }
 }
 
-__global__ void __launch_bounds__(256) solve_bwd_kernel(const SolveBox* __restrict__ boxes, zd* x,
-                                                        int adjoint) {
+__global__ void __launch_bounds__(256) solve_bfin_kernel(const SolveBox* __restrict__ boxes,
+                                                         const zd* __restrict__ Pbuf, zd* x, int adjoint) {
   const SolveBox b = boxes[blockIdx.x];
   extern __shared__ zd xr[];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // x_R -= U x_SN  (adjoint: Lp^H x_SN)
-  if (!adjoint) {
-    // Up: r x nsn; thread per output row i, reading x[SN[c]] (gathered on the fly)
-    for (int i = threadIdx.x; i < b.r; i += 256) {
-      zd acc{0.0, 0.0};
-      for (int c = 0; c < b.nsn; ++c) zfma(acc, b.Up[i + (int64_t)c * b.r], x[b.SN[c]]);
-      xr[i] = zsub(x[b.R[i]], acc);
-    }
-  } else {
-    // Lp: nsn x r; output k = sum_i conj(Lp[i, k]) x[SN[i]]
-    for (int k = wave; k < b.r; k += 4) {
-      zd acc{0.0, 0.0};
-      const zd* col = b.Lp + (int64_t)k * b.nsn;
-      for (int i = lane; i < b.nsn; i += 64) zfmac(acc, col[i], x[b.SN[i]]);
-      acc.re = wave_sum(acc.re);
-      acc.im = wave_sum(acc.im);
-      if (lane == 0) xr[k] = zsub(x[b.R[k]], acc);
-    }
+  __shared__ zd part[4][64];
+  for (int i = threadIdx.x; i < b.r; i += 256) {
+    zd acc = x[b.R[i]];
+    for (int c = 0; c < b.nchunk; ++c) acc = zsub(acc, Pbuf[b.p_off + (int64_t)c * b.r + i]);
+    xr[i] = acc;
+    x[b.R[i]] = acc;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < b.r; i += 256) x[b.R[i]] = xr[i];
-  // x_S -= T x_R  (adjoint: conj(T) x_R); T: s x r, thread per row
-  for (int l = threadIdx.x; l < b.s; l += 256) {
-    zd d = gemv_n_row(b.T, b.s, l, b.r, xr, adjoint != 0);
-    x[b.S[l]] = zsub(x[b.S[l]], d);
-  }
+  // x_S -= T x_R  (adjoint: conj(T) x_R); T: s x r
+  block_gemv_n(b.T, b.s, b.s, b.r, adjoint != 0, [&](int k) { return xr[k]; },
+               [&](int l, zd v) { x[b.S[l]] = zsub(x[b.S[l]], v); }, part);
 }
 
 __global__ void __launch_bounds__(256) gather_top_kernel(const int32_t* __restrict__ top, int n0,
@@ -157,14 +232,27 @@ __global__ void __launch_bounds__(256) gather_top_kernel(const int32_t* __restri
   if (i < n0) tmp[i] = x[top[i]];
 }
 
-// x[top[i]] = sum_j Ainv[i, j] tmp[j]; thread per row
-__global__ void __launch_bounds__(256) top_n_kernel(const zd* __restrict__ A, int n0,
-                                                    const int32_t* __restrict__ top,
-                                                    const zd* __restrict__ tmp, zd* __restrict__ x) {
+// Top block, normal: partial[cb][i] = sum_{j in column block cb} Ainv[i, j] tmp[j]
+// (grid: row blocks of 256 x column blocks of 256), then a finish pass sums the partials.
+__global__ void __launch_bounds__(256) top_n_part_kernel(const zd* __restrict__ A, int n0,
+                                                         const zd* __restrict__ tmp, zd* __restrict__ part) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * 256;
+  __shared__ zd tv[256];
+  const int jn = min(256, n0 - j0);
+  if (threadIdx.x < jn) tv[threadIdx.x] = tmp[j0 + threadIdx.x];
+  __syncthreads();
+  if (i >= n0) return;
+  zd acc{0.0, 0.0};
+  for (int j = 0; j < jn; ++j) zfma(acc, A[i + (int64_t)(j0 + j) * n0], tv[j]);
+  part[(int64_t)blockIdx.y * n0 + i] = acc;
+}
+__global__ void __launch_bounds__(256) top_n_fin_kernel(int n0, int nblk, const int32_t* __restrict__ top,
+                                                        const zd* __restrict__ part, zd* __restrict__ x) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n0) return;
   zd acc{0.0, 0.0};
-  for (int j = 0; j < n0; ++j) zfma(acc, A[i + (int64_t)j * n0], tmp[j]);
+  for (int c = 0; c < nblk; ++c) acc = zadd(acc, part[(int64_t)c * n0 + i]);
   x[top[i]] = acc;
 }
 
@@ -192,11 +280,17 @@ __global__ void __launch_bounds__(256) permute_kernel(const zd* __restrict__ src
 
 }  // namespace
 
-void launch_solve_fwd(const SolveBox* boxes, int nb, int rmax, zd* x, zd* y, int adjoint,
-                      hipStream_t st) {
+void launch_solve_xr(const SolveBox* boxes, int nb, zd* x, zd* XR, int adjoint, hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(solve_fwd_kernel, dim3(nb), dim3(256), (size_t)rmax * sizeof(zd), st, boxes, x, y,
-                     adjoint);
+  hipLaunchKernelGGL(solve_xr_kernel, dim3(nb), dim3(256), 0, st, boxes, x, XR, adjoint);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
+                    zd* y, int adjoint, hipStream_t st) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(solve_y_kernel, dim3(nt), dim3(256), (size_t)rmax * sizeof(zd), st, boxes, tasks, XR,
+                     y, adjoint);
   FMMLU_HIP(hipGetLastError());
 }
 
@@ -215,10 +309,18 @@ void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoi
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_solve_bwd(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, hipStream_t st) {
+void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
+                        int adjoint, hipStream_t st) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(solve_bpart_kernel, dim3(nt), dim3(256), 0, st, boxes, tasks, x, Pbuf, adjoint);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint,
+                       hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(solve_bwd_kernel, dim3(nb), dim3(256), (size_t)rmax * sizeof(zd), st, boxes, x,
-                     adjoint);
+  hipLaunchKernelGGL(solve_bfin_kernel, dim3(nb), dim3(256), (size_t)rmax * sizeof(zd), st, boxes, Pbuf,
+                     x, adjoint);
   FMMLU_HIP(hipGetLastError());
 }
 
@@ -227,10 +329,15 @@ void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp
   if (n0 <= 0) return;
   hipLaunchKernelGGL(gather_top_kernel, dim3((n0 + 255) / 256), dim3(256), 0, st, top, n0, x, tmp);
   FMMLU_HIP(hipGetLastError());
-  if (!adjoint)
-    hipLaunchKernelGGL(top_n_kernel, dim3((n0 + 255) / 256), dim3(256), 0, st, Ainv, n0, top, tmp, x);
-  else
+  if (!adjoint) {
+    const int nblk = (n0 + 255) / 256;
+    zd* part = tmp + n0;
+    hipLaunchKernelGGL(top_n_part_kernel, dim3(nblk, nblk), dim3(256), 0, st, Ainv, n0, tmp, part);
+    FMMLU_HIP(hipGetLastError());
+    hipLaunchKernelGGL(top_n_fin_kernel, dim3(nblk), dim3(256), 0, st, n0, nblk, top, part, x);
+  } else {
     hipLaunchKernelGGL(top_c_kernel, dim3((n0 + 3) / 4), dim3(256), 0, st, Ainv, n0, top, tmp, x);
+  }
   FMMLU_HIP(hipGetLastError());
 }
 

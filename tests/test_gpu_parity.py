@@ -177,3 +177,34 @@ def test_small_and_degenerate(n, leaf):
     err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
     say("small", n, leaf, err, f.info()["n0"])
     assert err <= 10 * 1e-6
+
+
+@pytest.mark.parametrize("route", [1, 2])
+def test_both_cpqr_routes_match_oracle(route):
+    """Gram-matrix route (pivoted Cholesky of M^H M) and Householder route give the oracle's
+    skeletons on the graded ellipsoid and solutions within 10 eps of dense LU."""
+    s = synth.graded_ellipsoid(2500, seed=2, k=3.0, eps=1e-6)
+    f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=s.eps, leaf_size=32, id_route=route)
+    of = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, leaf_size=32)
+    bx = f.boxes()
+    assert len(bx["s"]) == len(of.factors)
+    same = sum(int(a == b.S.size) for a, b in zip(bx["s"], of.factors))
+    say("route", route, "same ranks", same, "of", len(of.factors))
+    assert same >= 0.9 * len(of.factors)
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    b = _rhs(s)
+    xs = np.linalg.solve(a, b)
+    x = f.solve(_cuda(b)).cpu().numpy()
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 10 * s.eps
+
+
+def test_tight_tolerance_householder():
+    s = synth.unit_sphere(2000)
+    f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=1e-10, leaf_size=32)
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    b = _rhs(s)
+    xs = np.linalg.solve(a, b)
+    x = f.solve(_cuda(b)).cpu().numpy()
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    say("eps 1e-10 err", err, f.info()["n0"])
+    assert err <= 1e-9
