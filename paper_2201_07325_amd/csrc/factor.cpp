@@ -23,6 +23,7 @@
 #include "factor.hpp"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -164,8 +165,14 @@ struct Stage {
     FMMLU_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, st));
     return d;
   }
-  void sync_reset() {
+  double t_wait = 0;
+  void sync() {
+    auto a = std::chrono::steady_clock::now();
     FMMLU_HIP(hipStreamSynchronize(st));
+    t_wait += std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+  }
+  void sync_reset() {
+    sync();
     if (prof) prof->harvest();
     dev.reset();
     host.reset();
@@ -267,7 +274,9 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
   zd** dW = sg.up(W);
   int32_t** dwork = sg.up(work);
   zd** dout = sg.up(outs);
-  std::vector<GemmBatch> steps;
+  // all steps' GEMM descriptors are concatenated into one batch and uploaded once
+  GemmBatch all;
+  std::vector<std::array<int64_t, 4>> sidx;  // task begin, count, unit base, units
   for (int j0 = 0; j0 < nmax; j0 += kGjBlock) {
     GemmBatch gb;
     for (int i = 0; i < nt; ++i) {
@@ -282,16 +291,24 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
         gb.add1(t.A + (int64_t)c1 * t.lda, t.lda, t.n, t.n - c1, t.A + (int64_t)j0 * t.lda, t.lda,
                 W[i] + (int64_t)c1 * nb, nb, nb, 1.0, 1.0);
     }
-    gb.prepare(sg);
-    steps.push_back(std::move(gb));
+    const int64_t tb = (int64_t)all.tasks.size();
+    const int64_t seg0 = (int64_t)all.segs.size();
+    for (auto t : gb.tasks) {
+      t.seg_begin += (int32_t)seg0;
+      all.tasks.push_back(t);
+    }
+    for (auto& g : gb.segs) all.segs.push_back(g);
+    sidx.push_back({tb, (int64_t)gb.tasks.size(), 0, gb.units});
   }
+  all.prepare(sg);
   ProfScope ps(*sg.prof, cls);
   int step = 0;
   for (int j0 = 0; j0 < nmax; j0 += kGjBlock, ++step) {
     launch_gj_panel(dt, nt, j0, sg.st);
     launch_gj_swaps(dt, nt, j0, nmax, sg.st);
     launch_gj_copyrow(dt, nt, j0, nmax, dW, sg.st);
-    steps[step].launch(sg, 0);
+    if (sidx[step][1] > 0)
+      launch_gemm(0, all.dt + sidx[step][0], (int)sidx[step][1], sidx[step][3], all.ds, sg.st);
     launch_gj_fixrow(dt, nt, j0, nmax, dW, sg.st);
   }
   launch_gj_unpermute(dt, nt, nmax, dout, dwork, sg.st);
@@ -800,7 +817,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         FMMLU_HIP(hipMemcpyAsync(perms[i].data(), plan[i].perm, sizeof(int32_t) * plan[i].m,
                                  hipMemcpyDeviceToHost, st));
       }
-      FMMLU_HIP(hipStreamSynchronize(st));
+      sg.sync();
       for (int i = 0; i < nb; ++i) {
         double f = 0;
         for (int kk = 0; kk < ranks[i]; ++kk) f += 2.0 * (double)(plan[i].m - kk) * (plan[i].m - kk);
@@ -811,6 +828,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int pi;  // index into plan
         int s, r, nsn;
         zd *Ccol, *Crow;
+        zd* Up;  // X_RR^{-1} X_{R (S u N)} (r x nsn), scratch; stored transposed in the factor
         FactorBox* fb;
       };
       std::vector<ElimPlan> ep;
@@ -829,6 +847,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       if (ne > 0) {
         boxes.resize(box_base + ne);
         // factor storage and index lists
+        std::vector<int32_t> idx_cat;
+        std::vector<std::array<int64_t, 3>> idx_off(ne);
         std::vector<CrossTask> cross;
         std::vector<NSeg> nsegs;
         int64_t cunits = 0;
@@ -848,23 +868,23 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           fb.r = e.r;
           fb.nsn = e.nsn;
           const std::vector<int32_t>& pv = perms[e.pi];
-          std::vector<int32_t> Ridx(e.r), Sidx(e.s), SNidx;
-          for (int j = 0; j < e.s; ++j) Sidx[j] = (int32_t)B.act[pv[j]];
-          for (int j = 0; j < e.r; ++j) Ridx[j] = (int32_t)B.act[pv[e.s + j]];
-          SNidx = Sidx;
+          // index lists of all boxes of the phase go up in one copy (offsets patched below)
+          idx_off[q][0] = (int64_t)idx_cat.size();
+          for (int j = 0; j < e.r; ++j) idx_cat.push_back((int32_t)B.act[pv[e.s + j]]);
+          idx_off[q][1] = (int64_t)idx_cat.size();
+          for (int j = 0; j < e.s; ++j) idx_cat.push_back((int32_t)B.act[pv[j]]);
+          idx_off[q][2] = (int64_t)idx_cat.size();
+          for (int j = 0; j < e.s; ++j) idx_cat.push_back((int32_t)B.act[pv[j]]);
           for (int o : bp.nown_)
-            for (int32_t l : own[o].live) SNidx.push_back((int32_t)own[o].act[l]);
+            for (int32_t l : own[o].live) idx_cat.push_back((int32_t)own[o].act[l]);
           fb.skel_orig.resize(e.s);
-          for (int j = 0; j < e.s; ++j) fb.skel_orig[j] = order[Sidx[j]];
+          for (int j = 0; j < e.s; ++j) fb.skel_orig[j] = order[B.act[pv[j]]];
           std::sort(fb.skel_orig.begin(), fb.skel_orig.end());
           SolveBox& d = fb.dev;
-          d.R = sg.up_to(arena, Ridx);
-          d.S = e.s ? sg.up_to(arena, Sidx) : nullptr;
-          d.SN = e.nsn ? sg.up_to(arena, SNidx) : nullptr;
           d.T = e.s ? arena.alloc_n<zd>((size_t)e.s * e.r) : nullptr;
           d.Xi = arena.alloc_n<zd>((size_t)e.r * e.r);
           d.Lp = e.nsn ? arena.alloc_n<zd>((size_t)e.nsn * e.r) : nullptr;
-          d.Up = e.nsn ? arena.alloc_n<zd>((size_t)e.r * e.nsn) : nullptr;
+          d.UpT = e.nsn ? arena.alloc_n<zd>((size_t)e.r * e.nsn) : nullptr;
           d.r = e.r;
           d.s = e.s;
           d.nsn = e.nsn;
@@ -898,6 +918,15 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           cunits += units64(mn, bp.m) + units64(bp.m, mn);
           cross.push_back(ct);
           info.max_rank = std::max(info.max_rank, e.s);
+        }
+        {
+          int32_t* base = sg.up_to(arena, idx_cat);
+          for (int q = 0; q < ne; ++q) {
+            SolveBox& d = boxes[box_base + q].dev;
+            d.R = base + idx_off[q][0];
+            d.S = ep[q].s ? base + idx_off[q][1] : nullptr;
+            d.SN = ep[q].nsn ? base + idx_off[q][2] : nullptr;
+          }
         }
         CrossTask* dcross = sg.up(cross);
         NSeg* dns = nsegs.empty() ? nullptr : sg.up(nsegs);
@@ -952,8 +981,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         // panels: Lp = X_{SN,R} Xi ; Up = Xi X_{R,SN}; T compacted into the factor
         {
           GemmBatch gp;
-          std::vector<CopyTask> cps;
-          int64_t cu = 0;
+          std::vector<CopyTask> cps, trs;
+          int64_t cu = 0, tu = 0;
           for (auto& e : ep) {
             BoxPlan& bp = plan[e.pi];
             const int m = bp.m, mn = bp.m + bp.nN;
@@ -961,8 +990,11 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             if (e.nsn > 0) {
               const zd* XsnR = e.Ccol + (int64_t)e.s * mn + e.r;         // X_{(S u N) R}
               const zd* XRsn = e.Crow + e.s + (int64_t)e.r * m;          // X_{R (S u N)}
+              e.Up = sg.dev.alloc_n<zd>((size_t)e.r * e.nsn);
               gp.add1(const_cast<zd*>(d.Lp), e.nsn, e.nsn, e.r, XsnR, mn, d.Xi, e.r, e.r, 1.0, 0.0);
-              gp.add1(const_cast<zd*>(d.Up), e.r, e.r, e.nsn, d.Xi, e.r, XRsn, m, e.r, 1.0, 0.0);
+              gp.add1(e.Up, e.r, e.r, e.nsn, d.Xi, e.r, XRsn, m, e.r, 1.0, 0.0);
+              trs.push_back(CopyTask{e.Up, const_cast<zd*>(d.UpT), e.r, e.nsn, e.r, e.nsn, tu});
+              tu += units64(e.r, e.nsn);
             }
             if (e.s > 0) {
               CopyTask c{bp.T, const_cast<zd*>(d.T), e.s, e.r, m, e.s, cu};
@@ -972,29 +1004,28 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           }
           gp.prepare(sg);
           CopyTask* dcp = cps.empty() ? nullptr : sg.up(cps);
+          CopyTask* dtr = trs.empty() ? nullptr : sg.up(trs);
           ProfScope ps(prof, KC_ELIM);
           gp.launch(sg, 0);
           if (dcp) launch_copy(dcp, (int)cps.size(), cu, st);
+          if (dtr) launch_transpose(dtr, (int)trs.size(), tu, st);
           for (auto& e : ep) prof.flops[KC_ELIM] += 8.0 * 2.0 * (double)e.nsn * e.r * e.r;
         }
-        // 5. Schur update of near-near tiles: A[SN, SN] -= X_{SN,R} Up
+        // 5. Schur update of near-near tiles: A[SN, SN] -= X_{SN,R} Up. One GEMM task per
+        //    destination tile; contributions of several boxes are its segments, in box order.
         {
-          GemmBatch gs;
-          std::map<int64_t, int> dest;  // tile offset -> task index (ordered for determinism)
-          struct Dst {
-            zd* C;
-            int ldc, M, N;
-            const int32_t *rmap, *cmap;
-            std::vector<GemmSeg> segs;
+          struct Contrib {
+            int64_t toff;
+            int q;       // elimination index (box order)
+            int32_t a, b;  // group indices (0 = the box itself, else near owner index + 1)
           };
-          std::vector<Dst> dsts;
-          for (auto& e : ep) {
+          std::vector<Contrib> cl;
+          std::vector<std::vector<int>> grps(ne), goffs(ne);
+          for (int q = 0; q < ne; ++q) {
+            ElimPlan& e = ep[q];
             BoxPlan& bp = plan[e.pi];
-            const int mn = bp.m + bp.nN;
-            SolveBox& d = e.fb->dev;
-            // owners of the S u N rows: B itself then its near owners
-            std::vector<int> grp;
-            std::vector<int> goff;
+            auto& grp = grps[q];
+            auto& goff = goffs[q];
             grp.push_back(bp.oi);
             goff.push_back(0);
             int off = e.s;
@@ -1005,38 +1036,39 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             }
             for (size_t a = 0; a < grp.size(); ++a)
               for (size_t b = 0; b < grp.size(); ++b) {
-                const int o1 = grp[a], o2 = grp[b];
-                const int M = (a == 0) ? e.s : (int)own[o1].live.size();
-                const int N = (b == 0) ? e.s : (int)own[o2].live.size();
+                const int M = (a == 0) ? e.s : (int)own[grp[a]].live.size();
+                const int N = (b == 0) ? e.s : (int)own[grp[b]].live.size();
                 if (M == 0 || N == 0) continue;
-                const int64_t toff = pair_off.at((int64_t)o1 * nown + o2);
-                auto it = dest.find(toff);
-                int di;
-                if (it == dest.end()) {
-                  di = (int)dsts.size();
-                  dest[toff] = di;
-                  Dst ds;
-                  ds.C = pool + toff;
-                  ds.ldc = (int)own[o1].act.size();
-                  ds.M = M;
-                  ds.N = N;
-                  ds.rmap = (a == 0) ? bp.perm : own[o1].live_dev;
-                  ds.cmap = (b == 0) ? bp.perm : own[o2].live_dev;
-                  dsts.push_back(ds);
-                } else {
-                  di = it->second;
-                }
-                dsts[di].segs.push_back(GemmSeg{e.Ccol + (int64_t)e.s * mn + e.r + goff[a],
-                                                d.Up + (int64_t)goff[b] * e.r, mn, e.r, e.r, 0});
+                cl.push_back(Contrib{pair_off.at((int64_t)grp[a] * nown + grp[b]), q, (int32_t)a, (int32_t)b});
               }
           }
-          for (auto& kv : dest) {
-            Dst& ds = dsts[kv.second];
-            gs.add(ds.C, ds.ldc, ds.M, ds.N, ds.rmap, ds.cmap, ds.segs, -1.0, 0.0, 1.0);
+          std::stable_sort(cl.begin(), cl.end(), [](const Contrib& x, const Contrib& y) { return x.toff < y.toff; });
+          GemmBatch gs;
+          std::vector<GemmSeg> segs;
+          for (size_t i = 0; i < cl.size();) {
+            size_t j = i;
+            segs.clear();
+            for (; j < cl.size() && cl[j].toff == cl[i].toff; ++j) {
+              const Contrib& c = cl[j];
+              ElimPlan& e = ep[c.q];
+              const int mn = plan[e.pi].m + plan[e.pi].nN;
+              segs.push_back(GemmSeg{e.Ccol + (int64_t)e.s * mn + e.r + goffs[c.q][c.a],
+                                     e.Up + (int64_t)goffs[c.q][c.b] * e.r, mn, e.r, e.r, 0});
+            }
+            const Contrib& c0 = cl[i];
+            ElimPlan& e0 = ep[c0.q];
+            BoxPlan& bp0 = plan[e0.pi];
+            const int o1 = grps[c0.q][c0.a], o2 = grps[c0.q][c0.b];
+            const int M = (c0.a == 0) ? e0.s : (int)own[o1].live.size();
+            const int N = (c0.b == 0) ? e0.s : (int)own[o2].live.size();
+            const int32_t* rmap = (c0.a == 0) ? bp0.perm : own[o1].live_dev;
+            const int32_t* cmap = (c0.b == 0) ? bp0.perm : own[o2].live_dev;
+            gs.add(pool + c0.toff, (int)own[o1].act.size(), M, N, rmap, cmap, segs, -1.0, 0.0, 1.0);
             double kk = 0;
-            for (auto& sgm : ds.segs) kk += sgm.K;
-            prof.flops[KC_SCHUR] += 8.0 * ds.M * ds.N * kk;
-            prof.bytes[KC_SCHUR] += 32.0 * ds.M * ds.N;
+            for (auto& sgm : segs) kk += sgm.K;
+            prof.flops[KC_SCHUR] += 8.0 * M * N * kk;
+            prof.bytes[KC_SCHUR] += 32.0 * M * N;
+            i = j;
           }
           for (auto& e : ep) prof.bytes[KC_SCHUR] += 32.0 * (double)e.nsn * e.r;
           gs.prepare(sg);
@@ -1072,7 +1104,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         ph.box_begin = (int)box_base;
         ph.box_end = (int)boxes.size();
         int64_t yo = 0, xo = 0, po = 0;
-        std::map<int32_t, std::vector<int64_t>> contrib;
+        std::vector<std::pair<int32_t, int64_t>> contrib;  // (destination, y index)
         std::vector<SolveBox> db;
         std::vector<SweepTask> ty, tp;
         for (int b = ph.box_begin; b < ph.box_end; ++b) {
@@ -1088,6 +1120,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           for (int c = 0; c < fb.dev.nchunk; ++c)
             tp.push_back(SweepTask{lb, c * kSweepCols, std::min(kSweepCols, fb.nsn - c * kSweepCols), c});
           ph.rmax = std::max(ph.rmax, fb.r);
+          ph.smax = std::max(ph.smax, fb.s);
           db.push_back(fb.dev);
           yo += fb.nsn;
           xo += fb.r;
@@ -1100,19 +1133,25 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           Owner& B = own[bp.oi];
           const std::vector<int32_t>& pv = perms[e.pi];
           FactorBox& fb = boxes[box_base + q];
-          int c = 0;
-          for (int j = 0; j < e.s; ++j) contrib[(int32_t)B.act[pv[j]]].push_back(fb.y_off + c++);
+          int64_t c = fb.y_off;
+          for (int j = 0; j < e.s; ++j) contrib.emplace_back((int32_t)B.act[pv[j]], c++);
           for (int o : bp.nown_)
-            for (int32_t l : own[o].live) contrib[(int32_t)own[o].act[l]].push_back(fb.y_off + c++);
+            for (int32_t l : own[o].live) contrib.emplace_back((int32_t)own[o].act[l], c++);
         }
+        // group by destination; y indices increase with the box order, so sorting the pairs
+        // keeps each destination's contributions in box order
+        std::sort(contrib.begin(), contrib.end());
         std::vector<int32_t> dst;
         std::vector<int64_t> ptr{0}, src;
-        for (auto& kv : contrib) {
-          dst.push_back(kv.first);
-          for (int64_t v : kv.second) src.push_back(v);
-          ptr.push_back((int64_t)src.size());
+        dst.reserve(contrib.size());
+        src.reserve(contrib.size());
+        for (size_t i = 0; i < contrib.size(); ++i) {
+          if (i > 0 && contrib[i].first != contrib[i - 1].first) ptr.push_back((int64_t)src.size());
+          if (i == 0 || contrib[i].first != contrib[i - 1].first) dst.push_back(contrib[i].first);
+          src.push_back(contrib[i].second);
         }
-        if ((size_t)ph.rmax * sizeof(zd) > 65536)
+        if (!contrib.empty()) ptr.push_back((int64_t)src.size());
+        if ((size_t)std::max(ph.rmax, ph.smax) * sizeof(zd) > 65536)
           throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(ph.rmax) +
                                         " DOFs exceeds the solve kernels' LDS bound (4096)");
         ph.ylen = yo;
@@ -1285,6 +1324,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   }
   info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)arena.held());
   info.t_factor = std::chrono::duration<double>(Clock::now() - t0).count();
+  if (opts.verbose)
+    fprintf(stderr, "[fmmlu] factor %.3f s, of which waiting on the GPU %.3f s\n", info.t_factor, sg.t_wait);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1308,7 +1349,7 @@ void FactorImpl::solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream
     launch_permute(bc, wx, order_dev, n, 1, st);
     // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
     for (auto& ph : phases) {
-      launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, wx, wxr, adj, st);
+      launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, wx, wxr, adj, st);
       launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, st);
       launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
     }

@@ -80,7 +80,7 @@ struct SolvePhase {
   SweepTask* dy = nullptr;  // forward row chunks
   SweepTask* dp = nullptr;  // backward column chunks
   int ny = 0, np = 0;
-  int rmax = 0;
+  int rmax = 0, smax = 0;
 };
 
 struct FactorImpl {

@@ -204,6 +204,8 @@ struct CopyTask {
   int64_t unit_begin;
 };
 void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
+// dst[j + i*ldd] = src[i + j*lds] (rows x cols source); units of 64 x 64
+void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
 
 // ---- solve sweeps ----
 struct SolveBox {
@@ -212,8 +214,8 @@ struct SolveBox {
   const int32_t* SN;  // s + nN (S first)
   const zd* T;        // s x r, ld = s
   const zd* Xi;       // r x r inverse pivot block
-  const zd* Lp;       // (s+nN) x r, ld = s+nN
-  const zd* Up;       // r x (s+nN), ld = r
+  const zd* Lp;       // L = X_{(S u N) R} X_RR^{-1}: (s+nN) x r, ld = s+nN
+  const zd* UpT;      // U^T with U = X_RR^{-1} X_{R (S u N)}: (s+nN) x r, ld = s+nN
   int32_t r, s, nsn, nchunk;  // nchunk: backward partial chunks
   int64_t y_off;      // this box's outputs in the forward scatter buffer
   int64_t xr_off;     // this box's x_R copy in the phase buffer
@@ -224,7 +226,7 @@ struct SweepTask {
   int32_t box, k0, kn, chunk;
 };
 // forward, per box: x_R -= op(T) x_S (T^T, adjoint T^H); copy to XR
-void launch_solve_xr(const SolveBox* boxes, int nb, zd* x, zd* XR, int adjoint, hipStream_t st);
+void launch_solve_xr(const SolveBox* boxes, int nb, int smax, zd* x, zd* XR, int adjoint, hipStream_t st);
 // forward, per task: y = op(P) x_R on a row chunk (Lp, adjoint Up^H)
 void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
                     zd* y, int adjoint, hipStream_t st);

@@ -290,15 +290,16 @@ __global__ void __launch_bounds__(256) reduce_tw_kernel(const RedTwTask* __restr
 // The right-hand sides are processed transposed in scratch W (W[c + i*nc], nc = m - s) so
 // that the lanes of a wavefront, one right-hand side each, touch consecutive addresses;
 // R's column i is read as a broadcast. Call from all 256 threads after a barrier.
-__device__ inline void back_substitute(const zd* __restrict__ R, int64_t lda, int s, int m, zd* W,
-                                       zd* T, bool real_diag) {
+template <int NT>
+__device__ inline void back_substitute_n(const zd* __restrict__ R, int64_t lda, int s, int m, zd* W,
+                                         zd* T, bool real_diag) {
   const int nc = m - s;
-  for (int e = threadIdx.x; e < s * nc; e += 256) {
+  for (int e = threadIdx.x; e < s * nc; e += NT) {
     const int c = e % nc, i = e / nc;
     W[c + (int64_t)i * nc] = R[i + (int64_t)(s + c) * lda];
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < nc; c += 256) {
+  for (int c = threadIdx.x; c < nc; c += NT) {
     for (int i = s - 1; i >= 0; --i) {
       const zd rii = R[i + (int64_t)i * lda];
       const zd ti = real_diag ? zscale(W[c + (int64_t)i * nc], 1.0 / rii.re) : zdiv(W[c + (int64_t)i * nc], rii);
@@ -308,10 +309,14 @@ __device__ inline void back_substitute(const zd* __restrict__ R, int64_t lda, in
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < s * nc; e += 256) {
+  for (int e = threadIdx.x; e < s * nc; e += NT) {
     const int i = e % s, c = e / s;
     T[i + (int64_t)c * m] = W[c + (int64_t)i * nc];
   }
+}
+__device__ inline void back_substitute(const zd* __restrict__ R, int64_t lda, int s, int m, zd* W,
+                                       zd* T, bool real_diag) {
+  back_substitute_n<256>(R, lda, s, m, W, T, real_diag);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -471,19 +476,26 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restric
 }
 
 // Left-looking pivoted Cholesky of the Gram matrix (greedy CPQR of M in exact arithmetic).
-__global__ void __launch_bounds__(256) pchol_kernel(const PcholTask* __restrict__ tasks, double eps) {
+// 1024 threads: per step the pivot row of G is staged in LDS, then sixteen wavefronts form
+// the inner products with the previous rows of R, two columns in flight per wavefront.
+constexpr int kPcholThreads = 1024;
+__global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* __restrict__ tasks,
+                                                              double eps) {
   const PcholTask t = tasks[blockIdx.x];
   const int m = t.m;
   const zd* G = t.G;
   zd* R = t.R;
-  extern __shared__ double dg[];
-  __shared__ double bestv[4];
-  __shared__ int besti[4];
-  __shared__ int bestp[4];
+  extern __shared__ double smem[];
+  double* dg = smem;                         // m
+  zd* gk = reinterpret_cast<zd*>(smem + m);  // m (pivot row of G, permuted)
+  constexpr int NW = kPcholThreads / 64;
+  __shared__ double bestv[NW];
+  __shared__ int besti[NW];
+  __shared__ int bestp[NW];
   __shared__ int sh_piv, sh_stop;
   __shared__ double sh_r00;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int j = threadIdx.x; j < m; j += 256) {
+  for (int j = threadIdx.x; j < m; j += kPcholThreads) {
     t.perm[j] = j;
     dg[j] = G[j + (int64_t)j * m].re;
   }
@@ -492,7 +504,7 @@ __global__ void __launch_bounds__(256) pchol_kernel(const PcholTask* __restrict_
   for (int k = 0; k < m; ++k) {
     double mb = -1.0;
     int mi = -1, mp = 0x7fffffff;
-    for (int c = k + threadIdx.x; c < m; c += 256) {
+    for (int c = k + threadIdx.x; c < m; c += kPcholThreads) {
       const double v = dg[c];
       const int pc = t.perm[c];
       if (mi < 0 || v > mb || (v == mb && pc < mp)) {
@@ -520,7 +532,7 @@ __global__ void __launch_bounds__(256) pchol_kernel(const PcholTask* __restrict_
     if (threadIdx.x == 0) {
       double bv = -1.0;
       int bi = -1, bp = 0x7fffffff;
-      for (int w = 0; w < 4; ++w) {
+      for (int w = 0; w < NW; ++w) {
         if (besti[w] < 0) continue;
         if (bi < 0 || bestv[w] > bv || (bestv[w] == bv && bestp[w] < bp)) {
           bv = bestv[w];
@@ -546,12 +558,12 @@ __global__ void __launch_bounds__(256) pchol_kernel(const PcholTask* __restrict_
     }
     const int p = sh_piv;
     if (p != k) {
-      // swap columns k and p of the rows computed so far
-      for (int l = threadIdx.x; l < k; l += 256) {
+      for (int l = threadIdx.x; l < k; l += kPcholThreads) {
         zd a = R[l + (int64_t)k * m];
         R[l + (int64_t)k * m] = R[l + (int64_t)p * m];
         R[l + (int64_t)p * m] = a;
       }
+      __syncthreads();
       if (threadIdx.x == 0) {
         int q = t.perm[k];
         t.perm[k] = t.perm[p];
@@ -562,21 +574,36 @@ __global__ void __launch_bounds__(256) pchol_kernel(const PcholTask* __restrict_
       }
     }
     __syncthreads();
+    const int pk = t.perm[k];
+    for (int c = k + 1 + threadIdx.x; c < m; c += kPcholThreads) gk[c] = G[pk + (int64_t)t.perm[c] * m];
+    __syncthreads();
     const double rkk = sqrt(fmax(dg[k], 0.0));
     const double inv = rkk > 0.0 ? 1.0 / rkk : 0.0;
-    const int pk = t.perm[k];
     const zd* rk = R + (int64_t)k * m;  // column k of R, rows l < k
-    for (int c = k + 1 + wave; c < m; c += 4) {
-      const zd* rc = R + (int64_t)c * m;
-      zd dot{0.0, 0.0};
-      for (int l = lane; l < k; l += 64) zfmac(dot, rk[l], rc[l]);
-      dot.re = wave_sum(dot.re);
-      dot.im = wave_sum(dot.im);
+    for (int c0 = k + 1 + wave; c0 < m; c0 += 2 * NW) {
+      const int c1 = c0 + NW;
+      const bool two = c1 < m;
+      const zd* r0 = R + (int64_t)c0 * m;
+      const zd* r1 = R + (int64_t)(two ? c1 : c0) * m;
+      zd d0{0.0, 0.0}, d1{0.0, 0.0};
+      for (int l = lane; l < k; l += 64) {
+        const zd a = rk[l];
+        zfmac(d0, a, r0[l]);
+        zfmac(d1, a, r1[l]);
+      }
+      d0.re = wave_sum(d0.re);
+      d0.im = wave_sum(d0.im);
+      d1.re = wave_sum(d1.re);
+      d1.im = wave_sum(d1.im);
       if (lane == 0) {
-        const zd gkc = G[pk + (int64_t)t.perm[c] * m];
-        const zd v = zscale(zsub(gkc, dot), inv);
-        R[k + (int64_t)c * m] = v;
-        dg[c] -= zabs2(v);
+        const zd v0 = zscale(zsub(gk[c0], d0), inv);
+        R[k + (int64_t)c0 * m] = v0;
+        dg[c0] -= zabs2(v0);
+        if (two) {
+          const zd v1 = zscale(zsub(gk[c1], d1), inv);
+          R[k + (int64_t)c1 * m] = v1;
+          dg[c1] -= zabs2(v1);
+        }
       }
     }
     if (threadIdx.x == 0) R[k + (int64_t)k * m] = zd{rkk, 0.0};
@@ -584,7 +611,7 @@ __global__ void __launch_bounds__(256) pchol_kernel(const PcholTask* __restrict_
   }
   if (threadIdx.x == 0) *t.rank = s;
   __syncthreads();
-  back_substitute(R, m, s, m, t.W, t.T, true);
+  back_substitute_n<kPcholThreads>(R, m, s, m, t.W, t.T, true);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -849,7 +876,33 @@ __global__ void __launch_bounds__(256) copy_kernel(const CopyTask* __restrict__ 
   }
 }
 
+__global__ void __launch_bounds__(256) transpose_kernel(const CopyTask* __restrict__ tasks, int ntasks) {
+  __shared__ zd tile[64][65];
+  const int64_t u = blockIdx.x;
+  const int ti = find_task(tasks, ntasks, u);
+  const CopyTask t = tasks[ti];
+  const int64_t lu = u - t.unit_begin;
+  const int nbr = (t.rows + 63) >> 6;
+  const int bi = (int)(lu % nbr), bj = (int)(lu / nbr);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int q = ty; q < 64; q += 4) {
+    const int i = bi * 64 + tx, j = bj * 64 + q;
+    if (i < t.rows && j < t.cols) tile[q][tx] = t.src[i + (int64_t)j * t.lds];
+  }
+  __syncthreads();
+  for (int q = ty; q < 64; q += 4) {
+    const int j = bj * 64 + tx, i = bi * 64 + q;
+    if (i < t.rows && j < t.cols) t.dst[j + (int64_t)i * t.ldd] = tile[tx][q];
+  }
+}
+
 }  // namespace
+
+void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
+  FMMLU_HIP(hipGetLastError());
+}
 
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
                  hipStream_t st) {
@@ -873,8 +926,9 @@ void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStrea
 
 void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st) {
   if (ntasks <= 0) return;
-  if ((size_t)mmax * sizeof(double) > 65536) throw Error(FMMLU_EINVAL, "ID block wider than 8192");
-  hipLaunchKernelGGL(pchol_kernel, dim3(ntasks), dim3(256), (size_t)mmax * sizeof(double), st, tasks, eps);
+  const size_t lds = (size_t)mmax * (sizeof(double) + sizeof(zd));
+  if (lds > 65536) throw Error(FMMLU_EINVAL, "ID block wider than 2730");
+  hipLaunchKernelGGL(pchol_kernel, dim3(ntasks), dim3(kPcholThreads), lds, st, tasks, eps);
   FMMLU_HIP(hipGetLastError());
 }
 

@@ -98,11 +98,14 @@ __device__ inline void block_gemv_t(const zd* __restrict__ A, int64_t lda, int M
   }
 }
 
+// Forward, per box: x_R -= T^T x_S (adjoint T^H x_S). x_S is gathered into LDS first.
 __global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restrict__ boxes, zd* x,
                                                        zd* XR, int adjoint) {
   const SolveBox b = boxes[blockIdx.x];
-  // x_R -= T^T x_S  (adjoint: T^H x_S); T is s x r: output i is column i of T
-  block_gemv_t(b.T, b.s, b.r, b.s, adjoint != 0, [&](int k) { return x[b.S[k]]; },
+  extern __shared__ zd xs[];
+  for (int k = threadIdx.x; k < b.s; k += 256) xs[k] = x[b.S[k]];
+  __syncthreads();
+  block_gemv_t(b.T, b.s, b.r, b.s, adjoint != 0, [&](int k) { return xs[k]; },
                [&](int i, zd d) {
                  const zd v = zsub(x[b.R[i]], d);
                  x[b.R[i]] = v;
@@ -110,6 +113,8 @@ __global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restric
                });
 }
 
+// Forward, one row chunk of a box: y[i] = sum_k P[i, k] x_R[k] with P = Lp (adjoint: conj(U^T)),
+// P stored (s+nN) x r column-major; thread per row, four independent accumulators.
 __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict__ boxes,
                                                       const SweepTask* __restrict__ tasks,
                                                       const zd* __restrict__ XR, zd* __restrict__ y,
@@ -120,25 +125,30 @@ __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict
   for (int k = threadIdx.x; k < b.r; k += 256) xr[k] = XR[b.xr_off + k];
   __syncthreads();
   zd* yb = y + b.y_off;
-  if (!adjoint) {
-    // y[i] = sum_k Lp[i, k] x_R[k]; thread per row, rows [k0, k0 + kn)
-    for (int i = t.k0 + threadIdx.x; i < t.k0 + t.kn; i += 256) {
-      zd acc{0.0, 0.0};
-      const zd* a = b.Lp + i;
-      for (int k = 0; k < b.r; ++k) zfma(acc, a[(int64_t)k * b.nsn], xr[k]);
-      yb[i] = acc;
+  const zd* P = adjoint ? b.UpT : b.Lp;
+  const int64_t ld = b.nsn;
+  for (int i = t.k0 + threadIdx.x; i < t.k0 + t.kn; i += 256) {
+    zd a0{0.0, 0.0}, a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
+    const zd* pr = P + i;
+    int k = 0;
+    if (!adjoint) {
+      for (; k + 3 < b.r; k += 4) {
+        zfma(a0, pr[(int64_t)k * ld], xr[k]);
+        zfma(a1, pr[(int64_t)(k + 1) * ld], xr[k + 1]);
+        zfma(a2, pr[(int64_t)(k + 2) * ld], xr[k + 2]);
+        zfma(a3, pr[(int64_t)(k + 3) * ld], xr[k + 3]);
+      }
+      for (; k < b.r; ++k) zfma(a0, pr[(int64_t)k * ld], xr[k]);
+    } else {
+      for (; k + 3 < b.r; k += 4) {
+        zfmac(a0, pr[(int64_t)k * ld], xr[k]);
+        zfmac(a1, pr[(int64_t)(k + 1) * ld], xr[k + 1]);
+        zfmac(a2, pr[(int64_t)(k + 2) * ld], xr[k + 2]);
+        zfmac(a3, pr[(int64_t)(k + 3) * ld], xr[k + 3]);
+      }
+      for (; k < b.r; ++k) zfmac(a0, pr[(int64_t)k * ld], xr[k]);
     }
-  } else {
-    // y[i] = sum_k conj(Up[k, i]) x_R[k]; wavefront per output, lanes over k
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = t.k0 + wave; i < t.k0 + t.kn; i += 4) {
-      const zd* col = b.Up + (int64_t)i * b.r;
-      zd acc{0.0, 0.0};
-      for (int k = lane; k < b.r; k += 64) zfmac(acc, col[k], xr[k]);
-      acc.re = wave_sum(acc.re);
-      acc.im = wave_sum(acc.im);
-      if (lane == 0) yb[i] = acc;
-    }
+    yb[i] = zadd(zadd(a0, a1), zadd(a2, a3));
   }
 }
 
@@ -170,7 +180,8 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
                  [&](int i, zd v) { x[b.R[i]] = v; });
 }
 
-// Backward partials: P[chunk][i] = sum over the chunk of op(P)[i, k] x_SN[k], i < r.
+// Backward partials over a chunk of S u N: out[i] = sum_{k in chunk} Q[k, i] x_SN[k], i < r,
+// with Q = U^T (adjoint: conj(Lp)), stored (s+nN) x r; wavefront per output, lanes over k.
 __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __restrict__ boxes,
                                                           const SweepTask* __restrict__ tasks,
                                                           const zd* __restrict__ x, zd* __restrict__ Pbuf,
@@ -178,34 +189,34 @@ __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __rest
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd xsn[kSweepCols];
-  __shared__ zd part[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int q = threadIdx.x; q < t.kn; q += 256) xsn[q] = x[b.SN[t.k0 + q]];
   __syncthreads();
   zd* out = Pbuf + b.p_off + (int64_t)t.chunk * b.r;
-  if (!adjoint) {
-    // Up: r x nsn; lanes take rows i, wavefronts split the chunk's columns
-    for (int i0 = 0; i0 < b.r; i0 += 64) {
-      const int i = i0 + lane;
-      zd acc{0.0, 0.0};
-      if (i < b.r)
-        for (int k = wave; k < t.kn; k += 4) zfma(acc, b.Up[i + (int64_t)(t.k0 + k) * b.r], xsn[k]);
-      part[wave][lane] = acc;
-      __syncthreads();
-      if (wave == 0 && i < b.r)
-        out[i] = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
-      __syncthreads();
+  const zd* Q = adjoint ? b.Lp : b.UpT;
+  constexpr int NI = kSweepCols / 64;  // loads per lane, issued together
+  for (int i = wave; i < b.r; i += 4) {
+    const zd* col = Q + (int64_t)i * b.nsn + t.k0;
+    zd v[NI];
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int k = lane + 64 * j;
+      v[j] = k < t.kn ? col[k] : zd{0.0, 0.0};
     }
-  } else {
-    // Lp: nsn x r; output k = sum_{i in chunk} conj(Lp[i, k]) x_SN[i]
-    for (int k = wave; k < b.r; k += 4) {
-      const zd* col = b.Lp + (int64_t)k * b.nsn + t.k0;
-      zd acc{0.0, 0.0};
-      for (int i = lane; i < t.kn; i += 64) zfmac(acc, col[i], xsn[i]);
-      acc.re = wave_sum(acc.re);
-      acc.im = wave_sum(acc.im);
-      if (lane == 0) out[k] = acc;
+    zd acc{0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int k = lane + 64 * j;
+      if (k < t.kn) {
+        if (adjoint)
+          zfmac(acc, v[j], xsn[k]);
+        else
+          zfma(acc, v[j], xsn[k]);
+      }
     }
+    acc.re = wave_sum(acc.re);
+    acc.im = wave_sum(acc.im);
+    if (lane == 0) out[i] = acc;
   }
 }
 
@@ -280,9 +291,10 @@ __global__ void __launch_bounds__(256) permute_kernel(const zd* __restrict__ src
 
 }  // namespace
 
-void launch_solve_xr(const SolveBox* boxes, int nb, zd* x, zd* XR, int adjoint, hipStream_t st) {
+void launch_solve_xr(const SolveBox* boxes, int nb, int smax, zd* x, zd* XR, int adjoint, hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(solve_xr_kernel, dim3(nb), dim3(256), 0, st, boxes, x, XR, adjoint);
+  hipLaunchKernelGGL(solve_xr_kernel, dim3(nb), dim3(256), (size_t)smax * sizeof(zd), st, boxes, x, XR,
+                     adjoint);
   FMMLU_HIP(hipGetLastError());
 }
 
