@@ -137,12 +137,70 @@ int64_t gap_units(const Owner& a, const Owner& b) {
   return std::max<int64_t>(g, 0);
 }
 
+// Host wall-clock accumulators for the verbose report.
+struct HostTimers {
+  double t[8] = {0};
+  Clock::time_point last = Clock::now();
+  void mark(int i) {
+    auto now = Clock::now();
+    t[i] += std::chrono::duration<double>(now - last).count();
+    last = now;
+  }
+};
+
+// Two scratch buffers used alternately by consecutive colour phases: the rank read-back of
+// phase p waits for everything queued before phase p's ID, which includes all of phase
+// p-1's work, so the buffer of phase p-1 can be recycled by phase p+1 without a wait.
+class DoubleArena {
+ public:
+  void* alloc(size_t b) { return a_[cur_].alloc(b); }
+  template <class T>
+  T* alloc_n(size_t n) {
+    return a_[cur_].alloc_n<T>(n);
+  }
+  void reset() { a_[cur_].reset(); }
+  void reset_all() {
+    a_[0].reset();
+    a_[1].reset();
+  }
+  void flip() {
+    cur_ ^= 1;
+    a_[cur_].reset();
+  }
+
+ private:
+  DeviceArena a_[2] = {DeviceArena(size_t(512) << 20), DeviceArena(size_t(512) << 20)};
+  int cur_ = 0;
+};
+class DoubleHostStage {
+ public:
+  void* alloc(size_t b) { return h_[cur_].alloc(b); }
+  void reset() { h_[cur_].reset(); }
+  void reset_all() {
+    h_[0].reset();
+    h_[1].reset();
+  }
+  void flip() {
+    cur_ ^= 1;
+    h_[cur_].reset();
+  }
+
+ private:
+  HostStage h_[2];
+  int cur_ = 0;
+};
+
 struct Stage {
-  // device scratch for one phase / assembly, reset after each synchronisation
-  DeviceArena dev{size_t(512) << 20};
-  HostStage host;
+  // device scratch and pinned staging, double-buffered across colour phases
+  DoubleArena dev;
+  DoubleHostStage host;
   hipStream_t st = nullptr;
   Profiler* prof = nullptr;
+  // switch to the other buffer at the start of a colour phase (see DoubleArena)
+  void flip() {
+    dev.flip();
+    host.flip();
+  }
 
   template <class T>
   T* up(const std::vector<T>& v) {
@@ -174,8 +232,8 @@ struct Stage {
   void sync_reset() {
     sync();
     if (prof) prof->harvest();
-    dev.reset();
-    host.reset();
+    dev.reset_all();
+    host.reset_all();
   }
 };
 
@@ -478,6 +536,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     return -1;
   };
 
+  HostTimers ht;
   for (int lev = tree.nlevels - 1; lev >= 2; --lev) {
     const int nown = (int)own.size();
     by_box.clear();
@@ -520,6 +579,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     }
     info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)(arena.held() + pool_elems * 16));
     info.bytes_tiles += (double)pool_elems * 16.0;
+    ht.mark(0);
     // ---- assemble: slot/idx maps, dof lists, source tables
     {
       std::vector<int32_t> slot, idx;
@@ -636,6 +696,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
                morton3((uint32_t)own[b].c[0], (uint32_t)own[b].c[1], (uint32_t)own[b].c[2]);
       });
 
+    ht.mark(1);
     for (int colour = 0; colour < 8; ++colour) {
       // ---- plan the phase
       struct BoxPlan {
@@ -693,7 +754,11 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         plan.push_back(std::move(bp));
       }
       if (plan.empty()) continue;
+      // Only phases with work flip: each of them waits on its rank read-back below, which
+      // is what makes the buffer of the phase before last free for reuse.
+      sg.flip();
       const int nb = (int)plan.size();
+      ht.mark(2);
       // ---- 1. ID matrices
       std::vector<IdTask> idt;
       std::vector<QSeg> qsegs;
@@ -823,6 +888,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         for (int kk = 0; kk < ranks[i]; ++kk) f += 2.0 * (double)(plan[i].m - kk) * (plan[i].m - kk);
         prof.flops[KC_CPQR] += 8.0 * f;
       }
+      ht.mark(3);
       // ---- 3. elimination plan
       struct ElimPlan {
         int pi;  // index into plan
@@ -1011,6 +1077,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           if (dtr) launch_transpose(dtr, (int)trs.size(), tu, st);
           for (auto& e : ep) prof.flops[KC_ELIM] += 8.0 * 2.0 * (double)e.nsn * e.r * e.r;
         }
+        ht.mark(4);
         // 5. Schur update of near-near tiles: A[SN, SN] -= X_{SN,R} Up. One GEMM task per
         //    destination tile; contributions of several boxes are its segments, in box order.
         {
@@ -1098,6 +1165,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         live_total -= e.r;
         info.nboxes_factored++;
       }
+      ht.mark(5);
       // build the solve phase record
       if (ne > 0) {
         SolvePhase ph;
@@ -1151,7 +1219,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           src.push_back(contrib[i].second);
         }
         if (!contrib.empty()) ptr.push_back((int64_t)src.size());
-        if ((size_t)std::max(ph.rmax, ph.smax) * sizeof(zd) > 65536)
+        if ((size_t)(ph.rmax + ph.smax) * sizeof(zd) > 65536)
           throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(ph.rmax) +
                                         " DOFs exceeds the solve kernels' LDS bound (4096)");
         ph.ylen = yo;
@@ -1176,18 +1244,19 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         Owner& B = own[plan[ep[q].pi].oi];
         B.live_dev = B.live.empty() ? nullptr : sg.up_to(level_arena, B.live);
       }
-      sg.sync_reset();
-      {
-        int32_t hinfo = 0;
-        FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
-        if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block X_RR at level " + std::to_string(lev));
-      }
       for (auto& bp : plan) info.max_block = std::max(info.max_block, bp.m);
+    }
+    sg.sync_reset();
+    {
+      int32_t hinfo = 0;
+      FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block X_RR at level " + std::to_string(lev));
     }
     if (opts.verbose)
       fprintf(stderr, "[fmmlu] level %d: owners %d pairs %zu tiles %.1f MB live %lld\n", lev, nown,
               pairs.size(), pool_elems * 16.0 / 1e6, (long long)live_total);
 
+    ht.mark(6);
     // ---- next level's owners: merge live DOFs of level-lev owners into parents
     std::vector<Owner> next;
     std::unordered_map<int, int> next_by_box;
@@ -1228,6 +1297,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     FMMLU_HIP(hipStreamSynchronize(st));
   }
 
+  ht.mark(7);
   // ---- top block: all remaining live DOFs (tree order)
   {
     // own holds the owners after the last merge; their act lists are all live.
@@ -1324,8 +1394,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   }
   info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)arena.held());
   info.t_factor = std::chrono::duration<double>(Clock::now() - t0).count();
-  if (opts.verbose)
+  if (opts.verbose) {
     fprintf(stderr, "[fmmlu] factor %.3f s, of which waiting on the GPU %.3f s\n", info.t_factor, sg.t_wait);
+    fprintf(stderr,
+            "[fmmlu] host sections: pairs %.3f assemble %.3f plan %.3f id+readback %.3f elim %.3f "
+            "schur %.3f phase-end %.3f merge %.3f\n",
+            ht.t[0], ht.t[1], ht.t[2], ht.t[3], ht.t[4], ht.t[5], ht.t[6], ht.t[7]);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1349,7 +1424,7 @@ void FactorImpl::solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream
     launch_permute(bc, wx, order_dev, n, 1, st);
     // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
     for (auto& ph : phases) {
-      launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, wx, wxr, adj, st);
+      launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, ph.rmax, wx, wxr, adj, st);
       launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, st);
       launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
     }

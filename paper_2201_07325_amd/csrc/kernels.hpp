@@ -226,7 +226,8 @@ struct SweepTask {
   int32_t box, k0, kn, chunk;
 };
 // forward, per box: x_R -= op(T) x_S (T^T, adjoint T^H); copy to XR
-void launch_solve_xr(const SolveBox* boxes, int nb, int smax, zd* x, zd* XR, int adjoint, hipStream_t st);
+void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint,
+                     hipStream_t st);
 // forward, per task: y = op(P) x_R on a row chunk (Lp, adjoint Up^H)
 void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
                     zd* y, int adjoint, hipStream_t st);
@@ -248,7 +249,7 @@ void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp
 void launch_permute(const zd* src, zd* dst, const int64_t* map, int64_t n, int gather,
                     hipStream_t st);
 constexpr int kSweepRows = 256;   // forward row chunk
-constexpr int kSweepCols = 512;   // backward column chunk
+constexpr int kSweepCols = 256;   // backward column chunk
 
 // ---- stand-alone block of A~ (rows, cols: tree positions) ----
 void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64_t* cols,

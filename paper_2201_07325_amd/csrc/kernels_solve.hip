@@ -98,19 +98,61 @@ __device__ inline void block_gemv_t(const zd* __restrict__ A, int64_t lda, int M
   }
 }
 
-// Forward, per box: x_R -= T^T x_S (adjoint T^H x_S). x_S is gathered into LDS first.
+// y[i] = sum_k A[k, i]^(*) v[k] for i < M, four outputs per wavefront at a time (lanes over k,
+// coalesced; sixteen independent loads per lane in flight). v must be in LDS.
+template <class Emit>
+__device__ inline void block_gemv_t4(const zd* __restrict__ A, int64_t lda, int M, int K, bool conjA,
+                                     const zd* v, Emit emit) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i0 = 4 * wave; i0 < M; i0 += 16) {
+    zd acc[4] = {zd{0.0, 0.0}, zd{0.0, 0.0}, zd{0.0, 0.0}, zd{0.0, 0.0}};
+    for (int k0 = 0; k0 < K; k0 += 256) {
+      zd a[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int k = k0 + lane + 64 * j;
+          a[q][j] = (i0 + q < M && k < K) ? A[(int64_t)(i0 + q) * lda + k] : zd{0.0, 0.0};
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = k0 + lane + 64 * j;
+        const zd vk = k < K ? v[k] : zd{0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (conjA)
+            zfmac(acc[q], a[q][j], vk);
+          else
+            zfma(acc[q], a[q][j], vk);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc[q].re = wave_sum(acc[q].re);
+      acc[q].im = wave_sum(acc[q].im);
+      if (lane == 0 && i0 + q < M) emit(i0 + q, acc[q]);
+    }
+  }
+}
+
+// Forward, per box: x_R -= T^T x_S (adjoint T^H x_S). x_S and x_R are gathered into LDS first.
 __global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restrict__ boxes, zd* x,
-                                                       zd* XR, int adjoint) {
+                                                       zd* XR, int adjoint, int smax) {
   const SolveBox b = boxes[blockIdx.x];
-  extern __shared__ zd xs[];
+  extern __shared__ zd sh[];
+  zd* xs = sh;
+  zd* xr = sh + smax;
   for (int k = threadIdx.x; k < b.s; k += 256) xs[k] = x[b.S[k]];
+  for (int k = threadIdx.x; k < b.r; k += 256) xr[k] = x[b.R[k]];
   __syncthreads();
-  block_gemv_t(b.T, b.s, b.r, b.s, adjoint != 0, [&](int k) { return xs[k]; },
-               [&](int i, zd d) {
-                 const zd v = zsub(x[b.R[i]], d);
-                 x[b.R[i]] = v;
-                 XR[b.xr_off + i] = v;
-               });
+  block_gemv_t4(b.T, b.s, b.r, b.s, adjoint != 0, xs, [&](int i, zd d) { xr[i] = zsub(xr[i], d); });
+  __syncthreads();
+  for (int i = threadIdx.x; i < b.r; i += 256) {
+    x[b.R[i]] = xr[i];
+    XR[b.xr_off + i] = xr[i];
+  }
 }
 
 // Forward, one row chunk of a box: y[i] = sum_k P[i, k] x_R[k] with P = Lp (adjoint: conj(U^T)),
@@ -189,35 +231,11 @@ __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __rest
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd xsn[kSweepCols];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int q = threadIdx.x; q < t.kn; q += 256) xsn[q] = x[b.SN[t.k0 + q]];
   __syncthreads();
   zd* out = Pbuf + b.p_off + (int64_t)t.chunk * b.r;
   const zd* Q = adjoint ? b.Lp : b.UpT;
-  constexpr int NI = kSweepCols / 64;  // loads per lane, issued together
-  for (int i = wave; i < b.r; i += 4) {
-    const zd* col = Q + (int64_t)i * b.nsn + t.k0;
-    zd v[NI];
-#pragma unroll
-    for (int j = 0; j < NI; ++j) {
-      const int k = lane + 64 * j;
-      v[j] = k < t.kn ? col[k] : zd{0.0, 0.0};
-    }
-    zd acc{0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < NI; ++j) {
-      const int k = lane + 64 * j;
-      if (k < t.kn) {
-        if (adjoint)
-          zfmac(acc, v[j], xsn[k]);
-        else
-          zfma(acc, v[j], xsn[k]);
-      }
-    }
-    acc.re = wave_sum(acc.re);
-    acc.im = wave_sum(acc.im);
-    if (lane == 0) out[i] = acc;
-  }
+  block_gemv_t4(Q + t.k0, b.nsn, b.r, t.kn, adjoint != 0, xsn, [&](int i, zd d) { out[i] = d; });
 }
 
 __global__ void __launch_bounds__(256) solve_bfin_kernel(const SolveBox* __restrict__ boxes,
@@ -291,10 +309,11 @@ __global__ void __launch_bounds__(256) permute_kernel(const zd* __restrict__ src
 
 }  // namespace
 
-void launch_solve_xr(const SolveBox* boxes, int nb, int smax, zd* x, zd* XR, int adjoint, hipStream_t st) {
+void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint,
+                     hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(solve_xr_kernel, dim3(nb), dim3(256), (size_t)smax * sizeof(zd), st, boxes, x, XR,
-                     adjoint);
+  hipLaunchKernelGGL(solve_xr_kernel, dim3(nb), dim3(256), (size_t)(smax + rmax) * sizeof(zd), st, boxes, x,
+                     XR, adjoint, smax);
   FMMLU_HIP(hipGetLastError());
 }
 
