@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmmlu.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "fmmlu.h")
 
+ENOCONV = -5
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESINGULAR", -5: "ENOCONV", -6: "ESTATE"}
 
 
@@ -220,6 +221,24 @@ class Factor:
     def solve_adjoint(self, b):
         """x = A_f^{-H} b."""
         return self._apply(lib().fmmlu_solve_adjoint, b)
+
+    def solve_refined(self, b, adjoint=False, tol=1e-12, maxit=100, raise_on_fail=True):
+        """Float64 FGMRES on A~ (adjoint: A~^H) preconditioned by the factored inverse.
+
+        Returns (x, iterations, relative residual). With raise_on_fail False a run that
+        stops at maxit returns its last iterate instead of raising FmmluError."""
+        import torch
+        b = _dev_c128(b, self.n).contiguous()
+        if b.dim() != 1:
+            raise ValueError("solve_refined takes one right-hand side")
+        x = torch.empty_like(b)
+        it = I32()
+        rr = C.c_double()
+        st = lib().fmmlu_solve_refined(self.h, P(b.data_ptr()), P(x.data_ptr()), 1 if adjoint else 0,
+                                       float(tol), int(maxit), C.byref(it), C.byref(rr), _stream())
+        if st != 0 and not (st == ENOCONV and not raise_on_fail):
+            _check(st)
+        return x, int(it.value), float(rr.value)
 
     def matvec(self, x, op=0):
         """Exact float64 product: op 0 A~, 1 A~^H, 2 dA~/dk, 3 dA~/deta."""

@@ -218,28 +218,30 @@ fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, 
   return guarded([&] {
     FactorImpl& F = f->f;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    F.ensure_workspace();
-    zd* tin = F.wmv;
-    // permute in, apply, permute out (tree order inside)
-    launch_permute(static_cast<const zd*>(x), tin, F.order_dev, F.n, 1, st);
-    launch_matvec(F.g, op, tin, F.wx, st);
-    launch_permute(F.wx, static_cast<zd*>(y), F.order_dev, F.n, 0, st);
+    F.matvec(op, static_cast<const zd*>(x), static_cast<zd*>(y), st);
     FMMLU_HIP(hipStreamSynchronize(st));
   });
 }
 
 fmmlu_status fmmlu_solve_refined(fmmlu_factor_h f, const void* b, void* x, int32_t adjoint, double tol,
                                  int32_t maxit, int32_t* iters, double* relres, void* hip_stream) {
-  (void)b;
-  (void)x;
-  (void)adjoint;
-  (void)tol;
-  (void)maxit;
-  (void)iters;
-  (void)relres;
-  (void)hip_stream;
   if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
-  return fail(FMMLU_EINVAL, "fmmlu_solve_refined is not available in this build");
+  if (!b || !x) return fail(FMMLU_EINVAL, "vector pointer is NULL");
+  if (b == x) return fail(FMMLU_EINVAL, "b and x must not alias");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FMMLU_EINVAL, "tol must be positive");
+  if (maxit < 1) return fail(FMMLU_EINVAL, "maxit must be >= 1");
+  int32_t it = 0;
+  double rr = 0.0;
+  fmmlu_status stt = guarded([&] {
+    const bool ok = f->f.refine(static_cast<const zd*>(b), static_cast<zd*>(x), adjoint != 0, tol, maxit, &it,
+                                &rr, static_cast<hipStream_t>(hip_stream));
+    if (!ok)
+      throw Error(FMMLU_ENOCONV, "refinement stopped at relative residual " + std::to_string(rr) + " after " +
+                                     std::to_string(it) + " iterations");
+  });
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return stt;
 }
 
 fmmlu_status fmmlu_factor_info(fmmlu_factor_h f, fmmlu_info* out) {

@@ -110,11 +110,19 @@ struct FactorImpl {
   zd* wmv = nullptr;
   zd* wxr = nullptr;
   zd* wp = nullptr;
+  // refinement workspace (allocated on the first refined solve)
+  DeviceArena rarena{size_t(1) << 20};
+  zd* rbuf = nullptr;
 
   void factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
               hipStream_t st);
   void solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st);
   void ensure_workspace();
+  // exact float64 product in the original point order (op as fmmlu_matvec)
+  void matvec(int op, const zd* x, zd* y, hipStream_t st);
+  // restarted right-preconditioned FGMRES; returns true when relres <= tol
+  bool refine(const zd* b, zd* x, bool adjoint, double tol, int maxit, int* iters, double* relres,
+              hipStream_t st);
 };
 
 }  // namespace fmmlu

@@ -255,6 +255,13 @@ constexpr int kSweepCols = 256;   // backward column chunk
 void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64_t* cols,
                   int64_t nc, zd* out, hipStream_t st);
 
+// ---- vector kernels of the refinement ----
+constexpr int kDotBlocks = 512;  // fixed partition of inner products (deterministic)
+void launch_dotc_partial(const zd* x, const zd* y, int64_t n, zd* part, hipStream_t st);
+void launch_axpy(zd a, const zd* x, zd* y, int64_t n, hipStream_t st);
+void launch_scal_copy(zd a, const zd* x, zd* y, int64_t n, hipStream_t st);
+void launch_sub(const zd* a, const zd* b, zd* out, int64_t n, hipStream_t st);
+
 // ---- exact matvec on the fly ----
 void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, hipStream_t st);
 
