@@ -144,6 +144,20 @@ fmmlu_status fmmlu_solve_adjoint(fmmlu_factor_h f, const void* b, void* x, int64
 fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, void* hip_stream);
 
 /*
+ * Far-field pattern operator (Section 6.3's far-field pattern F[u], defined by
+ * u(x) = e^{ikr}/r F(x^) + O(1/r^2), of the potential u = sum_j K(x, x_j) sqrt(w_j) sigma~_j;
+ * the form below follows from the large-|x| limit of K):
+ *     C[m, j] = (-i / 4 pi) sqrt(w_j) (k d_m.n_j + eta) e^{-ik d_m.x_j}.
+ * dirs: DEVICE float64 SoA 3*ndir unit directions d_m (d_x[0..ndir), d_y, d_z).
+ * op 0: out (ndir) = C in (n);  1: out (n) = C^H in (ndir);
+ * op 2: out (ndir) = (dC/dk) in (n);  3: out (ndir) = (dC/deta) in (n).
+ * in, out: device complex128, vectors of length n in the original point order; must not
+ * alias. Sums are taken in a fixed order (deterministic). Synchronises the stream.
+ */
+fmmlu_status fmmlu_farfield(fmmlu_factor_h f, const double* dirs, int64_t ndir, int32_t op,
+                            const void* in, void* out, void* hip_stream);
+
+/*
  * Iterative refinement (Section 7's use of a low-precision direct solver as a
  * preconditioner): right-preconditioned restarted GMRES in float64 on A~ (adjoint != 0:
  * on A~^H) with the exact matvec above, preconditioned by fmmlu_solve (fmmlu_solve_adjoint).

@@ -77,6 +77,7 @@ def lib():
         "fmmlu_solve_adjoint": (I32, [P, P, P, I64, P]),
         "fmmlu_matvec": (I32, [P, I32, P, P, P]),
         "fmmlu_solve_refined": (I32, [P, P, P, I32, D, I32, C.POINTER(I32), PD, P]),
+        "fmmlu_farfield": (I32, [P, P, I64, I32, P, P, P]),
         "fmmlu_factor_info": (I32, [P, C.POINTER(Info)]),
         "fmmlu_factor_boxes": (I32, [P, C.POINTER(I64), P, P, P, P, P]),
         "fmmlu_factor_destroy": (None, [P]),
@@ -239,6 +240,27 @@ class Factor:
         if st != 0 and not (st == ENOCONV and not raise_on_fail):
             _check(st)
         return x, int(it.value), float(rr.value)
+
+    def farfield(self, dirs, v, op=0):
+        """Far-field pattern operator: op 0 C v, 1 C^H v, 2 (dC/dk) v, 3 (dC/deta) v.
+
+        dirs: (3, ndir) float64 unit directions (CUDA tensor or host array)."""
+        import torch
+        d = torch.as_tensor(dirs, dtype=torch.float64).to("cuda").contiguous()
+        if d.dim() != 2 or d.shape[0] != 3:
+            raise ValueError("dirs must have shape (3, ndir)")
+        ndir = d.shape[1]
+        if op == 1:
+            if not (isinstance(v, torch.Tensor) and v.is_cuda and v.dtype == torch.complex128) or v.shape != (ndir,):
+                raise ValueError("op 1 takes a complex128 CUDA vector of length ndir")
+            out = torch.empty(self.n, dtype=torch.complex128, device=v.device)
+        else:
+            v = _dev_c128(v, self.n)
+            out = torch.empty(ndir, dtype=torch.complex128, device=v.device)
+        v = v.contiguous()
+        _check(lib().fmmlu_farfield(self.h, P(d.data_ptr()), ndir, int(op), P(v.data_ptr()), P(out.data_ptr()),
+                                    _stream()))
+        return out
 
     def matvec(self, x, op=0):
         """Exact float64 product: op 0 A~, 1 A~^H, 2 dA~/dk, 3 dA~/deta."""

@@ -223,6 +223,27 @@ fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, 
   });
 }
 
+fmmlu_status fmmlu_farfield(fmmlu_factor_h f, const double* dirs, int64_t ndir, int32_t op, const void* in,
+                            void* out, void* hip_stream) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  if (!dirs || !in || !out) return fail(FMMLU_EINVAL, "pointer is NULL");
+  if (in == out) return fail(FMMLU_EINVAL, "in and out must not alias");
+  if (ndir < 1 || ndir > (int64_t(1) << 31) - 1) return fail(FMMLU_EINVAL, "ndir must be in [1, 2^31)");
+  if (op < 0 || op > 3) return fail(FMMLU_EINVAL, "op must be 0..3");
+  return guarded([&] {
+    FactorImpl& F = f->f;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t need = ndir * farfield_chunks(F.n);
+    if (op != 1 && need > F.fpart_cap) {
+      F.fpart = F.farena.alloc_n<zd>((size_t)need);
+      F.fpart_cap = need;
+    }
+    launch_farfield(F.g, op, dirs, ndir, F.order_dev, static_cast<const zd*>(in), static_cast<zd*>(out), F.fpart,
+                    st);
+    FMMLU_HIP(hipStreamSynchronize(st));
+  });
+}
+
 fmmlu_status fmmlu_solve_refined(fmmlu_factor_h f, const void* b, void* x, int32_t adjoint, double tol,
                                  int32_t maxit, int32_t* iters, double* relres, void* hip_stream) {
   if (!f) return fail(FMMLU_ESTATE, "factor is NULL");

@@ -113,6 +113,10 @@ struct FactorImpl {
   // refinement workspace (allocated on the first refined solve)
   DeviceArena rarena{size_t(1) << 20};
   zd* rbuf = nullptr;
+  // far-field partial sums (grown on demand)
+  DeviceArena farena{size_t(1) << 20};
+  zd* fpart = nullptr;
+  int64_t fpart_cap = 0;
 
   void factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
               hipStream_t st);

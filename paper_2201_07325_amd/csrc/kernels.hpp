@@ -262,6 +262,14 @@ void launch_axpy(zd a, const zd* x, zd* y, int64_t n, hipStream_t st);
 void launch_scal_copy(zd a, const zd* x, zd* y, int64_t n, hipStream_t st);
 void launch_sub(const zd* a, const zd* b, zd* out, int64_t n, hipStream_t st);
 
+// ---- far-field pattern operator ----
+// op 0: out(ndir) = C in(n); 1: out(n) = C^H in(ndir); 2: dC/dk; 3: dC/deta (as op 0).
+// part holds ndir * farfield_chunks(n) entries (ops 0, 2, 3).
+constexpr int64_t kFarChunk = 4096;
+int farfield_chunks(int64_t n);
+void launch_farfield(const DevGeom& g, int op, const double* dirs, int64_t ndir, const int64_t* order,
+                     const zd* in, zd* out, zd* part, hipStream_t st);
+
 // ---- exact matvec on the fly ----
 void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, hipStream_t st);
 

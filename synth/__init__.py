@@ -168,9 +168,13 @@ def bumpy_sphere(
     r(u) = 1 + sum_j h_j exp(-|u - c_j|^2 / (2 s_j^2)) with centres c_j uniform on the
     sphere, heights h_j ~ U[0.05, 0.2], widths s_j ~ U[0.01, 0.2]. Points have density
     proportional to ell(u)^-2 per unit area, ell(u)^-2 = 0.2^-2 + sum_j s_j^-2
-    exp(-|u - c_j|^2 / (2 (2 s_j)^2)), so spacing follows the local bump width. Sampling
-    is by rejection from area-uniform proposals on the radial map; normals come from the
-    gradient of |x| - r(x/|x|); weights are Z/(n density).
+    exp(-|u - c_j|^2 / (2 (2 s_j)^2)), so spacing follows the local bump width.
+
+    Sampling: on the unit sphere |u - c|^2 = 2 - 2 u.c, so ell^-2 is a constant plus a sum of
+    von Mises-Fisher densities with concentrations 1/(4 s_j^2); parameters u are drawn
+    exactly from that mixture and accepted with probability J(u)/J_max, J the area element
+    of the radial map x = r(u) u. Normals come from the gradient of |x| - r(x/|x|);
+    weights are Z/(n ell^-2(u)) with Z = int ell^-2 dA estimated from the proposals.
     """
     if eta is None:
         eta = k
@@ -178,51 +182,64 @@ def bumpy_sphere(
     cen = _uniform_sphere(rng, nbumps)
     h = rng.uniform(0.05, 0.2, nbumps)
     s = rng.uniform(0.01, 0.2, nbumps)
+    kap = 1.0 / (4.0 * s * s)
+    base = 0.2 ** -2
+    # mixture masses over the unit sphere: constant part and each vMF part
+    m_base = base * 4.0 * math.pi
+    m_bump = (s ** -2) * 2.0 * math.pi * (-np.expm1(-2.0 * kap)) / kap
+    z_rho = m_base + m_bump.sum()
+    probs = np.concatenate([[m_base], m_bump]) / z_rho
 
-    def radius_and_grad(u):
-        # r(u) and its tangential gradient on the unit sphere.
-        d = u[:, :, None] - cen[:, None, :]  # (3, m, nb)
-        d2 = np.sum(d * d, axis=0)
-        e = h[None, :] * np.exp(-d2 / (2.0 * s[None, :] ** 2))
-        r = 1.0 + e.sum(axis=1)
-        g = -np.einsum("amb,mb->am", d, e / s[None, :] ** 2)
-        g = g - u * np.sum(g * u, axis=0)  # project to the tangent plane
-        return r, g
+    def draw(m):
+        comp = rng.choice(nbumps + 1, size=m, p=probs)
+        u = _uniform_sphere(rng, m)
+        sel = np.nonzero(comp > 0)[0]
+        if sel.size:
+            c = cen[:, comp[sel] - 1]
+            kk = kap[comp[sel] - 1]
+            xi = rng.random(sel.size)
+            wcos = 1.0 + np.log(xi + (1.0 - xi) * np.exp(-2.0 * kk)) / kk
+            wcos = np.clip(wcos, -1.0, 1.0)
+            # unit tangent direction at c, uniform in angle
+            t = _uniform_sphere(rng, sel.size)
+            t = t - c * np.sum(t * c, axis=0)
+            t = t / np.linalg.norm(t, axis=0)
+            u[:, sel] = wcos * c + np.sqrt(np.maximum(0.0, 1.0 - wcos * wcos)) * t
+        return u
 
-    def dens(u):
-        d2 = np.sum((u[:, :, None] - cen[:, None, :]) ** 2, axis=0)
-        return 0.2 ** -2 + np.sum(s[None, :] ** -2 * np.exp(-d2 / (2.0 * (2.0 * s[None, :]) ** 2)), axis=1)
+    def surface(u):
+        dots = cen.T @ u  # (nb, m)
+        e = h[:, None] * np.exp((dots - 1.0) / (s * s)[:, None])
+        r = 1.0 + e.sum(axis=0)
+        g = cen @ (e / (s * s)[:, None])  # ambient gradient of r(u/|u|) at |u| = 1
+        g = g - u * np.sum(g * u, axis=0)
+        jac = r * np.sqrt(r * r + np.sum(g * g, axis=0))
+        rho = base + np.sum((s ** -2)[:, None] * np.exp(kap[:, None] * (dots - 1.0)), axis=0)
+        return jac, r, g, rho
 
-    def area_jac(u):
-        r, g = radius_and_grad(u)
-        # area element of x = r(u) u over the unit sphere: r * sqrt(r^2 + |grad r|^2)
-        return r * np.sqrt(r * r + np.sum(g * g, axis=0)), r, g
-
-    # Bound for rejection: sampled estimate with margin.
-    probe = _uniform_sphere(rng, 200_000)
-    jp, _, _ = area_jac(probe)
-    fp = jp * dens(probe)
-    fmax = 1.5 * float(fp.max())
-    z_est = 4.0 * math.pi * float(fp.mean())  # Monte-Carlo estimate of the integral of density dA
-    pts, nrm, dv = [], [], []
+    pts, nrm, dv, jsum, jcount = [], [], [], 0.0, 0
+    probe = draw(100_000)
+    jmax = 1.25 * float(surface(probe)[0].max())
     have = 0
     while have < n:
-        m = min(400_000, 8 * (n - have) + 4096)
-        u = _uniform_sphere(rng, m)
-        ja, r, g = area_jac(u)
-        dd = dens(u)
-        keep = rng.random(m) < (ja * dd) / fmax
-        u, r, g, dd = u[:, keep], r[keep], g[:, keep], dd[keep]
+        m = min(200_000, int(1.6 * (n - have)) + 4096)
+        u = draw(m)
+        ja, r, g, rho = surface(u)
+        jsum += float(ja.sum())
+        jcount += m
+        keep = rng.random(m) < ja / jmax
+        u, r, g, rho = u[:, keep], r[keep], g[:, keep], rho[keep]
         x = r * u
         nv = u - g / r  # gradient of |x| - r(x/|x|) at |x| = r
         nv = nv / np.linalg.norm(nv, axis=0)
         pts.append(x)
         nrm.append(nv)
-        dv.append(dd)
+        dv.append(rho)
         have += x.shape[1]
     x = np.concatenate(pts, axis=1)[:, :n]
     nv = np.concatenate(nrm, axis=1)[:, :n]
     dd = np.concatenate(dv)[:n]
+    z_est = z_rho * jsum / jcount  # int ell^-2 J du = Z_rho E_mixture[J]
     w = z_est / (n * dd)
     return Surface(np.ascontiguousarray(x), np.ascontiguousarray(nv), w, k, eta, eps,
                    name=f"bumpy_sphere_n{n}_b{nbumps}", meta={"seed": seed, "Z": z_est})
