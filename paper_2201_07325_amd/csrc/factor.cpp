@@ -826,8 +826,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           SumTask sm{part, G, mm, mm, nsplit, 0, su};
           su += (mm + 255) / 256;
           st_.push_back(sm);
-          zd* W = sg.dev.alloc_n<zd>((size_t)mm / 4 + bp.m + 1);
-          pt.push_back(PcholTask{G, bp.R, bp.perm, bp.rank, bp.T, W, bp.m, 0});
+          zd* Rp = sg.dev.alloc_n<zd>((size_t)mm);
+          pt.push_back(PcholTask{G, bp.R, Rp, bp.perm, bp.rank, bp.T, bp.m, 0});
           mmax = std::max(mmax, bp.m);
           prof.flops[KC_QR] += 8.0 * (double)bp.rows * bp.m * bp.m;
         }

@@ -154,16 +154,16 @@ struct SumTask {
 void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
 
 // ---- greedy CPQR through the Gram matrix: pivoted Cholesky of G = M^H M (m x m) ----
-// Left-looking: row k of R from G[perm[k], perm[.]] and the previous rows; the diagonal of
-// the Schur complement (the squared norms of the remaining columns after projection) is
-// updated exactly. Outputs as CpqrTask: perm, rank, T = R11^{-1} R12 (ld m).
+// Left-looking: row k of R from column p_k of G and the previous rows; the diagonal of the
+// Schur complement (the squared norms of the remaining columns after projection) is updated
+// exactly. Outputs as CpqrTask: perm, rank, T = R11^{-1} R12 (ld m).
 struct PcholTask {
-  const zd* G;     // m x m, ld m (not modified)
-  zd* R;           // m x m scratch, ld m
+  const zd* G;     // m x m, ld m, Hermitian (not modified)
+  zd* Rt;          // m x m scratch: rows of R by original column, Rt[l * m + c]
+  zd* Rp;          // m x m scratch: R in pivoted column order, ld m
   int32_t* perm;
   int32_t* rank;
   zd* T;
-  zd* W;           // scratch, m * m / 4 + m entries
   int32_t m, pad;
 };
 void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st);

@@ -476,142 +476,208 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restric
 }
 
 // Left-looking pivoted Cholesky of the Gram matrix (greedy CPQR of M in exact arithmetic).
-// 1024 threads: per step the pivot row of G is staged in LDS, then sixteen wavefronts form
-// the inner products with the previous rows of R, two columns in flight per wavefront.
+// Row k of R is R[k, c] = (G[p_k, c] - sum_{l<k} conj(R[l, p_k]) R[l, c]) / R[k, k] for every
+// column c not yet chosen, p_k maximising the Schur-complement diagonal dg (the squared norm
+// of column c of M after projection on the chosen columns; ties to the lowest column). R is
+// kept row-major by original column (Rt[l m + c]), so the sum is one coalesced pass over the
+// previous rows (split into row slices when m is small), and G[p_k, c] = conj(G[c, p_k]) is a
+// contiguous read. Positions follow column-pivoted QR's exchange rule (step k swaps positions
+// k and pos(p_k)). At the end R is written in pivoted column order, column-major (rows < rank,
+// upper triangle only), for the back substitution.
 constexpr int kPcholThreads = 1024;
-__global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* __restrict__ tasks,
-                                                              double eps) {
+
+__device__ inline bool pchol_better(double v, int c, double bv, int bc) {
+  return c >= 0 && (bc < 0 || v > bv || (v == bv && c < bc));
+}
+
+__global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* __restrict__ tasks, double eps,
+                                                              int mult_in_lds) {
   const PcholTask t = tasks[blockIdx.x];
   const int m = t.m;
-  const zd* G = t.G;
-  zd* R = t.R;
-  extern __shared__ double smem[];
-  double* dg = smem;                         // m
-  zd* gk = reinterpret_cast<zd*>(smem + m);  // m (pivot row of G, permuted)
-  constexpr int NW = kPcholThreads / 64;
-  __shared__ double bestv[NW];
-  __shared__ int besti[NW];
-  __shared__ int bestp[NW];
-  __shared__ int sh_piv, sh_stop;
-  __shared__ double sh_r00;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int j = threadIdx.x; j < m; j += kPcholThreads) {
-    t.perm[j] = j;
-    dg[j] = G[j + (int64_t)j * m].re;
+  const zd* __restrict__ G = t.G;
+  zd* __restrict__ Rt = t.Rt;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ zd part[32 * 33];  // row-slice partial sums; 32 x 33 tile in the final pass
+  __shared__ double bestv[kPcholThreads / 64];
+  __shared__ int bestc[kPcholThreads / 64];
+  zd* mult = mult_in_lds ? reinterpret_cast<zd*>(smem) : t.Rp;  // R[0:k, p_k]
+  double* dg = reinterpret_cast<double*>(smem + (mult_in_lds ? sizeof(zd) * (size_t)m : 0));
+  int* pos = reinterpret_cast<int*>(dg + m);  // column -> position
+  int* pv = pos + m;                          // position -> column
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int c = tid; c < m; c += kPcholThreads) {
+    dg[c] = G[c + (int64_t)c * m].re;
+    pos[c] = c;
+    pv[c] = c;
   }
   __syncthreads();
+  const int mpad = (m + 63) & ~63;
+  const int slices = mpad >= kPcholThreads ? 1 : kPcholThreads / mpad;
+  double r00 = 0.0;
   int s = m;
   for (int k = 0; k < m; ++k) {
-    double mb = -1.0;
-    int mi = -1, mp = 0x7fffffff;
-    for (int c = k + threadIdx.x; c < m; c += kPcholThreads) {
+    double bv = -1.0;
+    int bc = -1;
+    for (int c = tid; c < m; c += kPcholThreads) {
+      if (pos[c] < k) continue;
       const double v = dg[c];
-      const int pc = t.perm[c];
-      if (mi < 0 || v > mb || (v == mb && pc < mp)) {
-        mb = v;
-        mi = c;
-        mp = pc;
+      if (pchol_better(v, c, bv, bc)) {
+        bv = v;
+        bc = c;
       }
     }
     for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(mb, o, 64);
-      const int oi = __shfl_xor(mi, o, 64);
-      const int op = __shfl_xor(mp, o, 64);
-      if (oi >= 0 && (mi < 0 || ov > mb || (ov == mb && op < mp))) {
-        mb = ov;
-        mi = oi;
-        mp = op;
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oc = __shfl_xor(bc, o, 64);
+      if (pchol_better(ov, oc, bv, bc)) {
+        bv = ov;
+        bc = oc;
       }
     }
     if (lane == 0) {
-      bestv[wave] = mb;
-      besti[wave] = mi;
-      bestp[wave] = mp;
+      bestv[wave] = bv;
+      bestc[wave] = bc;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double bv = -1.0;
-      int bi = -1, bp = 0x7fffffff;
-      for (int w = 0; w < NW; ++w) {
-        if (besti[w] < 0) continue;
-        if (bi < 0 || bestv[w] > bv || (bestv[w] == bv && bestp[w] < bp)) {
-          bv = bestv[w];
-          bi = besti[w];
-          bp = bestp[w];
-        }
+    bv = -1.0;
+    bc = -1;
+    for (int w = 0; w < kPcholThreads / 64; ++w)
+      if (pchol_better(bestv[w], bestc[w], bv, bc)) {
+        bv = bestv[w];
+        bc = bestc[w];
       }
-      const double nk = sqrt(fmax(bv, 0.0));
-      int stop = 0;
-      if (k == 0) {
-        sh_r00 = nk;
-        if (nk == 0.0) stop = 1;
-      } else if (nk <= eps * sh_r00) {
-        stop = 1;
-      }
-      sh_stop = stop;
-      sh_piv = bi;
-    }
-    __syncthreads();
-    if (sh_stop) {
+    const int p = bc;
+    const double rkk = sqrt(fmax(bv, 0.0));
+    if (k == 0) r00 = rkk;
+    if (p < 0 || (k == 0 ? rkk == 0.0 : rkk <= eps * r00)) {
       s = k;
       break;
     }
-    const int p = sh_piv;
-    if (p != k) {
-      for (int l = threadIdx.x; l < k; l += kPcholThreads) {
-        zd a = R[l + (int64_t)k * m];
-        R[l + (int64_t)k * m] = R[l + (int64_t)p * m];
-        R[l + (int64_t)p * m] = a;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        int q = t.perm[k];
-        t.perm[k] = t.perm[p];
-        t.perm[p] = q;
-        double d = dg[k];
-        dg[k] = dg[p];
-        dg[p] = d;
-      }
+    if (tid == 0) {
+      const int q = pos[p], ck = pv[k];
+      pv[k] = p;
+      pv[q] = ck;
+      pos[p] = k;
+      pos[ck] = q;
     }
+    for (int l = tid; l < k; l += kPcholThreads) mult[l] = Rt[(int64_t)l * m + p];
     __syncthreads();
-    const int pk = t.perm[k];
-    for (int c = k + 1 + threadIdx.x; c < m; c += kPcholThreads) gk[c] = G[pk + (int64_t)t.perm[c] * m];
-    __syncthreads();
-    const double rkk = sqrt(fmax(dg[k], 0.0));
-    const double inv = rkk > 0.0 ? 1.0 / rkk : 0.0;
-    const zd* rk = R + (int64_t)k * m;  // column k of R, rows l < k
-    for (int c0 = k + 1 + wave; c0 < m; c0 += 2 * NW) {
-      const int c1 = c0 + NW;
-      const bool two = c1 < m;
-      const zd* r0 = R + (int64_t)c0 * m;
-      const zd* r1 = R + (int64_t)(two ? c1 : c0) * m;
-      zd d0{0.0, 0.0}, d1{0.0, 0.0};
-      for (int l = lane; l < k; l += 64) {
-        const zd a = rk[l];
-        zfmac(d0, a, r0[l]);
-        zfmac(d1, a, r1[l]);
-      }
-      d0.re = wave_sum(d0.re);
-      d0.im = wave_sum(d0.im);
-      d1.re = wave_sum(d1.re);
-      d1.im = wave_sum(d1.im);
-      if (lane == 0) {
-        const zd v0 = zscale(zsub(gk[c0], d0), inv);
-        R[k + (int64_t)c0 * m] = v0;
-        dg[c0] -= zabs2(v0);
-        if (two) {
-          const zd v1 = zscale(zsub(gk[c1], d1), inv);
-          R[k + (int64_t)c1 * m] = v1;
-          dg[c1] -= zabs2(v1);
+    const double inv = 1.0 / rkk;
+    if (slices == 1) {
+      for (int c = tid; c < m; c += kPcholThreads) {
+        if (pos[c] <= k) continue;
+        zd a0{0.0, 0.0}, a1{0.0, 0.0};
+        int l = 0;
+        for (; l + 1 < k; l += 2) {
+          zfmac(a0, mult[l], Rt[(int64_t)l * m + c]);
+          zfmac(a1, mult[l + 1], Rt[(int64_t)(l + 1) * m + c]);
         }
+        if (l < k) zfmac(a0, mult[l], Rt[(int64_t)l * m + c]);
+        const zd v = zscale(zsub(zconj(G[c + (int64_t)p * m]), zadd(a0, a1)), inv);
+        Rt[(int64_t)k * m + c] = v;
+        dg[c] -= zabs2(v);
+      }
+    } else {
+      const int q = tid / mpad, c = tid - q * mpad;
+      zd acc{0.0, 0.0};
+      if (q < slices && c < m && pos[c] > k) {
+        const int L = (k + slices - 1) / slices;
+        const int l0 = q * L, l1 = min(k, l0 + L);
+        for (int l = l0; l < l1; ++l) zfmac(acc, mult[l], Rt[(int64_t)l * m + c]);
+      }
+      if (q < slices) part[tid] = acc;
+      __syncthreads();
+      if (tid < m && pos[tid] > k) {
+        zd sum = part[tid];
+        for (int qq = 1; qq < slices; ++qq) sum = zadd(sum, part[qq * mpad + tid]);
+        const zd v = zscale(zsub(zconj(G[tid + (int64_t)p * m]), sum), inv);
+        Rt[(int64_t)k * m + tid] = v;
+        dg[tid] -= zabs2(v);
       }
     }
-    if (threadIdx.x == 0) R[k + (int64_t)k * m] = zd{rkk, 0.0};
+    if (tid == 0) Rt[(int64_t)k * m + p] = zd{rkk, 0.0};
     __syncthreads();
   }
-  if (threadIdx.x == 0) *t.rank = s;
+  if (tid == 0) *t.rank = s;
+  for (int j = tid; j < m; j += kPcholThreads) t.perm[j] = pv[j];
+  // R in pivoted order through a 32 x 32 LDS tile: reads along rows of Rt, writes down columns
+  zd(*tile)[33] = reinterpret_cast<zd(*)[33]>(part);
+  const int ta = tid & 31, tb = tid >> 5;
+  for (int i0 = 0; i0 < s; i0 += 32) {
+    for (int j0 = i0 & ~31; j0 < m; j0 += 32) {
+      __syncthreads();
+      {
+        const int i = i0 + tb, j = j0 + ta;
+        zd v{0.0, 0.0};
+        if (i < s && j < m && j >= i) v = Rt[(int64_t)i * m + pv[j]];
+        tile[tb][ta] = v;
+      }
+      __syncthreads();
+      {
+        const int i = i0 + ta, j = j0 + tb;
+        if (i < s && j < m) t.Rp[i + (int64_t)j * m] = tile[ta][tb];
+      }
+    }
+  }
+}
+
+// T = R11^{-1} R12 (s x (m - s), ld m) from R in pivoted order. Each workgroup holds NC
+// right-hand-side columns in LDS; blocks of 16 rows are solved there (diagonal block staged
+// in LDS), then the rows above are updated in one pass over the block's 16 columns of R.
+template <int NC>
+__global__ void __launch_bounds__(256) pchol_t_kernel(const PcholTask* __restrict__ tasks) {
+  const PcholTask t = tasks[blockIdx.x];
+  const int m = t.m, s = *t.rank;
+  const int c0 = blockIdx.y * NC;
+  if (s == 0 || c0 >= m - s) return;
+  const int nc = min(NC, m - s - c0);
+  extern __shared__ __align__(16) unsigned char smem[];
+  zd* W = reinterpret_cast<zd*>(smem);  // W[i * NC + j], i < s
+  __shared__ zd Rb[16][17];
+  __shared__ double dinv[16];
+  const zd* __restrict__ Rp = t.Rp;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < s * NC; e += 256) {
+    const int i = e % s, j = e / s;
+    W[i * NC + j] = j < nc ? Rp[i + (int64_t)(s + c0 + j) * m] : zd{0.0, 0.0};
+  }
+  for (int i1 = s; i1 > 0; i1 -= 16) {
+    const int i0 = max(0, i1 - 16), b = i1 - i0;
+    __syncthreads();
+    {
+      const int r = tid & 15, c = tid >> 4;
+      if (r < b && c < b && r <= c) Rb[r][c] = Rp[(i0 + r) + (int64_t)(i0 + c) * m];
+      if (tid < b) dinv[tid] = 1.0 / Rp[(i0 + tid) + (int64_t)(i0 + tid) * m].re;
+    }
+    __syncthreads();
+    for (int i = b - 1; i >= 0; --i) {
+      if (tid < NC) W[(i0 + i) * NC + tid] = zscale(W[(i0 + i) * NC + tid], dinv[i]);
+      __syncthreads();
+      if (tid < i * NC) {
+        const int r = tid / NC, j = tid - r * NC;
+        W[(i0 + r) * NC + j] = zsub(W[(i0 + r) * NC + j], zmul(Rb[r][i], W[(i0 + i) * NC + j]));
+      }
+      __syncthreads();
+    }
+    for (int r = tid; r < i0; r += 256) {
+      zd a[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = q < b ? Rp[r + (int64_t)(i0 + q) * m] : zd{0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < NC; ++j) {
+        zd acc = W[r * NC + j];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (q < b) acc = zsub(acc, zmul(a[q], W[(i0 + q) * NC + j]));
+        W[r * NC + j] = acc;
+      }
+    }
+  }
   __syncthreads();
-  back_substitute_n<kPcholThreads>(R, m, s, m, t.W, t.T, true);
+  for (int e = tid; e < s * nc; e += 256) {
+    const int i = e % s, j = e / s;
+    t.T[i + (int64_t)(c0 + j) * m] = W[i * NC + j];
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -926,9 +992,26 @@ void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStrea
 
 void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st) {
   if (ntasks <= 0) return;
-  const size_t lds = (size_t)mmax * (sizeof(double) + sizeof(zd));
-  if (lds > 65536) throw Error(FMMLU_EINVAL, "ID block wider than 2730");
-  hipLaunchKernelGGL(pchol_kernel, dim3(ntasks), dim3(kPcholThreads), lds, st, tasks, eps);
+  // dynamic LDS: [mult (16 B)] + dg (8 B) + pos, pv (4 B each) per column; 64 KB in all
+  // with the static part (about 17 KB)
+  constexpr size_t kBudget = 65536 - 17664;
+  const size_t with_mult = (size_t)mmax * 32, without = (size_t)mmax * 16;
+  if (without > kBudget) throw Error(FMMLU_EINVAL, "ID block wider than " + std::to_string(kBudget / 16));
+  const int in_lds = with_mult <= kBudget ? 1 : 0;
+  hipLaunchKernelGGL(pchol_kernel, dim3(ntasks), dim3(kPcholThreads), in_lds ? with_mult : without, st, tasks, eps,
+                     in_lds);
+  FMMLU_HIP(hipGetLastError());
+  // back substitution: NC right-hand-side columns per workgroup, s x NC in LDS
+  const dim3 grid_of_nc[4] = {dim3(ntasks, (mmax + 7) / 8), dim3(ntasks, (mmax + 3) / 4),
+                              dim3(ntasks, (mmax + 1) / 2), dim3(ntasks, mmax)};
+  if (mmax <= 480)
+    hipLaunchKernelGGL(pchol_t_kernel<8>, grid_of_nc[0], dim3(256), (size_t)mmax * 8 * sizeof(zd), st, tasks);
+  else if (mmax <= 960)
+    hipLaunchKernelGGL(pchol_t_kernel<4>, grid_of_nc[1], dim3(256), (size_t)mmax * 4 * sizeof(zd), st, tasks);
+  else if (mmax <= 1920)
+    hipLaunchKernelGGL(pchol_t_kernel<2>, grid_of_nc[2], dim3(256), (size_t)mmax * 2 * sizeof(zd), st, tasks);
+  else
+    hipLaunchKernelGGL(pchol_t_kernel<1>, grid_of_nc[3], dim3(256), (size_t)mmax * sizeof(zd), st, tasks);
   FMMLU_HIP(hipGetLastError());
 }
 
