@@ -322,13 +322,55 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
   const int nt = (int)tasks.size();
   std::vector<zd*> W(nt);
   std::vector<int32_t*> work(nt);
+  // panel groups: single-workgroup matrices in one launch; taller ones cooperatively, in
+  // groups whose grid (count x widest) fits the device
+  int nmulti = 0;
+  for (auto& t : tasks) nmulti += gj_wpt(t.n) > 1 ? 1 : 0;
+  int32_t* counters = nmulti ? sg.dev.alloc_n<int32_t>(nmulti) : nullptr;
+  if (nmulti) FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * nmulti, sg.st));
+  int ci = 0;
   for (int i = 0; i < nt; ++i) {
-    tasks[i].piv = sg.dev.alloc_n<int32_t>(tasks[i].n);
-    tasks[i].info = info_dev;
-    W[i] = sg.dev.alloc_n<zd>((size_t)kGjBlock * tasks[i].n);
-    work[i] = sg.dev.alloc_n<int32_t>(tasks[i].n);
+    GjTask& t = tasks[i];
+    t.piv = sg.dev.alloc_n<int32_t>(t.n);
+    t.info = info_dev;
+    t.wpt = gj_wpt(t.n);
+    t.slots = nullptr;
+    t.counter = nullptr;
+    if (t.wpt > 1) {
+      t.slots = sg.dev.alloc_n<zd>((size_t)(2 * gj_slot_len(t.wpt)));
+      t.counter = counters + ci++;
+    }
+    W[i] = sg.dev.alloc_n<zd>((size_t)kGjBlock * t.n);
+    work[i] = sg.dev.alloc_n<int32_t>(t.n);
   }
   GjTask* dt = sg.up(tasks);
+  struct PanelGroup {
+    GjTask* dt;
+    int count, wmax;
+  };
+  std::vector<PanelGroup> pgroups;
+  {
+    std::vector<GjTask> single, multi;
+    for (auto& t : tasks) (t.wpt > 1 ? multi : single).push_back(t);
+    if (!single.empty()) pgroups.push_back({sg.up(single), (int)single.size(), 1});
+    if (!multi.empty()) {
+      std::stable_sort(multi.begin(), multi.end(), [](const GjTask& a, const GjTask& b) { return a.wpt < b.wpt; });
+      const int cap = gj_panel_capacity();
+      size_t b = 0;
+      while (b < multi.size()) {
+        size_t e = b;
+        int wmax = 0;
+        while (e < multi.size() && (int64_t)(e - b + 1) * std::max(wmax, multi[e].wpt) <= cap) {
+          wmax = std::max(wmax, multi[e].wpt);
+          ++e;
+        }
+        if (e == b) throw Error(FMMLU_EINVAL, "pivot block too large for one cooperative panel launch");
+        std::vector<GjTask> grp(multi.begin() + (int64_t)b, multi.begin() + (int64_t)e);
+        pgroups.push_back({sg.up(grp), (int)grp.size(), wmax});
+        b = e;
+      }
+    }
+  }
   zd** dW = sg.up(W);
   int32_t** dwork = sg.up(work);
   zd** dout = sg.up(outs);
@@ -362,7 +404,7 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
   ProfScope ps(*sg.prof, cls);
   int step = 0;
   for (int j0 = 0; j0 < nmax; j0 += kGjBlock, ++step) {
-    launch_gj_panel(dt, nt, j0, sg.st);
+    for (auto& pg : pgroups) launch_gj_panel(pg.dt, pg.count, j0, pg.wmax, sg.st);
     launch_gj_swaps(dt, nt, j0, nmax, sg.st);
     launch_gj_copyrow(dt, nt, j0, nmax, dW, sg.st);
     if (sidx[step][1] > 0)
@@ -1250,6 +1292,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     {
       int32_t hinfo = 0;
       FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out at level " + std::to_string(lev));
       if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block X_RR at level " + std::to_string(lev));
     }
     if (opts.verbose)
@@ -1380,6 +1423,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     prev_pool = nullptr;
     int32_t hinfo = 0;
     FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out (top block)");
     if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular top block");
   }
   {

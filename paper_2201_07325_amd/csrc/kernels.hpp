@@ -173,9 +173,23 @@ struct GjTask {
   zd* A;      // n x n, ld = lda
   int32_t* piv;
   int32_t n, lda;
-  int32_t* info;  // set to 1 + column on a zero pivot
+  int32_t* info;  // set to 1 + column on a zero pivot; -1 if a panel barrier timed out
+  // panel: one row per thread, kGjPanelRows rows per workgroup, wpt workgroups per matrix.
+  // With wpt > 1 the workgroups exchange pivot candidates through slots (2 x gj_slot_len)
+  // and meet at a barrier counter that must be zero before the first panel.
+  zd* slots;
+  int32_t* counter;
+  int32_t wpt, pad;
 };
-void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, hipStream_t st);
+constexpr int kGjBlock = 16;  // Gauss-Jordan panel width
+constexpr int kGjPanelRows = 256;
+__host__ __device__ inline int gj_wpt(int n) { return (n + kGjPanelRows - 1) / kGjPanelRows; }
+// entries of one slot buffer: per workgroup a candidate (|pivot|^2, row) and its row values,
+// then the values of the row at the pivot position
+__host__ __device__ inline int64_t gj_slot_len(int wpt) { return (int64_t)wpt * (kGjBlock + 1) + kGjBlock; }
+// grid ntasks x wmax; cooperative when wmax > 1 (then ntasks * wmax <= gj_panel_capacity())
+void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStream_t st);
+int gj_panel_capacity();
 void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st);
 // W (nb x n) = A[J, :] with J = [j0, j0+nb)
 void launch_gj_copyrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,
@@ -186,7 +200,6 @@ void launch_gj_fixrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* con
 // undo the column permutation: Out = A * P (gather columns)
 void launch_gj_unpermute(const GjTask* tasks, int ntasks, int nmax, zd* const* out,
                          int32_t* const* work, hipStream_t st);
-constexpr int kGjBlock = 16;  // Gauss-Jordan panel width
 
 // ---- R factor extraction: R = triu(M[0:min(rows,m), 0:m]) padded to m x m ----
 struct ExtractTask {

@@ -682,37 +682,59 @@ __global__ void __launch_bounds__(256) pchol_t_kernel(const PcholTask* __restric
 
 // ---------------------------------------------------------------------------------------
 // Gauss-Jordan inversion with partial pivoting, blocked by column panels of kGjNb.
-constexpr int kGjNb = 16;
+constexpr int kGjNb = kGjBlock;
 
-// Panel: columns J = [j0, j0+nb) of all n rows; pivot rows searched among rows >= column.
+// Panel: columns J = [j0, j0+nb) of all n rows; pivot rows searched among rows >= column
+// (largest modulus, ties to the lowest row). Each thread keeps one row of the panel in
+// registers for all nb steps. A matrix taller than one workgroup is split over wpt
+// workgroups that meet once per column: each publishes its best candidate row (and the
+// owner of the pivot position publishes that row) in a double-buffered slot, arrives at a
+// counter, and waits (bounded) until all have arrived; the pivot row then comes from the
+// winning slot. Launched cooperatively, so all workgroups are resident.
+constexpr int64_t kGjSpinLimit = int64_t(1) << 22;
+
+__device__ inline bool gj_better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
 __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict__ tasks, int j0) {
   const GjTask t = tasks[blockIdx.x];
   const int n = t.n;
   if (j0 >= n) return;
+  const int w = blockIdx.y;
+  if (w >= t.wpt) return;
   const int nb = min(kGjNb, n - j0);
   const int64_t lda = t.lda;
   zd* A = t.A;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int gi = w * kGjPanelRows + tid;
+  const bool own = gi < n;
   __shared__ double bv[4];
   __shared__ int bi[4];
-  __shared__ zd rowg[kGjNb];
-  __shared__ zd sh_inv;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ zd prow[kGjNb], rowgc[kGjNb];
+  __shared__ int sh_win, sh_p;
+  __shared__ double sh_best;
+  zd a[kGjNb];
+#pragma unroll
+  for (int q = 0; q < kGjNb; ++q) a[q] = (own && q < nb) ? A[gi + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
+  const bool multi = t.wpt > 1;
+  const int64_t slen = gj_slot_len(t.wpt);
   for (int j = 0; j < nb; ++j) {
     const int gc = j0 + j;
-    // pivot search
+    zd aj = a[0];
+#pragma unroll
+    for (int q = 1; q < kGjNb; ++q)
+      if (q == j) aj = a[q];
     double best = -1.0;
     int besti = 0x7fffffff;
-    for (int i = gc + threadIdx.x; i < n; i += 256) {
-      const double v = zabs2(A[i + (int64_t)gc * lda]);
-      if (v > best) {
-        best = v;
-        besti = i;
-      }
+    if (own && gi >= gc) {
+      best = zabs2(aj);
+      besti = gi;
     }
     for (int o = 32; o > 0; o >>= 1) {
       const double ov = __shfl_xor(best, o, 64);
       const int oi = __shfl_xor(besti, o, 64);
-      if (ov > best || (ov == best && oi < besti)) {
+      if (gj_better(ov, oi, best, besti)) {
         best = ov;
         besti = oi;
       }
@@ -722,58 +744,119 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
       bi[wave] = besti;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       double b = bv[0];
       int p = bi[0];
-      for (int w = 1; w < 4; ++w)
-        if (bv[w] > b || (bv[w] == b && bi[w] < p)) {
-          b = bv[w];
-          p = bi[w];
+      for (int q = 1; q < 4; ++q)
+        if (gj_better(bv[q], bi[q], b, p)) {
+          b = bv[q];
+          p = bi[q];
         }
-      if (p >= n) p = gc;
-      t.piv[gc] = p;
-      if (b <= 0.0 && *t.info == 0) *t.info = gc + 1;
+      sh_win = p;
+      sh_best = b;
     }
     __syncthreads();
-    const int p = t.piv[gc];
-    // swap rows gc and p inside the panel
-    if (p != gc && threadIdx.x < nb) {
-      const int c = j0 + threadIdx.x;
-      zd a = A[gc + (int64_t)c * lda];
-      A[gc + (int64_t)c * lda] = A[p + (int64_t)c * lda];
-      A[p + (int64_t)c * lda] = a;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const zd piv = A[gc + (int64_t)gc * lda];
-      sh_inv = (zabs2(piv) > 0.0) ? zdiv(zd{1.0, 0.0}, piv) : zd{0.0, 0.0};
-    }
-    __syncthreads();
-    const zd inv = sh_inv;
-    // scale pivot row (panel columns other than gc)
-    if (threadIdx.x < nb) {
-      const int c = j0 + threadIdx.x;
-      zd v = A[gc + (int64_t)c * lda];
-      if (c != gc) v = zmul(v, inv);
-      rowg[threadIdx.x] = v;
-      if (c != gc) A[gc + (int64_t)c * lda] = v;
-    }
-    __syncthreads();
-    // eliminate column gc from the other rows
-    for (int i = threadIdx.x; i < n; i += 256) {
-      if (i == gc) continue;
-      zd* ai = A + i;
-      const zd f = ai[(int64_t)gc * lda];
-      for (int q = 0; q < nb; ++q) {
-        const int c = j0 + q;
-        if (c == gc) continue;
-        ai[(int64_t)c * lda] = zsub(ai[(int64_t)c * lda], zmul(f, rowg[q]));
+    if (!multi) {
+      if (gi == sh_win) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) prow[q] = a[q];
       }
-      ai[(int64_t)gc * lda] = zd{-(f.re * inv.re - f.im * inv.im), -(f.re * inv.im + f.im * inv.re)};
+      if (gi == gc) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) rowgc[q] = a[q];
+      }
+      if (tid == 0) sh_p = sh_win;
+      __syncthreads();
+    } else {
+      zd* slot = t.slots + (int64_t)(gc & 1) * slen;
+      if (tid == 0) slot[(int64_t)w * (kGjNb + 1)] = zd{sh_best, (double)sh_win};
+      if (gi == sh_win) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) slot[(int64_t)w * (kGjNb + 1) + 1 + q] = a[q];
+      }
+      if (gi == gc) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) slot[(int64_t)t.wpt * (kGjNb + 1) + q] = a[q];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int target = t.wpt * (gc + 1);
+        int64_t spins = 0;
+        while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          if (++spins > kGjSpinLimit) {
+            __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        double b = -1.0;
+        int p = 0x7fffffff, pw = 0;
+        for (int u = 0; u < t.wpt; ++u) {
+          const zd c = slot[(int64_t)u * (kGjNb + 1)];
+          const int ci = (int)c.im;
+          if (gj_better(c.re, ci, b, p)) {
+            b = c.re;
+            p = ci;
+            pw = u;
+          }
+        }
+        sh_p = p;
+        sh_best = b;
+        sh_win = pw;
+      }
+      __syncthreads();
+      if (tid < kGjNb) {
+        prow[tid] = slot[(int64_t)sh_win * (kGjNb + 1) + 1 + tid];
+        rowgc[tid] = slot[(int64_t)t.wpt * (kGjNb + 1) + tid];
+      }
+      __syncthreads();
+    }
+    int p = sh_p;
+    if (p >= n) p = gc;
+    if (w == 0 && tid == 0) {
+      t.piv[gc] = p;
+      if (!(sh_best > 0.0) && *t.info == 0) *t.info = gc + 1;
+    }
+    // the pivot row moves to position gc, the row from gc to position p
+    if (p != gc) {
+      if (gi == gc) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) a[q] = prow[q];
+      } else if (gi == p) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[q];
+      }
+    }
+    zd pv = prow[0];
+#pragma unroll
+    for (int q = 1; q < kGjNb; ++q)
+      if (q == j) pv = prow[q];
+    const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
+    if (gi == gc) {
+#pragma unroll
+      for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[q], inv);
+    } else if (own) {
+      zd f = a[0];
+#pragma unroll
+      for (int q = 1; q < kGjNb; ++q)
+        if (q == j) f = a[q];
+#pragma unroll
+      for (int q = 0; q < kGjNb; ++q) {
+        if (q == j)
+          a[q] = zd{-(f.re * inv.re - f.im * inv.im), -(f.re * inv.im + f.im * inv.re)};
+        else
+          a[q] = zsub(a[q], zmul(f, zmul(prow[q], inv)));
+      }
     }
     __syncthreads();
-    if (threadIdx.x == 0) A[gc + (int64_t)gc * lda] = inv;
-    __syncthreads();
+  }
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < kGjNb; ++q)
+      if (q < nb) A[gi + (int64_t)(j0 + q) * lda] = a[q];
   }
 }
 
@@ -1034,10 +1117,25 @@ void launch_cpqr(const CpqrTask* tasks, int ntasks, int mmax, double eps, hipStr
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, hipStream_t st) {
+void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStream_t st) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(gj_panel_kernel, dim3(ntasks), dim3(256), 0, st, tasks, j0);
+  if (wmax <= 1) {
+    hipLaunchKernelGGL(gj_panel_kernel, dim3(ntasks, 1), dim3(kGjPanelRows), 0, st, tasks, j0);
+  } else {
+    void* args[] = {(void*)&tasks, (void*)&j0};
+    FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_panel_kernel), dim3(ntasks, wmax),
+                                         dim3(kGjPanelRows), args, 0, st));
+  }
   FMMLU_HIP(hipGetLastError());
+}
+
+int gj_panel_capacity() {
+  int dev = 0, per_cu = 0, cus = 0;
+  FMMLU_HIP(hipGetDevice(&dev));
+  FMMLU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_panel_kernel),
+                                                         kGjPanelRows, 0));
+  return per_cu * cus;
 }
 
 void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st) {
