@@ -207,6 +207,15 @@ fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const doub
                                 double k, double eta, const int64_t* rows, int64_t nr,
                                 const int64_t* cols, int64_t nc, void* out, void* hip_stream);
 
+/*
+ * Batched dense inverse with partial pivoting (blocked Gauss-Jordan), the routine that
+ * inverts the pivot blocks X_RR (Section 4.1) and the top block (Section 4.2). a: device,
+ * count consecutive n x n complex128 column-major matrices (not modified); out: device,
+ * their inverses in the same layout. For testing and for callers that need dense inverses.
+ * Errors: EINVAL, ESINGULAR (an exactly zero pivot), ENOMEM, EHIP. Synchronises the stream.
+ */
+fmmlu_status fmmlu_dense_inverse(const void* a, int64_t n, int64_t count, void* out, void* hip_stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* fmmlu_last_error(void);
 

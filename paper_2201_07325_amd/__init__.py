@@ -78,6 +78,7 @@ def lib():
         "fmmlu_matvec": (I32, [P, I32, P, P, P]),
         "fmmlu_solve_refined": (I32, [P, P, P, I32, D, I32, C.POINTER(I32), PD, P]),
         "fmmlu_farfield": (I32, [P, P, I64, I32, P, P, P]),
+        "fmmlu_dense_inverse": (I32, [P, I64, I64, P, P]),
         "fmmlu_factor_info": (I32, [P, C.POINTER(Info)]),
         "fmmlu_factor_boxes": (I32, [P, C.POINTER(I64), P, P, P, P, P]),
         "fmmlu_factor_destroy": (None, [P]),
@@ -325,3 +326,23 @@ def kernel_block(points, normals, weights, k, eta, rows, cols):
                                     float(eta), P(r.data_ptr()), r.numel(), P(c.data_ptr()), c.numel(),
                                     P(out.data_ptr()), _stream()))
     return out.t()
+
+
+def dense_inverse(a):
+    """Inverses of a batch of complex128 CUDA matrices a (count, n, n) with the library's
+    blocked Gauss-Jordan (the routine used for pivot and top blocks)."""
+    import torch
+    if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.complex128):
+        raise TypeError("expected a complex128 CUDA tensor")
+    squeeze = a.dim() == 2
+    a3 = a.reshape(-1, a.shape[-2], a.shape[-1])
+    cnt, n, n2 = a3.shape
+    if n != n2:
+        raise ValueError("matrices must be square")
+    # column-major storage: the transpose of each row-major matrix
+    ac = a3.transpose(1, 2).contiguous()
+    out = torch.empty_like(ac)
+    _check(lib().fmmlu_dense_inverse(P(ac.data_ptr()), n, cnt, P(out.data_ptr()), _stream()))
+    res = out.transpose(1, 2)
+    return res[0] if squeeze else res
+

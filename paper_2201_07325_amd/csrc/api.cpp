@@ -305,6 +305,16 @@ fmmlu_status fmmlu_factor_profile(fmmlu_factor_h f, double* ms, int64_t* launche
 
 void fmmlu_factor_destroy(fmmlu_factor_h f) { delete f; }
 
+fmmlu_status fmmlu_dense_inverse(const void* a, int64_t n, int64_t count, void* out, void* hip_stream) {
+  if (!a || !out) return fail(FMMLU_EINVAL, "NULL pointer");
+  if (a == out) return fail(FMMLU_EINVAL, "a and out must not alias");
+  if (n < 1 || n > 65535 || count < 1) return fail(FMMLU_EINVAL, "bad sizes");
+  return guarded([&] {
+    dense_inverse_batch(static_cast<const zd*>(a), n, count, static_cast<zd*>(out),
+                        static_cast<hipStream_t>(hip_stream));
+  });
+}
+
 fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const double* w, int64_t n,
                                 double k, double eta, const int64_t* rows, int64_t nr,
                                 const int64_t* cols, int64_t nc, void* out, void* hip_stream) {

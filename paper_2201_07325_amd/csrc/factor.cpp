@@ -314,8 +314,8 @@ struct GemmBatch {
 
 // Batched Gauss-Jordan inversion of matrices A_b (n_b x n_b, lda_b) into out_b (ld n_b).
 // All descriptors are uploaded first; the launches are timed as class `cls`.
-void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd*>& outs,
-                     int32_t* info_dev, int cls) {
+void batched_inverse_pipeline(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd*>& outs,
+                              int32_t* info_dev, int cls) {
   if (tasks.empty()) return;
   int nmax = 0;
   for (auto& t : tasks) nmax = std::max(nmax, t.n);
@@ -384,12 +384,20 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
       if (j0 >= t.n) continue;
       const int nb = std::min(kGjBlock, t.n - j0);
       // A[:, c] += A[:, J] W[:, c] for c outside J (two column ranges)
-      if (j0 > 0)
-        gb.add1(t.A, t.lda, t.n, j0, t.A + (int64_t)j0 * t.lda, t.lda, W[i], nb, nb, 1.0, 1.0);
+      // A[:, c] += (A[:, J] - E_J) W[:, c] for c outside J (E_J: identity on rows J), which
+      // also subtracts the pivot rows W from rows J
+      const GemmSeg seg{t.A + (int64_t)j0 * t.lda, nullptr, t.lda, nb, nb, j0 + 1};
+      if (j0 > 0) {
+        GemmSeg g = seg;
+        g.B = W[i];
+        gb.add(t.A, t.lda, t.n, j0, nullptr, nullptr, {g}, 1.0, 0.0, 1.0);
+      }
       const int c1 = j0 + nb;
-      if (c1 < t.n)
-        gb.add1(t.A + (int64_t)c1 * t.lda, t.lda, t.n, t.n - c1, t.A + (int64_t)j0 * t.lda, t.lda,
-                W[i] + (int64_t)c1 * nb, nb, nb, 1.0, 1.0);
+      if (c1 < t.n) {
+        GemmSeg g = seg;
+        g.B = W[i] + (int64_t)c1 * nb;
+        gb.add(t.A + (int64_t)c1 * t.lda, t.lda, t.n, t.n - c1, nullptr, nullptr, {g}, 1.0, 0.0, 1.0);
+      }
     }
     const int64_t tb = (int64_t)all.tasks.size();
     const int64_t seg0 = (int64_t)all.segs.size();
@@ -405,14 +413,64 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
   int step = 0;
   for (int j0 = 0; j0 < nmax; j0 += kGjBlock, ++step) {
     for (auto& pg : pgroups) launch_gj_panel(pg.dt, pg.count, j0, pg.wmax, sg.st);
-    launch_gj_swaps(dt, nt, j0, nmax, sg.st);
-    launch_gj_copyrow(dt, nt, j0, nmax, dW, sg.st);
+    launch_gj_swapcopy(dt, nt, j0, nmax, dW, sg.st);
     if (sidx[step][1] > 0)
       launch_gemm(0, all.dt + sidx[step][0], (int)sidx[step][1], sidx[step][3], all.ds, sg.st);
-    launch_gj_fixrow(dt, nt, j0, nmax, dW, sg.st);
   }
   launch_gj_unpermute(dt, nt, nmax, dout, dwork, sg.st);
   for (auto& t : tasks) sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
+}
+
+// Inverses of a batch of matrices: those up to kGjCoopMax rows in cooperative launches
+// (several workgroups per matrix, one launch for the whole inversion), larger ones through
+// the multi-launch pipeline.
+void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd*>& outs, int32_t* info_dev,
+                     int cls) {
+  std::vector<GjTask> large;
+  std::vector<zd*> lo;
+  std::vector<GjCoopTask> small;
+  for (size_t i = 0; i < tasks.size(); ++i) {
+    if (tasks[i].n <= kGjCoopMax) {
+      GjCoopTask c{};
+      c.A = tasks[i].A;
+      c.out = outs[i];
+      c.n = tasks[i].n;
+      c.lda = tasks[i].lda;
+      c.nwg = std::max(1, std::min(8, c.n / 64));
+      small.push_back(c);
+    } else {
+      large.push_back(tasks[i]);
+      lo.push_back(outs[i]);
+    }
+  }
+  if (!small.empty()) {
+    int32_t* counters = sg.dev.alloc_n<int32_t>(small.size());
+    FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * small.size(), sg.st));
+    int nmax = 0;
+    for (size_t i = 0; i < small.size(); ++i) {
+      small[i].piv = sg.dev.alloc_n<int32_t>(small[i].n);
+      small[i].info = info_dev;
+      small[i].counter = counters + i;
+      nmax = std::max(nmax, small[i].n);
+    }
+    const int cap = gj_coop_capacity(nmax);
+    size_t b = 0;
+    while (b < small.size()) {
+      std::vector<GjCoopTask> grp;
+      int64_t units = 0;
+      while (b < small.size() && units + small[b].nwg <= cap) {
+        small[b].unit_begin = units;
+        units += small[b].nwg;
+        grp.push_back(small[b++]);
+      }
+      if (grp.empty()) throw Error(FMMLU_EINVAL, "pivot block too large for one cooperative launch");
+      GjCoopTask* dt = sg.up(grp);
+      ProfScope ps(*sg.prof, cls);
+      launch_gj_coop(dt, (int)grp.size(), units, nmax, sg.st);
+    }
+    for (auto& t : small) sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
+  }
+  batched_inverse_pipeline(sg, large, lo, info_dev, cls);
 }
 
 // Blocked Householder QR (no pivoting) of M_b (rows_b x m_b, ld rows_b), in place; the R
@@ -502,6 +560,36 @@ void batched_qr(Stage& sg, const std::vector<zd*>& Ms, const std::vector<int>& r
 }
 
 }  // namespace
+
+// Inverses of count consecutive n x n matrices (the routine the factorization uses for the
+// pivot blocks and the top block), for the library's dense-inverse entry point.
+void dense_inverse_batch(const zd* A, int64_t n, int64_t count, zd* out, hipStream_t st) {
+  Profiler prof;
+  Stage sg;
+  sg.st = st;
+  sg.prof = &prof;
+  DeviceArena keep(size_t(1) << 20);
+  int32_t* info_dev = keep.alloc_n<int32_t>(1);
+  FMMLU_HIP(hipMemsetAsync(info_dev, 0, sizeof(int32_t), st));
+  zd* work = keep.alloc_n<zd>((size_t)(n * n * count));
+  FMMLU_HIP(hipMemcpyAsync(work, A, sizeof(zd) * (size_t)(n * n * count), hipMemcpyDeviceToDevice, st));
+  std::vector<GjTask> tasks((size_t)count);
+  std::vector<zd*> outs((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    tasks[i] = GjTask{};
+    tasks[i].A = work + i * n * n;
+    tasks[i].n = (int32_t)n;
+    tasks[i].lda = (int32_t)n;
+    outs[i] = out + i * n * n;
+  }
+  batched_inverse(sg, tasks, outs, info_dev, KC_INV);
+  sg.sync_reset();
+  int32_t hinfo = 0;
+  FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out");
+  if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "zero pivot in column " + std::to_string(hinfo - 1));
+}
+
 
 // ------------------------------------------------------------------------------------------
 void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
@@ -847,6 +935,19 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       for (auto& bp : plan) prof.bytes[KC_IDMAT] += 16.0 * (double)bp.rows * bp.m;
       // ---- 2. greedy CPQR of M: through the Gram matrix (pivoted Cholesky of M^H M) when
       //      eps >= kGramEps, else Householder QR of M followed by CPQR of its R factor
+      // ranks and pivots of all boxes of the phase in two contiguous arrays (one read-back each)
+      int64_t perm_total = 0;
+      for (auto& bp : plan) perm_total += bp.m;
+      int32_t* rank_all = sg.dev.alloc_n<int32_t>(nb);
+      int32_t* perm_all = sg.dev.alloc_n<int32_t>((size_t)perm_total);
+      {
+        int64_t po = 0;
+        for (int i = 0; i < nb; ++i) {
+          plan[i].rank = rank_all + i;
+          plan[i].perm = perm_all + po;
+          po += plan[i].m;
+        }
+      }
       const bool gram = opts.id_route == 1 || (opts.id_route == 0 && eps >= kGramEps);
       if (gram) {
         constexpr int KCH = 512;
@@ -861,8 +962,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           zd* part = sg.dev.alloc_n<zd>((size_t)nsplit * mm);
           zd* G = sg.dev.alloc_n<zd>((size_t)mm);
           bp.R = sg.dev.alloc_n<zd>((size_t)mm);
-          bp.perm = sg.dev.alloc_n<int32_t>(bp.m);
-          bp.rank = sg.dev.alloc_n<int32_t>(1);
           bp.T = sg.dev.alloc_n<zd>((size_t)mm);
           gg.add_split(part, bp.m, bp.m, bp.m, bp.M, bp.rows, bp.M, bp.rows, bp.rows, KCH, mm);
           SumTask sm{part, G, mm, mm, nsplit, 0, su};
@@ -899,8 +998,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int mmax = 0;
         for (auto& bp : plan) {
           bp.R = sg.dev.alloc_n<zd>((size_t)bp.m * bp.m);
-          bp.perm = sg.dev.alloc_n<int32_t>(bp.m);
-          bp.rank = sg.dev.alloc_n<int32_t>(1);
           bp.T = sg.dev.alloc_n<zd>((size_t)bp.m * bp.m);
           et.push_back(ExtractTask{bp.M, bp.R, bp.rows, bp.m});
           zd* W = sg.dev.alloc_n<zd>((size_t)bp.m * bp.m / 4 + bp.m + 1);
@@ -918,13 +1015,18 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       // ---- read back ranks and pivots
       std::vector<int32_t> ranks(nb);
       std::vector<std::vector<int32_t>> perms(nb);
-      for (int i = 0; i < nb; ++i) {
-        perms[i].resize(plan[i].m);
-        FMMLU_HIP(hipMemcpyAsync(&ranks[i], plan[i].rank, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        FMMLU_HIP(hipMemcpyAsync(perms[i].data(), plan[i].perm, sizeof(int32_t) * plan[i].m,
-                                 hipMemcpyDeviceToHost, st));
+      {
+        int32_t* hr = static_cast<int32_t*>(sg.host.alloc(sizeof(int32_t) * (size_t)(nb + perm_total)));
+        FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
+        FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, st));
+        sg.sync();
+        int64_t po = nb;
+        for (int i = 0; i < nb; ++i) {
+          ranks[i] = hr[i];
+          perms[i].assign(hr + po, hr + po + plan[i].m);
+          po += plan[i].m;
+        }
       }
-      sg.sync();
       for (int i = 0; i < nb; ++i) {
         double f = 0;
         for (int kk = 0; kk < ranks[i]; ++kk) f += 2.0 * (double)(plan[i].m - kk) * (plan[i].m - kk);
@@ -1282,9 +1384,20 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         phases.push_back(ph);
       }
       // live lists of eliminated boxes to the device (persistent for the level)
-      for (int q = 0; q < ne; ++q) {
-        Owner& B = own[plan[ep[q].pi].oi];
-        B.live_dev = B.live.empty() ? nullptr : sg.up_to(level_arena, B.live);
+      {
+        std::vector<int32_t> live_cat;
+        std::vector<int64_t> live_off(ne, -1);
+        for (int q = 0; q < ne; ++q) {
+          Owner& B = own[plan[ep[q].pi].oi];
+          if (B.live.empty()) continue;
+          live_off[q] = (int64_t)live_cat.size();
+          live_cat.insert(live_cat.end(), B.live.begin(), B.live.end());
+        }
+        int32_t* live_base = live_cat.empty() ? nullptr : sg.up_to(level_arena, live_cat);
+        for (int q = 0; q < ne; ++q) {
+          Owner& B = own[plan[ep[q].pi].oi];
+          B.live_dev = live_off[q] < 0 ? nullptr : live_base + live_off[q];
+        }
       }
       for (auto& bp : plan) info.max_block = std::max(info.max_block, bp.m);
     }

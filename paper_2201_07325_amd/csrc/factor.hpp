@@ -129,4 +129,7 @@ struct FactorImpl {
               hipStream_t st);
 };
 
+// inverses of count consecutive n x n column-major matrices (device memory, A preserved)
+void dense_inverse_batch(const zd* A, int64_t n, int64_t count, zd* out, hipStream_t st);
+
 }  // namespace fmmlu

@@ -74,7 +74,8 @@ void launch_build_idmatrix(const DevGeom& g, const IdTask* tasks, int ntasks, in
 struct GemmSeg {
   const zd* A;
   const zd* B;
-  int32_t lda, ldb, K, pad;
+  int32_t lda, ldb, K;
+  int32_t ishift;  // opA N only: > 0 reads A - E with E[ishift - 1 + k, k] = 1 (shifted identity)
 };
 struct GemmTask {
   zd* C;
@@ -190,10 +191,27 @@ __host__ __device__ inline int64_t gj_slot_len(int wpt) { return (int64_t)wpt * 
 // grid ntasks x wmax; cooperative when wmax > 1 (then ntasks * wmax <= gj_panel_capacity())
 void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStream_t st);
 int gj_panel_capacity();
+// Whole inversion of matrices of n <= kGjCoopMax rows in one cooperative launch: nwg
+// workgroups per matrix starting at grid index unit_begin; out = A^{-1} (n x n, ld n);
+// counter zero before the launch.
+constexpr int kGjCoopMax = 512;
+struct GjCoopTask {
+  zd* A;
+  zd* out;
+  int32_t* piv;
+  int32_t* info;
+  int32_t* counter;
+  int32_t n, lda, nwg, pad;
+  int64_t unit_begin;
+};
+void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st);
+int gj_coop_capacity(int nmax);
 void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st);
 // W (nb x n) = A[J, :] with J = [j0, j0+nb)
 void launch_gj_copyrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,
                        hipStream_t st);
+// row exchanges of the panel on columns outside J, then W (nb x n) = A[J, :]
+void launch_gj_swapcopy(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W, hipStream_t st);
 // A[J, c] -= W[:, c] for c outside J
 void launch_gj_fixrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,
                       hipStream_t st);

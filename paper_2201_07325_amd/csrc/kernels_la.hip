@@ -98,9 +98,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ 
         const int gi = row0 + i, gk = k0 + kk;
         zd v{0.0, 0.0};
         if (gi < t.M && gk < kend) {
-          if (OPA == 0)
+          if (OPA == 0) {
             v = sg.A[gi + (int64_t)gk * sg.lda];
-          else {
+            if (sg.ishift > 0 && gi == sg.ishift - 1 + gk) v.re -= 1.0;
+          } else {
             v = sg.A[gk + (int64_t)gi * sg.lda];
             if (OPA == 2) v.im = -v.im;
           }
@@ -860,6 +861,258 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
   }
 }
 
+// Gauss-Jordan inversion of a batch of matrices of up to NT rows, several workgroups per
+// matrix, one launch for the whole inversion. Every workgroup of a matrix factors each
+// panel of kGjNb columns itself (one row per thread, in registers; identical arithmetic,
+// so identical results), then applies the panel to the columns it owns (panels assigned
+// round-robin): the panel's row exchanges, composed into at most 2 kGjNb moves, and the
+// update A[:, c] += A[:, J] W[:, c] - [rows J] W[:, c] with W = A[J, c] staged in LDS. The
+// owner of the panel's columns writes them back. The workgroups of a matrix then meet at a
+// counter (bounded wait; launched cooperatively so all are resident) before the next panel
+// reads columns another workgroup updated. Finally each workgroup gathers its share of the
+// inverse into out, undoing the column permutation.
+constexpr int kGjChunk = 16;
+constexpr int64_t kGjCoopSpin = int64_t(1) << 22;
+
+template <int NT>
+__global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restrict__ tasks, int ntasks) {
+  constexpr int NW = NT / 64;
+  const int64_t u = blockIdx.x;
+  const GjCoopTask t = tasks[find_task(tasks, ntasks, u)];
+  const int w = (int)(u - t.unit_begin);
+  const int nwg = t.nwg;
+  const int n = t.n;
+  const int64_t lda = t.lda;
+  zd* A = t.A;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const bool own = tid < n;
+  __shared__ double bv[NW];
+  __shared__ int bi[NW];
+  __shared__ zd prow[kGjNb], rowgc[kGjNb];
+  __shared__ int sh_p;
+  __shared__ double sh_best;
+  __shared__ int pivl[NT], idx[NT];
+  __shared__ int mv_dst[2 * kGjNb], mv_src[2 * kGjNb], rows[2 * kGjNb], cur[2 * kGjNb];
+  __shared__ zd Ws[kGjNb][kGjChunk + 1];
+  __shared__ zd Mv[kGjChunk][2 * kGjNb];
+  const int npan = (n + kGjNb - 1) / kGjNb;
+  for (int pn = 0; pn < npan; ++pn) {
+    const int j0 = pn * kGjNb, nb = min(kGjNb, n - j0);
+    zd a[kGjNb];
+#pragma unroll
+    for (int q = 0; q < kGjNb; ++q) a[q] = (own && q < nb) ? A[tid + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
+    for (int j = 0; j < nb; ++j) {
+      const int gc = j0 + j;
+      zd aj = a[0];
+#pragma unroll
+      for (int q = 1; q < kGjNb; ++q)
+        if (q == j) aj = a[q];
+      double best = -1.0;
+      int besti = 0x7fffffff;
+      if (own && tid >= gc) {
+        best = zabs2(aj);
+        besti = tid;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(besti, o, 64);
+        if (gj_better(ov, oi, best, besti)) {
+          best = ov;
+          besti = oi;
+        }
+      }
+      if (lane == 0) {
+        bv[wave] = best;
+        bi[wave] = besti;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double b = bv[0];
+        int p = bi[0];
+        for (int q = 1; q < NW; ++q)
+          if (gj_better(bv[q], bi[q], b, p)) {
+            b = bv[q];
+            p = bi[q];
+          }
+        if (p >= n) p = gc;
+        sh_p = p;
+        sh_best = b;
+        pivl[gc] = p;
+      }
+      __syncthreads();
+      const int p = sh_p;
+      if (tid == p) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) prow[q] = a[q];
+      }
+      if (tid == gc) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) rowgc[q] = a[q];
+      }
+      __syncthreads();
+      if (p != gc) {
+        if (tid == gc) {
+#pragma unroll
+          for (int q = 0; q < kGjNb; ++q) a[q] = prow[q];
+        } else if (tid == p) {
+#pragma unroll
+          for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[q];
+        }
+      }
+      zd pv = prow[0];
+#pragma unroll
+      for (int q = 1; q < kGjNb; ++q)
+        if (q == j) pv = prow[q];
+      const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
+      if (tid == gc) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[q], inv);
+      } else if (own) {
+        zd f = a[0];
+#pragma unroll
+        for (int q = 1; q < kGjNb; ++q)
+          if (q == j) f = a[q];
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q) {
+          if (q == j)
+            a[q] = zd{-(f.re * inv.re - f.im * inv.im), -(f.re * inv.im + f.im * inv.re)};
+          else
+            a[q] = zsub(a[q], zmul(f, zmul(prow[q], inv)));
+        }
+      }
+      if (w == 0 && tid == 0) {
+        t.piv[gc] = p;
+        if (!(sh_best > 0.0) && *t.info == 0) *t.info = gc + 1;
+      }
+      __syncthreads();
+    }
+    // compose the panel's exchanges; unused moves take row j0 onto itself and are applied
+    // first, so a real move into row j0 lands last
+    if (tid == 0) {
+      int nr = 0;
+      for (int q = 0; q < nb; ++q) {
+        const int g = j0 + q, pq = pivl[g];
+        int ig = -1, ip = -1;
+        for (int v = 0; v < nr; ++v) {
+          if (rows[v] == g) ig = v;
+          if (rows[v] == pq) ip = v;
+        }
+        if (ig < 0) {
+          rows[nr] = g;
+          cur[nr] = g;
+          ig = nr++;
+        }
+        if (ip < 0) {
+          rows[nr] = pq;
+          cur[nr] = pq;
+          ip = nr++;
+        }
+        const int x = cur[ig];
+        cur[ig] = cur[ip];
+        cur[ip] = x;
+      }
+      int nm = 0;
+      for (int v = 0; v < nr; ++v)
+        if (cur[v] != rows[v]) {
+          mv_dst[nm] = rows[v];
+          mv_src[nm] = cur[v];
+          ++nm;
+        }
+      for (int v = nm; v < 2 * kGjNb; ++v) {
+        mv_dst[v] = j0;
+        mv_src[v] = j0;
+      }
+    }
+    if (pn % nwg == w && own) {
+#pragma unroll
+      for (int q = 0; q < kGjNb; ++q)
+        if (q < nb) A[tid + (int64_t)(j0 + q) * lda] = a[q];
+    }
+    __syncthreads();
+    // the columns this workgroup owns, one panel-width chunk at a time
+    for (int pc = w; pc < npan; pc += nwg) {
+      if (pc == pn) continue;
+      const int c0 = pc * kGjNb;
+      // row exchanges: all loads to LDS, then the stores (unused moves first)
+      for (int e = tid; e < kGjChunk * 2 * kGjNb; e += NT) {
+        const int cc = e / (2 * kGjNb), v = e % (2 * kGjNb), c = c0 + cc;
+        if (c < n) Mv[cc][v] = A[mv_src[v] + (int64_t)c * lda];
+      }
+      __syncthreads();
+      if (tid < kGjChunk && c0 + tid < n) {
+        zd* col = A + (int64_t)(c0 + tid) * lda;
+        for (int v = 2 * kGjNb - 1; v >= 0; --v) col[mv_dst[v]] = Mv[tid][v];
+      }
+      __syncthreads();
+      for (int e = tid; e < kGjNb * kGjChunk; e += NT) {
+        const int q = e % kGjNb, cc = e / kGjNb, c = c0 + cc;
+        Ws[q][cc] = (q < nb && c < n) ? A[(j0 + q) + (int64_t)c * lda] : zd{0.0, 0.0};
+      }
+      __syncthreads();
+      if (own) {
+        zd acc[kGjChunk];
+#pragma unroll
+        for (int cc = 0; cc < kGjChunk; ++cc) {
+          const int c = c0 + cc;
+          acc[cc] = (c < n) ? A[tid + (int64_t)c * lda] : zd{0.0, 0.0};
+        }
+        const int qi = tid - j0;
+#pragma unroll
+        for (int cc = 0; cc < kGjChunk; ++cc) {
+#pragma unroll
+          for (int q = 0; q < kGjNb; ++q) zfma(acc[cc], a[q], Ws[q][cc]);
+          if (qi >= 0 && qi < nb) {
+            zd wv = Ws[0][cc];
+#pragma unroll
+            for (int q = 1; q < kGjNb; ++q)
+              if (q == qi) wv = Ws[q][cc];
+            acc[cc] = zsub(acc[cc], wv);
+          }
+        }
+#pragma unroll
+        for (int cc = 0; cc < kGjChunk; ++cc) {
+          const int c = c0 + cc;
+          if (c < n) A[tid + (int64_t)c * lda] = acc[cc];
+        }
+      }
+      __syncthreads();
+    }
+    // all workgroups of the matrix meet before the next panel reads their columns
+    if (nwg > 1) {
+      if (tid == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int target = nwg * (pn + 1);
+        int64_t spins = 0;
+        while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          if (++spins > kGjCoopSpin) {
+            __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+      }
+      __syncthreads();
+    }
+  }
+  // undo the column permutation: out[:, j] = A[:, idx[j]] for this workgroup's panels
+  if (tid == 0) {
+    for (int j = 0; j < n; ++j) idx[j] = j;
+    for (int gc = n - 1; gc >= 0; --gc) {
+      const int pq = pivl[gc];
+      const int x = idx[gc];
+      idx[gc] = idx[pq];
+      idx[pq] = x;
+    }
+  }
+  __syncthreads();
+  if (own)
+    for (int pc = w; pc < npan; pc += nwg)
+      for (int j = pc * kGjNb; j < min(n, pc * kGjNb + kGjNb); ++j)
+        t.out[tid + (int64_t)j * n] = A[tid + (int64_t)idx[j] * lda];
+}
+
 // Row swaps of the panel applied to columns outside J. grid.x = task, grid.y = column chunk.
 __global__ void __launch_bounds__(256) gj_swaps_kernel(const GjTask* __restrict__ tasks, int j0) {
   const GjTask t = tasks[blockIdx.x];
@@ -889,6 +1142,31 @@ __global__ void __launch_bounds__(256) gj_copyrow_kernel(const GjTask* __restric
   const int q = threadIdx.x & 15;
   if (c >= n || q >= nb) return;
   W[blockIdx.x][q + (int64_t)c * nb] = t.A[(j0 + q) + (int64_t)c * t.lda];
+}
+
+// Row exchanges of the panel on the columns outside J, then the pivot rows into W (all
+// columns): one thread per column. grid.x = task, grid.y = column chunk.
+__global__ void __launch_bounds__(256) gj_swapcopy_kernel(const GjTask* __restrict__ tasks, int j0,
+                                                          zd* const* __restrict__ W) {
+  const GjTask t = tasks[blockIdx.x];
+  const int n = t.n;
+  if (j0 >= n) return;
+  const int nb = min(kGjNb, n - j0);
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  if (c >= n) return;
+  zd* col = t.A + (int64_t)c * t.lda;
+  if (c < j0 || c >= j0 + nb) {
+    for (int q = 0; q < nb; ++q) {
+      const int gc = j0 + q, p = t.piv[gc];
+      if (p != gc) {
+        const zd a = col[gc];
+        col[gc] = col[p];
+        col[p] = a;
+      }
+    }
+  }
+  zd* w = W[blockIdx.x] + (int64_t)c * nb;
+  for (int q = 0; q < nb; ++q) w[q] = col[j0 + q];
 }
 
 __global__ void __launch_bounds__(256) gj_fixrow_kernel(const GjTask* __restrict__ tasks, int j0,
@@ -1129,6 +1407,33 @@ void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStrea
   FMMLU_HIP(hipGetLastError());
 }
 
+void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st) {
+  if (ntasks <= 0 || nwg_total <= 0) return;
+  void* args[] = {(void*)&tasks, (void*)&ntasks};
+  if (nmax <= 256)
+    FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<256>), dim3((unsigned)nwg_total),
+                                         dim3(256), args, 0, st));
+  else if (nmax <= 512)
+    FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<512>), dim3((unsigned)nwg_total),
+                                         dim3(512), args, 0, st));
+  else
+    throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
+  FMMLU_HIP(hipGetLastError());
+}
+
+int gj_coop_capacity(int nmax) {
+  int dev = 0, per_cu = 0, cus = 0;
+  FMMLU_HIP(hipGetDevice(&dev));
+  FMMLU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (nmax <= 256)
+    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<256>),
+                                                           256, 0));
+  else
+    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<512>),
+                                                           512, 0));
+  return per_cu * cus;
+}
+
 int gj_panel_capacity() {
   int dev = 0, per_cu = 0, cus = 0;
   FMMLU_HIP(hipGetDevice(&dev));
@@ -1148,6 +1453,12 @@ void launch_gj_copyrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* co
                        hipStream_t st) {
   if (ntasks <= 0) return;
   hipLaunchKernelGGL(gj_copyrow_kernel, dim3(ntasks, (nmax + 15) / 16), dim3(256), 0, st, tasks, j0, W);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gj_swapcopy(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(gj_swapcopy_kernel, dim3(ntasks, (nmax + 255) / 256), dim3(256), 0, st, tasks, j0, W);
   FMMLU_HIP(hipGetLastError());
 }
 
