@@ -237,8 +237,10 @@ struct Stage {
   }
 };
 
-// Units of a GEMM task with 32 x 32 output blocks
-inline int64_t gemm_units(int M, int N) { return int64_t((M + 31) / 32) * ((N + 31) / 32); }
+// Units of a GEMM task: kGemmTile x kGemmTile output blocks
+inline int64_t gemm_units(int M, int N) {
+  return int64_t((M + kGemmTile - 1) / kGemmTile) * ((N + kGemmTile - 1) / kGemmTile);
+}
 inline int64_t units64(int r, int c) { return int64_t((r + 63) / 64) * ((c + 63) / 64); }
 
 struct GemmBatch {

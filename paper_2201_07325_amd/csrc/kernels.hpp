@@ -71,6 +71,7 @@ void launch_build_idmatrix(const DevGeom& g, const IdTask* tasks, int ntasks, in
 // ---- batched complex GEMM with segments and scatter maps ----
 // C[rmap[i], cmap[j]] = beta * C[...] + alpha * sum_s opA(A_s)[i, :] * B_s[:, j]
 // opA: 0 = N (A is M x K, lda), 1 = T (A stored K x M), 2 = C (conjugate transpose).
+constexpr int kGemmTile = 64;  // C block per workgroup (kGemmTile x kGemmTile)
 struct GemmSeg {
   const zd* A;
   const zd* B;
@@ -86,7 +87,7 @@ struct GemmTask {
   int32_t kchunk;                   // > 0: split K into chunks; chunk c writes C + c*part_stride
   double alpha_re, alpha_im, beta;  // beta real
   int64_t part_stride;
-  int64_t unit_begin;              // prefix sum of 32x32 output blocks (times K chunks)
+  int64_t unit_begin;              // prefix sum of kGemmTile^2 output blocks (times K chunks)
 };
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
                  hipStream_t st);

@@ -1,0 +1,184 @@
+// Batched complex float64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64).
+//
+//   C[rmap[i], cmap[j]] = beta C[...] + alpha * sum_s opA(A_s)[i, :] B_s[:, j]
+//
+// A workgroup of four wavefronts computes a 64 x 64 block of C; each wavefront owns a
+// 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16, with the real and imaginary parts
+// accumulated separately: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br (four real MFMAs per
+// complex block and k-step of 4). K is staged through LDS in steps of 16, as separate real
+// and imaginary planes, with the next step's global loads issued before the current step's
+// MFMAs. MFMA operand layout (16 x 16 x 4, float64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16], and holds D[l / 16 + 4 r][l % 16] in accumulator element r.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace fmmlu {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <class Task>
+__device__ inline int find_unit_task(const Task* __restrict__ t, int n, int64_t u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (t[mid].unit_begin <= u)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+constexpr int BM = kGemmTile, BN = kGemmTile, BK = 16;
+constexpr int LDP = BM + 4;  // padded LDS row (doubles)
+
+template <int OPA>
+__global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks,
+                                                         const GemmSeg* __restrict__ segs) {
+  __shared__ double Asr[BK][LDP], Asi[BK][LDP], Bsr[BK][LDP], Bsi[BK][LDP];
+  const int64_t u = blockIdx.x;
+  const GemmTask t = tasks[find_unit_task(tasks, ntasks, u)];
+  int64_t lu = u - t.unit_begin;
+  const int nbm = (t.M + BM - 1) / BM;
+  const int64_t ntiles = (int64_t)nbm * ((t.N + BN - 1) / BN);
+  const int kc = (int)(lu / ntiles);  // split-K chunk (0 without split)
+  lu -= (int64_t)kc * ntiles;
+  const int row0 = (int)(lu % nbm) * BM, col0 = (int)(lu / nbm) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wavefront quarter
+  dbl4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      ci[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int sidx = 0; sidx < t.nseg; ++sidx) {
+    const GemmSeg sg = segs[t.seg_begin + sidx];
+    const int kbeg = t.kchunk > 0 ? kc * t.kchunk : 0;
+    const int kend = t.kchunk > 0 ? min(sg.K, kbeg + t.kchunk) : sg.K;
+    if (kbeg >= kend) continue;
+    zd ra[4], rb[4];  // next step's global values (4 of A, 4 of B per thread)
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        int i, kk;
+        if (OPA == 0) {
+          i = e % BM;
+          kk = e / BM;
+        } else {
+          kk = e % BK;
+          i = e / BK;
+        }
+        const int gi = row0 + i, gk = k0 + kk;
+        zd v{0.0, 0.0};
+        if (gi < t.M && gk < kend) {
+          if (OPA == 0) {
+            v = sg.A[gi + (int64_t)gk * sg.lda];
+            if (sg.ishift > 0 && gi == sg.ishift - 1 + gk) v.re -= 1.0;
+          } else {
+            v = sg.A[gk + (int64_t)gi * sg.lda];
+            if (OPA == 2) v.im = -v.im;
+          }
+        }
+        ra[q] = v;
+        const int kb = e % BK, j = e / BK;
+        const int gkb = k0 + kb, gj = col0 + j;
+        zd w{0.0, 0.0};
+        if (gkb < kend && gj < t.N) w = sg.B[gkb + (int64_t)gj * sg.ldb];
+        rb[q] = w;
+      }
+    };
+    auto store = [&]() {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q;
+        int i, kk;
+        if (OPA == 0) {
+          i = e % BM;
+          kk = e / BM;
+        } else {
+          kk = e % BK;
+          i = e / BK;
+        }
+        Asr[kk][i] = ra[q].re;
+        Asi[kk][i] = ra[q].im;
+        const int kb = e % BK, j = e / BK;
+        Bsr[kb][j] = rb[q].re;
+        Bsi[kb][j] = rb[q].im;
+      }
+    };
+    load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+      __syncthreads();
+      store();
+      __syncthreads();
+      if (k0 + BK < kend) load(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        const int kr = ks + (lane >> 4), cl = lane & 15;
+        double ar[2], ai[2], an[2], br[2], bi[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          ar[a] = Asr[kr][wr + 16 * a + cl];
+          ai[a] = Asi[kr][wr + 16 * a + cl];
+          an[a] = -ai[a];
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          br[b] = Bsr[kr][wc + 16 * b + cl];
+          bi[b] = Bsi[kr][wc + 16 * b + cl];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
+            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[a], bi[b], cr[a][b], 0, 0, 0);
+            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
+            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
+          }
+      }
+    }
+  }
+  const zd alpha{t.alpha_re, t.alpha_im};
+  zd* Cb = t.C + (int64_t)kc * t.part_stride;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row0 + wr + 16 * a + (lane >> 4) + 4 * r;
+        const int j = col0 + wc + 16 * b + (lane & 15);
+        if (i >= t.M || j >= t.N) continue;
+        const int ri = t.rmap ? t.rmap[i] : i;
+        const int cj = t.cmap ? t.cmap[j] : j;
+        zd* c = Cb + ri + (int64_t)cj * t.ldc;
+        zd v = zmul(alpha, zd{cr[a][b][r], ci[a][b][r]});
+        if (t.beta != 0.0) v = zadd(v, zscale(*c, t.beta));
+        *c = v;
+      }
+}
+
+}  // namespace
+
+void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
+                 hipStream_t st) {
+  if (ntasks <= 0 || nunits <= 0) return;
+  const dim3 g((unsigned)nunits), b(256);
+  if (opA == 0)
+    hipLaunchKernelGGL(zgemm_mfma_kernel<0>, g, b, 0, st, tasks, ntasks, segs);
+  else if (opA == 1)
+    hipLaunchKernelGGL(zgemm_mfma_kernel<1>, g, b, 0, st, tasks, ntasks, segs);
+  else
+    hipLaunchKernelGGL(zgemm_mfma_kernel<2>, g, b, 0, st, tasks, ntasks, segs);
+  FMMLU_HIP(hipGetLastError());
+}
+
+}  // namespace fmmlu

@@ -56,102 +56,6 @@ __device__ inline double block_sum_d(double v, double* red) {
 }
 
 // ---------------------------------------------------------------------------------------
-// GEMM: 256 threads as 16 x 16, each thread a TM x TN micro-tile, block (16 TM) x (16 TN),
-// K staged through LDS in steps of 16.
-template <int OPA, int TM, int TN>
-__global__ void __launch_bounds__(256) gemm_kernel(const GemmTask* __restrict__ tasks, int ntasks,
-                                                   const GemmSeg* __restrict__ segs) {
-  constexpr int BM = 16 * TM, BN = 16 * TN, BK = 16;
-  __shared__ zd As[BK][BM + 1];
-  __shared__ zd Bs[BK][BN + 1];
-  const int64_t u = blockIdx.x;
-  const int ti = find_task(tasks, ntasks, u);
-  const GemmTask t = tasks[ti];
-  int64_t lu = u - t.unit_begin;
-  const int nbm = (t.M + BM - 1) / BM;
-  const int64_t ntiles = (int64_t)nbm * ((t.N + BN - 1) / BN);
-  const int kc = (int)(lu / ntiles);  // split-K chunk (0 without split)
-  lu -= (int64_t)kc * ntiles;
-  const int bm = (int)(lu % nbm), bn = (int)(lu / nbm);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  zd acc[TM][TN];
-#pragma unroll
-  for (int a = 0; a < TM; ++a)
-#pragma unroll
-    for (int b = 0; b < TN; ++b) acc[a][b] = zd{0.0, 0.0};
-  const int row0 = bm * BM, col0 = bn * BN;
-  for (int sidx = 0; sidx < t.nseg; ++sidx) {
-    const GemmSeg sg = segs[t.seg_begin + sidx];
-    const int kbeg = t.kchunk > 0 ? kc * t.kchunk : 0;
-    const int kend = t.kchunk > 0 ? min(sg.K, kbeg + t.kchunk) : sg.K;
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-      // A tile: BM x BK
-      for (int e = threadIdx.x; e < BM * BK; e += 256) {
-        int i, kk;
-        if (OPA == 0) {
-          i = e % BM;
-          kk = e / BM;
-        } else {
-          kk = e % BK;
-          i = e / BK;
-        }
-        const int gi = row0 + i, gk = k0 + kk;
-        zd v{0.0, 0.0};
-        if (gi < t.M && gk < kend) {
-          if (OPA == 0) {
-            v = sg.A[gi + (int64_t)gk * sg.lda];
-            if (sg.ishift > 0 && gi == sg.ishift - 1 + gk) v.re -= 1.0;
-          } else {
-            v = sg.A[gk + (int64_t)gi * sg.lda];
-            if (OPA == 2) v.im = -v.im;
-          }
-        }
-        As[kk][i] = v;
-      }
-      // B tile: BK x BN
-      for (int e = threadIdx.x; e < BK * BN; e += 256) {
-        const int kk = e % BK, j = e / BK;
-        const int gk = k0 + kk, gj = col0 + j;
-        zd v{0.0, 0.0};
-        if (gk < kend && gj < t.N) v = sg.B[gk + (int64_t)gj * sg.ldb];
-        Bs[kk][j] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < BK; ++kk) {
-        zd a[TM], b[TN];
-#pragma unroll
-        for (int q = 0; q < TM; ++q) a[q] = As[kk][ty + 16 * q];
-#pragma unroll
-        for (int q = 0; q < TN; ++q) b[q] = Bs[kk][tx + 16 * q];
-#pragma unroll
-        for (int qa = 0; qa < TM; ++qa)
-#pragma unroll
-          for (int qb = 0; qb < TN; ++qb) zfma(acc[qa][qb], a[qa], b[qb]);
-      }
-      __syncthreads();
-    }
-  }
-  const zd alpha{t.alpha_re, t.alpha_im};
-#pragma unroll
-  for (int qa = 0; qa < TM; ++qa) {
-    const int i = row0 + ty + 16 * qa;
-    if (i >= t.M) continue;
-    const int ri = t.rmap ? t.rmap[i] : i;
-#pragma unroll
-    for (int qb = 0; qb < TN; ++qb) {
-      const int j = col0 + tx + 16 * qb;
-      if (j >= t.N) continue;
-      const int cj = t.cmap ? t.cmap[j] : j;
-      zd* c = t.C + (int64_t)kc * t.part_stride + ri + (int64_t)cj * t.ldc;
-      zd v = zmul(alpha, acc[qa][qb]);
-      if (t.beta != 0.0) v = zadd(v, zscale(*c, t.beta));
-      *c = v;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------------------
 // Householder QR of the panel A[j0:rows, j0:j0+nb], nb <= kQrNb. Reflector H = I - tau v v^H
 // with v = x + e^{i arg x0} |x| e_1 and tau = 2/|v|^2 (Hermitian, unitary), so that
 // H x = -e^{i arg x0} |x| e_1. The product H_1 ... H_nb = I - V Tw V^H (compact WY, forward)
@@ -886,11 +790,9 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
   zd* A = t.A;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const bool own = tid < n;
-  __shared__ double bv[NW];
-  __shared__ int bi[NW];
-  __shared__ zd prow[kGjNb], rowgc[kGjNb];
-  __shared__ int sh_p;
-  __shared__ double sh_best;
+  __shared__ double bv[2][NW];
+  __shared__ int bi[2][NW];
+  __shared__ zd prow[2][kGjNb], rowgc[2][kGjNb];
   __shared__ int pivl[NT], idx[NT];
   __shared__ int mv_dst[2 * kGjNb], mv_src[2 * kGjNb], rows[2 * kGjNb], cur[2 * kGjNb];
   __shared__ zd Ws[kGjNb][kGjChunk + 1];
@@ -901,8 +803,10 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
     zd a[kGjNb];
 #pragma unroll
     for (int q = 0; q < kGjNb; ++q) a[q] = (own && q < nb) ? A[tid + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
+    // two barriers per column: LDS slots alternate between even and odd columns, so the next
+    // column's writes never meet this column's reads
     for (int j = 0; j < nb; ++j) {
-      const int gc = j0 + j;
+      const int gc = j0 + j, par = j & 1;
       zd aj = a[0];
 #pragma unroll
       for (int q = 1; q < kGjNb; ++q)
@@ -922,70 +826,66 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
         }
       }
       if (lane == 0) {
-        bv[wave] = best;
-        bi[wave] = besti;
+        bv[par][wave] = best;
+        bi[par][wave] = besti;
       }
       __syncthreads();
-      if (tid == 0) {
-        double b = bv[0];
-        int p = bi[0];
-        for (int q = 1; q < NW; ++q)
-          if (gj_better(bv[q], bi[q], b, p)) {
-            b = bv[q];
-            p = bi[q];
-          }
-        if (p >= n) p = gc;
-        sh_p = p;
-        sh_best = b;
-        pivl[gc] = p;
-      }
-      __syncthreads();
-      const int p = sh_p;
+      double b = bv[par][0];
+      int p = bi[par][0];
+#pragma unroll
+      for (int q = 1; q < NW; ++q)
+        if (gj_better(bv[par][q], bi[par][q], b, p)) {
+          b = bv[par][q];
+          p = bi[par][q];
+        }
+      if (p >= n) p = gc;
       if (tid == p) {
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) prow[q] = a[q];
+        for (int q = 0; q < kGjNb; ++q) prow[par][q] = a[q];
       }
       if (tid == gc) {
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) rowgc[q] = a[q];
+        for (int q = 0; q < kGjNb; ++q) rowgc[par][q] = a[q];
+      }
+      if (tid == 0) pivl[gc] = p;
+      if (w == 0 && tid == 0) {
+        t.piv[gc] = p;
+        if (!(b > 0.0) && *t.info == 0) *t.info = gc + 1;
       }
       __syncthreads();
       if (p != gc) {
         if (tid == gc) {
 #pragma unroll
-          for (int q = 0; q < kGjNb; ++q) a[q] = prow[q];
+          for (int q = 0; q < kGjNb; ++q) a[q] = prow[par][q];
         } else if (tid == p) {
 #pragma unroll
-          for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[q];
+          for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[par][q];
         }
       }
-      zd pv = prow[0];
+      zd pv = prow[par][0];
 #pragma unroll
       for (int q = 1; q < kGjNb; ++q)
-        if (q == j) pv = prow[q];
+        if (q == j) pv = prow[par][q];
       const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
       if (tid == gc) {
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[q], inv);
+        for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[par][q], inv);
       } else if (own) {
         zd f = a[0];
 #pragma unroll
         for (int q = 1; q < kGjNb; ++q)
           if (q == j) f = a[q];
+        const zd fi = zmul(f, inv);
 #pragma unroll
         for (int q = 0; q < kGjNb; ++q) {
           if (q == j)
-            a[q] = zd{-(f.re * inv.re - f.im * inv.im), -(f.re * inv.im + f.im * inv.re)};
+            a[q] = zd{-fi.re, -fi.im};
           else
-            a[q] = zsub(a[q], zmul(f, zmul(prow[q], inv)));
+            a[q] = zsub(a[q], zmul(fi, prow[par][q]));
         }
       }
-      if (w == 0 && tid == 0) {
-        t.piv[gc] = p;
-        if (!(sh_best > 0.0) && *t.info == 0) *t.info = gc + 1;
-      }
-      __syncthreads();
     }
+    __syncthreads();
     // compose the panel's exchanges; unused moves take row j0 onto itself and are applied
     // first, so a real move into row j0 lands last
     if (tid == 0) {
@@ -1328,20 +1228,6 @@ __global__ void __launch_bounds__(256) transpose_kernel(const CopyTask* __restri
 void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
   hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
-  FMMLU_HIP(hipGetLastError());
-}
-
-void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
-                 hipStream_t st) {
-  if (ntasks <= 0 || nunits <= 0) return;
-  dim3 g((unsigned)nunits), b(256);
-  // 32 x 32 blocks (2 x 2 per thread); units must be counted with gemm_units(.., 32)
-  if (opA == 0)
-    hipLaunchKernelGGL((gemm_kernel<0, 2, 2>), g, b, 0, st, tasks, ntasks, segs);
-  else if (opA == 1)
-    hipLaunchKernelGGL((gemm_kernel<1, 2, 2>), g, b, 0, st, tasks, ntasks, segs);
-  else
-    hipLaunchKernelGGL((gemm_kernel<2, 2, 2>), g, b, 0, st, tasks, ntasks, segs);
   FMMLU_HIP(hipGetLastError());
 }
 
