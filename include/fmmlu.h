@@ -132,6 +132,17 @@ fmmlu_status fmmlu_factor(fmmlu_tree_h t, const double* xyz, const double* norma
  */
 fmmlu_status fmmlu_solve(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs, void* hip_stream);
 
+/*
+ * Solve launch mode. By default (enable = 1) the first solve in each direction captures its
+ * sweeps (kernels only) into a HIP graph on a private stream, and every solve then copies b
+ * into the graph's input, replays the graph on hip_stream and copies the result out: the
+ * same kernels in the same order, with one launch instead of a few hundred. enable = 0
+ * launches the kernels one by one on hip_stream (needed by callers that capture solves into
+ * graphs of their own). If capture is not possible the library falls back to enable = 0.
+ * Concurrent solves on one factor must be serialised by the caller (they share workspace).
+ */
+fmmlu_status fmmlu_set_solve_graph(fmmlu_factor_h f, int32_t enable);
+
 /* x = A_f^{-H} b (conjugate transpose of the factored inverse; same layout as fmmlu_solve). */
 fmmlu_status fmmlu_solve_adjoint(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs,
                                  void* hip_stream);

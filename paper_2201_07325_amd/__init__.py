@@ -79,6 +79,7 @@ def lib():
         "fmmlu_solve_refined": (I32, [P, P, P, I32, D, I32, C.POINTER(I32), PD, P]),
         "fmmlu_farfield": (I32, [P, P, I64, I32, P, P, P]),
         "fmmlu_dense_inverse": (I32, [P, I64, I64, P, P]),
+        "fmmlu_set_solve_graph": (I32, [P, I32]),
         "fmmlu_factor_info": (I32, [P, C.POINTER(Info)]),
         "fmmlu_factor_boxes": (I32, [P, C.POINTER(I64), P, P, P, P, P]),
         "fmmlu_factor_destroy": (None, [P]),
@@ -219,6 +220,10 @@ class Factor:
     def solve(self, b):
         """x = A_f^{-1} b."""
         return self._apply(lib().fmmlu_solve, b)
+
+    def set_solve_graph(self, enable):
+        """Replay solves from a captured HIP graph (default) or launch kernels one by one."""
+        _check(lib().fmmlu_set_solve_graph(self.h, 1 if enable else 0))
 
     def solve_adjoint(self, b):
         """x = A_f^{-H} b."""

@@ -199,6 +199,12 @@ fmmlu_status fmmlu_solve(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs,
   });
 }
 
+fmmlu_status fmmlu_set_solve_graph(fmmlu_factor_h f, int32_t enable) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  f->f.use_graph = enable != 0;
+  return FMMLU_OK;
+}
+
 fmmlu_status fmmlu_solve_adjoint(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs,
                                  void* hip_stream) {
   if (!f) return fail(FMMLU_ESTATE, "factor is NULL");

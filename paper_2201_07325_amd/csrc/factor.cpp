@@ -1574,29 +1574,86 @@ void FactorImpl::ensure_workspace() {
   wmv = arena.alloc_n<zd>((size_t)n);
 }
 
+void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) {
+  const int adj = adjoint ? 1 : 0;
+  launch_permute(bc, wx, order_dev, n, 1, st);
+  // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
+  for (auto& ph : phases) {
+    launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, ph.rmax, wx, wxr, adj, st);
+    launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, st);
+    launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
+  }
+  // D^{-1} (adjoint D^{-H}): all pivot blocks, then the top block
+  launch_solve_diag(all_boxes, nall, rmax_all, wx, adj, st);
+  launch_solve_top(Ainv, n0, top_dev, wx, wtop, adj, st);
+  // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse
+  for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
+    launch_solve_bpart(it->dboxes, it->dp, it->np, wx, wp, adj, st);
+    launch_solve_bfin(it->dboxes, it->box_end - it->box_begin, it->rmax, wp, wx, adj, st);
+  }
+  launch_permute(wx, xc, order_dev, n, 0, st);
+}
+
+// Capture the sweeps of one direction into a graph on a private stream (reading gin,
+// writing gout). The sweeps contain kernels only: no copies, fills or allocations.
+bool FactorImpl::capture(int adj) {
+  if (gexec[adj]) return true;
+  if (!gstream) FMMLU_HIP(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking));
+  if (!gin) {
+    gin = arena.alloc_n<zd>((size_t)n);
+    gout = arena.alloc_n<zd>((size_t)n);
+  }
+  if (hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  bool ok = true;
+  try {
+    solve_core(gin, gout, adj != 0, gstream);
+  } catch (const Error&) {
+    ok = false;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(gstream, &g) != hipSuccess || !ok || !g) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    return false;
+  }
+  hipGraphExec_t e = nullptr;
+  if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    return false;
+  }
+  graph[adj] = g;
+  gexec[adj] = e;
+  return true;
+}
+
 void FactorImpl::solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st) {
   ensure_workspace();
   const int adj = adjoint ? 1 : 0;
+  const bool g = use_graph && capture(adj);
+  if (!g) use_graph = false;
   for (int64_t c = 0; c < nrhs; ++c) {
     const zd* bc = b + c * n;
     zd* xc = x + c * n;
-    launch_permute(bc, wx, order_dev, n, 1, st);
-    // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
-    for (auto& ph : phases) {
-      launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, ph.rmax, wx, wxr, adj, st);
-      launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, st);
-      launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
+    if (g) {
+      FMMLU_HIP(hipMemcpyAsync(gin, bc, sizeof(zd) * (size_t)n, hipMemcpyDeviceToDevice, st));
+      FMMLU_HIP(hipGraphLaunch(gexec[adj], st));
+      FMMLU_HIP(hipMemcpyAsync(xc, gout, sizeof(zd) * (size_t)n, hipMemcpyDeviceToDevice, st));
+    } else {
+      solve_core(bc, xc, adjoint, st);
     }
-    // D^{-1} (adjoint D^{-H}): all pivot blocks, then the top block
-    launch_solve_diag(all_boxes, nall, rmax_all, wx, adj, st);
-    launch_solve_top(Ainv, n0, top_dev, wx, wtop, adj, st);
-    // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse
-    for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
-      launch_solve_bpart(it->dboxes, it->dp, it->np, wx, wp, adj, st);
-      launch_solve_bfin(it->dboxes, it->box_end - it->box_begin, it->rmax, wp, wx, adj, st);
-    }
-    launch_permute(wx, xc, order_dev, n, 0, st);
   }
+}
+
+FactorImpl::~FactorImpl() {
+  for (int a = 0; a < 2; ++a) {
+    if (gexec[a]) (void)hipGraphExecDestroy(gexec[a]);
+    if (graph[a]) (void)hipGraphDestroy(graph[a]);
+  }
+  if (gstream) (void)hipStreamDestroy(gstream);
 }
 
 }  // namespace fmmlu

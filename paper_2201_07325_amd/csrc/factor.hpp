@@ -121,7 +121,18 @@ struct FactorImpl {
   void factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
               hipStream_t st);
   void solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st);
+  // one right-hand side, every kernel of the sweeps (no copies, no allocation)
+  void solve_core(const zd* b, zd* x, bool adjoint, hipStream_t st);
   void ensure_workspace();
+  // solves replay a captured HIP graph per direction (input/output through gin/gout)
+  bool use_graph = true;
+  hipStream_t gstream = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  zd* gin = nullptr;
+  zd* gout = nullptr;
+  bool capture(int adj);
+  ~FactorImpl();
   // exact float64 product in the original point order (op as fmmlu_matvec)
   void matvec(int op, const zd* x, zd* y, hipStream_t st);
   // restarted right-preconditioned FGMRES; returns true when relres <= tol
