@@ -54,6 +54,7 @@ typedef enum {
 
 typedef struct fmmlu_tree_s* fmmlu_tree_h;
 typedef struct fmmlu_factor_s* fmmlu_factor_h;
+typedef struct fmmlu_batch_s* fmmlu_batch_h;
 
 /* Options of fmmlu_factor. Fill with fmmlu_default_opts() first. */
 typedef struct {
@@ -179,6 +180,38 @@ fmmlu_status fmmlu_farfield(fmmlu_factor_h f, const double* dirs, int64_t ndir, 
 fmmlu_status fmmlu_solve_refined(fmmlu_factor_h f, const void* b, void* x, int32_t adjoint,
                                  double tol, int32_t maxit, int32_t* iters, double* relres,
                                  void* hip_stream);
+
+/*
+ * Batch of independent problems (many scatterers, each its own system A~_i of Section 3):
+ * problem i has tree trees[i], host geometry xyz[i], normals[i], weights[i] (layouts as in
+ * fmmlu_factor) and wavenumber k[i], coupling eta[i]; every problem uses *opts. The problems
+ * are factored concurrently by nthreads host threads (0: min(count, 8)), each driving its own
+ * HIP stream on the calling thread's current device, so that one problem's latency-bound
+ * phases overlap another's. Errors name the failing problem. The batch owns its factors.
+ */
+fmmlu_status fmmlu_factor_batch(int32_t count, const fmmlu_tree_h* trees, const double* const* xyz,
+                                const double* const* normals, const double* const* weights,
+                                const double* k, const double* eta, const fmmlu_opts* opts,
+                                int32_t nthreads, fmmlu_batch_h* out);
+
+/* Problem count and offsets[0..count] of each problem's unknowns in the concatenated vectors
+ * of fmmlu_batch_solve (offsets[count] = total). Either pointer may be NULL. */
+fmmlu_status fmmlu_batch_info(fmmlu_batch_h b, int32_t* count, int64_t* offsets);
+
+/* Borrowed handle of problem i's factorization (for matvec, info, single solves); it stays
+ * owned by the batch: do not pass it to fmmlu_factor_destroy. */
+fmmlu_status fmmlu_batch_factor(fmmlu_batch_h b, int32_t i, fmmlu_factor_h* out);
+
+/*
+ * x_i = A_i^{-1} b_i (adjoint != 0: A_i^{-H} b_i) for every problem, on concatenated device
+ * complex128 vectors of the batch's total length (problem i at offsets[i], original point
+ * order). The sweeps of all problems replay from one captured HIP graph with a branch per
+ * problem (captured on first use per direction). b and x may alias. Asynchronous on hip_stream.
+ */
+fmmlu_status fmmlu_batch_solve(fmmlu_batch_h b, const void* rhs, void* x, int32_t adjoint,
+                               void* hip_stream);
+
+void fmmlu_batch_destroy(fmmlu_batch_h b);
 
 /* Statistics of a finished factorization. */
 fmmlu_status fmmlu_factor_info(fmmlu_factor_h f, fmmlu_info* out);

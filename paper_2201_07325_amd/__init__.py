@@ -80,6 +80,11 @@ def lib():
         "fmmlu_farfield": (I32, [P, P, I64, I32, P, P, P]),
         "fmmlu_dense_inverse": (I32, [P, I64, I64, P, P]),
         "fmmlu_set_solve_graph": (I32, [P, I32]),
+        "fmmlu_factor_batch": (I32, [I32, P, P, P, P, P, P, P, I32, P]),
+        "fmmlu_batch_info": (I32, [P, C.POINTER(I32), P]),
+        "fmmlu_batch_factor": (I32, [P, I32, P]),
+        "fmmlu_batch_solve": (I32, [P, P, P, I32, P]),
+        "fmmlu_batch_destroy": (None, [P]),
         "fmmlu_factor_info": (I32, [P, C.POINTER(Info)]),
         "fmmlu_factor_boxes": (I32, [P, C.POINTER(I64), P, P, P, P, P]),
         "fmmlu_factor_destroy": (None, [P]),
@@ -312,9 +317,9 @@ class Factor:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and _lib is not None:
+        if h is not None and _lib is not None and getattr(self, "_owner", None) is None:
             _lib.fmmlu_factor_destroy(h)
-            self.h = None
+        self.h = None
 
 
 def kernel_block(points, normals, weights, k, eta, rows, cols):
@@ -350,4 +355,73 @@ def dense_inverse(a):
     _check(lib().fmmlu_dense_inverse(P(ac.data_ptr()), n, cnt, P(out.data_ptr()), _stream()))
     res = out.transpose(1, 2)
     return res[0] if squeeze else res
+
+
+class FactorBatch:
+    """Independent problems (e.g. many scatterers) factored concurrently on the current GPU.
+
+    problems: sequence of (points, normals, weights, k, eta). Solves take and return one
+    concatenated complex128 CUDA vector; problem i occupies offsets[i]:offsets[i+1].
+    """
+
+    def __init__(self, problems, eps=1e-6, leaf_size=64, nthreads=0, proxy_radius=2.5, proxy_min_points=64,
+                 id_route=0):
+        L = lib()
+        self.problems = []
+        for pts, nrm, w, k, eta in problems:
+            p = _soa(pts)
+            n = p.size // 3
+            self.problems.append((p, _soa(nrm, n), np.ascontiguousarray(np.asarray(w, dtype=np.float64)),
+                                  float(k), float(eta)))
+        cnt = len(self.problems)
+        if cnt < 1:
+            raise ValueError("empty batch")
+        self.trees = [Tree(p[0], leaf_size) for p in self.problems]
+        arr = lambda vals: (P * cnt)(*vals)
+        trees = arr([t.h for t in self.trees])
+        xyz = arr([p[0].ctypes.data for p in self.problems])
+        nrm = arr([p[1].ctypes.data for p in self.problems])
+        ws = arr([p[2].ctypes.data for p in self.problems])
+        ks = (C.c_double * cnt)(*[p[3] for p in self.problems])
+        etas = (C.c_double * cnt)(*[p[4] for p in self.problems])
+        o = Opts()
+        _check(L.fmmlu_default_opts(C.byref(o)))
+        o.eps = float(eps)
+        o.proxy_radius = float(proxy_radius)
+        o.proxy_min_points = int(proxy_min_points)
+        o.id_route = int(id_route)
+        h = P()
+        _check(L.fmmlu_factor_batch(cnt, trees, xyz, nrm, ws, ks, etas, C.byref(o), int(nthreads), C.byref(h)))
+        self.h = h
+        c = I32()
+        off = np.zeros(cnt + 1, np.int64)
+        _check(L.fmmlu_batch_info(self.h, C.byref(c), off.ctypes.data))
+        self.count = int(c.value)
+        self.offsets = off
+        self.n = int(off[-1])
+
+    def solve(self, b, adjoint=False):
+        import torch
+        b = _dev_c128(b, self.n).contiguous()
+        x = torch.empty_like(b)
+        _check(lib().fmmlu_batch_solve(self.h, P(b.data_ptr()), P(x.data_ptr()), 1 if adjoint else 0, _stream()))
+        return x
+
+    def factor(self, i):
+        """Borrowed view of problem i's factorization (solve, matvec, info); the batch owns it."""
+        h = P()
+        _check(lib().fmmlu_batch_factor(self.h, int(i), C.byref(h)))
+        f = Factor.__new__(Factor)
+        p = self.problems[i]
+        f.points, f.normals, f.weights, f.k, f.eta = p[0], p[1], p[2], p[3], p[4]
+        f.n = p[0].size // 3
+        f.h = h
+        f._owner = self
+        return f
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.fmmlu_batch_destroy(h)
+            self.h = None
 

@@ -1,14 +1,18 @@
 // C ABI of the library: argument validation, handle management, error translation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fmmlu.h"
 #include "common.hpp"
+#include "batch.hpp"
 #include "factor.hpp"
 #include "kernels.hpp"
 #include "tree.hpp"
@@ -56,7 +60,67 @@ void check_finite(const double* v, int64_t cnt, const char* what) {
     if (!std::isfinite(v[i])) throw Error(FMMLU_EINVAL, std::string(what) + " contains NaN or Inf");
 }
 
+// Checks of fmmlu_factor's arguments that need no GPU; returns the options to use.
+fmmlu_opts checked_opts(fmmlu_tree_h t, const double* xyz, const double* normals, const double* weights, double k,
+                        double eta, const fmmlu_opts* opts) {
+  if (!t) throw Error(FMMLU_ESTATE, "tree is NULL");
+  if (!xyz || !normals || !weights) throw Error(FMMLU_EINVAL, "geometry pointer is NULL");
+  fmmlu_opts o;
+  if (opts)
+    o = *opts;
+  else
+    fmmlu_default_opts(&o);
+  if (!(o.eps > 0.0 && o.eps <= 0.1)) throw Error(FMMLU_EINVAL, "eps must be in (0, 0.1]");
+  if (!(k >= 0.0) || !std::isfinite(k)) throw Error(FMMLU_EINVAL, "k must be finite and >= 0");
+  if (!std::isfinite(eta)) throw Error(FMMLU_EINVAL, "eta must be finite");
+  if (!(o.proxy_radius >= 1.5 && o.proxy_radius <= 10.0)) throw Error(FMMLU_EINVAL, "proxy_radius must be in [1.5, 10]");
+  if (o.proxy_min_points < 1) throw Error(FMMLU_EINVAL, "proxy_min_points must be >= 1");
+  if (o.id_route < 0 || o.id_route > 2) throw Error(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
+  if (o.precision != FMMLU_FP64) throw Error(FMMLU_EINVAL, "only FMMLU_FP64 is available in this build");
+  const int64_t n = t->t.n;
+  check_finite(xyz, 3 * n, "points");
+  check_finite(normals, 3 * n, "normals");
+  check_finite(weights, n, "weights");
+  if (std::memcmp(xyz, t->xyz.data(), sizeof(double) * 3 * n) != 0)
+    throw Error(FMMLU_EINVAL, "points differ from those the tree was built from");
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(weights[i] > 0.0)) throw Error(FMMLU_EINVAL, "weights must be positive");
+    const double nn =
+        normals[i] * normals[i] + normals[n + i] * normals[n + i] + normals[2 * n + i] * normals[2 * n + i];
+    if (std::fabs(nn - 1.0) > 1e-6) throw Error(FMMLU_EINVAL, "normals must be unit vectors");
+  }
+  return o;
+}
+
+// Factor on the calling thread's current device; the handle owns the result.
+fmmlu_factor_s* make_factor(fmmlu_tree_h t, const double* xyz, const double* normals, const double* weights, double k,
+                            double eta, const fmmlu_opts& o, hipStream_t st) {
+  auto* h = new fmmlu_factor_s;
+  try {
+    FMMLU_HIP(hipGetDevice(&h->f.device));
+    h->f.k = k;
+    h->f.eta = eta;
+    h->f.opts = o;
+    h->f.factor(t->t, xyz, normals, weights, st);
+    h->f.info.t_tree = t->t_build;
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  return h;
+}
+
 }  // namespace
+
+// ---- batches of independent problems ----
+struct fmmlu_batch_s {
+  std::vector<fmmlu_factor_s*> factors;  // owned
+  std::vector<int64_t> offsets;          // count + 1
+  BatchSolver solver;
+  ~fmmlu_batch_s() {
+    for (auto* f : factors) delete f;
+  }
+};
 
 extern "C" {
 
@@ -145,49 +209,109 @@ fmmlu_status fmmlu_factor(fmmlu_tree_h t, const double* xyz, const double* norma
                           void* hip_stream, fmmlu_factor_h* out) {
   if (!out) return fail(FMMLU_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!t) return fail(FMMLU_ESTATE, "tree is NULL");
-  if (!xyz || !normals || !weights) return fail(FMMLU_EINVAL, "geometry pointer is NULL");
-  fmmlu_opts o;
-  if (opts)
-    o = *opts;
-  else
-    fmmlu_default_opts(&o);
-  if (!(o.eps > 0.0 && o.eps <= 0.1)) return fail(FMMLU_EINVAL, "eps must be in (0, 0.1]");
-  if (!(k >= 0.0) || !std::isfinite(k)) return fail(FMMLU_EINVAL, "k must be finite and >= 0");
-  if (!std::isfinite(eta)) return fail(FMMLU_EINVAL, "eta must be finite");
-  if (!(o.proxy_radius >= 1.5 && o.proxy_radius <= 10.0))
-    return fail(FMMLU_EINVAL, "proxy_radius must be in [1.5, 10]");
-  if (o.proxy_min_points < 1) return fail(FMMLU_EINVAL, "proxy_min_points must be >= 1");
-  if (o.id_route < 0 || o.id_route > 2) return fail(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
-  if (o.precision != FMMLU_FP64) return fail(FMMLU_EINVAL, "only FMMLU_FP64 is available in this build");
-  const int64_t n = t->t.n;
   return guarded([&] {
-    check_finite(xyz, 3 * n, "points");
-    check_finite(normals, 3 * n, "normals");
-    check_finite(weights, n, "weights");
-    if (std::memcmp(xyz, t->xyz.data(), sizeof(double) * 3 * n) != 0)
-      throw Error(FMMLU_EINVAL, "points differ from those the tree was built from");
-    for (int64_t i = 0; i < n; ++i) {
-      if (!(weights[i] > 0.0)) throw Error(FMMLU_EINVAL, "weights must be positive");
-      const double nn = normals[i] * normals[i] + normals[n + i] * normals[n + i] +
-                        normals[2 * n + i] * normals[2 * n + i];
-      if (std::fabs(nn - 1.0) > 1e-6) throw Error(FMMLU_EINVAL, "normals must be unit vectors");
-    }
-    auto* h = new fmmlu_factor_s;
-    try {
-      FMMLU_HIP(hipGetDevice(&h->f.device));
-      h->f.k = k;
-      h->f.eta = eta;
-      h->f.opts = o;
-      h->f.factor(t->t, xyz, normals, weights, static_cast<hipStream_t>(hip_stream));
-      h->f.info.t_tree = t->t_build;
-    } catch (...) {
-      delete h;
-      throw;
-    }
-    *out = h;
+    const fmmlu_opts o = checked_opts(t, xyz, normals, weights, k, eta, opts);
+    *out = make_factor(t, xyz, normals, weights, k, eta, o, static_cast<hipStream_t>(hip_stream));
   });
 }
+
+fmmlu_status fmmlu_factor_batch(int32_t count, const fmmlu_tree_h* trees, const double* const* xyz,
+                                const double* const* normals, const double* const* weights, const double* k,
+                                const double* eta, const fmmlu_opts* opts, int32_t nthreads, fmmlu_batch_h* out) {
+  if (!out) return fail(FMMLU_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1) return fail(FMMLU_EINVAL, "count must be >= 1");
+  if (!trees || !xyz || !normals || !weights || !k || !eta) return fail(FMMLU_EINVAL, "array pointer is NULL");
+  return guarded([&] {
+    std::vector<fmmlu_opts> os(count);
+    for (int i = 0; i < count; ++i) {
+      try {
+        os[i] = checked_opts(trees[i], xyz[i], normals[i], weights[i], k[i], eta[i], opts);
+      } catch (const Error& e) {
+        throw Error(e.status, "problem " + std::to_string(i) + ": " + e.what());
+      }
+    }
+    auto* b = new fmmlu_batch_s;
+    try {
+      b->factors.assign(count, nullptr);
+      int dev = 0;
+      FMMLU_HIP(hipGetDevice(&dev));
+      const int nt = std::max(1, std::min<int>(count, nthreads > 0 ? nthreads : 8));
+      std::atomic<int> next{0};
+      std::vector<fmmlu_status> st(count, FMMLU_OK);
+      std::vector<std::string> msg(count);
+      auto worker = [&]() {
+        hipStream_t s = nullptr;
+        if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+          (void)hipGetLastError();
+          for (int i = next++; i < count; i = next++) {
+            st[i] = FMMLU_EHIP;
+            msg[i] = "worker stream creation failed";
+          }
+          return;
+        }
+        for (int i = next++; i < count; i = next++) {
+          try {
+            b->factors[i] = make_factor(trees[i], xyz[i], normals[i], weights[i], k[i], eta[i], os[i], s);
+          } catch (const Error& e) {
+            st[i] = e.status;
+            msg[i] = e.what();
+          } catch (const std::bad_alloc&) {
+            st[i] = FMMLU_ENOMEM;
+            msg[i] = "host allocation failed";
+          } catch (const std::exception& e) {
+            st[i] = FMMLU_EHIP;
+            msg[i] = e.what();
+          }
+        }
+        (void)hipStreamDestroy(s);
+      };
+      std::vector<std::thread> pool;
+      for (int i = 1; i < nt; ++i) pool.emplace_back(worker);
+      worker();
+      for (auto& th : pool) th.join();
+      for (int i = 0; i < count; ++i)
+        if (st[i] != FMMLU_OK) throw Error(st[i], "problem " + std::to_string(i) + ": " + msg[i]);
+      b->offsets.assign(count + 1, 0);
+      std::vector<FactorImpl*> fs(count);
+      for (int i = 0; i < count; ++i) {
+        b->offsets[i + 1] = b->offsets[i] + b->factors[i]->f.n;
+        fs[i] = &b->factors[i]->f;
+      }
+      b->solver.init(fs, b->offsets);
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    *out = b;
+  });
+}
+
+fmmlu_status fmmlu_batch_info(fmmlu_batch_h b, int32_t* count, int64_t* offsets) {
+  if (!b) return fail(FMMLU_ESTATE, "batch is NULL");
+  if (count) *count = (int32_t)b->factors.size();
+  if (offsets) std::copy(b->offsets.begin(), b->offsets.end(), offsets);
+  return FMMLU_OK;
+}
+
+fmmlu_status fmmlu_batch_factor(fmmlu_batch_h b, int32_t i, fmmlu_factor_h* out) {
+  if (!b) return fail(FMMLU_ESTATE, "batch is NULL");
+  if (!out) return fail(FMMLU_EINVAL, "out is NULL");
+  if (i < 0 || i >= (int32_t)b->factors.size()) return fail(FMMLU_EINVAL, "index out of range");
+  *out = b->factors[i];
+  return FMMLU_OK;
+}
+
+fmmlu_status fmmlu_batch_solve(fmmlu_batch_h b, const void* rhs, void* x, int32_t adjoint, void* hip_stream) {
+  if (!b) return fail(FMMLU_ESTATE, "batch is NULL");
+  if (!rhs || !x) return fail(FMMLU_EINVAL, "vector pointer is NULL");
+  return guarded([&] {
+    b->solver.solve(static_cast<const zd*>(rhs), static_cast<zd*>(x), adjoint != 0,
+                    static_cast<hipStream_t>(hip_stream));
+  });
+}
+
+void fmmlu_batch_destroy(fmmlu_batch_h b) { delete b; }
 
 fmmlu_status fmmlu_solve(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs, void* hip_stream) {
   if (!f) return fail(FMMLU_ESTATE, "factor is NULL");

@@ -596,6 +596,7 @@ void dense_inverse_batch(const zd* A, int64_t n, int64_t count, zd* out, hipStre
 // ------------------------------------------------------------------------------------------
 void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
                         hipStream_t st) {
+  const ActiveFactorization active;
   auto t0 = Clock::now();
   n = tree.n;
   info = fmmlu_info{};

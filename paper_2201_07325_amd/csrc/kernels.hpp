@@ -207,6 +207,12 @@ struct GjCoopTask {
 };
 void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st);
 int gj_coop_capacity(int nmax);
+// marks a factorization in progress for the lifetime of the object (cooperative launches are
+// serialised while more than one is active)
+struct ActiveFactorization {
+  ActiveFactorization();
+  ~ActiveFactorization();
+};
 void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st);
 // W (nb x n) = A[J, :] with J = [j0, j0+nb)
 void launch_gj_copyrow(const GjTask* tasks, int ntasks, int j0, int nmax, zd* const* W,

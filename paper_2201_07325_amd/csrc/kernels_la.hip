@@ -8,6 +8,9 @@
 
 #include "kernels.hpp"
 
+#include <atomic>
+#include <mutex>
+
 namespace fmmlu {
 
 namespace {
@@ -1281,29 +1284,59 @@ void launch_cpqr(const CpqrTask* tasks, int ntasks, int mmax, double eps, hipStr
   FMMLU_HIP(hipGetLastError());
 }
 
+// While several factorizations run at once (on several host threads and streams), at most one
+// cooperative kernel may be in flight: two partially resident cooperative grids could each
+// wait for the other's compute units. The launch then holds a process-wide lock until the
+// kernel has finished.
+namespace {
+std::atomic<int> g_active_factorizations{0};
+std::mutex g_coop_mutex;
+
+template <class F>
+void coop_launch(F&& launch, hipStream_t st) {
+  if (g_active_factorizations.load() > 1) {
+    std::lock_guard<std::mutex> lk(g_coop_mutex);
+    launch();
+    FMMLU_HIP(hipStreamSynchronize(st));
+  } else {
+    launch();
+  }
+}
+}  // namespace
+
+ActiveFactorization::ActiveFactorization() { ++g_active_factorizations; }
+ActiveFactorization::~ActiveFactorization() { --g_active_factorizations; }
+
 void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStream_t st) {
   if (ntasks <= 0) return;
   if (wmax <= 1) {
     hipLaunchKernelGGL(gj_panel_kernel, dim3(ntasks, 1), dim3(kGjPanelRows), 0, st, tasks, j0);
   } else {
     void* args[] = {(void*)&tasks, (void*)&j0};
-    FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_panel_kernel), dim3(ntasks, wmax),
-                                         dim3(kGjPanelRows), args, 0, st));
+    coop_launch(
+        [&]() {
+          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_panel_kernel), dim3(ntasks, wmax),
+                                               dim3(kGjPanelRows), args, 0, st));
+        },
+        st);
   }
   FMMLU_HIP(hipGetLastError());
 }
 
 void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st) {
   if (ntasks <= 0 || nwg_total <= 0) return;
+  if (nmax > 512) throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
   void* args[] = {(void*)&tasks, (void*)&ntasks};
-  if (nmax <= 256)
-    FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<256>), dim3((unsigned)nwg_total),
-                                         dim3(256), args, 0, st));
-  else if (nmax <= 512)
-    FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<512>), dim3((unsigned)nwg_total),
-                                         dim3(512), args, 0, st));
-  else
-    throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
+  coop_launch(
+      [&]() {
+        if (nmax <= 256)
+          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<256>),
+                                               dim3((unsigned)nwg_total), dim3(256), args, 0, st));
+        else
+          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<512>),
+                                               dim3((unsigned)nwg_total), dim3(512), args, 0, st));
+      },
+      st);
   FMMLU_HIP(hipGetLastError());
 }
 
