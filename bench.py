@@ -56,6 +56,49 @@ def cpu_baseline(n_sample=2500):
             "sample": f"graded ellipsoid n={n_sample} (same recipe, seed 2), tree+factor+solve in {dt:.1f} s"}
 
 
+def batched_leg(solves=20):
+    """64 independent scatterers (spheres and ellipsoids, seed 3, sizes 2,000-20,000, k in
+    [1, 8], eta = k, eps = 1e-5): trees + concurrent factorization timed once, then batched
+    fwd+adj solves (one graph replay per direction for all problems)."""
+    import torch
+    import synth
+    import paper_2201_07325_amd as fm
+    surfs = synth.scatterer_batch()
+    probs = [(s.points, s.normals, s.weights, s.k, s.eta) for s in surfs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch = fm.FactorBatch(probs, eps=1e-5)
+    torch.cuda.synchronize()
+    t_fac = time.perf_counter() - t0
+    b = np.concatenate([np.sqrt(s.weights) * synth.point_source_data(
+        s.points, s.k, src=tuple(np.array([0.1, 0.2, 0.3]) * np.array(s.meta["axes"]))) for s in surfs])
+    bd = torch.as_tensor(b).cuda()
+    for _ in range(3):
+        batch.solve(bd)
+        batch.solve(bd, adjoint=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(solves):
+        ev0.record()
+        batch.solve(bd)
+        batch.solve(bd, adjoint=True)
+        ev1.record()
+        ev1.synchronize()
+        times.append(ev0.elapsed_time(ev1) / 1e3)
+    x = batch.solve(bd)
+    worst = 0.0
+    for i in range(0, batch.count, 8):  # every eighth problem: exact matvec residual
+        lo, hi = int(batch.offsets[i]), int(batch.offsets[i + 1])
+        r = batch.factor(i).matvec(x[lo:hi].contiguous()) - bd[lo:hi]
+        worst = max(worst, float(torch.linalg.norm(r) / torch.linalg.norm(bd[lo:hi])))
+    return {"workload": "64 scatterers (spheres/ellipsoids, axes U[0.5,3], n U[2000,20000], k U[1,8], "
+                        "eta=k, seed 3), eps=1e-5, FP64 factors",
+            "n_total": batch.n, "factor_s": t_fac, "unknowns_per_s": batch.n / t_fac,
+            "fwd_adj_batch_solves_per_s": 1.0 / float(np.median(times)),
+            "relres_sampled_max": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,6 +108,7 @@ def main():
     ap.add_argument("--solves", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2500)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -177,6 +221,10 @@ def main():
         "class_ms_per_step": breakdown,
         "roofline": roof,
     }
+    if not args.no_batch:
+        del f, x
+        log("batched scatterers")
+        out["batched"] = batched_leg()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
