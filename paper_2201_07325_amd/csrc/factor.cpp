@@ -1573,6 +1573,7 @@ void FactorImpl::ensure_workspace() {
   const int64_t nblk = (n0 + 255) / 256;
   wtop = arena.alloc_n<zd>((size_t)std::max<int64_t>((int64_t)n0 * (1 + nblk), 1));
   wmv = arena.alloc_n<zd>((size_t)n);
+  wpart = arena.alloc_n<zd>((size_t)matvec_slices(n) * (size_t)n);
 }
 
 void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) {

@@ -110,6 +110,7 @@ struct FactorImpl {
   zd* wmv = nullptr;
   zd* wxr = nullptr;
   zd* wp = nullptr;
+  zd* wpart = nullptr;  // matvec slice partials
   // refinement workspace (allocated on the first refined solve)
   DeviceArena rarena{size_t(1) << 20};
   zd* rbuf = nullptr;

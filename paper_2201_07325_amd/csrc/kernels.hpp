@@ -309,6 +309,9 @@ void launch_farfield(const DevGeom& g, int op, const double* dirs, int64_t ndir,
                      const zd* in, zd* out, zd* part, hipStream_t st);
 
 // ---- exact matvec on the fly ----
-void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, hipStream_t st);
+// part: matvec_slices(n) * n scratch entries (partial sums of source slices)
+constexpr int kMatvecMaxSlices = 16;
+int matvec_slices(int64_t n);
+void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipStream_t st);
 
 }  // namespace fmmlu

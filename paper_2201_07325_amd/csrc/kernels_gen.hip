@@ -9,6 +9,8 @@
 // (consecutive threads -> consecutive rows, coalesced stores).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace fmmlu {
@@ -194,10 +196,12 @@ __global__ void __launch_bounds__(256) block_kernel(DevGeom g, const int64_t* __
 }
 
 // ---------------------------------------------------------------------------------------
-// Exact matvec: each workgroup owns 256 target rows and streams all sources through LDS.
+// Exact matvec: each workgroup owns 256 target rows and streams one slice of the sources
+// through LDS; slices (grid.y) write partial sums that a second pass adds in a fixed order.
 // op 0: y = A~ x; 1: y = A~^H x; 2: y = dA~/dk x; 3: y = dA~/deta x. Vectors in tree order.
-__global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, int op, const zd* __restrict__ x,
-                                                     zd* __restrict__ y) {
+template <int OP>
+__global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __restrict__ x, zd* __restrict__ part,
+                                                     int64_t slice) {
   __shared__ double sp[7][256];
   __shared__ zd sx[256];
   const int64_t n = g.n;
@@ -207,51 +211,53 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, int op, const zd
   double xi[7];
   for (int a = 0; a < 7; ++a) xi[a] = live ? p[a * n + i] : 0.0;
   double are = 0.0, aim = 0.0;
-  for (int64_t j0 = 0; j0 < n; j0 += 256) {
+  const int64_t jbeg = (int64_t)blockIdx.y * slice, jend = min(n, jbeg + slice);
+  for (int64_t j0 = jbeg; j0 < jend; j0 += 256) {
     __syncthreads();
     const int64_t jl = j0 + threadIdx.x;
-    for (int a = 0; a < 7; ++a) sp[a][threadIdx.x] = jl < n ? p[a * n + jl] : 0.0;
-    sx[threadIdx.x] = jl < n ? x[jl] : zd{0.0, 0.0};
+    for (int a = 0; a < 7; ++a) sp[a][threadIdx.x] = jl < jend ? p[a * n + jl] : 0.0;
+    sx[threadIdx.x] = jl < jend ? x[jl] : zd{0.0, 0.0};
     __syncthreads();
-    const int cnt = (int)min<int64_t>(256, n - j0);
+    const int cnt = (int)min<int64_t>(256, jend - j0);
     if (!live) continue;
     for (int jj = 0; jj < cnt; ++jj) {
       const int64_t j = j0 + jj;
       if (j == i) {
-        if (op <= 1) {
+        if (OP <= 1) {
           are += 0.5 * sx[jj].re;
           aim += 0.5 * sx[jj].im;
         }
         continue;
       }
-      double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
-      double r2 = dx * dx + dy * dy + dz * dz;
-      double r = sqrt(r2);
+      const double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double r = sqrt(r2);
+      const double ir = 1.0 / r;
       double s, c;
       sincos(g.k * r, &s, &c);
-      double w = xi[6] * sp[6][jj] * kInv4Pi;
+      const double w = xi[6] * sp[6][jj] * kInv4Pi;
       double vr, vi;
-      if (op == 0) {
-        double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
-        double a = dn, b = g.k * r * dn + g.eta * r2;
-        double f = w / (r2 * r);
+      if (OP == 0) {
+        const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
+        const double a = dn, b = g.k * r * dn + g.eta * r2;
+        const double f = w * ir * ir * ir;
         vr = (c * a + s * b) * f;
         vi = (s * a - c * b) * f;
-      } else if (op == 1) {
+      } else if (OP == 1) {
         // conj(A~[j, i]): target j, source i with normal n_i; d = x_j - x_i = -(dx, dy, dz)
-        double dn = -(dx * xi[3] + dy * xi[4] + dz * xi[5]);
-        double a = dn, b = g.k * r * dn + g.eta * r2;
-        double f = w / (r2 * r);
+        const double dn = -(dx * xi[3] + dy * xi[4] + dz * xi[5]);
+        const double a = dn, b = g.k * r * dn + g.eta * r2;
+        const double f = w * ir * ir * ir;
         vr = (c * a + s * b) * f;
         vi = -(s * a - c * b) * f;
-      } else if (op == 2) {
-        double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
-        double a = g.k * dn + g.eta * r;
-        double f = w / r;
+      } else if (OP == 2) {
+        const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
+        const double a = g.k * dn + g.eta * r;
+        const double f = w * ir;
         vr = c * a * f;
         vi = s * a * f;
       } else {
-        double f = w / r;
+        const double f = w * ir;
         vr = s * f;
         vi = -c * f;
       }
@@ -260,7 +266,16 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, int op, const zd
       aim += vr * xv.im + vi * xv.re;
     }
   }
-  if (live) y[i] = zd{are, aim};
+  if (live) part[(int64_t)blockIdx.y * n + i] = zd{are, aim};
+}
+
+__global__ void __launch_bounds__(256) matvec_sum_kernel(const zd* __restrict__ part, int64_t n, int nslice,
+                                                         zd* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  zd s = part[i];
+  for (int q = 1; q < nslice; ++q) s = zadd(s, part[(int64_t)q * n + i]);
+  y[i] = s;
 }
 
 }  // namespace
@@ -291,10 +306,26 @@ void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, hipStream_t st) {
+int matvec_slices(int64_t n) {
+  const int64_t nbt = (n + 255) / 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMatvecMaxSlices, 2048 / std::max<int64_t>(nbt, 1)));
+}
+
+void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipStream_t st) {
   if (g.n <= 0) return;
-  hipLaunchKernelGGL(matvec_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), 0, st, g, op,
-                     x, y);
+  const int ns = matvec_slices(g.n);
+  const int64_t slice = ((g.n + ns - 1) / ns + 255) / 256 * 256;
+  const dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)ns), b(256);
+  if (op == 0)
+    hipLaunchKernelGGL(matvec_kernel<0>, grid, b, 0, st, g, x, part, slice);
+  else if (op == 1)
+    hipLaunchKernelGGL(matvec_kernel<1>, grid, b, 0, st, g, x, part, slice);
+  else if (op == 2)
+    hipLaunchKernelGGL(matvec_kernel<2>, grid, b, 0, st, g, x, part, slice);
+  else
+    hipLaunchKernelGGL(matvec_kernel<3>, grid, b, 0, st, g, x, part, slice);
+  FMMLU_HIP(hipGetLastError());
+  hipLaunchKernelGGL(matvec_sum_kernel, dim3((unsigned)((g.n + 255) / 256)), b, 0, st, part, g.n, ns, y);
   FMMLU_HIP(hipGetLastError());
 }
 
