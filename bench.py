@@ -56,6 +56,28 @@ def cpu_baseline(n_sample=2500):
             "sample": f"graded ellipsoid n={n_sample} (same recipe, seed 2), tree+factor+solve in {dt:.1f} s"}
 
 
+def fp32_leg(s, bd, steps):
+    """Same workload with complex float32 tiles and factors (float64 ID pivoting and pivot
+    inverses), each step followed by float64 FGMRES refinement to 1e-10 with the exact matvec:
+    n / (tree + factor + refined solve)."""
+    import torch
+    import paper_2201_07325_amd as fm
+    times, its, rel = [], 0, 0.0
+    f = None
+    for k in range(steps + 1):  # the first pass warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t = fm.Tree(s.points, 64)
+        f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=s.eps, tree=t, precision=1)
+        x, its, rel = f.solve_refined(bd, tol=1e-10, maxit=50, raise_on_fail=False)
+        torch.cuda.synchronize()
+        if k > 0:
+            times.append(time.perf_counter() - t0)
+    dt = float(np.mean(times))
+    return {"unknowns_per_s": s.n / dt, "ms_per_step": dt * 1e3, "refine_iterations": its, "relres": rel,
+            "tol": 1e-10, "factor_bytes": f.info()["factor_bytes"]}
+
+
 def batched_leg(solves=20):
     """64 independent scatterers (spheres and ellipsoids, seed 3, sizes 2,000-20,000, k in
     [1, 8], eta = k, eps = 1e-5): trees + concurrent factorization timed once, then batched
@@ -221,6 +243,8 @@ def main():
         "class_ms_per_step": breakdown,
         "roofline": roof,
     }
+    log("float32 factors + float64 refinement")
+    out["fp32_refine"] = fp32_leg(s, bd, args.steps)
     if not args.no_batch:
         del f, x
         log("batched scatterers")

@@ -76,7 +76,8 @@ fmmlu_opts checked_opts(fmmlu_tree_h t, const double* xyz, const double* normals
   if (!(o.proxy_radius >= 1.5 && o.proxy_radius <= 10.0)) throw Error(FMMLU_EINVAL, "proxy_radius must be in [1.5, 10]");
   if (o.proxy_min_points < 1) throw Error(FMMLU_EINVAL, "proxy_min_points must be >= 1");
   if (o.id_route < 0 || o.id_route > 2) throw Error(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
-  if (o.precision != FMMLU_FP64) throw Error(FMMLU_EINVAL, "only FMMLU_FP64 is available in this build");
+  if (o.precision != FMMLU_FP64 && o.precision != FMMLU_FP32)
+    throw Error(FMMLU_EINVAL, "precision must be FMMLU_FP64 or FMMLU_FP32");
   const int64_t n = t->t.n;
   check_finite(xyz, 3 * n, "points");
   check_finite(normals, 3 * n, "normals");

@@ -24,6 +24,19 @@ struct alignas(8) zf {
 };
 
 __host__ __device__ inline zd zmake(double r, double i) { return zd{r, i}; }
+// storage conversions between complex float64 and float32
+__host__ __device__ inline zd widen(zd v) { return v; }
+__host__ __device__ inline zd widen(zf v) { return zd{(double)v.re, (double)v.im}; }
+template <class T>
+__host__ __device__ inline T narrow(zd v);
+template <>
+__host__ __device__ inline zd narrow<zd>(zd v) {
+  return v;
+}
+template <>
+__host__ __device__ inline zf narrow<zf>(zd v) {
+  return zf{(float)v.re, (float)v.im};
+}
 __host__ __device__ inline zd zadd(zd a, zd b) { return zd{a.re + b.re, a.im + b.im}; }
 __host__ __device__ inline zd zsub(zd a, zd b) { return zd{a.re - b.re, a.im - b.im}; }
 __host__ __device__ inline zd zmul(zd a, zd b) {

@@ -247,7 +247,7 @@ struct GemmBatch {
   std::vector<GemmTask> tasks;
   std::vector<GemmSeg> segs;
   int64_t units = 0;
-  void add(zd* C, int ldc, int M, int N, const int32_t* rmap, const int32_t* cmap,
+  void add(void* C, int ldc, int M, int N, const int32_t* rmap, const int32_t* cmap,
            const std::vector<GemmSeg>& s, double are, double aim, double beta) {
     if (M <= 0 || N <= 0) return;
     GemmTask t{};
@@ -288,7 +288,7 @@ struct GemmBatch {
     segs.push_back(GemmSeg{A, B, lda, ldb, K, 0});
     tasks.push_back(t);
   }
-  void add1(zd* C, int ldc, int M, int N, const zd* A, int lda, const zd* B, int ldb, int K,
+  void add1(void* C, int ldc, int M, int N, const zd* A, int lda, const zd* B, int ldb, int K,
             double are, double beta) {
     if (K <= 0) {
       if (beta == 1.0) return;
@@ -304,9 +304,9 @@ struct GemmBatch {
     dt = sg.up(tasks);
     ds = sg.up(segs);
   }
-  void launch(Stage& sg, int opA) {
+  void launch(Stage& sg, int opA, bool c32 = false) {
     if (tasks.empty()) return;
-    launch_gemm(opA, dt, (int)tasks.size(), units, ds, sg.st);
+    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.st);
   }
   void run(Stage& sg, int opA) {
     prepare(sg);
@@ -417,7 +417,7 @@ void batched_inverse_pipeline(Stage& sg, std::vector<GjTask>& tasks, const std::
     for (auto& pg : pgroups) launch_gj_panel(pg.dt, pg.count, j0, pg.wmax, sg.st);
     launch_gj_swapcopy(dt, nt, j0, nmax, dW, sg.st);
     if (sidx[step][1] > 0)
-      launch_gemm(0, all.dt + sidx[step][0], (int)sidx[step][1], sidx[step][3], all.ds, sg.st);
+      launch_gemm(0, all.dt + sidx[step][0], (int)sidx[step][1], sidx[step][3], all.ds, false, sg.st);
   }
   launch_gj_unpermute(dt, nt, nmax, dout, dwork, sg.st);
   for (auto& t : tasks) sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
@@ -599,6 +599,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   const ActiveFactorization active;
   auto t0 = Clock::now();
   n = tree.n;
+  f32 = opts.precision == FMMLU_FP32;
+  const size_t te = f32 ? sizeof(zf) : sizeof(zd);  // bytes per stored tile or factor entry
   info = fmmlu_info{};
   info.n = n;
   info.nlevels = tree.nlevels;
@@ -648,7 +650,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   int64_t live_total = n;
 
   // tiles of the previous level (for assembly)
-  zd* prev_pool = nullptr;
+  void* prev_pool = nullptr;
   std::unordered_map<int64_t, int64_t> prev_pair;  // key o1*nprev+o2 -> offset
   std::vector<Owner> prev_own;
   bool first_level = true;
@@ -701,17 +703,17 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         pool_elems += (int64_t)own[i].act.size() * own[p].act.size();
       }
     }
-    zd* pool = nullptr;
+    void* pool = nullptr;
     {
-      size_t bytes = std::max<size_t>(1, (size_t)pool_elems) * sizeof(zd);
+      size_t bytes = std::max<size_t>(1, (size_t)pool_elems) * te;
       hipError_t e = hipMalloc(&pool, bytes);
       if (e != hipSuccess) {
         (void)hipGetLastError();
         throw Error(FMMLU_ENOMEM, "tile pool allocation failed (" + std::to_string(bytes) + " bytes)");
       }
     }
-    info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)(arena.held() + pool_elems * 16));
-    info.bytes_tiles += (double)pool_elems * 16.0;
+    info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)(arena.held() + pool_elems * (int64_t)te));
+    info.bytes_tiles += (double)pool_elems * (double)te;
     ht.mark(0);
     // ---- assemble: slot/idx maps, dof lists, source tables
     {
@@ -780,9 +782,9 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int64_t* ddof = sg.up(dof);
         AsmSrc* dtab = sg.up(table);
         ProfScope ps(prof, KC_ASSEMBLE);
-        launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, pool, st);
+        launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, f32, pool, f32, st);
       }
-      prof.bytes[KC_ASSEMBLE] += 16.0 * (double)pool_elems * (first_level ? 1.0 : 2.0);
+      prof.bytes[KC_ASSEMBLE] += (double)te * (double)pool_elems * (first_level ? 1.0 : 2.0);
       sg.sync_reset();
       if (prev_pool) FMMLU_HIP(hipFree(prev_pool));
       prev_pool = nullptr;
@@ -933,7 +935,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         IdTask* didt = sg.up(idt);
         QSeg* dq = qsegs.empty() ? nullptr : sg.up(qsegs);
         ProfScope ps(prof, KC_IDMAT);
-        launch_build_idmatrix(g, didt, nb, units, dq, act_dev, pool, st);
+        launch_build_idmatrix(g, didt, nb, units, dq, act_dev, pool, f32, st);
       }
       for (auto& bp : plan) prof.bytes[KC_IDMAT] += 16.0 * (double)bp.rows * bp.m;
       // ---- 2. greedy CPQR of M: through the Gram matrix (pivoted Cholesky of M^H M) when
@@ -1042,6 +1044,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int s, r, nsn;
         zd *Ccol, *Crow;
         zd* Up;  // X_RR^{-1} X_{R (S u N)} (r x nsn), scratch; stored transposed in the factor
+        zd* Xi64;  // X_RR^{-1} in float64
         FactorBox* fb;
       };
       std::vector<ElimPlan> ep;
@@ -1094,14 +1097,16 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           for (int j = 0; j < e.s; ++j) fb.skel_orig[j] = order[B.act[pv[j]]];
           std::sort(fb.skel_orig.begin(), fb.skel_orig.end());
           SolveBox& d = fb.dev;
-          d.T = e.s ? arena.alloc_n<zd>((size_t)e.s * e.r) : nullptr;
-          d.Xi = arena.alloc_n<zd>((size_t)e.r * e.r);
-          d.Lp = e.nsn ? arena.alloc_n<zd>((size_t)e.nsn * e.r) : nullptr;
-          d.UpT = e.nsn ? arena.alloc_n<zd>((size_t)e.r * e.nsn) : nullptr;
+          d.T = e.s ? arena.alloc(te * (size_t)e.s * e.r) : nullptr;
+          d.Xi = arena.alloc(te * (size_t)e.r * e.r);
+          d.Lp = e.nsn ? arena.alloc(te * (size_t)e.nsn * e.r) : nullptr;
+          d.UpT = e.nsn ? arena.alloc(te * (size_t)e.r * e.nsn) : nullptr;
+          // the inverse itself is formed in float64 (scratch when the factors are float32)
+          e.Xi64 = f32 ? sg.dev.alloc_n<zd>((size_t)e.r * e.r) : static_cast<zd*>(const_cast<void*>(d.Xi));
           d.r = e.r;
           d.s = e.s;
           d.nsn = e.nsn;
-          info.factor_bytes += 16 * ((int64_t)e.s * e.r + (int64_t)e.r * e.r + 2 * (int64_t)e.nsn * e.r);
+          info.factor_bytes += (int64_t)te * ((int64_t)e.s * e.r + (int64_t)e.r * e.r + 2 * (int64_t)e.nsn * e.r);
           // cross gathers
           const int mn = bp.m + bp.nN;
           e.Ccol = sg.dev.alloc_n<zd>((size_t)mn * bp.m);
@@ -1145,7 +1150,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         NSeg* dns = nsegs.empty() ? nullptr : sg.up(nsegs);
         {
           ProfScope ps(prof, KC_ELIM);
-          launch_gather_cross(dcross, ne, cunits, dns, pool, st);
+          launch_gather_cross(dcross, ne, cunits, dns, pool, f32, st);
         }
         // E/F transforms (Section 4.1). Ccol = A[(R,S,N),(S,R)], Crow = A[(S,R),(R,S,N)]:
         //   Ccol[:, s:m]      -= Ccol[:, 0:s] T        (A_{.R} - A_{.S} T)
@@ -1187,13 +1192,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             t.n = e.r;
             t.lda = plan[e.pi].m + plan[e.pi].nN;
             gt.push_back(t);
-            outs.push_back(const_cast<zd*>(e.fb->dev.Xi));
+            outs.push_back(e.Xi64);
           }
           batched_inverse(sg, gt, outs, info_dev, KC_INV);
         }
         // panels: Lp = X_{SN,R} Xi ; Up = Xi X_{R,SN}; T compacted into the factor
         {
-          GemmBatch gp;
+          GemmBatch gp, gl;  // gl: Lp straight into factor storage (float32 C when f32)
           std::vector<CopyTask> cps, trs;
           int64_t cu = 0, tu = 0;
           for (auto& e : ep) {
@@ -1204,24 +1209,30 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
               const zd* XsnR = e.Ccol + (int64_t)e.s * mn + e.r;         // X_{(S u N) R}
               const zd* XRsn = e.Crow + e.s + (int64_t)e.r * m;          // X_{R (S u N)}
               e.Up = sg.dev.alloc_n<zd>((size_t)e.r * e.nsn);
-              gp.add1(const_cast<zd*>(d.Lp), e.nsn, e.nsn, e.r, XsnR, mn, d.Xi, e.r, e.r, 1.0, 0.0);
-              gp.add1(e.Up, e.r, e.r, e.nsn, d.Xi, e.r, XRsn, m, e.r, 1.0, 0.0);
-              trs.push_back(CopyTask{e.Up, const_cast<zd*>(d.UpT), e.r, e.nsn, e.r, e.nsn, tu});
+              gl.add1(const_cast<void*>(d.Lp), e.nsn, e.nsn, e.r, XsnR, mn, e.Xi64, e.r, e.r, 1.0, 0.0);
+              gp.add1(e.Up, e.r, e.r, e.nsn, e.Xi64, e.r, XRsn, m, e.r, 1.0, 0.0);
+              trs.push_back(CopyTask{e.Up, const_cast<void*>(d.UpT), e.r, e.nsn, e.r, e.nsn, tu});
               tu += units64(e.r, e.nsn);
             }
             if (e.s > 0) {
-              CopyTask c{bp.T, const_cast<zd*>(d.T), e.s, e.r, m, e.s, cu};
+              CopyTask c{bp.T, const_cast<void*>(d.T), e.s, e.r, m, e.s, cu};
               cu += units64(e.s, e.r);
               cps.push_back(c);
             }
+            if (f32) {
+              cps.push_back(CopyTask{e.Xi64, const_cast<void*>(d.Xi), e.r, e.r, e.r, e.r, cu});
+              cu += units64(e.r, e.r);
+            }
           }
           gp.prepare(sg);
+          gl.prepare(sg);
           CopyTask* dcp = cps.empty() ? nullptr : sg.up(cps);
           CopyTask* dtr = trs.empty() ? nullptr : sg.up(trs);
           ProfScope ps(prof, KC_ELIM);
           gp.launch(sg, 0);
-          if (dcp) launch_copy(dcp, (int)cps.size(), cu, st);
-          if (dtr) launch_transpose(dtr, (int)trs.size(), tu, st);
+          gl.launch(sg, 0, f32);
+          if (dcp) launch_copy(dcp, (int)cps.size(), cu, f32, st);
+          if (dtr) launch_transpose(dtr, (int)trs.size(), tu, f32, st);
           for (auto& e : ep) prof.flops[KC_ELIM] += 8.0 * 2.0 * (double)e.nsn * e.r * e.r;
         }
         ht.mark(4);
@@ -1277,17 +1288,18 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             const int N = (c0.b == 0) ? e0.s : (int)own[o2].live.size();
             const int32_t* rmap = (c0.a == 0) ? bp0.perm : own[o1].live_dev;
             const int32_t* cmap = (c0.b == 0) ? bp0.perm : own[o2].live_dev;
-            gs.add(pool + c0.toff, (int)own[o1].act.size(), M, N, rmap, cmap, segs, -1.0, 0.0, 1.0);
+            gs.add(static_cast<char*>(pool) + (size_t)c0.toff * te, (int)own[o1].act.size(), M, N, rmap, cmap, segs,
+                   -1.0, 0.0, 1.0);
             double kk = 0;
             for (auto& sgm : segs) kk += sgm.K;
             prof.flops[KC_SCHUR] += 8.0 * M * N * kk;
-            prof.bytes[KC_SCHUR] += 32.0 * M * N;
+            prof.bytes[KC_SCHUR] += 2.0 * (double)te * M * N;
             i = j;
           }
           for (auto& e : ep) prof.bytes[KC_SCHUR] += 32.0 * (double)e.nsn * e.r;
           gs.prepare(sg);
           ProfScope ps(prof, KC_SCHUR);
-          gs.launch(sg, 0);
+          gs.launch(sg, 0, f32);
         }
         // flops of this phase
         for (auto& e : ep) {
@@ -1521,7 +1533,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int64_t* ddof = sg.up(dof);
         AsmSrc* dtab = sg.up(table);
         ProfScope ps(prof, KC_TOP);
-        launch_assemble(g, dt, 1, units64(n0, n0), dslot, didx, ddof, dtab, prev_pool, Att, st);
+        launch_assemble(g, dt, 1, units64(n0, n0), dslot, didx, ddof, dtab, prev_pool, f32, Att, false, st);
       }
       Ainv = arena.alloc_n<zd>((size_t)n0 * n0);
       std::vector<GjTask> gt(1);
@@ -1581,17 +1593,17 @@ void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) 
   launch_permute(bc, wx, order_dev, n, 1, st);
   // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
   for (auto& ph : phases) {
-    launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, ph.rmax, wx, wxr, adj, st);
-    launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, st);
+    launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, ph.rmax, wx, wxr, adj, f32, st);
+    launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, f32, st);
     launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
   }
   // D^{-1} (adjoint D^{-H}): all pivot blocks, then the top block
-  launch_solve_diag(all_boxes, nall, rmax_all, wx, adj, st);
+  launch_solve_diag(all_boxes, nall, rmax_all, wx, adj, f32, st);
   launch_solve_top(Ainv, n0, top_dev, wx, wtop, adj, st);
   // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
-    launch_solve_bpart(it->dboxes, it->dp, it->np, wx, wp, adj, st);
-    launch_solve_bfin(it->dboxes, it->box_end - it->box_begin, it->rmax, wp, wx, adj, st);
+    launch_solve_bpart(it->dboxes, it->dp, it->np, wx, wp, adj, f32, st);
+    launch_solve_bfin(it->dboxes, it->box_end - it->box_begin, it->rmax, wp, wx, adj, f32, st);
   }
   launch_permute(wx, xc, order_dev, n, 0, st);
 }

@@ -86,6 +86,7 @@ struct SolvePhase {
 struct FactorImpl {
   int64_t n = 0;
   double k = 0, eta = 0;
+  bool f32 = false;  // tiles and stored factors in complex float32
   fmmlu_opts opts{};
   int device = 0;
   DeviceArena arena;  // persistent: geometry, factors, top

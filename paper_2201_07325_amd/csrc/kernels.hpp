@@ -43,7 +43,8 @@ struct AsmSrc {
 
 void launch_assemble(const DevGeom& g, const AsmTask* tasks, int ntasks, int64_t nunits,
                      const int32_t* slot, const int32_t* idx, const int64_t* dof,
-                     const AsmSrc* table, const zd* src_pool, zd* dst_pool, hipStream_t st);
+                     const AsmSrc* table, const void* src_pool, bool src32, void* dst_pool, bool dst32,
+                     hipStream_t st);
 
 // ---- ID matrix [A_QB ; A_BQ^T ; proxy outgoing ; proxy incoming] (column-major) ----
 struct QSeg {
@@ -66,7 +67,7 @@ struct IdTask {
   int64_t unit_begin;
 };
 void launch_build_idmatrix(const DevGeom& g, const IdTask* tasks, int ntasks, int64_t nunits,
-                           const QSeg* segs, const int64_t* dof, const zd* pool, hipStream_t st);
+                           const QSeg* segs, const int64_t* dof, const void* pool, bool pool32, hipStream_t st);
 
 // ---- batched complex GEMM with segments and scatter maps ----
 // C[rmap[i], cmap[j]] = beta * C[...] + alpha * sum_s opA(A_s)[i, :] * B_s[:, j]
@@ -79,7 +80,7 @@ struct GemmSeg {
   int32_t ishift;  // opA N only: > 0 reads A - E with E[ishift - 1 + k, k] = 1 (shifted identity)
 };
 struct GemmTask {
-  zd* C;
+  void* C;  // complex float64, or float32 for launches with c32
   const int32_t* rmap;  // may be null (identity)
   const int32_t* cmap;  // may be null (identity)
   int32_t M, N, ldc;
@@ -89,7 +90,7 @@ struct GemmTask {
   int64_t part_stride;
   int64_t unit_begin;              // prefix sum of kGemmTile^2 output blocks (times K chunks)
 };
-void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
+void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st);
 
 // ---- Householder panel factorization (unpivoted QR) ----
@@ -143,7 +144,7 @@ struct CrossTask {
   int64_t unit_begin;
 };
 void launch_gather_cross(const CrossTask* tasks, int ntasks, int64_t nunits, const NSeg* segs,
-                         const zd* pool, hipStream_t st);
+                         const void* pool, bool pool32, hipStream_t st);
 
 // ---- sum of split-K partials: out[e] = sum_k part[k*stride + e], e < count ----
 struct SumTask {
@@ -237,23 +238,24 @@ void launch_extract_r(const ExtractTask* tasks, int ntasks, int mmax, hipStream_
 // ---- copy a sub-block (column-major) ----
 struct CopyTask {
   const zd* src;
-  zd* dst;
+  void* dst;  // complex float64, or float32 with dst32
   int32_t rows, cols, lds, ldd;
   int64_t unit_begin;
 };
-void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
+void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, bool dst32, hipStream_t st);
 // dst[j + i*ldd] = src[i + j*lds] (rows x cols source); units of 64 x 64
-void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
+void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, bool dst32, hipStream_t st);
 
 // ---- solve sweeps ----
 struct SolveBox {
   const int32_t* R;   // tree positions, r
   const int32_t* S;   // s
   const int32_t* SN;  // s + nN (S first)
-  const zd* T;        // s x r, ld = s
-  const zd* Xi;       // r x r inverse pivot block
-  const zd* Lp;       // L = X_{(S u N) R} X_RR^{-1}: (s+nN) x r, ld = s+nN
-  const zd* UpT;      // U^T with U = X_RR^{-1} X_{R (S u N)}: (s+nN) x r, ld = s+nN
+  // factors, complex float64 or float32 (the factorization's storage precision)
+  const void* T;      // s x r, ld = s
+  const void* Xi;     // r x r inverse pivot block
+  const void* Lp;     // L = X_{(S u N) R} X_RR^{-1}: (s+nN) x r, ld = s+nN
+  const void* UpT;    // U^T with U = X_RR^{-1} X_{R (S u N)}: (s+nN) x r, ld = s+nN
   int32_t r, s, nsn, nchunk;  // nchunk: backward partial chunks
   int64_t y_off;      // this box's outputs in the forward scatter buffer
   int64_t xr_off;     // this box's x_R copy in the phase buffer
@@ -264,21 +266,21 @@ struct SweepTask {
   int32_t box, k0, kn, chunk;
 };
 // forward, per box: x_R -= op(T) x_S (T^T, adjoint T^H); copy to XR
-void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint,
+void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint, bool f32,
                      hipStream_t st);
 // forward, per task: y = op(P) x_R on a row chunk (Lp, adjoint Up^H)
 void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
-                    zd* y, int adjoint, hipStream_t st);
+                    zd* y, int adjoint, bool f32, hipStream_t st);
 // scatter: x[dst[d]] -= sum_{q in [ptr[d], ptr[d+1])} y[src[q]]
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st);
 // diagonal: xR = Xi xR (adjoint: Xi^H xR), all boxes
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, hipStream_t st);
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, bool f32, hipStream_t st);
 // backward, per task: partial of op(P) x_SN over a column chunk (Up, adjoint Lp^H)
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
-                        int adjoint, hipStream_t st);
+                        int adjoint, bool f32, hipStream_t st);
 // backward, per box: x_R -= sum of partials; x_S -= op(T) x_R (T, adjoint conj(T))
-void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint,
+void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint, bool f32,
                        hipStream_t st);
 // top block: x[top] = Ainv x[top] (or Ainv^H); tmp >= n0 * (1 + ceil(n0 / 256)) entries
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,

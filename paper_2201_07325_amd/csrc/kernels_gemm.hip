@@ -1,4 +1,6 @@
-// Batched complex float64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64).
+// Batched complex GEMM on the matrix cores: float64 (v_mfma_f64_16x16x4f64) for float64
+// C, float32 (v_mfma_f32_16x16x4f32, operands rounded to float32 as they are staged) for
+// float32 C. Operands A and B are complex float64 in memory.
 //
 //   C[rmap[i], cmap[j]] = beta C[...] + alpha * sum_s opA(A_s)[i, :] B_s[:, j]
 //
@@ -8,7 +10,8 @@
 // complex block and k-step of 4). K is staged through LDS in steps of 16, as separate real
 // and imaginary planes, with the next step's global loads issued before the current step's
 // MFMAs. MFMA operand layout (16 x 16 x 4, float64): lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16], and holds D[l / 16 + 4 r][l % 16] in accumulator element r.
+// B[l / 16][l % 16]; it holds D[l / 16 + 4 r][l % 16] (float64) or D[4 (l / 16) + r][l % 16]
+// (float32) in accumulator element r.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -18,6 +21,24 @@ namespace fmmlu {
 namespace {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <class CT>
+struct Mfma;
+template <>
+struct Mfma<zd> {
+  using R = double;
+  using V = dbl4;
+  __device__ static V mma(R a, R b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<zf> {
+  using R = float;
+  using V = flt4;
+  __device__ static V mma(R a, R b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
 
 template <class Task>
 __device__ inline int find_unit_task(const Task* __restrict__ t, int n, int64_t u) {
@@ -35,10 +56,12 @@ __device__ inline int find_unit_task(const Task* __restrict__ t, int n, int64_t 
 constexpr int BM = kGemmTile, BN = kGemmTile, BK = 16;
 constexpr int LDP = BM + 4;  // padded LDS row (doubles)
 
-template <int OPA>
+template <int OPA, class CT>
 __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks,
                                                          const GemmSeg* __restrict__ segs) {
-  __shared__ double Asr[BK][LDP], Asi[BK][LDP], Bsr[BK][LDP], Bsi[BK][LDP];
+  using M = Mfma<CT>;
+  using R = typename M::R;
+  __shared__ R Asr[BK][LDP], Asi[BK][LDP], Bsr[BK][LDP], Bsi[BK][LDP];
   const int64_t u = blockIdx.x;
   const GemmTask t = tasks[find_unit_task(tasks, ntasks, u)];
   int64_t lu = u - t.unit_begin;
@@ -49,13 +72,13 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
   const int row0 = (int)(lu % nbm) * BM, col0 = (int)(lu / nbm) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wavefront quarter
-  dbl4 cr[2][2], ci[2][2];
+  typename M::V cr[2][2], ci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cr[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
-      ci[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      cr[a][b] = typename M::V{0, 0, 0, 0};
+      ci[a][b] = typename M::V{0, 0, 0, 0};
     }
   for (int sidx = 0; sidx < t.nseg; ++sidx) {
     const GemmSeg sg = segs[t.seg_begin + sidx];
@@ -106,11 +129,11 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
           kk = e % BK;
           i = e / BK;
         }
-        Asr[kk][i] = ra[q].re;
-        Asi[kk][i] = ra[q].im;
+        Asr[kk][i] = (R)ra[q].re;
+        Asi[kk][i] = (R)ra[q].im;
         const int kb = e % BK, j = e / BK;
-        Bsr[kb][j] = rb[q].re;
-        Bsi[kb][j] = rb[q].im;
+        Bsr[kb][j] = (R)rb[q].re;
+        Bsi[kb][j] = (R)rb[q].im;
       }
     };
     load(kbeg);
@@ -122,7 +145,7 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
         const int kr = ks + (lane >> 4), cl = lane & 15;
-        double ar[2], ai[2], an[2], br[2], bi[2];
+        R ar[2], ai[2], an[2], br[2], bi[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           ar[a] = Asr[kr][wr + 16 * a + cl];
@@ -138,46 +161,50 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
-            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cr[a][b], 0, 0, 0);
-            cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[a], bi[b], cr[a][b], 0, 0, 0);
-            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], ci[a][b], 0, 0, 0);
-            ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], ci[a][b], 0, 0, 0);
+            cr[a][b] = M::mma(ar[a], br[b], cr[a][b]);
+            cr[a][b] = M::mma(an[a], bi[b], cr[a][b]);
+            ci[a][b] = M::mma(ar[a], bi[b], ci[a][b]);
+            ci[a][b] = M::mma(ai[a], br[b], ci[a][b]);
           }
       }
     }
   }
   const zd alpha{t.alpha_re, t.alpha_im};
-  zd* Cb = t.C + (int64_t)kc * t.part_stride;
+  CT* Cb = static_cast<CT*>(t.C) + (int64_t)kc * t.part_stride;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = row0 + wr + 16 * a + (lane >> 4) + 4 * r;
+        const int i = row0 + wr + 16 * a + M::row(lane, r);
         const int j = col0 + wc + 16 * b + (lane & 15);
         if (i >= t.M || j >= t.N) continue;
         const int ri = t.rmap ? t.rmap[i] : i;
         const int cj = t.cmap ? t.cmap[j] : j;
-        zd* c = Cb + ri + (int64_t)cj * t.ldc;
-        zd v = zmul(alpha, zd{cr[a][b][r], ci[a][b][r]});
-        if (t.beta != 0.0) v = zadd(v, zscale(*c, t.beta));
-        *c = v;
+        CT* c = Cb + ri + (int64_t)cj * t.ldc;
+        zd v = zmul(alpha, zd{(double)cr[a][b][r], (double)ci[a][b][r]});
+        if (t.beta != 0.0) v = zadd(v, zscale(widen(*c), t.beta));
+        *c = narrow<CT>(v);
       }
 }
 
 }  // namespace
 
-void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs,
+void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
   const dim3 g((unsigned)nunits), b(256);
-  if (opA == 0)
-    hipLaunchKernelGGL(zgemm_mfma_kernel<0>, g, b, 0, st, tasks, ntasks, segs);
-  else if (opA == 1)
-    hipLaunchKernelGGL(zgemm_mfma_kernel<1>, g, b, 0, st, tasks, ntasks, segs);
-  else
-    hipLaunchKernelGGL(zgemm_mfma_kernel<2>, g, b, 0, st, tasks, ntasks, segs);
+  if (c32) {
+    if (opA != 0) throw Error(FMMLU_EINVAL, "float32 GEMM takes opA = N");
+    hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf>), g, b, 0, st, tasks, ntasks, segs);
+  } else if (opA == 0) {
+    hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd>), g, b, 0, st, tasks, ntasks, segs);
+  } else if (opA == 1) {
+    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd>), g, b, 0, st, tasks, ntasks, segs);
+  } else {
+    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd>), g, b, 0, st, tasks, ntasks, segs);
+  }
   FMMLU_HIP(hipGetLastError());
 }
 

@@ -76,12 +76,13 @@ __device__ inline int find_task(const Task* __restrict__ t, int n, int64_t u) {
 }
 
 // ---------------------------------------------------------------------------------------
+template <class ST, class DT>
 __global__ void __launch_bounds__(256) assemble_kernel(DevGeom g, const AsmTask* __restrict__ tasks,
                                                        int ntasks, const int32_t* __restrict__ slot,
                                                        const int32_t* __restrict__ idx,
                                                        const int64_t* __restrict__ dof,
                                                        const AsmSrc* __restrict__ table,
-                                                       const zd* __restrict__ src, zd* __restrict__ dst) {
+                                                       const ST* __restrict__ src, DT* __restrict__ dst) {
   const int64_t u = blockIdx.x;
   const int ti = find_task(tasks, ntasks, u);
   const AsmTask t = tasks[ti];
@@ -100,19 +101,20 @@ __global__ void __launch_bounds__(256) assemble_kernel(DevGeom g, const AsmTask*
     const AsmSrc sr = table[t.tab_off + (int64_t)rs * t.nsc + cs];
     zd v;
     if (sr.off >= 0) {
-      v = src[sr.off + ri + (int64_t)idx[t.cmap_off + j] * sr.ld];
+      v = widen(src[sr.off + ri + (int64_t)idx[t.cmap_off + j] * sr.ld]);
     } else {
       v = cfie_entry(g.p, g.n, g.k, g.eta, rd, dof[t.cdof_off + j]);
     }
-    dst[t.out_off + i + (int64_t)j * t.ld] = v;
+    dst[t.out_off + i + (int64_t)j * t.ld] = narrow<DT>(v);
   }
 }
 
 // ---------------------------------------------------------------------------------------
+template <class PT>
 __global__ void __launch_bounds__(256) idmatrix_kernel(DevGeom g, const IdTask* __restrict__ tasks,
                                                        int ntasks, const QSeg* __restrict__ segs,
                                                        const int64_t* __restrict__ dof,
-                                                       const zd* __restrict__ pool) {
+                                                       const PT* __restrict__ pool) {
   const int64_t u = blockIdx.x;
   const int ti = find_task(tasks, ntasks, u);
   const IdTask t = tasks[ti];
@@ -141,8 +143,8 @@ __global__ void __launch_bounds__(256) idmatrix_kernel(DevGeom g, const IdTask* 
     for (int jj = 0; jj < 16; ++jj) {
       const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
       if (j >= t.m) break;
-      zd v = transposed ? pool[sg.tile_bq + j + (int64_t)li * t.m]
-                        : pool[sg.tile_qb + li + (int64_t)j * sg.ld];
+      const zd v = widen(transposed ? pool[sg.tile_bq + j + (int64_t)li * t.m]
+                                    : pool[sg.tile_qb + li + (int64_t)j * sg.ld]);
       out[i + (int64_t)j * t.rows] = v;
     }
     return;
@@ -282,18 +284,34 @@ __global__ void __launch_bounds__(256) matvec_sum_kernel(const zd* __restrict__ 
 
 void launch_assemble(const DevGeom& g, const AsmTask* tasks, int ntasks, int64_t nunits,
                      const int32_t* slot, const int32_t* idx, const int64_t* dof,
-                     const AsmSrc* table, const zd* src_pool, zd* dst_pool, hipStream_t st) {
+                     const AsmSrc* table, const void* src_pool, bool src32, void* dst_pool, bool dst32,
+                     hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
-  hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)nunits), dim3(256), 0, st, g, tasks, ntasks,
-                     slot, idx, dof, table, src_pool, dst_pool);
+  const dim3 gr((unsigned)nunits), b(256);
+  if (!src32 && !dst32)
+    hipLaunchKernelGGL((assemble_kernel<zd, zd>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
+                       static_cast<const zd*>(src_pool), static_cast<zd*>(dst_pool));
+  else if (src32 && dst32)
+    hipLaunchKernelGGL((assemble_kernel<zf, zf>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
+                       static_cast<const zf*>(src_pool), static_cast<zf*>(dst_pool));
+  else if (src32)
+    hipLaunchKernelGGL((assemble_kernel<zf, zd>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
+                       static_cast<const zf*>(src_pool), static_cast<zd*>(dst_pool));
+  else
+    hipLaunchKernelGGL((assemble_kernel<zd, zf>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
+                       static_cast<const zd*>(src_pool), static_cast<zf*>(dst_pool));
   FMMLU_HIP(hipGetLastError());
 }
 
 void launch_build_idmatrix(const DevGeom& g, const IdTask* tasks, int ntasks, int64_t nunits,
-                           const QSeg* segs, const int64_t* dof, const zd* pool, hipStream_t st) {
+                           const QSeg* segs, const int64_t* dof, const void* pool, bool pool32, hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
-  hipLaunchKernelGGL(idmatrix_kernel, dim3((unsigned)nunits), dim3(256), 0, st, g, tasks, ntasks,
-                     segs, dof, pool);
+  if (pool32)
+    hipLaunchKernelGGL(idmatrix_kernel<zf>, dim3((unsigned)nunits), dim3(256), 0, st, g, tasks, ntasks, segs, dof,
+                       static_cast<const zf*>(pool));
+  else
+    hipLaunchKernelGGL(idmatrix_kernel<zd>, dim3((unsigned)nunits), dim3(256), 0, st, g, tasks, ntasks, segs, dof,
+                       static_cast<const zd*>(pool));
   FMMLU_HIP(hipGetLastError());
 }
 

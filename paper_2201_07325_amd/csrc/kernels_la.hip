@@ -1123,9 +1123,10 @@ __device__ inline int seg_of(const NSeg* __restrict__ segs, int64_t base, int ns
   return lo;
 }
 
+template <class PT>
 __global__ void __launch_bounds__(256) cross_kernel(const CrossTask* __restrict__ tasks, int ntasks,
                                                     const NSeg* __restrict__ segs,
-                                                    const zd* __restrict__ pool) {
+                                                    const PT* __restrict__ pool) {
   const int64_t u = blockIdx.x;
   const int ti = find_task(tasks, ntasks, u);
   const CrossTask t = tasks[ti];
@@ -1133,7 +1134,7 @@ __global__ void __launch_bounds__(256) cross_kernel(const CrossTask* __restrict_
   const int m = t.m, mn = t.m + t.nN, s = t.s, r = t.m - t.s;
   const int ucol_r = (mn + 63) >> 6, ucol_c = (m + 63) >> 6;
   const int64_t ncol_units = (int64_t)ucol_r * ucol_c;
-  const zd* bb = pool + t.tile_bb;
+  const PT* bb = pool + t.tile_bb;
   if (lu < ncol_units) {
     // Ccol: rows (R, S, N), cols (S, R) = perm order
     const int bi = (int)(lu % ucol_r), bj = (int)(lu / ucol_r);
@@ -1152,7 +1153,7 @@ __global__ void __launch_bounds__(256) cross_kernel(const CrossTask* __restrict_
       const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
       if (j >= m) break;
       const int pj = t.perm[j];
-      zd v = (i < m) ? bb[pi + (int64_t)pj * m] : pool[sg->tile_nb + li + (int64_t)pj * sg->ld];
+      const zd v = widen((i < m) ? bb[pi + (int64_t)pj * m] : pool[sg->tile_nb + li + (int64_t)pj * sg->ld]);
       t.Ccol[i + (int64_t)j * mn] = v;
     }
   } else {
@@ -1169,10 +1170,10 @@ __global__ void __launch_bounds__(256) cross_kernel(const CrossTask* __restrict_
       zd v;
       if (j < m) {
         const int pj = (j < r) ? t.perm[s + j] : t.perm[j - r];
-        v = bb[pi + (int64_t)pj * m];
+        v = widen(bb[pi + (int64_t)pj * m]);
       } else {
         const NSeg& sg = segs[t.seg_off + seg_of(segs, t.seg_off, t.nseg, j - m)];
-        v = pool[sg.tile_bn + pi + (int64_t)sg.live[j - m - sg.off] * m];
+        v = widen(pool[sg.tile_bn + pi + (int64_t)sg.live[j - m - sg.off] * m]);
       }
       t.Crow[i + (int64_t)j * m] = v;
     }
@@ -1190,6 +1191,7 @@ __global__ void __launch_bounds__(256) extract_r_kernel(const ExtractTask* __res
   }
 }
 
+template <class DT>
 __global__ void __launch_bounds__(256) copy_kernel(const CopyTask* __restrict__ tasks, int ntasks) {
   const int64_t u = blockIdx.x;
   const int ti = find_task(tasks, ntasks, u);
@@ -1202,10 +1204,11 @@ __global__ void __launch_bounds__(256) copy_kernel(const CopyTask* __restrict__ 
   for (int jj = 0; jj < 16; ++jj) {
     const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
     if (j >= t.cols) break;
-    t.dst[i + (int64_t)j * t.ldd] = t.src[i + (int64_t)j * t.lds];
+    static_cast<DT*>(t.dst)[i + (int64_t)j * t.ldd] = narrow<DT>(t.src[i + (int64_t)j * t.lds]);
   }
 }
 
+template <class DT>
 __global__ void __launch_bounds__(256) transpose_kernel(const CopyTask* __restrict__ tasks, int ntasks) {
   __shared__ zd tile[64][65];
   const int64_t u = blockIdx.x;
@@ -1222,15 +1225,18 @@ __global__ void __launch_bounds__(256) transpose_kernel(const CopyTask* __restri
   __syncthreads();
   for (int q = ty; q < 64; q += 4) {
     const int j = bj * 64 + tx, i = bi * 64 + q;
-    if (i < t.rows && j < t.cols) t.dst[j + (int64_t)i * t.ldd] = tile[tx][q];
+    if (i < t.rows && j < t.cols) static_cast<DT*>(t.dst)[j + (int64_t)i * t.ldd] = narrow<DT>(tile[tx][q]);
   }
 }
 
 }  // namespace
 
-void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st) {
+void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, bool dst32, hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
-  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
+  if (dst32)
+    hipLaunchKernelGGL(transpose_kernel<zf>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
+  else
+    hipLaunchKernelGGL(transpose_kernel<zd>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
   FMMLU_HIP(hipGetLastError());
 }
 
@@ -1398,9 +1404,14 @@ void launch_gj_unpermute(const GjTask* tasks, int ntasks, int nmax, zd* const* o
 }
 
 void launch_gather_cross(const CrossTask* tasks, int ntasks, int64_t nunits, const NSeg* segs,
-                         const zd* pool, hipStream_t st) {
+                         const void* pool, bool pool32, hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
-  hipLaunchKernelGGL(cross_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks, segs, pool);
+  if (pool32)
+    hipLaunchKernelGGL(cross_kernel<zf>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks, segs,
+                       static_cast<const zf*>(pool));
+  else
+    hipLaunchKernelGGL(cross_kernel<zd>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks, segs,
+                       static_cast<const zd*>(pool));
   FMMLU_HIP(hipGetLastError());
 }
 
@@ -1410,9 +1421,12 @@ void launch_extract_r(const ExtractTask* tasks, int ntasks, int mmax, hipStream_
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, hipStream_t st) {
+void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, bool dst32, hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
-  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
+  if (dst32)
+    hipLaunchKernelGGL(copy_kernel<zf>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
+  else
+    hipLaunchKernelGGL(copy_kernel<zd>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
   FMMLU_HIP(hipGetLastError());
 }
 

@@ -23,18 +23,6 @@ __device__ inline double wave_sum(double v) {
 
 // x_R of a box is held in dynamic LDS (r complex values, sized by the launch).
 
-// y[i] = sum_k op(A)[i, k] v[k]; N: A is rows x cols (lda), thread per row (coalesced).
-__device__ inline zd gemv_n_row(const zd* __restrict__ A, int64_t lda, int i, int cols,
-                                const zd* v, bool conjA) {
-  zd acc{0.0, 0.0};
-  for (int k = 0; k < cols; ++k) {
-    zd a = A[i + (int64_t)k * lda];
-    if (conjA) a.im = -a.im;
-    zfma(acc, a, v[k]);
-  }
-  return acc;
-}
-
 // y[i] = sum_k A[k, i]^(*) v[k] for one i, wavefront-cooperative (lanes over k, coalesced).
 __device__ inline zd gemv_t_wave(const zd* __restrict__ A, int64_t lda, int i, int rows,
                                  const zd* v, bool conjA, int lane) {
@@ -54,8 +42,8 @@ __device__ inline zd gemv_t_wave(const zd* __restrict__ A, int64_t lda, int i, i
 // y[0:M] = op(A)[0:M, 0:K] v with A column-major (lda); v[k] = fetch(k). Lanes take rows,
 // the four wavefronts split k, partial sums meet in LDS (part: 4 x 64). Result handed to
 // emit(i, value) for i < M. Call from all 256 threads.
-template <class Fetch, class Emit>
-__device__ inline void block_gemv_n(const zd* __restrict__ A, int64_t lda, int M, int K, bool conjA,
+template <class FT, class Fetch, class Emit>
+__device__ inline void block_gemv_n(const FT* __restrict__ A, int64_t lda, int M, int K, bool conjA,
                                     Fetch fetch, Emit emit, zd (*part)[64]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i0 = 0; i0 < M; i0 += 64) {
@@ -63,7 +51,7 @@ __device__ inline void block_gemv_n(const zd* __restrict__ A, int64_t lda, int M
     zd acc{0.0, 0.0};
     if (i < M) {
       for (int k = wave; k < K; k += 4) {
-        zd a = A[i + (int64_t)k * lda];
+        zd a = widen(A[i + (int64_t)k * lda]);
         if (conjA) a.im = -a.im;
         zfma(acc, a, fetch(k));
       }
@@ -79,18 +67,18 @@ __device__ inline void block_gemv_n(const zd* __restrict__ A, int64_t lda, int M
 }
 
 // y[i] = sum_k A[k, i]^(*) v[k] for i < M; wavefront per output, lanes over k (coalesced).
-template <class Fetch, class Emit>
-__device__ inline void block_gemv_t(const zd* __restrict__ A, int64_t lda, int M, int K, bool conjA,
+template <class FT, class Fetch, class Emit>
+__device__ inline void block_gemv_t(const FT* __restrict__ A, int64_t lda, int M, int K, bool conjA,
                                     Fetch fetch, Emit emit) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = wave; i < M; i += 4) {
     zd acc{0.0, 0.0};
-    const zd* col = A + (int64_t)i * lda;
+    const FT* col = A + (int64_t)i * lda;
     for (int k = lane; k < K; k += 64) {
       if (conjA)
-        zfmac(acc, col[k], fetch(k));
+        zfmac(acc, widen(col[k]), fetch(k));
       else
-        zfma(acc, col[k], fetch(k));
+        zfma(acc, widen(col[k]), fetch(k));
     }
     acc.re = wave_sum(acc.re);
     acc.im = wave_sum(acc.im);
@@ -100,8 +88,8 @@ __device__ inline void block_gemv_t(const zd* __restrict__ A, int64_t lda, int M
 
 // y[i] = sum_k A[k, i]^(*) v[k] for i < M, four outputs per wavefront at a time (lanes over k,
 // coalesced; sixteen independent loads per lane in flight). v must be in LDS.
-template <class Emit>
-__device__ inline void block_gemv_t4(const zd* __restrict__ A, int64_t lda, int M, int K, bool conjA,
+template <class FT, class Emit>
+__device__ inline void block_gemv_t4(const FT* __restrict__ A, int64_t lda, int M, int K, bool conjA,
                                      const zd* v, Emit emit) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i0 = 4 * wave; i0 < M; i0 += 16) {
@@ -113,7 +101,7 @@ __device__ inline void block_gemv_t4(const zd* __restrict__ A, int64_t lda, int 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int k = k0 + lane + 64 * j;
-          a[q][j] = (i0 + q < M && k < K) ? A[(int64_t)(i0 + q) * lda + k] : zd{0.0, 0.0};
+          a[q][j] = (i0 + q < M && k < K) ? widen(A[(int64_t)(i0 + q) * lda + k]) : zd{0.0, 0.0};
         }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -138,6 +126,7 @@ __device__ inline void block_gemv_t4(const zd* __restrict__ A, int64_t lda, int 
 }
 
 // Forward, per box: x_R -= T^T x_S (adjoint T^H x_S). x_S and x_R are gathered into LDS first.
+template <class FT>
 __global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restrict__ boxes, zd* x,
                                                        zd* XR, int adjoint, int smax) {
   const SolveBox b = boxes[blockIdx.x];
@@ -147,7 +136,8 @@ __global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restric
   for (int k = threadIdx.x; k < b.s; k += 256) xs[k] = x[b.S[k]];
   for (int k = threadIdx.x; k < b.r; k += 256) xr[k] = x[b.R[k]];
   __syncthreads();
-  block_gemv_t4(b.T, b.s, b.r, b.s, adjoint != 0, xs, [&](int i, zd d) { xr[i] = zsub(xr[i], d); });
+  block_gemv_t4(static_cast<const FT*>(b.T), b.s, b.r, b.s, adjoint != 0, xs,
+                [&](int i, zd d) { xr[i] = zsub(xr[i], d); });
   __syncthreads();
   for (int i = threadIdx.x; i < b.r; i += 256) {
     x[b.R[i]] = xr[i];
@@ -157,6 +147,7 @@ __global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restric
 
 // Forward, one row chunk of a box: y[i] = sum_k P[i, k] x_R[k] with P = Lp (adjoint: conj(U^T)),
 // P stored (s+nN) x r column-major; thread per row, four independent accumulators.
+template <class FT>
 __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict__ boxes,
                                                       const SweepTask* __restrict__ tasks,
                                                       const zd* __restrict__ XR, zd* __restrict__ y,
@@ -167,28 +158,28 @@ __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict
   for (int k = threadIdx.x; k < b.r; k += 256) xr[k] = XR[b.xr_off + k];
   __syncthreads();
   zd* yb = y + b.y_off;
-  const zd* P = adjoint ? b.UpT : b.Lp;
+  const FT* P = static_cast<const FT*>(adjoint ? b.UpT : b.Lp);
   const int64_t ld = b.nsn;
   for (int i = t.k0 + threadIdx.x; i < t.k0 + t.kn; i += 256) {
     zd a0{0.0, 0.0}, a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
-    const zd* pr = P + i;
+    const FT* pr = P + i;
     int k = 0;
     if (!adjoint) {
       for (; k + 3 < b.r; k += 4) {
-        zfma(a0, pr[(int64_t)k * ld], xr[k]);
-        zfma(a1, pr[(int64_t)(k + 1) * ld], xr[k + 1]);
-        zfma(a2, pr[(int64_t)(k + 2) * ld], xr[k + 2]);
-        zfma(a3, pr[(int64_t)(k + 3) * ld], xr[k + 3]);
+        zfma(a0, widen(pr[(int64_t)k * ld]), xr[k]);
+        zfma(a1, widen(pr[(int64_t)(k + 1) * ld]), xr[k + 1]);
+        zfma(a2, widen(pr[(int64_t)(k + 2) * ld]), xr[k + 2]);
+        zfma(a3, widen(pr[(int64_t)(k + 3) * ld]), xr[k + 3]);
       }
-      for (; k < b.r; ++k) zfma(a0, pr[(int64_t)k * ld], xr[k]);
+      for (; k < b.r; ++k) zfma(a0, widen(pr[(int64_t)k * ld]), xr[k]);
     } else {
       for (; k + 3 < b.r; k += 4) {
-        zfmac(a0, pr[(int64_t)k * ld], xr[k]);
-        zfmac(a1, pr[(int64_t)(k + 1) * ld], xr[k + 1]);
-        zfmac(a2, pr[(int64_t)(k + 2) * ld], xr[k + 2]);
-        zfmac(a3, pr[(int64_t)(k + 3) * ld], xr[k + 3]);
+        zfmac(a0, widen(pr[(int64_t)k * ld]), xr[k]);
+        zfmac(a1, widen(pr[(int64_t)(k + 1) * ld]), xr[k + 1]);
+        zfmac(a2, widen(pr[(int64_t)(k + 2) * ld]), xr[k + 2]);
+        zfmac(a3, widen(pr[(int64_t)(k + 3) * ld]), xr[k + 3]);
       }
-      for (; k < b.r; ++k) zfmac(a0, pr[(int64_t)k * ld], xr[k]);
+      for (; k < b.r; ++k) zfmac(a0, widen(pr[(int64_t)k * ld]), xr[k]);
     }
     yb[i] = zadd(zadd(a0, a1), zadd(a2, a3));
   }
@@ -207,6 +198,7 @@ __global__ void __launch_bounds__(256) scatter_sub_kernel(const int32_t* __restr
   x[t] = zsub(x[t], acc);
 }
 
+template <class FT>
 __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restrict__ boxes, zd* x,
                                                          int adjoint) {
   const SolveBox b = boxes[blockIdx.x];
@@ -215,15 +207,16 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
   for (int l = threadIdx.x; l < b.r; l += 256) xr[l] = x[b.R[l]];
   __syncthreads();
   if (!adjoint)
-    block_gemv_n(b.Xi, b.r, b.r, b.r, false, [&](int k) { return xr[k]; },
+    block_gemv_n(static_cast<const FT*>(b.Xi), b.r, b.r, b.r, false, [&](int k) { return xr[k]; },
                  [&](int i, zd v) { x[b.R[i]] = v; }, part);
   else
-    block_gemv_t(b.Xi, b.r, b.r, b.r, true, [&](int k) { return xr[k]; },
+    block_gemv_t(static_cast<const FT*>(b.Xi), b.r, b.r, b.r, true, [&](int k) { return xr[k]; },
                  [&](int i, zd v) { x[b.R[i]] = v; });
 }
 
 // Backward partials over a chunk of S u N: out[i] = sum_{k in chunk} Q[k, i] x_SN[k], i < r,
 // with Q = U^T (adjoint: conj(Lp)), stored (s+nN) x r; wavefront per output, lanes over k.
+template <class FT>
 __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __restrict__ boxes,
                                                           const SweepTask* __restrict__ tasks,
                                                           const zd* __restrict__ x, zd* __restrict__ Pbuf,
@@ -234,10 +227,11 @@ __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __rest
   for (int q = threadIdx.x; q < t.kn; q += 256) xsn[q] = x[b.SN[t.k0 + q]];
   __syncthreads();
   zd* out = Pbuf + b.p_off + (int64_t)t.chunk * b.r;
-  const zd* Q = adjoint ? b.Lp : b.UpT;
+  const FT* Q = static_cast<const FT*>(adjoint ? b.Lp : b.UpT);
   block_gemv_t4(Q + t.k0, b.nsn, b.r, t.kn, adjoint != 0, xsn, [&](int i, zd d) { out[i] = d; });
 }
 
+template <class FT>
 __global__ void __launch_bounds__(256) solve_bfin_kernel(const SolveBox* __restrict__ boxes,
                                                          const zd* __restrict__ Pbuf, zd* x, int adjoint) {
   const SolveBox b = boxes[blockIdx.x];
@@ -251,7 +245,7 @@ __global__ void __launch_bounds__(256) solve_bfin_kernel(const SolveBox* __restr
   }
   __syncthreads();
   // x_S -= T x_R  (adjoint: conj(T) x_R); T: s x r
-  block_gemv_n(b.T, b.s, b.s, b.r, adjoint != 0, [&](int k) { return xr[k]; },
+  block_gemv_n(static_cast<const FT*>(b.T), b.s, b.s, b.r, adjoint != 0, [&](int k) { return xr[k]; },
                [&](int l, zd v) { x[b.S[l]] = zsub(x[b.S[l]], v); }, part);
 }
 
@@ -309,19 +303,25 @@ __global__ void __launch_bounds__(256) permute_kernel(const zd* __restrict__ src
 
 }  // namespace
 
-void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint,
+void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint, bool f32,
                      hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(solve_xr_kernel, dim3(nb), dim3(256), (size_t)(smax + rmax) * sizeof(zd), st, boxes, x,
-                     XR, adjoint, smax);
+  const size_t lds = (size_t)(smax + rmax) * sizeof(zd);
+  if (f32)
+    hipLaunchKernelGGL(solve_xr_kernel<zf>, dim3(nb), dim3(256), lds, st, boxes, x, XR, adjoint, smax);
+  else
+    hipLaunchKernelGGL(solve_xr_kernel<zd>, dim3(nb), dim3(256), lds, st, boxes, x, XR, adjoint, smax);
   FMMLU_HIP(hipGetLastError());
 }
 
 void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
-                    zd* y, int adjoint, hipStream_t st) {
+                    zd* y, int adjoint, bool f32, hipStream_t st) {
   if (nt <= 0) return;
-  hipLaunchKernelGGL(solve_y_kernel, dim3(nt), dim3(256), (size_t)rmax * sizeof(zd), st, boxes, tasks, XR,
-                     y, adjoint);
+  const size_t lds = (size_t)rmax * sizeof(zd);
+  if (f32)
+    hipLaunchKernelGGL(solve_y_kernel<zf>, dim3(nt), dim3(256), lds, st, boxes, tasks, XR, y, adjoint);
+  else
+    hipLaunchKernelGGL(solve_y_kernel<zd>, dim3(nt), dim3(256), lds, st, boxes, tasks, XR, y, adjoint);
   FMMLU_HIP(hipGetLastError());
 }
 
@@ -333,25 +333,34 @@ void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* s
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, hipStream_t st) {
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, bool f32, hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(solve_diag_kernel, dim3(nb), dim3(256), (size_t)rmax * sizeof(zd), st, boxes, x,
-                     adjoint);
+  const size_t lds = (size_t)rmax * sizeof(zd);
+  if (f32)
+    hipLaunchKernelGGL(solve_diag_kernel<zf>, dim3(nb), dim3(256), lds, st, boxes, x, adjoint);
+  else
+    hipLaunchKernelGGL(solve_diag_kernel<zd>, dim3(nb), dim3(256), lds, st, boxes, x, adjoint);
   FMMLU_HIP(hipGetLastError());
 }
 
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
-                        int adjoint, hipStream_t st) {
+                        int adjoint, bool f32, hipStream_t st) {
   if (nt <= 0) return;
-  hipLaunchKernelGGL(solve_bpart_kernel, dim3(nt), dim3(256), 0, st, boxes, tasks, x, Pbuf, adjoint);
+  if (f32)
+    hipLaunchKernelGGL(solve_bpart_kernel<zf>, dim3(nt), dim3(256), 0, st, boxes, tasks, x, Pbuf, adjoint);
+  else
+    hipLaunchKernelGGL(solve_bpart_kernel<zd>, dim3(nt), dim3(256), 0, st, boxes, tasks, x, Pbuf, adjoint);
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint,
+void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint, bool f32,
                        hipStream_t st) {
   if (nb <= 0) return;
-  hipLaunchKernelGGL(solve_bfin_kernel, dim3(nb), dim3(256), (size_t)rmax * sizeof(zd), st, boxes, Pbuf,
-                     x, adjoint);
+  const size_t lds = (size_t)rmax * sizeof(zd);
+  if (f32)
+    hipLaunchKernelGGL(solve_bfin_kernel<zf>, dim3(nb), dim3(256), lds, st, boxes, Pbuf, x, adjoint);
+  else
+    hipLaunchKernelGGL(solve_bfin_kernel<zd>, dim3(nb), dim3(256), lds, st, boxes, Pbuf, x, adjoint);
   FMMLU_HIP(hipGetLastError());
 }
 

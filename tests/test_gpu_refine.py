@@ -94,3 +94,34 @@ def test_refined_zero_rhs_and_bad_args(case):
     for kw in ({"tol": 0.0}, {"tol": -1.0}, {"maxit": 0}):
         with pytest.raises(fm.FmmluError):
             f.solve_refined(bd, **kw)
+
+
+@pytest.mark.parametrize("leaf", [64, 32])
+def test_float32_factors_refined_to_float64_accuracy(leaf):
+    """Complex float32 tiles, panels and Schur updates (ID pivoting and pivot-block inverses
+    in float64): the factored inverse alone is float32-accurate; float64 FGMRES with the
+    exact matvec brings the solution to the dense LU answer."""
+    s = synth.unit_sphere(3000)
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    b = np.sqrt(s.weights) * synth.point_source_data(s.points, s.k)
+    xs = dense.DenseLU(a).solve(b)
+    f64 = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=1e-6, leaf_size=leaf)
+    f32 = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=1e-6, leaf_size=leaf, precision=1)
+    i32, i64 = f32.info(), f64.info()
+    assert i32["precision"] == 1
+    bd = torch.as_tensor(b).cuda()
+    x32 = f32.solve(bd).cpu().numpy()
+    e32 = np.linalg.norm(x32 - xs) / np.linalg.norm(xs)
+    y32 = f32.solve_adjoint(bd).cpu().numpy()
+    ys = np.linalg.solve(a.conj().T, b)
+    ey32 = np.linalg.norm(y32 - ys) / np.linalg.norm(ys)
+    x, it, rr = f32.solve_refined(bd, tol=1e-12, maxit=40)
+    er = np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs)
+    say(f"leaf {leaf}: factor bytes fp32 {i32['factor_bytes']} vs fp64 {i64['factor_bytes']}; "
+        f"fp32 solve err {e32:.2e} adjoint {ey32:.2e}; refined {it} its relres {rr:.2e} err {er:.2e}")
+    # the top block stays float64 (its dense inverse); every other factor byte halves
+    box32 = i32["factor_bytes"] - 16 * i32["n0"] ** 2
+    box64 = i64["factor_bytes"] - 16 * i64["n0"] ** 2
+    assert box32 < 0.6 * box64
+    assert e32 < 1e-4 and ey32 < 1e-4
+    assert rr <= 1e-12 and er < 1e-10
