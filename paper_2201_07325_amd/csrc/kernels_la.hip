@@ -627,139 +627,138 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
   for (int q = 0; q < kGjNb; ++q) a[q] = (own && q < nb) ? A[gi + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
   const bool multi = t.wpt > 1;
   const int64_t slen = gj_slot_len(t.wpt);
-  for (int j = 0; j < nb; ++j) {
-    const int gc = j0 + j;
-    zd aj = a[0];
+  for (int j = 0; j < kGjNb; ++j) {
+    if (j < nb) {
+      const int gc = j0 + j;
+      zd aj = a[0];
 #pragma unroll
-    for (int q = 1; q < kGjNb; ++q)
-      if (q == j) aj = a[q];
-    double best = -1.0;
-    int besti = 0x7fffffff;
-    if (own && gi >= gc) {
-      best = zabs2(aj);
-      besti = gi;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(besti, o, 64);
-      if (gj_better(ov, oi, best, besti)) {
-        best = ov;
-        besti = oi;
+      for (int q = 1; q < kGjNb; ++q)
+        if (q == j) aj = a[q];
+      double best = -1.0;
+      int besti = 0x7fffffff;
+      if (own && gi >= gc) {
+        best = zabs2(aj);
+        besti = gi;
       }
-    }
-    if (lane == 0) {
-      bv[wave] = best;
-      bi[wave] = besti;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double b = bv[0];
-      int p = bi[0];
-      for (int q = 1; q < 4; ++q)
-        if (gj_better(bv[q], bi[q], b, p)) {
-          b = bv[q];
-          p = bi[q];
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(besti, o, 64);
+        if (gj_better(ov, oi, best, besti)) {
+          best = ov;
+          besti = oi;
         }
-      sh_win = p;
-      sh_best = b;
-    }
-    __syncthreads();
-    if (!multi) {
-      if (gi == sh_win) {
-#pragma unroll
-        for (int q = 0; q < kGjNb; ++q) prow[q] = a[q];
       }
-      if (gi == gc) {
-#pragma unroll
-        for (int q = 0; q < kGjNb; ++q) rowgc[q] = a[q];
-      }
-      if (tid == 0) sh_p = sh_win;
-      __syncthreads();
-    } else {
-      zd* slot = t.slots + (int64_t)(gc & 1) * slen;
-      if (tid == 0) slot[(int64_t)w * (kGjNb + 1)] = zd{sh_best, (double)sh_win};
-      if (gi == sh_win) {
-#pragma unroll
-        for (int q = 0; q < kGjNb; ++q) slot[(int64_t)w * (kGjNb + 1) + 1 + q] = a[q];
-      }
-      if (gi == gc) {
-#pragma unroll
-        for (int q = 0; q < kGjNb; ++q) slot[(int64_t)t.wpt * (kGjNb + 1) + q] = a[q];
+      if (lane == 0) {
+        bv[wave] = best;
+        bi[wave] = besti;
       }
       __syncthreads();
       if (tid == 0) {
-        __threadfence();
-        __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const int target = t.wpt * (gc + 1);
-        int64_t spins = 0;
-        while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-          if (++spins > kGjSpinLimit) {
-            __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+        double b = bv[0];
+        int p = bi[0];
+        for (int q = 1; q < 4; ++q)
+          if (gj_better(bv[q], bi[q], b, p)) {
+            b = bv[q];
+            p = bi[q];
           }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        __threadfence();
-        double b = -1.0;
-        int p = 0x7fffffff, pw = 0;
-        for (int u = 0; u < t.wpt; ++u) {
-          const zd c = slot[(int64_t)u * (kGjNb + 1)];
-          const int ci = (int)c.im;
-          if (gj_better(c.re, ci, b, p)) {
-            b = c.re;
-            p = ci;
-            pw = u;
-          }
-        }
-        sh_p = p;
+        sh_win = p;
         sh_best = b;
-        sh_win = pw;
       }
       __syncthreads();
-      if (tid < kGjNb) {
-        prow[tid] = slot[(int64_t)sh_win * (kGjNb + 1) + 1 + tid];
-        rowgc[tid] = slot[(int64_t)t.wpt * (kGjNb + 1) + tid];
+      if (!multi) {
+        if (gi == sh_win) {
+  #pragma unroll
+          for (int q = 0; q < kGjNb; ++q) prow[q] = a[q];
+        }
+        if (gi == gc) {
+  #pragma unroll
+          for (int q = 0; q < kGjNb; ++q) rowgc[q] = a[q];
+        }
+        if (tid == 0) sh_p = sh_win;
+        __syncthreads();
+      } else {
+        zd* slot = t.slots + (int64_t)(gc & 1) * slen;
+        if (tid == 0) slot[(int64_t)w * (kGjNb + 1)] = zd{sh_best, (double)sh_win};
+        if (gi == sh_win) {
+  #pragma unroll
+          for (int q = 0; q < kGjNb; ++q) slot[(int64_t)w * (kGjNb + 1) + 1 + q] = a[q];
+        }
+        if (gi == gc) {
+  #pragma unroll
+          for (int q = 0; q < kGjNb; ++q) slot[(int64_t)t.wpt * (kGjNb + 1) + q] = a[q];
+        }
+        __syncthreads();
+        if (tid == 0) {
+          __threadfence();
+          __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          const int target = t.wpt * (gc + 1);
+          int64_t spins = 0;
+          while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > kGjSpinLimit) {
+              __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+          }
+          __threadfence();
+          double b = -1.0;
+          int p = 0x7fffffff, pw = 0;
+          for (int u = 0; u < t.wpt; ++u) {
+            const zd c = slot[(int64_t)u * (kGjNb + 1)];
+            const int ci = (int)c.im;
+            if (gj_better(c.re, ci, b, p)) {
+              b = c.re;
+              p = ci;
+              pw = u;
+            }
+          }
+          sh_p = p;
+          sh_best = b;
+          sh_win = pw;
+        }
+        __syncthreads();
+        if (tid < kGjNb) {
+          prow[tid] = slot[(int64_t)sh_win * (kGjNb + 1) + 1 + tid];
+          rowgc[tid] = slot[(int64_t)t.wpt * (kGjNb + 1) + tid];
+        }
+        __syncthreads();
       }
-      __syncthreads();
-    }
-    int p = sh_p;
-    if (p >= n) p = gc;
-    if (w == 0 && tid == 0) {
-      t.piv[gc] = p;
-      if (!(sh_best > 0.0) && *t.info == 0) *t.info = gc + 1;
-    }
-    // the pivot row moves to position gc, the row from gc to position p
-    if (p != gc) {
+      int p = sh_p;
+      if (p >= n) p = gc;
+      if (w == 0 && tid == 0) {
+        t.piv[gc] = p;
+        if (!(sh_best > 0.0) && *t.info == 0) *t.info = gc + 1;
+      }
+      // the pivot row moves to position gc, the row from gc to position p
+      if (p != gc) {
+        if (gi == gc) {
+  #pragma unroll
+          for (int q = 0; q < kGjNb; ++q) a[q] = prow[q];
+        } else if (gi == p) {
+  #pragma unroll
+          for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[q];
+        }
+      }
+      const zd pv = prow[j];
+      const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
       if (gi == gc) {
+  #pragma unroll
+        for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[q], inv);
+      } else if (own) {
+        zd f = a[0];
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) a[q] = prow[q];
-      } else if (gi == p) {
-#pragma unroll
-        for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[q];
+        for (int q = 1; q < kGjNb; ++q)
+          if (q == j) f = a[q];
+  #pragma unroll
+        for (int q = 0; q < kGjNb; ++q) {
+          if (q == j)
+            a[q] = zd{-(f.re * inv.re - f.im * inv.im), -(f.re * inv.im + f.im * inv.re)};
+          else
+            a[q] = zsub(a[q], zmul(f, zmul(prow[q], inv)));
+        }
       }
+      __syncthreads();
     }
-    zd pv = prow[0];
-#pragma unroll
-    for (int q = 1; q < kGjNb; ++q)
-      if (q == j) pv = prow[q];
-    const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
-    if (gi == gc) {
-#pragma unroll
-      for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[q], inv);
-    } else if (own) {
-      zd f = a[0];
-#pragma unroll
-      for (int q = 1; q < kGjNb; ++q)
-        if (q == j) f = a[q];
-#pragma unroll
-      for (int q = 0; q < kGjNb; ++q) {
-        if (q == j)
-          a[q] = zd{-(f.re * inv.re - f.im * inv.im), -(f.re * inv.im + f.im * inv.re)};
-        else
-          a[q] = zsub(a[q], zmul(f, zmul(prow[q], inv)));
-      }
-    }
-    __syncthreads();
   }
   if (own) {
 #pragma unroll
@@ -807,84 +806,77 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
 #pragma unroll
     for (int q = 0; q < kGjNb; ++q) a[q] = (own && q < nb) ? A[tid + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
     // two barriers per column: LDS slots alternate between even and odd columns, so the next
-    // column's writes never meet this column's reads
-    for (int j = 0; j < nb; ++j) {
-      const int gc = j0 + j, par = j & 1;
-      zd aj = a[0];
+    // column's writes never meet this column's reads. The column loop is unrolled so that
+    // the register row is indexed by constants only.
 #pragma unroll
-      for (int q = 1; q < kGjNb; ++q)
-        if (q == j) aj = a[q];
-      double best = -1.0;
-      int besti = 0x7fffffff;
-      if (own && tid >= gc) {
-        best = zabs2(aj);
-        besti = tid;
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(besti, o, 64);
-        if (gj_better(ov, oi, best, besti)) {
-          best = ov;
-          besti = oi;
+    for (int j = 0; j < kGjNb; ++j) {
+      if (j < nb) {
+        const int gc = j0 + j, par = j & 1;
+        double best = -1.0;
+        int besti = 0x7fffffff;
+        if (own && tid >= gc) {
+          best = zabs2(a[j]);
+          besti = tid;
         }
-      }
-      if (lane == 0) {
-        bv[par][wave] = best;
-        bi[par][wave] = besti;
-      }
-      __syncthreads();
-      double b = bv[par][0];
-      int p = bi[par][0];
-#pragma unroll
-      for (int q = 1; q < NW; ++q)
-        if (gj_better(bv[par][q], bi[par][q], b, p)) {
-          b = bv[par][q];
-          p = bi[par][q];
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ov = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(besti, o, 64);
+          if (gj_better(ov, oi, best, besti)) {
+            best = ov;
+            besti = oi;
+          }
         }
-      if (p >= n) p = gc;
-      if (tid == p) {
+        if (lane == 0) {
+          bv[par][wave] = best;
+          bi[par][wave] = besti;
+        }
+        __syncthreads();
+        double b = bv[par][0];
+        int p = bi[par][0];
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) prow[par][q] = a[q];
-      }
-      if (tid == gc) {
+        for (int q = 1; q < NW; ++q)
+          if (gj_better(bv[par][q], bi[par][q], b, p)) {
+            b = bv[par][q];
+            p = bi[par][q];
+          }
+        if (p >= n) p = gc;
+        if (tid == p) {
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) rowgc[par][q] = a[q];
-      }
-      if (tid == 0) pivl[gc] = p;
-      if (w == 0 && tid == 0) {
-        t.piv[gc] = p;
-        if (!(b > 0.0) && *t.info == 0) *t.info = gc + 1;
-      }
-      __syncthreads();
-      if (p != gc) {
+          for (int q = 0; q < kGjNb; ++q) prow[par][q] = a[q];
+        }
         if (tid == gc) {
 #pragma unroll
-          for (int q = 0; q < kGjNb; ++q) a[q] = prow[par][q];
-        } else if (tid == p) {
-#pragma unroll
-          for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[par][q];
+          for (int q = 0; q < kGjNb; ++q) rowgc[par][q] = a[q];
         }
-      }
-      zd pv = prow[par][0];
+        if (tid == 0) pivl[gc] = p;
+        if (w == 0 && tid == 0) {
+          t.piv[gc] = p;
+          if (!(b > 0.0) && *t.info == 0) *t.info = gc + 1;
+        }
+        __syncthreads();
+        if (p != gc) {
+          if (tid == gc) {
 #pragma unroll
-      for (int q = 1; q < kGjNb; ++q)
-        if (q == j) pv = prow[par][q];
-      const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
-      if (tid == gc) {
+            for (int q = 0; q < kGjNb; ++q) a[q] = prow[par][q];
+          } else if (tid == p) {
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[par][q], inv);
-      } else if (own) {
-        zd f = a[0];
+            for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[par][q];
+          }
+        }
+        const zd pv = prow[par][j];
+        const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
+        if (tid == gc) {
 #pragma unroll
-        for (int q = 1; q < kGjNb; ++q)
-          if (q == j) f = a[q];
-        const zd fi = zmul(f, inv);
+          for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[par][q], inv);
+        } else if (own) {
+          const zd fi = zmul(a[j], inv);
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) {
-          if (q == j)
-            a[q] = zd{-fi.re, -fi.im};
-          else
-            a[q] = zsub(a[q], zmul(fi, prow[par][q]));
+          for (int q = 0; q < kGjNb; ++q) {
+            if (q == j)
+              a[q] = zd{-fi.re, -fi.im};
+            else
+              a[q] = zsub(a[q], zmul(fi, prow[par][q]));
+          }
         }
       }
     }
@@ -960,17 +952,12 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
           acc[cc] = (c < n) ? A[tid + (int64_t)c * lda] : zd{0.0, 0.0};
         }
         const int qi = tid - j0;
+        const bool inJ = qi >= 0 && qi < nb;
 #pragma unroll
         for (int cc = 0; cc < kGjChunk; ++cc) {
 #pragma unroll
           for (int q = 0; q < kGjNb; ++q) zfma(acc[cc], a[q], Ws[q][cc]);
-          if (qi >= 0 && qi < nb) {
-            zd wv = Ws[0][cc];
-#pragma unroll
-            for (int q = 1; q < kGjNb; ++q)
-              if (q == qi) wv = Ws[q][cc];
-            acc[cc] = zsub(acc[cc], wv);
-          }
+          if (inJ) acc[cc] = zsub(acc[cc], Ws[qi][cc]);
         }
 #pragma unroll
         for (int cc = 0; cc < kGjChunk; ++cc) {
