@@ -649,8 +649,22 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   std::sort(own.begin(), own.end(), [](const Owner& a, const Owner& b) { return a.first_pos < b.first_pos; });
   int64_t live_total = n;
 
-  // tiles of the previous level (for assembly)
+  // tiles of the previous level (for assembly). Two pools used alternately by consecutive
+  // levels and grown on demand, so that no level boundary frees memory (a free waits for the
+  // device to drain).
   void* prev_pool = nullptr;
+  void* pools[2] = {nullptr, nullptr};
+  size_t pool_cap[2] = {0, 0};
+  int pool_slot = 0;
+  struct PoolGuard {
+    void** p;
+    ~PoolGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (p[i]) (void)hipFree(p[i]);
+    }
+  } pool_guard{pools};
+  // per-level device lists stay alive until the factorization has drained
+  std::vector<std::unique_ptr<DeviceArena>> level_arenas;
   std::unordered_map<int64_t, int64_t> prev_pair;  // key o1*nprev+o2 -> offset
   std::vector<Owner> prev_own;
   bool first_level = true;
@@ -705,12 +719,22 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     }
     void* pool = nullptr;
     {
-      size_t bytes = std::max<size_t>(1, (size_t)pool_elems) * te;
-      hipError_t e = hipMalloc(&pool, bytes);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error(FMMLU_ENOMEM, "tile pool allocation failed (" + std::to_string(bytes) + " bytes)");
+      const size_t bytes = std::max<size_t>(1, (size_t)pool_elems) * te;
+      const int ps = pool_slot;
+      pool_slot ^= 1;
+      if (pool_cap[ps] < bytes) {
+        if (pools[ps]) FMMLU_HIP(hipFree(pools[ps]));
+        pools[ps] = nullptr;
+        pool_cap[ps] = 0;
+        hipError_t e = hipMalloc(&pools[ps], bytes);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          pools[ps] = nullptr;
+          throw Error(FMMLU_ENOMEM, "tile pool allocation failed (" + std::to_string(bytes) + " bytes)");
+        }
+        pool_cap[ps] = bytes;
       }
+      pool = pools[ps];
     }
     info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)(arena.held() + pool_elems * (int64_t)te));
     info.bytes_tiles += (double)pool_elems * (double)te;
@@ -785,8 +809,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, f32, pool, f32, st);
       }
       prof.bytes[KC_ASSEMBLE] += (double)te * (double)pool_elems * (first_level ? 1.0 : 2.0);
-      sg.sync_reset();
-      if (prev_pool) FMMLU_HIP(hipFree(prev_pool));
       prev_pool = nullptr;
     }
     // every owner starts the level fully live; device copies of act positions as int32 tree
@@ -804,8 +826,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       std::iota(ident.begin(), ident.end(), 0);
       int32_t* dident = sg.up_to(arena, ident);  // persistent for the level (small)
       for (auto& o : own) o.live_dev = dident;
-      FMMLU_HIP(hipStreamSynchronize(st));
-      sg.host.reset();
     }
     // device copy of all act lists (int64 tree positions) for the ID matrix proxy rows
     std::vector<int64_t> act_cat;
@@ -814,7 +834,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       act_off[i] = (int64_t)act_cat.size();
       act_cat.insert(act_cat.end(), own[i].act.begin(), own[i].act.end());
     }
-    DeviceArena level_arena(size_t(64) << 20);
+    level_arenas.emplace_back(new DeviceArena(size_t(4) << 20));
+    DeviceArena& level_arena = *level_arenas.back();
     int64_t* act_dev = sg.up_to(level_arena, act_cat);
 
     // ---- processed boxes by colour, Morton order within a colour
@@ -1416,13 +1437,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       }
       for (auto& bp : plan) info.max_block = std::max(info.max_block, bp.m);
     }
-    sg.sync_reset();
-    {
-      int32_t hinfo = 0;
-      FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
-      if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out at level " + std::to_string(lev));
-      if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block X_RR at level " + std::to_string(lev));
-    }
     if (opts.verbose)
       fprintf(stderr, "[fmmlu] level %d: owners %d pairs %zu tiles %.1f MB live %lld\n", lev, nown,
               pairs.size(), pool_elems * 16.0 / 1e6, (long long)live_total);
@@ -1465,7 +1479,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     prev_pool = pool;
     own = std::move(next);
     first_level = false;
-    FMMLU_HIP(hipStreamSynchronize(st));
   }
 
   ht.mark(7);
@@ -1547,12 +1560,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       info.factor_bytes += 16 * (int64_t)n0 * n0;
     }
     sg.sync_reset();
-    if (prev_pool) FMMLU_HIP(hipFree(prev_pool));
     prev_pool = nullptr;
+    // the first zero pivot of any pivot block or of the top block (column + 1), or -1 if a
+    // cooperative barrier timed out
     int32_t hinfo = 0;
     FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
-    if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out (top block)");
-    if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular top block");
+    if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out");
+    if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block (X_RR or the top block)");
   }
   {
     std::vector<SolveBox> all;
