@@ -780,6 +780,25 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
 constexpr int kGjChunk = 16;
 constexpr int64_t kGjCoopSpin = int64_t(1) << 22;
 
+// Barrier of the workgroups of one matrix: a counter that each arrival bumps once, so the
+// k-th barrier completes at k * nwg. A bounded wait; on time-out info = -1.
+__device__ inline void gj_coop_barrier(const GjCoopTask& t, int target) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t spins = 0;
+    while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > kGjCoopSpin) {
+        __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restrict__ tasks, int ntasks) {
   constexpr int NW = NT / 64;
@@ -918,7 +937,8 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
         mv_src[v] = j0;
       }
     }
-    if (pn % nwg == w && own) {
+    // single workgroup: the panel goes back at once (several: after the barrier below)
+    if (nwg == 1 && own) {
 #pragma unroll
       for (int q = 0; q < kGjNb; ++q)
         if (q < nb) A[tid + (int64_t)(j0 + q) * lda] = a[q];
@@ -967,25 +987,22 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
       }
       __syncthreads();
     }
-    // all workgroups of the matrix meet before the next panel reads their columns
+    // All workgroups of the matrix meet before the next panel reads their columns. Only
+    // then does the panel's owner store the transformed panel: every workgroup reads the
+    // panel's columns when it starts the panel, and a workgroup that started late could
+    // otherwise read them half overwritten.
     if (nwg > 1) {
-      if (tid == 0) {
-        __threadfence();
-        __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        const int target = nwg * (pn + 1);
-        int64_t spins = 0;
-        while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-          if (++spins > kGjCoopSpin) {
-            __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        __threadfence();
+      gj_coop_barrier(t, nwg * (pn + 1));
+      if (pn % nwg == w && own) {
+#pragma unroll
+        for (int q = 0; q < kGjNb; ++q)
+          if (q < nb) A[tid + (int64_t)(j0 + q) * lda] = a[q];
       }
       __syncthreads();
     }
   }
+  // the last panel's store must be visible to every workgroup's unpermute below
+  if (nwg > 1) gj_coop_barrier(t, nwg * (npan + 1));
   // undo the column permutation: out[:, j] = A[:, idx[j]] for this workgroup's panels
   if (tid == 0) {
     for (int j = 0; j < n; ++j) idx[j] = j;
