@@ -196,6 +196,11 @@ struct Stage {
   DoubleHostStage host;
   hipStream_t st = nullptr;
   Profiler* prof = nullptr;
+  // the buffers are freed only once the stream's work on them has finished (also when an
+  // error unwinds the factorization); members are destroyed after this body runs
+  ~Stage() {
+    if (st) (void)hipStreamSynchronize(st);
+  }
   // switch to the other buffer at the start of a colour phase (see DoubleArena)
   void flip() {
     dev.flip();
@@ -658,13 +663,20 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   int pool_slot = 0;
   struct PoolGuard {
     void** p;
+    hipStream_t st;
     ~PoolGuard() {
+      (void)hipStreamSynchronize(st);
       for (int i = 0; i < 2; ++i)
         if (p[i]) (void)hipFree(p[i]);
     }
-  } pool_guard{pools};
+  } pool_guard{pools, st};
   // per-level device lists stay alive until the factorization has drained
   std::vector<std::unique_ptr<DeviceArena>> level_arenas;
+  // destroyed first: no buffer above is freed while kernels queued on st may still use it
+  struct DrainOnExit {
+    hipStream_t st;
+    ~DrainOnExit() { (void)hipStreamSynchronize(st); }
+  } drain_on_exit{st};
   std::unordered_map<int64_t, int64_t> prev_pair;  // key o1*nprev+o2 -> offset
   std::vector<Owner> prev_own;
   bool first_level = true;
@@ -723,7 +735,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       const int ps = pool_slot;
       pool_slot ^= 1;
       if (pool_cap[ps] < bytes) {
-        if (pools[ps]) FMMLU_HIP(hipFree(pools[ps]));
+        // The previous level's assembly, still queued on st, may be reading this pool. The
+        // stream is drained before the free: a free is not ordered with work on other
+        // (non-blocking) streams, and another thread's allocation could reuse the memory.
+        if (pools[ps]) {
+          FMMLU_HIP(hipStreamSynchronize(st));
+          FMMLU_HIP(hipFree(pools[ps]));
+        }
         pools[ps] = nullptr;
         pool_cap[ps] = 0;
         hipError_t e = hipMalloc(&pools[ps], bytes);
@@ -1351,28 +1369,50 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         SolvePhase ph;
         ph.box_begin = (int)box_base;
         ph.box_end = (int)boxes.size();
-        int64_t yo = 0, xo = 0, po = 0;
+        int64_t yo = 0, xo = 0, po = 0, xpo = 0, ypo = 0, tpo = 0;
         std::vector<std::pair<int32_t, int64_t>> contrib;  // (destination, y index)
         std::vector<SolveBox> db;
-        std::vector<SweepTask> ty, tp;
+        std::vector<SweepTask> txr, typ, tyr, tbp, tbt, tbf;
         for (int b = ph.box_begin; b < ph.box_end; ++b) {
           FactorBox& fb = boxes[b];
           const int lb = b - ph.box_begin;
+          SolveBox& d = fb.dev;
           fb.y_off = yo;
-          fb.dev.y_off = yo;
-          fb.dev.xr_off = xo;
-          fb.dev.p_off = po;
-          fb.dev.nchunk = (fb.nsn + kSweepCols - 1) / kSweepCols;
-          for (int k0 = 0; k0 < fb.nsn; k0 += kSweepRows)
-            ty.push_back(SweepTask{lb, k0, std::min(kSweepRows, fb.nsn - k0), 0});
-          for (int c = 0; c < fb.dev.nchunk; ++c)
-            tp.push_back(SweepTask{lb, c * kSweepCols, std::min(kSweepCols, fb.nsn - c * kSweepCols), c});
+          d.y_off = yo;
+          d.xr_off = xo;
+          d.p_off = po;
+          d.xrp_off = xpo;
+          d.yp_off = ypo;
+          d.tp_off = tpo;
+          d.nks = (fb.s + kSolveK - 1) / kSolveK;
+          d.nkr = (fb.r + kSolveKr - 1) / kSolveKr;
+          d.nchunk = (fb.nsn + kSolveK - 1) / kSolveK;
+          const int ngrp = (fb.r + kSolveOut - 1) / kSolveOut;
+          for (int c = 0; c < d.nks; ++c)
+            for (int g = 0; g < ngrp; ++g)
+              txr.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.s - c * kSolveK), c, g, 0});
+          for (int k0 = 0; k0 < fb.nsn; k0 += kSolveRows) {
+            const int kn = std::min(kSolveRows, fb.nsn - k0);
+            tyr.push_back(SweepTask{lb, k0, kn, 0, 0, 0});
+            for (int c = 0; c < d.nkr; ++c) typ.push_back(SweepTask{lb, k0, kn, c, 0, 0});
+          }
+          for (int c = 0; c < d.nchunk; ++c)
+            for (int g = 0; g < ngrp; ++g)
+              tbp.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.nsn - c * kSolveK), c, g, 0});
+          for (int l0 = 0; l0 < fb.s; l0 += kSolveRows) {
+            const int ln = std::min(kSolveRows, fb.s - l0);
+            tbf.push_back(SweepTask{lb, l0, ln, 0, 0, 0});
+            for (int c = 0; c < d.nkr; ++c) tbt.push_back(SweepTask{lb, l0, ln, c, 0, 0});
+          }
           ph.rmax = std::max(ph.rmax, fb.r);
           ph.smax = std::max(ph.smax, fb.s);
-          db.push_back(fb.dev);
+          db.push_back(d);
           yo += fb.nsn;
           xo += fb.r;
-          po += (int64_t)fb.dev.nchunk * fb.r;
+          po += (int64_t)d.nchunk * fb.r;
+          xpo += (int64_t)d.nks * fb.r;
+          ypo += (int64_t)d.nkr * fb.nsn;
+          tpo += (int64_t)d.nkr * fb.s;
         }
         // scatter lists: every S u N position of every box of the phase, summed in box order
         for (int q = 0; q < ne; ++q) {
@@ -1399,24 +1439,38 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           src.push_back(contrib[i].second);
         }
         if (!contrib.empty()) ptr.push_back((int64_t)src.size());
-        if ((size_t)(ph.rmax + ph.smax) * sizeof(zd) > 65536)
+        if ((size_t)ph.rmax * sizeof(zd) > 65536)
           throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(ph.rmax) +
                                         " DOFs exceeds the solve kernels' LDS bound (4096)");
         ph.ylen = yo;
         ph.xrlen = xo;
         ph.plen = po;
+        ph.xrplen = xpo;
+        ph.yplen = ypo;
+        ph.tplen = tpo;
         ph.nd = (int64_t)dst.size();
         ph.dboxes = sg.up_to(arena, db);
         ph.sc_dst = sg.up_to(arena, dst);
         ph.sc_ptr = sg.up_to(arena, ptr);
         ph.sc_src = sg.up_to(arena, src);
-        ph.dy = sg.up_to(arena, ty);
-        ph.dp = sg.up_to(arena, tp);
-        ph.ny = (int)ty.size();
-        ph.np = (int)tp.size();
+        ph.dxr = sg.up_to(arena, txr);
+        ph.dyp = sg.up_to(arena, typ);
+        ph.dyr = sg.up_to(arena, tyr);
+        ph.dbp = sg.up_to(arena, tbp);
+        ph.dbt = sg.up_to(arena, tbt);
+        ph.dbf = sg.up_to(arena, tbf);
+        ph.nxr = (int)txr.size();
+        ph.nyp = (int)typ.size();
+        ph.nyr = (int)tyr.size();
+        ph.nbp = (int)tbp.size();
+        ph.nbt = (int)tbt.size();
+        ph.nbf = (int)tbf.size();
         ymax = std::max(ymax, yo);
         xrmax = std::max(xrmax, xo);
         pmax = std::max(pmax, po);
+        xrpmax = std::max(xrpmax, xpo);
+        ypmax = std::max(ypmax, ypo);
+        tpmax = std::max(tpmax, tpo);
         phases.push_back(ph);
       }
       // live lists of eliminated boxes to the device (persistent for the level)
@@ -1600,6 +1654,9 @@ void FactorImpl::ensure_workspace() {
   wtop = arena.alloc_n<zd>((size_t)std::max<int64_t>((int64_t)n0 * (1 + nblk), 1));
   wmv = arena.alloc_n<zd>((size_t)n);
   wpart = arena.alloc_n<zd>((size_t)matvec_slices(n) * (size_t)n);
+  wxrp = arena.alloc_n<zd>((size_t)std::max<int64_t>(xrpmax, 1));
+  wyp = arena.alloc_n<zd>((size_t)std::max<int64_t>(ypmax, 1));
+  wtp = arena.alloc_n<zd>((size_t)std::max<int64_t>(tpmax, 1));
 }
 
 void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) {
@@ -1607,8 +1664,11 @@ void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) 
   launch_permute(bc, wx, order_dev, n, 1, st);
   // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
   for (auto& ph : phases) {
-    launch_solve_xr(ph.dboxes, ph.box_end - ph.box_begin, ph.smax, ph.rmax, wx, wxr, adj, f32, st);
-    launch_solve_y(ph.dboxes, ph.dy, ph.ny, ph.rmax, wxr, wy, adj, f32, st);
+    const int nb = ph.box_end - ph.box_begin;
+    launch_solve_xr_part(ph.dboxes, ph.dxr, ph.nxr, wx, wxrp, adj, f32, st);
+    launch_solve_xr_fin(ph.dboxes, nb, wx, wxr, wxrp, st);
+    launch_solve_y_part(ph.dboxes, ph.dyp, ph.nyp, wxr, wyp, adj, f32, st);
+    launch_solve_y_red(ph.dboxes, ph.dyr, ph.nyr, wyp, wy, st);
     launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
   }
   // D^{-1} (adjoint D^{-H}): all pivot blocks, then the top block
@@ -1616,8 +1676,11 @@ void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) 
   launch_solve_top(Ainv, n0, top_dev, wx, wtop, adj, st);
   // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
-    launch_solve_bpart(it->dboxes, it->dp, it->np, wx, wp, adj, f32, st);
-    launch_solve_bfin(it->dboxes, it->box_end - it->box_begin, it->rmax, wp, wx, adj, f32, st);
+    const int nb = it->box_end - it->box_begin;
+    launch_solve_bpart(it->dboxes, it->dbp, it->nbp, wx, wp, adj, f32, st);
+    launch_solve_bfin(it->dboxes, nb, wp, wx, wxr, st);
+    launch_solve_bt_part(it->dboxes, it->dbt, it->nbt, wxr, wtp, adj, f32, st);
+    launch_solve_bt_fin(it->dboxes, it->dbf, it->nbf, wtp, wx, st);
   }
   launch_permute(wx, xc, order_dev, n, 0, st);
 }
@@ -1677,6 +1740,8 @@ void FactorImpl::solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream
 }
 
 FactorImpl::~FactorImpl() {
+  // solves may still be running on any stream; the arenas are freed after the device drains
+  (void)hipDeviceSynchronize();
   for (int a = 0; a < 2; ++a) {
     if (gexec[a]) (void)hipGraphExecDestroy(gexec[a]);
     if (graph[a]) (void)hipGraphDestroy(graph[a]);

@@ -76,10 +76,11 @@ struct SolvePhase {
   int64_t* sc_ptr = nullptr;
   int64_t* sc_src = nullptr;
   int64_t nd = 0;
-  int64_t ylen = 0, xrlen = 0, plen = 0;
-  SweepTask* dy = nullptr;  // forward row chunks
-  SweepTask* dp = nullptr;  // backward column chunks
-  int ny = 0, np = 0;
+  int64_t ylen = 0, xrlen = 0, plen = 0, xrplen = 0, yplen = 0, tplen = 0;
+  // work items: forward x_R partials, y partials, y row reductions; backward partials,
+  // T-row partials, T-row reductions
+  SweepTask *dxr = nullptr, *dyp = nullptr, *dyr = nullptr, *dbp = nullptr, *dbt = nullptr, *dbf = nullptr;
+  int nxr = 0, nyp = 0, nyr = 0, nbp = 0, nbt = 0, nbf = 0;
   int rmax = 0, smax = 0;
 };
 
@@ -96,7 +97,7 @@ struct FactorImpl {
   std::vector<int64_t> order;  // host copy
   std::vector<FactorBox> boxes;
   std::vector<SolvePhase> phases;
-  int64_t ymax = 0, xrmax = 0, pmax = 0;
+  int64_t ymax = 0, xrmax = 0, pmax = 0, xrpmax = 0, ypmax = 0, tpmax = 0;
   SolveBox* all_boxes = nullptr;  // every factored box, for the diagonal step
   int nall = 0, rmax_all = 0;
   int n0 = 0;
@@ -112,6 +113,9 @@ struct FactorImpl {
   zd* wxr = nullptr;
   zd* wp = nullptr;
   zd* wpart = nullptr;  // matvec slice partials
+  zd* wxrp = nullptr;   // forward x_R partials
+  zd* wyp = nullptr;    // forward y partials
+  zd* wtp = nullptr;    // backward x_S partials
   // refinement workspace (allocated on the first refined solve)
   DeviceArena rarena{size_t(1) << 20};
   zd* rbuf = nullptr;

@@ -256,40 +256,58 @@ struct SolveBox {
   const void* Xi;     // r x r inverse pivot block
   const void* Lp;     // L = X_{(S u N) R} X_RR^{-1}: (s+nN) x r, ld = s+nN
   const void* UpT;    // U^T with U = X_RR^{-1} X_{R (S u N)}: (s+nN) x r, ld = s+nN
-  int32_t r, s, nsn, nchunk;  // nchunk: backward partial chunks
+  int32_t r, s, nsn;
+  int32_t nks;        // chunks of kSolveK over s (forward x_R partials)
+  int32_t nkr;        // chunks of kSolveKr over r (row-GEMV partials)
+  int32_t nchunk;     // chunks of kSolveK over s + nN (backward partials)
   int64_t y_off;      // this box's outputs in the forward scatter buffer
   int64_t xr_off;     // this box's x_R copy in the phase buffer
-  int64_t p_off;      // this box's backward partials (nchunk x r)
+  int64_t p_off;      // backward partials (nchunk x r)
+  int64_t xrp_off;    // forward x_R partials (nks x r)
+  int64_t yp_off;     // forward y partials (nkr x nsn)
+  int64_t tp_off;     // backward x_S partials (nkr x s)
 };
-// Work item of a box: rows [k0, k0 + kn) of its panel (forward), or columns (backward).
+// Work item of a sweep kernel: rows or columns [k0, k0 + kn) of box `box`; `chunk` is the
+// k-chunk (row GEMVs) and `grp` the group of kSolveOut outputs (column GEMVs).
 struct SweepTask {
-  int32_t box, k0, kn, chunk;
+  int32_t box, k0, kn, chunk, grp, pad;
 };
-// forward, per box: x_R -= op(T) x_S (T^T, adjoint T^H); copy to XR
-void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint, bool f32,
-                     hipStream_t st);
-// forward, per task: y = op(P) x_R on a row chunk (Lp, adjoint Up^H)
-void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
-                    zd* y, int adjoint, bool f32, hipStream_t st);
-// scatter: x[dst[d]] -= sum_{q in [ptr[d], ptr[d+1])} y[src[q]]
+constexpr int kSolveRows = 256;  // rows per row-GEMV work item
+constexpr int kSolveKr = 64;     // k-chunk of row GEMVs (over r)
+constexpr int kSolveK = 256;     // k-chunk of column GEMVs (over s or s + nN)
+constexpr int kSolveOut = 64;    // outputs per column-GEMV work item
+
+// forward: partials of op(T)^T x_S (T^T, adjoint T^H) per (box, s-chunk, output group)
+void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
+                          bool f32, hipStream_t st);
+// forward, per box: x_R -= sum of partials; copy to XR
+void launch_solve_xr_fin(const SolveBox* boxes, int nb, zd* x, zd* XR, const zd* Pxr, hipStream_t st);
+// forward: partials of op(P) x_R (Lp, adjoint conj(Up^T)) per (box, row chunk, k-chunk)
+void launch_solve_y_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Yp, int adjoint,
+                         bool f32, hipStream_t st);
+// forward: y = sum of partials per (box, row chunk)
+void launch_solve_y_red(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Yp, zd* y, hipStream_t st);
+// x[dst[d]] -= sum of y[src[q]] over ptr[d] <= q < ptr[d+1] (deterministic scatter)
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st);
-// diagonal: xR = Xi xR (adjoint: Xi^H xR), all boxes
+// diagonal: x_R = Xi x_R (adjoint Xi^H x_R) for every box
 void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, bool f32, hipStream_t st);
-// backward, per task: partial of op(P) x_SN over a column chunk (Up, adjoint Lp^H)
+// backward: partials of op(Q)^T x_SN (Up, adjoint Lp^H) per (box, column chunk, output group)
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
                         int adjoint, bool f32, hipStream_t st);
-// backward, per box: x_R -= sum of partials; x_S -= op(T) x_R (T, adjoint conj(T))
-void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint, bool f32,
-                       hipStream_t st);
-// top block: x[top] = Ainv x[top] (or Ainv^H); tmp >= n0 * (1 + ceil(n0 / 256)) entries
+// backward, per box: x_R -= sum of partials; copy to XR
+void launch_solve_bfin(const SolveBox* boxes, int nb, const zd* Pbuf, zd* x, zd* XR, hipStream_t st);
+// backward: partials of op(T) x_R (T, adjoint conj(T)) per (box, s-row chunk, k-chunk)
+void launch_solve_bt_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Pt, int adjoint,
+                          bool f32, hipStream_t st);
+// backward: x_S -= sum of partials per (box, s-row chunk)
+void launch_solve_bt_fin(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Pt, zd* x, hipStream_t st);
+// top block: x_t = Ainv x_t (adjoint Ainv^H); tmp holds n0 * (1 + nblk) entries
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
                       hipStream_t st);
-// permutations between original and tree order
+// permute: gather (dst[i] = src[map[i]]) or scatter (dst[map[i]] = src[i])
 void launch_permute(const zd* src, zd* dst, const int64_t* map, int64_t n, int gather,
                     hipStream_t st);
-constexpr int kSweepRows = 256;   // forward row chunk
-constexpr int kSweepCols = 256;   // backward column chunk
 
 // ---- stand-alone block of A~ (rows, cols: tree positions) ----
 void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64_t* cols,

@@ -86,103 +86,131 @@ __device__ inline void block_gemv_t(const FT* __restrict__ A, int64_t lda, int M
   }
 }
 
-// y[i] = sum_k A[k, i]^(*) v[k] for i < M, four outputs per wavefront at a time (lanes over k,
-// coalesced; sixteen independent loads per lane in flight). v must be in LDS.
+// Column GEMV partials: out[i] = sum_{k in [k0, k0+kn)} A[k, i]^(*) v[k] for the outputs of
+// one group, four per wavefront at a time, lanes over k (coalesced down columns of A), v in
+// LDS. kn <= kSolveK.
 template <class FT, class Emit>
-__device__ inline void block_gemv_t4(const FT* __restrict__ A, int64_t lda, int M, int K, bool conjA,
+__device__ inline void colgemv_group(const FT* __restrict__ A, int64_t lda, int i0, int i1, int kn, bool conjA,
                                      const zd* v, Emit emit) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i0 = 4 * wave; i0 < M; i0 += 16) {
+  for (int ib = i0 + 4 * wave; ib < i1; ib += 16) {
     zd acc[4] = {zd{0.0, 0.0}, zd{0.0, 0.0}, zd{0.0, 0.0}, zd{0.0, 0.0}};
-    for (int k0 = 0; k0 < K; k0 += 256) {
-      zd a[4][4];
+    zd a[4][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int k = k0 + lane + 64 * j;
-          a[q][j] = (i0 + q < M && k < K) ? widen(A[(int64_t)(i0 + q) * lda + k]) : zd{0.0, 0.0};
-        }
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int k = k0 + lane + 64 * j;
-        const zd vk = k < K ? v[k] : zd{0.0, 0.0};
+        const int k = lane + 64 * j;
+        a[q][j] = (ib + q < i1 && k < kn) ? widen(A[(int64_t)(ib + q) * lda + k]) : zd{0.0, 0.0};
+      }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (conjA)
-            zfmac(acc[q], a[q][j], vk);
-          else
-            zfma(acc[q], a[q][j], vk);
-        }
+    for (int j = 0; j < 4; ++j) {
+      const int k = lane + 64 * j;
+      const zd vk = k < kn ? v[k] : zd{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (conjA)
+          zfmac(acc[q], a[q][j], vk);
+        else
+          zfma(acc[q], a[q][j], vk);
       }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       acc[q].re = wave_sum(acc[q].re);
       acc[q].im = wave_sum(acc[q].im);
-      if (lane == 0 && i0 + q < M) emit(i0 + q, acc[q]);
+      if (lane == 0 && ib + q < i1) emit(ib + q, acc[q]);
     }
   }
 }
 
-// Forward, per box: x_R -= T^T x_S (adjoint T^H x_S). x_S and x_R are gathered into LDS first.
+// Row GEMV partial: sum_{k < kn} A[i, k]^(*) v[k] for one row i (thread per row; rows
+// consecutive across threads, so each k is one coalesced load), eight loads in flight.
 template <class FT>
-__global__ void __launch_bounds__(256) solve_xr_kernel(const SolveBox* __restrict__ boxes, zd* x,
-                                                       zd* XR, int adjoint, int smax) {
-  const SolveBox b = boxes[blockIdx.x];
-  extern __shared__ zd sh[];
-  zd* xs = sh;
-  zd* xr = sh + smax;
-  for (int k = threadIdx.x; k < b.s; k += 256) xs[k] = x[b.S[k]];
-  for (int k = threadIdx.x; k < b.r; k += 256) xr[k] = x[b.R[k]];
-  __syncthreads();
-  block_gemv_t4(static_cast<const FT*>(b.T), b.s, b.r, b.s, adjoint != 0, xs,
-                [&](int i, zd d) { xr[i] = zsub(xr[i], d); });
-  __syncthreads();
-  for (int i = threadIdx.x; i < b.r; i += 256) {
-    x[b.R[i]] = xr[i];
-    XR[b.xr_off + i] = xr[i];
+__device__ inline zd rowgemv(const FT* __restrict__ A, int64_t lda, int i, int kn, bool conjA, const zd* v) {
+  zd acc[4] = {zd{0.0, 0.0}, zd{0.0, 0.0}, zd{0.0, 0.0}, zd{0.0, 0.0}};
+  const FT* ar = A + i;
+  int k = 0;
+  for (; k + 7 < kn; k += 8) {
+    zd a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = widen(ar[(int64_t)(k + q) * lda]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (conjA)
+        zfmac(acc[q & 3], a[q], v[k + q]);
+      else
+        zfma(acc[q & 3], a[q], v[k + q]);
+    }
   }
+  for (; k < kn; ++k) {
+    const zd a = widen(ar[(int64_t)k * lda]);
+    if (conjA)
+      zfmac(acc[0], a, v[k]);
+    else
+      zfma(acc[0], a, v[k]);
+  }
+  return zadd(zadd(acc[0], acc[1]), zadd(acc[2], acc[3]));
 }
 
-// Forward, one row chunk of a box: y[i] = sum_k P[i, k] x_R[k] with P = Lp (adjoint: conj(U^T)),
-// P stored (s+nN) x r column-major; thread per row, four independent accumulators.
+// Forward: Pxr[c][i] = sum_{k in s-chunk c} op(T)[k, i] x_S[k] (T^T, adjoint T^H).
 template <class FT>
-__global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict__ boxes,
-                                                      const SweepTask* __restrict__ tasks,
-                                                      const zd* __restrict__ XR, zd* __restrict__ y,
-                                                      int adjoint) {
+__global__ void __launch_bounds__(256) solve_xr_part_kernel(const SolveBox* __restrict__ boxes,
+                                                            const SweepTask* __restrict__ tasks,
+                                                            const zd* __restrict__ x, zd* __restrict__ Pxr,
+                                                            int adjoint) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
-  extern __shared__ zd xr[];
-  for (int k = threadIdx.x; k < b.r; k += 256) xr[k] = XR[b.xr_off + k];
+  __shared__ zd xs[kSolveK];
+  for (int q = threadIdx.x; q < t.kn; q += 256) xs[q] = x[b.S[t.k0 + q]];
   __syncthreads();
-  zd* yb = y + b.y_off;
-  const FT* P = static_cast<const FT*>(adjoint ? b.UpT : b.Lp);
-  const int64_t ld = b.nsn;
-  for (int i = t.k0 + threadIdx.x; i < t.k0 + t.kn; i += 256) {
-    zd a0{0.0, 0.0}, a1{0.0, 0.0}, a2{0.0, 0.0}, a3{0.0, 0.0};
-    const FT* pr = P + i;
-    int k = 0;
-    if (!adjoint) {
-      for (; k + 3 < b.r; k += 4) {
-        zfma(a0, widen(pr[(int64_t)k * ld]), xr[k]);
-        zfma(a1, widen(pr[(int64_t)(k + 1) * ld]), xr[k + 1]);
-        zfma(a2, widen(pr[(int64_t)(k + 2) * ld]), xr[k + 2]);
-        zfma(a3, widen(pr[(int64_t)(k + 3) * ld]), xr[k + 3]);
-      }
-      for (; k < b.r; ++k) zfma(a0, widen(pr[(int64_t)k * ld]), xr[k]);
-    } else {
-      for (; k + 3 < b.r; k += 4) {
-        zfmac(a0, widen(pr[(int64_t)k * ld]), xr[k]);
-        zfmac(a1, widen(pr[(int64_t)(k + 1) * ld]), xr[k + 1]);
-        zfmac(a2, widen(pr[(int64_t)(k + 2) * ld]), xr[k + 2]);
-        zfmac(a3, widen(pr[(int64_t)(k + 3) * ld]), xr[k + 3]);
-      }
-      for (; k < b.r; ++k) zfmac(a0, widen(pr[(int64_t)k * ld]), xr[k]);
-    }
-    yb[i] = zadd(zadd(a0, a1), zadd(a2, a3));
+  zd* out = Pxr + b.xrp_off + (int64_t)(t.k0 / kSolveK) * b.r;
+  const int i0 = t.grp * kSolveOut, i1 = min(b.r, i0 + kSolveOut);
+  colgemv_group(static_cast<const FT*>(b.T) + t.k0, b.s, i0, i1, t.kn, adjoint != 0, xs,
+                [&](int i, zd d) { out[i] = d; });
+}
+
+// Forward, per box: x_R -= sum_c Pxr[c]; the result also goes to XR for the row GEMVs.
+__global__ void __launch_bounds__(256) solve_xr_fin_kernel(const SolveBox* __restrict__ boxes, zd* x,
+                                                           zd* __restrict__ XR, const zd* __restrict__ Pxr) {
+  const SolveBox b = boxes[blockIdx.x];
+  for (int i = threadIdx.x; i < b.r; i += 256) {
+    zd v = x[b.R[i]];
+    for (int c = 0; c < b.nks; ++c) v = zsub(v, Pxr[b.xrp_off + (int64_t)c * b.r + i]);
+    x[b.R[i]] = v;
+    XR[b.xr_off + i] = v;
   }
+}
+
+// Forward: Yp[c][i] = sum_{k in r-chunk c} P[i, k] x_R[k], P = Lp (adjoint: conj(U^T)).
+template <class FT>
+__global__ void __launch_bounds__(256) solve_y_part_kernel(const SolveBox* __restrict__ boxes,
+                                                           const SweepTask* __restrict__ tasks,
+                                                           const zd* __restrict__ XR, zd* __restrict__ Yp,
+                                                           int adjoint) {
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
+  __shared__ zd xr[kSolveKr];
+  const int kb = t.chunk * kSolveKr, kn = min(kSolveKr, b.r - kb);
+  for (int q = threadIdx.x; q < kn; q += 256) xr[q] = XR[b.xr_off + kb + q];
+  __syncthreads();
+  const FT* P = static_cast<const FT*>(adjoint ? b.UpT : b.Lp) + (int64_t)kb * b.nsn;
+  zd* out = Yp + b.yp_off + (int64_t)t.chunk * b.nsn;
+  const int i = t.k0 + threadIdx.x;
+  if (i < t.k0 + t.kn) out[i] = rowgemv(P, b.nsn, i, kn, adjoint != 0, xr);
+}
+
+// Forward: y[i] = sum_c Yp[c][i] for the rows of one (box, row chunk).
+__global__ void __launch_bounds__(256) solve_y_red_kernel(const SolveBox* __restrict__ boxes,
+                                                          const SweepTask* __restrict__ tasks,
+                                                          const zd* __restrict__ Yp, zd* __restrict__ y) {
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
+  const int i = t.k0 + threadIdx.x;
+  if (i >= t.k0 + t.kn) return;
+  zd v{0.0, 0.0};
+  for (int c = 0; c < b.nkr; ++c) v = zadd(v, Yp[b.yp_off + (int64_t)c * b.nsn + i]);
+  y[b.y_off + i] = v;
 }
 
 __global__ void __launch_bounds__(256) scatter_sub_kernel(const int32_t* __restrict__ dst,
@@ -214,8 +242,8 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
                  [&](int i, zd v) { x[b.R[i]] = v; });
 }
 
-// Backward partials over a chunk of S u N: out[i] = sum_{k in chunk} Q[k, i] x_SN[k], i < r,
-// with Q = U^T (adjoint: conj(Lp)), stored (s+nN) x r; wavefront per output, lanes over k.
+// Backward: Pbuf[c][i] = sum_{k in chunk c of S u N} Q[k, i] x_SN[k], Q = U^T (adjoint:
+// conj(Lp)), stored (s+nN) x r; per (box, chunk, output group).
 template <class FT>
 __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __restrict__ boxes,
                                                           const SweepTask* __restrict__ tasks,
@@ -223,30 +251,56 @@ __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __rest
                                                           int adjoint) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
-  __shared__ zd xsn[kSweepCols];
+  __shared__ zd xsn[kSolveK];
   for (int q = threadIdx.x; q < t.kn; q += 256) xsn[q] = x[b.SN[t.k0 + q]];
   __syncthreads();
   zd* out = Pbuf + b.p_off + (int64_t)t.chunk * b.r;
-  const FT* Q = static_cast<const FT*>(adjoint ? b.Lp : b.UpT);
-  block_gemv_t4(Q + t.k0, b.nsn, b.r, t.kn, adjoint != 0, xsn, [&](int i, zd d) { out[i] = d; });
+  const FT* Q = static_cast<const FT*>(adjoint ? b.Lp : b.UpT) + t.k0;
+  const int i0 = t.grp * kSolveOut, i1 = min(b.r, i0 + kSolveOut);
+  colgemv_group(Q, b.nsn, i0, i1, t.kn, adjoint != 0, xsn, [&](int i, zd d) { out[i] = d; });
 }
 
-template <class FT>
+// Backward, per box: x_R -= sum_c Pbuf[c]; the result also goes to XR.
 __global__ void __launch_bounds__(256) solve_bfin_kernel(const SolveBox* __restrict__ boxes,
-                                                         const zd* __restrict__ Pbuf, zd* x, int adjoint) {
+                                                         const zd* __restrict__ Pbuf, zd* x, zd* __restrict__ XR) {
   const SolveBox b = boxes[blockIdx.x];
-  extern __shared__ zd xr[];
-  __shared__ zd part[4][64];
   for (int i = threadIdx.x; i < b.r; i += 256) {
-    zd acc = x[b.R[i]];
-    for (int c = 0; c < b.nchunk; ++c) acc = zsub(acc, Pbuf[b.p_off + (int64_t)c * b.r + i]);
-    xr[i] = acc;
-    x[b.R[i]] = acc;
+    zd v = x[b.R[i]];
+    for (int c = 0; c < b.nchunk; ++c) v = zsub(v, Pbuf[b.p_off + (int64_t)c * b.r + i]);
+    x[b.R[i]] = v;
+    XR[b.xr_off + i] = v;
   }
+}
+
+// Backward: Pt[c][l] = sum_{k in r-chunk c} op(T)[l, k] x_R[k] (T, adjoint conj(T)), T: s x r.
+template <class FT>
+__global__ void __launch_bounds__(256) solve_bt_part_kernel(const SolveBox* __restrict__ boxes,
+                                                            const SweepTask* __restrict__ tasks,
+                                                            const zd* __restrict__ XR, zd* __restrict__ Pt,
+                                                            int adjoint) {
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
+  __shared__ zd xr[kSolveKr];
+  const int kb = t.chunk * kSolveKr, kn = min(kSolveKr, b.r - kb);
+  for (int q = threadIdx.x; q < kn; q += 256) xr[q] = XR[b.xr_off + kb + q];
   __syncthreads();
-  // x_S -= T x_R  (adjoint: conj(T) x_R); T: s x r
-  block_gemv_n(static_cast<const FT*>(b.T), b.s, b.s, b.r, adjoint != 0, [&](int k) { return xr[k]; },
-               [&](int l, zd v) { x[b.S[l]] = zsub(x[b.S[l]], v); }, part);
+  const FT* T = static_cast<const FT*>(b.T) + (int64_t)kb * b.s;
+  zd* out = Pt + b.tp_off + (int64_t)t.chunk * b.s;
+  const int l = t.k0 + threadIdx.x;
+  if (l < t.k0 + t.kn) out[l] = rowgemv(T, b.s, l, kn, adjoint != 0, xr);
+}
+
+// Backward: x_S -= sum_c Pt[c] for the rows of one (box, s-row chunk).
+__global__ void __launch_bounds__(256) solve_bt_fin_kernel(const SolveBox* __restrict__ boxes,
+                                                           const SweepTask* __restrict__ tasks,
+                                                           const zd* __restrict__ Pt, zd* x) {
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
+  const int l = t.k0 + threadIdx.x;
+  if (l >= t.k0 + t.kn) return;
+  zd v{0.0, 0.0};
+  for (int c = 0; c < b.nkr; ++c) v = zadd(v, Pt[b.tp_off + (int64_t)c * b.s + l]);
+  x[b.S[l]] = zsub(x[b.S[l]], v);
 }
 
 __global__ void __launch_bounds__(256) gather_top_kernel(const int32_t* __restrict__ top, int n0,
@@ -303,25 +357,62 @@ __global__ void __launch_bounds__(256) permute_kernel(const zd* __restrict__ src
 
 }  // namespace
 
-void launch_solve_xr(const SolveBox* boxes, int nb, int smax, int rmax, zd* x, zd* XR, int adjoint, bool f32,
-                     hipStream_t st) {
+
+
+#define FMMLU_FT_LAUNCH(kern, grid, lds, ...)                                      \
+  do {                                                                              \
+    if (f32)                                                                        \
+      hipLaunchKernelGGL(kern<zf>, dim3(grid), dim3(256), lds, st, __VA_ARGS__);    \
+    else                                                                            \
+      hipLaunchKernelGGL(kern<zd>, dim3(grid), dim3(256), lds, st, __VA_ARGS__);    \
+    FMMLU_HIP(hipGetLastError());                                                   \
+  } while (0)
+
+void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
+                          bool f32, hipStream_t st) {
+  if (nt <= 0) return;
+  FMMLU_FT_LAUNCH(solve_xr_part_kernel, nt, 0, boxes, tasks, x, Pxr, adjoint);
+}
+
+void launch_solve_xr_fin(const SolveBox* boxes, int nb, zd* x, zd* XR, const zd* Pxr, hipStream_t st) {
   if (nb <= 0) return;
-  const size_t lds = (size_t)(smax + rmax) * sizeof(zd);
-  if (f32)
-    hipLaunchKernelGGL(solve_xr_kernel<zf>, dim3(nb), dim3(256), lds, st, boxes, x, XR, adjoint, smax);
-  else
-    hipLaunchKernelGGL(solve_xr_kernel<zd>, dim3(nb), dim3(256), lds, st, boxes, x, XR, adjoint, smax);
+  hipLaunchKernelGGL(solve_xr_fin_kernel, dim3(nb), dim3(256), 0, st, boxes, x, XR, Pxr);
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XR,
-                    zd* y, int adjoint, bool f32, hipStream_t st) {
+void launch_solve_y_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Yp, int adjoint,
+                         bool f32, hipStream_t st) {
   if (nt <= 0) return;
-  const size_t lds = (size_t)rmax * sizeof(zd);
-  if (f32)
-    hipLaunchKernelGGL(solve_y_kernel<zf>, dim3(nt), dim3(256), lds, st, boxes, tasks, XR, y, adjoint);
-  else
-    hipLaunchKernelGGL(solve_y_kernel<zd>, dim3(nt), dim3(256), lds, st, boxes, tasks, XR, y, adjoint);
+  FMMLU_FT_LAUNCH(solve_y_part_kernel, nt, 0, boxes, tasks, XR, Yp, adjoint);
+}
+
+void launch_solve_y_red(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Yp, zd* y, hipStream_t st) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(solve_y_red_kernel, dim3(nt), dim3(256), 0, st, boxes, tasks, Yp, y);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
+                        int adjoint, bool f32, hipStream_t st) {
+  if (nt <= 0) return;
+  FMMLU_FT_LAUNCH(solve_bpart_kernel, nt, 0, boxes, tasks, x, Pbuf, adjoint);
+}
+
+void launch_solve_bfin(const SolveBox* boxes, int nb, const zd* Pbuf, zd* x, zd* XR, hipStream_t st) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL(solve_bfin_kernel, dim3(nb), dim3(256), 0, st, boxes, Pbuf, x, XR);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_solve_bt_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Pt, int adjoint,
+                          bool f32, hipStream_t st) {
+  if (nt <= 0) return;
+  FMMLU_FT_LAUNCH(solve_bt_part_kernel, nt, 0, boxes, tasks, XR, Pt, adjoint);
+}
+
+void launch_solve_bt_fin(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Pt, zd* x, hipStream_t st) {
+  if (nt <= 0) return;
+  hipLaunchKernelGGL(solve_bt_fin_kernel, dim3(nt), dim3(256), 0, st, boxes, tasks, Pt, x);
   FMMLU_HIP(hipGetLastError());
 }
 
@@ -343,26 +434,7 @@ void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoi
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
-                        int adjoint, bool f32, hipStream_t st) {
-  if (nt <= 0) return;
-  if (f32)
-    hipLaunchKernelGGL(solve_bpart_kernel<zf>, dim3(nt), dim3(256), 0, st, boxes, tasks, x, Pbuf, adjoint);
-  else
-    hipLaunchKernelGGL(solve_bpart_kernel<zd>, dim3(nt), dim3(256), 0, st, boxes, tasks, x, Pbuf, adjoint);
-  FMMLU_HIP(hipGetLastError());
-}
 
-void launch_solve_bfin(const SolveBox* boxes, int nb, int rmax, const zd* Pbuf, zd* x, int adjoint, bool f32,
-                       hipStream_t st) {
-  if (nb <= 0) return;
-  const size_t lds = (size_t)rmax * sizeof(zd);
-  if (f32)
-    hipLaunchKernelGGL(solve_bfin_kernel<zf>, dim3(nb), dim3(256), lds, st, boxes, Pbuf, x, adjoint);
-  else
-    hipLaunchKernelGGL(solve_bfin_kernel<zd>, dim3(nb), dim3(256), lds, st, boxes, Pbuf, x, adjoint);
-  FMMLU_HIP(hipGetLastError());
-}
 
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
                       hipStream_t st) {
