@@ -131,6 +131,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2500)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size kernel "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -147,6 +151,14 @@ def main():
     b = np.sqrt(s.weights) * synth.point_source_data(s.points, s.k)
     bd = torch.as_tensor(b).cuda()
     n = s.n
+    if args.copy_calib_mb > 0:
+        nel = args.copy_calib_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)  # an elementwise kernel: reads and writes each byte once
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_calib_mb} MiB read + {args.copy_calib_mb} MiB written")
+        del src, dst
 
     def step(profile):
         t = fm.Tree(s.points, 64)
@@ -243,8 +255,9 @@ def main():
         "class_ms_per_step": breakdown,
         "roofline": roof,
     }
-    log("float32 factors + float64 refinement")
-    out["fp32_refine"] = fp32_leg(s, bd, args.steps)
+    if not args.no_fp32:
+        log("float32 factors + float64 refinement")
+        out["fp32_refine"] = fp32_leg(s, bd, args.steps)
     if not args.no_batch:
         del f, x
         log("batched scatterers")

@@ -443,7 +443,6 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
       c.out = outs[i];
       c.n = tasks[i].n;
       c.lda = tasks[i].lda;
-      c.nwg = std::max(1, std::min(8, c.n / 64));
       small.push_back(c);
     } else {
       large.push_back(tasks[i]);
@@ -451,16 +450,35 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
     }
   }
   if (!small.empty()) {
-    int32_t* counters = sg.dev.alloc_n<int32_t>(small.size());
-    FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * small.size(), sg.st));
+    // per matrix: 2 npan + 1 synchronisation words of the cooperative kernel, zeroed
+    size_t nsync = 0;
+    for (auto& c : small) nsync += (size_t)gj_coop_sync_words(c.n);
+    int32_t* counters = sg.dev.alloc_n<int32_t>(nsync);
+    FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * nsync, sg.st));
     int nmax = 0;
+    size_t so = 0;
     for (size_t i = 0; i < small.size(); ++i) {
       small[i].piv = sg.dev.alloc_n<int32_t>(small[i].n);
       small[i].info = info_dev;
-      small[i].counter = counters + i;
+      small[i].counter = counters + so;
+      so += (size_t)gj_coop_sync_words(small[i].n);
       nmax = std::max(nmax, small[i].n);
     }
     const int cap = gj_coop_capacity(nmax);
+    // Workgroups per matrix: one per panel up to K, with K the largest that keeps the whole
+    // batch at one workgroup per compute unit (a matrix's time is its panel chain; fewer
+    // workgroups add each one's share of the column updates to that chain, and workgroups
+    // sharing a compute unit slow each other's redundant panel work).
+    auto npan_of = [](int n) { return (n + kGjBlock - 1) / kGjBlock; };
+    const int64_t budget = std::min(cap, gj_coop_cus());
+    int K = 1;
+    for (int k = 2; k <= kGjCoopMax / kGjBlock; ++k) {
+      int64_t tot = 0;
+      for (auto& c : small) tot += std::min(npan_of(c.n), k);
+      if (tot > budget) break;
+      K = k;
+    }
+    for (auto& c : small) c.nwg = std::min(npan_of(c.n), K);
     size_t b = 0;
     while (b < small.size()) {
       std::vector<GjCoopTask> grp;

@@ -202,12 +202,17 @@ struct GjCoopTask {
   zd* out;
   int32_t* piv;
   int32_t* info;
-  int32_t* counter;
+  int32_t* counter;  // gj_coop_sync_words(n) zeroed words
   int32_t n, lda, nwg, pad;
   int64_t unit_begin;
 };
+// synchronisation words of one matrix: panel-ready flags, panel-read counts, final count
+inline int gj_coop_sync_words(int n) { return 2 * ((n + kGjBlock - 1) / kGjBlock) + 1; }
 void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st);
+// workgroups of gj_coop that can be resident at once; compute units of the device
 int gj_coop_capacity(int nmax);
+int gj_coop_cus();
+constexpr int kGjCoopThreads = 256;  // threads per cooperative Gauss-Jordan workgroup
 // marks a factorization in progress for the lifetime of the object (cooperative launches are
 // serialised while more than one is active)
 struct ActiveFactorization {

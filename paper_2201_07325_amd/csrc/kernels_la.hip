@@ -768,28 +768,66 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
 }
 
 // Gauss-Jordan inversion of a batch of matrices of up to NT rows, several workgroups per
-// matrix, one launch for the whole inversion. Every workgroup of a matrix factors each
-// panel of kGjNb columns itself (one row per thread, in registers; identical arithmetic,
-// so identical results), then applies the panel to the columns it owns (panels assigned
-// round-robin): the panel's row exchanges, composed into at most 2 kGjNb moves, and the
-// update A[:, c] += A[:, J] W[:, c] - [rows J] W[:, c] with W = A[J, c] staged in LDS. The
-// owner of the panel's columns writes them back. The workgroups of a matrix then meet at a
-// counter (bounded wait; launched cooperatively so all are resident) before the next panel
-// reads columns another workgroup updated. Finally each workgroup gathers its share of the
-// inverse into out, undoing the column permutation.
+// matrix, one launch for the whole inversion. Pivoting is implicit: rows are never moved;
+// the pivot of column j is the unused row pi(j) of largest modulus (ties to the smaller
+// row), and the in-place result M satisfies inv(A)[j, c] = M[pi(j), pi^-1(c)]. Every
+// workgroup of a matrix factors each panel of kGjNb columns itself (one row per thread,
+// in registers; identical arithmetic, so identical results), then applies the panel to the
+// columns it owns (panels assigned round-robin):
+//   A[:, c] += T W[:, c] - E W[:, c],  W = A[pi(J), c] staged in LDS,
+// with T the transformed panel and E the rows pi(J). Finally each workgroup gathers its
+// share of the inverse into out.
+//
+// Workgroups of a matrix synchronise per panel through sync words (zeroed by the host;
+// 2 npan + 1 per matrix), not through full barriers:
+//   ready[p]  the owner of panel p has applied every earlier panel to p's columns. The
+//             owner updates the next panel's columns first (look-ahead) and raises the
+//             flag at once, so the rest of its update overlaps the next panel's pivoting;
+//   reads[p]  workgroups other than the owner that have loaded panel p: the owner stores
+//             the transformed panel only once all of them have it in registers;
+//   done      arrivals before the final gather, which reads every workgroup's columns.
+// Waits are bounded (cooperative launch: all workgroups are resident); on time-out
+// info = -1.
 constexpr int kGjChunk = 16;
 constexpr int64_t kGjCoopSpin = int64_t(1) << 22;
 
-// Barrier of the workgroups of one matrix: a counter that each arrival bumps once, so the
-// k-th barrier completes at k * nwg. A bounded wait; on time-out info = -1.
-__device__ inline void gj_coop_barrier(const GjCoopTask& t, int target) {
+// 32-bit lane permutation of a wave (DPP) applied to a double and an int
+template <int CTRL>
+__device__ inline void gj_dpp(double& v, int& i) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int ii = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  const double ov = __hiloint2double(hi, lo);
+  if (gj_better(ov, ii, v, i)) {
+    v = ov;
+    i = ii;
+  }
+}
+
+// (value, row) with the largest value, ties to the smaller row, in every lane of the wave:
+// quads (DPP quad_perm), half rows and rows of 16 (DPP mirrors), then across rows.
+__device__ inline void gj_wave_argmax(double& v, int& i) {
+  gj_dpp<0xB1>(v, i);   // quad_perm [1,0,3,2]
+  gj_dpp<0x4E>(v, i);   // quad_perm [2,3,0,1]
+  gj_dpp<0x141>(v, i);  // row_half_mirror
+  gj_dpp<0x140>(v, i);  // row_mirror
+  for (int o = 16; o <= 32; o <<= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(i, o, 64);
+    if (gj_better(ov, oi, v, i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+}
+
+// thread 0 waits until *w >= target, then the workgroup continues (acquire)
+__device__ inline void gj_wait_at_least(int32_t* w, int target, int32_t* info) {
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     int64_t spins = 0;
-    while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (++spins > kGjCoopSpin) {
-        __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
       __builtin_amdgcn_s_sleep(1);
@@ -799,9 +837,32 @@ __device__ inline void gj_coop_barrier(const GjCoopTask& t, int target) {
   __syncthreads();
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restrict__ tasks, int ntasks) {
-  constexpr int NW = NT / 64;
+// after a workgroup barrier: thread 0 publishes the workgroup's prior memory operations
+__device__ inline void gj_signal(int32_t* w) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_fetch_add(w, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// complex helpers as fused multiply-adds (four per complex product)
+__device__ inline void gj_fma(zd& acc, const zd& a, const zd& b) {  // acc += a b
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+__device__ inline zd gj_fms(const zd& a, const zd& f, const zd& c) {  // a - f c
+  return zd{fma(-f.re, c.re, fma(f.im, c.im, a.re)), fma(-f.re, c.im, fma(-f.im, c.re, a.im))};
+}
+__device__ inline zd gj_mul(const zd& a, const zd& b) {
+  return zd{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+
+// kGjCoopThreads threads per workgroup, RPT rows per thread (rows tid + r kGjCoopThreads)
+template <int RPT>
+__global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTask* __restrict__ tasks, int ntasks) {
+  constexpr int NT = kGjCoopThreads, NW = NT / 64, NR = NT * RPT;
   const int64_t u = blockIdx.x;
   const GjCoopTask t = tasks[find_task(tasks, ntasks, u)];
   const int w = (int)(u - t.unit_begin);
@@ -810,214 +871,188 @@ __global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restric
   const int64_t lda = t.lda;
   zd* A = t.A;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const bool own = tid < n;
-  __shared__ double bv[2][NW];
-  __shared__ int bi[2][NW];
-  __shared__ zd prow[2][kGjNb], rowgc[2][kGjNb];
-  __shared__ int pivl[NT], idx[NT];
-  __shared__ int mv_dst[2 * kGjNb], mv_src[2 * kGjNb], rows[2 * kGjNb], cur[2 * kGjNb];
+  // per column: each wave's best candidate (value, row, the row itself); two slots
+  // alternate between even and odd columns
+  __shared__ double cv[2][NW];
+  __shared__ int ci[2][NW];
+  __shared__ zd crow[2][NW][kGjNb];
+  __shared__ int pivl[NR], idx[NR];
   __shared__ zd Ws[kGjNb][kGjChunk + 1];
-  __shared__ zd Mv[kGjChunk][2 * kGjNb];
   const int npan = (n + kGjNb - 1) / kGjNb;
+  int32_t* ready = t.counter;
+  int32_t* reads = t.counter + npan;
+  int32_t* done = t.counter + 2 * npan;
+  bool used[RPT];  // the row has been a pivot
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) used[r] = false;
+
+  // apply panel (j0, nb) to the columns of panel pc; myq[r]: row r is pi(j0 + myq[r]), or -1
+  auto update_panel = [&](int pc, int j0, int nb, const zd (&a)[RPT][kGjNb], const int (&myq)[RPT]) {
+    const int c0 = pc * kGjNb;
+    for (int e = tid; e < kGjNb * kGjChunk; e += NT) {
+      const int q = e % kGjNb, cc = e / kGjNb, c = c0 + cc;
+      Ws[q][cc] = (q < nb && c < n) ? A[pivl[j0 + q] + (int64_t)c * lda] : zd{0.0, 0.0};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int row = tid + r * NT;
+      if (row < n) {
+        zd acc[kGjChunk];
+#pragma unroll
+        for (int cc = 0; cc < kGjChunk; ++cc) {
+          const int c = c0 + cc;
+          acc[cc] = (c < n) ? A[row + (int64_t)c * lda] : zd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int cc = 0; cc < kGjChunk; ++cc) {
+#pragma unroll
+          for (int q = 0; q < kGjNb; ++q) gj_fma(acc[cc], a[r][q], Ws[q][cc]);
+          if (myq[r] >= 0) acc[cc] = zsub(acc[cc], Ws[myq[r]][cc]);
+        }
+#pragma unroll
+        for (int cc = 0; cc < kGjChunk; ++cc) {
+          const int c = c0 + cc;
+          if (c < n) A[row + (int64_t)c * lda] = acc[cc];
+        }
+      }
+    }
+    __syncthreads();
+  };
+
   for (int pn = 0; pn < npan; ++pn) {
     const int j0 = pn * kGjNb, nb = min(kGjNb, n - j0);
-    zd a[kGjNb];
+    const int owner = pn % nwg;
+    // panel pn must be final; its owner made it so itself
+    if (nwg > 1 && pn > 0 && owner != w) gj_wait_at_least(ready + pn, 1, t.info);
+    zd a[RPT][kGjNb];
 #pragma unroll
-    for (int q = 0; q < kGjNb; ++q) a[q] = (own && q < nb) ? A[tid + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
-    // two barriers per column: LDS slots alternate between even and odd columns, so the next
-    // column's writes never meet this column's reads. The column loop is unrolled so that
-    // the register row is indexed by constants only.
+    for (int r = 0; r < RPT; ++r) {
+      const int row = tid + r * NT;
+#pragma unroll
+      for (int q = 0; q < kGjNb; ++q)
+        a[r][q] = (row < n && q < nb) ? A[row + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
+    }
+    if (nwg > 1 && owner != w) {
+      __syncthreads();  // every thread's loads of the panel have completed
+      gj_signal(reads + pn);
+    }
+    int myq[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) myq[r] = -1;
+    // one workgroup barrier per column; the column loop is unrolled so that the register
+    // rows are indexed by constants only
 #pragma unroll
     for (int j = 0; j < kGjNb; ++j) {
       if (j < nb) {
         const int gc = j0 + j, par = j & 1;
         double best = -1.0;
         int besti = 0x7fffffff;
-        if (own && tid >= gc) {
-          best = zabs2(a[j]);
-          besti = tid;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-          const double ov = __shfl_xor(best, o, 64);
-          const int oi = __shfl_xor(besti, o, 64);
-          if (gj_better(ov, oi, best, besti)) {
-            best = ov;
-            besti = oi;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int row = tid + r * NT;
+          if (row < n && !used[r]) {
+            const double v = zabs2(a[r][j]);
+            if (gj_better(v, row, best, besti)) {
+              best = v;
+              besti = row;
+            }
           }
         }
+        gj_wave_argmax(best, besti);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if (besti == tid + r * NT) {
+#pragma unroll
+            for (int q = 0; q < kGjNb; ++q) crow[par][wave][q] = a[r][q];
+          }
         if (lane == 0) {
-          bv[par][wave] = best;
-          bi[par][wave] = besti;
+          cv[par][wave] = best;
+          ci[par][wave] = besti;
         }
         __syncthreads();
-        double b = bv[par][0];
-        int p = bi[par][0];
+        double b = cv[par][0];
+        int p = ci[par][0], pw = 0;
 #pragma unroll
         for (int q = 1; q < NW; ++q)
-          if (gj_better(bv[par][q], bi[par][q], b, p)) {
-            b = bv[par][q];
-            p = bi[par][q];
+          if (gj_better(cv[par][q], ci[par][q], b, p)) {
+            b = cv[par][q];
+            p = ci[par][q];
+            pw = q;
           }
-        if (p >= n) p = gc;
-        if (tid == p) {
-#pragma unroll
-          for (int q = 0; q < kGjNb; ++q) prow[par][q] = a[q];
-        }
-        if (tid == gc) {
-#pragma unroll
-          for (int q = 0; q < kGjNb; ++q) rowgc[par][q] = a[q];
-        }
+        // n - gc > 0 rows remain unused, so some wave has a candidate and p < n
         if (tid == 0) pivl[gc] = p;
         if (w == 0 && tid == 0) {
           t.piv[gc] = p;
           if (!(b > 0.0) && *t.info == 0) *t.info = gc + 1;
         }
-        __syncthreads();
-        if (p != gc) {
-          if (tid == gc) {
+        zd pr[kGjNb];
 #pragma unroll
-            for (int q = 0; q < kGjNb; ++q) a[q] = prow[par][q];
-          } else if (tid == p) {
+        for (int q = 0; q < kGjNb; ++q) pr[q] = crow[par][pw][q];
+        const double d2 = zabs2(pr[j]);
+        const double s = d2 > 0.0 ? 1.0 / d2 : 0.0;
+        const zd inv{pr[j].re * s, -pr[j].im * s};
 #pragma unroll
-            for (int q = 0; q < kGjNb; ++q) a[q] = rowgc[par][q];
-          }
-        }
-        const zd pv = prow[par][j];
-        const zd inv = (zabs2(pv) > 0.0) ? zdiv(zd{1.0, 0.0}, pv) : zd{0.0, 0.0};
-        if (tid == gc) {
+        for (int r = 0; r < RPT; ++r) {
+          const int row = tid + r * NT;
+          if (row == p) {
+            used[r] = true;
+            myq[r] = j;
 #pragma unroll
-          for (int q = 0; q < kGjNb; ++q) a[q] = (q == j) ? inv : zmul(prow[par][q], inv);
-        } else if (own) {
-          const zd fi = zmul(a[j], inv);
+            for (int q = 0; q < kGjNb; ++q) a[r][q] = (q == j) ? inv : gj_mul(a[r][q], inv);
+          } else if (row < n) {
+            const zd fi = gj_mul(a[r][j], inv);
 #pragma unroll
-          for (int q = 0; q < kGjNb; ++q) {
-            if (q == j)
-              a[q] = zd{-fi.re, -fi.im};
-            else
-              a[q] = zsub(a[q], zmul(fi, prow[par][q]));
+            for (int q = 0; q < kGjNb; ++q) a[r][q] = (q == j) ? zd{-fi.re, -fi.im} : gj_fms(a[r][q], fi, pr[q]);
           }
         }
       }
     }
     __syncthreads();
-    // compose the panel's exchanges; unused moves take row j0 onto itself and are applied
-    // first, so a real move into row j0 lands last
-    if (tid == 0) {
-      int nr = 0;
-      for (int q = 0; q < nb; ++q) {
-        const int g = j0 + q, pq = pivl[g];
-        int ig = -1, ip = -1;
-        for (int v = 0; v < nr; ++v) {
-          if (rows[v] == g) ig = v;
-          if (rows[v] == pq) ip = v;
-        }
-        if (ig < 0) {
-          rows[nr] = g;
-          cur[nr] = g;
-          ig = nr++;
-        }
-        if (ip < 0) {
-          rows[nr] = pq;
-          cur[nr] = pq;
-          ip = nr++;
-        }
-        const int x = cur[ig];
-        cur[ig] = cur[ip];
-        cur[ip] = x;
-      }
-      int nm = 0;
-      for (int v = 0; v < nr; ++v)
-        if (cur[v] != rows[v]) {
-          mv_dst[nm] = rows[v];
-          mv_src[nm] = cur[v];
-          ++nm;
-        }
-      for (int v = nm; v < 2 * kGjNb; ++v) {
-        mv_dst[v] = j0;
-        mv_src[v] = j0;
-      }
-    }
-    // single workgroup: the panel goes back at once (several: after the barrier below)
-    if (nwg == 1 && own) {
+    // the owner stores the transformed panel once every other workgroup has loaded it
+    if (owner == w) {
+      if (nwg > 1) gj_wait_at_least(reads + pn, nwg - 1, t.info);
 #pragma unroll
-      for (int q = 0; q < kGjNb; ++q)
-        if (q < nb) A[tid + (int64_t)(j0 + q) * lda] = a[q];
-    }
-    __syncthreads();
-    // the columns this workgroup owns, one panel-width chunk at a time
-    for (int pc = w; pc < npan; pc += nwg) {
-      if (pc == pn) continue;
-      const int c0 = pc * kGjNb;
-      // row exchanges: all loads to LDS, then the stores (unused moves first)
-      for (int e = tid; e < kGjChunk * 2 * kGjNb; e += NT) {
-        const int cc = e / (2 * kGjNb), v = e % (2 * kGjNb), c = c0 + cc;
-        if (c < n) Mv[cc][v] = A[mv_src[v] + (int64_t)c * lda];
-      }
-      __syncthreads();
-      if (tid < kGjChunk && c0 + tid < n) {
-        zd* col = A + (int64_t)(c0 + tid) * lda;
-        for (int v = 2 * kGjNb - 1; v >= 0; --v) col[mv_dst[v]] = Mv[tid][v];
-      }
-      __syncthreads();
-      for (int e = tid; e < kGjNb * kGjChunk; e += NT) {
-        const int q = e % kGjNb, cc = e / kGjNb, c = c0 + cc;
-        Ws[q][cc] = (q < nb && c < n) ? A[(j0 + q) + (int64_t)c * lda] : zd{0.0, 0.0};
-      }
-      __syncthreads();
-      if (own) {
-        zd acc[kGjChunk];
+      for (int r = 0; r < RPT; ++r) {
+        const int row = tid + r * NT;
+        if (row < n) {
 #pragma unroll
-        for (int cc = 0; cc < kGjChunk; ++cc) {
-          const int c = c0 + cc;
-          acc[cc] = (c < n) ? A[tid + (int64_t)c * lda] : zd{0.0, 0.0};
-        }
-        const int qi = tid - j0;
-        const bool inJ = qi >= 0 && qi < nb;
-#pragma unroll
-        for (int cc = 0; cc < kGjChunk; ++cc) {
-#pragma unroll
-          for (int q = 0; q < kGjNb; ++q) zfma(acc[cc], a[q], Ws[q][cc]);
-          if (inJ) acc[cc] = zsub(acc[cc], Ws[qi][cc]);
-        }
-#pragma unroll
-        for (int cc = 0; cc < kGjChunk; ++cc) {
-          const int c = c0 + cc;
-          if (c < n) A[tid + (int64_t)c * lda] = acc[cc];
+          for (int q = 0; q < kGjNb; ++q)
+            if (q < nb) A[row + (int64_t)(j0 + q) * lda] = a[r][q];
         }
       }
       __syncthreads();
     }
-    // All workgroups of the matrix meet before the next panel reads their columns. Only
-    // then does the panel's owner store the transformed panel: every workgroup reads the
-    // panel's columns when it starts the panel, and a workgroup that started late could
-    // otherwise read them half overwritten.
-    if (nwg > 1) {
-      gj_coop_barrier(t, nwg * (pn + 1));
-      if (pn % nwg == w && own) {
-#pragma unroll
-        for (int q = 0; q < kGjNb; ++q)
-          if (q < nb) A[tid + (int64_t)(j0 + q) * lda] = a[q];
-      }
-      __syncthreads();
+    // look-ahead: the next panel's columns first, then its flag, then the other columns
+    const int la = pn + 1;
+    if (la < npan && la % nwg == w) {
+      update_panel(la, j0, nb, a, myq);
+      if (nwg > 1) gj_signal(ready + la);
     }
+    for (int pc = w; pc < npan; pc += nwg)
+      if (pc != pn && pc != la) update_panel(pc, j0, nb, a, myq);
   }
-  // the last panel's store must be visible to every workgroup's unpermute below
-  if (nwg > 1) gj_coop_barrier(t, nwg * (npan + 1));
-  // undo the column permutation: out[:, j] = A[:, idx[j]] for this workgroup's panels
-  if (tid == 0) {
-    for (int j = 0; j < n; ++j) idx[j] = j;
-    for (int gc = n - 1; gc >= 0; --gc) {
-      const int pq = pivl[gc];
-      const int x = idx[gc];
-      idx[gc] = idx[pq];
-      idx[pq] = x;
-    }
+  // every workgroup's columns are final before any reads them below
+  if (nwg > 1) {
+    __syncthreads();
+    gj_signal(done);
+    gj_wait_at_least(done, nwg, t.info);
+  }
+  // inv(A)[j, c] = M[pi(j), pi^-1(c)]: this workgroup's columns of out
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int row = tid + r * NT;
+    if (row < n) idx[pivl[row]] = row;
   }
   __syncthreads();
-  if (own)
-    for (int pc = w; pc < npan; pc += nwg)
-      for (int j = pc * kGjNb; j < min(n, pc * kGjNb + kGjNb); ++j)
-        t.out[tid + (int64_t)j * n] = A[tid + (int64_t)idx[j] * lda];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int row = tid + r * NT;
+    if (row < n)
+      for (int pc = w; pc < npan; pc += nwg)
+        for (int c = pc * kGjNb; c < min(n, pc * kGjNb + kGjNb); ++c)
+          t.out[row + (int64_t)c * n] = A[pivl[row] + (int64_t)idx[c] * lda];
+  }
 }
 
 // Row swaps of the panel applied to columns outside J. grid.x = task, grid.y = column chunk.
@@ -1335,16 +1370,16 @@ void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStrea
 
 void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st) {
   if (ntasks <= 0 || nwg_total <= 0) return;
-  if (nmax > 512) throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
+  if (nmax > kGjCoopMax) throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
   void* args[] = {(void*)&tasks, (void*)&ntasks};
   coop_launch(
       [&]() {
-        if (nmax <= 256)
-          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<256>),
-                                               dim3((unsigned)nwg_total), dim3(256), args, 0, st));
+        if (nmax <= kGjCoopThreads)
+          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<1>),
+                                               dim3((unsigned)nwg_total), dim3(kGjCoopThreads), args, 0, st));
         else
-          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<512>),
-                                               dim3((unsigned)nwg_total), dim3(512), args, 0, st));
+          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<2>),
+                                               dim3((unsigned)nwg_total), dim3(kGjCoopThreads), args, 0, st));
       },
       st);
   FMMLU_HIP(hipGetLastError());
@@ -1354,12 +1389,12 @@ int gj_coop_capacity(int nmax) {
   int dev = 0, per_cu = 0, cus = 0;
   FMMLU_HIP(hipGetDevice(&dev));
   FMMLU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  if (nmax <= 256)
-    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<256>),
-                                                           256, 0));
+  if (nmax <= kGjCoopThreads)
+    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<1>),
+                                                           kGjCoopThreads, 0));
   else
-    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<512>),
-                                                           512, 0));
+    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<2>),
+                                                           kGjCoopThreads, 0));
   return per_cu * cus;
 }
 
@@ -1370,6 +1405,13 @@ int gj_panel_capacity() {
   FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_panel_kernel),
                                                          kGjPanelRows, 0));
   return per_cu * cus;
+}
+
+int gj_coop_cus() {
+  int dev = 0, cus = 0;
+  FMMLU_HIP(hipGetDevice(&dev));
+  FMMLU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return cus;
 }
 
 void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st) {
