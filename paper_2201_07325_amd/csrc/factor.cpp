@@ -137,9 +137,27 @@ int64_t gap_units(const Owner& a, const Owner& b) {
   return std::max<int64_t>(g, 0);
 }
 
+// Close owners of each owner (gap <= 1 box) in ascending order, with the offsets of their
+// pair tiles in the level's tile pool.
+struct PairIndex {
+  std::vector<int64_t> beg{0};  // owner a's pairs: [beg[a], beg[a + 1])
+  std::vector<int32_t> ids;
+  std::vector<int64_t> off;
+  int64_t find(int a, int b) const {  // offset of tile (a, b), or -1
+    const auto first = ids.begin() + beg[a], last = ids.begin() + beg[a + 1];
+    const auto it = std::lower_bound(first, last, b);
+    return (it != last && *it == b) ? off[it - ids.begin()] : -1;
+  }
+  int64_t at(int a, int b) const {
+    const int64_t o = find(a, b);
+    if (o < 0) throw Error(FMMLU_EINVAL, "internal: tile of a pair that is not close");
+    return o;
+  }
+};
+
 // Host wall-clock accumulators for the verbose report.
 struct HostTimers {
-  double t[8] = {0};
+  double t[9] = {0};
   Clock::time_point last = Clock::now();
   void mark(int i) {
     auto now = Clock::now();
@@ -272,9 +290,10 @@ struct GemmBatch {
     for (auto& g : s) segs.push_back(g);
     tasks.push_back(t);
   }
-  // C_part[k] = alpha * A^op B over K chunk k (k < ceil(K / kchunk)); partials at stride pstride
+  // C_part[k] = alpha * A^op B over K chunk k (k < ceil(K / kchunk)); partials at stride pstride.
+  // lower (M == N): only the output tiles on or below the diagonal are formed.
   void add_split(zd* Cpart, int ldc, int M, int N, const zd* A, int lda, const zd* B, int ldb, int K,
-                 int kchunk, int64_t pstride) {
+                 int kchunk, int64_t pstride, bool lower = false) {
     if (M <= 0 || N <= 0 || K <= 0) return;
     const int nsplit = (K + kchunk - 1) / kchunk;
     GemmTask t{};
@@ -285,11 +304,12 @@ struct GemmBatch {
     t.seg_begin = (int32_t)segs.size();
     t.nseg = 1;
     t.kchunk = kchunk;
+    t.lower = lower && M == N ? 1 : 0;
     t.part_stride = pstride;
     t.alpha_re = 1.0;
     t.beta = 0.0;
     t.unit_begin = units;
-    units += gemm_units(M, N) * nsplit;
+    units += gemm_task_tiles(M, N, t.lower) * nsplit;
     segs.push_back(GemmSeg{A, B, lda, ldb, K, 0});
     tasks.push_back(t);
   }
@@ -655,7 +675,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
 
   // ---- initial owners: every non-empty leaf, points in tree order (contiguous)
   std::vector<Owner> own;
-  std::unordered_map<int, int> by_box;
   for (int b = 0; b < (int)tree.nboxes(); ++b) {
     if (!tree.is_leaf(b) || tree.npts(b) == 0) continue;
     Owner o;
@@ -695,31 +714,47 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     hipStream_t st;
     ~DrainOnExit() { (void)hipStreamSynchronize(st); }
   } drain_on_exit{st};
-  std::unordered_map<int64_t, int64_t> prev_pair;  // key o1*nprev+o2 -> offset
+  PairIndex prev_pidx;  // pairs of the previous level's owners
   std::vector<Owner> prev_own;
   bool first_level = true;
   int32_t* info_dev = arena.alloc_n<int32_t>(1);
   FMMLU_HIP(hipMemsetAsync(info_dev, 0, sizeof(int32_t), st));
 
-  auto owner_lookup = [&](int lev, int64_t x, int64_t y, int64_t z) -> int {
-    // owner containing level-lev cell (x,y,z) with level <= lev; -1 if none
+  // Owner boxes are disjoint; at the finest depth D each covers the Morton key range
+  // [klo, khi). The owner containing a cell of level lev is the one whose range holds the
+  // cell's first key, if that owner's level is <= lev (else the cell is split among finer
+  // owners, or holds none).
+  const int D = std::max(tree.nlevels - 1, 0);
+  std::vector<uint64_t> klo, khi;
+  std::vector<int> kown;  // owners by ascending klo
+  auto index_owners = [&](const std::vector<Owner>& ow) {
+    const int no = (int)ow.size();
+    klo.resize(no);
+    khi.resize(no);
+    kown.resize(no);
+    for (int i = 0; i < no; ++i) {
+      const int sh = D - ow[i].level;
+      klo[i] = morton3((uint32_t)(ow[i].c[0] << sh), (uint32_t)(ow[i].c[1] << sh), (uint32_t)(ow[i].c[2] << sh));
+      khi[i] = klo[i] + (uint64_t(1) << (3 * sh));
+      kown[i] = i;
+    }
+    std::sort(kown.begin(), kown.end(), [&](int a, int b) { return klo[a] < klo[b]; });
+  };
+  auto owner_lookup = [&](const std::vector<Owner>& ow, int lev, int64_t x, int64_t y, int64_t z) -> int {
     const int64_t lim = int64_t(1) << lev;
     if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
-    for (int l = lev; l >= 0; --l) {
-      const int sh = lev - l;
-      const int b = tree.find(l, x >> sh, y >> sh, z >> sh);
-      if (b < 0) continue;
-      auto it = by_box.find(b);
-      return it == by_box.end() ? -1 : it->second;
-    }
-    return -1;
+    const int sh = D - lev;
+    const uint64_t key = morton3((uint32_t)(x << sh), (uint32_t)(y << sh), (uint32_t)(z << sh));
+    auto it = std::upper_bound(kown.begin(), kown.end(), key, [&](uint64_t k, int o) { return k < klo[o]; });
+    if (it == kown.begin()) return -1;
+    const int o = *(it - 1);
+    return (key < khi[o] && ow[o].level <= lev) ? o : -1;
   };
 
   HostTimers ht;
   for (int lev = tree.nlevels - 1; lev >= 2; --lev) {
     const int nown = (int)own.size();
-    by_box.clear();
-    for (int i = 0; i < nown; ++i) by_box[own[i].box] = i;
+    index_owners(own);
     // ---- close pairs of owners and their tiles
     std::vector<std::vector<int>> close(nown);
     for (int i = 0; i < nown; ++i) {
@@ -727,13 +762,14 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       for (int dz = -2; dz <= 2; ++dz)
         for (int dy = -2; dy <= 2; ++dy)
           for (int dx = -2; dx <= 2; ++dx) {
-            const int p = owner_lookup(o.level, o.c[0] + dx, o.c[1] + dy, o.c[2] + dz);
+            const int p = owner_lookup(own, o.level, o.c[0] + dx, o.c[1] + dy, o.c[2] + dz);
             if (p < 0) continue;
             close[i].push_back(p);
             close[p].push_back(i);
           }
     }
-    std::unordered_map<int64_t, int64_t> pair_off;
+    PairIndex pidx;
+    pidx.beg.assign(1, 0);
     int64_t pool_elems = 0;
     std::vector<std::pair<int, int>> pairs;
     for (int i = 0; i < nown; ++i) {
@@ -742,11 +778,14 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       v.erase(std::unique(v.begin(), v.end()), v.end());
       for (int p : v) {
         if (gap_units(own[i], own[p]) > 1) continue;
-        pair_off[(int64_t)i * nown + p] = pool_elems;
+        pidx.ids.push_back(p);
+        pidx.off.push_back(pool_elems);
         pairs.emplace_back(i, p);
         pool_elems += (int64_t)own[i].act.size() * own[p].act.size();
       }
+      pidx.beg.push_back((int64_t)pidx.ids.size());
     }
+    ht.mark(0);
     void* pool = nullptr;
     {
       const size_t bytes = std::max<size_t>(1, (size_t)pool_elems) * te;
@@ -774,7 +813,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     }
     info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)(arena.held() + pool_elems * (int64_t)te));
     info.bytes_tiles += (double)pool_elems * (double)te;
-    ht.mark(0);
+    ht.mark(8);
     // ---- assemble: slot/idx maps, dof lists, source tables
     {
       std::vector<int32_t> slot, idx;
@@ -802,11 +841,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       std::vector<AsmTask> tasks;
       std::vector<AsmSrc> table;
       int64_t units = 0;
-      for (auto& pr : pairs) {
+      for (size_t k = 0; k < pairs.size(); ++k) {
+        const auto& pr = pairs[k];
         const Owner& a = own[pr.first];
         const Owner& b = own[pr.second];
         AsmTask t{};
-        t.out_off = pair_off[(int64_t)pr.first * nown + pr.second];
+        t.out_off = pidx.off[k];
         t.nr = (int)a.act.size();
         t.nc = (int)b.act.size();
         t.ld = t.nr;
@@ -820,14 +860,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           table.push_back(AsmSrc{-1, 0, 0});
         } else {
           t.nsc = (int)b.sub.size();
-          const int64_t nprev = (int64_t)prev_own.size();
           for (int sa : a.sub)
             for (int sb : b.sub) {
-              auto it = prev_pair.find((int64_t)sa * nprev + sb);
-              if (it == prev_pair.end())
+              const int64_t o = prev_pidx.find(sa, sb);
+              if (o < 0)
                 table.push_back(AsmSrc{-1, 0, 0});
               else
-                table.push_back(AsmSrc{it->second, (int32_t)prev_own[sa].act.size(), 0});
+                table.push_back(AsmSrc{o, (int32_t)prev_own[sa].act.size(), 0});
             }
         }
         t.unit_begin = units;
@@ -968,8 +1007,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int row0 = 0;
         for (int q : bp.qown) {
           QSeg s{};
-          s.tile_qb = pair_off.at((int64_t)q * nown + bp.oi);
-          s.tile_bq = pair_off.at((int64_t)bp.oi * nown + q);
+          s.tile_qb = pidx.at(q, bp.oi);
+          s.tile_bq = pidx.at(bp.oi, q);
           s.live = own[q].live_dev;
           s.ld = (int)own[q].act.size();
           s.row0 = row0;
@@ -1025,14 +1064,15 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           zd* G = sg.dev.alloc_n<zd>((size_t)mm);
           bp.R = sg.dev.alloc_n<zd>((size_t)mm);
           bp.T = sg.dev.alloc_n<zd>((size_t)mm);
-          gg.add_split(part, bp.m, bp.m, bp.m, bp.M, bp.rows, bp.M, bp.rows, bp.rows, KCH, mm);
+          // G = M^H M is Hermitian: its lower triangle of tiles only (pchol reads no more)
+          gg.add_split(part, bp.m, bp.m, bp.m, bp.M, bp.rows, bp.M, bp.rows, bp.rows, KCH, mm, true);
           SumTask sm{part, G, mm, mm, nsplit, 0, su};
           su += (mm + 255) / 256;
           st_.push_back(sm);
           zd* Rp = sg.dev.alloc_n<zd>((size_t)mm);
           pt.push_back(PcholTask{G, bp.R, Rp, bp.perm, bp.rank, bp.T, bp.m, 0});
           mmax = std::max(mmax, bp.m);
-          prof.flops[KC_QR] += 8.0 * (double)bp.rows * bp.m * bp.m;
+          prof.flops[KC_QR] += 4.0 * (double)bp.rows * bp.m * (bp.m + 1);
         }
         gg.prepare(sg);
         SumTask* dst_ = sg.up(st_);
@@ -1171,7 +1211,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           CrossTask ct{};
           ct.Ccol = e.Ccol;
           ct.Crow = e.Crow;
-          ct.tile_bb = pair_off.at((int64_t)bp.oi * nown + bp.oi);
+          ct.tile_bb = pidx.at(bp.oi, bp.oi);
           ct.perm = bp.perm;
           ct.m = bp.m;
           ct.nN = bp.nN;
@@ -1180,8 +1220,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           int off = 0;
           for (int o : bp.nown_) {
             NSeg s{};
-            s.tile_nb = pair_off.at((int64_t)o * nown + bp.oi);
-            s.tile_bn = pair_off.at((int64_t)bp.oi * nown + o);
+            s.tile_nb = pidx.at(o, bp.oi);
+            s.tile_bn = pidx.at(bp.oi, o);
             s.live = own[o].live_dev;
             s.ld = (int)own[o].act.size();
             s.off = off;
@@ -1321,7 +1361,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
                 const int M = (a == 0) ? e.s : (int)own[grp[a]].live.size();
                 const int N = (b == 0) ? e.s : (int)own[grp[b]].live.size();
                 if (M == 0 || N == 0) continue;
-                cl.push_back(Contrib{pair_off.at((int64_t)grp[a] * nown + grp[b]), q, (int32_t)a, (int32_t)b});
+                cl.push_back(Contrib{pidx.at(grp[a], grp[b]), q, (int32_t)a, (int32_t)b});
               }
           }
           std::stable_sort(cl.begin(), cl.end(), [](const Contrib& x, const Contrib& y) { return x.toff < y.toff; });
@@ -1547,7 +1587,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     }
     std::sort(next.begin(), next.end(), [](const Owner& a, const Owner& b) { return a.first_pos < b.first_pos; });
     prev_own = std::move(own);
-    prev_pair = std::move(pair_off);
+    prev_pidx = std::move(pidx);
     prev_pool = pool;
     own = std::move(next);
     first_level = false;
@@ -1592,10 +1632,9 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       } else {
         const int64_t np = (int64_t)prev_own.size();
         table.resize((size_t)np * np, AsmSrc{-1, 0, 0});
-        for (auto& kv : prev_pair) {
-          const int64_t a = kv.first / np, b = kv.first % np;
-          table[a * np + b] = AsmSrc{kv.second, (int32_t)prev_own[a].act.size(), 0};
-        }
+        for (int64_t a = 0; a < np; ++a)
+          for (int64_t k = prev_pidx.beg[a]; k < prev_pidx.beg[a + 1]; ++k)
+            table[a * np + prev_pidx.ids[k]] = AsmSrc{prev_pidx.off[k], (int32_t)prev_own[a].act.size(), 0};
       }
       zd* Att = sg.dev.alloc_n<zd>((size_t)n0 * n0);
       AsmTask t{};
@@ -1655,9 +1694,9 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   if (opts.verbose) {
     fprintf(stderr, "[fmmlu] factor %.3f s, of which waiting on the GPU %.3f s\n", info.t_factor, sg.t_wait);
     fprintf(stderr,
-            "[fmmlu] host sections: pairs %.3f assemble %.3f plan %.3f id+readback %.3f elim %.3f "
+            "[fmmlu] host sections: pairs %.3f pool %.3f assemble %.3f plan %.3f id+readback %.3f elim %.3f "
             "schur %.3f phase-end %.3f merge %.3f\n",
-            ht.t[0], ht.t[1], ht.t[2], ht.t[3], ht.t[4], ht.t[5], ht.t[6], ht.t[7]);
+            ht.t[0], ht.t[8], ht.t[1], ht.t[2], ht.t[3], ht.t[4], ht.t[5], ht.t[6], ht.t[7]);
   }
 }
 

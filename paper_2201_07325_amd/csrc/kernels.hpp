@@ -86,10 +86,17 @@ struct GemmTask {
   int32_t M, N, ldc;
   int32_t seg_begin, nseg;
   int32_t kchunk;                   // > 0: split K into chunks; chunk c writes C + c*part_stride
+  int32_t lower;                    // M == N: only the output tiles on or below the diagonal
+  int32_t pad;
   double alpha_re, alpha_im, beta;  // beta real
   int64_t part_stride;
   int64_t unit_begin;              // prefix sum of kGemmTile^2 output blocks (times K chunks)
 };
+// output blocks of one K chunk of a task: all, or the T (T + 1) / 2 on or below the diagonal
+__host__ __device__ inline int64_t gemm_task_tiles(int M, int N, int lower) {
+  const int64_t tm = (M + kGemmTile - 1) / kGemmTile, tn = (N + kGemmTile - 1) / kGemmTile;
+  return lower ? tm * (tm + 1) / 2 : tm * tn;
+}
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st);
 

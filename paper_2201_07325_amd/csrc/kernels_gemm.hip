@@ -66,10 +66,21 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
   const GemmTask t = tasks[find_unit_task(tasks, ntasks, u)];
   int64_t lu = u - t.unit_begin;
   const int nbm = (t.M + BM - 1) / BM;
-  const int64_t ntiles = (int64_t)nbm * ((t.N + BN - 1) / BN);
+  const int64_t ntiles = gemm_task_tiles(t.M, t.N, t.lower);
   const int kc = (int)(lu / ntiles);  // split-K chunk (0 without split)
   lu -= (int64_t)kc * ntiles;
-  const int row0 = (int)(lu % nbm) * BM, col0 = (int)(lu / nbm) * BN;
+  int row0, col0;
+  if (t.lower) {
+    // lu = ti (ti + 1) / 2 + tj with tj <= ti
+    int ti = (int)((sqrt(8.0 * (double)lu + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(ti + 1) * (ti + 2) / 2 <= lu) ++ti;
+    while ((int64_t)ti * (ti + 1) / 2 > lu) --ti;
+    row0 = ti * BM;
+    col0 = (int)(lu - (int64_t)ti * (ti + 1) / 2) * BN;
+  } else {
+    row0 = (int)(lu % nbm) * BM;
+    col0 = (int)(lu / nbm) * BN;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wavefront quarter
   typename M::V cr[2][2], ci[2][2];

@@ -388,11 +388,16 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restric
 // column c not yet chosen, p_k maximising the Schur-complement diagonal dg (the squared norm
 // of column c of M after projection on the chosen columns; ties to the lowest column). R is
 // kept row-major by original column (Rt[l m + c]), so the sum is one coalesced pass over the
-// previous rows (split into row slices when m is small), and G[p_k, c] = conj(G[c, p_k]) is a
-// contiguous read. Positions follow column-pivoted QR's exchange rule (step k swaps positions
+// previous rows (split into row slices when m is small). Only the lower triangle of G is
+// read: G[p_k, c] = conj(G[c, p_k]) for c >= p_k (contiguous), G[p_k, c] for c < p_k. Positions follow column-pivoted QR's exchange rule (step k swaps positions
 // k and pos(p_k)). At the end R is written in pivoted column order, column-major (rows < rank,
 // upper triangle only), for the back substitution.
 constexpr int kPcholThreads = 1024;
+
+// G[p, c] from the lower triangle of the Hermitian G (column-major, ld m)
+__device__ inline zd pchol_grow(const zd* __restrict__ G, int m, int p, int c) {
+  return c >= p ? zconj(G[c + (int64_t)p * m]) : G[p + (int64_t)c * m];
+}
 
 __device__ inline bool pchol_better(double v, int c, double bv, int bc) {
   return c >= 0 && (bc < 0 || v > bv || (v == bv && c < bc));
@@ -481,7 +486,7 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* _
           zfmac(a1, mult[l + 1], Rt[(int64_t)(l + 1) * m + c]);
         }
         if (l < k) zfmac(a0, mult[l], Rt[(int64_t)l * m + c]);
-        const zd v = zscale(zsub(zconj(G[c + (int64_t)p * m]), zadd(a0, a1)), inv);
+        const zd v = zscale(zsub(pchol_grow(G, m, p, c), zadd(a0, a1)), inv);
         Rt[(int64_t)k * m + c] = v;
         dg[c] -= zabs2(v);
       }
@@ -498,7 +503,7 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* _
       if (tid < m && pos[tid] > k) {
         zd sum = part[tid];
         for (int qq = 1; qq < slices; ++qq) sum = zadd(sum, part[qq * mpad + tid]);
-        const zd v = zscale(zsub(zconj(G[tid + (int64_t)p * m]), sum), inv);
+        const zd v = zscale(zsub(pchol_grow(G, m, p, tid), sum), inv);
         Rt[(int64_t)k * m + tid] = v;
         dg[tid] -= zabs2(v);
       }
