@@ -29,6 +29,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <thread>
 #include <unordered_map>
 
 namespace fmmlu {
@@ -154,6 +155,25 @@ struct PairIndex {
     return o;
   }
 };
+
+// fn(lo, hi) over [0, n) split into contiguous ranges on up to 8 host threads
+template <class F>
+void parallel_ranges(int n, F&& fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::max(1, std::min({8, hw, n / 64}));
+  if (nt <= 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int chunk = (n + nt - 1) / nt;
+  for (int t = 1; t < nt; ++t) {
+    const int lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo < hi) th.emplace_back([&fn, lo, hi] { fn(lo, hi); });
+  }
+  fn(0, std::min(n, chunk));
+  for (auto& x : th) x.join();
+}
 
 // Host wall-clock accumulators for the verbose report.
 struct HostTimers {
@@ -755,28 +775,43 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   for (int lev = tree.nlevels - 1; lev >= 2; --lev) {
     const int nown = (int)own.size();
     index_owners(own);
-    // ---- close pairs of owners and their tiles
+    // ---- close pairs of owners and their tiles. Each owner finds the owners covering the
+    // cells within two of its own (in parallel); an owner coarser than one it finds cannot
+    // find it back, so those pairs are added to the coarser owner's list afterwards.
     std::vector<std::vector<int>> close(nown);
-    for (int i = 0; i < nown; ++i) {
-      const Owner& o = own[i];
-      for (int dz = -2; dz <= 2; ++dz)
-        for (int dy = -2; dy <= 2; ++dy)
-          for (int dx = -2; dx <= 2; ++dx) {
-            const int p = owner_lookup(own, o.level, o.c[0] + dx, o.c[1] + dy, o.c[2] + dz);
-            if (p < 0) continue;
-            close[i].push_back(p);
-            close[p].push_back(i);
-          }
+    parallel_ranges(nown, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i) {
+        const Owner& o = own[i];
+        auto& v = close[i];
+        for (int dz = -2; dz <= 2; ++dz)
+          for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+              const int p = owner_lookup(own, o.level, o.c[0] + dx, o.c[1] + dy, o.c[2] + dz);
+              if (p >= 0) v.push_back(p);
+            }
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+      }
+    });
+    {
+      std::vector<std::vector<int>> back(nown);
+      for (int i = 0; i < nown; ++i)
+        for (int p : close[i])
+          if (own[p].level < own[i].level) back[p].push_back(i);
+      for (int p = 0; p < nown; ++p) {
+        if (back[p].empty()) continue;
+        auto& v = close[p];
+        v.insert(v.end(), back[p].begin(), back[p].end());
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+      }
     }
     PairIndex pidx;
     pidx.beg.assign(1, 0);
     int64_t pool_elems = 0;
     std::vector<std::pair<int, int>> pairs;
     for (int i = 0; i < nown; ++i) {
-      auto& v = close[i];
-      std::sort(v.begin(), v.end());
-      v.erase(std::unique(v.begin(), v.end()), v.end());
-      for (int p : v) {
+      for (int p : close[i]) {
         if (gap_units(own[i], own[p]) > 1) continue;
         pidx.ids.push_back(p);
         pidx.off.push_back(pool_elems);
