@@ -156,11 +156,12 @@ struct PairIndex {
   }
 };
 
-// fn(lo, hi) over [0, n) split into contiguous ranges on up to 8 host threads
+// fn(lo, hi) over [0, n) split into contiguous ranges of at least `grain` items on up to 8
+// host threads
 template <class F>
-void parallel_ranges(int n, F&& fn) {
+void parallel_ranges(int n, int grain, F&& fn) {
   const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-  const int nt = std::max(1, std::min({8, hw, n / 64}));
+  const int nt = std::max(1, std::min({8, hw, n / std::max(grain, 1)}));
   if (nt <= 1) {
     fn(0, n);
     return;
@@ -656,6 +657,17 @@ void dense_inverse_batch(const zd* A, int64_t n, int64_t count, zd* out, hipStre
 }
 
 
+// A colour phase's solve record before its scatter lists are grouped and uploaded (done at
+// the end of the factorization, overlapping the top block on the device).
+struct PendingPhase {
+  SolvePhase ph;
+  std::vector<std::pair<int32_t, int64_t>> contrib;  // (destination, y index)
+  std::vector<SolveBox> db;
+  std::vector<SweepTask> txr, typ, tyr, tbp, tbt, tbf;
+  std::vector<int32_t> dst;
+  std::vector<int64_t> ptr, src;
+};
+
 // ------------------------------------------------------------------------------------------
 void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
                         hipStream_t st) {
@@ -729,6 +741,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   } pool_guard{pools, st};
   // per-level device lists stay alive until the factorization has drained
   std::vector<std::unique_ptr<DeviceArena>> level_arenas;
+  std::vector<PendingPhase> pending;  // solve records, completed at the end
   // destroyed first: no buffer above is freed while kernels queued on st may still use it
   struct DrainOnExit {
     hipStream_t st;
@@ -779,7 +792,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     // cells within two of its own (in parallel); an owner coarser than one it finds cannot
     // find it back, so those pairs are added to the coarser owner's list afterwards.
     std::vector<std::vector<int>> close(nown);
-    parallel_ranges(nown, [&](int lo, int hi) {
+    parallel_ranges(nown, 64, [&](int lo, int hi) {
       for (int i = lo; i < hi; ++i) {
         const Owner& o = own[i];
         auto& v = close[i];
@@ -1459,13 +1472,15 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       ht.mark(5);
       // build the solve phase record
       if (ne > 0) {
-        SolvePhase ph;
+        pending.emplace_back();
+        PendingPhase& pp = pending.back();
+        SolvePhase& ph = pp.ph;
         ph.box_begin = (int)box_base;
         ph.box_end = (int)boxes.size();
         int64_t yo = 0, xo = 0, po = 0, xpo = 0, ypo = 0, tpo = 0;
-        std::vector<std::pair<int32_t, int64_t>> contrib;  // (destination, y index)
-        std::vector<SolveBox> db;
-        std::vector<SweepTask> txr, typ, tyr, tbp, tbt, tbf;
+        auto& contrib = pp.contrib;
+        auto& db = pp.db;
+        auto &txr = pp.txr, &typ = pp.typ, &tyr = pp.tyr, &tbp = pp.tbp, &tbt = pp.tbt, &tbf = pp.tbf;
         for (int b = ph.box_begin; b < ph.box_end; ++b) {
           FactorBox& fb = boxes[b];
           const int lb = b - ph.box_begin;
@@ -1519,19 +1534,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           for (int o : bp.nown_)
             for (int32_t l : own[o].live) contrib.emplace_back((int32_t)own[o].act[l], c++);
         }
-        // group by destination; y indices increase with the box order, so sorting the pairs
-        // keeps each destination's contributions in box order
-        std::sort(contrib.begin(), contrib.end());
-        std::vector<int32_t> dst;
-        std::vector<int64_t> ptr{0}, src;
-        dst.reserve(contrib.size());
-        src.reserve(contrib.size());
-        for (size_t i = 0; i < contrib.size(); ++i) {
-          if (i > 0 && contrib[i].first != contrib[i - 1].first) ptr.push_back((int64_t)src.size());
-          if (i == 0 || contrib[i].first != contrib[i - 1].first) dst.push_back(contrib[i].first);
-          src.push_back(contrib[i].second);
-        }
-        if (!contrib.empty()) ptr.push_back((int64_t)src.size());
         if ((size_t)ph.rmax * sizeof(zd) > 65536)
           throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(ph.rmax) +
                                         " DOFs exceeds the solve kernels' LDS bound (4096)");
@@ -1541,30 +1543,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         ph.xrplen = xpo;
         ph.yplen = ypo;
         ph.tplen = tpo;
-        ph.nd = (int64_t)dst.size();
-        ph.dboxes = sg.up_to(arena, db);
-        ph.sc_dst = sg.up_to(arena, dst);
-        ph.sc_ptr = sg.up_to(arena, ptr);
-        ph.sc_src = sg.up_to(arena, src);
-        ph.dxr = sg.up_to(arena, txr);
-        ph.dyp = sg.up_to(arena, typ);
-        ph.dyr = sg.up_to(arena, tyr);
-        ph.dbp = sg.up_to(arena, tbp);
-        ph.dbt = sg.up_to(arena, tbt);
-        ph.dbf = sg.up_to(arena, tbf);
-        ph.nxr = (int)txr.size();
-        ph.nyp = (int)typ.size();
-        ph.nyr = (int)tyr.size();
-        ph.nbp = (int)tbp.size();
-        ph.nbt = (int)tbt.size();
-        ph.nbf = (int)tbf.size();
         ymax = std::max(ymax, yo);
         xrmax = std::max(xrmax, xo);
         pmax = std::max(pmax, po);
         xrpmax = std::max(xrpmax, xpo);
         ypmax = std::max(ypmax, ypo);
         tpmax = std::max(tpmax, tpo);
-        phases.push_back(ph);
       }
       // live lists of eliminated boxes to the device (persistent for the level)
       {
@@ -1705,6 +1689,47 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       info.flops_top = 8.0 * (double)n0 * n0 * n0;
       info.factor_bytes += 16 * (int64_t)n0 * n0;
     }
+    // solve records (host work overlapping the top block on the device). Scatter lists are
+    // grouped by destination; y indices increase with the box order, so sorting the pairs
+    // keeps each destination's contributions in box order.
+    parallel_ranges((int)pending.size(), 1, [&](int lo, int hi) {
+      for (int i = lo; i < hi; ++i) {
+        PendingPhase& pp = pending[i];
+        auto& contrib = pp.contrib;
+        std::sort(contrib.begin(), contrib.end());
+        pp.ptr.assign(1, 0);
+        pp.dst.reserve(contrib.size());
+        pp.src.reserve(contrib.size());
+        for (size_t k = 0; k < contrib.size(); ++k) {
+          if (k > 0 && contrib[k].first != contrib[k - 1].first) pp.ptr.push_back((int64_t)pp.src.size());
+          if (k == 0 || contrib[k].first != contrib[k - 1].first) pp.dst.push_back(contrib[k].first);
+          pp.src.push_back(contrib[k].second);
+        }
+        if (!contrib.empty()) pp.ptr.push_back((int64_t)pp.src.size());
+      }
+    });
+    for (PendingPhase& pp : pending) {
+      SolvePhase ph = pp.ph;
+      ph.nd = (int64_t)pp.dst.size();
+      ph.dboxes = sg.up_to(arena, pp.db);
+      ph.sc_dst = sg.up_to(arena, pp.dst);
+      ph.sc_ptr = sg.up_to(arena, pp.ptr);
+      ph.sc_src = sg.up_to(arena, pp.src);
+      ph.dxr = sg.up_to(arena, pp.txr);
+      ph.dyp = sg.up_to(arena, pp.typ);
+      ph.dyr = sg.up_to(arena, pp.tyr);
+      ph.dbp = sg.up_to(arena, pp.tbp);
+      ph.dbt = sg.up_to(arena, pp.tbt);
+      ph.dbf = sg.up_to(arena, pp.tbf);
+      ph.nxr = (int)pp.txr.size();
+      ph.nyp = (int)pp.typ.size();
+      ph.nyr = (int)pp.tyr.size();
+      ph.nbp = (int)pp.tbp.size();
+      ph.nbt = (int)pp.tbt.size();
+      ph.nbf = (int)pp.tbf.size();
+      phases.push_back(ph);
+    }
+    pending.clear();
     sg.sync_reset();
     prev_pool = nullptr;
     // the first zero pivot of any pivot block or of the top block (column + 1), or -1 if a
