@@ -491,29 +491,30 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
     }
   }
   if (!small.empty()) {
+    int nmax = 0;
+    for (auto& c : small) nmax = std::max(nmax, c.n);
+    const int NB = gj_coop_panel(nmax);
     // per matrix: 2 npan + 1 synchronisation words of the cooperative kernel, zeroed
     size_t nsync = 0;
-    for (auto& c : small) nsync += (size_t)gj_coop_sync_words(c.n);
+    for (auto& c : small) nsync += (size_t)gj_coop_sync_words(c.n, NB);
     int32_t* counters = sg.dev.alloc_n<int32_t>(nsync);
     FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * nsync, sg.st));
-    int nmax = 0;
     size_t so = 0;
     for (size_t i = 0; i < small.size(); ++i) {
       small[i].piv = sg.dev.alloc_n<int32_t>(small[i].n);
       small[i].info = info_dev;
       small[i].counter = counters + so;
-      so += (size_t)gj_coop_sync_words(small[i].n);
-      nmax = std::max(nmax, small[i].n);
+      so += (size_t)gj_coop_sync_words(small[i].n, NB);
     }
     const int cap = gj_coop_capacity(nmax);
     // Workgroups per matrix: one per panel up to K, with K the largest that keeps the whole
     // batch at one workgroup per compute unit (a matrix's time is its panel chain; fewer
     // workgroups add each one's share of the column updates to that chain, and workgroups
     // sharing a compute unit slow each other's redundant panel work).
-    auto npan_of = [](int n) { return (n + kGjBlock - 1) / kGjBlock; };
+    auto npan_of = [NB](int n) { return (n + NB - 1) / NB; };
     const int64_t budget = std::min(cap, gj_coop_cus());
     int K = 1;
-    for (int k = 2; k <= kGjCoopMax / kGjBlock; ++k) {
+    for (int k = 2; k <= npan_of(nmax); ++k) {
       int64_t tot = 0;
       for (auto& c : small) tot += std::min(npan_of(c.n), k);
       if (tot > budget) break;
@@ -536,7 +537,31 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
     }
     for (auto& t : small) sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
   }
-  batched_inverse_pipeline(sg, large, lo, info_dev, cls);
+  // up to kGjStepMax rows: one launch per panel; beyond, the blocked multi-launch pipeline
+  std::vector<GjTask> huge;
+  std::vector<zd*> ho;
+  for (size_t i = 0; i < large.size(); ++i) {
+    GjTask& t = large[i];
+    if (t.n > kGjStepMax) {
+      huge.push_back(t);
+      ho.push_back(lo[i]);
+      continue;
+    }
+    GjStepArgs a{};
+    a.A = t.A;
+    a.n = t.n;
+    a.lda = t.lda;
+    a.info = info_dev;
+    a.piv = sg.dev.alloc_n<int32_t>(t.n);
+    a.rowcol = sg.dev.alloc_n<int32_t>(t.n);
+    FMMLU_HIP(hipMemsetAsync(a.rowcol, 0xFF, sizeof(int32_t) * t.n, sg.st));  // all -1
+    ProfScope ps(*sg.prof, cls);
+    const int npan = (t.n + kGjStepNb - 1) / kGjStepNb;
+    for (int j = -1; j < npan; ++j) launch_gj_step(a, j, sg.st);
+    launch_gj_step_gather(a, lo[i], sg.st);
+    sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
+  }
+  batched_inverse_pipeline(sg, huge, ho, info_dev, cls);
 }
 
 // Blocked Householder QR (no pivoting) of M_b (rows_b x m_b, ld rows_b), in place; the R

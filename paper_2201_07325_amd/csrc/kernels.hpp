@@ -202,7 +202,8 @@ void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStrea
 int gj_panel_capacity();
 // Whole inversion of matrices of n <= kGjCoopMax rows in one cooperative launch: nwg
 // workgroups per matrix starting at grid index unit_begin; out = A^{-1} (n x n, ld n);
-// counter zero before the launch.
+// counter: gj_coop_sync_words zeroed words. Panels of gj_coop_panel(nmax) columns, nmax the
+// largest n of the launch.
 constexpr int kGjCoopMax = 512;
 struct GjCoopTask {
   zd* A;
@@ -213,13 +214,34 @@ struct GjCoopTask {
   int32_t n, lda, nwg, pad;
   int64_t unit_begin;
 };
+inline int gj_coop_panel(int) { return 16; }
 // synchronisation words of one matrix: panel-ready flags, panel-read counts, final count
-inline int gj_coop_sync_words(int n) { return 2 * ((n + kGjBlock - 1) / kGjBlock) + 1; }
+inline int gj_coop_sync_words(int n, int nb) { return 2 * ((n + nb - 1) / nb) + 1; }
 void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st);
 // workgroups of gj_coop that can be resident at once; compute units of the device
 int gj_coop_capacity(int nmax);
 int gj_coop_cus();
 constexpr int kGjCoopThreads = 256;  // threads per cooperative Gauss-Jordan workgroup
+
+// Stepped Gauss-Jordan inversion of one matrix of kGjCoopMax < n <= kGjStepMax rows with
+// implicit pivoting, one launch per panel of kGjStepNb columns (the launch boundary is the
+// only synchronisation between workgroups). Launch j: workgroup 0 applies panel j to the
+// columns of panel j + 1 and factors that panel; the other workgroups apply panel j to every
+// other column. piv (n): pivot row of each column; rowcol (n, all -1 before the first
+// launch): the column each row pivots. After the last step out[i, c] = M[piv[i], rowcol[c]]
+// (launch_gj_step_gather). info as for the other inversions.
+constexpr int kGjStepMax = 2048;
+constexpr int kGjStepNb = 8;
+constexpr int kGjStepThreads = 512;
+struct GjStepArgs {
+  zd* A;
+  int32_t* piv;
+  int32_t* rowcol;
+  int32_t* info;
+  int32_t n, lda;
+};
+void launch_gj_step(const GjStepArgs& a, int j, hipStream_t st);  // j = -1 .. npan - 1
+void launch_gj_step_gather(const GjStepArgs& a, zd* out, hipStream_t st);
 // marks a factorization in progress for the lifetime of the object (cooperative launches are
 // serialised while more than one is active)
 struct ActiveFactorization {

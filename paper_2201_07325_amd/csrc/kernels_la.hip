@@ -864,8 +864,9 @@ __device__ inline zd gj_mul(const zd& a, const zd& b) {
   return zd{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
 
-// kGjCoopThreads threads per workgroup, RPT rows per thread (rows tid + r kGjCoopThreads)
-template <int RPT>
+// kGjCoopThreads threads per workgroup, RPT rows per thread (rows tid + r kGjCoopThreads),
+// panels of NB columns
+template <int RPT, int NB>
 __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTask* __restrict__ tasks, int ntasks) {
   constexpr int NT = kGjCoopThreads, NW = NT / 64, NR = NT * RPT;
   const int64_t u = blockIdx.x;
@@ -880,10 +881,10 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
   // alternate between even and odd columns
   __shared__ double cv[2][NW];
   __shared__ int ci[2][NW];
-  __shared__ zd crow[2][NW][kGjNb];
+  __shared__ zd crow[2][NW][NB];
   __shared__ int pivl[NR], idx[NR];
-  __shared__ zd Ws[kGjNb][kGjChunk + 1];
-  const int npan = (n + kGjNb - 1) / kGjNb;
+  __shared__ zd Ws[NB][NB + 1];
+  const int npan = (n + NB - 1) / NB;
   int32_t* ready = t.counter;
   int32_t* reads = t.counter + npan;
   int32_t* done = t.counter + 2 * npan;
@@ -892,10 +893,10 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
   for (int r = 0; r < RPT; ++r) used[r] = false;
 
   // apply panel (j0, nb) to the columns of panel pc; myq[r]: row r is pi(j0 + myq[r]), or -1
-  auto update_panel = [&](int pc, int j0, int nb, const zd (&a)[RPT][kGjNb], const int (&myq)[RPT]) {
-    const int c0 = pc * kGjNb;
-    for (int e = tid; e < kGjNb * kGjChunk; e += NT) {
-      const int q = e % kGjNb, cc = e / kGjNb, c = c0 + cc;
+  auto update_panel = [&](int pc, int j0, int nb, const zd (&a)[RPT][NB], const int (&myq)[RPT]) {
+    const int c0 = pc * NB;
+    for (int e = tid; e < NB * NB; e += NT) {
+      const int q = e % NB, cc = e / NB, c = c0 + cc;
       Ws[q][cc] = (q < nb && c < n) ? A[pivl[j0 + q] + (int64_t)c * lda] : zd{0.0, 0.0};
     }
     __syncthreads();
@@ -903,20 +904,20 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
     for (int r = 0; r < RPT; ++r) {
       const int row = tid + r * NT;
       if (row < n) {
-        zd acc[kGjChunk];
+        zd acc[NB];
 #pragma unroll
-        for (int cc = 0; cc < kGjChunk; ++cc) {
+        for (int cc = 0; cc < NB; ++cc) {
           const int c = c0 + cc;
           acc[cc] = (c < n) ? A[row + (int64_t)c * lda] : zd{0.0, 0.0};
         }
 #pragma unroll
-        for (int cc = 0; cc < kGjChunk; ++cc) {
+        for (int cc = 0; cc < NB; ++cc) {
 #pragma unroll
-          for (int q = 0; q < kGjNb; ++q) gj_fma(acc[cc], a[r][q], Ws[q][cc]);
+          for (int q = 0; q < NB; ++q) gj_fma(acc[cc], a[r][q], Ws[q][cc]);
           if (myq[r] >= 0) acc[cc] = zsub(acc[cc], Ws[myq[r]][cc]);
         }
 #pragma unroll
-        for (int cc = 0; cc < kGjChunk; ++cc) {
+        for (int cc = 0; cc < NB; ++cc) {
           const int c = c0 + cc;
           if (c < n) A[row + (int64_t)c * lda] = acc[cc];
         }
@@ -926,16 +927,16 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
   };
 
   for (int pn = 0; pn < npan; ++pn) {
-    const int j0 = pn * kGjNb, nb = min(kGjNb, n - j0);
+    const int j0 = pn * NB, nb = min(NB, n - j0);
     const int owner = pn % nwg;
     // panel pn must be final; its owner made it so itself
     if (nwg > 1 && pn > 0 && owner != w) gj_wait_at_least(ready + pn, 1, t.info);
-    zd a[RPT][kGjNb];
+    zd a[RPT][NB];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
       const int row = tid + r * NT;
 #pragma unroll
-      for (int q = 0; q < kGjNb; ++q)
+      for (int q = 0; q < NB; ++q)
         a[r][q] = (row < n && q < nb) ? A[row + (int64_t)(j0 + q) * lda] : zd{0.0, 0.0};
     }
     if (nwg > 1 && owner != w) {
@@ -948,7 +949,7 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
     // one workgroup barrier per column; the column loop is unrolled so that the register
     // rows are indexed by constants only
 #pragma unroll
-    for (int j = 0; j < kGjNb; ++j) {
+    for (int j = 0; j < NB; ++j) {
       if (j < nb) {
         const int gc = j0 + j, par = j & 1;
         double best = -1.0;
@@ -969,7 +970,7 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
         for (int r = 0; r < RPT; ++r)
           if (besti == tid + r * NT) {
 #pragma unroll
-            for (int q = 0; q < kGjNb; ++q) crow[par][wave][q] = a[r][q];
+            for (int q = 0; q < NB; ++q) crow[par][wave][q] = a[r][q];
           }
         if (lane == 0) {
           cv[par][wave] = best;
@@ -991,9 +992,9 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
           t.piv[gc] = p;
           if (!(b > 0.0) && *t.info == 0) *t.info = gc + 1;
         }
-        zd pr[kGjNb];
+        zd pr[NB];
 #pragma unroll
-        for (int q = 0; q < kGjNb; ++q) pr[q] = crow[par][pw][q];
+        for (int q = 0; q < NB; ++q) pr[q] = crow[par][pw][q];
         const double d2 = zabs2(pr[j]);
         const double s = d2 > 0.0 ? 1.0 / d2 : 0.0;
         const zd inv{pr[j].re * s, -pr[j].im * s};
@@ -1004,11 +1005,11 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
             used[r] = true;
             myq[r] = j;
 #pragma unroll
-            for (int q = 0; q < kGjNb; ++q) a[r][q] = (q == j) ? inv : gj_mul(a[r][q], inv);
+            for (int q = 0; q < NB; ++q) a[r][q] = (q == j) ? inv : gj_mul(a[r][q], inv);
           } else if (row < n) {
             const zd fi = gj_mul(a[r][j], inv);
 #pragma unroll
-            for (int q = 0; q < kGjNb; ++q) a[r][q] = (q == j) ? zd{-fi.re, -fi.im} : gj_fms(a[r][q], fi, pr[q]);
+            for (int q = 0; q < NB; ++q) a[r][q] = (q == j) ? zd{-fi.re, -fi.im} : gj_fms(a[r][q], fi, pr[q]);
           }
         }
       }
@@ -1022,7 +1023,7 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
         const int row = tid + r * NT;
         if (row < n) {
 #pragma unroll
-          for (int q = 0; q < kGjNb; ++q)
+          for (int q = 0; q < NB; ++q)
             if (q < nb) A[row + (int64_t)(j0 + q) * lda] = a[r][q];
         }
       }
@@ -1055,9 +1056,178 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
     const int row = tid + r * NT;
     if (row < n)
       for (int pc = w; pc < npan; pc += nwg)
-        for (int c = pc * kGjNb; c < min(n, pc * kGjNb + kGjNb); ++c)
+        for (int c = pc * NB; c < min(n, pc * NB + NB); ++c)
           t.out[row + (int64_t)c * n] = A[pivl[row] + (int64_t)idx[c] * lda];
   }
+}
+
+// ---- stepped Gauss-Jordan: one launch per panel (see GjStepArgs)
+constexpr int kStepRpt = kGjStepMax / kGjStepThreads;  // rows per thread of workgroup 0
+constexpr int kStepCols = 16;                          // columns per updating workgroup
+
+__global__ void __launch_bounds__(kGjStepThreads) gj_step_kernel(GjStepArgs g, int j) {
+  constexpr int NB = kGjStepNb, NT = kGjStepThreads, NW = NT / 64, RPT = kStepRpt;
+  const int n = g.n;
+  const int64_t lda = g.lda;
+  zd* A = g.A;
+  const int npan = (n + NB - 1) / NB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j0 = j * NB, nb = j >= 0 ? min(NB, n - j0) : 0;  // panel j, applied in this step
+  __shared__ zd W[NB][kStepCols + 1];                        // panel j's pivot rows, block's columns
+  if (blockIdx.x == 0) {
+    // ---- panel j + 1: apply panel j to its columns, then factor it
+    const int jn = j + 1;
+    if (jn >= npan) return;
+    const int k0 = jn * NB, kb = min(NB, n - k0);
+    __shared__ double cv[2][NW];
+    __shared__ int ci[2][NW];
+    __shared__ zd crow[2][NW][NB];
+    zd a[RPT][NB];
+    bool used[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int row = tid + r * NT;
+      used[r] = row >= n || g.rowcol[row] >= 0;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) a[r][q] = (row < n && q < kb) ? A[row + (int64_t)(k0 + q) * lda] : zd{0.0, 0.0};
+    }
+    if (nb > 0) {
+      for (int e = tid; e < NB * NB; e += NT) {
+        const int pp = e / NB, q = e % NB;
+        W[pp][q] = (pp < nb && q < kb) ? A[g.piv[j0 + pp] + (int64_t)(k0 + q) * lda] : zd{0.0, 0.0};
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RPT; ++r) {
+        const int row = tid + r * NT;
+        if (row >= n) continue;
+        zd tr[NB];
+#pragma unroll
+        for (int pp = 0; pp < NB; ++pp) tr[pp] = pp < nb ? A[row + (int64_t)(j0 + pp) * lda] : zd{0.0, 0.0};
+        const int rc = g.rowcol[row];
+        const int qi = (rc >= j0 && rc < j0 + nb) ? rc - j0 : -1;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+#pragma unroll
+          for (int pp = 0; pp < NB; ++pp) gj_fma(a[r][q], tr[pp], W[pp][q]);
+          if (qi >= 0) a[r][q] = zsub(a[r][q], W[qi][q]);
+        }
+      }
+    }
+    // factor panel j + 1: one workgroup barrier per column (as in gj_coop_kernel)
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) {
+      if (jj < kb) {
+        const int gc = k0 + jj, par = jj & 1;
+        double best = -1.0;
+        int besti = 0x7fffffff;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int row = tid + r * NT;
+          if (!used[r]) {
+            const double v = zabs2(a[r][jj]);
+            if (gj_better(v, row, best, besti)) {
+              best = v;
+              besti = row;
+            }
+          }
+        }
+        gj_wave_argmax(best, besti);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r)
+          if (besti == tid + r * NT) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) crow[par][wave][q] = a[r][q];
+          }
+        if (lane == 0) {
+          cv[par][wave] = best;
+          ci[par][wave] = besti;
+        }
+        __syncthreads();
+        double b = cv[par][0];
+        int p = ci[par][0], pw = 0;
+#pragma unroll
+        for (int q = 1; q < NW; ++q)
+          if (gj_better(cv[par][q], ci[par][q], b, p)) {
+            b = cv[par][q];
+            p = ci[par][q];
+            pw = q;
+          }
+        // n - gc > 0 rows remain unused, so p < n
+        if (tid == 0) {
+          g.piv[gc] = p;
+          if (!(b > 0.0) && *g.info == 0) *g.info = gc + 1;
+        }
+        zd pr[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) pr[q] = crow[par][pw][q];
+        const double d2 = zabs2(pr[jj]);
+        const double sc = d2 > 0.0 ? 1.0 / d2 : 0.0;
+        const zd inv{pr[jj].re * sc, -pr[jj].im * sc};
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          const int row = tid + r * NT;
+          if (row == p) {
+            used[r] = true;
+            g.rowcol[row] = gc;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) a[r][q] = (q == jj) ? inv : gj_mul(a[r][q], inv);
+          } else if (row < n) {
+            const zd fi = gj_mul(a[r][jj], inv);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) a[r][q] = (q == jj) ? zd{-fi.re, -fi.im} : gj_fms(a[r][q], fi, pr[q]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int row = tid + r * NT;
+      if (row < n) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < kb) A[row + (int64_t)(k0 + q) * lda] = a[r][q];
+      }
+    }
+    return;
+  }
+  // ---- the other workgroups: apply panel j to kStepCols columns (all rows), skipping the
+  // columns of panels j (the multipliers) and j + 1 (workgroup 0's)
+  if (nb == 0) return;
+  const int c0 = (blockIdx.x - 1) * kStepCols;
+  const int s0 = (j + 1) * NB, s1 = min(n, s0 + NB);
+  for (int e = tid; e < NB * kStepCols; e += NT) {
+    const int pp = e / kStepCols, cc = e % kStepCols, c = c0 + cc;
+    W[pp][cc] = (pp < nb && c < n) ? A[g.piv[j0 + pp] + (int64_t)c * lda] : zd{0.0, 0.0};
+  }
+  __syncthreads();  // every pivot-row value is read before any row of these columns changes
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int row = tid + r * NT;
+    if (row >= n) continue;
+    zd tr[NB];
+#pragma unroll
+    for (int pp = 0; pp < NB; ++pp) tr[pp] = pp < nb ? A[row + (int64_t)(j0 + pp) * lda] : zd{0.0, 0.0};
+    const int rc = g.rowcol[row];
+    const int qi = (rc >= j0 && rc < j0 + nb) ? rc - j0 : -1;
+    for (int cc = 0; cc < kStepCols; ++cc) {
+      const int c = c0 + cc;
+      if (c >= n) break;
+      if ((c >= j0 && c < j0 + nb) || (c >= s0 && c < s1)) continue;
+      zd v = A[row + (int64_t)c * lda];
+#pragma unroll
+      for (int pp = 0; pp < NB; ++pp) gj_fma(v, tr[pp], W[pp][cc]);
+      if (qi >= 0) v = zsub(v, W[qi][cc]);
+      A[row + (int64_t)c * lda] = v;
+    }
+  }
+}
+
+// out[i, c] = M[piv[i], rowcol[c]]  (grid: row blocks of 256 x columns)
+__global__ void __launch_bounds__(256) gj_step_gather_kernel(GjStepArgs g, zd* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+  if (i >= g.n) return;
+  out[i + (int64_t)c * g.n] = g.A[g.piv[i] + (int64_t)g.rowcol[c] * g.lda];
 }
 
 // Row swaps of the panel applied to columns outside J. grid.x = task, grid.y = column chunk.
@@ -1373,20 +1543,23 @@ void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStrea
   FMMLU_HIP(hipGetLastError());
 }
 
+// (rows per thread, panel width) for matrices of up to n rows
+template <class F>
+void gj_coop_dispatch(int nmax, F&& f) {
+  if (nmax <= kGjCoopThreads)
+    f(reinterpret_cast<const void*>(gj_coop_kernel<1, 16>));
+  else
+    f(reinterpret_cast<const void*>(gj_coop_kernel<2, 16>));
+}
+
 void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st) {
   if (ntasks <= 0 || nwg_total <= 0) return;
   if (nmax > kGjCoopMax) throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
   void* args[] = {(void*)&tasks, (void*)&ntasks};
-  coop_launch(
-      [&]() {
-        if (nmax <= kGjCoopThreads)
-          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<1>),
-                                               dim3((unsigned)nwg_total), dim3(kGjCoopThreads), args, 0, st));
-        else
-          FMMLU_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(gj_coop_kernel<2>),
-                                               dim3((unsigned)nwg_total), dim3(kGjCoopThreads), args, 0, st));
-      },
-      st);
+  gj_coop_dispatch(nmax, [&](const void* k) {
+    coop_launch([&]() { FMMLU_HIP(hipLaunchCooperativeKernel(k, dim3((unsigned)nwg_total), dim3(kGjCoopThreads), args, 0, st)); },
+                st);
+  });
   FMMLU_HIP(hipGetLastError());
 }
 
@@ -1394,13 +1567,24 @@ int gj_coop_capacity(int nmax) {
   int dev = 0, per_cu = 0, cus = 0;
   FMMLU_HIP(hipGetDevice(&dev));
   FMMLU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  if (nmax <= kGjCoopThreads)
-    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<1>),
-                                                           kGjCoopThreads, 0));
-  else
-    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(gj_coop_kernel<2>),
-                                                           kGjCoopThreads, 0));
+  gj_coop_dispatch(nmax, [&](const void* k) {
+    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kGjCoopThreads, 0));
+  });
   return per_cu * cus;
+}
+
+void launch_gj_step(const GjStepArgs& a, int j, hipStream_t st) {
+  if (a.n <= 0) return;
+  if (a.n > kGjStepMax) throw Error(FMMLU_EINVAL, "stepped Gauss-Jordan takes n <= 2048");
+  const int ncb = (a.n + kStepCols - 1) / kStepCols;
+  hipLaunchKernelGGL(gj_step_kernel, dim3(1 + ncb), dim3(kGjStepThreads), 0, st, a, j);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_gj_step_gather(const GjStepArgs& a, zd* out, hipStream_t st) {
+  if (a.n <= 0) return;
+  hipLaunchKernelGGL(gj_step_gather_kernel, dim3((a.n + 255) / 256, a.n), dim3(256), 0, st, a, out);
+  FMMLU_HIP(hipGetLastError());
 }
 
 int gj_panel_capacity() {
