@@ -229,10 +229,76 @@ class DoubleHostStage {
   int cur_ = 0;
 };
 
+// Task descriptors on their way to the device: pinned host and device buffers of equal size,
+// bump-allocated at the same offsets, so the uploads queued between two launches leave in
+// one copy. Chunks are kept for reuse; reset() only after the device is done with them.
+class UploadRing {
+ public:
+  ~UploadRing() {
+    for (auto& c : chunks_) {
+      (void)hipHostFree(c.h);
+      (void)hipFree(c.d);
+    }
+  }
+  bool pending() const { return cur_ < chunks_.size() && flushed_ < used_; }
+  // host and device addresses of b bytes (the caller flushes first when told to)
+  bool fits(size_t b) const { return cur_ < chunks_.size() && used_ + align(b) <= chunks_[cur_].cap; }
+  std::pair<void*, void*> alloc(size_t b) {
+    b = align(b);
+    if (!fits(b)) {
+      // next chunk that fits, else a new one (pending bytes of the current chunk are
+      // flushed by the caller before this point)
+      size_t next = cur_ < chunks_.size() ? cur_ + 1 : 0;
+      while (next < chunks_.size() && chunks_[next].cap < b) ++next;
+      if (next >= chunks_.size()) {
+        Chunk c{};
+        c.cap = std::max(b, size_t(16) << 20);
+        FMMLU_HIP(hipHostMalloc(&c.h, c.cap, hipHostMallocDefault));
+        if (hipMalloc(&c.d, c.cap) != hipSuccess) {
+          (void)hipGetLastError();
+          (void)hipHostFree(c.h);
+          throw Error(FMMLU_ENOMEM, "upload buffer allocation failed");
+        }
+        chunks_.push_back(c);
+        next = chunks_.size() - 1;
+      }
+      cur_ = next;
+      used_ = flushed_ = 0;
+    }
+    Chunk& c = chunks_[cur_];
+    std::pair<void*, void*> r{static_cast<char*>(c.h) + used_, static_cast<char*>(c.d) + used_};
+    used_ += b;
+    return r;
+  }
+  void flush(hipStream_t st) {
+    if (!pending()) return;
+    Chunk& c = chunks_[cur_];
+    FMMLU_HIP(hipMemcpyAsync(static_cast<char*>(c.d) + flushed_, static_cast<char*>(c.h) + flushed_,
+                             used_ - flushed_, hipMemcpyHostToDevice, st));
+    flushed_ = used_;
+  }
+  void reset() {
+    cur_ = 0;
+    used_ = flushed_ = 0;
+  }
+
+ private:
+  static size_t align(size_t b) { return std::max<size_t>((b + 255) & ~size_t(255), 256); }
+  struct Chunk {
+    void* h;
+    void* d;
+    size_t cap;
+  };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, used_ = 0, flushed_ = 0;
+};
+
 struct Stage {
   // device scratch and pinned staging, double-buffered across colour phases
   DoubleArena dev;
   DoubleHostStage host;
+  UploadRing ring[2];
+  int rcur = 0;
   hipStream_t st = nullptr;
   Profiler* prof = nullptr;
   // the buffers are freed only once the stream's work on them has finished (also when an
@@ -242,19 +308,28 @@ struct Stage {
   }
   // switch to the other buffer at the start of a colour phase (see DoubleArena)
   void flip() {
+    flush();
     dev.flip();
     host.flip();
+    rcur ^= 1;
+    ring[rcur].reset();
+  }
+  // queued uploads leave in one copy; every launch that may read them goes through go()
+  void flush() { ring[rcur].flush(st); }
+  hipStream_t go() {
+    flush();
+    return st;
   }
 
   template <class T>
   T* up(const std::vector<T>& v) {
     if (v.empty()) return nullptr;
-    size_t b = v.size() * sizeof(T);
-    void* h = host.alloc(b);
-    std::memcpy(h, v.data(), b);
-    T* d = static_cast<T*>(dev.alloc(b));
-    FMMLU_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, st));
-    return d;
+    const size_t b = v.size() * sizeof(T);
+    UploadRing& r = ring[rcur];
+    if (!r.fits(b)) r.flush(st);
+    auto hd = r.alloc(b);
+    std::memcpy(hd.first, v.data(), b);
+    return static_cast<T*>(hd.second);
   }
   // persistent upload into another arena
   template <class T>
@@ -269,6 +344,7 @@ struct Stage {
   }
   double t_wait = 0;
   void sync() {
+    flush();
     auto a = std::chrono::steady_clock::now();
     FMMLU_HIP(hipStreamSynchronize(st));
     t_wait += std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
@@ -278,6 +354,8 @@ struct Stage {
     if (prof) prof->harvest();
     dev.reset_all();
     host.reset_all();
+    ring[0].reset();
+    ring[1].reset();
   }
 };
 
@@ -352,7 +430,7 @@ struct GemmBatch {
   }
   void launch(Stage& sg, int opA, bool c32 = false) {
     if (tasks.empty()) return;
-    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.st);
+    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.go());
   }
   void run(Stage& sg, int opA) {
     prepare(sg);
@@ -375,7 +453,7 @@ void batched_inverse_pipeline(Stage& sg, std::vector<GjTask>& tasks, const std::
   int nmulti = 0;
   for (auto& t : tasks) nmulti += gj_wpt(t.n) > 1 ? 1 : 0;
   int32_t* counters = nmulti ? sg.dev.alloc_n<int32_t>(nmulti) : nullptr;
-  if (nmulti) FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * nmulti, sg.st));
+  if (nmulti) FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * nmulti, sg.go()));
   int ci = 0;
   for (int i = 0; i < nt; ++i) {
     GjTask& t = tasks[i];
@@ -460,12 +538,12 @@ void batched_inverse_pipeline(Stage& sg, std::vector<GjTask>& tasks, const std::
   ProfScope ps(*sg.prof, cls);
   int step = 0;
   for (int j0 = 0; j0 < nmax; j0 += kGjBlock, ++step) {
-    for (auto& pg : pgroups) launch_gj_panel(pg.dt, pg.count, j0, pg.wmax, sg.st);
-    launch_gj_swapcopy(dt, nt, j0, nmax, dW, sg.st);
+    for (auto& pg : pgroups) launch_gj_panel(pg.dt, pg.count, j0, pg.wmax, sg.go());
+    launch_gj_swapcopy(dt, nt, j0, nmax, dW, sg.go());
     if (sidx[step][1] > 0)
-      launch_gemm(0, all.dt + sidx[step][0], (int)sidx[step][1], sidx[step][3], all.ds, false, sg.st);
+      launch_gemm(0, all.dt + sidx[step][0], (int)sidx[step][1], sidx[step][3], all.ds, false, sg.go());
   }
-  launch_gj_unpermute(dt, nt, nmax, dout, dwork, sg.st);
+  launch_gj_unpermute(dt, nt, nmax, dout, dwork, sg.go());
   for (auto& t : tasks) sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
 }
 
@@ -498,7 +576,7 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
     size_t nsync = 0;
     for (auto& c : small) nsync += (size_t)gj_coop_sync_words(c.n, NB);
     int32_t* counters = sg.dev.alloc_n<int32_t>(nsync);
-    FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * nsync, sg.st));
+    FMMLU_HIP(hipMemsetAsync(counters, 0, sizeof(int32_t) * nsync, sg.go()));
     size_t so = 0;
     for (size_t i = 0; i < small.size(); ++i) {
       small[i].piv = sg.dev.alloc_n<int32_t>(small[i].n);
@@ -533,7 +611,7 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
       if (grp.empty()) throw Error(FMMLU_EINVAL, "pivot block too large for one cooperative launch");
       GjCoopTask* dt = sg.up(grp);
       ProfScope ps(*sg.prof, cls);
-      launch_gj_coop(dt, (int)grp.size(), units, nmax, sg.st);
+      launch_gj_coop(dt, (int)grp.size(), units, nmax, sg.go());
     }
     for (auto& t : small) sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
   }
@@ -554,11 +632,11 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
     a.info = info_dev;
     a.piv = sg.dev.alloc_n<int32_t>(t.n);
     a.rowcol = sg.dev.alloc_n<int32_t>(t.n);
-    FMMLU_HIP(hipMemsetAsync(a.rowcol, 0xFF, sizeof(int32_t) * t.n, sg.st));  // all -1
+    FMMLU_HIP(hipMemsetAsync(a.rowcol, 0xFF, sizeof(int32_t) * t.n, sg.go()));  // all -1
     ProfScope ps(*sg.prof, cls);
     const int npan = (t.n + kGjStepNb - 1) / kGjStepNb;
-    for (int j = -1; j < npan; ++j) launch_gj_step(a, j, sg.st);
-    launch_gj_step_gather(a, lo[i], sg.st);
+    for (int j = -1; j < npan; ++j) launch_gj_step(a, j, sg.go());
+    launch_gj_step_gather(a, lo[i], sg.go());
     sg.prof->flops[cls] += 8.0 * (double)t.n * t.n * t.n;
   }
   batched_inverse_pipeline(sg, huge, ho, info_dev, cls);
@@ -637,9 +715,9 @@ void batched_qr(Stage& sg, const std::vector<zd*>& Ms, const std::vector<int>& r
   {
     ProfScope ps(*sg.prof, KC_QR);
     for (auto& stp : steps) {
-      launch_qr_panel(stp.dqt, stp.nq, sg.st);
+      launch_qr_panel(stp.dqt, stp.nq, sg.go());
       stp.g1.launch(sg, 2);
-      if (stp.nrt) launch_reduce_tw(stp.drt, stp.nrt, stp.cmax, sg.st);
+      if (stp.nrt) launch_reduce_tw(stp.drt, stp.nrt, stp.cmax, sg.go());
       stp.g3.launch(sg, 0);
     }
   }
@@ -954,7 +1032,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int64_t* ddof = sg.up(dof);
         AsmSrc* dtab = sg.up(table);
         ProfScope ps(prof, KC_ASSEMBLE);
-        launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, f32, pool, f32, st);
+        launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, f32, pool, f32, sg.go());
       }
       prof.bytes[KC_ASSEMBLE] += (double)te * (double)pool_elems * (first_level ? 1.0 : 2.0);
       prev_pool = nullptr;
@@ -1104,7 +1182,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         IdTask* didt = sg.up(idt);
         QSeg* dq = qsegs.empty() ? nullptr : sg.up(qsegs);
         ProfScope ps(prof, KC_IDMAT);
-        launch_build_idmatrix(g, didt, nb, units, dq, act_dev, pool, f32, st);
+        launch_build_idmatrix(g, didt, nb, units, dq, act_dev, pool, f32, sg.go());
       }
       for (auto& bp : plan) prof.bytes[KC_IDMAT] += 16.0 * (double)bp.rows * bp.m;
       // ---- 2. greedy CPQR of M: through the Gram matrix (pivoted Cholesky of M^H M) when
@@ -1153,11 +1231,11 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         {
           ProfScope ps(prof, KC_QR);
           gg.launch(sg, 2);
-          launch_sum_parts(dst_, (int)st_.size(), su, st);
+          launch_sum_parts(dst_, (int)st_.size(), su, sg.go());
         }
         {
           ProfScope ps(prof, KC_CPQR);
-          launch_pchol(dpt, nb, mmax, eps, st);
+          launch_pchol(dpt, nb, mmax, eps, sg.go());
         }
       } else {
         std::vector<zd*> Ms;
@@ -1183,8 +1261,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         CpqrTask* dct = sg.up(ct);
         {
           ProfScope ps(prof, KC_CPQR);
-          launch_extract_r(det, nb, mmax, st);
-          launch_cpqr(dct, nb, mmax, eps, st);
+          launch_extract_r(det, nb, mmax, sg.go());
+          launch_cpqr(dct, nb, mmax, eps, sg.go());
         }
       }
       // ---- read back ranks and pivots
@@ -1192,8 +1270,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       std::vector<std::vector<int32_t>> perms(nb);
       {
         int32_t* hr = static_cast<int32_t*>(sg.host.alloc(sizeof(int32_t) * (size_t)(nb + perm_total)));
-        FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
-        FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, st));
+        FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
+        FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
         sg.sync();
         int64_t po = nb;
         for (int i = 0; i < nb; ++i) {
@@ -1320,7 +1398,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         NSeg* dns = nsegs.empty() ? nullptr : sg.up(nsegs);
         {
           ProfScope ps(prof, KC_ELIM);
-          launch_gather_cross(dcross, ne, cunits, dns, pool, f32, st);
+          launch_gather_cross(dcross, ne, cunits, dns, pool, f32, sg.go());
         }
         // E/F transforms (Section 4.1). Ccol = A[(R,S,N),(S,R)], Crow = A[(S,R),(R,S,N)]:
         //   Ccol[:, s:m]      -= Ccol[:, 0:s] T        (A_{.R} - A_{.S} T)
@@ -1401,8 +1479,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           ProfScope ps(prof, KC_ELIM);
           gp.launch(sg, 0);
           gl.launch(sg, 0, f32);
-          if (dcp) launch_copy(dcp, (int)cps.size(), cu, f32, st);
-          if (dtr) launch_transpose(dtr, (int)trs.size(), tu, f32, st);
+          if (dcp) launch_copy(dcp, (int)cps.size(), cu, f32, sg.go());
+          if (dtr) launch_transpose(dtr, (int)trs.size(), tu, f32, sg.go());
           for (auto& e : ep) prof.flops[KC_ELIM] += 8.0 * 2.0 * (double)e.nsn * e.r * e.r;
         }
         ht.mark(4);
@@ -1701,7 +1779,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int64_t* ddof = sg.up(dof);
         AsmSrc* dtab = sg.up(table);
         ProfScope ps(prof, KC_TOP);
-        launch_assemble(g, dt, 1, units64(n0, n0), dslot, didx, ddof, dtab, prev_pool, f32, Att, false, st);
+        launch_assemble(g, dt, 1, units64(n0, n0), dslot, didx, ddof, dtab, prev_pool, f32, Att, false, sg.go());
       }
       Ainv = arena.alloc_n<zd>((size_t)n0 * n0);
       std::vector<GjTask> gt(1);
