@@ -430,7 +430,9 @@ struct GemmBatch {
   }
   void launch(Stage& sg, int opA, bool c32 = false) {
     if (tasks.empty()) return;
-    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.go());
+    bool mapped = false;
+    for (auto& t : tasks) mapped = mapped || t.rmap || t.cmap;
+    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.go(), mapped);
   }
   void run(Stage& sg, int opA) {
     prepare(sg);

@@ -97,8 +97,9 @@ __host__ __device__ inline int64_t gemm_task_tiles(int M, int N, int lower) {
   const int64_t tm = (M + kGemmTile - 1) / kGemmTile, tn = (N + kGemmTile - 1) / kGemmTile;
   return lower ? tm * (tm + 1) / 2 : tm * tn;
 }
+// mapped: tasks may carry rmap / cmap (a separate kernel instance); otherwise they are ignored
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
-                 hipStream_t st);
+                 hipStream_t st, bool mapped = false);
 
 // ---- Householder panel factorization (unpivoted QR) ----
 struct QrTask {

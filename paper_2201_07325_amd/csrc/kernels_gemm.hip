@@ -56,7 +56,8 @@ __device__ inline int find_unit_task(const Task* __restrict__ t, int n, int64_t 
 constexpr int BM = kGemmTile, BN = kGemmTile, BK = 16;
 constexpr int LDP = BM + 4;  // padded LDS row (doubles)
 
-template <int OPA, class CT>
+// SCAT: C entries through the row / column maps (the Schur updates of pair tiles)
+template <int OPA, class CT, bool SCAT>
 __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks,
                                                          const GemmSeg* __restrict__ segs) {
   using M = Mfma<CT>;
@@ -191,8 +192,8 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
         const int i = row0 + wr + 16 * a + M::row(lane, r);
         const int j = col0 + wc + 16 * b + (lane & 15);
         if (i >= t.M || j >= t.N) continue;
-        const int ri = t.rmap ? t.rmap[i] : i;
-        const int cj = t.cmap ? t.cmap[j] : j;
+        const int ri = (SCAT && t.rmap) ? t.rmap[i] : i;
+        const int cj = (SCAT && t.cmap) ? t.cmap[j] : j;
         CT* c = Cb + ri + (int64_t)cj * t.ldc;
         zd v = zmul(alpha, zd{(double)cr[a][b][r], (double)ci[a][b][r]});
         if (t.beta != 0.0) v = zadd(v, zscale(widen(*c), t.beta));
@@ -203,18 +204,25 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
 }  // namespace
 
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
-                 hipStream_t st) {
+                 hipStream_t st, bool mapped) {
   if (ntasks <= 0 || nunits <= 0) return;
   const dim3 g((unsigned)nunits), b(256);
+  if (mapped && opA != 0) throw Error(FMMLU_EINVAL, "mapped GEMM takes opA = N");
   if (c32) {
     if (opA != 0) throw Error(FMMLU_EINVAL, "float32 GEMM takes opA = N");
-    hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf>), g, b, 0, st, tasks, ntasks, segs);
+    if (mapped)
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, true>), g, b, 0, st, tasks, ntasks, segs);
+    else
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false>), g, b, 0, st, tasks, ntasks, segs);
   } else if (opA == 0) {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd>), g, b, 0, st, tasks, ntasks, segs);
+    if (mapped)
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, true>), g, b, 0, st, tasks, ntasks, segs);
+    else
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false>), g, b, 0, st, tasks, ntasks, segs);
   } else if (opA == 1) {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd>), g, b, 0, st, tasks, ntasks, segs);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false>), g, b, 0, st, tasks, ntasks, segs);
   } else {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd>), g, b, 0, st, tasks, ntasks, segs);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd, false>), g, b, 0, st, tasks, ntasks, segs);
   }
   FMMLU_HIP(hipGetLastError());
 }
