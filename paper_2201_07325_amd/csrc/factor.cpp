@@ -1882,29 +1882,94 @@ void FactorImpl::ensure_workspace() {
 }
 
 void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) {
+  SolveWs w;
+  w.x = wx;
+  w.y = wy;
+  w.top = wtop;
+  w.xr = wxr;
+  w.p = wp;
+  w.xrp = wxrp;
+  w.yp = wyp;
+  w.tp = wtp;
+  sweep(w, 1, bc, n, xc, n, 1, adjoint, st);
+}
+
+void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* xc, int64_t ldx, int m,
+                       bool adjoint, hipStream_t st) {
   const int adj = adjoint ? 1 : 0;
-  launch_permute(bc, wx, order_dev, n, 1, st);
+  launch_permute(bc, w.x, order_dev, n, 1, st, nr, ldb, m);
   // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
   for (auto& ph : phases) {
     const int nb = ph.box_end - ph.box_begin;
-    launch_solve_xr_part(ph.dboxes, ph.dxr, ph.nxr, wx, wxrp, adj, f32, st);
-    launch_solve_xr_fin(ph.dboxes, nb, wx, wxr, wxrp, st);
-    launch_solve_y_part(ph.dboxes, ph.dyp, ph.nyp, wxr, wyp, adj, f32, st);
-    launch_solve_y_red(ph.dboxes, ph.dyr, ph.nyr, wyp, wy, st);
-    launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, wy, wx, st);
+    launch_solve_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st, nr);
+    launch_solve_xr_fin(ph.dboxes, nb, w.x, w.xr, w.xrp, st, nr);
+    launch_solve_y_part(ph.dboxes, ph.dyp, ph.nyp, w.xr, w.yp, adj, f32, st, nr);
+    launch_solve_y_red(ph.dboxes, ph.dyr, ph.nyr, w.yp, w.y, st, nr);
+    launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, w.y, w.x, st, nr);
   }
   // D^{-1} (adjoint D^{-H}): all pivot blocks, then the top block
-  launch_solve_diag(all_boxes, nall, rmax_all, wx, adj, f32, st);
-  launch_solve_top(Ainv, n0, top_dev, wx, wtop, adj, st);
+  launch_solve_diag(all_boxes, nall, rmax_all, w.x, adj, f32, st, nr);
+  launch_solve_top(Ainv, n0, top_dev, w.x, w.top, adj, st, nr);
   // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
     const int nb = it->box_end - it->box_begin;
-    launch_solve_bpart(it->dboxes, it->dbp, it->nbp, wx, wp, adj, f32, st);
-    launch_solve_bfin(it->dboxes, nb, wp, wx, wxr, st);
-    launch_solve_bt_part(it->dboxes, it->dbt, it->nbt, wxr, wtp, adj, f32, st);
-    launch_solve_bt_fin(it->dboxes, it->dbf, it->nbf, wtp, wx, st);
+    launch_solve_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st, nr);
+    launch_solve_bfin(it->dboxes, nb, w.p, w.x, w.xr, st, nr);
+    launch_solve_bt_part(it->dboxes, it->dbt, it->nbt, w.xr, w.tp, adj, f32, st, nr);
+    launch_solve_bt_fin(it->dboxes, it->dbf, it->nbf, w.tp, w.x, st, nr);
   }
-  launch_permute(wx, xc, order_dev, n, 0, st);
+  launch_permute(w.x, xc, order_dev, n, 0, st, nr, ldx, m);
+}
+
+// the blocked sweeps keep kSolveBlock copies of the largest x_R in LDS for the diagonal step
+bool FactorImpl::blocked_ok() const { return (size_t)rmax_all * kSolveBlock * sizeof(zd) <= 65536; }
+
+void FactorImpl::ensure_block_workspace() {
+  if (wsb.x) return;
+  const size_t B = kSolveBlock;
+  auto al = [&](int64_t len) { return arena.alloc_n<zd>((size_t)std::max<int64_t>(len, 1) * B); };
+  const int64_t nblk = (n0 + 255) / 256;
+  wsb.x = al(n);
+  wsb.y = al(ymax);
+  wsb.top = al((int64_t)n0 * (1 + nblk));
+  wsb.xr = al(xrmax);
+  wsb.p = al(pmax);
+  wsb.xrp = al(xrpmax);
+  wsb.yp = al(ypmax);
+  wsb.tp = al(tpmax);
+  ginb = al(n);
+  goutb = al(n);
+}
+
+// the blocked sweeps of one direction in a graph on the private stream (ginb -> goutb)
+bool FactorImpl::capture_block(int adj) {
+  if (gexecb[adj]) return true;
+  if (!gstream) FMMLU_HIP(hipStreamCreateWithFlags(&gstream, hipStreamNonBlocking));
+  if (hipStreamBeginCapture(gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  bool ok = true;
+  try {
+    sweep(wsb, kSolveBlock, ginb, n, goutb, n, kSolveBlock, adj != 0, gstream);
+  } catch (const Error&) {
+    ok = false;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(gstream, &g) != hipSuccess || !ok || !g) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    return false;
+  }
+  hipGraphExec_t e = nullptr;
+  if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipGraphDestroy(g);
+    return false;
+  }
+  graphb[adj] = g;
+  gexecb[adj] = e;
+  return true;
 }
 
 // Capture the sweeps of one direction into a graph on a private stream (reading gin,
@@ -1946,6 +2011,26 @@ bool FactorImpl::capture(int adj) {
 void FactorImpl::solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st) {
   ensure_workspace();
   const int adj = adjoint ? 1 : 0;
+  if (nrhs > 1 && blocked_ok()) {
+    // blocks of kSolveBlock columns: every factor entry is read once per block
+    ensure_block_workspace();
+    const bool g = use_graph && capture_block(adj);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += kSolveBlock) {
+      const int m = (int)std::min<int64_t>(kSolveBlock, nrhs - c0);
+      const zd* bc = b + c0 * n;
+      zd* xc = x + c0 * n;
+      if (g) {
+        FMMLU_HIP(hipMemcpyAsync(ginb, bc, sizeof(zd) * (size_t)(n * m), hipMemcpyDeviceToDevice, st));
+        if (m < kSolveBlock)
+          FMMLU_HIP(hipMemsetAsync(ginb + n * m, 0, sizeof(zd) * (size_t)(n * (kSolveBlock - m)), st));
+        FMMLU_HIP(hipGraphLaunch(gexecb[adj], st));
+        FMMLU_HIP(hipMemcpyAsync(xc, goutb, sizeof(zd) * (size_t)(n * m), hipMemcpyDeviceToDevice, st));
+      } else {
+        sweep(wsb, kSolveBlock, bc, n, xc, n, m, adjoint, st);
+      }
+    }
+    return;
+  }
   const bool g = use_graph && capture(adj);
   if (!g) use_graph = false;
   for (int64_t c = 0; c < nrhs; ++c) {
@@ -1965,6 +2050,8 @@ FactorImpl::~FactorImpl() {
   // solves may still be running on any stream; the arenas are freed after the device drains
   (void)hipDeviceSynchronize();
   for (int a = 0; a < 2; ++a) {
+    if (gexecb[a]) (void)hipGraphExecDestroy(gexecb[a]);
+    if (graphb[a]) (void)hipGraphDestroy(graphb[a]);
     if (gexec[a]) (void)hipGraphExecDestroy(gexec[a]);
     if (graph[a]) (void)hipGraphDestroy(graph[a]);
   }

@@ -84,6 +84,12 @@ struct SolvePhase {
   int rmax = 0, smax = 0;
 };
 
+// Workspace of the sweeps for blocks of nr right-hand sides (interleaved vectors)
+struct SolveWs {
+  zd *x = nullptr, *y = nullptr, *top = nullptr, *xr = nullptr, *p = nullptr;
+  zd *xrp = nullptr, *yp = nullptr, *tp = nullptr;
+};
+
 struct FactorImpl {
   int64_t n = 0;
   double k = 0, eta = 0;
@@ -129,7 +135,19 @@ struct FactorImpl {
   void solve(const zd* b, zd* x, int64_t nrhs, bool adjoint, hipStream_t st);
   // one right-hand side, every kernel of the sweeps (no copies, no allocation)
   void solve_core(const zd* b, zd* x, bool adjoint, hipStream_t st);
+  // the sweeps for m <= nr right-hand sides (columns of b and x at strides ldb, ldx)
+  void sweep(const SolveWs& w, int nr, const zd* b, int64_t ldb, zd* x, int64_t ldx, int m, bool adjoint,
+             hipStream_t st);
   void ensure_workspace();
+  // blocks of kSolveBlock right-hand sides (allocated on the first multi-column solve)
+  SolveWs wsb{};
+  zd* ginb = nullptr;
+  zd* goutb = nullptr;
+  hipGraph_t graphb[2] = {nullptr, nullptr};
+  hipGraphExec_t gexecb[2] = {nullptr, nullptr};
+  bool blocked_ok() const;
+  void ensure_block_workspace();
+  bool capture_block(int adj);
   // solves replay a captured HIP graph per direction (input/output through gin/gout)
   bool use_graph = true;
   hipStream_t gstream = nullptr;

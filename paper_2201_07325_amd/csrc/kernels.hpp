@@ -312,37 +312,45 @@ constexpr int kSolveKr = 64;     // k-chunk of row GEMVs (over r)
 constexpr int kSolveK = 256;     // k-chunk of column GEMVs (over s or s + nN)
 constexpr int kSolveOut = 64;    // outputs per column-GEMV work item
 
+// Every solve launcher takes nr = 1 or kSolveBlock right-hand sides; vectors inside the
+// sweeps are interleaved (entry i of right-hand side c at [i nr + c]).
+constexpr int kSolveBlock = 8;
 // forward: partials of op(T)^T x_S (T^T, adjoint T^H) per (box, s-chunk, output group)
 void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
-                          bool f32, hipStream_t st);
+                          bool f32, hipStream_t st, int nr = 1);
 // forward, per box: x_R -= sum of partials; copy to XR
-void launch_solve_xr_fin(const SolveBox* boxes, int nb, zd* x, zd* XR, const zd* Pxr, hipStream_t st);
+void launch_solve_xr_fin(const SolveBox* boxes, int nb, zd* x, zd* XR, const zd* Pxr, hipStream_t st, int nr = 1);
 // forward: partials of op(P) x_R (Lp, adjoint conj(Up^T)) per (box, row chunk, k-chunk)
 void launch_solve_y_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Yp, int adjoint,
-                         bool f32, hipStream_t st);
+                         bool f32, hipStream_t st, int nr = 1);
 // forward: y = sum of partials per (box, row chunk)
-void launch_solve_y_red(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Yp, zd* y, hipStream_t st);
+void launch_solve_y_red(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Yp, zd* y, hipStream_t st,
+                        int nr = 1);
 // x[dst[d]] -= sum of y[src[q]] over ptr[d] <= q < ptr[d+1] (deterministic scatter)
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
-                        const zd* y, zd* x, hipStream_t st);
-// diagonal: x_R = Xi x_R (adjoint Xi^H x_R) for every box
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, bool f32, hipStream_t st);
+                        const zd* y, zd* x, hipStream_t st, int nr = 1);
+// diagonal: x_R = Xi x_R (adjoint Xi^H x_R) for every box (rmax nr 16 bytes of LDS <= 64 KiB)
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, bool f32, hipStream_t st,
+                       int nr = 1);
 // backward: partials of op(Q)^T x_SN (Up, adjoint Lp^H) per (box, column chunk, output group)
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
-                        int adjoint, bool f32, hipStream_t st);
+                        int adjoint, bool f32, hipStream_t st, int nr = 1);
 // backward, per box: x_R -= sum of partials; copy to XR
-void launch_solve_bfin(const SolveBox* boxes, int nb, const zd* Pbuf, zd* x, zd* XR, hipStream_t st);
+void launch_solve_bfin(const SolveBox* boxes, int nb, const zd* Pbuf, zd* x, zd* XR, hipStream_t st, int nr = 1);
 // backward: partials of op(T) x_R (T, adjoint conj(T)) per (box, s-row chunk, k-chunk)
 void launch_solve_bt_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Pt, int adjoint,
-                          bool f32, hipStream_t st);
+                          bool f32, hipStream_t st, int nr = 1);
 // backward: x_S -= sum of partials per (box, s-row chunk)
-void launch_solve_bt_fin(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Pt, zd* x, hipStream_t st);
-// top block: x_t = Ainv x_t (adjoint Ainv^H); tmp holds n0 * (1 + nblk) entries
+void launch_solve_bt_fin(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Pt, zd* x, hipStream_t st,
+                         int nr = 1);
+// top block: x_t = Ainv x_t (adjoint Ainv^H); tmp holds n0 (1 + nblk) nr entries
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
-                      hipStream_t st);
-// permute: gather (dst[i] = src[map[i]]) or scatter (dst[map[i]] = src[i])
+                      hipStream_t st, int nr = 1);
+// permute between the caller's column-major vectors (ld, m <= nr active columns) and the
+// interleaved tree-order block: gather dst[i nr + c] = src[map[i] + c ld] (zero for c >= m),
+// or scatter dst[map[i] + c ld] = src[i nr + c] for c < m
 void launch_permute(const zd* src, zd* dst, const int64_t* map, int64_t n, int gather,
-                    hipStream_t st);
+                    hipStream_t st, int nr = 1, int64_t ld = 0, int m = 1);
 
 // ---- stand-alone block of A~ (rows, cols: tree positions) ----
 void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64_t* cols,
