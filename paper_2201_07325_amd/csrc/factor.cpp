@@ -28,6 +28,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <numeric>
 #include <thread>
 #include <unordered_map>
@@ -144,10 +147,14 @@ struct PairIndex {
   std::vector<int64_t> beg{0};  // owner a's pairs: [beg[a], beg[a + 1])
   std::vector<int32_t> ids;
   std::vector<int64_t> off;
-  int64_t find(int a, int b) const {  // offset of tile (a, b), or -1
+  int64_t pos(int a, int b) const {  // index of pair (a, b) in ids / off, or -1
     const auto first = ids.begin() + beg[a], last = ids.begin() + beg[a + 1];
     const auto it = std::lower_bound(first, last, b);
-    return (it != last && *it == b) ? off[it - ids.begin()] : -1;
+    return (it != last && *it == b) ? (int64_t)(it - ids.begin()) : -1;
+  }
+  int64_t find(int a, int b) const {  // offset of tile (a, b), or -1
+    const int64_t k = pos(a, b);
+    return k < 0 ? -1 : off[k];
   }
   int64_t at(int a, int b) const {
     const int64_t o = find(a, b);
@@ -156,29 +163,81 @@ struct PairIndex {
   }
 };
 
-// fn(lo, hi) over [0, n) split into contiguous ranges of at least `grain` items on up to 8
-// host threads
-template <class F>
-void parallel_ranges(int n, int grain, F&& fn) {
-  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-  const int nt = std::max(1, std::min({8, hw, n / std::max(grain, 1)}));
-  if (nt <= 1) {
-    fn(0, n);
-    return;
+// Host worker threads kept for one factorization: ranges(n, grain, fn) runs fn(lo, hi) over
+// contiguous ranges of [0, n) on the caller and the workers. fn must not throw.
+class HostPool {
+ public:
+  explicit HostPool(int nworkers) : nw_(std::max(1, nworkers)) {
+    for (int w = 1; w < nw_; ++w) th_.emplace_back([this, w] { loop(w); });
   }
-  std::vector<std::thread> th;
-  const int chunk = (n + nt - 1) / nt;
-  for (int t = 1; t < nt; ++t) {
-    const int lo = t * chunk, hi = std::min(n, lo + chunk);
-    if (lo < hi) th.emplace_back([&fn, lo, hi] { fn(lo, hi); });
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> l(m_);
+      stop_ = true;
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
   }
-  fn(0, std::min(n, chunk));
-  for (auto& x : th) x.join();
-}
+  template <class F>
+  void ranges(int n, int grain, F&& fn) {
+    const int nt = std::max(1, std::min(nw_, n / std::max(grain, 1)));
+    if (nt <= 1) {
+      fn(0, n);
+      return;
+    }
+    const int chunk = (n + nt - 1) / nt;
+    std::function<void(int)> job = [&](int w) {
+      const int lo = w * chunk, hi = std::min(n, lo + chunk);
+      if (lo < hi) fn(lo, hi);
+    };
+    {
+      std::lock_guard<std::mutex> l(m_);
+      job_ = &job;
+      nt_ = nt;
+      left_ = nt - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    job(0);
+    std::unique_lock<std::mutex> l(m_);
+    done_.wait(l, [&] { return left_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  void loop(int w) {
+    int64_t seen = 0;
+    for (;;) {
+      std::function<void(int)>* job = nullptr;
+      {
+        std::unique_lock<std::mutex> l(m_);
+        cv_.wait(l, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        if (w >= nt_) continue;
+        job = job_;
+      }
+      (*job)(w);
+      {
+        std::lock_guard<std::mutex> l(m_);
+        if (--left_ == 0) done_.notify_one();
+      }
+    }
+  }
+  int nw_;
+  std::vector<std::thread> th_;
+  std::mutex m_;
+  std::condition_variable cv_, done_;
+  std::function<void(int)>* job_ = nullptr;
+  int nt_ = 0, left_ = 0;
+  int64_t gen_ = 0;
+  bool stop_ = false;
+};
 
 // Host wall-clock accumulators for the verbose report.
 struct HostTimers {
-  double t[9] = {0};
+  double t[16] = {0};
   Clock::time_point last = Clock::now();
   void mark(int i) {
     auto now = Clock::now();
@@ -788,6 +847,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   if (opts.device_mem_cap > 0) arena.set_cap((size_t)opts.device_mem_cap);
   Stage sg;
   sg.st = st;
+  HostPool hp((int)std::min(8u, std::max(1u, std::thread::hardware_concurrency())));
   prof.on = opts.profile != 0;
   prof.st = st;
   sg.prof = &prof;
@@ -897,7 +957,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     // cells within two of its own (in parallel); an owner coarser than one it finds cannot
     // find it back, so those pairs are added to the coarser owner's list afterwards.
     std::vector<std::vector<int>> close(nown);
-    parallel_ranges(nown, 64, [&](int lo, int hi) {
+    hp.ranges(nown, 64, [&](int lo, int hi) {
       for (int i = lo; i < hi; ++i) {
         const Owner& o = own[i];
         auto& v = close[i];
@@ -926,6 +986,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     }
     PairIndex pidx;
     pidx.beg.assign(1, 0);
+    std::vector<int32_t> kcount;  // per pair, zero between colour phases (Schur grouping)
     int64_t pool_elems = 0;
     std::vector<std::pair<int, int>> pairs;
     for (int i = 0; i < nown; ++i) {
@@ -938,6 +999,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       }
       pidx.beg.push_back((int64_t)pidx.ids.size());
     }
+    kcount.assign(pidx.ids.size(), 0);
     ht.mark(0);
     void* pool = nullptr;
     {
@@ -991,42 +1053,55 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         }
         for (int64_t a : o.act) dof.push_back(a);
       }
-      std::vector<AsmTask> tasks;
-      std::vector<AsmSrc> table;
-      int64_t units = 0;
-      for (size_t k = 0; k < pairs.size(); ++k) {
-        const auto& pr = pairs[k];
-        const Owner& a = own[pr.first];
-        const Owner& b = own[pr.second];
-        AsmTask t{};
-        t.out_off = pidx.off[k];
-        t.nr = (int)a.act.size();
-        t.nc = (int)b.act.size();
-        t.ld = t.nr;
-        t.rmap_off = map_off[pr.first];
-        t.cmap_off = map_off[pr.second];
-        t.rdof_off = map_off[pr.first];
-        t.cdof_off = map_off[pr.second];
-        t.tab_off = (int64_t)table.size();
-        if (first_level) {
-          t.nsc = 1;
-          table.push_back(AsmSrc{-1, 0, 0});
-        } else {
-          t.nsc = (int)b.sub.size();
-          for (int sa : a.sub)
-            for (int sb : b.sub) {
-              const int64_t o = prev_pidx.find(sa, sb);
-              if (o < 0)
-                table.push_back(AsmSrc{-1, 0, 0});
-              else
-                table.push_back(AsmSrc{o, (int32_t)prev_own[sa].act.size(), 0});
-            }
-        }
-        t.unit_begin = units;
-        units += units64(t.nr, t.nc);
-        if (t.nr > 0 && t.nc > 0) tasks.push_back(t);
-        else units = t.unit_begin;
+      // tasks and source tables of all pairs: sizes first, then filled on host threads
+      const int np = (int)pairs.size();
+      std::vector<int64_t> tabo(np + 1, 0), unito(np + 1, 0);
+      for (int k = 0; k < np; ++k) {
+        const Owner& a = own[pairs[k].first];
+        const Owner& b = own[pairs[k].second];
+        tabo[k + 1] = tabo[k] + (first_level ? 1 : (int64_t)a.sub.size() * (int64_t)b.sub.size());
+        const bool live = !a.act.empty() && !b.act.empty();
+        unito[k + 1] = unito[k] + (live ? units64((int)a.act.size(), (int)b.act.size()) : 0);
       }
+      std::vector<AsmSrc> table((size_t)tabo[np]);
+      std::vector<AsmTask> all((size_t)np);
+      hp.ranges(np, 256, [&](int lo, int hi) {
+        for (int k = lo; k < hi; ++k) {
+          const auto& pr = pairs[k];
+          const Owner& a = own[pr.first];
+          const Owner& b = own[pr.second];
+          AsmTask t{};
+          t.out_off = pidx.off[k];
+          t.nr = (int)a.act.size();
+          t.nc = (int)b.act.size();
+          t.ld = t.nr;
+          t.rmap_off = map_off[pr.first];
+          t.cmap_off = map_off[pr.second];
+          t.rdof_off = map_off[pr.first];
+          t.cdof_off = map_off[pr.second];
+          t.tab_off = tabo[k];
+          AsmSrc* tab = table.data() + tabo[k];
+          if (first_level) {
+            t.nsc = 1;
+            tab[0] = AsmSrc{-1, 0, 0};
+          } else {
+            t.nsc = (int)b.sub.size();
+            int64_t e = 0;
+            for (int sa : a.sub)
+              for (int sb : b.sub) {
+                const int64_t o = prev_pidx.find(sa, sb);
+                tab[e++] = o < 0 ? AsmSrc{-1, 0, 0} : AsmSrc{o, (int32_t)prev_own[sa].act.size(), 0};
+              }
+          }
+          t.unit_begin = unito[k];
+          all[k] = t;
+        }
+      });
+      std::vector<AsmTask> tasks;
+      tasks.reserve(all.size());
+      for (auto& t : all)
+        if (t.nr > 0 && t.nc > 0) tasks.push_back(t);
+      const int64_t units = unito[np];
       {
         AsmTask* dt = sg.up(tasks);
         int32_t* dslot = sg.up(slot);
@@ -1396,12 +1471,14 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             d.SN = ep[q].nsn ? base + idx_off[q][2] : nullptr;
           }
         }
+        ht.mark(9);
         CrossTask* dcross = sg.up(cross);
         NSeg* dns = nsegs.empty() ? nullptr : sg.up(nsegs);
         {
           ProfScope ps(prof, KC_ELIM);
           launch_gather_cross(dcross, ne, cunits, dns, pool, f32, sg.go());
         }
+        ht.mark(10);
         // E/F transforms (Section 4.1). Ccol = A[(R,S,N),(S,R)], Crow = A[(S,R),(R,S,N)]:
         //   Ccol[:, s:m]      -= Ccol[:, 0:s] T        (A_{.R} - A_{.S} T)
         //   Ccol[0:r, s:m]    -= T^T Ccol[r:m, s:m]    -> X_RR;  Ccol[r:, s:m] = X_{(S u N) R}
@@ -1432,6 +1509,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           gc.launch(sg, 1);
           gb.launch(sg, 1);
         }
+        ht.mark(11);
         // 4. inverse of X_RR (in place in Ccol[0:r, 0:r]) -> Xi
         {
           std::vector<GjTask> gt;
@@ -1446,6 +1524,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           }
           batched_inverse(sg, gt, outs, info_dev, KC_INV);
         }
+        ht.mark(12);
         // panels: Lp = X_{SN,R} Xi ; Up = Xi X_{R,SN}; T compacted into the factor
         {
           GemmBatch gp, gl;  // gl: Lp straight into factor storage (float32 C when f32)
@@ -1491,62 +1570,110 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         {
           struct Contrib {
             int64_t toff;
-            int q;       // elimination index (box order)
+            int64_t k;     // destination pair index (tiles lie in the pool in pair order)
+            int q;         // elimination index (box order)
             int32_t a, b;  // group indices (0 = the box itself, else near owner index + 1)
           };
-          std::vector<Contrib> cl;
           std::vector<std::vector<int>> grps(ne), goffs(ne);
-          for (int q = 0; q < ne; ++q) {
-            ElimPlan& e = ep[q];
-            BoxPlan& bp = plan[e.pi];
-            auto& grp = grps[q];
-            auto& goff = goffs[q];
-            grp.push_back(bp.oi);
-            goff.push_back(0);
-            int off = e.s;
-            for (int o : bp.nown_) {
-              grp.push_back(o);
-              goff.push_back(off);
-              off += (int)own[o].live.size();
-            }
-            for (size_t a = 0; a < grp.size(); ++a)
-              for (size_t b = 0; b < grp.size(); ++b) {
-                const int M = (a == 0) ? e.s : (int)own[grp[a]].live.size();
-                const int N = (b == 0) ? e.s : (int)own[grp[b]].live.size();
-                if (M == 0 || N == 0) continue;
-                cl.push_back(Contrib{pidx.at(grp[a], grp[b]), q, (int32_t)a, (int32_t)b});
+          std::vector<std::vector<Contrib>> pcl(ne);  // per box, built on host threads
+          std::vector<int> bad(ne, 0);
+          hp.ranges(ne, 4, [&](int lo, int hi) {
+            for (int q = lo; q < hi; ++q) {
+              ElimPlan& e = ep[q];
+              BoxPlan& bp = plan[e.pi];
+              auto& grp = grps[q];
+              auto& goff = goffs[q];
+              grp.push_back(bp.oi);
+              goff.push_back(0);
+              int off = e.s;
+              for (int o : bp.nown_) {
+                grp.push_back(o);
+                goff.push_back(off);
+                off += (int)own[o].live.size();
               }
-          }
-          std::stable_sort(cl.begin(), cl.end(), [](const Contrib& x, const Contrib& y) { return x.toff < y.toff; });
-          GemmBatch gs;
-          std::vector<GemmSeg> segs;
-          for (size_t i = 0; i < cl.size();) {
-            size_t j = i;
-            segs.clear();
-            for (; j < cl.size() && cl[j].toff == cl[i].toff; ++j) {
-              const Contrib& c = cl[j];
-              ElimPlan& e = ep[c.q];
-              const int mn = plan[e.pi].m + plan[e.pi].nN;
-              segs.push_back(GemmSeg{e.Ccol + (int64_t)e.s * mn + e.r + goffs[c.q][c.a],
-                                     e.Up + (int64_t)goffs[c.q][c.b] * e.r, mn, e.r, e.r, 0});
+              for (size_t a = 0; a < grp.size(); ++a)
+                for (size_t b = 0; b < grp.size(); ++b) {
+                  const int M = (a == 0) ? e.s : (int)own[grp[a]].live.size();
+                  const int N = (b == 0) ? e.s : (int)own[grp[b]].live.size();
+                  if (M == 0 || N == 0) continue;
+                  const int64_t k = pidx.pos(grp[a], grp[b]);
+                  if (k < 0) {
+                    bad[q] = 1;
+                    continue;
+                  }
+                  pcl[q].push_back(Contrib{pidx.off[k], k, q, (int32_t)a, (int32_t)b});
+                }
             }
-            const Contrib& c0 = cl[i];
-            ElimPlan& e0 = ep[c0.q];
-            BoxPlan& bp0 = plan[e0.pi];
-            const int o1 = grps[c0.q][c0.a], o2 = grps[c0.q][c0.b];
-            const int M = (c0.a == 0) ? e0.s : (int)own[o1].live.size();
-            const int N = (c0.b == 0) ? e0.s : (int)own[o2].live.size();
-            const int32_t* rmap = (c0.a == 0) ? bp0.perm : own[o1].live_dev;
-            const int32_t* cmap = (c0.b == 0) ? bp0.perm : own[o2].live_dev;
-            gs.add(static_cast<char*>(pool) + (size_t)c0.toff * te, (int)own[o1].act.size(), M, N, rmap, cmap, segs,
-                   -1.0, 0.0, 1.0);
-            double kk = 0;
-            for (auto& sgm : segs) kk += sgm.K;
-            prof.flops[KC_SCHUR] += 8.0 * M * N * kk;
-            prof.bytes[KC_SCHUR] += 2.0 * (double)te * M * N;
-            i = j;
+          });
+          for (int q = 0; q < ne; ++q)
+            if (bad[q]) throw Error(FMMLU_EINVAL, "internal: tile of a pair that is not close");
+          ht.mark(13);
+          // group by destination tile, boxes in order within a tile: count per touched pair
+          // (kcount is all zero between phases), order the touched pairs, place stably
+          std::vector<int64_t> tk;
+          size_t ncl = 0;
+          for (auto& v : pcl) {
+            ncl += v.size();
+            for (auto& c : v)
+              if (kcount[c.k]++ == 0) tk.push_back(c.k);
+          }
+          std::sort(tk.begin(), tk.end());
+          const int ntk = (int)tk.size();
+          std::vector<int32_t> first(ntk + 1, 0);
+          for (int u = 0; u < ntk; ++u) {
+            first[u + 1] = first[u] + kcount[tk[u]];
+            kcount[tk[u]] = first[u];  // now the fill position of pair tk[u]
+          }
+          std::vector<Contrib> cl(ncl);
+          for (auto& v : pcl)
+            for (auto& c : v) cl[kcount[c.k]++] = c;
+          for (int u = 0; u < ntk; ++u) kcount[tk[u]] = 0;
+          // one GEMM task per destination tile with contributions, its segments in box order
+          GemmBatch gs;
+          gs.tasks.resize(ntk);
+          gs.segs.resize(cl.size());
+          std::vector<double> tflops(ntk), tbytes(ntk);
+          hp.ranges(ntk, 64, [&](int lo, int hi) {
+            for (int u = lo; u < hi; ++u) {
+              const int i0 = first[u], i1 = first[u + 1];
+              double kk = 0;
+              for (int i = i0; i < i1; ++i) {
+                const Contrib& c = cl[i];
+                const ElimPlan& e = ep[c.q];
+                const int mn = plan[e.pi].m + plan[e.pi].nN;
+                gs.segs[i] = GemmSeg{e.Ccol + (int64_t)e.s * mn + e.r + goffs[c.q][c.a],
+                                     e.Up + (int64_t)goffs[c.q][c.b] * e.r, mn, e.r, e.r, 0};
+                kk += e.r;
+              }
+              const Contrib& c0 = cl[i0];
+              const ElimPlan& e0 = ep[c0.q];
+              const BoxPlan& bp0 = plan[e0.pi];
+              const int o1 = grps[c0.q][c0.a], o2 = grps[c0.q][c0.b];
+              GemmTask t{};
+              t.C = static_cast<char*>(pool) + (size_t)c0.toff * te;
+              t.ldc = (int)own[o1].act.size();
+              t.M = (c0.a == 0) ? e0.s : (int)own[o1].live.size();
+              t.N = (c0.b == 0) ? e0.s : (int)own[o2].live.size();
+              t.rmap = (c0.a == 0) ? bp0.perm : own[o1].live_dev;
+              t.cmap = (c0.b == 0) ? bp0.perm : own[o2].live_dev;
+              t.seg_begin = i0;
+              t.nseg = i1 - i0;
+              t.alpha_re = -1.0;
+              t.alpha_im = 0.0;
+              t.beta = 1.0;
+              gs.tasks[u] = t;
+              tflops[u] = 8.0 * t.M * t.N * kk;
+              tbytes[u] = 2.0 * (double)te * t.M * t.N;
+            }
+          });
+          for (int u = 0; u < ntk; ++u) {
+            gs.tasks[u].unit_begin = gs.units;
+            gs.units += gemm_units(gs.tasks[u].M, gs.tasks[u].N);
+            prof.flops[KC_SCHUR] += tflops[u];
+            prof.bytes[KC_SCHUR] += tbytes[u];
           }
           for (auto& e : ep) prof.bytes[KC_SCHUR] += 32.0 * (double)e.nsn * e.r;
+          ht.mark(14);
           gs.prepare(sg);
           ProfScope ps(prof, KC_SCHUR);
           gs.launch(sg, 0, f32);
@@ -1797,7 +1924,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     // solve records (host work overlapping the top block on the device). Scatter lists are
     // grouped by destination; y indices increase with the box order, so sorting the pairs
     // keeps each destination's contributions in box order.
-    parallel_ranges((int)pending.size(), 1, [&](int lo, int hi) {
+    hp.ranges((int)pending.size(), 1, [&](int lo, int hi) {
       for (int i = lo; i < hi; ++i) {
         PendingPhase& pp = pending[i];
         auto& contrib = pp.contrib;
@@ -1862,6 +1989,10 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             "[fmmlu] host sections: pairs %.3f pool %.3f assemble %.3f plan %.3f id+readback %.3f elim %.3f "
             "schur %.3f phase-end %.3f merge %.3f\n",
             ht.t[0], ht.t[8], ht.t[1], ht.t[2], ht.t[3], ht.t[4], ht.t[5], ht.t[6], ht.t[7]);
+    fprintf(stderr, "[fmmlu] elimination planning: boxes %.3f cross %.3f E/F %.3f inverse %.3f panels %.3f\n",
+            ht.t[9], ht.t[10], ht.t[11], ht.t[12], ht.t[4]);
+    fprintf(stderr, "[fmmlu] schur planning: contributions %.3f tasks %.3f launch+rest %.3f\n", ht.t[13], ht.t[14],
+            ht.t[5]);
   }
 }
 
