@@ -19,8 +19,21 @@ namespace fmmlu {
 
 namespace {
 
+// v summed over the wavefront (the sum is complete in lane 0): DPP within rows of 16
+// (quads, half-row and row mirrors), then across rows
+template <int CTRL>
+__device__ inline double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return v + __hiloint2double(hi, lo);
+}
 __device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141>(v);  // row_half_mirror
+  v = dpp_add<0x140>(v);  // row_mirror
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -212,12 +225,18 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
   if (!adjoint) {
     for (int i0 = 0; i0 < r; i0 += 64) {
       const int i = i0 + lane;
+      zd acc[NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[c] = zd{0.0, 0.0};
+      if (i < r)
+        for (int k = wave; k < r; k += 4) {
+          const zd a = widen(Xi[i + (int64_t)k * r]);
+#pragma unroll
+          for (int c = 0; c < NR; ++c) zfma(acc[c], a, xr[k][c]);
+        }
 #pragma unroll 1
       for (int c = 0; c < NR; ++c) {
-        zd acc{0.0, 0.0};
-        if (i < r)
-          for (int k = wave; k < r; k += 4) zfma(acc, widen(Xi[i + (int64_t)k * r]), xr[k][c]);
-        part[wave][lane] = acc;
+        part[wave][lane] = acc[c];
         __syncthreads();
         if (wave == 0 && i < r)
           x[(int64_t)b.R[i] * NR + c] = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
