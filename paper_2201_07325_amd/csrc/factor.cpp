@@ -429,9 +429,10 @@ struct GemmBatch {
   std::vector<GemmSeg> segs;
   int64_t units = 0;
   void add(void* C, int ldc, int M, int N, const int32_t* rmap, const int32_t* cmap,
-           const std::vector<GemmSeg>& s, double are, double aim, double beta) {
+           const std::vector<GemmSeg>& s, double are, double aim, double beta, bool lower = false) {
     if (M <= 0 || N <= 0) return;
     GemmTask t{};
+    t.lower = lower && M == N ? 1 : 0;
     t.C = C;
     t.rmap = rmap;
     t.cmap = cmap;
@@ -444,7 +445,7 @@ struct GemmBatch {
     t.alpha_im = aim;
     t.beta = beta;
     t.unit_begin = units;
-    units += gemm_units(M, N);
+    units += gemm_task_tiles(M, N, t.lower);
     for (auto& g : s) segs.push_back(g);
     tasks.push_back(t);
   }
@@ -1298,9 +1299,26 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           su += (mm + 255) / 256;
           st_.push_back(sm);
           zd* Rp = sg.dev.alloc_n<zd>((size_t)mm);
-          pt.push_back(PcholTask{G, bp.R, Rp, bp.perm, bp.rank, bp.T, bp.m, 0});
+          pt.push_back(PcholTask{G, bp.R, Rp, bp.perm, bp.rank, bp.T, bp.m, 0, nullptr, nullptr, nullptr});
           mmax = std::max(mmax, bp.m);
           prof.flops[KC_QR] += 4.0 * (double)bp.rows * bp.m * (bp.m + 1);
+        }
+        // wide blocks: the blocked form (pivots in blocks of kPcholNb, G downdated between
+        // blocks by a batched GEMM on all compute units) instead of one workgroup streaming
+        // every earlier row of R at every pivot
+        const bool blocked = mmax >= kPcholBlockedMin && mmax <= kPcholThreadsB;
+        GemmBatch gu;
+        if (blocked) {
+          for (size_t i = 0; i < plan.size(); ++i) {
+            PcholTask& t = pt[i];
+            const int m = t.m;
+            t.Rb = sg.dev.alloc_n<zd>((size_t)kPcholNb * m);
+            t.dgs = sg.dev.alloc_n<double>((size_t)m + 1);
+            t.ist = sg.dev.alloc_n<int32_t>((size_t)2 * m + 2);
+            gu.add(t.G, m, m, m, nullptr, nullptr, {GemmSeg{t.Rb, t.Rb, kPcholNb, kPcholNb, kPcholNb, 0}}, -1.0, 0.0,
+                   1.0, true);
+          }
+          gu.prepare(sg);
         }
         gg.prepare(sg);
         SumTask* dst_ = sg.up(st_);
@@ -1312,7 +1330,16 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         }
         {
           ProfScope ps(prof, KC_CPQR);
-          launch_pchol(dpt, nb, mmax, eps, sg.go());
+          if (blocked) {
+            const int nblk = (mmax + kPcholNb - 1) / kPcholNb;
+            for (int b = 0; b < nblk; ++b) {
+              launch_pchol_block(dpt, nb, b * kPcholNb, eps, sg.go());
+              if (b + 1 < nblk) gu.launch(sg, 2);
+            }
+            launch_pchol_finish(dpt, nb, mmax, sg.go());
+          } else {
+            launch_pchol(dpt, nb, mmax, eps, sg.go());
+          }
         }
       } else {
         std::vector<zd*> Ms;

@@ -169,14 +169,29 @@ void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStrea
 // Schur complement (the squared norms of the remaining columns after projection) is updated
 // exactly. Outputs as CpqrTask: perm, rank, T = R11^{-1} R12 (ld m).
 struct PcholTask {
-  const zd* G;     // m x m, ld m, Hermitian (not modified)
+  zd* G;           // m x m, ld m, Hermitian, lower triangle (the blocked form overwrites it)
   zd* Rt;          // m x m scratch: rows of R by original column, Rt[l * m + c]
   zd* Rp;          // m x m scratch: R in pivoted column order, ld m
   int32_t* perm;
   int32_t* rank;
   zd* T;
   int32_t m, pad;
+  // blocked form only: the block's rows of R (kPcholNb x m, column-major), and the state
+  // kept between block launches (dg and r00: m + 1 doubles; pos, pv, then k, done: 2m + 2)
+  zd* Rb;
+  double* dgs;
+  int32_t* ist;
 };
+// Blocked greedy pivoted Cholesky (matrices of m <= kPcholThreadsB columns): launch block
+// b = 0, 1, ... takes pivots kPcholNb b .. kPcholNb (b + 1) - 1 left-looking within the block
+// (rows of the block in registers, one column per thread) against G, then the caller
+// downdates G -= Rb^H Rb (lower tiles) before the next block; pchol_finish writes rank,
+// perm and R in pivoted order. Equal to launch_pchol's result in exact arithmetic.
+constexpr int kPcholNb = 16;
+constexpr int kPcholThreadsB = 1024;
+constexpr int kPcholBlockedMin = 256;  // widest block of a phase from which the blocked form is used
+void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st);
+void launch_pchol_finish(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st);
 void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st);
 
 // ---- Gauss-Jordan inversion with partial pivoting, blocked ----

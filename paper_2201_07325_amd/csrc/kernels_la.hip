@@ -394,6 +394,34 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restric
 // upper triangle only), for the back substitution.
 constexpr int kPcholThreads = 1024;
 
+// rank, perm = pv, and the rows < s of R in pivoted order (column-major, ld m, upper
+// triangle) through a 32 x 32 LDS tile (part: >= 32 x 33 entries): reads along rows of Rt,
+// writes down columns. Called by all kPcholThreads threads.
+__device__ inline void pchol_write_out(const PcholTask& t, int s, const int* pv, zd* part) {
+  const int m = t.m, tid = threadIdx.x;
+  const zd* __restrict__ Rt = t.Rt;
+  if (tid == 0) *t.rank = s;
+  for (int j = tid; j < m; j += kPcholThreads) t.perm[j] = pv[j];
+  zd(*tile)[33] = reinterpret_cast<zd(*)[33]>(part);
+  const int ta = tid & 31, tb = tid >> 5;
+  for (int i0 = 0; i0 < s; i0 += 32) {
+    for (int j0 = i0 & ~31; j0 < m; j0 += 32) {
+      __syncthreads();
+      {
+        const int i = i0 + tb, j = j0 + ta;
+        zd v{0.0, 0.0};
+        if (i < s && j < m && j >= i) v = Rt[(int64_t)i * m + pv[j]];
+        tile[tb][ta] = v;
+      }
+      __syncthreads();
+      {
+        const int i = i0 + ta, j = j0 + tb;
+        if (i < s && j < m) t.Rp[i + (int64_t)j * m] = tile[ta][tb];
+      }
+    }
+  }
+}
+
 // G[p, c] from the lower triangle of the Hermitian G (column-major, ld m)
 __device__ inline zd pchol_grow(const zd* __restrict__ G, int m, int p, int c) {
   return c >= p ? zconj(G[c + (int64_t)p * m]) : G[p + (int64_t)c * m];
@@ -511,27 +539,154 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* _
     if (tid == 0) Rt[(int64_t)k * m + p] = zd{rkk, 0.0};
     __syncthreads();
   }
-  if (tid == 0) *t.rank = s;
-  for (int j = tid; j < m; j += kPcholThreads) t.perm[j] = pv[j];
-  // R in pivoted order through a 32 x 32 LDS tile: reads along rows of Rt, writes down columns
-  zd(*tile)[33] = reinterpret_cast<zd(*)[33]>(part);
-  const int ta = tid & 31, tb = tid >> 5;
-  for (int i0 = 0; i0 < s; i0 += 32) {
-    for (int j0 = i0 & ~31; j0 < m; j0 += 32) {
-      __syncthreads();
-      {
-        const int i = i0 + tb, j = j0 + ta;
-        zd v{0.0, 0.0};
-        if (i < s && j < m && j >= i) v = Rt[(int64_t)i * m + pv[j]];
-        tile[tb][ta] = v;
-      }
-      __syncthreads();
-      {
-        const int i = i0 + ta, j = j0 + tb;
-        if (i < s && j < m) t.Rp[i + (int64_t)j * m] = tile[ta][tb];
-      }
+  pchol_write_out(t, s, pv, part);
+}
+
+// One block of kPcholNb pivots of the blocked pivoted Cholesky (see PcholTask): G holds the
+// Schur complement of the Gram matrix after the earlier blocks (lower triangle), so row k of
+// R is R[k, c] = (G[p_k, c] - sum_{k0 <= l < k} conj(R[l, p_k]) R[l, c]) / R[k, k]. Thread c
+// keeps column c's rows of the block in registers; the pivot column's values are broadcast
+// through LDS. State (dg, positions, k, done) lives in global memory between launches.
+__global__ void __launch_bounds__(kPcholThreadsB) pchol_block_kernel(const PcholTask* __restrict__ tasks, int k0,
+                                                                     double eps) {
+  constexpr int NB = kPcholNb, NT = kPcholThreadsB, NW = NT / 64;
+  const PcholTask t = tasks[blockIdx.x];
+  const int m = t.m;
+  if (k0 >= m) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* dgs = t.dgs;
+  int* pos = t.ist;
+  int* pv = t.ist + m;
+  int* ctl = t.ist + 2 * m;  // [0] k reached, [1] done
+  __shared__ double bestv[NW];
+  __shared__ int bestc[NW];
+  __shared__ zd multb[NB];
+  __shared__ int sh_done, sh_p;
+  __shared__ double sh_r00;
+  if (k0 == 0) {
+    for (int c = tid; c < m; c += NT) {
+      dgs[c] = t.G[c + (int64_t)c * m].re;
+      pos[c] = c;
+      pv[c] = c;
+    }
+    if (tid == 0) {
+      ctl[0] = 0;
+      ctl[1] = 0;
+      dgs[m] = 0.0;
     }
   }
+  __syncthreads();
+  if (tid == 0) {
+    sh_done = ctl[1];
+    sh_r00 = dgs[m];
+  }
+  __syncthreads();
+  const int c = tid;  // this thread's column (m <= NT)
+  zd rb[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) rb[j] = zd{0.0, 0.0};
+  double dgc = c < m ? dgs[c] : 0.0;
+  if (!sh_done) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = k0 + j;
+      if (k >= m || sh_done) break;
+      // pivot: the remaining column with the largest Schur-complement diagonal (ties: lowest)
+      double bv = -1.0;
+      int bc = -1;
+      if (c < m && pos[c] >= k) {
+        bv = dgc;
+        bc = c;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oc = __shfl_xor(bc, o, 64);
+        if (pchol_better(ov, oc, bv, bc)) {
+          bv = ov;
+          bc = oc;
+        }
+      }
+      if (lane == 0) {
+        bestv[wave] = bv;
+        bestc[wave] = bc;
+      }
+      __syncthreads();
+      bv = -1.0;
+      bc = -1;
+      for (int w = 0; w < NW; ++w)
+        if (pchol_better(bestv[w], bestc[w], bv, bc)) {
+          bv = bestv[w];
+          bc = bestc[w];
+        }
+      const int p = bc;
+      const double rkk = sqrt(fmax(bv, 0.0));
+      const double r00 = k == 0 ? rkk : sh_r00;
+      const bool stop = p < 0 || (k == 0 ? rkk == 0.0 : rkk <= eps * r00);
+      if (stop) {
+        if (tid == 0) {
+          sh_done = 1;
+          ctl[1] = 1;
+          ctl[0] = k;
+        }
+        __syncthreads();
+        break;
+      }
+      if (tid == 0) {
+        if (k == 0) sh_r00 = rkk;
+        const int q = pos[p], ck = pv[k];
+        pv[k] = p;
+        pv[q] = ck;
+        pos[p] = k;
+        pos[ck] = q;
+        sh_p = p;
+      }
+      if (c == p) {
+#pragma unroll
+        for (int l = 0; l < NB; ++l)
+          if (l < j) multb[l] = rb[l];
+      }
+      __syncthreads();
+      const double inv = 1.0 / rkk;
+      if (c < m) {
+        if (c == p) {
+          rb[j] = zd{rkk, 0.0};
+          t.Rt[(int64_t)k * m + c] = rb[j];
+        } else if (pos[c] > k) {
+          zd acc{0.0, 0.0};
+#pragma unroll
+          for (int l = 0; l < NB; ++l)
+            if (l < j) zfmac(acc, multb[l], rb[l]);
+          const zd g = pchol_grow(t.G, m, p, c);
+          const zd v = zscale(zsub(g, acc), inv);
+          rb[j] = v;
+          t.Rt[(int64_t)k * m + c] = v;
+          dgc -= zabs2(v);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // the block's rows for the downdate (zero where nothing was computed), and the state
+  if (c < m) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) t.Rb[j + (int64_t)c * NB] = rb[j];
+    dgs[c] = dgc;
+  }
+  if (tid == 0) {
+    dgs[m] = sh_r00;
+    if (!sh_done) ctl[0] = min(m, k0 + NB);
+    if (!sh_done && k0 + NB >= m) ctl[1] = 1;
+  }
+}
+
+// after the last block: rank, perm and R in pivoted order
+__global__ void __launch_bounds__(kPcholThreads) pchol_finish_kernel(const PcholTask* __restrict__ tasks) {
+  const PcholTask t = tasks[blockIdx.x];
+  __shared__ zd part[32 * 33];
+  extern __shared__ int pvs[];
+  for (int j = threadIdx.x; j < t.m; j += kPcholThreads) pvs[j] = t.ist[t.m + j];
+  __syncthreads();
+  pchol_write_out(t, t.ist[2 * t.m], pvs, part);
 }
 
 // T = R11^{-1} R12 (s x (m - s), ld m) from R in pivoted order. Each workgroup holds NC
@@ -1482,6 +1637,27 @@ void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipS
     hipLaunchKernelGGL(pchol_t_kernel<2>, grid_of_nc[2], dim3(256), (size_t)mmax * 2 * sizeof(zd), st, tasks);
   else
     hipLaunchKernelGGL(pchol_t_kernel<1>, grid_of_nc[3], dim3(256), (size_t)mmax * sizeof(zd), st, tasks);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(pchol_block_kernel, dim3(ntasks), dim3(kPcholThreadsB), 0, st, tasks, k0, eps);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_pchol_finish(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(pchol_finish_kernel, dim3(ntasks), dim3(kPcholThreads), (size_t)mmax * sizeof(int), st, tasks);
+  FMMLU_HIP(hipGetLastError());
+  const dim3 grid_of_nc[4] = {dim3(ntasks, (mmax + 7) / 8), dim3(ntasks, (mmax + 3) / 4),
+                              dim3(ntasks, (mmax + 1) / 2), dim3(ntasks, mmax)};
+  if (mmax <= 480)
+    hipLaunchKernelGGL(pchol_t_kernel<8>, grid_of_nc[0], dim3(256), (size_t)mmax * 8 * sizeof(zd), st, tasks);
+  else if (mmax <= 960)
+    hipLaunchKernelGGL(pchol_t_kernel<4>, grid_of_nc[1], dim3(256), (size_t)mmax * 4 * sizeof(zd), st, tasks);
+  else
+    hipLaunchKernelGGL(pchol_t_kernel<2>, grid_of_nc[2], dim3(256), (size_t)mmax * 2 * sizeof(zd), st, tasks);
   FMMLU_HIP(hipGetLastError());
 }
 
