@@ -392,6 +392,41 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restric
 // read: G[p_k, c] = conj(G[c, p_k]) for c >= p_k (contiguous), G[p_k, c] for c < p_k. Positions follow column-pivoted QR's exchange rule (step k swaps positions
 // k and pos(p_k)). At the end R is written in pivoted column order, column-major (rows < rank,
 // upper triangle only), for the back substitution.
+// (value, index) ordering of pivot searches: larger value, ties to the smaller index
+__device__ inline bool gj_better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+// 32-bit lane permutation of a wave (DPP) applied to a double and an int
+template <int CTRL>
+__device__ inline void gj_dpp(double& v, int& i) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int ii = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
+  const double ov = __hiloint2double(hi, lo);
+  if (gj_better(ov, ii, v, i)) {
+    v = ov;
+    i = ii;
+  }
+}
+
+// (value, row) with the largest value, ties to the smaller row, in every lane of the wave:
+// quads (DPP quad_perm), half rows and rows of 16 (DPP mirrors), then across rows.
+__device__ inline void gj_wave_argmax(double& v, int& i) {
+  gj_dpp<0xB1>(v, i);   // quad_perm [1,0,3,2]
+  gj_dpp<0x4E>(v, i);   // quad_perm [2,3,0,1]
+  gj_dpp<0x141>(v, i);  // row_half_mirror
+  gj_dpp<0x140>(v, i);  // row_mirror
+  for (int o = 16; o <= 32; o <<= 1) {
+    const double ov = __shfl_xor(v, o, 64);
+    const int oi = __shfl_xor(i, o, 64);
+    if (gj_better(ov, oi, v, i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+}
+
 constexpr int kPcholThreads = 1024;
 
 // rank, perm = pv, and the rows < s of R in pivoted order (column-major, ld m, upper
@@ -555,9 +590,10 @@ __global__ void __launch_bounds__(kPcholThreadsB) pchol_block_kernel(const Pchol
   if (k0 >= m) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double* dgs = t.dgs;
-  int* pos = t.ist;
-  int* pv = t.ist + m;
+  int* gpos = t.ist;
+  int* gpv = t.ist + m;
   int* ctl = t.ist + 2 * m;  // [0] k reached, [1] done
+  __shared__ int pos[kPcholThreadsB], pv[kPcholThreadsB];
   __shared__ double bestv[NW];
   __shared__ int bestc[NW];
   __shared__ zd multb[NB];
@@ -573,6 +609,11 @@ __global__ void __launch_bounds__(kPcholThreadsB) pchol_block_kernel(const Pchol
       ctl[0] = 0;
       ctl[1] = 0;
       dgs[m] = 0.0;
+    }
+  } else {
+    for (int c = tid; c < m; c += NT) {
+      pos[c] = gpos[c];
+      pv[c] = gpv[c];
     }
   }
   __syncthreads();
@@ -592,32 +633,28 @@ __global__ void __launch_bounds__(kPcholThreadsB) pchol_block_kernel(const Pchol
       const int k = k0 + j;
       if (k >= m || sh_done) break;
       // pivot: the remaining column with the largest Schur-complement diagonal (ties: lowest)
-      double bv = -1.0;
-      int bc = -1;
+      // non-candidates carry (-inf, m): every candidate beats them, and their ties stay
+      double bv = -INFINITY;
+      int bc = m;
       if (c < m && pos[c] >= k) {
         bv = dgc;
         bc = c;
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(bv, o, 64);
-        const int oc = __shfl_xor(bc, o, 64);
-        if (pchol_better(ov, oc, bv, bc)) {
-          bv = ov;
-          bc = oc;
-        }
-      }
+      gj_wave_argmax(bv, bc);
       if (lane == 0) {
         bestv[wave] = bv;
         bestc[wave] = bc;
       }
       __syncthreads();
-      bv = -1.0;
-      bc = -1;
-      for (int w = 0; w < NW; ++w)
-        if (pchol_better(bestv[w], bestc[w], bv, bc)) {
+      bv = bestv[0];
+      bc = bestc[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w)
+        if (gj_better(bestv[w], bestc[w], bv, bc)) {
           bv = bestv[w];
           bc = bestc[w];
         }
+      if (bc >= m) bc = -1;  // no candidate left
       const int p = bc;
       const double rkk = sqrt(fmax(bv, 0.0));
       const double r00 = k == 0 ? rkk : sh_r00;
@@ -671,6 +708,8 @@ __global__ void __launch_bounds__(kPcholThreadsB) pchol_block_kernel(const Pchol
 #pragma unroll
     for (int j = 0; j < NB; ++j) t.Rb[j + (int64_t)c * NB] = rb[j];
     dgs[c] = dgc;
+    gpos[c] = pos[c];
+    gpv[c] = pv[c];
   }
   if (tid == 0) {
     dgs[m] = sh_r00;
@@ -761,9 +800,6 @@ constexpr int kGjNb = kGjBlock;
 // winning slot. Launched cooperatively, so all workgroups are resident.
 constexpr int64_t kGjSpinLimit = int64_t(1) << 22;
 
-__device__ inline bool gj_better(double v, int i, double bv, int bi) {
-  return v > bv || (v == bv && i < bi);
-}
 
 __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict__ tasks, int j0) {
   const GjTask t = tasks[blockIdx.x];
@@ -950,36 +986,6 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
 // info = -1.
 constexpr int kGjChunk = 16;
 constexpr int64_t kGjCoopSpin = int64_t(1) << 22;
-
-// 32-bit lane permutation of a wave (DPP) applied to a double and an int
-template <int CTRL>
-__device__ inline void gj_dpp(double& v, int& i) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  const int ii = __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false);
-  const double ov = __hiloint2double(hi, lo);
-  if (gj_better(ov, ii, v, i)) {
-    v = ov;
-    i = ii;
-  }
-}
-
-// (value, row) with the largest value, ties to the smaller row, in every lane of the wave:
-// quads (DPP quad_perm), half rows and rows of 16 (DPP mirrors), then across rows.
-__device__ inline void gj_wave_argmax(double& v, int& i) {
-  gj_dpp<0xB1>(v, i);   // quad_perm [1,0,3,2]
-  gj_dpp<0x4E>(v, i);   // quad_perm [2,3,0,1]
-  gj_dpp<0x141>(v, i);  // row_half_mirror
-  gj_dpp<0x140>(v, i);  // row_mirror
-  for (int o = 16; o <= 32; o <<= 1) {
-    const double ov = __shfl_xor(v, o, 64);
-    const int oi = __shfl_xor(i, o, 64);
-    if (gj_better(ov, oi, v, i)) {
-      v = ov;
-      i = oi;
-    }
-  }
-}
 
 // thread 0 waits until *w >= target, then the workgroup continues (acquire)
 __device__ inline void gj_wait_at_least(int32_t* w, int target, int32_t* info) {
