@@ -424,6 +424,8 @@ inline int64_t gemm_units(int M, int N) {
 }
 inline int64_t units64(int r, int c) { return int64_t((r + 63) / 64) * ((c + 63) / 64); }
 
+constexpr int64_t kUnitMapMax = int64_t(1) << 22;  // largest grid given a block -> task map
+
 struct GemmBatch {
   std::vector<GemmTask> tasks;
   std::vector<GemmSeg> segs;
@@ -483,16 +485,31 @@ struct GemmBatch {
   }
   GemmTask* dt = nullptr;
   GemmSeg* ds = nullptr;
+  int32_t* du = nullptr;  // task of each output block (one read per workgroup on the device)
   void prepare(Stage& sg) {
     if (tasks.empty()) return;
     dt = sg.up(tasks);
     ds = sg.up(segs);
+    du = nullptr;
+    // the map needs one batch-wide prefix (batches concatenated from separate launches
+    // restart it and keep the search)
+    const int nt = (int)tasks.size();
+    bool one_prefix = units > 0 && units <= kUnitMapMax && tasks[0].unit_begin == 0;
+    for (int i = 1; i < nt && one_prefix; ++i) one_prefix = tasks[i].unit_begin >= tasks[i - 1].unit_begin;
+    if (one_prefix && tasks[nt - 1].unit_begin <= units) {
+      std::vector<int32_t> ut((size_t)units);
+      for (int i = 0; i < nt; ++i) {
+        const int64_t e = i + 1 < nt ? tasks[i + 1].unit_begin : units;
+        std::fill(ut.begin() + tasks[i].unit_begin, ut.begin() + e, (int32_t)i);
+      }
+      du = sg.up(ut);
+    }
   }
   void launch(Stage& sg, int opA, bool c32 = false) {
     if (tasks.empty()) return;
     bool mapped = false;
     for (auto& t : tasks) mapped = mapped || t.rmap || t.cmap;
-    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.go(), mapped);
+    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.go(), mapped, du);
   }
   void run(Stage& sg, int opA) {
     prepare(sg);
@@ -1317,6 +1334,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             t.ist = sg.dev.alloc_n<int32_t>((size_t)2 * m + 2);
             gu.add(t.G, m, m, m, nullptr, nullptr, {GemmSeg{t.Rb, t.Rb, kPcholNb, kPcholNb, kPcholNb, 0}}, -1.0, 0.0,
                    1.0, true);
+            gu.tasks.back().skip = t.ist + 2 * m + 1;  // no downdate once the box's pivoting stopped
           }
           gu.prepare(sg);
         }

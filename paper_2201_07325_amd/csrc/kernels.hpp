@@ -83,6 +83,7 @@ struct GemmTask {
   void* C;  // complex float64, or float32 for launches with c32
   const int32_t* rmap;  // may be null (identity)
   const int32_t* cmap;  // may be null (identity)
+  const int32_t* skip;  // may be null; the task is skipped when *skip != 0 at launch time
   int32_t M, N, ldc;
   int32_t seg_begin, nseg;
   int32_t kchunk;                   // > 0: split K into chunks; chunk c writes C + c*part_stride
@@ -97,9 +98,11 @@ __host__ __device__ inline int64_t gemm_task_tiles(int M, int N, int lower) {
   const int64_t tm = (M + kGemmTile - 1) / kGemmTile, tn = (N + kGemmTile - 1) / kGemmTile;
   return lower ? tm * (tm + 1) / 2 : tm * tn;
 }
-// mapped: tasks may carry rmap / cmap (a separate kernel instance); otherwise they are ignored
+// mapped: tasks may carry rmap / cmap (a separate kernel instance); otherwise they are ignored.
+// utask (optional, nunits entries): the task of each output block, in place of a search of
+// the tasks' unit_begin prefix sums
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
-                 hipStream_t st, bool mapped = false);
+                 hipStream_t st, bool mapped = false, const int32_t* utask = nullptr);
 
 // ---- Householder panel factorization (unpivoted QR) ----
 struct QrTask {

@@ -59,12 +59,14 @@ constexpr int LDP = BM + 4;  // padded LDS row (doubles)
 // SCAT: C entries through the row / column maps (the Schur updates of pair tiles)
 template <int OPA, class CT, bool SCAT>
 __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks,
-                                                         const GemmSeg* __restrict__ segs) {
+                                                         const GemmSeg* __restrict__ segs,
+                                                         const int32_t* __restrict__ utask) {
   using M = Mfma<CT>;
   using R = typename M::R;
   __shared__ R Asr[BK][LDP], Asi[BK][LDP], Bsr[BK][LDP], Bsi[BK][LDP];
   const int64_t u = blockIdx.x;
-  const GemmTask t = tasks[find_unit_task(tasks, ntasks, u)];
+  const GemmTask t = tasks[utask ? utask[u] : find_unit_task(tasks, ntasks, u)];
+  if (t.skip && *t.skip) return;
   int64_t lu = u - t.unit_begin;
   const int nbm = (t.M + BM - 1) / BM;
   const int64_t ntiles = gemm_task_tiles(t.M, t.N, t.lower);
@@ -84,6 +86,10 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wavefront quarter
+  // 16 x 16 blocks of the quarter that hold entries of C (wave-uniform): the others skip
+  // their MFMAs and operand reads
+  const int vm = t.M - row0 - wr, vn = t.N - col0 - wc;
+  const bool ua[2] = {vm > 0, vm > 16}, ub[2] = {vn > 0, vn > 16};
   typename M::V cr[2][2], ci[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -160,19 +166,20 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
         R ar[2], ai[2], an[2], br[2], bi[2];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          ar[a] = Asr[kr][wr + 16 * a + cl];
-          ai[a] = Asi[kr][wr + 16 * a + cl];
+          ar[a] = ua[a] ? Asr[kr][wr + 16 * a + cl] : R(0);
+          ai[a] = ua[a] ? Asi[kr][wr + 16 * a + cl] : R(0);
           an[a] = -ai[a];
         }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          br[b] = Bsr[kr][wc + 16 * b + cl];
-          bi[b] = Bsi[kr][wc + 16 * b + cl];
+          br[b] = ub[b] ? Bsr[kr][wc + 16 * b + cl] : R(0);
+          bi[b] = ub[b] ? Bsi[kr][wc + 16 * b + cl] : R(0);
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
+            if (!(ua[a] && ub[b])) continue;
             cr[a][b] = M::mma(ar[a], br[b], cr[a][b]);
             cr[a][b] = M::mma(an[a], bi[b], cr[a][b]);
             ci[a][b] = M::mma(ar[a], bi[b], ci[a][b]);
@@ -204,25 +211,25 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
 }  // namespace
 
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
-                 hipStream_t st, bool mapped) {
+                 hipStream_t st, bool mapped, const int32_t* utask) {
   if (ntasks <= 0 || nunits <= 0) return;
   const dim3 g((unsigned)nunits), b(256);
   if (mapped && opA != 0) throw Error(FMMLU_EINVAL, "mapped GEMM takes opA = N");
   if (c32) {
     if (opA != 0) throw Error(FMMLU_EINVAL, "float32 GEMM takes opA = N");
     if (mapped)
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, true>), g, b, 0, st, tasks, ntasks, segs);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, true>), g, b, 0, st, tasks, ntasks, segs, utask);
     else
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false>), g, b, 0, st, tasks, ntasks, segs);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false>), g, b, 0, st, tasks, ntasks, segs, utask);
   } else if (opA == 0) {
     if (mapped)
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, true>), g, b, 0, st, tasks, ntasks, segs);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, true>), g, b, 0, st, tasks, ntasks, segs, utask);
     else
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false>), g, b, 0, st, tasks, ntasks, segs);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false>), g, b, 0, st, tasks, ntasks, segs, utask);
   } else if (opA == 1) {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false>), g, b, 0, st, tasks, ntasks, segs);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false>), g, b, 0, st, tasks, ntasks, segs, utask);
   } else {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd, false>), g, b, 0, st, tasks, ntasks, segs);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd, false>), g, b, 0, st, tasks, ntasks, segs, utask);
   }
   FMMLU_HIP(hipGetLastError());
 }
