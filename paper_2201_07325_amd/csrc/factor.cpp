@@ -27,6 +27,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <exception>
 #include <map>
 #include <condition_variable>
 #include <functional>
@@ -246,6 +248,73 @@ struct HostTimers {
   }
 };
 
+// One worker thread for host jobs that nothing waits on until the end of the factorization
+// (grouping the solve records' scatter lists); it runs while the planning thread waits on
+// the device. Jobs run in submission order; drain() returns once all have finished and
+// rethrows the first exception one of them raised.
+class Background {
+ public:
+  Background() : th_([this] { loop(); }) {}
+  ~Background() {
+    {
+      std::lock_guard<std::mutex> l(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    th_.join();
+  }
+  void post(std::function<void()> job) {
+    {
+      std::lock_guard<std::mutex> l(m_);
+      q_.push_back(std::move(job));
+      ++posted_;
+    }
+    cv_.notify_all();
+  }
+  void drain() {
+    std::unique_lock<std::mutex> l(m_);
+    idle_.wait(l, [&] { return done_ == posted_; });
+    if (err_) {
+      std::exception_ptr e = err_;
+      err_ = nullptr;
+      std::rethrow_exception(e);
+    }
+  }
+
+ private:
+  void loop() {
+    for (;;) {
+      std::function<void()> job;
+      {
+        std::unique_lock<std::mutex> l(m_);
+        cv_.wait(l, [&] { return stop_ || !q_.empty(); });
+        if (q_.empty()) return;  // stop requested and nothing left
+        job = std::move(q_.front());
+        q_.pop_front();
+      }
+      std::exception_ptr e;
+      try {
+        job();
+      } catch (...) {
+        e = std::current_exception();
+      }
+      {
+        std::lock_guard<std::mutex> l(m_);
+        if (e && !err_) err_ = e;
+        ++done_;
+      }
+      idle_.notify_all();
+    }
+  }
+  std::mutex m_;
+  std::condition_variable cv_, idle_;
+  std::deque<std::function<void()>> q_;
+  int64_t posted_ = 0, done_ = 0;
+  bool stop_ = false;
+  std::exception_ptr err_;
+  std::thread th_;
+};
+
 // Two scratch buffers used alternately by consecutive colour phases: the rank read-back of
 // phase p waits for everything queued before phase p's ID, which includes all of phase
 // p-1's work, so the buffer of phase p-1 can be recycled by phase p+1 without a wait.
@@ -400,6 +469,37 @@ struct Stage {
     T* d = static_cast<T*>(a.alloc(b));
     FMMLU_HIP(hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, st));
     return d;
+  }
+  // several persistent uploads in one device allocation and one copy: add() records where
+  // each array's device address goes, commit() allocates, stages and copies them all
+  struct Packed {
+    struct Part {
+      const void* src;
+      size_t bytes, off;
+      void** out;
+    };
+    std::vector<Part> parts;
+    size_t total = 0;
+    template <class T>
+    void add(T** out, const std::vector<T>& v) {
+      *out = nullptr;
+      if (v.empty()) return;
+      total = (total + 255) & ~size_t(255);
+      parts.push_back(Part{v.data(), v.size() * sizeof(T), total, reinterpret_cast<void**>(out)});
+      total += v.size() * sizeof(T);
+    }
+  };
+  void commit(DeviceArena& a, Packed& pk) {
+    if (pk.parts.empty()) return;
+    char* h = static_cast<char*>(host.alloc(pk.total));
+    char* d = static_cast<char*>(a.alloc(pk.total));
+    for (auto& p : pk.parts) {
+      std::memcpy(h + p.off, p.src, p.bytes);
+      *p.out = d + p.off;
+    }
+    FMMLU_HIP(hipMemcpyAsync(d, h, pk.total, hipMemcpyHostToDevice, st));
+    pk.parts.clear();
+    pk.total = 0;
   }
   double t_wait = 0;
   void sync() {
@@ -850,6 +950,24 @@ struct PendingPhase {
   std::vector<int64_t> ptr, src;
 };
 
+// Scatter lists of a phase grouped by destination (CSR): y indices increase with the box
+// order, so sorting the (destination, y) pairs keeps each destination's contributions in box
+// order. The pair list is released afterwards.
+void group_scatter(PendingPhase& pp) {
+  auto& contrib = pp.contrib;
+  std::sort(contrib.begin(), contrib.end());
+  pp.ptr.assign(1, 0);
+  pp.dst.reserve(contrib.size());
+  pp.src.reserve(contrib.size());
+  for (size_t k = 0; k < contrib.size(); ++k) {
+    if (k > 0 && contrib[k].first != contrib[k - 1].first) pp.ptr.push_back((int64_t)pp.src.size());
+    if (k == 0 || contrib[k].first != contrib[k - 1].first) pp.dst.push_back(contrib[k].first);
+    pp.src.push_back(contrib[k].second);
+  }
+  if (!contrib.empty()) pp.ptr.push_back((int64_t)pp.src.size());
+  std::vector<std::pair<int32_t, int64_t>>().swap(contrib);
+}
+
 // ------------------------------------------------------------------------------------------
 void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm, const double* w,
                         hipStream_t st) {
@@ -924,7 +1042,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   } pool_guard{pools, st};
   // per-level device lists stay alive until the factorization has drained
   std::vector<std::unique_ptr<DeviceArena>> level_arenas;
-  std::vector<PendingPhase> pending;  // solve records, completed at the end
+  std::deque<PendingPhase> pending;  // solve records (stable addresses for the grouping jobs)
+  Background bgw;                     // declared after pending: its jobs end before pending goes
   // destroyed first: no buffer above is freed while kernels queued on st may still use it
   struct DrainOnExit {
     hipStream_t st;
@@ -1826,6 +1945,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         xrpmax = std::max(xrpmax, xpo);
         ypmax = std::max(ypmax, ypo);
         tpmax = std::max(tpmax, tpo);
+        bgw.post([&pp] { group_scatter(pp); });
       }
       // live lists of eliminated boxes to the device (persistent for the level)
       {
@@ -1966,45 +2086,36 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       info.flops_top = 8.0 * (double)n0 * n0 * n0;
       info.factor_bytes += 16 * (int64_t)n0 * n0;
     }
-    // solve records (host work overlapping the top block on the device). Scatter lists are
-    // grouped by destination; y indices increase with the box order, so sorting the pairs
-    // keeps each destination's contributions in box order.
-    hp.ranges((int)pending.size(), 1, [&](int lo, int hi) {
-      for (int i = lo; i < hi; ++i) {
-        PendingPhase& pp = pending[i];
-        auto& contrib = pp.contrib;
-        std::sort(contrib.begin(), contrib.end());
-        pp.ptr.assign(1, 0);
-        pp.dst.reserve(contrib.size());
-        pp.src.reserve(contrib.size());
-        for (size_t k = 0; k < contrib.size(); ++k) {
-          if (k > 0 && contrib[k].first != contrib[k - 1].first) pp.ptr.push_back((int64_t)pp.src.size());
-          if (k == 0 || contrib[k].first != contrib[k - 1].first) pp.dst.push_back(contrib[k].first);
-          pp.src.push_back(contrib[k].second);
-        }
-        if (!contrib.empty()) pp.ptr.push_back((int64_t)pp.src.size());
+    // solve records: the scatter lists were grouped on the background worker while the
+    // planning thread waited on the device; all arrays of all phases leave in one copy
+    bgw.drain();
+    {
+      std::vector<SolvePhase> newph(pending.size());
+      Stage::Packed pk;
+      size_t i = 0;
+      for (PendingPhase& pp : pending) {
+        SolvePhase& ph = newph[i++];
+        ph = pp.ph;
+        ph.nd = (int64_t)pp.dst.size();
+        pk.add(&ph.dboxes, pp.db);
+        pk.add(&ph.sc_dst, pp.dst);
+        pk.add(&ph.sc_ptr, pp.ptr);
+        pk.add(&ph.sc_src, pp.src);
+        pk.add(&ph.dxr, pp.txr);
+        pk.add(&ph.dyp, pp.typ);
+        pk.add(&ph.dyr, pp.tyr);
+        pk.add(&ph.dbp, pp.tbp);
+        pk.add(&ph.dbt, pp.tbt);
+        pk.add(&ph.dbf, pp.tbf);
+        ph.nxr = (int)pp.txr.size();
+        ph.nyp = (int)pp.typ.size();
+        ph.nyr = (int)pp.tyr.size();
+        ph.nbp = (int)pp.tbp.size();
+        ph.nbt = (int)pp.tbt.size();
+        ph.nbf = (int)pp.tbf.size();
       }
-    });
-    for (PendingPhase& pp : pending) {
-      SolvePhase ph = pp.ph;
-      ph.nd = (int64_t)pp.dst.size();
-      ph.dboxes = sg.up_to(arena, pp.db);
-      ph.sc_dst = sg.up_to(arena, pp.dst);
-      ph.sc_ptr = sg.up_to(arena, pp.ptr);
-      ph.sc_src = sg.up_to(arena, pp.src);
-      ph.dxr = sg.up_to(arena, pp.txr);
-      ph.dyp = sg.up_to(arena, pp.typ);
-      ph.dyr = sg.up_to(arena, pp.tyr);
-      ph.dbp = sg.up_to(arena, pp.tbp);
-      ph.dbt = sg.up_to(arena, pp.tbt);
-      ph.dbf = sg.up_to(arena, pp.tbf);
-      ph.nxr = (int)pp.txr.size();
-      ph.nyp = (int)pp.typ.size();
-      ph.nyr = (int)pp.tyr.size();
-      ph.nbp = (int)pp.tbp.size();
-      ph.nbt = (int)pp.tbt.size();
-      ph.nbf = (int)pp.tbf.size();
-      phases.push_back(ph);
+      sg.commit(arena, pk);
+      for (auto& ph : newph) phases.push_back(ph);
     }
     pending.clear();
     sg.sync_reset();
