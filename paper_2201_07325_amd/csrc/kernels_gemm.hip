@@ -58,7 +58,7 @@ constexpr int LDP = BM + 4;  // padded LDS row (doubles)
 
 // SCAT: C entries through the row / column maps (the Schur updates of pair tiles)
 template <int OPA, class CT, bool SCAT>
-__global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks,
+__global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks,
                                                          const GemmSeg* __restrict__ segs,
                                                          const int32_t* __restrict__ utask) {
   using M = Mfma<CT>;
@@ -98,95 +98,116 @@ __global__ void __launch_bounds__(256) zgemm_mfma_kernel(const GemmTask* __restr
       cr[a][b] = typename M::V{0, 0, 0, 0};
       ci[a][b] = typename M::V{0, 0, 0, 0};
     }
-  for (int sidx = 0; sidx < t.nseg; ++sidx) {
-    const GemmSeg sg = segs[t.seg_begin + sidx];
-    const int kbeg = t.kchunk > 0 ? kc * t.kchunk : 0;
-    const int kend = t.kchunk > 0 ? min(sg.K, kbeg + t.kchunk) : sg.K;
-    if (kbeg >= kend) continue;
-    zd ra[4], rb[4];  // next step's global values (4 of A, 4 of B per thread)
-    auto load = [&](int k0) {
+  // the K steps of all segments form one stream: the global loads of the next step (which
+  // may belong to the next segment) are issued before the current step's products
+  auto krange = [&](const GemmSeg& g, int& b, int& e) {
+    b = t.kchunk > 0 ? kc * t.kchunk : 0;
+    e = t.kchunk > 0 ? min(g.K, b + t.kchunk) : g.K;
+  };
+  // first segment with work at or after index s (t.nseg if none)
+  auto next_seg = [&](int s, GemmSeg& g, int& b, int& e) {
+    for (; s < t.nseg; ++s) {
+      g = segs[t.seg_begin + s];
+      krange(g, b, e);
+      if (b < e) break;
+    }
+    return s;
+  };
+  zd ra[4], rb[4];  // next step's global values (4 of A, 4 of B per thread)
+  auto load = [&](const GemmSeg& sg, int k0, int kend) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        int i, kk;
-        if (OPA == 0) {
-          i = e % BM;
-          kk = e / BM;
-        } else {
-          kk = e % BK;
-          i = e / BK;
-        }
-        const int gi = row0 + i, gk = k0 + kk;
-        zd v{0.0, 0.0};
-        if (gi < t.M && gk < kend) {
-          if (OPA == 0) {
-            v = sg.A[gi + (int64_t)gk * sg.lda];
-            if (sg.ishift > 0 && gi == sg.ishift - 1 + gk) v.re -= 1.0;
-          } else {
-            v = sg.A[gk + (int64_t)gi * sg.lda];
-            if (OPA == 2) v.im = -v.im;
-          }
-        }
-        ra[q] = v;
-        const int kb = e % BK, j = e / BK;
-        const int gkb = k0 + kb, gj = col0 + j;
-        zd w{0.0, 0.0};
-        if (gkb < kend && gj < t.N) w = sg.B[gkb + (int64_t)gj * sg.ldb];
-        rb[q] = w;
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int i, kk;
+      if (OPA == 0) {
+        i = e % BM;
+        kk = e / BM;
+      } else {
+        kk = e % BK;
+        i = e / BK;
       }
-    };
-    auto store = [&]() {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int e = tid + 256 * q;
-        int i, kk;
+      const int gi = row0 + i, gk = k0 + kk;
+      zd v{0.0, 0.0};
+      if (gi < t.M && gk < kend) {
         if (OPA == 0) {
-          i = e % BM;
-          kk = e / BM;
+          v = sg.A[gi + (int64_t)gk * sg.lda];
+          if (sg.ishift > 0 && gi == sg.ishift - 1 + gk) v.re -= 1.0;
         } else {
-          kk = e % BK;
-          i = e / BK;
+          v = sg.A[gk + (int64_t)gi * sg.lda];
+          if (OPA == 2) v.im = -v.im;
         }
-        Asr[kk][i] = (R)ra[q].re;
-        Asi[kk][i] = (R)ra[q].im;
-        const int kb = e % BK, j = e / BK;
-        Bsr[kb][j] = (R)rb[q].re;
-        Bsi[kb][j] = (R)rb[q].im;
       }
-    };
-    load(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-      __syncthreads();
-      store();
-      __syncthreads();
-      if (k0 + BK < kend) load(k0 + BK);
+      ra[q] = v;
+      const int kb = e % BK, j = e / BK;
+      const int gkb = k0 + kb, gj = col0 + j;
+      zd w{0.0, 0.0};
+      if (gkb < kend && gj < t.N) w = sg.B[gkb + (int64_t)gj * sg.ldb];
+      rb[q] = w;
+    }
+  };
+  auto store = [&]() {
 #pragma unroll
-      for (int ks = 0; ks < BK; ks += 4) {
-        const int kr = ks + (lane >> 4), cl = lane & 15;
-        R ar[2], ai[2], an[2], br[2], bi[2];
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int i, kk;
+      if (OPA == 0) {
+        i = e % BM;
+        kk = e / BM;
+      } else {
+        kk = e % BK;
+        i = e / BK;
+      }
+      Asr[kk][i] = (R)ra[q].re;
+      Asi[kk][i] = (R)ra[q].im;
+      const int kb = e % BK, j = e / BK;
+      Bsr[kb][j] = (R)rb[q].re;
+      Bsi[kb][j] = (R)rb[q].im;
+    }
+  };
+  GemmSeg cur;
+  int kb0, ke0;
+  int cs = next_seg(0, cur, kb0, ke0);
+  int ck = kb0;
+  if (cs < t.nseg) load(cur, ck, ke0);
+  while (cs < t.nseg) {
+    // position of the next step
+    GemmSeg nxt = cur;
+    int ns = cs, nk = ck + BK, ne = ke0;
+    if (nk >= ke0) ns = next_seg(cs + 1, nxt, nk, ne);
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (ns < t.nseg) load(nxt, nk, ne);
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          ar[a] = ua[a] ? Asr[kr][wr + 16 * a + cl] : R(0);
-          ai[a] = ua[a] ? Asi[kr][wr + 16 * a + cl] : R(0);
-          an[a] = -ai[a];
-        }
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4), cl = lane & 15;
+      R ar[2], ai[2], an[2], br[2], bi[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        ar[a] = ua[a] ? Asr[kr][wr + 16 * a + cl] : R(0);
+        ai[a] = ua[a] ? Asi[kr][wr + 16 * a + cl] : R(0);
+        an[a] = -ai[a];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        br[b] = ub[b] ? Bsr[kr][wc + 16 * b + cl] : R(0);
+        bi[b] = ub[b] ? Bsi[kr][wc + 16 * b + cl] : R(0);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          br[b] = ub[b] ? Bsr[kr][wc + 16 * b + cl] : R(0);
-          bi[b] = ub[b] ? Bsi[kr][wc + 16 * b + cl] : R(0);
+          if (!(ua[a] && ub[b])) continue;
+          cr[a][b] = M::mma(ar[a], br[b], cr[a][b]);
+          cr[a][b] = M::mma(an[a], bi[b], cr[a][b]);
+          ci[a][b] = M::mma(ar[a], bi[b], ci[a][b]);
+          ci[a][b] = M::mma(ai[a], br[b], ci[a][b]);
         }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            if (!(ua[a] && ub[b])) continue;
-            cr[a][b] = M::mma(ar[a], br[b], cr[a][b]);
-            cr[a][b] = M::mma(an[a], bi[b], cr[a][b]);
-            ci[a][b] = M::mma(ar[a], bi[b], ci[a][b]);
-            ci[a][b] = M::mma(ai[a], br[b], ci[a][b]);
-          }
-      }
     }
+    cs = ns;
+    ck = nk;
+    ke0 = ne;
+    cur = nxt;
   }
   const zd alpha{t.alpha_re, t.alpha_im};
   CT* Cb = static_cast<CT*>(t.C) + (int64_t)kc * t.part_stride;
