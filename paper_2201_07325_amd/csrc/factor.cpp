@@ -40,8 +40,48 @@
 namespace fmmlu {
 
 // ------------------------------------------------------------------------------------------
+// Pinned host staging blocks outlive the factorization that allocated them: later ones take
+// them back instead of pinning new memory. At most kMax bytes are kept; never torn down (no
+// HIP calls at static teardown; the process exit reclaims the memory).
+class PinnedCache {
+ public:
+  static constexpr size_t kMax = size_t(512) << 20;
+  static PinnedCache& get() {
+    static PinnedCache* c = new PinnedCache;
+    return *c;
+  }
+  void* take(size_t b, size_t& cap) {
+    std::lock_guard<std::mutex> l(m_);
+    int best = -1;
+    for (int i = 0; i < (int)free_.size(); ++i)
+      if (free_[i].second >= b && (best < 0 || free_[i].second < free_[best].second)) best = i;
+    if (best < 0) return nullptr;
+    void* p = free_[best].first;
+    cap = free_[best].second;
+    held_ -= cap;
+    free_.erase(free_.begin() + best);
+    return p;
+  }
+  void give(void* p, size_t cap) {
+    {
+      std::lock_guard<std::mutex> l(m_);
+      if (held_ + cap <= kMax) {
+        free_.emplace_back(p, cap);
+        held_ += cap;
+        return;
+      }
+    }
+    (void)hipHostFree(p);
+  }
+
+ private:
+  std::mutex m_;
+  std::vector<std::pair<void*, size_t>> free_;
+  size_t held_ = 0;
+};
+
 HostStage::~HostStage() {
-  for (void* p : chunks_) (void)hipHostFree(p);
+  for (size_t i = 0; i < chunks_.size(); ++i) PinnedCache::get().give(chunks_[i], sizes_[i]);
 }
 
 void* HostStage::alloc(size_t bytes) {
@@ -57,8 +97,8 @@ void* HostStage::alloc(size_t bytes) {
     used_ = 0;
   }
   size_t sz = std::max(bytes, size_t(64) << 20);
-  void* p = nullptr;
-  FMMLU_HIP(hipHostMalloc(&p, sz, hipHostMallocDefault));
+  void* p = PinnedCache::get().take(bytes, sz);
+  if (!p) FMMLU_HIP(hipHostMalloc(&p, sz, hipHostMallocDefault));
   chunks_.push_back(p);
   sizes_.push_back(sz);
   cur_ = chunks_.size() - 1;
@@ -357,16 +397,62 @@ class DoubleHostStage {
   int cur_ = 0;
 };
 
+// Upload chunks (pinned host memory and its device twin) outlive the factorization that
+// allocated them: later factorizations of the process take them back instead of pinning new
+// host memory (about a millisecond per few tens of megabytes). At most kChunkCacheMax bytes
+// are kept; the cache is never torn down (the process exit reclaims it).
+struct UploadChunk {
+  void* h;
+  void* d;
+  size_t cap;
+  int dev;
+};
+class ChunkCache {
+ public:
+  static constexpr size_t kChunkCacheMax = size_t(512) << 20;
+  static ChunkCache& get() {
+    static ChunkCache* c = new ChunkCache;  // not destroyed: no HIP calls at static teardown
+    return *c;
+  }
+  // smallest cached chunk of this device holding at least b bytes
+  bool take(size_t b, int dev, UploadChunk& out) {
+    std::lock_guard<std::mutex> l(m_);
+    int best = -1;
+    for (int i = 0; i < (int)free_.size(); ++i)
+      if (free_[i].dev == dev && free_[i].cap >= b && (best < 0 || free_[i].cap < free_[best].cap)) best = i;
+    if (best < 0) return false;
+    out = free_[best];
+    held_ -= out.cap;
+    free_.erase(free_.begin() + best);
+    return true;
+  }
+  void give(const UploadChunk& c) {
+    {
+      std::lock_guard<std::mutex> l(m_);
+      if (held_ + c.cap <= kChunkCacheMax) {
+        free_.push_back(c);
+        held_ += c.cap;
+        return;
+      }
+    }
+    (void)hipHostFree(c.h);
+    (void)hipFree(c.d);
+  }
+
+ private:
+  std::mutex m_;
+  std::vector<UploadChunk> free_;
+  size_t held_ = 0;
+};
+
 // Task descriptors on their way to the device: pinned host and device buffers of equal size,
 // bump-allocated at the same offsets, so the uploads queued between two launches leave in
 // one copy. Chunks are kept for reuse; reset() only after the device is done with them.
 class UploadRing {
  public:
+  // the owner drains the stream before the ring goes, so no copy still reads a chunk
   ~UploadRing() {
-    for (auto& c : chunks_) {
-      (void)hipHostFree(c.h);
-      (void)hipFree(c.d);
-    }
+    for (auto& c : chunks_) ChunkCache::get().give(c);
   }
   bool pending() const { return cur_ < chunks_.size() && flushed_ < used_; }
   // host and device addresses of b bytes (the caller flushes first when told to)
@@ -379,13 +465,18 @@ class UploadRing {
       size_t next = cur_ < chunks_.size() ? cur_ + 1 : 0;
       while (next < chunks_.size() && chunks_[next].cap < b) ++next;
       if (next >= chunks_.size()) {
-        Chunk c{};
-        c.cap = std::max(b, size_t(16) << 20);
-        FMMLU_HIP(hipHostMalloc(&c.h, c.cap, hipHostMallocDefault));
-        if (hipMalloc(&c.d, c.cap) != hipSuccess) {
-          (void)hipGetLastError();
-          (void)hipHostFree(c.h);
-          throw Error(FMMLU_ENOMEM, "upload buffer allocation failed");
+        UploadChunk c{};
+        int dev = 0;
+        FMMLU_HIP(hipGetDevice(&dev));
+        if (!ChunkCache::get().take(b, dev, c)) {
+          c.cap = std::max(b, size_t(16) << 20);
+          c.dev = dev;
+          FMMLU_HIP(hipHostMalloc(&c.h, c.cap, hipHostMallocDefault));
+          if (hipMalloc(&c.d, c.cap) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(c.h);
+            throw Error(FMMLU_ENOMEM, "upload buffer allocation failed");
+          }
         }
         chunks_.push_back(c);
         next = chunks_.size() - 1;
@@ -393,14 +484,14 @@ class UploadRing {
       cur_ = next;
       used_ = flushed_ = 0;
     }
-    Chunk& c = chunks_[cur_];
+    UploadChunk& c = chunks_[cur_];
     std::pair<void*, void*> r{static_cast<char*>(c.h) + used_, static_cast<char*>(c.d) + used_};
     used_ += b;
     return r;
   }
   void flush(hipStream_t st) {
     if (!pending()) return;
-    Chunk& c = chunks_[cur_];
+    UploadChunk& c = chunks_[cur_];
     FMMLU_HIP(hipMemcpyAsync(static_cast<char*>(c.d) + flushed_, static_cast<char*>(c.h) + flushed_,
                              used_ - flushed_, hipMemcpyHostToDevice, st));
     flushed_ = used_;
@@ -412,12 +503,7 @@ class UploadRing {
 
  private:
   static size_t align(size_t b) { return std::max<size_t>((b + 255) & ~size_t(255), 256); }
-  struct Chunk {
-    void* h;
-    void* d;
-    size_t cap;
-  };
-  std::vector<Chunk> chunks_;
+  std::vector<UploadChunk> chunks_;
   size_t cur_ = 0, used_ = 0, flushed_ = 0;
 };
 
@@ -1025,21 +1111,26 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   int64_t live_total = n;
 
   // tiles of the previous level (for assembly). Two pools used alternately by consecutive
-  // levels and grown on demand, so that no level boundary frees memory (a free waits for the
-  // device to drain).
+  // levels and grown on demand. A pool outgrown at a level boundary may still be read by work
+  // queued on st: it is retired and freed after the next rank read-back, which has waited for
+  // that work anyway (a free is not ordered with the stream, and another thread's allocation
+  // could reuse the memory).
   void* prev_pool = nullptr;
   void* pools[2] = {nullptr, nullptr};
   size_t pool_cap[2] = {0, 0};
   int pool_slot = 0;
+  std::vector<void*> retired;
   struct PoolGuard {
     void** p;
+    std::vector<void*>* r;
     hipStream_t st;
     ~PoolGuard() {
       (void)hipStreamSynchronize(st);
       for (int i = 0; i < 2; ++i)
         if (p[i]) (void)hipFree(p[i]);
+      for (void* q : *r) (void)hipFree(q);
     }
-  } pool_guard{pools, st};
+  } pool_guard{pools, &retired, st};
   // per-level device lists stay alive until the factorization has drained
   std::vector<std::unique_ptr<DeviceArena>> level_arenas;
   std::deque<PendingPhase> pending;  // solve records (stable addresses for the grouping jobs)
@@ -1144,13 +1235,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       const int ps = pool_slot;
       pool_slot ^= 1;
       if (pool_cap[ps] < bytes) {
-        // The previous level's assembly, still queued on st, may be reading this pool. The
-        // stream is drained before the free: a free is not ordered with work on other
-        // (non-blocking) streams, and another thread's allocation could reuse the memory.
-        if (pools[ps]) {
-          FMMLU_HIP(hipStreamSynchronize(st));
-          FMMLU_HIP(hipFree(pools[ps]));
-        }
+        // the previous level's assembly, still queued on st, may be reading this pool
+        if (pools[ps]) retired.push_back(pools[ps]);
         pools[ps] = nullptr;
         pool_cap[ps] = 0;
         hipError_t e = hipMalloc(&pools[ps], bytes);
@@ -1514,6 +1600,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
         FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
         sg.sync();
+        for (void* q : retired) FMMLU_HIP(hipFree(q));  // everything queued before has finished
+        retired.clear();
         int64_t po = nb;
         for (int i = 0; i < nb; ++i) {
           ranks[i] = hr[i];
