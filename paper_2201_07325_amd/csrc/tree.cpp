@@ -170,11 +170,22 @@ void Octree::build(const double* xyz, int64_t n_, int leaf_size_) {
     }
     key[i] = morton3(q[0], q[1], q[2]);
   }
-  msort.resize(n);
-  std::iota(msort.begin(), msort.end(), 0);
-  std::sort(msort.begin(), msort.end(), [&](int64_t a, int64_t b) {
-    return key[a] != key[b] ? key[a] < key[b] : a < b;
-  });
+  // order by (key, index): least-significant-digit radix sort of (key, index) pairs, stable
+  // and started in index order, so equal keys keep increasing indices
+  {
+    std::vector<std::pair<uint64_t, int64_t>> a((size_t)n), b((size_t)n);
+    for (int64_t i = 0; i < n; ++i) a[i] = {key[i], i};
+    for (int sh = 0; sh < 3 * kDepth; sh += 8) {
+      size_t cnt[257] = {0};
+      for (const auto& e : a) ++cnt[((e.first >> sh) & 255) + 1];
+      if (cnt[((a[0].first >> sh) & 255) + 1] == (size_t)n) continue;  // one digit value: order unchanged
+      for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
+      for (const auto& e : a) b[cnt[(e.first >> sh) & 255]++] = e;
+      a.swap(b);
+    }
+    msort.resize(n);
+    for (int64_t i = 0; i < n; ++i) msort[i] = a[i].second;
+  }
   level.clear(); cx.clear(); cy.clear(); cz.clear(); parent.clear(); child0.clear();
   pbeg.clear(); pend.clear(); lookup.clear();
   new_box(0, 0, 0, 0, -1, 0, n);
