@@ -1642,6 +1642,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         // factor storage and index lists
         std::vector<int32_t> idx_cat;
         std::vector<std::array<int64_t, 3>> idx_off(ne);
+        int64_t idx_len = 0;
         std::vector<CrossTask> cross;
         std::vector<NSeg> nsegs;
         int64_t cunits = 0;
@@ -1660,19 +1661,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           fb.s = e.s;
           fb.r = e.r;
           fb.nsn = e.nsn;
-          const std::vector<int32_t>& pv = perms[e.pi];
-          // index lists of all boxes of the phase go up in one copy (offsets patched below)
-          idx_off[q][0] = (int64_t)idx_cat.size();
-          for (int j = 0; j < e.r; ++j) idx_cat.push_back((int32_t)B.act[pv[e.s + j]]);
-          idx_off[q][1] = (int64_t)idx_cat.size();
-          for (int j = 0; j < e.s; ++j) idx_cat.push_back((int32_t)B.act[pv[j]]);
-          idx_off[q][2] = (int64_t)idx_cat.size();
-          for (int j = 0; j < e.s; ++j) idx_cat.push_back((int32_t)B.act[pv[j]]);
-          for (int o : bp.nown_)
-            for (int32_t l : own[o].live) idx_cat.push_back((int32_t)own[o].act[l]);
-          fb.skel_orig.resize(e.s);
-          for (int j = 0; j < e.s; ++j) fb.skel_orig[j] = order[B.act[pv[j]]];
-          std::sort(fb.skel_orig.begin(), fb.skel_orig.end());
+          // index lists of all boxes of the phase go up in one copy: R, S, then S u N (filled
+          // on the host threads below)
+          idx_off[q][0] = idx_len;
+          idx_off[q][1] = idx_len + e.r;
+          idx_off[q][2] = idx_len + e.r + e.s;
+          idx_len += (int64_t)e.r + e.s + e.nsn;
           SolveBox& d = fb.dev;
           d.T = e.s ? arena.alloc(te * (size_t)e.s * e.r) : nullptr;
           d.Xi = arena.alloc(te * (size_t)e.r * e.r);
@@ -1714,6 +1708,33 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           cross.push_back(ct);
           info.max_rank = std::max(info.max_rank, e.s);
         }
+        idx_cat.resize((size_t)idx_len);
+        std::vector<int> short_sn(ne, 0);
+        hp.ranges(ne, 8, [&](int lo, int hi) {
+          for (int q = lo; q < hi; ++q) {
+            const ElimPlan& e = ep[q];
+            const BoxPlan& bp = plan[e.pi];
+            const Owner& B = own[bp.oi];
+            const std::vector<int32_t>& pv = perms[e.pi];
+            int32_t* rl = idx_cat.data() + idx_off[q][0];
+            int32_t* sl = idx_cat.data() + idx_off[q][1];
+            int32_t* sn = idx_cat.data() + idx_off[q][2];
+            for (int j = 0; j < e.r; ++j) rl[j] = (int32_t)B.act[pv[e.s + j]];
+            for (int j = 0; j < e.s; ++j) sl[j] = sn[j] = (int32_t)B.act[pv[j]];
+            int64_t c = e.s;
+            for (int o : bp.nown_)
+              for (int32_t l : own[o].live)
+                if (c < e.nsn) sn[c++] = (int32_t)own[o].act[l];
+                else short_sn[q] = 1;
+            if (c != e.nsn) short_sn[q] = 1;
+            FactorBox& fb = boxes[box_base + q];
+            fb.skel_orig.resize(e.s);
+            for (int j = 0; j < e.s; ++j) fb.skel_orig[j] = order[B.act[pv[j]]];
+            std::sort(fb.skel_orig.begin(), fb.skel_orig.end());
+          }
+        });
+        for (int q = 0; q < ne; ++q)
+          if (short_sn[q]) throw Error(FMMLU_EINVAL, "internal: near-field list size changed within a phase");
         {
           int32_t* base = sg.up_to(arena, idx_cat);
           for (int q = 0; q < ne; ++q) {
