@@ -1325,14 +1325,26 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       for (auto& t : all)
         if (t.nr > 0 && t.nc > 0) tasks.push_back(t);
       const int64_t units = unito[np];
+      // task of each 64 x 64 unit (one read per workgroup in place of a search)
+      std::vector<int32_t> ut;
+      if (units <= kUnitMapMax) {
+        ut.resize((size_t)units);
+        const int ntk = (int)tasks.size();
+        for (int k = 0; k < ntk; ++k) {
+          const int64_t e = k + 1 < ntk ? tasks[k + 1].unit_begin : units;
+          std::fill(ut.begin() + tasks[k].unit_begin, ut.begin() + e, (int32_t)k);
+        }
+      }
       {
         AsmTask* dt = sg.up(tasks);
         int32_t* dslot = sg.up(slot);
         int32_t* didx = sg.up(idx);
         int64_t* ddof = sg.up(dof);
         AsmSrc* dtab = sg.up(table);
+        int32_t* dut = sg.up(ut);
         ProfScope ps(prof, KC_ASSEMBLE);
-        launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, f32, pool, f32, sg.go());
+        launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, f32, pool, f32, sg.go(),
+                        dut);
       }
       prof.bytes[KC_ASSEMBLE] += (double)te * (double)pool_elems * (first_level ? 1.0 : 2.0);
       prev_pool = nullptr;

@@ -44,7 +44,7 @@ struct AsmSrc {
 void launch_assemble(const DevGeom& g, const AsmTask* tasks, int ntasks, int64_t nunits,
                      const int32_t* slot, const int32_t* idx, const int64_t* dof,
                      const AsmSrc* table, const void* src_pool, bool src32, void* dst_pool, bool dst32,
-                     hipStream_t st);
+                     hipStream_t st, const int32_t* utask = nullptr);
 
 // ---- ID matrix [A_QB ; A_BQ^T ; proxy outgoing ; proxy incoming] (column-major) ----
 struct QSeg {

@@ -82,9 +82,10 @@ __global__ void __launch_bounds__(256) assemble_kernel(DevGeom g, const AsmTask*
                                                        const int32_t* __restrict__ idx,
                                                        const int64_t* __restrict__ dof,
                                                        const AsmSrc* __restrict__ table,
-                                                       const ST* __restrict__ src, DT* __restrict__ dst) {
+                                                       const ST* __restrict__ src, DT* __restrict__ dst,
+                                                       const int32_t* __restrict__ utask) {
   const int64_t u = blockIdx.x;
-  const int ti = find_task(tasks, ntasks, u);
+  const int ti = utask ? utask[u] : find_task(tasks, ntasks, u);
   const AsmTask t = tasks[ti];
   const int64_t lu = u - t.unit_begin;
   const int nbr = (t.nr + 63) >> 6;
@@ -140,12 +141,19 @@ __global__ void __launch_bounds__(256) idmatrix_kernel(DevGeom g, const IdTask* 
     }
     const QSeg sg = segs[t.seg_off + lo];
     const int li = sg.live[iq - sg.row0];
+    // all 16 reads in flight before the writes
+    PT vals[16];
+#pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
-      if (j >= t.m) break;
-      const zd v = widen(transposed ? pool[sg.tile_bq + j + (int64_t)li * t.m]
-                                    : pool[sg.tile_qb + li + (int64_t)j * sg.ld]);
-      out[i + (int64_t)j * t.rows] = v;
+      vals[jj] = PT{};
+      if (j < t.m)
+        vals[jj] = transposed ? pool[sg.tile_bq + j + (int64_t)li * t.m] : pool[sg.tile_qb + li + (int64_t)j * sg.ld];
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+      if (j < t.m) out[i + (int64_t)j * t.rows] = widen(vals[jj]);
     }
     return;
   }
@@ -285,21 +293,21 @@ __global__ void __launch_bounds__(256) matvec_sum_kernel(const zd* __restrict__ 
 void launch_assemble(const DevGeom& g, const AsmTask* tasks, int ntasks, int64_t nunits,
                      const int32_t* slot, const int32_t* idx, const int64_t* dof,
                      const AsmSrc* table, const void* src_pool, bool src32, void* dst_pool, bool dst32,
-                     hipStream_t st) {
+                     hipStream_t st, const int32_t* utask) {
   if (ntasks <= 0 || nunits <= 0) return;
   const dim3 gr((unsigned)nunits), b(256);
   if (!src32 && !dst32)
     hipLaunchKernelGGL((assemble_kernel<zd, zd>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
-                       static_cast<const zd*>(src_pool), static_cast<zd*>(dst_pool));
+                       static_cast<const zd*>(src_pool), static_cast<zd*>(dst_pool), utask);
   else if (src32 && dst32)
     hipLaunchKernelGGL((assemble_kernel<zf, zf>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
-                       static_cast<const zf*>(src_pool), static_cast<zf*>(dst_pool));
+                       static_cast<const zf*>(src_pool), static_cast<zf*>(dst_pool), utask);
   else if (src32)
     hipLaunchKernelGGL((assemble_kernel<zf, zd>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
-                       static_cast<const zf*>(src_pool), static_cast<zd*>(dst_pool));
+                       static_cast<const zf*>(src_pool), static_cast<zd*>(dst_pool), utask);
   else
     hipLaunchKernelGGL((assemble_kernel<zd, zf>), gr, b, 0, st, g, tasks, ntasks, slot, idx, dof, table,
-                       static_cast<const zd*>(src_pool), static_cast<zf*>(dst_pool));
+                       static_cast<const zd*>(src_pool), static_cast<zf*>(dst_pool), utask);
   FMMLU_HIP(hipGetLastError());
 }
 
