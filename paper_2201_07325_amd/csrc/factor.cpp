@@ -1036,6 +1036,72 @@ struct PendingPhase {
   std::vector<int64_t> ptr, src;
 };
 
+// Owner geometry for the pair search: level and cell coordinates at that level.
+struct OwnerCell {
+  int level;
+  int64_t c[3];
+};
+
+// Close lists of a set of disjoint owner boxes: for each owner (ascending, unique) the owners
+// covering the cells within two of its own at its level, plus every finer owner that found
+// it (a coarser owner cannot find a finer one back). At the finest depth D each owner
+// covers the Morton key range [klo, khi); the owner containing a cell of level lev is the
+// one whose range holds the cell's first key, if that owner's level is <= lev. Runs on the
+// pool's threads when one is given.
+std::vector<std::vector<int>> close_owner_lists(const std::vector<OwnerCell>& ow, int D, HostPool* hp) {
+  const int no = (int)ow.size();
+  std::vector<uint64_t> klo(no), khi(no);
+  std::vector<int> kown(no);
+  for (int i = 0; i < no; ++i) {
+    const int sh = D - ow[i].level;
+    klo[i] = morton3((uint32_t)(ow[i].c[0] << sh), (uint32_t)(ow[i].c[1] << sh), (uint32_t)(ow[i].c[2] << sh));
+    khi[i] = klo[i] + (uint64_t(1) << (3 * sh));
+    kown[i] = i;
+  }
+  std::sort(kown.begin(), kown.end(), [&](int a, int b) { return klo[a] < klo[b]; });
+  auto lookup = [&](int lev, int64_t x, int64_t y, int64_t z) -> int {
+    const int64_t lim = int64_t(1) << lev;
+    if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
+    const int sh = D - lev;
+    const uint64_t key = morton3((uint32_t)(x << sh), (uint32_t)(y << sh), (uint32_t)(z << sh));
+    auto it = std::upper_bound(kown.begin(), kown.end(), key, [&](uint64_t k, int o) { return k < klo[o]; });
+    if (it == kown.begin()) return -1;
+    const int o = *(it - 1);
+    return (key < khi[o] && ow[o].level <= lev) ? o : -1;
+  };
+  std::vector<std::vector<int>> close(no);
+  auto search = [&](int lo, int hi) {
+    for (int i = lo; i < hi; ++i) {
+      const OwnerCell& o = ow[i];
+      auto& v = close[i];
+      for (int dz = -2; dz <= 2; ++dz)
+        for (int dy = -2; dy <= 2; ++dy)
+          for (int dx = -2; dx <= 2; ++dx) {
+            const int p = lookup(o.level, o.c[0] + dx, o.c[1] + dy, o.c[2] + dz);
+            if (p >= 0) v.push_back(p);
+          }
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+  };
+  if (hp)
+    hp->ranges(no, 64, search);
+  else
+    search(0, no);
+  std::vector<std::vector<int>> back(no);
+  for (int i = 0; i < no; ++i)
+    for (int p : close[i])
+      if (ow[p].level < ow[i].level) back[p].push_back(i);
+  for (int p = 0; p < no; ++p) {
+    if (back[p].empty()) continue;
+    auto& v = close[p];
+    v.insert(v.end(), back[p].begin(), back[p].end());
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  return close;
+}
+
 // Scatter lists of a phase grouped by destination (CSR): y indices increase with the box
 // order, so sorting the (destination, y) pairs keeps each destination's contributions in box
 // order. The pair list is released afterwards.
@@ -1146,71 +1212,55 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   int32_t* info_dev = arena.alloc_n<int32_t>(1);
   FMMLU_HIP(hipMemsetAsync(info_dev, 0, sizeof(int32_t), st));
 
-  // Owner boxes are disjoint; at the finest depth D each covers the Morton key range
-  // [klo, khi). The owner containing a cell of level lev is the one whose range holds the
-  // cell's first key, if that owner's level is <= lev (else the cell is split among finer
-  // owners, or holds none).
   const int D = std::max(tree.nlevels - 1, 0);
-  std::vector<uint64_t> klo, khi;
-  std::vector<int> kown;  // owners by ascending klo
-  auto index_owners = [&](const std::vector<Owner>& ow) {
-    const int no = (int)ow.size();
-    klo.resize(no);
-    khi.resize(no);
-    kown.resize(no);
-    for (int i = 0; i < no; ++i) {
-      const int sh = D - ow[i].level;
-      klo[i] = morton3((uint32_t)(ow[i].c[0] << sh), (uint32_t)(ow[i].c[1] << sh), (uint32_t)(ow[i].c[2] << sh));
-      khi[i] = klo[i] + (uint64_t(1) << (3 * sh));
-      kown[i] = i;
-    }
-    std::sort(kown.begin(), kown.end(), [&](int a, int b) { return klo[a] < klo[b]; });
-  };
-  auto owner_lookup = [&](const std::vector<Owner>& ow, int lev, int64_t x, int64_t y, int64_t z) -> int {
-    const int64_t lim = int64_t(1) << lev;
-    if (x < 0 || y < 0 || z < 0 || x >= lim || y >= lim || z >= lim) return -1;
-    const int sh = D - lev;
-    const uint64_t key = morton3((uint32_t)(x << sh), (uint32_t)(y << sh), (uint32_t)(z << sh));
-    auto it = std::upper_bound(kown.begin(), kown.end(), key, [&](uint64_t k, int o) { return k < klo[o]; });
-    if (it == kown.begin()) return -1;
-    const int o = *(it - 1);
-    return (key < khi[o] && ow[o].level <= lev) ? o : -1;
-  };
+  // close lists of the next level's owners, computed ahead on a worker thread (see below);
+  // the worker is declared last so that its job ends before the lists it writes go
+  std::vector<int> spec_boxes;
+  std::vector<std::vector<int>> spec_close;
+  bool spec_posted = false;
+  Background spec_worker;
 
   HostTimers ht;
   for (int lev = tree.nlevels - 1; lev >= 2; --lev) {
     const int nown = (int)own.size();
-    index_owners(own);
-    // ---- close pairs of owners and their tiles. Each owner finds the owners covering the
-    // cells within two of its own (in parallel); an owner coarser than one it finds cannot
-    // find it back, so those pairs are added to the coarser owner's list afterwards.
-    std::vector<std::vector<int>> close(nown);
-    hp.ranges(nown, 64, [&](int lo, int hi) {
-      for (int i = lo; i < hi; ++i) {
-        const Owner& o = own[i];
-        auto& v = close[i];
-        for (int dz = -2; dz <= 2; ++dz)
-          for (int dy = -2; dy <= 2; ++dy)
-            for (int dx = -2; dx <= 2; ++dx) {
-              const int p = owner_lookup(own, o.level, o.c[0] + dx, o.c[1] + dy, o.c[2] + dz);
-              if (p >= 0) v.push_back(p);
-            }
-        std::sort(v.begin(), v.end());
-        v.erase(std::unique(v.begin(), v.end()), v.end());
+    // ---- close pairs of owners and their tiles: taken from the worker's speculative lists
+    // when this level's owners are the ones it assumed, else searched here
+    std::vector<std::vector<int>> close;
+    bool spec_hit = false;
+    if (spec_posted) {
+      spec_worker.drain();
+      spec_posted = false;
+      bool same = (int)spec_boxes.size() == nown;
+      for (int i = 0; same && i < nown; ++i) same = spec_boxes[i] == own[i].box;
+      if (same) close.swap(spec_close);
+      spec_hit = same;
+      spec_close.clear();
+    }
+    if (close.empty()) {
+      std::vector<OwnerCell> cells(nown);
+      for (int i = 0; i < nown; ++i) cells[i] = OwnerCell{own[i].level, {own[i].c[0], own[i].c[1], own[i].c[2]}};
+      close = close_owner_lists(cells, D, &hp);
+    }
+    // the next level's owners if every owner keeps live DOFs (the merge below checks): the
+    // parents of this level's boxes and the coarser owners, in tree order; their close
+    // lists depend on geometry only
+    if (lev - 1 >= 2) {
+      std::vector<std::pair<int64_t, int>> nb;  // (a tree position inside the box, box)
+      std::unordered_map<int, int> seen;
+      for (const Owner& o : own) {
+        const int tb = o.level == lev ? tree.parent[o.box] : o.box;
+        if (seen.emplace(tb, 1).second) nb.emplace_back(o.first_pos, tb);
       }
-    });
-    {
-      std::vector<std::vector<int>> back(nown);
-      for (int i = 0; i < nown; ++i)
-        for (int p : close[i])
-          if (own[p].level < own[i].level) back[p].push_back(i);
-      for (int p = 0; p < nown; ++p) {
-        if (back[p].empty()) continue;
-        auto& v = close[p];
-        v.insert(v.end(), back[p].begin(), back[p].end());
-        std::sort(v.begin(), v.end());
-        v.erase(std::unique(v.begin(), v.end()), v.end());
+      std::sort(nb.begin(), nb.end());
+      spec_boxes.resize(nb.size());
+      std::vector<OwnerCell> cells(nb.size());
+      for (size_t i = 0; i < nb.size(); ++i) {
+        const int b = nb[i].second;
+        spec_boxes[i] = b;
+        cells[i] = OwnerCell{(int)tree.level[b], {(int64_t)tree.cx[b], (int64_t)tree.cy[b], (int64_t)tree.cz[b]}};
       }
+      spec_worker.post([&spec_close, cells = std::move(cells), D] { spec_close = close_owner_lists(cells, D, nullptr); });
+      spec_posted = true;
     }
     PairIndex pidx;
     pidx.beg.assign(1, 0);
@@ -2087,8 +2137,9 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       for (auto& bp : plan) info.max_block = std::max(info.max_block, bp.m);
     }
     if (opts.verbose)
-      fprintf(stderr, "[fmmlu] level %d: owners %d pairs %zu tiles %.1f MB live %lld\n", lev, nown,
-              pairs.size(), pool_elems * 16.0 / 1e6, (long long)live_total);
+      fprintf(stderr, "[fmmlu] level %d: owners %d pairs %zu%s tiles %.1f MB live %lld\n", lev, nown,
+              pairs.size(), spec_hit ? " (close lists from the worker)" : "", pool_elems * 16.0 / 1e6,
+              (long long)live_total);
 
     ht.mark(6);
     // ---- next level's owners: merge live DOFs of level-lev owners into parents

@@ -192,7 +192,7 @@ struct PcholTask {
 // perm and R in pivoted order. Equal to launch_pchol's result in exact arithmetic.
 constexpr int kPcholNb = 16;
 constexpr int kPcholThreadsB = 1024;
-constexpr int kPcholBlockedMin = 256;  // widest block of a phase from which the blocked form is used
+constexpr int kPcholBlockedMin = 128;  // widest block of a phase from which the blocked form is used
 void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st);
 void launch_pchol_finish(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st);
 void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st);
