@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <stdexcept>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/fmmlu.h"
@@ -86,7 +87,59 @@ struct Error : std::runtime_error {
   } while (0)
 
 // ---------------------------------------------------------------------------------
-// Device arena: large chunks, bump allocation, 256-byte alignment, freed together.
+// Device memory blocks given back by one factorization and taken by the next (hipMalloc and
+// hipFree of large blocks cost a fraction of a millisecond each, and hipFree waits for the
+// device). Only memory the device no longer uses may be given back. At most kMax bytes are
+// kept; the cache is never torn down (the process exit reclaims the memory).
+class DeviceChunkCache {
+ public:
+  static constexpr size_t kMax = size_t(8) << 30;
+  static DeviceChunkCache& get() {
+    static DeviceChunkCache* c = new DeviceChunkCache;
+    return *c;
+  }
+  // smallest cached block of the current device holding at least b bytes (its size in cap)
+  void* take(size_t b, size_t& cap) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> l(m_);
+    int best = -1;
+    for (int i = 0; i < (int)free_.size(); ++i)
+      if (free_[i].dev == dev && free_[i].cap >= b && (best < 0 || free_[i].cap < free_[best].cap)) best = i;
+    if (best < 0) return nullptr;
+    void* p = free_[best].p;
+    cap = free_[best].cap;
+    held_ -= cap;
+    free_.erase(free_.begin() + best);
+    return p;
+  }
+  void give(void* p, size_t cap) {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      std::lock_guard<std::mutex> l(m_);
+      if (held_ + cap <= kMax) {
+        free_.push_back(Block{p, cap, dev});
+        held_ += cap;
+        return;
+      }
+    }
+    (void)hipFree(p);
+  }
+
+ private:
+  struct Block {
+    void* p;
+    size_t cap;
+    int dev;
+  };
+  std::mutex m_;
+  std::vector<Block> free_;
+  size_t held_ = 0;
+};
+
+// Device arena: large chunks, bump allocation, 256-byte alignment, freed together. With
+// recycle set, the chunks come from and go back to DeviceChunkCache (the owner then frees
+// the arena only after the device is done with it).
 class DeviceArena {
  public:
   explicit DeviceArena(size_t chunk = size_t(256) << 20) : chunk_(chunk) {}
@@ -113,11 +166,13 @@ class DeviceArena {
     if (cap_ && held_ + sz > cap_)
       throw Error(FMMLU_ENOMEM, "device memory cap exceeded (" + std::to_string(held_ + sz) +
                                     " > " + std::to_string(cap_) + " bytes)");
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sz);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error(FMMLU_ENOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed");
+    void* p = (recycle_ && !cap_) ? DeviceChunkCache::get().take(sz, sz) : nullptr;  // a cap counts exact sizes
+    if (!p) {
+      hipError_t e = hipMalloc(&p, sz);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(FMMLU_ENOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed");
+      }
     }
     chunks_.push_back(p);
     sizes_.push_back(sz);
@@ -137,7 +192,12 @@ class DeviceArena {
     total_ = 0;
   }
   void release() {
-    for (void* p : chunks_) (void)hipFree(p);
+    for (size_t i = 0; i < chunks_.size(); ++i) {
+      if (recycle_)
+        DeviceChunkCache::get().give(chunks_[i], sizes_[i]);
+      else
+        (void)hipFree(chunks_[i]);
+    }
     chunks_.clear();
     sizes_.clear();
     cur_ = 0;
@@ -148,9 +208,11 @@ class DeviceArena {
   size_t held() const { return held_; }
   void set_cap(size_t cap) { cap_ = cap; }
   void set_chunk(size_t c) { chunk_ = c; }
+  void set_recycle(bool r) { recycle_ = r; }
 
  private:
   size_t chunk_;
+  bool recycle_ = false;
   size_t cap_ = 0;
   std::vector<void*> chunks_;
   std::vector<size_t> sizes_;

@@ -378,6 +378,13 @@ class DoubleArena {
  private:
   DeviceArena a_[2] = {DeviceArena(size_t(512) << 20), DeviceArena(size_t(512) << 20)};
   int cur_ = 0;
+
+ public:
+  // the owner (Stage) drains its stream before the arenas go
+  DoubleArena() {
+    a_[0].set_recycle(true);
+    a_[1].set_recycle(true);
+  }
 };
 class DoubleHostStage {
  public:
@@ -1133,6 +1140,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   info.nlevels = tree.nlevels;
   info.precision = opts.precision;
   if (opts.device_mem_cap > 0) arena.set_cap((size_t)opts.device_mem_cap);
+  arena.set_recycle(true);  // freed by the destructor after the device has drained
   Stage sg;
   sg.st = st;
   HostPool hp((int)std::min(8u, std::max(1u, std::thread::hardware_concurrency())));
@@ -1185,18 +1193,19 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   void* pools[2] = {nullptr, nullptr};
   size_t pool_cap[2] = {0, 0};
   int pool_slot = 0;
-  std::vector<void*> retired;
+  std::vector<std::pair<void*, size_t>> retired;
   struct PoolGuard {
     void** p;
-    std::vector<void*>* r;
+    std::vector<std::pair<void*, size_t>>* r;
     hipStream_t st;
+    size_t* cap;
     ~PoolGuard() {
       (void)hipStreamSynchronize(st);
       for (int i = 0; i < 2; ++i)
-        if (p[i]) (void)hipFree(p[i]);
-      for (void* q : *r) (void)hipFree(q);
+        if (p[i]) DeviceChunkCache::get().give(p[i], cap[i]);
+      for (auto& q : *r) DeviceChunkCache::get().give(q.first, q.second);
     }
-  } pool_guard{pools, &retired, st};
+  } pool_guard{pools, &retired, st, pool_cap};
   // per-level device lists stay alive until the factorization has drained
   std::vector<std::unique_ptr<DeviceArena>> level_arenas;
   std::deque<PendingPhase> pending;  // solve records (stable addresses for the grouping jobs)
@@ -1286,16 +1295,21 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       pool_slot ^= 1;
       if (pool_cap[ps] < bytes) {
         // the previous level's assembly, still queued on st, may be reading this pool
-        if (pools[ps]) retired.push_back(pools[ps]);
+        if (pools[ps]) retired.emplace_back(pools[ps], pool_cap[ps]);
         pools[ps] = nullptr;
         pool_cap[ps] = 0;
-        hipError_t e = hipMalloc(&pools[ps], bytes);
-        if (e != hipSuccess) {
-          (void)hipGetLastError();
-          pools[ps] = nullptr;
-          throw Error(FMMLU_ENOMEM, "tile pool allocation failed (" + std::to_string(bytes) + " bytes)");
+        size_t got = bytes;
+        void* pp = DeviceChunkCache::get().take(bytes, got);
+        if (!pp) {
+          hipError_t e = hipMalloc(&pp, bytes);
+          if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(FMMLU_ENOMEM, "tile pool allocation failed (" + std::to_string(bytes) + " bytes)");
+          }
+          got = bytes;
         }
-        pool_cap[ps] = bytes;
+        pools[ps] = pp;
+        pool_cap[ps] = got;
       }
       pool = pools[ps];
     }
@@ -1662,7 +1676,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
         FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
         sg.sync();
-        for (void* q : retired) FMMLU_HIP(hipFree(q));  // everything queued before has finished
+        for (auto& q : retired) DeviceChunkCache::get().give(q.first, q.second);  // its readers have finished
         retired.clear();
         int64_t po = nb;
         for (int i = 0; i < nb; ++i) {
