@@ -94,14 +94,17 @@ fmmlu_opts checked_opts(fmmlu_tree_h t, const double* xyz, const double* normals
 }
 
 // Factor on the calling thread's current device; the handle owns the result.
+// precapture: record the solve graphs at the end of the factorization (not while other
+// threads factor: their legacy-stream work may not overlap a capture)
 fmmlu_factor_s* make_factor(fmmlu_tree_h t, const double* xyz, const double* normals, const double* weights, double k,
-                            double eta, const fmmlu_opts& o, hipStream_t st) {
+                            double eta, const fmmlu_opts& o, hipStream_t st, bool precapture = true) {
   auto* h = new fmmlu_factor_s;
   try {
     FMMLU_HIP(hipGetDevice(&h->f.device));
     h->f.k = k;
     h->f.eta = eta;
     h->f.opts = o;
+    h->f.precapture = precapture;
     h->f.factor(t->t, xyz, normals, weights, st);
     h->f.info.t_tree = t->t_build;
   } catch (...) {
@@ -253,7 +256,7 @@ fmmlu_status fmmlu_factor_batch(int32_t count, const fmmlu_tree_h* trees, const 
         }
         for (int i = next++; i < count; i = next++) {
           try {
-            b->factors[i] = make_factor(trees[i], xyz[i], normals[i], weights[i], k[i], eta[i], os[i], s);
+            b->factors[i] = make_factor(trees[i], xyz[i], normals[i], weights[i], k[i], eta[i], os[i], s, false);
           } catch (const Error& e) {
             st[i] = e.status;
             msg[i] = e.what();

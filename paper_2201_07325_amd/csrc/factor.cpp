@@ -1024,9 +1024,9 @@ void dense_inverse_batch(const zd* A, int64_t n, int64_t count, zd* out, hipStre
     outs[i] = out + i * n * n;
   }
   batched_inverse(sg, tasks, outs, info_dev, KC_INV);
-  sg.sync_reset();
   int32_t hinfo = 0;
-  FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+  FMMLU_HIP(hipMemcpyAsync(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost, sg.go()));
+  sg.sync_reset();
   if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out");
   if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "zero pivot in column " + std::to_string(hinfo - 1));
 }
@@ -2196,6 +2196,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   }
 
   ht.mark(7);
+  Clock::time_point tt[6];
+  tt[0] = Clock::now();
   // ---- top block: all remaining live DOFs (tree order)
   {
     // own holds the owners after the last merge; their act lists are all live.
@@ -2269,12 +2271,15 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       std::vector<zd*> outs{Ainv};
       batched_inverse(sg, gt, outs, info_dev, KC_TOP);
       top_dev = sg.up_to(arena, top);
+      tt[1] = Clock::now();
       info.flops_top = 8.0 * (double)n0 * n0 * n0;
       info.factor_bytes += 16 * (int64_t)n0 * n0;
     }
     // solve records: the scatter lists were grouped on the background worker while the
     // planning thread waited on the device; all arrays of all phases leave in one copy
+    if (n0 <= 0) tt[1] = Clock::now();
     bgw.drain();
+    tt[2] = Clock::now();
     {
       std::vector<SolvePhase> newph(pending.size());
       Stage::Packed pk;
@@ -2304,24 +2309,33 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       for (auto& ph : newph) phases.push_back(ph);
     }
     pending.clear();
+    // the table of all boxes, then the forward and adjoint solve graphs, captured while the
+    // top block is still running (a capture only records launches)
+    {
+      std::vector<SolveBox> all;
+      for (auto& fb : boxes) {
+        all.push_back(fb.dev);
+        rmax_all = std::max(rmax_all, fb.r);
+      }
+      nall = (int)all.size();
+      all_boxes = sg.up_to(arena, all);
+    }
+    tt[3] = Clock::now();
+    if (use_graph && precapture && ActiveFactorization::count() == 1) {
+      ensure_workspace();
+      if (!capture(0) || !capture(1)) use_graph = false;
+    }
+    tt[4] = Clock::now();
     sg.sync_reset();
+    tt[5] = Clock::now();
     prev_pool = nullptr;
     // the first zero pivot of any pivot block or of the top block (column + 1), or -1 if a
     // cooperative barrier timed out
     int32_t hinfo = 0;
-    FMMLU_HIP(hipMemcpy(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost));
+    FMMLU_HIP(hipMemcpyAsync(&hinfo, info_dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    FMMLU_HIP(hipStreamSynchronize(st));
     if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out");
     if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block (X_RR or the top block)");
-  }
-  {
-    std::vector<SolveBox> all;
-    for (auto& fb : boxes) {
-      all.push_back(fb.dev);
-      rmax_all = std::max(rmax_all, fb.r);
-    }
-    nall = (int)all.size();
-    all_boxes = sg.up_to(arena, all);
-    sg.sync_reset();
   }
   info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)arena.held());
   info.t_factor = std::chrono::duration<double>(Clock::now() - t0).count();
@@ -2333,6 +2347,9 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             ht.t[0], ht.t[8], ht.t[1], ht.t[2], ht.t[3], ht.t[4], ht.t[5], ht.t[6], ht.t[7]);
     fprintf(stderr, "[fmmlu] elimination planning: boxes %.3f cross %.3f E/F %.3f inverse %.3f panels %.3f\n",
             ht.t[9], ht.t[10], ht.t[11], ht.t[12], ht.t[4]);
+    auto ms = [&](int a, int b) { return std::chrono::duration<double, std::milli>(tt[b] - tt[a]).count(); };
+    fprintf(stderr, "[fmmlu] tail (ms): top block planning+launch %.2f, record grouping wait %.2f, records upload %.2f, "
+            "graph capture %.2f, final wait %.2f\n", ms(0, 1), ms(1, 2), ms(2, 3), ms(3, 4), ms(4, 5));
     fprintf(stderr, "[fmmlu] schur planning: contributions %.3f tasks %.3f launch+rest %.3f\n", ht.t[13], ht.t[14],
             ht.t[5]);
   }

@@ -150,6 +150,7 @@ struct FactorImpl {
   bool capture_block(int adj);
   // solves replay a captured HIP graph per direction (input/output through gin/gout)
   bool use_graph = true;
+  bool precapture = true;  // capture the solve graphs while the top block runs (single factorizations)
   hipStream_t gstream = nullptr;
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};

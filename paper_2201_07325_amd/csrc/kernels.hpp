@@ -266,6 +266,7 @@ void launch_gj_step_gather(const GjStepArgs& a, zd* out, hipStream_t st);
 struct ActiveFactorization {
   ActiveFactorization();
   ~ActiveFactorization();
+  static int count();  // factorizations in progress in the process
 };
 void launch_gj_swaps(const GjTask* tasks, int ntasks, int j0, int nmax, hipStream_t st);
 // W (nb x n) = A[J, :] with J = [j0, j0+nb)

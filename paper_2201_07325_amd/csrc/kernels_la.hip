@@ -1708,6 +1708,7 @@ void coop_launch(F&& launch, hipStream_t st) {
 
 ActiveFactorization::ActiveFactorization() { ++g_active_factorizations; }
 ActiveFactorization::~ActiveFactorization() { --g_active_factorizations; }
+int ActiveFactorization::count() { return g_active_factorizations.load(); }
 
 void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStream_t st) {
   if (ntasks <= 0) return;
