@@ -171,7 +171,9 @@ struct Owner {
   std::vector<int64_t> sub_rowbase;
 };
 
-int64_t gap_units(const Owner& a, const Owner& b) {
+// gap between two owner boxes in units of the finer one's size (0: touching)
+template <class O>
+int64_t gap_units(const O& a, const O& b) {
   const int L = std::max(a.level, b.level);
   const int64_t sa = int64_t(1) << (L - a.level), sb = int64_t(1) << (L - b.level);
   int64_t g = 0;
@@ -1109,6 +1111,24 @@ std::vector<std::vector<int>> close_owner_lists(const std::vector<OwnerCell>& ow
   return close;
 }
 
+// The close pairs that get a tile (gap of at most one box), owner by owner in ascending
+// order: beg (per owner, CSR), ids (the partner), pairs ((owner, partner) in that order).
+void tile_pairs(const std::vector<OwnerCell>& ow, const std::vector<std::vector<int>>& close,
+                std::vector<int64_t>& beg, std::vector<int32_t>& ids, std::vector<std::pair<int, int>>& pairs) {
+  const int no = (int)ow.size();
+  beg.assign(1, 0);
+  ids.clear();
+  pairs.clear();
+  for (int i = 0; i < no; ++i) {
+    for (int p : close[i]) {
+      if (gap_units(ow[i], ow[p]) > 1) continue;
+      ids.push_back(p);
+      pairs.emplace_back(i, p);
+    }
+    beg.push_back((int64_t)ids.size());
+  }
+}
+
 // Scatter lists of a phase grouped by destination (CSR): y indices increase with the box
 // order, so sorting the (destination, y) pairs keeps each destination's contributions in box
 // order. The pair list is released afterwards.
@@ -1225,7 +1245,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   // close lists of the next level's owners, computed ahead on a worker thread (see below);
   // the worker is declared last so that its job ends before the lists it writes go
   std::vector<int> spec_boxes;
-  std::vector<std::vector<int>> spec_close;
+  struct SpecLevel {
+    std::vector<std::vector<int>> close;
+    std::vector<int64_t> beg;
+    std::vector<int32_t> ids;
+    std::vector<std::pair<int, int>> pairs;
+  } spec;
   bool spec_posted = false;
   Background spec_worker;
 
@@ -1235,20 +1260,28 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     // ---- close pairs of owners and their tiles: taken from the worker's speculative lists
     // when this level's owners are the ones it assumed, else searched here
     std::vector<std::vector<int>> close;
+    PairIndex pidx;
+    std::vector<std::pair<int, int>> pairs;
     bool spec_hit = false;
     if (spec_posted) {
       spec_worker.drain();
       spec_posted = false;
       bool same = (int)spec_boxes.size() == nown;
       for (int i = 0; same && i < nown; ++i) same = spec_boxes[i] == own[i].box;
-      if (same) close.swap(spec_close);
+      if (same) {
+        close.swap(spec.close);
+        pidx.beg.swap(spec.beg);
+        pidx.ids.swap(spec.ids);
+        pairs.swap(spec.pairs);
+      }
       spec_hit = same;
-      spec_close.clear();
+      spec = SpecLevel{};
     }
-    if (close.empty()) {
+    if (!spec_hit) {
       std::vector<OwnerCell> cells(nown);
       for (int i = 0; i < nown; ++i) cells[i] = OwnerCell{own[i].level, {own[i].c[0], own[i].c[1], own[i].c[2]}};
       close = close_owner_lists(cells, D, &hp);
+      tile_pairs(cells, close, pidx.beg, pidx.ids, pairs);
     }
     // the next level's owners if every owner keeps live DOFs (the merge below checks): the
     // parents of this level's boxes and the coarser owners, in tree order; their close
@@ -1268,23 +1301,19 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         spec_boxes[i] = b;
         cells[i] = OwnerCell{(int)tree.level[b], {(int64_t)tree.cx[b], (int64_t)tree.cy[b], (int64_t)tree.cz[b]}};
       }
-      spec_worker.post([&spec_close, cells = std::move(cells), D] { spec_close = close_owner_lists(cells, D, nullptr); });
+      spec_worker.post([&spec, cells = std::move(cells), D] {
+        spec.close = close_owner_lists(cells, D, nullptr);
+        tile_pairs(cells, spec.close, spec.beg, spec.ids, spec.pairs);
+      });
       spec_posted = true;
     }
-    PairIndex pidx;
-    pidx.beg.assign(1, 0);
+    // tile offsets in the level's pool (pair order)
     std::vector<int32_t> kcount;  // per pair, zero between colour phases (Schur grouping)
     int64_t pool_elems = 0;
-    std::vector<std::pair<int, int>> pairs;
-    for (int i = 0; i < nown; ++i) {
-      for (int p : close[i]) {
-        if (gap_units(own[i], own[p]) > 1) continue;
-        pidx.ids.push_back(p);
-        pidx.off.push_back(pool_elems);
-        pairs.emplace_back(i, p);
-        pool_elems += (int64_t)own[i].act.size() * own[p].act.size();
-      }
-      pidx.beg.push_back((int64_t)pidx.ids.size());
+    pidx.off.resize(pairs.size());
+    for (size_t k = 0; k < pairs.size(); ++k) {
+      pidx.off[k] = pool_elems;
+      pool_elems += (int64_t)own[pairs[k].first].act.size() * own[pairs[k].second].act.size();
     }
     kcount.assign(pidx.ids.size(), 0);
     ht.mark(0);
