@@ -554,6 +554,17 @@ struct Stage {
     std::memcpy(hd.first, v.data(), b);
     return static_cast<T*>(hd.second);
   }
+  // upload space for n values that the caller fills in place on the host (before the next
+  // go()): the host and device addresses
+  template <class T>
+  std::pair<T*, T*> up_raw(size_t n) {
+    if (n == 0) return {nullptr, nullptr};
+    const size_t b = n * sizeof(T);
+    UploadRing& r = ring[rcur];
+    if (!r.fits(b)) r.flush(st);
+    auto hd = r.alloc(b);
+    return {static_cast<T*>(hd.first), static_cast<T*>(hd.second)};
+  }
   // persistent upload into another arena
   template <class T>
   T* up_to(DeviceArena& a, const std::vector<T>& v) {
@@ -1379,7 +1390,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         const bool live = !a.act.empty() && !b.act.empty();
         unito[k + 1] = unito[k] + (live ? units64((int)a.act.size(), (int)b.act.size()) : 0);
       }
-      std::vector<AsmSrc> table((size_t)tabo[np]);
+      // the source table is written straight into its upload space (no copy)
+      const std::pair<AsmSrc*, AsmSrc*> table = sg.up_raw<AsmSrc>((size_t)tabo[np]);
       std::vector<AsmTask> all((size_t)np);
       hp.ranges(np, 256, [&](int lo, int hi) {
         for (int k = lo; k < hi; ++k) {
@@ -1396,7 +1408,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           t.rdof_off = map_off[pr.first];
           t.cdof_off = map_off[pr.second];
           t.tab_off = tabo[k];
-          AsmSrc* tab = table.data() + tabo[k];
+          AsmSrc* tab = table.first + tabo[k];
           if (first_level) {
             t.nsc = 1;
             tab[0] = AsmSrc{-1, 0, 0};
@@ -1433,7 +1445,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int32_t* dslot = sg.up(slot);
         int32_t* didx = sg.up(idx);
         int64_t* ddof = sg.up(dof);
-        AsmSrc* dtab = sg.up(table);
+        AsmSrc* dtab = table.second;
         int32_t* dut = sg.up(ut);
         ProfScope ps(prof, KC_ASSEMBLE);
         launch_assemble(g, dt, (int)tasks.size(), units, dslot, didx, ddof, dtab, prev_pool, f32, pool, f32, sg.go(),
