@@ -528,6 +528,19 @@ struct Stage {
   // error unwinds the factorization); members are destroyed after this body runs
   ~Stage() {
     if (st) (void)hipStreamSynchronize(st);
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  // a point in the stream that the host can wait for without waiting for what follows it
+  hipEvent_t ev = nullptr;
+  void mark() {
+    flush();
+    if (!ev) FMMLU_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    FMMLU_HIP(hipEventRecord(ev, st));
+  }
+  void wait_mark() {
+    auto a = std::chrono::steady_clock::now();
+    FMMLU_HIP(hipEventSynchronize(ev));
+    t_wait += std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
   }
   // switch to the other buffer at the start of a colour phase (see DoubleArena)
   void flip() {
@@ -1617,6 +1630,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           po += plan[i].m;
         }
       }
+      int32_t* hr = nullptr;  // host copy of ranks and pivots (set where the read-back is queued)
       const bool gram = opts.id_route == 1 || (opts.id_route == 0 && eps >= kGramEps);
       if (gram) {
         constexpr int KCH = 512;
@@ -1681,6 +1695,16 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             launch_pchol(dpt, nb, mmax, eps, sg.go());
           }
         }
+        // ranks and pivots are final here: their read-back goes ahead of T's back
+        // substitution, which then runs while the host plans the elimination
+        hr = static_cast<int32_t*>(sg.host.alloc(sizeof(int32_t) * (size_t)(nb + perm_total)));
+        FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
+        FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
+        sg.mark();
+        {
+          ProfScope ps(prof, KC_CPQR);
+          launch_pchol_t(dpt, nb, mmax, sg.go());
+        }
       } else {
         std::vector<zd*> Ms;
         std::vector<int> rws, mms;
@@ -1713,10 +1737,14 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       std::vector<int32_t> ranks(nb);
       std::vector<std::vector<int32_t>> perms(nb);
       {
-        int32_t* hr = static_cast<int32_t*>(sg.host.alloc(sizeof(int32_t) * (size_t)(nb + perm_total)));
-        FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
-        FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
-        sg.sync();
+        if (hr) {
+          sg.wait_mark();
+        } else {
+          hr = static_cast<int32_t*>(sg.host.alloc(sizeof(int32_t) * (size_t)(nb + perm_total)));
+          FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
+          FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
+          sg.sync();
+        }
         for (auto& q : retired) DeviceChunkCache::get().give(q.first, q.second);  // its readers have finished
         retired.clear();
         int64_t po = nb;

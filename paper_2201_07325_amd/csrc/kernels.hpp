@@ -196,6 +196,9 @@ constexpr int kPcholBlockedMin = 128;  // widest block of a phase from which the
 void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st);
 void launch_pchol_finish(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st);
 void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st);
+// after launch_pchol or launch_pchol_finish: T = R11^{-1} R12 by back substitution (rank and
+// perm are final before it, so their read-back can be queued ahead of it)
+void launch_pchol_t(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st);
 
 // ---- Gauss-Jordan inversion with partial pivoting, blocked ----
 struct GjTask {

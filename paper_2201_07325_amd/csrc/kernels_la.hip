@@ -1632,6 +1632,10 @@ void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipS
   hipLaunchKernelGGL(pchol_kernel, dim3(ntasks), dim3(kPcholThreads), in_lds ? with_mult : without, st, tasks, eps,
                      in_lds);
   FMMLU_HIP(hipGetLastError());
+}
+
+void launch_pchol_t(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st) {
+  if (ntasks <= 0) return;
   // back substitution: NC right-hand-side columns per workgroup, s x NC in LDS
   const dim3 grid_of_nc[4] = {dim3(ntasks, (mmax + 7) / 8), dim3(ntasks, (mmax + 3) / 4),
                               dim3(ntasks, (mmax + 1) / 2), dim3(ntasks, mmax)};
@@ -1655,15 +1659,6 @@ void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, 
 void launch_pchol_finish(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st) {
   if (ntasks <= 0) return;
   hipLaunchKernelGGL(pchol_finish_kernel, dim3(ntasks), dim3(kPcholThreads), (size_t)mmax * sizeof(int), st, tasks);
-  FMMLU_HIP(hipGetLastError());
-  const dim3 grid_of_nc[4] = {dim3(ntasks, (mmax + 7) / 8), dim3(ntasks, (mmax + 3) / 4),
-                              dim3(ntasks, (mmax + 1) / 2), dim3(ntasks, mmax)};
-  if (mmax <= 480)
-    hipLaunchKernelGGL(pchol_t_kernel<8>, grid_of_nc[0], dim3(256), (size_t)mmax * 8 * sizeof(zd), st, tasks);
-  else if (mmax <= 960)
-    hipLaunchKernelGGL(pchol_t_kernel<4>, grid_of_nc[1], dim3(256), (size_t)mmax * 4 * sizeof(zd), st, tasks);
-  else
-    hipLaunchKernelGGL(pchol_t_kernel<2>, grid_of_nc[2], dim3(256), (size_t)mmax * 2 * sizeof(zd), st, tasks);
   FMMLU_HIP(hipGetLastError());
 }
 
