@@ -889,7 +889,9 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
           __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
           const int target = t.wpt * (gc + 1);
           int64_t spins = 0;
-          while (__hip_atomic_load(t.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          // relaxed polling (an acquire load would invalidate the caches at every poll); the
+          // fence after the loop orders what follows
+          while (__hip_atomic_load(t.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (++spins > kGjSpinLimit) {
               __hip_atomic_store(t.info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               break;
@@ -987,11 +989,13 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
 constexpr int kGjChunk = 16;
 constexpr int64_t kGjCoopSpin = int64_t(1) << 22;
 
-// thread 0 waits until *w >= target, then the workgroup continues (acquire)
+// thread 0 waits until *w >= target, then the workgroup continues (acquire). The flag is
+// polled with relaxed loads (an acquire load would invalidate the caches at every poll, also
+// for the other workgroups on the same XCD); the fence after the loop orders what follows.
 __device__ inline void gj_wait_at_least(int32_t* w, int target, int32_t* info) {
   if (threadIdx.x == 0) {
     int64_t spins = 0;
-    while (__hip_atomic_load(w, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (++spins > kGjCoopSpin) {
         __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
