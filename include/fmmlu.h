@@ -64,7 +64,8 @@ typedef struct {
   int32_t precision;          /* fmmlu_precision */
   int64_t device_mem_cap;     /* bytes of device memory the factorization may hold; 0 = no cap */
   int32_t verbose;            /* 0 silent, 1 per-level summary on stderr */
-  int32_t profile;            /* 1: time each kernel class with HIP events (fmmlu_factor_profile) */
+  int32_t profile;            /* 1: time each kernel class with HIP events (fmmlu_factor_profile);
+                                 2: the Schur-update class (6) only, fewer event records */
   int32_t id_route;           /* greedy CPQR route: 0 auto (Gram matrix when eps >= 1e-7, else
                                  Householder), 1 Gram matrix + pivoted Cholesky, 2 Householder QR */
   int32_t reserved[5];

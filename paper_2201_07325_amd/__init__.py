@@ -202,7 +202,8 @@ class Factor:
         o.precision = int(precision)
         o.verbose = int(verbose)
         o.device_mem_cap = int(mem_cap)
-        o.profile = 1 if profile else 0
+        # True / 1: every kernel class; 2: the Schur-update class only
+        o.profile = int(profile) if isinstance(profile, int) and not isinstance(profile, bool) else (1 if profile else 0)
         o.id_route = int(id_route)
         h = P()
         _check(L.fmmlu_factor(self.tree.h, _ptr(self.points), _ptr(self.normals), _ptr(self.weights),

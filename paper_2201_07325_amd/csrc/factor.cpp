@@ -117,7 +117,7 @@ hipEvent_t Profiler::get() {
   return e;
 }
 void Profiler::begin(int cls) {
-  if (!on) return;
+  if (!on || !((mask >> cls) & 1u)) return;
   cur = cls;
   cur_a = get();
   FMMLU_HIP(hipEventRecord(cur_a, st));
@@ -1189,6 +1189,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   sg.st = st;
   HostPool hp((int)std::min(8u, std::max(1u, std::thread::hardware_concurrency())));
   prof.on = opts.profile != 0;
+  prof.mask = opts.profile == 2 ? (1u << KC_SCHUR) : ~0u;
   prof.st = st;
   sg.prof = &prof;
   // ---- geometry in tree order: x, y, z, nx, ny, nz, sqrt(w)

@@ -35,6 +35,7 @@ class HostStage {
 enum KClass { KC_ASSEMBLE = 0, KC_IDMAT, KC_QR, KC_CPQR, KC_ELIM, KC_INV, KC_SCHUR, KC_TOP, KC_COUNT };
 struct Profiler {
   bool on = false;
+  unsigned mask = ~0u;  // classes bracketed while on
   hipStream_t st = nullptr;
   struct Rec {
     int cls;
