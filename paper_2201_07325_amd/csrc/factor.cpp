@@ -1947,6 +1947,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         // panels: Lp = X_{SN,R} Xi ; Up = Xi X_{R,SN}; T compacted into the factor
         {
           GemmBatch gp, gl;  // gl: Lp straight into factor storage (float32 C when f32)
+          GemmBatch& glr = f32 ? gl : gp;  // float64 C: one launch for both panels
           std::vector<CopyTask> cps, trs;
           int64_t cu = 0, tu = 0;
           for (auto& e : ep) {
@@ -1957,7 +1958,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
               const zd* XsnR = e.Ccol + (int64_t)e.s * mn + e.r;         // X_{(S u N) R}
               const zd* XRsn = e.Crow + e.s + (int64_t)e.r * m;          // X_{R (S u N)}
               e.Up = sg.dev.alloc_n<zd>((size_t)e.r * e.nsn);
-              gl.add1(const_cast<void*>(d.Lp), e.nsn, e.nsn, e.r, XsnR, mn, e.Xi64, e.r, e.r, 1.0, 0.0);
+              glr.add1(const_cast<void*>(d.Lp), e.nsn, e.nsn, e.r, XsnR, mn, e.Xi64, e.r, e.r, 1.0, 0.0);
               gp.add1(e.Up, e.r, e.r, e.nsn, e.Xi64, e.r, XRsn, m, e.r, 1.0, 0.0);
               trs.push_back(CopyTask{e.Up, const_cast<void*>(d.UpT), e.r, e.nsn, e.r, e.nsn, tu});
               tu += units64(e.r, e.nsn);
