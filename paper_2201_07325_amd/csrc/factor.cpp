@@ -1903,13 +1903,15 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         //   Ccol[0:r, s:m]    -= T^T Ccol[r:m, s:m]    -> X_RR;  Ccol[r:, s:m] = X_{(S u N) R}
         //   Crow[s:m, r:]     -= T^T Crow[0:s, r:]     -> X_{R (S u N)}
         {
-          GemmBatch ga, gb, gc;
+          // ga first; gb depends on it. The Crow transform is independent of both and has
+          // the same operand form as gb, so it goes in gb's launch.
+          GemmBatch ga, gb;
           for (auto& e : ep) {
             BoxPlan& bp = plan[e.pi];
             const int m = bp.m, mn = bp.m + bp.nN;
             zd* CcR = e.Ccol + (int64_t)e.s * mn;
             ga.add1(CcR, mn, mn, e.r, e.Ccol, mn, bp.T, m, e.s, -1.0, 1.0);
-            gc.add1(e.Crow + e.s + (int64_t)e.r * m, m, e.r, mn - e.r, bp.T, m, e.Crow + (int64_t)e.r * m, m,
+            gb.add1(e.Crow + e.s + (int64_t)e.r * m, m, e.r, mn - e.r, bp.T, m, e.Crow + (int64_t)e.r * m, m,
                     e.s, -1.0, 1.0);
           }
           for (auto& e : ep) {
@@ -1922,10 +1924,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           }
           ga.prepare(sg);
           gb.prepare(sg);
-          gc.prepare(sg);
           ProfScope ps(prof, KC_ELIM);
           ga.launch(sg, 0);
-          gc.launch(sg, 1);
           gb.launch(sg, 1);
         }
         ht.mark(11);
