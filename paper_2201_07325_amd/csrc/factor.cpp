@@ -1960,7 +1960,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
               e.Up = sg.dev.alloc_n<zd>((size_t)e.r * e.nsn);
               glr.add1(const_cast<void*>(d.Lp), e.nsn, e.nsn, e.r, XsnR, mn, e.Xi64, e.r, e.r, 1.0, 0.0);
               gp.add1(e.Up, e.r, e.r, e.nsn, e.Xi64, e.r, XRsn, m, e.r, 1.0, 0.0);
-              trs.push_back(CopyTask{e.Up, const_cast<void*>(d.UpT), e.r, e.nsn, e.r, e.nsn, tu});
+              trs.push_back(CopyTask{e.Up, const_cast<void*>(d.UpT), e.r, e.nsn, e.r, e.nsn, tu, 1, 0});
               tu += units64(e.r, e.nsn);
             }
             if (e.s > 0) {
@@ -1975,13 +1975,16 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           }
           gp.prepare(sg);
           gl.prepare(sg);
+          // the copies and the transposes (of Up, after its product) in one launch
+          for (auto& c : trs) {
+            c.unit_begin += cu;
+            cps.push_back(c);
+          }
           CopyTask* dcp = cps.empty() ? nullptr : sg.up(cps);
-          CopyTask* dtr = trs.empty() ? nullptr : sg.up(trs);
           ProfScope ps(prof, KC_ELIM);
           gp.launch(sg, 0);
           gl.launch(sg, 0, f32);
-          if (dcp) launch_copy(dcp, (int)cps.size(), cu, f32, sg.go());
-          if (dtr) launch_transpose(dtr, (int)trs.size(), tu, f32, sg.go());
+          if (dcp) launch_copy(dcp, (int)cps.size(), cu + tu, f32, sg.go());
           for (auto& e : ep) prof.flops[KC_ELIM] += 8.0 * 2.0 * (double)e.nsn * e.r * e.r;
         }
         ht.mark(4);

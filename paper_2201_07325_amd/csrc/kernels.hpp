@@ -298,10 +298,11 @@ struct CopyTask {
   void* dst;  // complex float64, or float32 with dst32
   int32_t rows, cols, lds, ldd;
   int64_t unit_begin;
+  int32_t transpose;  // 0: dst[i + j*ldd] = src[i + j*lds]; 1: dst[j + i*ldd] = src[i + j*lds]
+  int32_t pad;
 };
+// copies and transposes of rows x cols sources; units of 64 x 64
 void launch_copy(const CopyTask* tasks, int ntasks, int64_t nunits, bool dst32, hipStream_t st);
-// dst[j + i*ldd] = src[i + j*lds] (rows x cols source); units of 64 x 64
-void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, bool dst32, hipStream_t st);
 
 // ---- solve sweeps ----
 struct SolveBox {

@@ -1570,14 +1570,29 @@ __global__ void __launch_bounds__(256) extract_r_kernel(const ExtractTask* __res
   }
 }
 
+// copies and transposes in one launch (t.transpose, uniform per task); units of 64 x 64
 template <class DT>
 __global__ void __launch_bounds__(256) copy_kernel(const CopyTask* __restrict__ tasks, int ntasks) {
+  __shared__ zd tile[64][65];
   const int64_t u = blockIdx.x;
   const int ti = find_task(tasks, ntasks, u);
   const CopyTask t = tasks[ti];
   const int64_t lu = u - t.unit_begin;
   const int nbr = (t.rows + 63) >> 6;
   const int bi = (int)(lu % nbr), bj = (int)(lu / nbr);
+  if (t.transpose) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int q = ty; q < 64; q += 4) {
+      const int i = bi * 64 + tx, j = bj * 64 + q;
+      if (i < t.rows && j < t.cols) tile[q][tx] = t.src[i + (int64_t)j * t.lds];
+    }
+    __syncthreads();
+    for (int q = ty; q < 64; q += 4) {
+      const int j = bj * 64 + tx, i = bi * 64 + q;
+      if (i < t.rows && j < t.cols) static_cast<DT*>(t.dst)[j + (int64_t)i * t.ldd] = narrow<DT>(tile[tx][q]);
+    }
+    return;
+  }
   const int i = bi * 64 + (threadIdx.x & 63);
   if (i >= t.rows) return;
   for (int jj = 0; jj < 16; ++jj) {
@@ -1587,37 +1602,8 @@ __global__ void __launch_bounds__(256) copy_kernel(const CopyTask* __restrict__ 
   }
 }
 
-template <class DT>
-__global__ void __launch_bounds__(256) transpose_kernel(const CopyTask* __restrict__ tasks, int ntasks) {
-  __shared__ zd tile[64][65];
-  const int64_t u = blockIdx.x;
-  const int ti = find_task(tasks, ntasks, u);
-  const CopyTask t = tasks[ti];
-  const int64_t lu = u - t.unit_begin;
-  const int nbr = (t.rows + 63) >> 6;
-  const int bi = (int)(lu % nbr), bj = (int)(lu / nbr);
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int q = ty; q < 64; q += 4) {
-    const int i = bi * 64 + tx, j = bj * 64 + q;
-    if (i < t.rows && j < t.cols) tile[q][tx] = t.src[i + (int64_t)j * t.lds];
-  }
-  __syncthreads();
-  for (int q = ty; q < 64; q += 4) {
-    const int j = bj * 64 + tx, i = bi * 64 + q;
-    if (i < t.rows && j < t.cols) static_cast<DT*>(t.dst)[j + (int64_t)i * t.ldd] = narrow<DT>(tile[tx][q]);
-  }
-}
-
 }  // namespace
 
-void launch_transpose(const CopyTask* tasks, int ntasks, int64_t nunits, bool dst32, hipStream_t st) {
-  if (ntasks <= 0 || nunits <= 0) return;
-  if (dst32)
-    hipLaunchKernelGGL(transpose_kernel<zf>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
-  else
-    hipLaunchKernelGGL(transpose_kernel<zd>, dim3((unsigned)nunits), dim3(256), 0, st, tasks, ntasks);
-  FMMLU_HIP(hipGetLastError());
-}
 
 void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStream_t st) {
   if (ntasks <= 0 || nunits <= 0) return;
