@@ -13,6 +13,8 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <thread>
+#include <vector>
 
 #include "common.hpp"
 
@@ -26,6 +28,22 @@ static inline uint64_t spread3(uint32_t v) {
   x = (x | (x << 4)) & 0x10c30c30c30c30c3ULL;
   x = (x | (x << 2)) & 0x1249249249249249ULL;
   return x;
+}
+
+// fn(lo, hi) over [0, n) in contiguous chunks on up to 8 threads (inline when small)
+template <class F>
+static void chunked(int64_t n, int64_t grain, F&& fn) {
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({8, (int64_t)std::thread::hardware_concurrency(), n / grain}));
+  if (nt <= 1) {
+    fn(int64_t(0), n);
+    return;
+  }
+  const int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::thread> th;
+  for (int64_t t = 1; t < nt; ++t)
+    th.emplace_back([&, t] { fn(t * chunk, std::min(n, (t + 1) * chunk)); });
+  fn(int64_t(0), std::min(n, chunk));
+  for (auto& x : th) x.join();
 }
 
 uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
@@ -130,14 +148,21 @@ void Octree::finish() {
   for (int b = 0; b < (int)level.size(); ++b)
     if (child0[b] < 0 && pend[b] > pbeg[b]) leaves.push_back(b);
   std::sort(leaves.begin(), leaves.end(), [&](int a, int b) { return pbeg[a] < pbeg[b]; });
-  int64_t pos = 0;
-  for (int b : leaves) {
-    int64_t s = pos;
-    for (int64_t i = pbeg[b]; i < pend[b]; ++i) order[pos++] = msort[i];
-    std::sort(order.begin() + s, order.begin() + pos);
-  }
+  // leaf l's run starts at the sum of the earlier leaves' sizes; runs are independent
+  std::vector<int64_t> start(leaves.size() + 1, 0);
+  for (size_t l = 0; l < leaves.size(); ++l) start[l + 1] = start[l] + (pend[leaves[l]] - pbeg[leaves[l]]);
+  chunked((int64_t)leaves.size(), 256, [&](int64_t lo, int64_t hi) {
+    for (int64_t l = lo; l < hi; ++l) {
+      const int b = leaves[l];
+      int64_t pos = start[l];
+      for (int64_t i = pbeg[b]; i < pend[b]; ++i) order[pos++] = msort[i];
+      std::sort(order.begin() + start[l], order.begin() + pos);
+    }
+  });
   rank.resize(n);
-  for (int64_t i = 0; i < n; ++i) rank[order[i]] = i;
+  chunked(n, 8192, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) rank[order[i]] = i;
+  });
 }
 
 void Octree::build(const double* xyz, int64_t n_, int leaf_size_) {
@@ -160,16 +185,18 @@ void Octree::build(const double* xyz, int64_t n_, int leaf_size_) {
   const double scale = double(int64_t(1) << kDepth);
   const int64_t qmax = (int64_t(1) << kDepth) - 1;
   key.resize(n);
-  for (int64_t i = 0; i < n; ++i) {
-    uint32_t q[3];
-    for (int a = 0; a < 3; ++a) {
-      volatile double t = (X[a][i] - root_lo[a]) / side;  // no contraction: match IEEE order
-      double u = std::floor(t * scale);
-      int64_t v = (int64_t)u;
-      q[a] = (uint32_t)std::min<int64_t>(std::max<int64_t>(v, 0), qmax);
+  chunked(n, 8192, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      uint32_t q[3];
+      for (int a = 0; a < 3; ++a) {
+        volatile double t = (X[a][i] - root_lo[a]) / side;  // no contraction: match IEEE order
+        double u = std::floor(t * scale);
+        int64_t v = (int64_t)u;
+        q[a] = (uint32_t)std::min<int64_t>(std::max<int64_t>(v, 0), qmax);
+      }
+      key[i] = morton3(q[0], q[1], q[2]);
     }
-    key[i] = morton3(q[0], q[1], q[2]);
-  }
+  });
   // order by (key, index): least-significant-digit radix sort of (key, index) pairs, stable
   // and started in index order, so equal keys keep increasing indices
   {
