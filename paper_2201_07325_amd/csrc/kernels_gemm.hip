@@ -64,7 +64,14 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
   using M = Mfma<CT>;
   using R = typename M::R;
   __shared__ R Asr[BK][LDP], Asi[BK][LDP], Bsr[BK][LDP], Bsi[BK][LDP];
-  const int64_t u = blockIdx.x;
+  // blocks are dealt to the 8 XCDs in turn: in each round of 64 blocks, XCD x gets the 8
+  // consecutive output blocks 8x .. 8x + 7 (neighbouring tiles of a task share its panels
+  // in that XCD's L2); the last partial round keeps the identity
+  int64_t u = blockIdx.x;
+  {
+    const int64_t g = gridDim.x, full = g - g % 64;
+    if (u < full) u = (u & ~int64_t(63)) + (u & 7) * 8 + ((u >> 3) & 7);
+  }
   const GemmTask t = tasks[utask ? utask[u] : find_unit_task(tasks, ntasks, u)];
   if (t.skip && *t.skip) return;
   int64_t lu = u - t.unit_begin;
