@@ -57,10 +57,16 @@ constexpr int BM = kGemmTile, BN = kGemmTile, BK = 16;
 constexpr int LDP = BM + 4;  // padded LDS row (doubles)
 
 // SCAT: C entries through the row / column maps (the Schur updates of pair tiles)
-template <int OPA, class CT, bool SCAT>
-__global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks,
-                                                         const GemmSeg* __restrict__ segs,
-                                                         const int32_t* __restrict__ utask) {
+// NWV wavefronts per workgroup (4: each owns a 32 x 32 quarter of the 64 x 64 block; 8: a
+// 32 x 16 eighth, with half the accumulators and staging registers, so more wavefronts
+// fit per SIMD)
+template <int OPA, class CT, bool SCAT, int NWV>
+__global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
+    zgemm_mfma_kernel(const GemmTask* __restrict__ tasks, int ntasks, const GemmSeg* __restrict__ segs,
+                      const int32_t* __restrict__ utask) {
+  constexpr int GT = 64 * NWV;          // threads
+  constexpr int NQ = BM * BK / GT;      // staged values per thread and operand per K step
+  constexpr int WB = 8 / NWV;           // 16-column blocks per wavefront
   using M = Mfma<CT>;
   using R = typename M::R;
   __shared__ R Asr[BK][LDP], Asi[BK][LDP], Bsr[BK][LDP], Bsi[BK][LDP];
@@ -92,16 +98,18 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
     col0 = (int)(lu / nbm) * BN;
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wavefront quarter
-  // 16 x 16 blocks of the quarter that hold entries of C (wave-uniform): the others skip
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 16 * WB;  // wavefront's 32 x 16 WB part
+  // 16 x 16 blocks of the part that hold entries of C (wave-uniform): the others skip
   // their MFMAs and operand reads
   const int vm = t.M - row0 - wr, vn = t.N - col0 - wc;
-  const bool ua[2] = {vm > 0, vm > 16}, ub[2] = {vn > 0, vn > 16};
-  typename M::V cr[2][2], ci[2][2];
+  bool ua[2] = {vm > 0, vm > 16}, ub[WB];
+#pragma unroll
+  for (int b = 0; b < WB; ++b) ub[b] = vn > 16 * b;
+  typename M::V cr[2][WB], ci[2][WB];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < WB; ++b) {
       cr[a][b] = typename M::V{0, 0, 0, 0};
       ci[a][b] = typename M::V{0, 0, 0, 0};
     }
@@ -120,11 +128,11 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
     }
     return s;
   };
-  zd ra[4], rb[4];  // next step's global values (4 of A, 4 of B per thread)
+  zd ra[NQ], rb[NQ];  // next step's global values
   auto load = [&](const GemmSeg& sg, int k0, int kend) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + GT * q;
       int i, kk;
       if (OPA == 0) {
         i = e % BM;
@@ -154,8 +162,8 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
   };
   auto store = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tid + GT * q;
       int i, kk;
       if (OPA == 0) {
         i = e % BM;
@@ -188,7 +196,7 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;
-      R ar[2], ai[2], an[2], br[2], bi[2];
+      R ar[2], ai[2], an[2], br[WB], bi[WB];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         ar[a] = ua[a] ? Asr[kr][wr + 16 * a + cl] : R(0);
@@ -196,14 +204,14 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
         an[a] = -ai[a];
       }
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < WB; ++b) {
         br[b] = ub[b] ? Bsr[kr][wc + 16 * b + cl] : R(0);
         bi[b] = ub[b] ? Bsi[kr][wc + 16 * b + cl] : R(0);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < WB; ++b) {
           if (!(ua[a] && ub[b])) continue;
           cr[a][b] = M::mma(ar[a], br[b], cr[a][b]);
           cr[a][b] = M::mma(an[a], bi[b], cr[a][b]);
@@ -221,7 +229,7 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < WB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = row0 + wr + 16 * a + M::row(lane, r);
@@ -241,23 +249,25 @@ __global__ void __launch_bounds__(256, 3) zgemm_mfma_kernel(const GemmTask* __re
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st, bool mapped, const int32_t* utask) {
   if (ntasks <= 0 || nunits <= 0) return;
-  const dim3 g((unsigned)nunits), b(256);
+  // eight wavefronts per block for the Schur updates (mapped) and the Gram products and
+  // downdates (opA = 2); four for the elimination products, which measured faster so
+  const dim3 g((unsigned)nunits), b4(256), b8(512);
   if (mapped && opA != 0) throw Error(FMMLU_EINVAL, "mapped GEMM takes opA = N");
   if (c32) {
     if (opA != 0) throw Error(FMMLU_EINVAL, "float32 GEMM takes opA = N");
     if (mapped)
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, true>), g, b, 0, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, true, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
     else
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false>), g, b, 0, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
   } else if (opA == 0) {
     if (mapped)
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, true>), g, b, 0, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, true, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
     else
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false>), g, b, 0, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
   } else if (opA == 1) {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false>), g, b, 0, st, tasks, ntasks, segs, utask);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
   } else {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd, false>), g, b, 0, st, tasks, ntasks, segs, utask);
+    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd, false, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
   }
   FMMLU_HIP(hipGetLastError());
 }
