@@ -249,8 +249,8 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st, bool mapped, const int32_t* utask) {
   if (ntasks <= 0 || nunits <= 0) return;
-  // eight wavefronts per block for the Schur updates (mapped) and the Gram products and
-  // downdates (opA = 2); four for the elimination products, which measured faster so
+  // eight wavefronts per block, except for the transposed-A elimination products (opA = 1),
+  // which measured faster with four
   const dim3 g((unsigned)nunits), b4(256), b8(512);
   if (mapped && opA != 0) throw Error(FMMLU_EINVAL, "mapped GEMM takes opA = N");
   if (c32) {
@@ -263,7 +263,7 @@ void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, con
     if (mapped)
       hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, true, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
     else
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
   } else if (opA == 1) {
     hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
   } else {
