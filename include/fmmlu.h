@@ -261,6 +261,14 @@ fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const doub
  */
 fmmlu_status fmmlu_dense_inverse(const void* a, int64_t n, int64_t count, void* out, void* hip_stream);
 
+/*
+ * Frees the memory that released factorizations leave for reuse by later ones in the same
+ * process: device blocks (factor storage, planning scratch, tile pools; at most 8 GiB) and
+ * pinned host staging buffers (at most 512 MiB each for two pools). Call it between
+ * factorizations, not while one is running on another thread. Errors: EHIP.
+ */
+fmmlu_status fmmlu_trim_caches(void);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* fmmlu_last_error(void);
 

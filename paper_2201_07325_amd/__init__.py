@@ -90,6 +90,7 @@ def lib():
         "fmmlu_factor_destroy": (None, [P]),
         "fmmlu_factor_profile": (I32, [P, P, P, P, P]),
         "fmmlu_kernel_block": (I32, [P, P, P, I64, D, D, P, I64, P, I64, P, P]),
+        "fmmlu_trim_caches": (I32, []),
         "fmmlu_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -337,6 +338,12 @@ def kernel_block(points, normals, weights, k, eta, rows, cols):
                                     float(eta), P(r.data_ptr()), r.numel(), P(c.data_ptr()), c.numel(),
                                     P(out.data_ptr()), _stream()))
     return out.t()
+
+
+def trim_caches():
+    """Free the device and pinned host memory that released factorizations keep for reuse
+    by later ones (call between factorizations)."""
+    _check(lib().fmmlu_trim_caches())
 
 
 def dense_inverse(a):

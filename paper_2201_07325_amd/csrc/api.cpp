@@ -484,6 +484,10 @@ fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const doub
   });
 }
 
+fmmlu_status fmmlu_trim_caches(void) {
+  return guarded([&] { trim_reuse_caches(); });
+}
+
 const char* fmmlu_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

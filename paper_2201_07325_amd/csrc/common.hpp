@@ -113,6 +113,16 @@ class DeviceChunkCache {
     free_.erase(free_.begin() + best);
     return p;
   }
+  // free every cached block (of every device)
+  void trim() {
+    std::vector<Block> all;
+    {
+      std::lock_guard<std::mutex> l(m_);
+      all.swap(free_);
+      held_ = 0;
+    }
+    for (auto& b : all) (void)hipFree(b.p);
+  }
   void give(void* p, size_t cap) {
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) {

@@ -62,6 +62,15 @@ class PinnedCache {
     free_.erase(free_.begin() + best);
     return p;
   }
+  void trim() {
+    std::vector<std::pair<void*, size_t>> all;
+    {
+      std::lock_guard<std::mutex> l(m_);
+      all.swap(free_);
+      held_ = 0;
+    }
+    for (auto& b : all) (void)hipHostFree(b.first);
+  }
   void give(void* p, size_t cap) {
     {
       std::lock_guard<std::mutex> l(m_);
@@ -434,6 +443,18 @@ class ChunkCache {
     held_ -= out.cap;
     free_.erase(free_.begin() + best);
     return true;
+  }
+  void trim() {
+    std::vector<UploadChunk> all;
+    {
+      std::lock_guard<std::mutex> l(m_);
+      all.swap(free_);
+      held_ = 0;
+    }
+    for (auto& c : all) {
+      (void)hipHostFree(c.h);
+      (void)hipFree(c.d);
+    }
   }
   void give(const UploadChunk& c) {
     {
@@ -1027,6 +1048,12 @@ void batched_qr(Stage& sg, const std::vector<zd*>& Ms, const std::vector<int>& r
 }
 
 }  // namespace
+
+void trim_reuse_caches() {
+  ChunkCache::get().trim();
+  PinnedCache::get().trim();
+  DeviceChunkCache::get().trim();
+}
 
 // Inverses of count consecutive n x n matrices (the routine the factorization uses for the
 // pivot blocks and the top block), for the library's dense-inverse entry point.

@@ -15,6 +15,9 @@
 namespace fmmlu {
 
 // Pinned host staging memory for task descriptors; bump allocation, reset after a sync.
+// frees the device and pinned host memory that finished factorizations left for reuse
+void trim_reuse_caches();
+
 class HostStage {
  public:
   ~HostStage();

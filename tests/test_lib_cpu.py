@@ -17,6 +17,12 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_trim_caches_with_nothing_cached():
+    # no factorization has run in this process: nothing to free, no device call needed
+    fm.trim_caches()
+    fm.trim_caches()
+
+
 def _compare_trees(points, leaf):
     ot = OracleTree(points, leaf)
     gt = fm.Tree(points, leaf).export()
