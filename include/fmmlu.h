@@ -228,6 +228,22 @@ fmmlu_status fmmlu_factor_boxes(fmmlu_factor_h f, int64_t* count, int32_t* level
                                 int32_t* m, int32_t* s, int64_t* skel);
 
 /*
+ * Factors of record rec (0 <= rec < count of fmmlu_factor_boxes, elimination order), copied
+ * to host memory for inspection and testing (synchronises the device). sizes[0..2] receive
+ * r = |R|, s = |S| and s + n_N. DOF lists as original point indices: R (r entries) and S (s)
+ * in the order of the box's ID pivots, SN (s + n_N) = S followed by the near DOFs. Matrices,
+ * complex128 column-major (widened when the factorization stores complex float32):
+ *   T  (s x r)        interpolation matrix of the ID, A_{.R} ~ A_{.S} T (Section 4.1);
+ *   Xi (r x r)        X_RR^{-1}, the inverse pivot block;
+ *   L  ((s+n_N) x r)  X_{(S u N) R} X_RR^{-1};
+ *   UT ((s+n_N) x r)  U^T with U = X_RR^{-1} X_{R (S u N)}.
+ * Any output pointer may be NULL (call with only sizes first to size the buffers).
+ * Errors: ESTATE (NULL factor), EINVAL (rec out of range), EHIP.
+ */
+fmmlu_status fmmlu_factor_box_data(fmmlu_factor_h f, int64_t rec, int32_t* sizes, int64_t* R, int64_t* S,
+                                   int64_t* SN, void* T, void* Xi, void* L, void* UT);
+
+/*
  * Kernel-class profile of the factorization (only when opts.profile was set): for each of
  * the FMMLU_NKCLASS classes (0 tile assembly, 1 ID-matrix generation, 2 Householder QR,
  * 3 pivoted QR, 4 elimination GEMMs and gathers, 5 pivot-block inversion, 6 Schur update,
@@ -251,6 +267,22 @@ void fmmlu_factor_destroy(fmmlu_factor_h f);
 fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const double* w, int64_t n,
                                 double k, double eta, const int64_t* rows, int64_t nr,
                                 const int64_t* cols, int64_t nc, void* out, void* hip_stream);
+
+/*
+ * Proxy rows on the device (the generator the factorization uses for the ID matrix, Sections
+ * 5.1.1-5.1.3): with y_l = centre + radius u_l (l < ngamma), u_l the Fibonacci lattice of the
+ * unit sphere (z_l = 1 - (2l+1)/ngamma, phi_l = l pi (3 - sqrt 5)) and s = sqrt(4 pi radius^2 /
+ * ngamma), out (2 ngamma x m, complex128 column-major) holds
+ *   rows l < ngamma:        s K(y_l, x_j) sqrt(w_j)   (outgoing, source normal n_j),
+ *   rows ngamma + l:        s G(x_j, y_l) sqrt(w_j)   (incoming, single layer),
+ * for columns j = dofs[0..m) (device int64, original point indices). xyz, nrm: device SoA
+ * 3*n doubles; w: device n doubles; centre: host 3 doubles. For testing and for callers that
+ * build ID matrices. Errors: EINVAL (NULL pointers, sizes, index out of range), ENOMEM, EHIP.
+ * Synchronises the stream.
+ */
+fmmlu_status fmmlu_proxy_block(const double* xyz, const double* nrm, const double* w, int64_t n, double k,
+                               double eta, const int64_t* dofs, int64_t m, const double* centre, double radius,
+                               int32_t ngamma, void* out, void* hip_stream);
 
 /*
  * Batched dense inverse with partial pivoting (blocked Gauss-Jordan), the routine that

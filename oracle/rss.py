@@ -25,9 +25,20 @@ Readings where the paper is silent (each is also listed in the design notes):
     outside the proxy sphere. The cube is the sphere's bounding cube: it puts every box
     that meets the sphere into Q.
   * Boxes without far-field DOFs (Q and P empty) are not skeletonized at that level.
-  * Schedule within a level: by colour (ix mod 2) + 2 (iy mod 2) + 4 (iz mod 2), then by
-    Morton key. Same-colour boxes never touch, so none of them reads what another one
-    writes; their updates only add into shared near-near blocks.
+  * Order within a level: by colour (ix mod 2) + 2 (iy mod 2) + 4 (iz mod 2), then by
+    Morton key. Same-colour boxes never touch, but two of them can lie in each other's Q
+    region (one box side apart).
+  * schedule="sequential" (the paper's box-by-box loop): each box classifies the DOFs that
+    are active when its turn comes, so the redundant DOFs of a same-colour box eliminated
+    earlier in the phase are gone from its Q rows.
+    schedule="phase_start" (the colour phase as one concurrent step): every box of a colour
+    phase classifies the DOFs that were active when the phase began, so its Q rows also
+    hold the redundant DOFs R1 of an earlier same-colour box B1. Those rows are, to the ID
+    tolerance, combinations of B1's skeleton rows (B1's own ID compressed A[B1, B2] with B2
+    in B1's Q region: A[R1, B2] ~ T1^T A[S1, B2]), so the ID of the larger matrix is equally
+    valid, and nothing else differs: a box's elimination reads only blocks between its own
+    and its near DOFs, which no other box of its colour writes (same-colour boxes do not
+    touch), and the Schur updates of same-colour boxes to shared near-near blocks add.
   * Proxy surface (Section 5.1, 5.2): sphere of radius rho = 2.5R about the centre of B,
     n_gamma Fibonacci points, n_gamma = max(64, 2 (p+1)^2) with
     p = ceil(log(1/eps) / log(rho/r_B)) + ceil(k 2 r_B), r_B = (sqrt 3 / 2) R. Proxy rows
@@ -69,6 +80,21 @@ def proxy_count(side, k, eps):
     return max(64, 2 * (p + 1) ** 2)
 
 
+def proxy_block(x, nrm, w, k, eta, eps, ctr, side, idx):
+    """Proxy rows for the DOFs idx of a box with centre ctr and side `side` (Sections 5.1.1-
+    5.1.3): on n_gamma Fibonacci points y_l of the sphere of radius 2.5 side about ctr,
+    outgoing rows s K(y_l, x_j) sqrt(w_j) (source normal n_j) and incoming rows
+    s G(x_j, y_l) sqrt(w_j), s = sqrt(4 pi rho^2 / n_gamma). Returns (pout, pin, n_gamma)."""
+    rho = PROXY_RADIUS * side
+    ng = proxy_count(side, k, eps)
+    y = np.asarray(ctr, dtype=np.float64)[:, None] + rho * fibonacci_dirs(ng)
+    sg = math.sqrt(4.0 * math.pi * rho * rho / ng)
+    xb, nb, swb = x[:, idx], nrm[:, idx], np.sqrt(w[idx])
+    pout = sg * kernel.cfie(y, xb, nb, k, eta) * swb[None, :]
+    pin = sg * kernel.green(y, xb, k) * swb[None, :]
+    return pout, pin, ng
+
+
 def colour(c):
     return int(c[0] & 1) + 2 * int(c[1] & 1) + 4 * int(c[2] & 1)
 
@@ -89,6 +115,10 @@ class BoxFactor:
     m: int
     nq: int
     ngamma: int
+    margins: dict = None  # decision margins of the box's CPQR (idqr.cpqr)
+    Q: np.ndarray = None  # DOFs of the Q region (rows of the ID matrix's first two blocks)
+    M: np.ndarray = None  # the ID matrix itself (kept only with keep_id=True)
+    cols: np.ndarray = None  # the box's active DOFs: the ID matrix's columns, in order
 
     @property
     def SN(self):
@@ -99,7 +129,10 @@ class RSSFactor:
     """Dense-bookkeeping RS-S factorization of A~ (see module docstring)."""
 
     def __init__(self, x, nrm, w, k, eta, eps, leaf_size=64, check_invariant=False,
-                 brute_force_check=False, use_proxy=True):
+                 brute_force_check=False, use_proxy=True, schedule="sequential", keep_id=False):
+        if schedule not in ("sequential", "phase_start"):
+            raise ValueError(schedule)
+        self.schedule = schedule
         self.x = np.asarray(x, dtype=np.float64)
         self.nrm = np.asarray(nrm, dtype=np.float64)
         self.w = np.asarray(w, dtype=np.float64)
@@ -122,8 +155,11 @@ class RSSFactor:
                 {int(owner[i]) for i in np.nonzero(active)[0] if t.level[owner[i]] == lev},
                 key=lambda b: (colour(t.coord[b]), int(morton(*t.coord[b]))))
             nproc = 0
+            phase_colour, frozen = None, None
             for B in processed:
-                act = np.nonzero(active)[0]
+                if colour(t.coord[B]) != phase_colour:
+                    phase_colour, frozen = colour(t.coord[B]), active.copy()
+                act = np.nonzero(frozen if schedule == "phase_start" else active)[0]
                 own = owner[act]
                 ob = np.unique(own)
                 gaps = self._gaps(lev, t.coord[B], ob)
@@ -158,7 +194,7 @@ class RSSFactor:
                     blocks.append(A[np.ix_(idxP, idxB)])
                     blocks.append(A[np.ix_(idxB, idxP)].T)
                 M = np.vstack(blocks)
-                Spos, Rpos, T = interp_decomp(M, self.eps)
+                Spos, Rpos, T, margins = interp_decomp(M, self.eps, margins=True)
                 if brute_force_check and idxP.size:
                     F = np.concatenate([idxQ, idxP])
                     full = np.vstack([A[np.ix_(F, idxB)], A[np.ix_(idxB, F)].T])
@@ -169,6 +205,11 @@ class RSSFactor:
                     continue
                 f = self._eliminate(A, lev, B, idxB[Rpos], idxB[Spos], idxN, T, M.shape[0], ng)
                 f.nq = int(idxQ.size)
+                f.margins = margins
+                f.Q = idxQ
+                f.cols = idxB
+                if keep_id:
+                    f.M = M
                 self.factors.append(f)
                 active[f.R] = False
             self.level_stats.append((lev, nproc, int(active.sum())))
@@ -206,18 +247,10 @@ class RSSFactor:
         return np.maximum(g, 0)
 
     def proxy_rows(self, B, idxB):
-        """Outgoing and incoming proxy blocks (Section 5.1.1-5.1.3)."""
+        """Outgoing and incoming proxy blocks of box B (Section 5.1.1-5.1.3)."""
         t = self.tree
-        side = t.box_side(B)
-        ctr = t.box_centre(B)
-        rho = PROXY_RADIUS * side
-        ng = proxy_count(side, self.k, self.eps)
-        y = ctr[:, None] + rho * fibonacci_dirs(ng)
-        sg = math.sqrt(4.0 * math.pi * rho * rho / ng)
-        xb, nb, swb = self.x[:, idxB], self.nrm[:, idxB], np.sqrt(self.w[idxB])
-        pout = sg * kernel.cfie(y, xb, nb, self.k, self.eta) * swb[None, :]
-        pin = sg * kernel.green(y, xb, self.k) * swb[None, :]
-        return pout, pin, ng
+        return proxy_block(self.x, self.nrm, self.w, self.k, self.eta, self.eps, t.box_centre(B),
+                           t.box_side(B), idxB)
 
     def _eliminate(self, A, lev, B, R, S, N, T, mrows, ng):
         """Section 4.1: E, F from T, then L, U from X_RR; Schur update in place."""

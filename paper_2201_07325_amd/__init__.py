@@ -9,9 +9,11 @@ RuntimeError if libfmmlu.so has not been built (python -m paper_2201_07325_amd.b
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -51,6 +53,8 @@ class Info(C.Structure):
 
 
 _lib = None
+# Factor and FactorBatch objects that own a library handle (borrowed views excluded)
+_live = weakref.WeakSet()
 P = C.c_void_p
 I64 = C.c_int64
 I32 = C.c_int32
@@ -87,9 +91,11 @@ def lib():
         "fmmlu_batch_destroy": (None, [P]),
         "fmmlu_factor_info": (I32, [P, C.POINTER(Info)]),
         "fmmlu_factor_boxes": (I32, [P, C.POINTER(I64), P, P, P, P, P]),
+        "fmmlu_factor_box_data": (I32, [P, I64, P, P, P, P, P, P, P, P]),
         "fmmlu_factor_destroy": (None, [P]),
         "fmmlu_factor_profile": (I32, [P, P, P, P, P]),
         "fmmlu_kernel_block": (I32, [P, P, P, I64, D, D, P, I64, P, I64, P, P]),
+        "fmmlu_proxy_block": (I32, [P, P, P, I64, D, D, P, I64, PD, D, I32, P, P]),
         "fmmlu_trim_caches": (I32, []),
         "fmmlu_last_error": (C.c_char_p, []),
     }
@@ -210,6 +216,7 @@ class Factor:
         _check(L.fmmlu_factor(self.tree.h, _ptr(self.points), _ptr(self.normals), _ptr(self.weights),
                               self.k, self.eta, C.byref(o), _stream(), C.byref(h)))
         self.h = h
+        _live.add(self)
 
     def _apply(self, fn, b, out=None):
         import torch
@@ -317,6 +324,27 @@ class Factor:
         _check(lib().fmmlu_factor_boxes(self.h, C.byref(cnt), None, None, None, None, skel.ctypes.data))
         return {"level": level, "coord": coord, "m": m, "s": s, "skel": skel}
 
+    def box_data(self, rec):
+        """Factors of record rec (elimination order) on the host: R, S, SN as original point
+        indices (R, S in the ID's pivot order), T (s x r), Xi = X_RR^{-1} (r x r),
+        L ((s + n_N) x r) and U ((r x (s + n_N)), complex128."""
+        L_ = lib()
+        sz = np.zeros(3, np.int32)
+        _check(L_.fmmlu_factor_box_data(self.h, int(rec), sz.ctypes.data, None, None, None, None, None, None,
+                                        None))
+        r, s, nsn = (int(v) for v in sz)
+        R = np.zeros(r, np.int64)
+        S = np.zeros(s, np.int64)
+        SN = np.zeros(nsn, np.int64)
+        T = np.zeros((r, s), np.complex128)      # column-major s x r == row-major r x s
+        Xi = np.zeros((r, r), np.complex128)
+        Lt = np.zeros((r, nsn), np.complex128)
+        UT = np.zeros((r, nsn), np.complex128)
+        _check(L_.fmmlu_factor_box_data(self.h, int(rec), sz.ctypes.data, R.ctypes.data, S.ctypes.data,
+                                        SN.ctypes.data, T.ctypes.data, Xi.ctypes.data, Lt.ctypes.data,
+                                        UT.ctypes.data))
+        return {"R": R, "S": S, "SN": SN, "T": T.T.copy(), "Xi": Xi.T.copy(), "L": Lt.T.copy(), "U": UT}
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and _lib is not None and getattr(self, "_owner", None) is None:
@@ -340,10 +368,42 @@ def kernel_block(points, normals, weights, k, eta, rows, cols):
     return out.t()
 
 
+def proxy_block(points, normals, weights, k, eta, dofs, centre, radius, ngamma):
+    """Proxy rows of the ID matrix generated on the device: a complex128 CUDA tensor
+    (2 ngamma, len(dofs)), outgoing rows first, then incoming rows."""
+    import torch
+    pts = torch.as_tensor(_soa(points)).cuda()
+    n = pts.numel() // 3
+    nrm = torch.as_tensor(_soa(normals, n)).cuda()
+    w = torch.as_tensor(np.ascontiguousarray(weights, dtype=np.float64)).cuda()
+    d = torch.as_tensor(np.asarray(dofs, np.int64)).cuda()
+    c = np.ascontiguousarray(centre, dtype=np.float64)
+    out = torch.empty((d.numel(), 2 * int(ngamma)), dtype=torch.complex128, device="cuda")
+    _check(lib().fmmlu_proxy_block(P(pts.data_ptr()), P(nrm.data_ptr()), P(w.data_ptr()), n, float(k),
+                                   float(eta), P(d.data_ptr()), d.numel(), _ptr(c), float(radius), int(ngamma),
+                                   P(out.data_ptr()), _stream()))
+    return out.t()
+
+
 def trim_caches():
     """Free the device and pinned host memory that released factorizations keep for reuse
     by later ones (call between factorizations)."""
     _check(lib().fmmlu_trim_caches())
+
+
+def release_all():
+    """Destroy every factorization and batch this process still holds, then free the reuse
+    caches. Registered with atexit, so that the library makes its last HIP calls while the
+    interpreter is still running, before the runtime and any attached tools shut down."""
+    if _lib is None:
+        return
+    for obj in list(_live):
+        obj.__del__()
+    _live.clear()
+    _lib.fmmlu_trim_caches()
+
+
+atexit.register(release_all)
 
 
 def dense_inverse(a):
@@ -401,6 +461,7 @@ class FactorBatch:
         h = P()
         _check(L.fmmlu_factor_batch(cnt, trees, xyz, nrm, ws, ks, etas, C.byref(o), int(nthreads), C.byref(h)))
         self.h = h
+        _live.add(self)
         c = I32()
         off = np.zeros(cnt + 1, np.int64)
         _check(L.fmmlu_batch_info(self.h, C.byref(c), off.ctypes.data))

@@ -424,6 +424,52 @@ fmmlu_status fmmlu_factor_boxes(fmmlu_factor_h f, int64_t* count, int32_t* level
   return FMMLU_OK;
 }
 
+fmmlu_status fmmlu_factor_box_data(fmmlu_factor_h f, int64_t rec, int32_t* sizes, int64_t* R, int64_t* S,
+                                   int64_t* SN, void* T, void* Xi, void* L, void* UT) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  const auto& bx = f->f.boxes;
+  if (rec < 0 || rec >= (int64_t)bx.size()) return fail(FMMLU_EINVAL, "record index out of range");
+  return guarded([&] {
+    const FactorImpl& F = f->f;
+    const SolveBox& d = bx[(size_t)rec].dev;
+    const int64_t r = d.r, s = d.s, nsn = d.nsn;
+    if (sizes) {
+      sizes[0] = (int32_t)r;
+      sizes[1] = (int32_t)s;
+      sizes[2] = (int32_t)nsn;
+    }
+    int dev = 0;
+    FMMLU_HIP(hipGetDevice(&dev));
+    if (dev != F.device) FMMLU_HIP(hipSetDevice(F.device));
+    FMMLU_HIP(hipDeviceSynchronize());
+    auto idx = [&](const int32_t* src, int64_t cnt, int64_t* out) {
+      if (!out || cnt == 0) return;
+      std::vector<int32_t> h((size_t)cnt);
+      FMMLU_HIP(hipMemcpy(h.data(), src, sizeof(int32_t) * (size_t)cnt, hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < cnt; ++i) out[i] = F.order[(size_t)h[(size_t)i]];
+    };
+    auto mat = [&](const void* src, int64_t cnt, void* out) {
+      if (!out || cnt == 0) return;
+      zd* o = static_cast<zd*>(out);
+      if (F.f32) {
+        std::vector<zf> h((size_t)cnt);
+        FMMLU_HIP(hipMemcpy(h.data(), src, sizeof(zf) * (size_t)cnt, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < cnt; ++i) o[i] = widen(h[(size_t)i]);
+      } else {
+        FMMLU_HIP(hipMemcpy(o, src, sizeof(zd) * (size_t)cnt, hipMemcpyDeviceToHost));
+      }
+    };
+    idx(d.R, r, R);
+    idx(d.S, s, S);
+    idx(d.SN, nsn, SN);
+    mat(d.T, s * r, T);
+    mat(d.Xi, r * r, Xi);
+    mat(d.Lp, nsn * r, L);
+    mat(d.UpT, nsn * r, UT);
+    if (dev != F.device) FMMLU_HIP(hipSetDevice(dev));
+  });
+}
+
 fmmlu_status fmmlu_factor_profile(fmmlu_factor_h f, double* ms, int64_t* launches, double* flops,
                                   double* bytes) {
   if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
@@ -449,6 +495,35 @@ fmmlu_status fmmlu_dense_inverse(const void* a, int64_t n, int64_t count, void* 
   });
 }
 
+namespace {
+// SoA geometry with sqrt(w) packed on the device (original order), 7 * n doubles in a
+double* pack_geometry(DeviceArena& a, const double* xyz, const double* nrm, const double* w, int64_t n,
+                      hipStream_t st) {
+  double* p = a.alloc_n<double>(7 * (size_t)n);
+  FMMLU_HIP(hipMemcpyAsync(p, xyz, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+  FMMLU_HIP(hipMemcpyAsync(p + 3 * n, nrm, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
+  std::vector<double> hw(n), hs(n);
+  FMMLU_HIP(hipMemcpyAsync(hw.data(), w, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  FMMLU_HIP(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(hw[i] > 0.0)) throw Error(FMMLU_EINVAL, "weights must be positive");
+    hs[i] = std::sqrt(hw[i]);
+  }
+  FMMLU_HIP(hipMemcpyAsync(p + 6 * n, hs.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+  FMMLU_HIP(hipStreamSynchronize(st));
+  return p;
+}
+
+// indices must address the geometry: checked on the host before any kernel reads them
+void check_indices(const int64_t* dev, int64_t cnt, int64_t n, hipStream_t st, const char* what) {
+  std::vector<int64_t> h((size_t)cnt);
+  if (cnt) FMMLU_HIP(hipMemcpyAsync(h.data(), dev, sizeof(int64_t) * cnt, hipMemcpyDeviceToHost, st));
+  FMMLU_HIP(hipStreamSynchronize(st));
+  for (int64_t v : h)
+    if (v < 0 || v >= n) throw Error(FMMLU_EINVAL, std::string(what) + " index out of range");
+}
+}  // namespace
+
 fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const double* w, int64_t n,
                                 double k, double eta, const int64_t* rows, int64_t nr,
                                 const int64_t* cols, int64_t nc, void* out, void* hip_stream) {
@@ -456,30 +531,48 @@ fmmlu_status fmmlu_kernel_block(const double* xyz, const double* nrm, const doub
   if (n < 1 || nr < 0 || nc < 0) return fail(FMMLU_EINVAL, "bad sizes");
   return guarded([&] {
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    // pack SoA geometry with sqrt(w) on the device (original order)
     DeviceArena a(size_t(8) << 20);
-    double* p = a.alloc_n<double>(7 * (size_t)n);
-    FMMLU_HIP(hipMemcpyAsync(p, xyz, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
-    FMMLU_HIP(hipMemcpyAsync(p + 3 * n, nrm, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st));
-    std::vector<double> hw(n), hs(n);
-    FMMLU_HIP(hipMemcpyAsync(hw.data(), w, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-    FMMLU_HIP(hipStreamSynchronize(st));
-    for (int64_t i = 0; i < n; ++i) {
-      if (!(hw[i] > 0.0)) throw Error(FMMLU_EINVAL, "weights must be positive");
-      hs[i] = std::sqrt(hw[i]);
-    }
-    FMMLU_HIP(hipMemcpyAsync(p + 6 * n, hs.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
-    // indices must address the geometry: checked on the host before any kernel reads them
-    std::vector<int64_t> hr(nr), hc(nc);
-    if (nr) FMMLU_HIP(hipMemcpyAsync(hr.data(), rows, sizeof(int64_t) * nr, hipMemcpyDeviceToHost, st));
-    if (nc) FMMLU_HIP(hipMemcpyAsync(hc.data(), cols, sizeof(int64_t) * nc, hipMemcpyDeviceToHost, st));
-    FMMLU_HIP(hipStreamSynchronize(st));
-    for (int64_t v : hr)
-      if (v < 0 || v >= n) throw Error(FMMLU_EINVAL, "row index out of range");
-    for (int64_t v : hc)
-      if (v < 0 || v >= n) throw Error(FMMLU_EINVAL, "column index out of range");
+    double* p = pack_geometry(a, xyz, nrm, w, n, st);
+    check_indices(rows, nr, n, st, "row");
+    check_indices(cols, nc, n, st, "column");
     DevGeom g{p, n, k, eta};
     launch_block(g, rows, nr, cols, nc, static_cast<zd*>(out), st);
+    FMMLU_HIP(hipStreamSynchronize(st));
+  });
+}
+
+fmmlu_status fmmlu_proxy_block(const double* xyz, const double* nrm, const double* w, int64_t n, double k,
+                               double eta, const int64_t* dofs, int64_t m, const double* centre, double radius,
+                               int32_t ngamma, void* out, void* hip_stream) {
+  if (!xyz || !nrm || !w || !dofs || !centre || !out) return fail(FMMLU_EINVAL, "NULL pointer");
+  if (n < 1 || m < 1 || m > (int64_t(1) << 30) || ngamma < 1 || ngamma > (1 << 24))
+    return fail(FMMLU_EINVAL, "bad sizes");
+  if (!(radius > 0.0) || !std::isfinite(radius)) return fail(FMMLU_EINVAL, "radius must be positive");
+  return guarded([&] {
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    DeviceArena a(size_t(8) << 20);
+    double* p = pack_geometry(a, xyz, nrm, w, n, st);
+    check_indices(dofs, m, n, st, "dof");
+    IdTask t{};
+    t.M = static_cast<zd*>(out);
+    t.rows = 2 * ngamma;
+    t.m = (int32_t)m;
+    t.nq = 0;
+    t.ngamma = ngamma;
+    t.nseg = 0;
+    t.seg_off = 0;
+    t.dof_off = 0;
+    t.cx = centre[0];
+    t.cy = centre[1];
+    t.cz = centre[2];
+    t.radius = radius;
+    t.wgamma = std::sqrt(4.0 * M_PI * radius * radius / ngamma);
+    t.unit_begin = 0;
+    const int64_t units = int64_t((t.rows + 63) / 64) * ((m + 63) / 64);
+    IdTask* dt = a.alloc_n<IdTask>(1);
+    FMMLU_HIP(hipMemcpyAsync(dt, &t, sizeof(IdTask), hipMemcpyHostToDevice, st));
+    DevGeom g{p, n, k, eta};
+    launch_build_idmatrix(g, dt, 1, units, nullptr, dofs, nullptr, false, st);
     FMMLU_HIP(hipStreamSynchronize(st));
   });
 }

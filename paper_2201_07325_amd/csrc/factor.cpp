@@ -10,12 +10,17 @@
 //
 // Per level: tiles are assembled (copied from the previous level's tiles restricted to the
 // surviving skeletons, or generated), then the level's boxes are processed in eight colour
-// phases (parity of the integer box coordinates). Same-colour boxes never touch, so within
-// a phase nothing one box writes is read by another; their Schur updates to shared
-// near-near tiles are summed by one output-stationary GEMM task per destination tile.
+// phases (parity of the integer box coordinates), each phase as one concurrent step: every
+// box classifies the DOFs that are live when the phase begins. Same-colour boxes never touch,
+// so no box's elimination reads a block another box of its phase writes, and their Schur
+// updates to shared near-near tiles are summed by one output-stationary GEMM task per
+// destination tile. Two same-colour boxes can lie in each other's Q region, though: the Q
+// rows of one then still hold the other's redundant DOFs, rows that its own ID has shown to
+// be combinations of its skeleton rows to the tolerance, so both IDs stay valid.
 // Within a phase:
 //   1. ID matrix M = [A_QB ; A_BQ^T ; proxy outgoing ; proxy incoming]  (Section 5.1.3)
-//   2. blocked Householder QR of M -> R;  greedy CPQR of R -> S, R, T  (Section 4.1)
+//   2. greedy CPQR of M -> S, R, T (Section 4.1): pivoted Cholesky of the Gram matrix M^H M
+//      (eps >= 1e-7), or blocked Householder QR of M then column pivoting on R
 //   3. gathers and GEMMs for X_RR, X_{(S u N) R}, X_{R (S u N)}       (Section 4.1)
 //   4. Gauss-Jordan inversion of X_RR, panels L = X_{.R} X_RR^{-1}, U = X_RR^{-1} X_{R.}
 //   5. Schur update of the near-near tiles with X_{.R} U

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import dense
 
 pytestmark = pytest.mark.gpu
 
@@ -60,6 +61,25 @@ def test_blocked_solves_match_single_columns(precision):
         worst = max(worst, float(torch.linalg.norm(r) / torch.linalg.norm(B[:, c])))
     say(f"precision {precision}: worst relative residual of 9 blocked columns {worst:.2e}")
     assert worst < (10 * eps if precision == 0 else 1e-3)
+
+
+def test_blocked_solves_match_oracle_dense_lu():
+    """Eleven columns (a block of eight and a ragged block of three), forward and adjoint,
+    against the oracle's dense LU column by column (<= 10 eps)."""
+    s = synth.unit_sphere(3000)
+    f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=s.eps)
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    lu = dense.DenseLU(a)
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((s.n, 11)) + 1j * rng.standard_normal((s.n, 11))
+    B[:, 0] = np.sqrt(s.weights) * synth.point_source_data(s.points, s.k)
+    Bd = torch.as_tensor(B).cuda()
+    for adjoint in (False, True):
+        X = (f.solve_adjoint(Bd) if adjoint else f.solve(Bd)).cpu().numpy()
+        ref = lu.solve_adjoint(B) if adjoint else lu.solve(B)
+        errs = np.linalg.norm(X - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        say(f"adjoint {adjoint}: worst column error vs dense LU {errs.max():.2e}")
+        assert errs.max() <= 10 * s.eps
 
 
 def test_blocked_solve_in_place_and_zero_columns():
