@@ -331,6 +331,10 @@ def main():
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out), flush=True)
+    # last HIP calls of the library while the interpreter runs: factors destroyed, caches freed
+    f = x = xr = XB = None
+    fm.release_all()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
