@@ -157,6 +157,21 @@ fmmlu_status fmmlu_solve_adjoint(fmmlu_factor_h f, const void* b, void* x, int64
 fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, void* hip_stream);
 
 /*
+ * Allocation-free variant of fmmlu_matvec, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same operation, arguments and kernels as fmmlu_matvec, but its scratch (the permuted
+ * input, the tree-order result and the source-slice partial sums: (2 + s) * n complex128
+ * entries, s <= 16 slices) lives in a static device array of 64 MiB that the library holds
+ * on each GPU it runs on until the process ends; nothing is allocated or freed. n up to
+ * about 400,000 fits at any slice count (n = 1,000,000 uses one slice: 48 MB); a larger
+ * need returns FMMLU_EINVAL. The current device must be the factor's device (EINVAL
+ * otherwise). Asynchronous on hip_stream (no synchronisation). Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (different streams or
+ * host threads) race and must be serialised by the caller.
+ */
+fmmlu_status fmmlu_matvec_noalloc(fmmlu_factor_h f, int32_t op, const void* x, void* y, void* hip_stream);
+
+/*
  * Far-field pattern operator (Section 6.3's far-field pattern F[u], defined by
  * u(x) = e^{ikr}/r F(x^) + O(1/r^2), of the potential u = sum_j K(x, x_j) sqrt(w_j) sigma~_j;
  * the form below follows from the large-|x| limit of K):

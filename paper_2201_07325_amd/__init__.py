@@ -80,6 +80,7 @@ def lib():
         "fmmlu_solve": (I32, [P, P, P, I64, P]),
         "fmmlu_solve_adjoint": (I32, [P, P, P, I64, P]),
         "fmmlu_matvec": (I32, [P, I32, P, P, P]),
+        "fmmlu_matvec_noalloc": (I32, [P, I32, P, P, P]),
         "fmmlu_solve_refined": (I32, [P, P, P, I32, D, I32, C.POINTER(I32), PD, P]),
         "fmmlu_farfield": (I32, [P, P, I64, I32, P, P, P]),
         "fmmlu_dense_inverse": (I32, [P, I64, I64, P, P]),

@@ -357,6 +357,34 @@ fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, 
   });
 }
 
+fmmlu_status fmmlu_matvec_noalloc(fmmlu_factor_h f, int32_t op, const void* x, void* y, void* hip_stream) {
+  if (!f) return fail(FMMLU_ESTATE, "factor is NULL");
+  if (!x || !y) return fail(FMMLU_EINVAL, "vector pointer is NULL");
+  if (x == y) return fail(FMMLU_EINVAL, "x and y must not alias");
+  if (op < 0 || op > 3) return fail(FMMLU_EINVAL, "op must be 0..3");
+  return guarded([&] {
+    FactorImpl& F = f->f;
+    const int64_t need = matvec_noalloc_entries(F.n);
+    if (need * (int64_t)sizeof(zd) > (int64_t)kNoallocScratchBytes)
+      throw Error(FMMLU_EINVAL, "n = " + std::to_string(F.n) + " needs " + std::to_string(need * sizeof(zd)) +
+                                    " bytes of matvec scratch; the static scratch holds " +
+                                    std::to_string(kNoallocScratchBytes));
+    int dev = 0;
+    FMMLU_HIP(hipGetDevice(&dev));
+    if (dev != F.device)
+      throw Error(FMMLU_EINVAL, "the current device (" + std::to_string(dev) + ") is not the factor's device (" +
+                                    std::to_string(F.device) + ")");
+    zd* ws = noalloc_scratch();
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    zd* xt = ws;
+    zd* yt = ws + F.n;
+    zd* part = ws + 2 * F.n;
+    launch_permute(static_cast<const zd*>(x), xt, F.order_dev, F.n, 1, st);
+    launch_matvec(F.g, op, xt, yt, part, st);
+    launch_permute(yt, static_cast<zd*>(y), F.order_dev, F.n, 0, st);
+  });
+}
+
 fmmlu_status fmmlu_farfield(fmmlu_factor_h f, const double* dirs, int64_t ndir, int32_t op, const void* in,
                             void* out, void* hip_stream) {
   if (!f) return fail(FMMLU_ESTATE, "factor is NULL");

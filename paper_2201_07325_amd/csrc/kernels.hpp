@@ -400,4 +400,12 @@ constexpr int kMatvecMaxSlices = 16;
 int matvec_slices(int64_t n);
 void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipStream_t st);
 
+// ---- allocation-free exact matvec ----
+// One file-scope device array per GPU (kNoallocScratchBytes) holds the permuted input, the
+// tree-order result and the slice partials: (2 + matvec_slices(n)) * n entries.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+int64_t matvec_noalloc_entries(int64_t n);
+// device address of the current device's array (hipGetSymbolAddress on first use per device)
+zd* noalloc_scratch();
+
 }  // namespace fmmlu

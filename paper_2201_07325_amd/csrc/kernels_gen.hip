@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "kernels.hpp"
 
@@ -353,6 +355,31 @@ void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipSt
   FMMLU_HIP(hipGetLastError());
   hipLaunchKernelGGL(matvec_sum_kernel, dim3((unsigned)((g.n + 255) / 256)), b, 0, st, part, g.n, ns, y);
   FMMLU_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------
+// Scratch of the allocation-free matvec: a file-scope device array, one copy per GPU, held
+// until the process ends. Host code never names it directly: its device address on each GPU
+// comes from hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) zd scratch[kNoallocScratchBytes / sizeof(zd)];
+
+int64_t matvec_noalloc_entries(int64_t n) { return (2 + (int64_t)matvec_slices(n)) * n; }
+
+zd* noalloc_scratch() {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static zd* ptr[kMaxDev] = {};
+  int dev = 0;
+  FMMLU_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDev) throw Error(FMMLU_EINVAL, "device ordinal " + std::to_string(dev) + " out of range");
+  std::lock_guard<std::mutex> l(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    FMMLU_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(FMMLU_EHIP, "hipGetSymbolAddress returned a null address for the matvec scratch");
+    ptr[dev] = static_cast<zd*>(p);
+  }
+  return ptr[dev];
 }
 
 }  // namespace fmmlu
