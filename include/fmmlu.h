@@ -62,13 +62,31 @@ typedef struct {
   double proxy_radius;        /* proxy sphere radius in units of the box side (Section 4.4: 2.5) */
   int32_t proxy_min_points;   /* floor on proxy points per sphere (64) */
   int32_t precision;          /* fmmlu_precision */
-  int64_t device_mem_cap;     /* bytes of device memory the factorization may hold; 0 = no cap */
+  int64_t device_mem_cap;     /* bytes of device memory the factorization may hold (all of it:
+                                 factors, tile pools, scratch, upload buffers); 0 = no cap.
+                                 Exceeding it returns FMMLU_ENOMEM */
   int32_t verbose;            /* 0 silent, 1 per-level summary on stderr */
   int32_t profile;            /* 1: time each kernel class with HIP events (fmmlu_factor_profile);
                                  2: the Schur-update class (6) only, fewer event records */
   int32_t id_route;           /* greedy CPQR route: 0 auto (Gram matrix when eps >= 1e-7, else
                                  Householder), 1 Gram matrix + pivoted Cholesky, 2 Householder QR */
-  int32_t reserved[5];
+  int32_t test_zero_pivot_block; /* failure-path testing only: -1 (default) off; r >= 0 zeroes the
+                                 pivot block X_RR of the r-th eliminated box before its inversion,
+                                 so that the factorization returns FMMLU_ESINGULAR */
+  /* Device memory. With alloc == NULL the library allocates with hipMalloc and keeps released
+   * blocks in a process-wide cache for later factorizations (fmmlu_trim_caches frees it).
+   * With alloc set, EVERY device block a factorization holds (geometry, factors, tile pools,
+   * planning scratch, upload buffers, solve and refinement workspace) comes from
+   * alloc(bytes, hip_stream, alloc_ctx) and goes back through free(ptr, hip_stream, alloc_ctx),
+   * nothing is cached by the library, and a NULL return is reported as FMMLU_ENOMEM. A block is
+   * handed to free only after the device has finished the work that used it, or with that
+   * work ordered before anything later queued on the given stream (the factorization's stream,
+   * or the null stream once fmmlu_factor has returned). Both functions must be thread-safe when
+   * fmmlu_factor_batch uses them from several threads. */
+  void* (*alloc)(size_t bytes, void* hip_stream, void* ctx);
+  void (*free)(void* ptr, void* hip_stream, void* ctx);
+  void* alloc_ctx;
+  int32_t reserved[4];
 } fmmlu_opts;
 
 /* Per-factorization statistics. */
@@ -78,7 +96,8 @@ typedef struct {
   int32_t nlevels;            /* octree levels, root = 0 */
   int32_t nboxes_factored;    /* boxes whose redundant DOFs were eliminated */
   int64_t factor_bytes;       /* device bytes held by the factors */
-  int64_t peak_bytes;         /* peak device bytes during the factorization */
+  int64_t peak_bytes;         /* peak device bytes held during the factorization: factors, tile
+                                 pools, planning scratch and upload buffers together */
   int32_t max_rank;           /* largest skeleton size |S| */
   int32_t max_block;          /* largest active DOF count m of a box */
   double t_tree, t_factor;    /* seconds (host wall clock, device synchronised) */

@@ -34,10 +34,45 @@ class FmmluError(RuntimeError):
         self.code = STATUS.get(status, str(status))
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("proxy_radius", C.c_double), ("proxy_min_points", C.c_int32),
                 ("precision", C.c_int32), ("device_mem_cap", C.c_int64), ("verbose", C.c_int32),
-                ("profile", C.c_int32), ("id_route", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("profile", C.c_int32), ("id_route", C.c_int32), ("test_zero_pivot_block", C.c_int32),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p), ("reserved", C.c_int32 * 4)]
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    """Device memory for the library from PyTorch's caching allocator (NULL on failure)."""
+    try:
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=torch.cuda.current_device(),
+                                                  stream=int(stream or 0))
+    except Exception:  # reported by the library as FMMLU_ENOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# kept alive for the life of the process: the library may call them until a factor is destroyed
+_TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+_TORCH_FREE = FREE_FN(_torch_free)
+
+
+def _set_allocator(o, allocator):
+    if allocator == "torch":
+        o.alloc, o.free, o.alloc_ctx = _TORCH_ALLOC, _TORCH_FREE, None
+    elif allocator not in (None, "library"):
+        raise ValueError("allocator must be 'torch' or 'library'")
 
 
 class Info(C.Structure):
@@ -188,11 +223,15 @@ class Factor:
 
     points, normals: (3, n) float64; weights: (n,) positive. Solves take and return
     complex128 CUDA tensors of shape (n,) or (n, nrhs) in the original point order.
+    allocator: "torch" (default) takes every device block of the factorization from PyTorch's
+    caching allocator (so torch.cuda.memory_allocated() counts it); "library" lets the
+    library hipMalloc and cache its own blocks. test_zero_pivot_block >= 0 forces a zero pivot
+    block at that eliminated box (failure-path testing).
     """
 
     def __init__(self, points, normals, weights, k, eta, eps=1e-6, leaf_size=64, tree=None,
                  proxy_radius=2.5, proxy_min_points=64, precision=0, verbose=0, mem_cap=0, profile=False,
-                 id_route=0):
+                 id_route=0, allocator="torch", test_zero_pivot_block=-1):
         L = lib()
         self.points = _soa(points)
         self.n = self.points.size // 3
@@ -213,6 +252,8 @@ class Factor:
         # True / 1: every kernel class; 2: the Schur-update class only
         o.profile = int(profile) if isinstance(profile, int) and not isinstance(profile, bool) else (1 if profile else 0)
         o.id_route = int(id_route)
+        o.test_zero_pivot_block = int(test_zero_pivot_block)
+        _set_allocator(o, allocator)
         h = P()
         _check(L.fmmlu_factor(self.tree.h, _ptr(self.points), _ptr(self.normals), _ptr(self.weights),
                               self.k, self.eta, C.byref(o), _stream(), C.byref(h)))
@@ -434,7 +475,7 @@ class FactorBatch:
     """
 
     def __init__(self, problems, eps=1e-6, leaf_size=64, nthreads=0, proxy_radius=2.5, proxy_min_points=64,
-                 id_route=0):
+                 id_route=0, precision=0, allocator="torch"):
         L = lib()
         self.problems = []
         for pts, nrm, w, k, eta in problems:
@@ -459,6 +500,8 @@ class FactorBatch:
         o.proxy_radius = float(proxy_radius)
         o.proxy_min_points = int(proxy_min_points)
         o.id_route = int(id_route)
+        o.precision = int(precision)
+        _set_allocator(o, allocator)
         h = P()
         _check(L.fmmlu_factor_batch(cnt, trees, xyz, nrm, ws, ks, etas, C.byref(o), int(nthreads), C.byref(h)))
         self.h = h

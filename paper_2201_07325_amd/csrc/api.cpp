@@ -76,6 +76,8 @@ fmmlu_opts checked_opts(fmmlu_tree_h t, const double* xyz, const double* normals
   if (!(o.proxy_radius >= 1.5 && o.proxy_radius <= 10.0)) throw Error(FMMLU_EINVAL, "proxy_radius must be in [1.5, 10]");
   if (o.proxy_min_points < 1) throw Error(FMMLU_EINVAL, "proxy_min_points must be >= 1");
   if (o.id_route < 0 || o.id_route > 2) throw Error(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
+  if ((o.alloc == nullptr) != (o.free == nullptr))
+    throw Error(FMMLU_EINVAL, "alloc and free must be given together");
   if (o.precision != FMMLU_FP64 && o.precision != FMMLU_FP32)
     throw Error(FMMLU_EINVAL, "precision must be FMMLU_FP64 or FMMLU_FP32");
   const int64_t n = t->t.n;
@@ -139,6 +141,7 @@ fmmlu_status fmmlu_default_opts(fmmlu_opts* opts) {
   opts->verbose = 0;
   opts->profile = 0;
   opts->id_route = 0;
+  opts->test_zero_pivot_block = -1;
   return FMMLU_OK;
 }
 

@@ -396,10 +396,11 @@ class DoubleArena {
   int cur_ = 0;
 
  public:
-  // the owner (Stage) drains its stream before the arenas go
-  DoubleArena() {
-    a_[0].set_recycle(true);
-    a_[1].set_recycle(true);
+  // chunks from the factorization's device memory; the owner (Stage) drains its stream before
+  // the arenas go
+  void attach(DeviceMemory* m) {
+    a_[0].set_memory(m);
+    a_[1].set_memory(m);
   }
 };
 class DoubleHostStage {
@@ -487,8 +488,18 @@ class UploadRing {
  public:
   // the owner drains the stream before the ring goes, so no copy still reads a chunk
   ~UploadRing() {
-    for (auto& c : chunks_) ChunkCache::get().give(c);
+    for (auto& c : chunks_) {
+      if (mem_ && mem_->caller_allocator()) {
+        (void)hipHostFree(c.h);
+        mem_->put(c.d, c.cap);
+      } else {
+        if (mem_) mem_->unaccount(c.cap);
+        ChunkCache::get().give(c);
+      }
+    }
   }
+  // device memory the chunks are counted in (and, with a caller allocator, allocated from)
+  void attach(DeviceMemory* m) { mem_ = m; }
   bool pending() const { return cur_ < chunks_.size() && flushed_ < used_; }
   // host and device addresses of b bytes (the caller flushes first when told to)
   bool fits(size_t b) const { return cur_ < chunks_.size() && used_ + align(b) <= chunks_[cur_].cap; }
@@ -503,14 +514,34 @@ class UploadRing {
         UploadChunk c{};
         int dev = 0;
         FMMLU_HIP(hipGetDevice(&dev));
-        if (!ChunkCache::get().take(b, dev, c)) {
+        if (mem_ && mem_->caller_allocator()) {
           c.cap = std::max(b, size_t(16) << 20);
           c.dev = dev;
           FMMLU_HIP(hipHostMalloc(&c.h, c.cap, hipHostMallocDefault));
-          if (hipMalloc(&c.d, c.cap) != hipSuccess) {
-            (void)hipGetLastError();
+          try {
+            c.d = mem_->get(c.cap, c.cap);
+          } catch (...) {
             (void)hipHostFree(c.h);
-            throw Error(FMMLU_ENOMEM, "upload buffer allocation failed");
+            throw;
+          }
+        } else {
+          if (!ChunkCache::get().take(b, dev, c)) {
+            c.cap = std::max(b, size_t(16) << 20);
+            c.dev = dev;
+            FMMLU_HIP(hipHostMalloc(&c.h, c.cap, hipHostMallocDefault));
+            if (hipMalloc(&c.d, c.cap) != hipSuccess) {
+              (void)hipGetLastError();
+              (void)hipHostFree(c.h);
+              throw Error(FMMLU_ENOMEM, "upload buffer allocation failed");
+            }
+          }
+          if (mem_) {
+            try {
+              mem_->account(c.cap);
+            } catch (...) {
+              ChunkCache::get().give(c);
+              throw;
+            }
           }
         }
         chunks_.push_back(c);
@@ -538,6 +569,7 @@ class UploadRing {
 
  private:
   static size_t align(size_t b) { return std::max<size_t>((b + 255) & ~size_t(255), 256); }
+  DeviceMemory* mem_ = nullptr;
   std::vector<UploadChunk> chunks_;
   size_t cur_ = 0, used_ = 0, flushed_ = 0;
 };
@@ -550,6 +582,12 @@ struct Stage {
   int rcur = 0;
   hipStream_t st = nullptr;
   Profiler* prof = nullptr;
+  // scratch and upload buffers counted in (and taken from) a factorization's device memory
+  void attach(DeviceMemory* m) {
+    dev.attach(m);
+    ring[0].attach(m);
+    ring[1].attach(m);
+  }
   // the buffers are freed only once the stream's work on them has finished (also when an
   // error unwinds the factorization); members are destroyed after this body runs
   ~Stage() {
@@ -1215,10 +1253,19 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   info.n = n;
   info.nlevels = tree.nlevels;
   info.precision = opts.precision;
-  if (opts.device_mem_cap > 0) arena.set_cap((size_t)opts.device_mem_cap);
-  arena.set_recycle(true);  // freed by the destructor after the device has drained
+  mem.configure(opts, st);
+  // whatever is released after this call (also when an error unwinds it) is ordered on the
+  // null stream: the caller's stream may be gone by then
+  struct StreamReset {
+    DeviceMemory& m;
+    ~StreamReset() { m.set_stream(nullptr); }
+  } stream_reset{mem};
+  arena.set_memory(&mem);  // freed by the destructor after the device has drained
+  rarena.set_memory(&mem);
+  farena.set_memory(&mem);
   Stage sg;
   sg.st = st;
+  sg.attach(&mem);
   HostPool hp((int)std::min(8u, std::max(1u, std::thread::hardware_concurrency())));
   prof.on = opts.profile != 0;
   prof.mask = opts.profile == 2 ? (1u << KC_SCHUR) : ~0u;
@@ -1276,13 +1323,14 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     std::vector<std::pair<void*, size_t>>* r;
     hipStream_t st;
     size_t* cap;
+    DeviceMemory* mem;
     ~PoolGuard() {
       (void)hipStreamSynchronize(st);
       for (int i = 0; i < 2; ++i)
-        if (p[i]) DeviceChunkCache::get().give(p[i], cap[i]);
-      for (auto& q : *r) DeviceChunkCache::get().give(q.first, q.second);
+        if (p[i]) mem->put(p[i], cap[i]);
+      for (auto& q : *r) mem->put(q.first, q.second);
     }
-  } pool_guard{pools, &retired, st, pool_cap};
+  } pool_guard{pools, &retired, st, pool_cap, &mem};
   // per-level device lists stay alive until the factorization has drained
   std::vector<std::unique_ptr<DeviceArena>> level_arenas;
   std::deque<PendingPhase> pending;  // solve records (stable addresses for the grouping jobs)
@@ -1385,21 +1433,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         pools[ps] = nullptr;
         pool_cap[ps] = 0;
         size_t got = bytes;
-        void* pp = DeviceChunkCache::get().take(bytes, got);
-        if (!pp) {
-          hipError_t e = hipMalloc(&pp, bytes);
-          if (e != hipSuccess) {
-            (void)hipGetLastError();
-            throw Error(FMMLU_ENOMEM, "tile pool allocation failed (" + std::to_string(bytes) + " bytes)");
-          }
-          got = bytes;
-        }
+        void* pp = mem.get(bytes, got);
         pools[ps] = pp;
         pool_cap[ps] = got;
       }
       pool = pools[ps];
     }
-    info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)(arena.held() + pool_elems * (int64_t)te));
     info.bytes_tiles += (double)pool_elems * (double)te;
     ht.mark(8);
     // ---- assemble: slot/idx maps, dof lists, source tables
@@ -1523,7 +1562,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       act_off[i] = (int64_t)act_cat.size();
       act_cat.insert(act_cat.end(), own[i].act.begin(), own[i].act.end());
     }
-    level_arenas.emplace_back(new DeviceArena(size_t(4) << 20));
+    level_arenas.emplace_back(new DeviceArena(size_t(4) << 20, &mem));
     DeviceArena& level_arena = *level_arenas.back();
     int64_t* act_dev = sg.up_to(level_arena, act_cat);
 
@@ -1778,7 +1817,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           FMMLU_HIP(hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
           sg.sync();
         }
-        for (auto& q : retired) DeviceChunkCache::get().give(q.first, q.second);  // its readers have finished
+        for (auto& q : retired) mem.put(q.first, q.second);  // its readers have finished
         retired.clear();
         int64_t po = nb;
         for (int i = 0; i < nb; ++i) {
@@ -1972,6 +2011,11 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             t.lda = plan[e.pi].m + plan[e.pi].nN;
             gt.push_back(t);
             outs.push_back(e.Xi64);
+            // failure-path testing: a pivot block forced to zero makes its inversion report
+            // a zero pivot (FMMLU_ESINGULAR at the end of the factorization)
+            if (opts.test_zero_pivot_block >= 0 && e.fb - boxes.data() == opts.test_zero_pivot_block)
+              FMMLU_HIP(hipMemset2DAsync(t.A, sizeof(zd) * (size_t)t.lda, 0, sizeof(zd) * (size_t)t.n, (size_t)t.n,
+                                         sg.go()));
           }
           batched_inverse(sg, gt, outs, info_dev, KC_INV);
         }
@@ -2443,7 +2487,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     if (hinfo < 0) throw Error(FMMLU_EHIP, "Gauss-Jordan panel barrier timed out");
     if (hinfo != 0) throw Error(FMMLU_ESINGULAR, "singular pivot block (X_RR or the top block)");
   }
-  info.peak_bytes = std::max<int64_t>(info.peak_bytes, (int64_t)arena.held());
+  info.peak_bytes = (int64_t)mem.peak();
   info.t_factor = std::chrono::duration<double>(Clock::now() - t0).count();
   if (opts.verbose) {
     fprintf(stderr, "[fmmlu] factor %.3f s, of which waiting on the GPU %.3f s\n", info.t_factor, sg.t_wait);

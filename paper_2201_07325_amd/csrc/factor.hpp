@@ -100,6 +100,8 @@ struct FactorImpl {
   bool f32 = false;  // tiles and stored factors in complex float32
   fmmlu_opts opts{};
   int device = 0;
+  // every device block of the factorization (declared before the arenas that return to it)
+  DeviceMemory mem;
   DeviceArena arena;  // persistent: geometry, factors, top
   double* geom = nullptr;
   int64_t* order_dev = nullptr;  // tree position -> original index
