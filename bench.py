@@ -107,6 +107,41 @@ def fp32_leg(s, bd, steps):
             "tol": 1e-10, "factor_bytes": f.info()["factor_bytes"]}
 
 
+def c5_leg(n=1_000_000):
+    """Large multiscale workload: bumpy sphere with 2,000 seeded bumps (seed 4), n = 1,000,000
+    adaptive points, k = 10, eta = k, eps = 1e-4; complex float32 factors, float64 FGMRES
+    refinement with the exact matvec to 1e-8. n / (tree + factor + refined solve), and the peak
+    device memory of the factorization against the 288 GB of one MI355X."""
+    import torch
+    import synth
+    import paper_2201_07325_amd as fm
+    t0 = time.perf_counter()
+    s = synth.bumpy_sphere(n, nbumps=2000, seed=4, k=10.0, eps=1e-4)
+    t_gen = time.perf_counter() - t0
+    log(f"c5: surface generated in {t_gen:.1f} s")
+    d = np.random.default_rng(5).standard_normal(3)
+    b = torch.as_tensor(s.weights ** 0.5 * synth.plane_wave_data(s.points, s.k, d)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t = fm.Tree(s.points, 64)
+    f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=s.eps, tree=t, precision=1)
+    torch.cuda.synchronize()
+    t_fac = time.perf_counter() - t0
+    log(f"c5: tree + factor {t_fac:.2f} s")
+    t1 = time.perf_counter()
+    x, its, rel = f.solve_refined(b, tol=1e-8, maxit=30, raise_on_fail=False)
+    torch.cuda.synchronize()
+    t_ref = time.perf_counter() - t1
+    info = f.info()
+    log(f"c5: refined solve {t_ref:.2f} s, {its} iterations, relres {rel:.2e}")
+    return {"workload": "bumpy sphere, 2000 bumps (seed 4), n=1,000,000, k=10, eta=k, eps=1e-4, "
+                        "FP32 factors + FP64 FGMRES to 1e-8, plane-wave RHS (direction seed 5)",
+            "n": s.n, "unknowns_per_s": s.n / (t_fac + t_ref), "tree_factor_s": t_fac, "refined_solve_s": t_ref,
+            "refine_iterations": its, "relres": rel, "n0": info["n0"], "factor_bytes": info["factor_bytes"],
+            "peak_bytes": info["peak_bytes"], "peak_frac_of_288GB": info["peak_bytes"] / 288e9,
+            "surface_generation_s": t_gen}
+
+
 def batched_leg(solves=20):
     """64 independent scatterers (spheres and ellipsoids, seed 3, sizes 2,000-20,000, k in
     [1, 8], eta = k, eps = 1e-5): trees + concurrent factorization timed once, then batched
@@ -161,6 +196,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=2500)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -323,6 +359,9 @@ def main():
     if not args.no_fp32:
         log("float32 factors + float64 refinement")
         out["fp32_refine"] = fp32_leg(s, bd, args.steps)
+    if not args.no_c5:
+        log("large multiscale workload (1M points)")
+        out["c5"] = c5_leg()
     if not args.no_batch:
         del f, x
         log("batched scatterers")

@@ -17,6 +17,7 @@ shape (3, n); weights have shape (n,).
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -216,6 +217,20 @@ def bumpy_sphere(
         jac = r * np.sqrt(r * r + np.sum(g * g, axis=0))
         rho = base + np.sum((s ** -2)[:, None] * np.exp(kap[:, None] * (dots - 1.0)), axis=0)
         return jac, r, g, rho
+
+    surface_one = surface
+    if nbumps > 500:
+        # many bumps: the (bumps x samples) arrays are evaluated in fixed column blocks on
+        # host threads (same values for any thread count)
+        import concurrent.futures as cf
+
+        def surface(u):
+            blk = 16384
+            parts = [u[:, i:i + blk] for i in range(0, u.shape[1], blk)]
+            with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                res = list(ex.map(surface_one, parts))
+            return (np.concatenate([q[0] for q in res]), np.concatenate([q[1] for q in res]),
+                    np.concatenate([q[2] for q in res], axis=1), np.concatenate([q[3] for q in res]))
 
     pts, nrm, dv, jsum, jcount = [], [], [], 0.0, 0
     probe = draw(100_000)
