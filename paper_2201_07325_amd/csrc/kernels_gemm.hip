@@ -8,9 +8,10 @@
 // 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16, with the real and imaginary parts
 // accumulated separately: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br (four real MFMAs per
 // complex block and k-step of 4). K is staged through LDS in steps of 16, as separate real
-// and imaginary planes, with the next step's global loads issued before the current step's
-// MFMAs. MFMA operand layout (16 x 16 x 4, float64): lane l supplies A[l % 16][l / 16] and
-// B[l / 16][l % 16]; it holds D[l / 16 + 4 r][l % 16] (float64) or D[4 (l / 16) + r][l % 16]
+// and imaginary planes; for float32 with eight wavefronts the global loads run two steps ahead
+// of the step in LDS (two register sets used in turn), so each load has two steps of the
+// shorter float32 MFMAs to arrive (one step ahead otherwise). MFMA operand layout (16 x 16 x
+// 4, float64): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it holds D[l / 16 + 4 r][l % 16] (float64) or D[4 (l / 16) + r][l % 16]
 // (float32) in accumulator element r.
 #include <hip/hip_runtime.h>
 
@@ -128,8 +129,9 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
     }
     return s;
   };
-  zd ra[NQ], rb[NQ];  // next step's global values
-  auto load = [&](const GemmSeg& sg, int k0, int kend) {
+  // global values of the two steps ahead of the one in LDS (two register sets, used in turn)
+  zd ra0[NQ], rb0[NQ], ra1[NQ], rb1[NQ];
+  auto load = [&](zd(&ra)[NQ], zd(&rb)[NQ], const GemmSeg& sg, int k0, int kend) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tid + GT * q;
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
       rb[q] = w;
     }
   };
-  auto store = [&]() {
+  auto store = [&](const zd(&ra)[NQ], const zd(&rb)[NQ]) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tid + GT * q;
@@ -179,20 +181,7 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
       Bsi[kb][j] = (R)rb[q].im;
     }
   };
-  GemmSeg cur;
-  int kb0, ke0;
-  int cs = next_seg(0, cur, kb0, ke0);
-  int ck = kb0;
-  if (cs < t.nseg) load(cur, ck, ke0);
-  while (cs < t.nseg) {
-    // position of the next step
-    GemmSeg nxt = cur;
-    int ns = cs, nk = ck + BK, ne = ke0;
-    if (nk >= ke0) ns = next_seg(cs + 1, nxt, nk, ne);
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (ns < t.nseg) load(nxt, nk, ne);
+  auto compute = [&]() {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4), cl = lane & 15;
@@ -219,10 +208,73 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
           ci[a][b] = M::mma(ai[a], br[b], ci[a][b]);
         }
     }
-    cs = ns;
-    ck = nk;
-    ke0 = ne;
-    cur = nxt;
+  };
+  if constexpr (NWV == 4 || sizeof(R) == 8) {
+    // four wavefronts hold twice the accumulators, and a float64 MFMA step is long enough to
+    // cover the loads: one register set, loads one step ahead (a second set would cost one of
+    // the six wavefronts per SIMD)
+    GemmSeg cur;
+    int kb0, ke0;
+    int cs = next_seg(0, cur, kb0, ke0);
+    int ck = kb0;
+    if (cs < t.nseg) load(ra0, rb0, cur, ck, ke0);
+    while (cs < t.nseg) {
+      // position of the next step
+      GemmSeg nxt = cur;
+      int ns = cs, nk = ck + BK, ne = ke0;
+      if (nk >= ke0) ns = next_seg(cs + 1, nxt, nk, ne);
+      __syncthreads();
+      store(ra0, rb0);
+      __syncthreads();
+      if (ns < t.nseg) load(ra0, rb0, nxt, nk, ne);
+      compute();
+      cs = ns;
+      ck = nk;
+      ke0 = ne;
+      cur = nxt;
+    }
+  } else {
+    // total K steps over the segments; the load cursor runs two steps ahead of the LDS copy
+    int nsteps = 0;
+    for (int q = 0; q < t.nseg; ++q) {
+      int b, e;
+      krange(segs[t.seg_begin + q], b, e);
+      if (b < e) nsteps += (e - b + BK - 1) / BK;
+    }
+    GemmSeg lg;
+    int lk, le;
+    int ls = next_seg(0, lg, lk, le);
+    auto advance = [&]() {
+      lk += BK;
+      if (lk >= le) ls = next_seg(ls + 1, lg, lk, le);
+    };
+    if (nsteps > 0) {
+      load(ra0, rb0, lg, lk, le);
+      advance();
+    }
+    if (nsteps > 1) {
+      load(ra1, rb1, lg, lk, le);
+      advance();
+    }
+    for (int st = 0; st < nsteps; st += 2) {
+      __syncthreads();
+      store(ra0, rb0);
+      __syncthreads();
+      if (st + 2 < nsteps) {
+        load(ra0, rb0, lg, lk, le);
+        advance();
+      }
+      compute();
+      if (st + 1 >= nsteps) break;
+      __syncthreads();
+      store(ra1, rb1);
+      __syncthreads();
+      if (st + 3 < nsteps) {
+        load(ra1, rb1, lg, lk, le);
+        advance();
+      }
+      compute();
+    }
   }
   const zd alpha{t.alpha_re, t.alpha_im};
   CT* Cb = static_cast<CT*>(t.C) + (int64_t)kc * t.part_stride;
