@@ -208,8 +208,11 @@ fmmlu_status fmmlu_farfield(fmmlu_factor_h f, const double* dirs, int64_t ndir, 
  * Iterative refinement (Section 7's use of a low-precision direct solver as a
  * preconditioner): right-preconditioned restarted GMRES in float64 on A~ (adjoint != 0:
  * on A~^H) with the exact matvec above, preconditioned by fmmlu_solve (fmmlu_solve_adjoint).
- * b, x: device complex128 vectors of length n. x is overwritten. Stops when
- * ||b - A~ x|| <= tol ||b|| or after maxit iterations (FMMLU_ENOCONV; *relres and *iters
+ * b, x: device complex128 vectors of length n. x is overwritten. Starts from x0 = 0 (the
+ * first step applies the factored inverse to b); each iteration is one factored-inverse
+ * application and one exact product. Stops when the true residual, recomputed with the
+ * exact product after each restart cycle or reached tolerance, satisfies
+ * ||b - A~ x|| <= tol ||b||, or after maxit iterations (FMMLU_ENOCONV; *relres and *iters
  * still reported). Synchronises the stream.
  */
 fmmlu_status fmmlu_solve_refined(fmmlu_factor_h f, const void* b, void* x, int32_t adjoint,

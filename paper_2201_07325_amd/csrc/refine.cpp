@@ -58,15 +58,24 @@ bool FactorImpl::refine(const zd* b, zd* x, bool adjoint, double tol, int maxit,
     *relres_out = 0.0;
     return true;
   }
-  // initial guess: one application of the factored inverse
-  precond(b, x);
+  // x0 = 0, so r0 = b needs no product with A~; the first Arnoldi step applies the factored
+  // inverse to b (what an initial guess x0 = A_f^{-1} b would cost, without its residual)
+  FMMLU_HIP(hipMemsetAsync(x, 0, sizeof(zd) * n, st));
   int iters = 0;
   double relres = 1.0;
+  bool first = true;
   for (;;) {
     // true residual of the current iterate; the loop ends only here
-    matvec(op, x, w, st);
-    launch_sub(b, w, r, n, st);
-    const double beta = std::sqrt(std::abs(dotc(r, r, n, part, st)));
+    double beta;
+    if (first) {
+      FMMLU_HIP(hipMemcpyAsync(r, b, sizeof(zd) * n, hipMemcpyDeviceToDevice, st));
+      beta = bnorm;
+      first = false;
+    } else {
+      matvec(op, x, w, st);
+      launch_sub(b, w, r, n, st);
+      beta = std::sqrt(std::abs(dotc(r, r, n, part, st)));
+    }
     relres = beta / bnorm;
     if (relres <= tol || iters >= maxit) break;
     launch_scal_copy(zd{1.0 / beta, 0.0}, r, V, n, st);
