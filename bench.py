@@ -64,10 +64,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_sample=2500):
+def cpu_baseline(n_sample=4000):
     """The oracle (dense-bookkeeping RS-S, NumPy/SciPy) on a bounded sample of the same
     recipe: the graded ellipsoid with n_sample points, same k, eta, eps; tree + factor +
-    solve timed on the host."""
+    solve timed on the host. cores = the BLAS threads its products ran on (its other steps
+    are single-threaded NumPy); the host's available cores are reported beside it."""
     import synth
     from oracle import rss
     try:
@@ -75,6 +76,7 @@ def cpu_baseline(n_sample=2500):
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
+    avail = len(os.sched_getaffinity(0))
     s = synth.graded_ellipsoid(n_sample, seed=2)
     b = np.sqrt(s.weights) * synth.point_source_data(s.points, s.k)
     t0 = time.perf_counter()
@@ -82,29 +84,98 @@ def cpu_baseline(n_sample=2500):
     f.solve(b)
     dt = time.perf_counter() - t0
     return {"value": n_sample / dt, "unit": "unknowns/s", "cores": int(threads), "kind": "oracle",
+            "host_cores_available": avail,
             "sample": f"graded ellipsoid n={n_sample} (same recipe, seed 2), tree+factor+solve in {dt:.1f} s"}
+
+
+def ceilings():
+    """Measured ceilings on this GPU beside the datasheet peaks: HBM bandwidth of a plain
+    2 GiB device copy (bytes read + written per second), and the rate of a large float64 and
+    complex128 library GEMM (torch.matmul, 8192^3; 8 flops per complex multiply-add)."""
+    import torch
+    out = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    src = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    ev0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev1.record()
+    ev1.synchronize()
+    out["hbm_copy_GBps"] = 5 * 2 * src.numel() * 8 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    del src, dst
+    for name, dt, fl in (("fp64_gemm_TFLOPs", torch.float64, 2), ("c128_gemm_TFLOPs", torch.complex128, 8)):
+        n = 8192 if dt == torch.float64 else 4096
+        a = torch.randn(n, n, dtype=dt, device="cuda")
+        b = torch.randn(n, n, dtype=dt, device="cuda")
+        torch.matmul(a, b)
+        ev0.record()
+        for _ in range(3):
+            torch.matmul(a, b)
+        ev1.record()
+        ev1.synchronize()
+        out[name] = 3 * fl * n ** 3 / (ev0.elapsed_time(ev1) / 1e3) / 1e12
+        del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def golden_errors(f, bd, x, n):
+    """Errors against the oracle's reference solutions of this workload (x* = A~^{-1} b and
+    y* = A~^{-H} b from float64 GMRES with the exact matvec to relres <= 1e-13, written by
+    tests/golden/make_ellipsoid50k_reference.py): relative 2-norm and max-entry errors of the
+    factored solve, of the adjoint solve and of the refined solve."""
+    path = os.path.join(ROOT, "tests", "golden", "ellipsoid50k_reference.npz")
+    if n != 50_000 or not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    xs, ys = ref["x"], ref["y"]
+
+    def err(v, r):
+        v = v.cpu().numpy()
+        return {"rel2": float(np.linalg.norm(v - r) / np.linalg.norm(r)),
+                "max": float(np.max(np.abs(v - r)) / np.max(np.abs(r)))}
+    out = {"solve": err(x, xs), "adjoint": err(f.solve_adjoint(bd), ys)}
+    return out
 
 
 def fp32_leg(s, bd, steps):
     """Same workload with complex float32 tiles and factors (float64 ID pivoting and pivot
     inverses), each step followed by float64 FGMRES refinement to 1e-10 with the exact matvec:
-    n / (tree + factor + refined solve)."""
+    n / (tree + factor + refined solve). Also the tree + factor time alone, the per-class
+    breakdown of one extra profiled factorization, and the refined solution's error against
+    the oracle's reference."""
     import torch
     import paper_2201_07325_amd as fm
-    times, its, rel = [], 0, 0.0
-    f = None
+    times, tfac, its, rel = [], [], 0, 0.0
+    f = x = None
     for k in range(steps + 1):  # the first pass warms up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         t = fm.Tree(s.points, 64)
         f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=s.eps, tree=t, precision=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         x, its, rel = f.solve_refined(bd, tol=1e-10, maxit=50, raise_on_fail=False)
         torch.cuda.synchronize()
         if k > 0:
             times.append(time.perf_counter() - t0)
+            tfac.append(t1 - t0)
     dt = float(np.mean(times))
-    return {"unknowns_per_s": s.n / dt, "ms_per_step": dt * 1e3, "refine_iterations": its, "relres": rel,
-            "tol": 1e-10, "factor_bytes": f.info()["factor_bytes"]}
+    out = {"unknowns_per_s": s.n / dt, "ms_per_step": dt * 1e3, "tree_factor_ms": float(np.mean(tfac)) * 1e3,
+           "refine_iterations": its, "relres": rel, "tol": 1e-10, "factor_bytes": f.info()["factor_bytes"]}
+    path = os.path.join(ROOT, "tests", "golden", "ellipsoid50k_reference.npz")
+    if s.n == 50_000 and os.path.exists(path):
+        xs = np.load(path)["x"]
+        xv = x.cpu().numpy()
+        out["err_vs_oracle"] = {"rel2": float(np.linalg.norm(xv - xs) / np.linalg.norm(xs)),
+                                "max": float(np.max(np.abs(xv - xs)) / np.max(np.abs(xs)))}
+    del f
+    fp = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=s.eps, precision=1, profile=1)
+    out["class_ms"] = {c: round(v["ms"], 2) for c, v in fp.profile().items()}
+    return out
 
 
 def c5_leg(n=1_000_000):
@@ -193,7 +264,7 @@ def main():
     ap.add_argument("--n", type=int, default=50_000)
     ap.add_argument("--solves", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2500)
+    ap.add_argument("--cpu-sample", type=int, default=4000)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
@@ -302,6 +373,13 @@ def main():
     torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
     log(f"refined solve: {r_it} iterations, relres {r_rel:.2e}, {t_ref * 1e3:.1f} ms")
+    err_oracle = golden_errors(f, bd, x, n)
+    if err_oracle is not None:
+        xr_np = xr.cpu().numpy()
+        xs_ref = np.load(os.path.join(ROOT, "tests", "golden", "ellipsoid50k_reference.npz"))["x"]
+        err_oracle["refined"] = {"rel2": float(np.linalg.norm(xr_np - xs_ref) / np.linalg.norm(xs_ref)),
+                                 "max": float(np.max(np.abs(xr_np - xs_ref)) / np.max(np.abs(xs_ref)))}
+        log(f"error vs oracle reference: {err_oracle}")
 
     # dominant kernel class (from the fully bracketed step); its figures from the timed steps
     # when they bracketed it (the Schur update), else from that step
@@ -327,6 +405,9 @@ def main():
     roof["ms_per_step"] = d["ms"] / nsteps_d
     roof["source"] = "timed steps" if nsteps_d == args.steps else "separate fully profiled step"
     breakdown = {c: round(full[c]["ms"], 2) for c in classes}
+    # step-level roofline fraction: every class at its own bound (algorithmic flops at the FP64
+    # peak, or algorithmic bytes at HBM bandwidth, whichever is longer) over the measured step
+    ideal_ms = sum(max(full[c]["flops"] / PEAK_FP64, full[c]["bytes"] / PEAK_HBM) * 1e3 for c in classes)
 
     out = {
         "metric": METRIC,
@@ -355,6 +436,9 @@ def main():
         "factor_bytes": info["factor_bytes"],
         "class_ms_per_step": breakdown,
         "roofline": roof,
+        "step_roofline": {"ideal_ms": ideal_ms, "measured_ms": dt * 1e3, "frac": ideal_ms / (dt * 1e3),
+                          "note": "sum over kernel classes of max(flops / FP64 peak, bytes / HBM peak)"},
+        "err_vs_oracle": err_oracle,
     }
     if not args.no_fp32:
         log("float32 factors + float64 refinement")
@@ -366,6 +450,8 @@ def main():
         del f, x
         log("batched scatterers")
         out["batched"] = batched_leg()
+    log("measured ceilings")
+    out["ceilings"] = ceilings()
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
