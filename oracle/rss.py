@@ -58,7 +58,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from . import dense, kernel
-from .idqr import interp_decomp
+from .idqr import cpqr, interp_decomp
 from .tree import Tree, morton
 
 PROXY_RADIUS = 2.5
@@ -101,17 +101,20 @@ def colour(c):
 
 @dataclass
 class BoxFactor:
+    """Factors of one eliminated box. Column (outgoing) sets R, S, N with T, and row
+    (incoming) sets Rr, Sr, Nr with Tr; with shared skeletons the row sets are the column
+    sets and Tr is T."""
     level: int
     box: int
     coord: tuple
-    R: np.ndarray      # redundant DOFs (global indices), in ID pivot order
-    S: np.ndarray      # skeleton DOFs, in ID pivot order
-    N: np.ndarray      # near DOFs
-    T: np.ndarray      # s x r interpolation matrix
-    XRR: np.ndarray    # pivot block
+    R: np.ndarray      # redundant column DOFs (global indices), in ID pivot order
+    S: np.ndarray      # skeleton column DOFs, in ID pivot order
+    N: np.ndarray      # near column DOFs
+    T: np.ndarray      # s x r interpolation matrix of the columns: A_{F R} ~ A_{F S} T
+    XRR: np.ndarray    # pivot block X_{Rr R}
     lu: tuple          # LU of XRR (scipy lu_factor)
-    Lp: np.ndarray     # X_{(S u N) R} X_RR^{-1}
-    Up: np.ndarray     # X_RR^{-1} X_{R (S u N)}
+    Lp: np.ndarray     # X_{(Sr u Nr) R} X_RR^{-1}
+    Up: np.ndarray     # X_RR^{-1} X_{Rr (S u N)}
     m: int
     nq: int
     ngamma: int
@@ -119,20 +122,47 @@ class BoxFactor:
     Q: np.ndarray = None  # DOFs of the Q region (rows of the ID matrix's first two blocks)
     M: np.ndarray = None  # the ID matrix itself (kept only with keep_id=True)
     cols: np.ndarray = None  # the box's active DOFs: the ID matrix's columns, in order
+    Rr: np.ndarray = None  # row sets and row interpolation matrix: A_{Rr F} ~ Tr^T A_{Sr F}
+    Sr: np.ndarray = None
+    Nr: np.ndarray = None
+    Tr: np.ndarray = None
+    margins_r: dict = None
+
+    def __post_init__(self):
+        if self.Rr is None:
+            self.Rr, self.Sr, self.Nr, self.Tr = self.R, self.S, self.N, self.T
 
     @property
     def SN(self):
         return np.concatenate([self.S, self.N])
+
+    @property
+    def SNr(self):
+        return np.concatenate([self.Sr, self.Nr])
+
+
+def _id_at_rank(M, eps, s):
+    """Greedy CPQR ID of M's columns at rank s (at least its own eps-rank): positions of the
+    skeleton and redundant columns, T = R11^{-1} R12, and the decision margins."""
+    piv, R, s0, mg = cpqr(M, eps, margins=True)
+    if s0 < s:
+        piv, R, s0 = cpqr(M, 0.0, max_rank=s)
+    S, Rd = piv[:s].copy(), piv[s:].copy()
+    T = sla.solve_triangular(R[:s, :s], R[:s, s:M.shape[1]], lower=False) if s else \
+        np.zeros((0, M.shape[1]), dtype=np.complex128)
+    return S, Rd, T, mg
 
 
 class RSSFactor:
     """Dense-bookkeeping RS-S factorization of A~ (see module docstring)."""
 
     def __init__(self, x, nrm, w, k, eta, eps, leaf_size=64, check_invariant=False,
-                 brute_force_check=False, use_proxy=True, schedule="sequential", keep_id=False):
+                 brute_force_check=False, use_proxy=True, schedule="sequential", keep_id=False,
+                 separate=False):
         if schedule not in ("sequential", "phase_start"):
             raise ValueError(schedule)
         self.schedule = schedule
+        self.separate = bool(separate)
         self.x = np.asarray(x, dtype=np.float64)
         self.nrm = np.asarray(nrm, dtype=np.float64)
         self.w = np.asarray(w, dtype=np.float64)
@@ -145,76 +175,107 @@ class RSSFactor:
         self.level_stats = []
         self.bf_errors = []
         self.invariant_checked = 0
-        active = np.ones(self.n, dtype=bool)
+        # active rows and columns (equal as long as skeletons are shared)
+        act_r = np.ones(self.n, dtype=bool)
+        act_c = np.ones(self.n, dtype=bool)
         t = self.tree
         rank = t.rank
         for lev in range(t.nlevels - 1, 1, -1):
             anc = self._owner_map(lev)
             owner = anc[t.point_leaf]
             processed = sorted(
-                {int(owner[i]) for i in np.nonzero(active)[0] if t.level[owner[i]] == lev},
+                {int(owner[i]) for i in np.nonzero(act_r)[0] if t.level[owner[i]] == lev},
                 key=lambda b: (colour(t.coord[b]), int(morton(*t.coord[b]))))
             nproc = 0
             phase_colour, frozen = None, None
             for B in processed:
                 if colour(t.coord[B]) != phase_colour:
-                    phase_colour, frozen = colour(t.coord[B]), active.copy()
-                act = np.nonzero(frozen if schedule == "phase_start" else active)[0]
-                own = owner[act]
-                ob = np.unique(own)
+                    phase_colour, frozen = colour(t.coord[B]), (act_r.copy(), act_c.copy())
+                ar, ac = frozen if schedule == "phase_start" else (act_r, act_c)
+                rows, cols = np.nonzero(ar)[0], np.nonzero(ac)[0]
+                own_r, own_c = owner[rows], owner[cols]
+                ob = np.unique(own_r)  # owners holding active DOFs (the same for columns)
                 gaps = self._gaps(lev, t.coord[B], ob)
-                idxB = self._sorted(act[own == B], rank)
                 near_owners = [int(o) for o, g in zip(ob, gaps) if g == 0 and o != B]
                 q_owners = [int(o) for o, g in zip(ob, gaps) if g == 1]
-                p_any = any(g >= 2 for g in gaps)
-                near_owners.sort(key=lambda o: rank[t.pts[o]].min() if t.pts[o].size else 0)
-                q_owners.sort(key=lambda o: rank[t.pts[o]].min() if t.pts[o].size else 0)
-                idxN = np.concatenate([self._sorted(act[own == o], rank) for o in near_owners]
-                                      ) if near_owners else np.zeros(0, np.int64)
-                idxQ = np.concatenate([self._sorted(act[own == o], rank) for o in q_owners]
-                                      ) if q_owners else np.zeros(0, np.int64)
-                idxP = act[np.isin(own, [o for o, g in zip(ob, gaps) if g >= 2])]
-                if idxQ.size == 0 and not p_any:
+                p_owners = [int(o) for o, g in zip(ob, gaps) if g >= 2]
+                p_any = bool(p_owners)
+                key = lambda o: rank[t.pts[o]].min() if t.pts[o].size else 0  # noqa: E731
+                near_owners.sort(key=key)
+                q_owners.sort(key=key)
+
+                def gather(idx, own, owners):
+                    return (np.concatenate([self._sorted(idx[own == o], rank) for o in owners])
+                            if owners else np.zeros(0, np.int64))
+                idxB_r, idxB_c = self._sorted(rows[own_r == B], rank), self._sorted(cols[own_c == B], rank)
+                idxN_r, idxN_c = gather(rows, own_r, near_owners), gather(cols, own_c, near_owners)
+                idxQ_r, idxQ_c = gather(rows, own_r, q_owners), gather(cols, own_c, q_owners)
+                idxP_r, idxP_c = rows[np.isin(own_r, p_owners)], cols[np.isin(own_c, p_owners)]
+                if idxQ_r.size == 0 and not p_any:
                     continue
-                if check_invariant and idxP.size:
-                    ok = (np.array_equal(A[np.ix_(idxP, idxB)], self.A0[np.ix_(idxP, idxB)])
-                          and np.array_equal(A[np.ix_(idxB, idxP)], self.A0[np.ix_(idxB, idxP)]))
+                if check_invariant and idxP_r.size:
+                    ok = (np.array_equal(A[np.ix_(idxP_r, idxB_c)], self.A0[np.ix_(idxP_r, idxB_c)])
+                          and np.array_equal(A[np.ix_(idxB_r, idxP_c)], self.A0[np.ix_(idxB_r, idxP_c)]))
                     if not ok:
                         raise AssertionError(f"far-field block of box {B} was modified")
                     self.invariant_checked += 1
-                blocks = []
-                if idxQ.size:
-                    blocks.append(A[np.ix_(idxQ, idxB)])
-                    blocks.append(A[np.ix_(idxB, idxQ)].T)
+                # outgoing blocks (columns of B) and incoming blocks (rows of B, transposed)
+                out_blk, in_blk = [], []
+                if idxQ_r.size:
+                    out_blk.append(A[np.ix_(idxQ_r, idxB_c)])
+                    in_blk.append(A[np.ix_(idxB_r, idxQ_c)].T)
                 ng = 0
                 if p_any and use_proxy:
-                    pout, pin, ng = self.proxy_rows(B, idxB)
-                    blocks += [pout, pin]
+                    pout, _, ng = self.proxy_rows(B, idxB_c)
+                    _, pin, _ = self.proxy_rows(B, idxB_r)
+                    out_blk.append(pout)
+                    in_blk.append(pin)
                 elif p_any:
-                    blocks.append(A[np.ix_(idxP, idxB)])
-                    blocks.append(A[np.ix_(idxB, idxP)].T)
-                M = np.vstack(blocks)
-                Spos, Rpos, T, margins = interp_decomp(M, self.eps, margins=True)
-                if brute_force_check and idxP.size:
-                    F = np.concatenate([idxQ, idxP])
-                    full = np.vstack([A[np.ix_(F, idxB)], A[np.ix_(idxB, F)].T])
-                    err = np.linalg.norm(full[:, Rpos] - full[:, Spos] @ T, 2) if Rpos.size else 0.0
-                    self.bf_errors.append((B, err / np.linalg.norm(full, 2), Spos.size, idxB.size))
+                    out_blk.append(A[np.ix_(idxP_r, idxB_c)])
+                    in_blk.append(A[np.ix_(idxB_r, idxP_c)].T)
+                if not self.separate:
+                    # one ID of the stacked matrix [A_QB ; A_BQ^T ; proxy out ; proxy in]
+                    # (the incoming block's columns are B's rows: the same DOFs here)
+                    M = np.vstack(out_blk[:1] + in_blk[:1] + out_blk[1:] + in_blk[1:])
+                    Spos, Rpos, T, margins = interp_decomp(M, self.eps, margins=True)
+                    Spos_r, Rpos_r, Tr, margins_r = Spos, Rpos, T, margins
+                else:
+                    # separate IDs of the outgoing and incoming blocks, at a common rank (the
+                    # larger of the two eps-ranks) so that the pivot block is square
+                    Mo, Mi = np.vstack(out_blk), np.vstack(in_blk)
+                    s_o = cpqr(Mo, self.eps)[2]
+                    s_i = cpqr(Mi, self.eps)[2]
+                    srank = max(s_o, s_i)
+                    Spos, Rpos, T, margins = _id_at_rank(Mo, self.eps, srank)
+                    Spos_r, Rpos_r, Tr, margins_r = _id_at_rank(Mi, self.eps, srank)
+                    M = Mo
+                if brute_force_check and idxP_r.size:
+                    F_r, F_c = np.concatenate([idxQ_r, idxP_r]), np.concatenate([idxQ_c, idxP_c])
+                    fo = A[np.ix_(F_r, idxB_c)]
+                    fi = A[np.ix_(idxB_r, F_c)].T
+                    errs = []
+                    for full, S_, R_, T_ in ((fo, Spos, Rpos, T), (fi, Spos_r, Rpos_r, Tr)):
+                        e = np.linalg.norm(full[:, R_] - full[:, S_] @ T_, 2) if R_.size else 0.0
+                        errs.append(e / np.linalg.norm(full, 2))
+                    self.bf_errors.append((B, max(errs), Spos.size, idxB_c.size))
                 nproc += 1
                 if Rpos.size == 0:
                     continue
-                f = self._eliminate(A, lev, B, idxB[Rpos], idxB[Spos], idxN, T, M.shape[0], ng)
-                f.nq = int(idxQ.size)
-                f.margins = margins
-                f.Q = idxQ
-                f.cols = idxB
+                f = self._eliminate(A, lev, B, idxB_r[Rpos_r], idxB_r[Spos_r], idxN_r, Tr,
+                                    idxB_c[Rpos], idxB_c[Spos], idxN_c, T, ng)
+                f.nq = int(idxQ_r.size)
+                f.margins, f.margins_r = margins, margins_r
+                f.Q = idxQ_c
+                f.cols = idxB_c
                 if keep_id:
                     f.M = M
                 self.factors.append(f)
-                active[f.R] = False
-            self.level_stats.append((lev, nproc, int(active.sum())))
-        self.top = self._sorted(np.nonzero(active)[0], rank)
-        self.Att = A[np.ix_(self.top, self.top)].copy()
+                act_r[f.Rr] = False
+                act_c[f.R] = False
+            self.level_stats.append((lev, nproc, int(act_r.sum())))
+        self.top_r = self._sorted(np.nonzero(act_r)[0], rank)
+        self.top = self._sorted(np.nonzero(act_c)[0], rank)
+        self.Att = A[np.ix_(self.top_r, self.top)].copy()
         self.top_lu = sla.lu_factor(self.Att, check_finite=False)
         self.A = A
 
@@ -252,16 +313,21 @@ class RSSFactor:
         return proxy_block(self.x, self.nrm, self.w, self.k, self.eta, self.eps, t.box_centre(B),
                            t.box_side(B), idxB)
 
-    def _eliminate(self, A, lev, B, R, S, N, T, mrows, ng):
-        """Section 4.1: E, F from T, then L, U from X_RR; Schur update in place."""
-        ARR, ARS, ASR, ASS = (A[np.ix_(R, R)], A[np.ix_(R, S)], A[np.ix_(S, R)], A[np.ix_(S, S)])
-        ARN, ANR, ASN, ANS = (A[np.ix_(R, N)], A[np.ix_(N, R)], A[np.ix_(S, N)], A[np.ix_(N, S)])
-        Tt = T.T
-        XRR = ARR - Tt @ ASR - ARS @ T + Tt @ ASS @ T
-        XRS = ARS - Tt @ ASS
-        XSR = ASR - ASS @ T
-        XRN = ARN - Tt @ ASN
-        XNR = ANR - ANS @ T
+    def _eliminate(self, A, lev, B, Rr, Sr, Nr, Tr, R, S, N, T, ng):
+        """Section 4.1: row transform E with Tr on rows (Rr, Sr), column transform F with T on
+        columns (R, S), then L, U with the pivot block X_{Rr R}; the Schur complement is
+        subtracted from A_{(Sr u Nr)(S u N)} in place. With shared skeletons the row and
+        column sets coincide."""
+        Ttr = Tr.T
+        A_RR, A_RS = A[np.ix_(Rr, R)], A[np.ix_(Rr, S)]
+        A_SR, A_SS = A[np.ix_(Sr, R)], A[np.ix_(Sr, S)]
+        A_RN, A_SN = A[np.ix_(Rr, N)], A[np.ix_(Sr, N)]
+        A_NR, A_NS = A[np.ix_(Nr, R)], A[np.ix_(Nr, S)]
+        XRR = A_RR - Ttr @ A_SR - A_RS @ T + Ttr @ A_SS @ T
+        XRS = A_RS - Ttr @ A_SS
+        XSR = A_SR - A_SS @ T
+        XRN = A_RN - Ttr @ A_SN
+        XNR = A_NR - A_NS @ T
         XR_SN = np.hstack([XRS, XRN])
         XSN_R = np.vstack([XSR, XNR])
         lu = sla.lu_factor(XRR, check_finite=False)
@@ -269,22 +335,24 @@ class RSSFactor:
             raise np.linalg.LinAlgError(f"singular pivot block at box {B}")
         Up = sla.lu_solve(lu, XR_SN, check_finite=False)
         Lp = sla.lu_solve(lu, XSN_R.T, trans=1, check_finite=False).T
-        SN = np.concatenate([S, N])
-        A[np.ix_(SN, SN)] -= XSN_R @ Up
+        SNr, SN = np.concatenate([Sr, Nr]), np.concatenate([S, N])
+        A[np.ix_(SNr, SN)] -= XSN_R @ Up
         return BoxFactor(lev, B, tuple(int(v) for v in self.tree.coord[B]), R, S, N, T, XRR, lu,
-                         Lp, Up, R.size + S.size, 0, ng)
+                         Lp, Up, R.size + S.size, 0, ng, Rr=Rr, Sr=Sr, Nr=Nr, Tr=Tr)
 
     # -- application of the factors (Section 4.2) ----------------------------------------
     def solve(self, b):
-        """x = A_f^{-1} b: V_1^{-1} ... V_M^{-1} in box order (E then L), D^{-1},
-        then W_M^{-1} ... W_1^{-1} in reverse order (U then F)."""
-        x = np.array(b, dtype=np.complex128, copy=True)
+        """x = A_f^{-1} b: V_1^{-1} ... V_M^{-1} in box order (E then L, on the row sets),
+        D^{-1} (rows Rr to columns R, and the top block), then W_M^{-1} ... W_1^{-1} in reverse
+        order (U then F, on the column sets)."""
+        y = np.array(b, dtype=np.complex128, copy=True)
         for f in self.factors:
-            x[f.R] -= f.T.T @ x[f.S]
-            x[f.SN] -= f.Lp @ x[f.R]
+            y[f.Rr] -= f.Tr.T @ y[f.Sr]
+            y[f.SNr] -= f.Lp @ y[f.Rr]
+        x = np.zeros_like(y)
         for f in self.factors:
-            x[f.R] = sla.lu_solve(f.lu, x[f.R], check_finite=False)
-        x[self.top] = sla.lu_solve(self.top_lu, x[self.top], check_finite=False)
+            x[f.R] = sla.lu_solve(f.lu, y[f.Rr], check_finite=False)
+        x[self.top] = sla.lu_solve(self.top_lu, y[self.top_r], check_finite=False)
         for f in reversed(self.factors):
             x[f.R] -= f.Up @ x[f.SN]
             x[f.S] -= f.T @ x[f.R]
@@ -292,16 +360,17 @@ class RSSFactor:
 
     def solve_adjoint(self, b):
         """x = A_f^{-H} b = V_1^{-H} ... V_M^{-H} D^{-H} W_M^{-H} ... W_1^{-H} b."""
-        x = np.array(b, dtype=np.complex128, copy=True)
+        y = np.array(b, dtype=np.complex128, copy=True)
         for f in self.factors:
-            x[f.R] -= f.T.conj().T @ x[f.S]
-            x[f.SN] -= f.Up.conj().T @ x[f.R]
+            y[f.R] -= f.T.conj().T @ y[f.S]
+            y[f.SN] -= f.Up.conj().T @ y[f.R]
+        x = np.zeros_like(y)
         for f in self.factors:
-            x[f.R] = sla.lu_solve(f.lu, x[f.R], trans=2, check_finite=False)
-        x[self.top] = sla.lu_solve(self.top_lu, x[self.top], trans=2, check_finite=False)
+            x[f.Rr] = sla.lu_solve(f.lu, y[f.R], trans=2, check_finite=False)
+        x[self.top_r] = sla.lu_solve(self.top_lu, y[self.top], trans=2, check_finite=False)
         for f in reversed(self.factors):
-            x[f.R] -= f.Lp.conj().T @ x[f.SN]
-            x[f.S] -= f.T.conj() @ x[f.R]
+            x[f.Rr] -= f.Lp.conj().T @ x[f.SNr]
+            x[f.Sr] -= f.Tr.conj() @ x[f.Rr]
         return x
 
     def apply(self, v):
@@ -310,13 +379,14 @@ class RSSFactor:
         for f in self.factors:
             x[f.S] += f.T @ x[f.R]
             x[f.R] += f.Up @ x[f.SN]
+        y = np.zeros_like(x)
         for f in self.factors:
-            x[f.R] = f.XRR @ x[f.R]
-        x[self.top] = self.Att @ x[self.top]
+            y[f.Rr] = f.XRR @ x[f.R]
+        y[self.top_r] = self.Att @ x[self.top]
         for f in reversed(self.factors):
-            x[f.SN] += f.Lp @ x[f.R]
-            x[f.R] += f.T.T @ x[f.S]
-        return x
+            y[f.SNr] += f.Lp @ y[f.Rr]
+            y[f.Rr] += f.Tr.T @ y[f.Sr]
+        return y
 
     @property
     def n0(self):
@@ -326,5 +396,5 @@ class RSSFactor:
         """Stored complex entries (T, X_RR, L and U panels, top block)."""
         tot = self.top.size ** 2
         for f in self.factors:
-            tot += f.T.size + f.XRR.size + f.Lp.size + f.Up.size
+            tot += f.T.size + f.XRR.size + f.Lp.size + f.Up.size + (f.Tr.size if f.Tr is not f.T else 0)
         return tot

@@ -122,3 +122,30 @@ def test_phase_start_schedule():
     # some box of this workload has a same-colour box in its Q region eliminated earlier in
     # its phase: the two schedules then see different Q rows
     assert any(g.nq != h.nq for g, h in zip(f.factors, seq.factors))
+
+
+def test_separate_skeletons():
+    """Separate outgoing (column) and incoming (row) skeletons, each from its own ID at a
+    common rank (the larger eps-rank, so the pivot block is square): within 10 eps of dense
+    LU forward and adjoint, A_f reproduces A~ to O(eps), the far-field blocks are untouched
+    kernel values at every box, both proxy IDs are as accurate as brute-force IDs of the full
+    far field, and the common ranks are no larger in total than the shared ones (Section 4.1:
+    one T for both blocks costs a slightly larger skeleton)."""
+    s = synth.graded_ellipsoid(1500, seed=2, k=3.0, eps=1e-6)
+    kw = dict(leaf_size=32, check_invariant=True)
+    f = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, separate=True,
+                      brute_force_check=True, **kw)
+    shared = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, **kw)
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    lu = dense.DenseLU(a)
+    b = _rhs(s)
+    xs, ys = lu.solve(b), lu.solve_adjoint(b)
+    assert np.linalg.norm(f.solve(b) - xs) / np.linalg.norm(xs) <= 10 * s.eps
+    assert np.linalg.norm(f.solve_adjoint(b) - ys) / np.linalg.norm(ys) <= 10 * s.eps
+    v = np.random.default_rng(2).standard_normal(s.n) * (1 - 1j)
+    assert np.linalg.norm(f.apply(v) - a @ v) / np.linalg.norm(a @ v) <= 10 * s.eps
+    assert f.invariant_checked > 10
+    assert max(e[1] for e in f.bf_errors) <= 3 * s.eps
+    assert sum(g.S.size for g in f.factors) <= sum(g.S.size for g in shared.factors)
+    # the row and column skeletons really differ somewhere
+    assert any(not np.array_equal(np.sort(g.S), np.sort(g.Sr)) for g in f.factors)
