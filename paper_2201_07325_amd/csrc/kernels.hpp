@@ -93,16 +93,21 @@ struct GemmTask {
   int64_t part_stride;
   int64_t unit_begin;              // prefix sum of kGemmTile^2 output blocks (times K chunks)
 };
-// output blocks of one K chunk of a task: all, or the T (T + 1) / 2 on or below the diagonal
-__host__ __device__ inline int64_t gemm_task_tiles(int M, int N, int lower) {
-  const int64_t tm = (M + kGemmTile - 1) / kGemmTile, tn = (N + kGemmTile - 1) / kGemmTile;
+// output blocks (tile x tile) of one K chunk of a task: all, or the T (T + 1) / 2 on or
+// below the diagonal
+__host__ __device__ inline int64_t gemm_task_tiles_t(int M, int N, int lower, int tile) {
+  const int64_t tm = (M + tile - 1) / tile, tn = (N + tile - 1) / tile;
   return lower ? tm * (tm + 1) / 2 : tm * tn;
+}
+__host__ __device__ inline int64_t gemm_task_tiles(int M, int N, int lower) {
+  return gemm_task_tiles_t(M, N, lower, kGemmTile);
 }
 // mapped: tasks may carry rmap / cmap (a separate kernel instance); otherwise they are ignored.
 // utask (optional, nunits entries): the task of each output block, in place of a search of
 // the tasks' unit_begin prefix sums
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st, bool mapped = false, const int32_t* utask = nullptr);
+
 
 // ---- Householder panel factorization (unpivoted QR) ----
 struct QrTask {

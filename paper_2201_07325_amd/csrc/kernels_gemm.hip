@@ -296,7 +296,220 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
       }
 }
 
+// ---------------------------------------------------------------------------------------
+// The same batched GEMM for opA = N with float64 C, operands copied from global memory
+// straight into LDS (global_load_lds_dwordx4: no staging registers), two LDS buffers used in
+// turn, one barrier per K step. TM x TM output blocks (instantiated for TM = 64): eight
+// wavefronts in a 2 x 4 grid, each owning a (TM / 2) x (TM / 4) part. Per buffer: A as [16 k][TM rows] and B
+// as [TM cols][16 k] of interleaved complex values; within a B column the 16 k positions are
+// XOR-swizzled with the column's low four bits, so that the 16 lanes of an MFMA operand read
+// (16 columns, one k) fall into 16 different LDS bank groups. Loads outside the task are
+// clamped to its last row, column or k (finite values): rows and columns outside C are never
+// stored, and k positions past the segment's end are zeroed in the A operand. A segment's
+// shifted identity (ishift, unmapped launches only) is subtracted as the A operand is read from
+// LDS. LDS: 64 KB per workgroup (TM = 64), dynamic, so two workgroups share a compute unit.
+// (128 x 128 blocks, one workgroup per compute unit, measured slower on the Schur updates:
+// 37.6 vs 29.4 ms.) The output rows and columns are read through the maps before the K loop,
+// and the epilogue issues all old values of C before its stores.
+template <bool SCAT, int TM>
+__global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
+    zgemm_lds_kernel(const GemmTask* __restrict__ tasks, int ntasks, const GemmSeg* __restrict__ segs,
+                     const int32_t* __restrict__ utask) {
+  using M = Mfma<zd>;
+  constexpr int AB = TM / 32, BB = TM / 64;  // 16 x 16 MFMA blocks per wavefront: rows, columns
+  constexpr int NLA = TM / 32;               // LDS copies per wavefront and operand per K step
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  zd* lds = reinterpret_cast<zd*>(smem_raw);  // [buffer][A: 16 TM | B: TM 16]
+  int64_t u = blockIdx.x;
+  {
+    const int64_t g = gridDim.x, full = g - g % 64;
+    if (u < full) u = (u & ~int64_t(63)) + (u & 7) * 8 + ((u >> 3) & 7);
+  }
+  const GemmTask t = tasks[utask ? utask[u] : find_unit_task(tasks, ntasks, u)];
+  if (t.skip && *t.skip) return;
+  int64_t lu = u - t.unit_begin;
+  const int nbm = (t.M + TM - 1) / TM;
+  const int64_t ntiles = gemm_task_tiles_t(t.M, t.N, t.lower, TM);
+  const int kc = (int)(lu / ntiles);
+  lu -= (int64_t)kc * ntiles;
+  int row0, col0;
+  if (t.lower) {
+    int ti = (int)((sqrt(8.0 * (double)lu + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(ti + 1) * (ti + 2) / 2 <= lu) ++ti;
+    while ((int64_t)ti * (ti + 1) / 2 > lu) --ti;
+    row0 = ti * TM;
+    col0 = (int)(lu - (int64_t)ti * (ti + 1) / 2) * TM;
+  } else {
+    row0 = (int)(lu % nbm) * TM;
+    col0 = (int)(lu / nbm) * TM;
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * (TM / 2), wc = (wave >> 1) * (TM / 4);  // wavefront's part
+  const int vm = t.M - row0 - wr, vn = t.N - col0 - wc;
+  bool ua[AB], ub[BB];
+#pragma unroll
+  for (int a = 0; a < AB; ++a) ua[a] = vm > 16 * a;
+#pragma unroll
+  for (int b = 0; b < BB; ++b) ub[b] = vn > 16 * b;
+  M::V cr[AB][BB], ci[AB][BB];
+#pragma unroll
+  for (int a = 0; a < AB; ++a)
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+      cr[a][b] = M::V{0, 0, 0, 0};
+      ci[a][b] = M::V{0, 0, 0, 0};
+    }
+  // this lane's output rows and columns through the maps, read now so that the epilogue does
+  // not wait for them (-1: outside C)
+  int orow[AB][4], ocol[BB];
+#pragma unroll
+  for (int b = 0; b < BB; ++b) {
+    const int j = col0 + wc + 16 * b + (lane & 15);
+    ocol[b] = j < t.N ? ((SCAT && t.cmap) ? t.cmap[j] : j) : -1;
+  }
+#pragma unroll
+  for (int a = 0; a < AB; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = row0 + wr + 16 * a + M::row(lane, r);
+      orow[a][r] = i < t.M ? ((SCAT && t.rmap) ? t.rmap[i] : i) : -1;
+    }
+  auto krange = [&](const GemmSeg& g, int& b, int& e) {
+    b = t.kchunk > 0 ? kc * t.kchunk : 0;
+    e = t.kchunk > 0 ? min(g.K, b + t.kchunk) : g.K;
+  };
+  auto next_seg = [&](int s, GemmSeg& g, int& b, int& e) {
+    for (; s < t.nseg; ++s) {
+      g = segs[t.seg_begin + s];
+      krange(g, b, e);
+      if (b < e) break;
+    }
+    return s;
+  };
+  // this lane's copies: A copy q of the wavefront is k = c / (TM / 64), rows 64 (c % (TM / 64))
+  // + lane, with c = NLA wave + q; B copy q holds tile column j = 4 (NLA wave + q) + lane / 16
+  // at swizzled k = (lane % 16) ^ (j % 16)
+  int arow[NLA], ak[NLA], bcol[NLA], bk[NLA];
+#pragma unroll
+  for (int q = 0; q < NLA; ++q) {
+    const int c = NLA * wave + q;
+    ak[q] = c / (TM / 64);
+    arow[q] = min(row0 + 64 * (c % (TM / 64)) + lane, t.M - 1);
+    const int j = 4 * c + (lane >> 4);
+    bcol[q] = min(col0 + j, t.N - 1);
+    bk[q] = (lane & 15) ^ (j & 15);
+  }
+  auto issue = [&](int buf, const GemmSeg& g, int k0, int kend) {
+    zd* la = lds + (size_t)buf * 32 * TM;
+    zd* lb = la + 16 * TM;
+#pragma unroll
+    for (int q = 0; q < NLA; ++q) {
+      const int c = NLA * wave + q;
+      const zd* src = g.A + arow[q] + (int64_t)min(k0 + ak[q], kend - 1) * g.lda;
+      __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)(la + 64 * c), 16, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < NLA; ++q) {
+      const int c = NLA * wave + q;
+      const zd* src = g.B + min(k0 + bk[q], kend - 1) + (int64_t)bcol[q] * g.ldb;
+      __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)(lb + 64 * c), 16, 0, 0);
+    }
+  };
+  int nsteps = 0;
+  for (int q = 0; q < t.nseg; ++q) {
+    int b, e;
+    krange(segs[t.seg_begin + q], b, e);
+    if (b < e) nsteps += (e - b + BK - 1) / BK;
+  }
+  GemmSeg lg;
+  int lk, le;
+  int ls = next_seg(0, lg, lk, le);
+  // per buffer: valid k count, and the row of A whose entry at k = 0 of the step carries the
+  // shifted identity (A - E, E[ishift - 1 + k, k] = 1; -1 if none)
+  int kval[2] = {0, 0}, kdiag[2] = {-1, -1};
+  auto note = [&](int buf) {
+    kval[buf] = le - lk;
+    kdiag[buf] = lg.ishift > 0 ? lg.ishift - 1 + lk : -1;
+  };
+  if (nsteps > 0) {
+    issue(0, lg, lk, le);
+    note(0);
+    lk += BK;
+    if (lk >= le) ls = next_seg(ls + 1, lg, lk, le);
+  }
+  const int cl = lane & 15, kq = lane >> 4;
+  for (int st = 0; st < nsteps; ++st) {
+    const int buf = st & 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this wavefront's copies of step st have landed
+    __syncthreads();                // everyone's have, and step st - 1 is no longer read
+    if (st + 1 < nsteps) {
+      issue(buf ^ 1, lg, lk, le);
+      note(buf ^ 1);
+      lk += BK;
+      if (lk >= le) ls = next_seg(ls + 1, lg, lk, le);
+    }
+    const int kv = kval[buf], kd = kdiag[buf];
+    const zd* As = lds + (size_t)buf * 32 * TM;
+    const zd* Bs = As + 16 * TM;
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int k = ks + kq;
+      const bool kin = k < kv;
+      zd av[AB], bv[BB];
+#pragma unroll
+      for (int a = 0; a < AB; ++a) {
+        av[a] = As[k * TM + wr + 16 * a + cl];
+        if (!SCAT && kd >= 0 && row0 + wr + 16 * a + cl == kd + k) av[a].re -= 1.0;
+        if (!kin) av[a] = zd{0.0, 0.0};
+      }
+#pragma unroll
+      for (int b = 0; b < BB; ++b) {
+        const int c = wc + 16 * b + cl;
+        bv[b] = Bs[c * 16 + (k ^ (c & 15))];
+      }
+#pragma unroll
+      for (int a = 0; a < AB; ++a)
+#pragma unroll
+        for (int b = 0; b < BB; ++b) {
+          if (!(ua[a] && ub[b])) continue;
+          cr[a][b] = M::mma(av[a].re, bv[b].re, cr[a][b]);
+          cr[a][b] = M::mma(-av[a].im, bv[b].im, cr[a][b]);
+          ci[a][b] = M::mma(av[a].re, bv[b].im, ci[a][b]);
+          ci[a][b] = M::mma(av[a].im, bv[b].re, ci[a][b]);
+        }
+    }
+  }
+  const zd alpha{t.alpha_re, t.alpha_im};
+  zd* Cb = static_cast<zd*>(t.C) + (int64_t)kc * t.part_stride;
+#pragma unroll
+  for (int b = 0; b < BB; ++b) {
+    if (ocol[b] < 0) continue;
+    // all old values of the column block first (in flight together: the entries are
+    // distinct, which the compiler cannot see through the maps), then the stores
+    zd old[AB][4];
+    if (t.beta != 0.0) {
+#pragma unroll
+      for (int a = 0; a < AB; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          old[a][r] = orow[a][r] >= 0 ? Cb[orow[a][r] + (int64_t)ocol[b] * t.ldc] : zd{0.0, 0.0};
+    }
+#pragma unroll
+    for (int a = 0; a < AB; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (orow[a][r] < 0) continue;
+        zd v = zmul(alpha, zd{(double)cr[a][b][r], (double)ci[a][b][r]});
+        if (t.beta != 0.0) v = zadd(v, zscale(old[a][r], t.beta));
+        Cb[orow[a][r] + (int64_t)ocol[b] * t.ldc] = v;
+      }
+  }
+}
+
 }  // namespace
+
+// LDS of the direct-copy kernels: two buffers of A and B (16 K steps of TM complex each)
+constexpr size_t kLdsGemmBytes64 = 2 * 32 * 64 * sizeof(zd);
 
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st, bool mapped, const int32_t* utask) {
@@ -313,9 +526,9 @@ void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, con
       hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
   } else if (opA == 0) {
     if (mapped)
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, true, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_lds_kernel<true, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
     else
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zd, false, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_lds_kernel<false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
   } else if (opA == 1) {
     hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
   } else {

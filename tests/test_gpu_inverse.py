@@ -2,8 +2,9 @@
 pivot blocks X_RR and the top block, against LAPACK's inverse on random complex matrices.
 Sizes cover every code path: one workgroup per matrix (n <= 320, one to five rows per
 lane), the multi-launch pipeline with a single-workgroup panel, and the cooperative panel
-(n > 256 rows split over workgroups); ragged panel tails; matrices that need row exchanges
-at every step; an exactly singular matrix."""
+(n > 256 rows split over workgroups), and above 2048 rows the panel pipeline whose updates
+run as GEMMs on the matrix cores with the shifted identity folded into the A operand; ragged
+panel tails; matrices that need row exchanges at every step; an exactly singular matrix."""
 import sys
 
 import numpy as np
@@ -33,7 +34,7 @@ def _rand(rng, cnt, n):
 
 @pytest.mark.parametrize("n,cnt", [(1, 3), (7, 3), (16, 2), (17, 3), (63, 2), (64, 2), (65, 2), (100, 3),
                                    (128, 2), (129, 2), (193, 2), (256, 2), (257, 2), (300, 2), (320, 2),
-                                   (321, 2), (513, 1), (1000, 1)])
+                                   (321, 2), (513, 1), (1000, 1), (2049, 1), (2600, 1)])
 def test_inverse_matches_lapack(n, cnt):
     rng = np.random.default_rng(n)
     a = _rand(rng, cnt, n)
