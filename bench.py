@@ -38,12 +38,9 @@ PEAK_HBM = 8.0e12         # bytes/s
 # x1.0). Valid only while the listed kernel sources are unchanged (checked by hash); the
 # counts and commands are in profiles/ellipsoid50k_hbm_traffic.md.
 TRAFFIC = {
-    # counters taken on the previous revision of kernels_gemm.hip (sha256 fae053f4...); the
-    # hashed revision differs only in the launcher's wave count for the unmapped elimination
-    # products: the Schur-update instance is the same code
-    "schur_update": {"bytes": 1314936240,
+    "schur_update": {"bytes": 1260338350,
                      "sources": {"paper_2201_07325_amd/csrc/kernels_gemm.hip":
-                                 "832309604c8de73c9153257a27d34f25de2042fe7fb97e5befd81b97dd6b121c"}},
+                                 "e540a4e6bd783548b61d95aa20d39153820602192825e1b230de5eaea93b185f"}},
 }
 MFMA_CLASSES = ("householder_qr", "elimination", "schur_update", "top_block")
 
@@ -268,6 +265,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--factor-only", action="store_true",
+                    help="only the timed steps (tree + factor + one solve), for hardware-counter runs")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -317,6 +316,11 @@ def main():
         log(f"step {k} done")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    if args.factor_only:
+        print(json.dumps({"factor_only": True, "n": n, "steps": args.steps, "ms_per_step": dt * 1e3}), flush=True)
+        f = x = None
+        fm.release_all()
+        return
     info = f.info()
     # one more step, untimed, with every kernel class bracketed: the per-class breakdown and
     # the dominant class
