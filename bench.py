@@ -213,44 +213,47 @@ def c5_leg(n=1_000_000):
 def batched_leg(solves=20):
     """64 independent scatterers (spheres and ellipsoids, seed 3, sizes 2,000-20,000, k in
     [1, 8], eta = k, eps = 1e-5): trees + concurrent factorization timed once, then batched
-    fwd+adj solves (one graph replay per direction for all problems)."""
+    fwd+adj solves (one graph replay per direction for all problems). Complex float32 factors
+    (the workload's stated precision), and float64 factors beside them."""
     import torch
     import synth
     import paper_2201_07325_amd as fm
     surfs = synth.scatterer_batch()
     probs = [(s.points, s.normals, s.weights, s.k, s.eta) for s in surfs]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch = fm.FactorBatch(probs, eps=1e-5)
-    torch.cuda.synchronize()
-    t_fac = time.perf_counter() - t0
     b = np.concatenate([np.sqrt(s.weights) * synth.point_source_data(
         s.points, s.k, src=tuple(np.array([0.1, 0.2, 0.3]) * np.array(s.meta["axes"]))) for s in surfs])
     bd = torch.as_tensor(b).cuda()
-    for _ in range(3):
-        batch.solve(bd)
-        batch.solve(bd, adjoint=True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    times = []
-    for _ in range(solves):
-        ev0.record()
-        batch.solve(bd)
-        batch.solve(bd, adjoint=True)
-        ev1.record()
-        ev1.synchronize()
-        times.append(ev0.elapsed_time(ev1) / 1e3)
-    x = batch.solve(bd)
-    worst = 0.0
-    for i in range(0, batch.count, 8):  # every eighth problem: exact matvec residual
-        lo, hi = int(batch.offsets[i]), int(batch.offsets[i + 1])
-        r = batch.factor(i).matvec(x[lo:hi].contiguous()) - bd[lo:hi]
-        worst = max(worst, float(torch.linalg.norm(r) / torch.linalg.norm(bd[lo:hi])))
-    return {"workload": "64 scatterers (spheres/ellipsoids, axes U[0.5,3], n U[2000,20000], k U[1,8], "
-                        "eta=k, seed 3), eps=1e-5, FP64 factors",
-            "n_total": batch.n, "factor_s": t_fac, "unknowns_per_s": batch.n / t_fac,
-            "fwd_adj_batch_solves_per_s": 1.0 / float(np.median(times)),
-            "relres_sampled_max": worst}
+    out = {"workload": "64 scatterers (spheres/ellipsoids, axes U[0.5,3], n U[2000,20000], k U[1,8], "
+                       "eta=k, seed 3), eps=1e-5"}
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch = fm.FactorBatch(probs, eps=1e-5, precision=prec)
+        torch.cuda.synchronize()
+        t_fac = time.perf_counter() - t0
+        for _ in range(3):
+            batch.solve(bd)
+            batch.solve(bd, adjoint=True)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(solves):
+            ev0.record()
+            batch.solve(bd)
+            batch.solve(bd, adjoint=True)
+            ev1.record()
+            ev1.synchronize()
+            times.append(ev0.elapsed_time(ev1) / 1e3)
+        x = batch.solve(bd)
+        worst = 0.0
+        for i in range(0, batch.count, 8):  # every eighth problem: exact matvec residual
+            lo, hi = int(batch.offsets[i]), int(batch.offsets[i + 1])
+            r = batch.factor(i).matvec(x[lo:hi].contiguous()) - bd[lo:hi]
+            worst = max(worst, float(torch.linalg.norm(r) / torch.linalg.norm(bd[lo:hi])))
+        out[name] = {"n_total": batch.n, "factor_s": t_fac, "unknowns_per_s": batch.n / t_fac,
+                     "fwd_adj_batch_solves_per_s": 1.0 / float(np.median(times)), "relres_sampled_max": worst}
+        del batch, x
+    return out
 
 
 def main():

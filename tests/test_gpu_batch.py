@@ -64,6 +64,31 @@ def test_small_batch_matches_dense_and_single():
         assert np.linalg.norm(r) / np.linalg.norm(bi) < 10 * eps
 
 
+def test_small_batch_fp32_factors():
+    """The same six scatterers with complex float32 factors (the batched workload's stated
+    precision): every problem within 10 eps of the oracle's dense LU, forward and adjoint,
+    and bitwise equal to the problem factored alone in float32."""
+    surfs = synth.scatterer_batch(count=6, seed=3, nmin=1200, nmax=3000)
+    eps = 1e-5
+    batch = fm.FactorBatch([(s.points, s.normals, s.weights, s.k, s.eta) for s in surfs], eps=eps, nthreads=3,
+                           precision=1)
+    off = batch.offsets
+    b = np.concatenate([_rhs(s) for s in surfs])
+    x = batch.solve(torch.as_tensor(b).cuda()).cpu().numpy()
+    y = batch.solve(torch.as_tensor(b).cuda(), adjoint=True).cpu().numpy()
+    for i, s in enumerate(surfs):
+        a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+        bi = b[off[i]:off[i + 1]]
+        ex = np.linalg.norm(x[off[i]:off[i + 1]] - np.linalg.solve(a, bi)) / np.linalg.norm(np.linalg.solve(a, bi))
+        ys = np.linalg.solve(a.conj().T, bi)
+        ey = np.linalg.norm(y[off[i]:off[i + 1]] - ys) / np.linalg.norm(ys)
+        single = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=eps, precision=1)
+        xi = single.solve(torch.as_tensor(bi).cuda()).cpu().numpy()
+        say(f"fp32 problem {i}: n={s.n} err {ex:.2e} adjoint {ey:.2e}")
+        assert ex < 10 * eps and ey < 10 * eps
+        assert np.abs(xi - x[off[i]:off[i + 1]]).max() <= 1e-13 * np.abs(xi).max()
+
+
 def test_full_batch_64_scatterers_residual():
     """The 64-scatterer workload (seed 3, sizes 2,000-20,000, k in [1, 8], eps = 1e-5):
     per-problem relative residual on 200 sampled rows, (A~ x - b)[rows], with A~ x formed row
