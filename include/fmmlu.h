@@ -86,6 +86,18 @@ typedef struct {
   void* (*alloc)(size_t bytes, void* hip_stream, void* ctx);
   void (*free)(void* ptr, void* hip_stream, void* ctx);
   void* alloc_ctx;
+  /* Locally corrected quadrature (Section 5.3), optional (all NULL: none): the weight of
+   * source j at target i becomes w_j (1 + a_ij) for the listed pairs, i.e. the entry
+   * A~_ij = sqrt(w_i) K(x_i, x_j) sqrt(w_j) is multiplied by 1 + a_ij. HOST arrays in the
+   * original point order, CSR by target: for i < n the pairs (i, corr_col[e]) with factor
+   * corr_a[e], e in [corr_row_ptr[i], corr_row_ptr[i + 1]); corr_row_ptr[0] = 0. Pairs with
+   * j == i are ignored (the diagonal is 1/2); a pair listed twice is EINVAL. The library
+   * copies the table. An owner box that a listed pair links to box B while lying in B's far
+   * region P joins B's Q region for B's interpolative decomposition (its entries are not
+   * kernel values, so the proxy surface cannot stand for them). fmmlu_factor only. */
+  const int64_t* corr_row_ptr;
+  const int64_t* corr_col;
+  const double* corr_a;
   int32_t reserved[4];
 } fmmlu_opts;
 
@@ -104,7 +116,9 @@ typedef struct {
   double flops_id, flops_elim, flops_schur, flops_top;  /* algorithmic flop counts */
   double bytes_tiles;         /* bytes of pair tiles generated or merged */
   int32_t precision;
-  int32_t reserved[7];
+  int32_t nspill;             /* Q-region additions for quadrature corrections reaching a box's
+                                 far field (Section 5.3 spill-over), summed over boxes */
+  int32_t reserved[6];
 } fmmlu_info;
 
 /* Fill *opts with defaults: eps 1e-6, proxy_radius 2.5, proxy_min_points 64, FP64. */

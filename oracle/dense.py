@@ -1,8 +1,9 @@
 """Dense scaled Nystrom system and its direct solution (oracle; test infrastructure).
 
-Section 3, eqs. (disc1) and (disc3), with plain smooth weights w_ij = w_j (no local
-quadrature corrections) and alpha = 1/2:
-    A~_ii = 1/2,    A~_ij = sqrt(w_i) K(x_i, x_j) sqrt(w_j)   (i != j),
+Section 3, eqs. (disc1) and (disc3), with alpha = 1/2 and weights w_ij = w_j, or, for the
+pairs listed in an optional correction table (locally corrected quadrature, target-dependent
+weights w_ij = w_j (1 + a_ij), i != j):
+    A~_ii = 1/2,    A~_ij = sqrt(w_i) K(x_i, x_j) w_ij / sqrt(w_j)   (i != j),
 acting on the scaled unknowns sigma~_j = sqrt(w_j) sigma_j with right-hand side
 b~_i = sqrt(w_i) f(x_i). The exact discrete solution is x* = A~^{-1} b~, obtained here
 by LAPACK's partial-pivoting LU (scipy.linalg.lu_factor / lu_solve).
@@ -15,8 +16,25 @@ import scipy.linalg as sla
 from . import kernel
 
 
-def system_matrix(x, nrm, w, k, eta, rows=None, cols=None):
-    """Block A~[rows, cols] of the scaled CFIE matrix (all of it by default)."""
+def apply_corrections(blk, rows, cols, corr):
+    """Multiply the entries of the block A~[rows, cols] that the correction table lists by
+    (1 + a_ij). corr = (row_ptr, col, a): CSR by target row i, sources j, factors a_ij."""
+    if corr is None:
+        return blk
+    row_ptr, ccol, ca = corr
+    rows, cols = np.asarray(rows), np.asarray(cols)
+    cpos = {int(j): q for q, j in enumerate(cols)}
+    for p, i in enumerate(rows):
+        for e in range(int(row_ptr[i]), int(row_ptr[i + 1])):
+            q = cpos.get(int(ccol[e]))
+            if q is not None and int(ccol[e]) != int(i):
+                blk[p, q] *= 1.0 + ca[e]
+    return blk
+
+
+def system_matrix(x, nrm, w, k, eta, rows=None, cols=None, corr=None):
+    """Block A~[rows, cols] of the scaled CFIE matrix (all of it by default), with the
+    correction table's target-dependent weights when one is given."""
     n = x.shape[1]
     rows = np.arange(n) if rows is None else np.asarray(rows)
     cols = np.arange(n) if cols is None else np.asarray(cols)
@@ -31,11 +49,12 @@ def system_matrix(x, nrm, w, k, eta, rows=None, cols=None):
         blk = sw[ri][:, None] * blk * sw[cols][None, :]
         blk[same] = 0.5
         out[r0:r0 + step] = blk
-    return out
+    return apply_corrections(out, rows, cols, corr)
 
 
-def derivative_matrix(x, nrm, w, k, eta, which):
-    """dA~/dk ('k') or dA~/deta ('eta'); the diagonal 1/2 does not depend on either."""
+def derivative_matrix(x, nrm, w, k, eta, which, corr=None):
+    """dA~/dk ('k') or dA~/deta ('eta'); the diagonal 1/2 does not depend on either, and the
+    correction factors (1 + a_ij) carry over to the derivative."""
     n = x.shape[1]
     sw = np.sqrt(w)
     with np.errstate(divide="ignore", invalid="ignore"):
@@ -47,7 +66,7 @@ def derivative_matrix(x, nrm, w, k, eta, which):
             raise ValueError(which)
     m = sw[:, None] * m * sw[None, :]
     m[np.arange(n), np.arange(n)] = 0.0
-    return m
+    return apply_corrections(m, np.arange(n), np.arange(n), corr)
 
 
 def matvec(x, nrm, w, k, eta, v, adjoint=False):

@@ -48,6 +48,13 @@ Readings where the paper is silent (each is also listed in the design notes):
     not conjugate (Section 4.1, eq. proxy-split-1).
   * DOF order inside a box: tree order (the octree's point order); near DOFs listed
     owner by owner in tree order.
+  * Quadrature corrections (Section 5.3, optional): target-dependent weights w_ij =
+    w_j (1 + a_ij) for listed pairs make those entries differ from kernel values. An owner
+    that would lie in B's P region but is linked to B's active DOFs by a listed pair (either
+    direction) joins Q: its rows enter the ID explicitly instead of through the proxy
+    surface, which represents kernel values only (spill-over). Such owners are never
+    Schur-updated together with B (updates pair only owners next to a common box), so their
+    blocks are still the corrected kernel values.
 """
 from __future__ import annotations
 
@@ -158,7 +165,7 @@ class RSSFactor:
 
     def __init__(self, x, nrm, w, k, eta, eps, leaf_size=64, check_invariant=False,
                  brute_force_check=False, use_proxy=True, schedule="sequential", keep_id=False,
-                 separate=False):
+                 separate=False, corr=None, spill=True):
         if schedule not in ("sequential", "phase_start"):
             raise ValueError(schedule)
         self.schedule = schedule
@@ -169,7 +176,22 @@ class RSSFactor:
         self.k, self.eta, self.eps = float(k), float(eta), float(eps)
         self.n = self.x.shape[1]
         self.tree = Tree(self.x, leaf_size)
-        A = dense.system_matrix(self.x, self.nrm, self.w, k, eta)
+        A = dense.system_matrix(self.x, self.nrm, self.w, k, eta, corr=corr)
+        # Section 5.3: DOFs linked by a quadrature correction (either direction); an owner box
+        # linked to B that would lie in B's P region joins Q instead (spill-over)
+        self.partners = None
+        if corr is not None:
+            row_ptr, ccol, _ = corr
+            links = [set() for _ in range(self.n)]
+            for i in range(self.n):
+                for e in range(int(row_ptr[i]), int(row_ptr[i + 1])):
+                    j = int(ccol[e])
+                    if j != i:
+                        links[i].add(j)
+                        links[j].add(i)
+            self.partners = [np.array(sorted(v), dtype=np.int64) for v in links]
+        self.spill = bool(spill)
+        self.spill_count = 0
         self.A0 = A.copy() if (check_invariant or brute_force_check) else None
         self.factors: list[BoxFactor] = []
         self.level_stats = []
@@ -199,6 +221,16 @@ class RSSFactor:
                 near_owners = [int(o) for o, g in zip(ob, gaps) if g == 0 and o != B]
                 q_owners = [int(o) for o, g in zip(ob, gaps) if g == 1]
                 p_owners = [int(o) for o, g in zip(ob, gaps) if g >= 2]
+                if self.partners is not None and self.spill and p_owners:
+                    mine = np.nonzero((owner == B) & (ar | ac))[0]
+                    linked = np.unique(np.concatenate([self.partners[d] for d in mine])) if mine.size else mine
+                    linked = linked[ar[linked] | ac[linked]]
+                    lo = set(int(o) for o in owner[linked])
+                    spill_owners = [o for o in p_owners if o in lo]
+                    if spill_owners:
+                        self.spill_count += len(spill_owners)
+                        q_owners += spill_owners
+                        p_owners = [o for o in p_owners if o not in lo]
                 p_any = bool(p_owners)
                 key = lambda o: rank[t.pts[o]].min() if t.pts[o].size else 0  # noqa: E731
                 near_owners.sort(key=key)
@@ -218,6 +250,11 @@ class RSSFactor:
                           and np.array_equal(A[np.ix_(idxB_r, idxP_c)], self.A0[np.ix_(idxB_r, idxP_c)]))
                     if not ok:
                         raise AssertionError(f"far-field block of box {B} was modified")
+                    if self.partners is not None and self.spill:
+                        mineB = np.concatenate([idxB_r, idxB_c])
+                        far = set(np.concatenate([idxP_r, idxP_c]).tolist())
+                        if any(int(p_) in far for d in mineB for p_ in self.partners[d]):
+                            raise AssertionError(f"a quadrature correction links box {B} to its P region")
                     self.invariant_checked += 1
                 # outgoing blocks (columns of B) and incoming blocks (rows of B, transposed)
                 out_blk, in_blk = [], []

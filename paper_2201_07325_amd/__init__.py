@@ -42,7 +42,9 @@ class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("proxy_radius", C.c_double), ("proxy_min_points", C.c_int32),
                 ("precision", C.c_int32), ("device_mem_cap", C.c_int64), ("verbose", C.c_int32),
                 ("profile", C.c_int32), ("id_route", C.c_int32), ("test_zero_pivot_block", C.c_int32),
-                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p), ("reserved", C.c_int32 * 4)]
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
+                ("corr_row_ptr", C.c_void_p), ("corr_col", C.c_void_p), ("corr_a", C.c_void_p),
+                ("reserved", C.c_int32 * 4)]
 
 
 def _torch_alloc(nbytes, stream, ctx):
@@ -81,7 +83,7 @@ class Info(C.Structure):
                 ("max_rank", C.c_int32), ("max_block", C.c_int32), ("t_tree", C.c_double),
                 ("t_factor", C.c_double), ("flops_id", C.c_double), ("flops_elim", C.c_double),
                 ("flops_schur", C.c_double), ("flops_top", C.c_double), ("bytes_tiles", C.c_double),
-                ("precision", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("precision", C.c_int32), ("nspill", C.c_int32), ("reserved", C.c_int32 * 6)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
@@ -226,12 +228,14 @@ class Factor:
     allocator: "torch" (default) takes every device block of the factorization from PyTorch's
     caching allocator (so torch.cuda.memory_allocated() counts it); "library" lets the
     library hipMalloc and cache its own blocks. test_zero_pivot_block >= 0 forces a zero pivot
-    block at that eliminated box (failure-path testing).
+    block at that eliminated box (failure-path testing). corrections: optional (row_ptr, col, a),
+    CSR by target in the original point order: the entry (i, col) is multiplied by 1 + a
+    (locally corrected quadrature weights w_ij = w_j (1 + a_ij)).
     """
 
     def __init__(self, points, normals, weights, k, eta, eps=1e-6, leaf_size=64, tree=None,
                  proxy_radius=2.5, proxy_min_points=64, precision=0, verbose=0, mem_cap=0, profile=False,
-                 id_route=0, allocator="torch", test_zero_pivot_block=-1):
+                 id_route=0, allocator="torch", test_zero_pivot_block=-1, corrections=None):
         L = lib()
         self.points = _soa(points)
         self.n = self.points.size // 3
@@ -254,6 +258,14 @@ class Factor:
         o.id_route = int(id_route)
         o.test_zero_pivot_block = int(test_zero_pivot_block)
         _set_allocator(o, allocator)
+        keep = None
+        if corrections is not None:
+            rp, cc, ca = corrections
+            keep = (np.ascontiguousarray(rp, dtype=np.int64), np.ascontiguousarray(cc, dtype=np.int64),
+                    np.ascontiguousarray(ca, dtype=np.float64))
+            if keep[0].size != self.n + 1 or keep[1].size != keep[2].size or keep[1].size < keep[0][-1]:
+                raise ValueError("corrections: row_ptr of n + 1 entries, col and a of row_ptr[n] entries")
+            o.corr_row_ptr, o.corr_col, o.corr_a = keep[0].ctypes.data, keep[1].ctypes.data, keep[2].ctypes.data
         h = P()
         _check(L.fmmlu_factor(self.tree.h, _ptr(self.points), _ptr(self.normals), _ptr(self.weights),
                               self.k, self.eta, C.byref(o), _stream(), C.byref(h)))

@@ -78,6 +78,18 @@ fmmlu_opts checked_opts(fmmlu_tree_h t, const double* xyz, const double* normals
   if (o.id_route < 0 || o.id_route > 2) throw Error(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
   if ((o.alloc == nullptr) != (o.free == nullptr))
     throw Error(FMMLU_EINVAL, "alloc and free must be given together");
+  if ((o.corr_row_ptr == nullptr) != (o.corr_col == nullptr) || (o.corr_row_ptr == nullptr) != (o.corr_a == nullptr))
+    throw Error(FMMLU_EINVAL, "corr_row_ptr, corr_col and corr_a must be given together");
+  if (o.corr_row_ptr) {
+    const int64_t nn = t->t.n;
+    if (o.corr_row_ptr[0] != 0) throw Error(FMMLU_EINVAL, "corr_row_ptr[0] must be 0");
+    for (int64_t i = 0; i < nn; ++i)
+      if (o.corr_row_ptr[i + 1] < o.corr_row_ptr[i]) throw Error(FMMLU_EINVAL, "corr_row_ptr must not decrease");
+    for (int64_t e = 0; e < o.corr_row_ptr[nn]; ++e) {
+      if (o.corr_col[e] < 0 || o.corr_col[e] >= nn) throw Error(FMMLU_EINVAL, "corr_col entry out of range");
+      if (!std::isfinite(o.corr_a[e])) throw Error(FMMLU_EINVAL, "corr_a contains NaN or Inf");
+    }
+  }
   if (o.precision != FMMLU_FP64 && o.precision != FMMLU_FP32)
     throw Error(FMMLU_EINVAL, "precision must be FMMLU_FP64 or FMMLU_FP32");
   const int64_t n = t->t.n;
@@ -230,6 +242,8 @@ fmmlu_status fmmlu_factor_batch(int32_t count, const fmmlu_tree_h* trees, const 
   if (count < 1) return fail(FMMLU_EINVAL, "count must be >= 1");
   if (!trees || !xyz || !normals || !weights || !k || !eta) return fail(FMMLU_EINVAL, "array pointer is NULL");
   return guarded([&] {
+    if (opts && opts->corr_row_ptr)
+      throw Error(FMMLU_EINVAL, "quadrature corrections are per problem: use fmmlu_factor");
     std::vector<fmmlu_opts> os(count);
     for (int i = 0; i < count; ++i) {
       try {

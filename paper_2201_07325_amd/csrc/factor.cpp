@@ -1287,6 +1287,62 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     order_dev = sg.up_to(arena, order);
   }
   g = DevGeom{geom, n, k, eta};
+  // ---- quadrature corrections (Section 5.3): tree-order CSR by row and by column on the
+  // device; on the host, every position's partners (either direction) for the spill-over rule
+  std::vector<int64_t> adj_ptr;
+  std::vector<int32_t> adj;
+  if (opts.corr_row_ptr) {
+    std::vector<int64_t> pos(n);
+    for (int64_t p = 0; p < n; ++p) pos[order[p]] = p;
+    std::vector<std::vector<std::pair<int32_t, double>>> byrow(n), bycol(n);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t e = opts.corr_row_ptr[i]; e < opts.corr_row_ptr[i + 1]; ++e) {
+        const int64_t j = opts.corr_col[e];
+        if (j == i) continue;  // the diagonal is 1/2, not a quadrature entry
+        byrow[pos[i]].emplace_back((int32_t)pos[j], opts.corr_a[e]);
+        bycol[pos[j]].emplace_back((int32_t)pos[i], opts.corr_a[e]);
+      }
+    std::vector<int64_t> rptr(n + 1, 0), cptr(n + 1, 0);
+    std::vector<int32_t> rcol, crow;
+    std::vector<double> ra, ca;
+    adj_ptr.assign(n + 1, 0);
+    for (int64_t p = 0; p < n; ++p) {
+      auto& r = byrow[p];
+      std::sort(r.begin(), r.end());
+      for (size_t q = 0; q < r.size(); ++q) {
+        if (q > 0 && r[q].first == r[q - 1].first)
+          throw Error(FMMLU_EINVAL, "correction table lists a pair twice");
+        rcol.push_back(r[q].first);
+        ra.push_back(r[q].second);
+      }
+      rptr[p + 1] = (int64_t)rcol.size();
+      auto& c = bycol[p];
+      std::sort(c.begin(), c.end());
+      for (auto& v : c) {
+        crow.push_back(v.first);
+        ca.push_back(v.second);
+      }
+      cptr[p + 1] = (int64_t)crow.size();
+      std::vector<int32_t> part;
+      for (auto& v : r) part.push_back(v.first);
+      for (auto& v : c) part.push_back(v.first);
+      std::sort(part.begin(), part.end());
+      part.erase(std::unique(part.begin(), part.end()), part.end());
+      adj.insert(adj.end(), part.begin(), part.end());
+      adj_ptr[p + 1] = (int64_t)adj.size();
+    }
+    g.corr.rptr = sg.up_to(arena, rptr);
+    g.corr.rcol = sg.up_to(arena, rcol);
+    g.corr.ra = sg.up_to(arena, ra);
+    g.corr.cptr = sg.up_to(arena, cptr);
+    g.corr.crow = sg.up_to(arena, crow);
+    g.corr.ca = sg.up_to(arena, ca);
+  }
+  // the caller's table is only valid during this call: nothing keeps its pointers
+  opts.corr_row_ptr = nullptr;
+  opts.corr_col = nullptr;
+  opts.corr_a = nullptr;
+  std::vector<uint8_t> pos_live(adj_ptr.empty() ? 0 : (size_t)n, 1);  // active at the phase start
   const double eps = opts.eps;
   const double prad = opts.proxy_radius;
 
@@ -1565,6 +1621,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     level_arenas.emplace_back(new DeviceArena(size_t(4) << 20, &mem));
     DeviceArena& level_arena = *level_arenas.back();
     int64_t* act_dev = sg.up_to(level_arena, act_cat);
+    // owner of every position active at this level (spill-over rule)
+    std::vector<int32_t> owner_of;
+    if (!adj_ptr.empty()) {
+      owner_of.assign((size_t)n, -1);
+      for (int i = 0; i < nown; ++i)
+        for (int64_t a : own[i].act) owner_of[(size_t)a] = i;
+    }
 
     // ---- processed boxes by colour, Morton order within a colour
     std::vector<std::vector<int>> colours(8);
@@ -1587,6 +1650,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int oi;
         int m;
         std::vector<int> nown_, qown;  // near and Q owners (with live DOFs)
+        std::vector<int> qspill;       // Q owners beyond the stored pairs (spill-over)
         int nN = 0, nQ = 0;
         bool far_p = false;
         int ngamma = 0;
@@ -1617,6 +1681,26 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             bp.qown.push_back(p);
             bp.nQ += (int)own[p].live.size();
           }
+        }
+        // Section 5.3: an owner beyond the stored pairs (in B's P region) linked to B by a
+        // quadrature correction joins Q; its rows are generated (corrected kernel values)
+        if (!adj_ptr.empty()) {
+          std::vector<int> sp;
+          for (int64_t a : B.act)
+            for (int64_t e = adj_ptr[a]; e < adj_ptr[a + 1]; ++e) {
+              const int32_t p = adj[e];
+              const int q = owner_of[p];
+              if (q < 0 || q == oi || !pos_live[p]) continue;
+              if (gap_units(B, own[q]) >= 2) sp.push_back(q);
+            }
+          std::sort(sp.begin(), sp.end());
+          sp.erase(std::unique(sp.begin(), sp.end()), sp.end());
+          for (int q : sp) {
+            bp.qown.push_back(q);
+            bp.qspill.push_back(q);
+            bp.nQ += (int)own[q].live.size();
+          }
+          info.nspill += (int32_t)sp.size();
         }
         near_live = (int64_t)bp.nN + bp.nQ + (int64_t)B.live.size();
         bp.far_p = live_total - near_live > 0;
@@ -1660,8 +1744,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int row0 = 0;
         for (int q : bp.qown) {
           QSeg s{};
-          s.tile_qb = pidx.at(q, bp.oi);
-          s.tile_bq = pidx.at(bp.oi, q);
+          if (std::binary_search(bp.qspill.begin(), bp.qspill.end(), q)) {
+            s.tile_qb = s.tile_bq = -1;
+            s.gdof = act_dev + act_off[q];
+          } else {
+            s.tile_qb = pidx.at(q, bp.oi);
+            s.tile_bq = pidx.at(bp.oi, q);
+          }
           s.live = own[q].live_dev;
           s.ld = (int)own[q].act.size();
           s.row0 = row0;
@@ -2198,6 +2287,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         std::sort(nl.begin(), nl.end());
         B.live = nl;
         live_total -= e.r;
+        if (!pos_live.empty())
+          for (int j = e.s; j < (int)pv.size(); ++j) pos_live[(size_t)B.act[pv[j]]] = 0;
         info.nboxes_factored++;
       }
       ht.mark(5);

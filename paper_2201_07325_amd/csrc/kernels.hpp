@@ -12,11 +12,26 @@
 
 namespace fmmlu {
 
-// Geometry on the device, structure of arrays in tree order: x, y, z, nx, ny, nz, sqrt(w).
+// Quadrature corrections on the device (Section 5.3's locally corrected near field): the
+// entry of a listed pair (i, j), i != j, is multiplied by 1 + a_ij (target-dependent weight
+// w_ij = w_j (1 + a_ij)). CSR by row in tree positions, columns ascending, and the same
+// pairs by column (for products with the conjugate transpose).
+struct DevCorr {
+  const int64_t* rptr = nullptr;  // n + 1
+  const int32_t* rcol = nullptr;  // column of each entry
+  const double* ra = nullptr;     // a_ij
+  const int64_t* cptr = nullptr;  // n + 1, by column
+  const int32_t* crow = nullptr;  // row of each entry
+  const double* ca = nullptr;
+};
+
+// Geometry on the device, structure of arrays in tree order: x, y, z, nx, ny, nz, sqrt(w);
+// corrections when the system has them (corr.rptr != nullptr).
 struct DevGeom {
   const double* p;  // 7 * n doubles
   int64_t n;
   double k, eta;
+  DevCorr corr;
 };
 
 // ---- tile assembly: out block = copy from old tiles where stored, else kernel entries ----
@@ -48,9 +63,11 @@ void launch_assemble(const DevGeom& g, const AsmTask* tasks, int ntasks, int64_t
 
 // ---- ID matrix [A_QB ; A_BQ^T ; proxy outgoing ; proxy incoming] (column-major) ----
 struct QSeg {
-  int64_t tile_qb;      // offset of tile (q, B): rows = act(q), cols = act(B)
+  int64_t tile_qb;      // offset of tile (q, B): rows = act(q), cols = act(B); -1: generate
   int64_t tile_bq;      // offset of tile (B, q): rows = act(B), cols = act(q)
   const int32_t* live;  // live rows of q (positions in act(q))
+  const int64_t* gdof;  // generated segments: tree positions of act(q) (a spill-over owner
+                        // beyond the stored tiles: its entries are corrected kernel values)
   int32_t ld;           // |act(q)|, leading dimension of tile (q, B)
   int32_t row0;         // first row of this segment inside the A_QB block
 };

@@ -64,6 +64,26 @@ __device__ inline zd cfie_entry_deta(const double* __restrict__ p, int64_t n, do
   return zd{s * f, -c * f};
 }
 
+// correction factor 1 + a_ij of a listed pair (1 when the pair is not listed or i == j)
+__device__ inline double corr_factor(const DevCorr& c, int64_t i, int64_t j) {
+  if (!c.rptr || i == j) return 1.0;
+  int64_t lo = c.rptr[i], hi = c.rptr[i + 1];
+  const int64_t end = hi;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (c.rcol[mid] < j)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < end && c.rcol[lo] == j) ? 1.0 + c.ra[lo] : 1.0;
+}
+
+// A~[i, j] with the quadrature corrections of the system
+__device__ inline zd entry(const DevGeom& g, int64_t i, int64_t j) {
+  return zscale(cfie_entry(g.p, g.n, g.k, g.eta, i, j), corr_factor(g.corr, i, j));
+}
+
 template <class Task>
 __device__ inline int find_task(const Task* __restrict__ t, int n, int64_t u) {
   int lo = 0, hi = n - 1;
@@ -106,7 +126,7 @@ __global__ void __launch_bounds__(256) assemble_kernel(DevGeom g, const AsmTask*
     if (sr.off >= 0) {
       v = widen(src[sr.off + ri + (int64_t)idx[t.cmap_off + j] * sr.ld]);
     } else {
-      v = cfie_entry(g.p, g.n, g.k, g.eta, rd, dof[t.cdof_off + j]);
+      v = entry(g, rd, dof[t.cdof_off + j]);
     }
     dst[t.out_off + i + (int64_t)j * t.ld] = narrow<DT>(v);
   }
@@ -143,6 +163,17 @@ __global__ void __launch_bounds__(256) idmatrix_kernel(DevGeom g, const IdTask* 
     }
     const QSeg sg = segs[t.seg_off + lo];
     const int li = sg.live[iq - sg.row0];
+    if (sg.tile_qb < 0) {
+      // spill-over owner without a stored tile: corrected kernel values
+      const int64_t q = sg.gdof[li];
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = bj * 64 + (threadIdx.x >> 6) + 4 * jj;
+        if (j >= t.m) break;
+        const int64_t b = dof[t.dof_off + j];
+        out[i + (int64_t)j * t.rows] = transposed ? entry(g, b, q) : entry(g, q, b);
+      }
+      return;
+    }
     // all 16 reads in flight before the writes
     PT vals[16];
 #pragma unroll
@@ -204,7 +235,7 @@ __global__ void __launch_bounds__(256) block_kernel(DevGeom g, const int64_t* __
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= nr * nc) return;
   const int64_t i = e % nr, j = e / nr;
-  out[e] = cfie_entry(g.p, g.n, g.k, g.eta, rows[i], cols[j]);
+  out[e] = entry(g, rows[i], cols[j]);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -281,6 +312,32 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __rest
   if (live) part[(int64_t)blockIdx.y * n + i] = zd{are, aim};
 }
 
+// The corrections' share of the exact product: the listed entries beyond their kernel value,
+// a_ij K_ij (or its derivative), added to y in the order of the lists. op 1 walks the lists
+// by column for the conjugate transpose.
+template <int OP>
+__global__ void __launch_bounds__(256) matvec_corr_kernel(DevGeom g, const zd* __restrict__ x, zd* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= g.n) return;
+  const DevCorr& c = g.corr;
+  zd acc = y[i];
+  if (OP == 1) {
+    for (int64_t e = c.cptr[i]; e < c.cptr[i + 1]; ++e) {
+      const int64_t r = c.crow[e];
+      zfmac(acc, zscale(cfie_entry(g.p, g.n, g.k, g.eta, r, i), c.ca[e]), x[r]);
+    }
+  } else {
+    for (int64_t e = c.rptr[i]; e < c.rptr[i + 1]; ++e) {
+      const int64_t j = c.rcol[e];
+      const zd v = OP == 0 ? cfie_entry(g.p, g.n, g.k, g.eta, i, j)
+                 : OP == 2 ? cfie_entry_dk(g.p, g.n, g.k, g.eta, i, j)
+                           : cfie_entry_deta(g.p, g.n, g.k, i, j);
+      zfma(acc, zscale(v, c.ra[e]), x[j]);
+    }
+  }
+  y[i] = acc;
+}
+
 __global__ void __launch_bounds__(256) matvec_sum_kernel(const zd* __restrict__ part, int64_t n, int nslice,
                                                          zd* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -355,6 +412,18 @@ void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipSt
   FMMLU_HIP(hipGetLastError());
   hipLaunchKernelGGL(matvec_sum_kernel, dim3((unsigned)((g.n + 255) / 256)), b, 0, st, part, g.n, ns, y);
   FMMLU_HIP(hipGetLastError());
+  if (g.corr.rptr) {
+    const dim3 gc((unsigned)((g.n + 255) / 256));
+    if (op == 0)
+      hipLaunchKernelGGL(matvec_corr_kernel<0>, gc, b, 0, st, g, x, y);
+    else if (op == 1)
+      hipLaunchKernelGGL(matvec_corr_kernel<1>, gc, b, 0, st, g, x, y);
+    else if (op == 2)
+      hipLaunchKernelGGL(matvec_corr_kernel<2>, gc, b, 0, st, g, x, y);
+    else
+      hipLaunchKernelGGL(matvec_corr_kernel<3>, gc, b, 0, st, g, x, y);
+    FMMLU_HIP(hipGetLastError());
+  }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -32,6 +32,7 @@ __all__ = [
     "point_source_data",
     "plane_wave_data",
     "exterior_targets",
+    "near_corrections",
     "by_name",
 ]
 
@@ -298,6 +299,53 @@ def plane_wave_data(points: np.ndarray, k: float, direction) -> np.ndarray:
     d = np.asarray(direction, dtype=np.float64)
     d = d / np.linalg.norm(d)
     return -np.exp(1j * k * (d @ points))
+
+
+def near_corrections(points: np.ndarray, seed: int = 0, kref: int = 8, radius_factor: float = 2.5,
+                     maxnb: int = 24, amp: float = 0.3, long_frac: float = 0.0, long_factor: float = 0.0,
+                     long_max: int = 8):
+    """Synthetic locally corrected quadrature: target-dependent weight factors for near pairs.
+
+    For target i the quadrature weight of source j becomes w_j (1 + alpha_ij) for the listed
+    pairs (a stand-in for the corrected near-field weights of a high-order rule, which are
+    not available here). Pairs: the sources within radius_factor times the distance to the
+    kref-th nearest neighbour of x_i (at most maxnb, nearest first, i itself excluded); for a
+    fraction long_frac of the targets also up to long_max sources at distances in
+    (that radius, long_factor times the kref-th neighbour distance], so that some corrections
+    reach beyond a box's near field.
+    alpha_ij ~ U[-amp, amp], seeded.
+
+    Returns (row_ptr (n + 1), col (nnz), alpha (nnz)): CSR by target, columns ascending.
+    """
+    from scipy.spatial import cKDTree
+
+    x = np.ascontiguousarray(np.asarray(points, dtype=np.float64).T)
+    n = x.shape[0]
+    rng = np.random.default_rng(seed)
+    tree = cKDTree(x)
+    dref, _ = tree.query(x, k=min(kref + 1, n))
+    h = dref[:, -1] if dref.ndim == 2 else dref
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i in range(n):
+        r0 = radius_factor * h[i]
+        near = np.asarray(tree.query_ball_point(x[i], r0), dtype=np.int64)
+        near = near[near != i]
+        if near.size > maxnb:
+            dist = np.linalg.norm(x[near] - x[i], axis=1)
+            near = near[np.argsort(dist, kind="stable")[:maxnb]]
+        far = np.zeros(0, dtype=np.int64)
+        if long_frac > 0.0 and rng.random() < long_frac:
+            cand = np.asarray(tree.query_ball_point(x[i], long_factor * h[i]), dtype=np.int64)
+            cand = cand[np.linalg.norm(x[cand] - x[i], axis=1) > r0]
+            if cand.size:
+                far = rng.choice(cand, size=min(long_max, cand.size), replace=False)
+        c = np.unique(np.concatenate([near, far]))
+        cols.append(c)
+        vals.append(rng.uniform(-amp, amp, c.size))
+        row_ptr[i + 1] = row_ptr[i] + c.size
+    return row_ptr, np.concatenate(cols) if cols else np.zeros(0, np.int64), \
+        np.concatenate(vals) if vals else np.zeros(0)
 
 
 def exterior_targets(m: int = 50, seed: int = 0, rmin: float = 1.5, rmax: float = 3.0) -> np.ndarray:

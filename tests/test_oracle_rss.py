@@ -149,3 +149,60 @@ def test_separate_skeletons():
     assert sum(g.S.size for g in f.factors) <= sum(g.S.size for g in shared.factors)
     # the row and column skeletons really differ somewhere
     assert any(not np.array_equal(np.sort(g.S), np.sort(g.Sr)) for g in f.factors)
+
+
+def _corrected_case():
+    s = synth.graded_ellipsoid(2500, seed=2, k=3.0, eps=1e-6)
+    corr = synth.near_corrections(s.points, seed=1, long_frac=0.03, long_factor=14.0)
+    return s, corr
+
+
+def test_corrected_matrix_entries():
+    """Listed pairs are the kernel entries times (1 + a_ij); every other entry and the
+    diagonal are unchanged; the derivative matrices carry the same factors."""
+    s = synth.unit_sphere(400)
+    corr = synth.near_corrections(s.points, seed=3)
+    a0 = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
+    a1 = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta, corr=corr)
+    rp, cc, ca = corr
+    fac = np.ones_like(a0)
+    for i in range(s.n):
+        for e in range(rp[i], rp[i + 1]):
+            if cc[e] != i:
+                fac[i, cc[e]] = 1.0 + ca[e]
+    assert np.array_equal(a1, a0 * fac)
+    assert np.all(np.diag(a1) == 0.5)
+    d0 = dense.derivative_matrix(s.points, s.normals, s.weights, s.k, s.eta, "k")
+    d1 = dense.derivative_matrix(s.points, s.normals, s.weights, s.k, s.eta, "k", corr=corr)
+    assert np.array_equal(d1, d0 * fac)
+
+
+def test_quadrature_corrections_spill_over():
+    """Section 5.3: corrections that reach a box's far field move the linked owner into Q.
+    With that rule the factorization stays within 10 eps of dense LU (forward and adjoint),
+    no correction ever links a box to its P region, and the proxy IDs are as accurate as the
+    brute-force IDs of the full far field. Without it (spill=False) the proxy surface misses
+    the corrected entries: brute-force ID errors far above eps and a worse solve."""
+    s, corr = _corrected_case()
+    a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta, corr=corr)
+    lu = dense.DenseLU(a)
+    b = _rhs(s)
+    xs, ys = lu.solve(b), lu.solve_adjoint(b)
+    kw = dict(leaf_size=32, brute_force_check=True, schedule="phase_start", corr=corr)
+    f = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, check_invariant=True, **kw)
+    assert f.spill_count > 0
+    assert np.linalg.norm(f.solve(b) - xs) / np.linalg.norm(xs) <= 10 * s.eps
+    assert np.linalg.norm(f.solve_adjoint(b) - ys) / np.linalg.norm(ys) <= 10 * s.eps
+    assert max(e[1] for e in f.bf_errors) <= 3 * s.eps
+    off = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, spill=False, **kw)
+    assert max(e[1] for e in off.bf_errors) > 30 * s.eps
+    assert np.linalg.norm(off.solve(b) - xs) > np.linalg.norm(f.solve(b) - xs)
+
+
+def test_empty_correction_table_is_the_plain_method():
+    s = synth.unit_sphere(1500)
+    empty = (np.zeros(s.n + 1, np.int64), np.zeros(0, np.int64), np.zeros(0))
+    f0 = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, leaf_size=32)
+    f1 = rss.RSSFactor(s.points, s.normals, s.weights, s.k, s.eta, s.eps, leaf_size=32, corr=empty)
+    b = _rhs(s)
+    assert np.array_equal(f0.solve(b), f1.solve(b)) and f1.spill_count == 0
