@@ -31,6 +31,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <exception>
@@ -1134,7 +1135,7 @@ struct PendingPhase {
   SolvePhase ph;
   std::vector<std::pair<int32_t, int64_t>> contrib;  // (destination, y index)
   std::vector<SolveBox> db;
-  std::vector<SweepTask> txr, typ, tyr, tbp, tbt, tbf;
+  std::vector<SweepTask> txr, ty, tbp, tbt;
   std::vector<int32_t> dst;
   std::vector<int64_t> ptr, src;
 };
@@ -2299,50 +2300,41 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         SolvePhase& ph = pp.ph;
         ph.box_begin = (int)box_base;
         ph.box_end = (int)boxes.size();
-        int64_t yo = 0, xo = 0, po = 0, xpo = 0, ypo = 0, tpo = 0;
+        int64_t yo = 0, po = 0, xpo = 0;
         auto& contrib = pp.contrib;
         auto& db = pp.db;
-        auto &txr = pp.txr, &typ = pp.typ, &tyr = pp.tyr, &tbp = pp.tbp, &tbt = pp.tbt, &tbf = pp.tbf;
+        auto &txr = pp.txr, &ty = pp.ty, &tbp = pp.tbp, &tbt = pp.tbt;
         for (int b = ph.box_begin; b < ph.box_end; ++b) {
           FactorBox& fb = boxes[b];
           const int lb = b - ph.box_begin;
           SolveBox& d = fb.dev;
           fb.y_off = yo;
           d.y_off = yo;
-          d.xr_off = xo;
           d.p_off = po;
           d.xrp_off = xpo;
-          d.yp_off = ypo;
-          d.tp_off = tpo;
           d.nks = (fb.s + kSolveK - 1) / kSolveK;
-          d.nkr = (fb.r + kSolveKr - 1) / kSolveKr;
           d.nchunk = (fb.nsn + kSolveK - 1) / kSolveK;
+          d.dx_off = dxlen;
+          dxlen += fb.r;
           const int ngrp = (fb.r + kSolveOut - 1) / kSolveOut;
           for (int c = 0; c < d.nks; ++c)
             for (int g = 0; g < ngrp; ++g)
               txr.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.s - c * kSolveK), c, g, 0});
-          for (int k0 = 0; k0 < fb.nsn; k0 += kSolveRows) {
-            const int kn = std::min(kSolveRows, fb.nsn - k0);
-            tyr.push_back(SweepTask{lb, k0, kn, 0, 0, 0});
-            for (int c = 0; c < d.nkr; ++c) typ.push_back(SweepTask{lb, k0, kn, c, 0, 0});
-          }
+          // rows of S u N (forward) and of S (backward), 64 per item; the item of rows 0..63
+          // also stores x_R, so a box without such rows still gets one (empty) item
+          for (int k0 = 0; k0 < std::max(fb.nsn, 1); k0 += kSolveRows)
+            ty.push_back(SweepTask{lb, k0, std::max(0, std::min(kSolveRows, fb.nsn - k0)), 0, 0, 0});
           for (int c = 0; c < d.nchunk; ++c)
             for (int g = 0; g < ngrp; ++g)
               tbp.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.nsn - c * kSolveK), c, g, 0});
-          for (int l0 = 0; l0 < fb.s; l0 += kSolveRows) {
-            const int ln = std::min(kSolveRows, fb.s - l0);
-            tbf.push_back(SweepTask{lb, l0, ln, 0, 0, 0});
-            for (int c = 0; c < d.nkr; ++c) tbt.push_back(SweepTask{lb, l0, ln, c, 0, 0});
-          }
+          for (int l0 = 0; l0 < std::max(fb.s, 1); l0 += kSolveRows)
+            tbt.push_back(SweepTask{lb, l0, std::max(0, std::min(kSolveRows, fb.s - l0)), 0, 0, 0});
           ph.rmax = std::max(ph.rmax, fb.r);
           ph.smax = std::max(ph.smax, fb.s);
           db.push_back(d);
           yo += fb.nsn;
-          xo += fb.r;
           po += (int64_t)d.nchunk * fb.r;
           xpo += (int64_t)d.nks * fb.r;
-          ypo += (int64_t)d.nkr * fb.nsn;
-          tpo += (int64_t)d.nkr * fb.s;
         }
         // scatter lists: every S u N position of every box of the phase, summed in box order
         for (int q = 0; q < ne; ++q) {
@@ -2360,17 +2352,11 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(ph.rmax) +
                                         " DOFs exceeds the solve kernels' LDS bound (4096)");
         ph.ylen = yo;
-        ph.xrlen = xo;
         ph.plen = po;
         ph.xrplen = xpo;
-        ph.yplen = ypo;
-        ph.tplen = tpo;
         ymax = std::max(ymax, yo);
-        xrmax = std::max(xrmax, xo);
         pmax = std::max(pmax, po);
         xrpmax = std::max(xrpmax, xpo);
-        ypmax = std::max(ypmax, ypo);
-        tpmax = std::max(tpmax, tpo);
         bgw.post([&pp] { group_scatter(pp); });
       }
       // live lists of eliminated boxes to the device (persistent for the level)
@@ -2534,17 +2520,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         pk.add(&ph.sc_ptr, pp.ptr);
         pk.add(&ph.sc_src, pp.src);
         pk.add(&ph.dxr, pp.txr);
-        pk.add(&ph.dyp, pp.typ);
-        pk.add(&ph.dyr, pp.tyr);
+        pk.add(&ph.dy, pp.ty);
         pk.add(&ph.dbp, pp.tbp);
         pk.add(&ph.dbt, pp.tbt);
-        pk.add(&ph.dbf, pp.tbf);
         ph.nxr = (int)pp.txr.size();
-        ph.nyp = (int)pp.typ.size();
-        ph.nyr = (int)pp.tyr.size();
+        ph.ny = (int)pp.ty.size();
         ph.nbp = (int)pp.tbp.size();
         ph.nbt = (int)pp.tbt.size();
-        ph.nbf = (int)pp.tbf.size();
       }
       sg.commit(arena, pk);
       for (auto& ph : newph) phases.push_back(ph);
@@ -2597,57 +2579,47 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
 }
 
 // ------------------------------------------------------------------------------------------
-void FactorImpl::ensure_workspace() {
-  if (wx) return;
-  wx = arena.alloc_n<zd>((size_t)n);
-  wy = arena.alloc_n<zd>((size_t)std::max<int64_t>(ymax, 1));
-  wxr = arena.alloc_n<zd>((size_t)std::max<int64_t>(xrmax, 1));
-  wp = arena.alloc_n<zd>((size_t)std::max<int64_t>(pmax, 1));
+void FactorImpl::alloc_ws(SolveWs& w, int nr) {
+  auto al = [&](int64_t len) { return arena.alloc_n<zd>((size_t)std::max<int64_t>(len, 1) * (size_t)nr); };
   const int64_t nblk = (n0 + 255) / 256;
-  wtop = arena.alloc_n<zd>((size_t)std::max<int64_t>((int64_t)n0 * (1 + nblk), 1));
+  w.x = al(n);
+  w.y = al(ymax);
+  w.p = al(pmax);
+  w.xrp = al(xrpmax);
+  w.xrg = al(dxlen);
+  w.top = al((int64_t)n0 * (1 + nblk));
+}
+
+void FactorImpl::ensure_workspace() {
+  if (ws1.x) return;
+  alloc_ws(ws1, 1);
   wmv = arena.alloc_n<zd>((size_t)n);
   wpart = arena.alloc_n<zd>((size_t)matvec_slices(n) * (size_t)n);
-  wxrp = arena.alloc_n<zd>((size_t)std::max<int64_t>(xrpmax, 1));
-  wyp = arena.alloc_n<zd>((size_t)std::max<int64_t>(ypmax, 1));
-  wtp = arena.alloc_n<zd>((size_t)std::max<int64_t>(tpmax, 1));
 }
 
 void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) {
-  SolveWs w;
-  w.x = wx;
-  w.y = wy;
-  w.top = wtop;
-  w.xr = wxr;
-  w.p = wp;
-  w.xrp = wxrp;
-  w.yp = wyp;
-  w.tp = wtp;
-  sweep(w, 1, bc, n, xc, n, 1, adjoint, st);
+  sweep(ws1, 1, bc, n, xc, n, 1, adjoint, st);
 }
 
 void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* xc, int64_t ldx, int m,
                        bool adjoint, hipStream_t st) {
   const int adj = adjoint ? 1 : 0;
   launch_permute(bc, w.x, order_dev, n, 1, st, nr, ldb, m);
-  // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase
+  // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase: x_R partials, then
+  // x_R and the updates y of S u N, then their deterministic sum into x
   for (auto& ph : phases) {
-    const int nb = ph.box_end - ph.box_begin;
     launch_solve_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st, nr);
-    launch_solve_xr_fin(ph.dboxes, nb, w.x, w.xr, w.xrp, st, nr);
-    launch_solve_y_part(ph.dboxes, ph.dyp, ph.nyp, w.xr, w.yp, adj, f32, st, nr);
-    launch_solve_y_red(ph.dboxes, ph.dyr, ph.nyr, w.yp, w.y, st, nr);
+    launch_solve_y(ph.dboxes, ph.dy, ph.ny, w.x, w.xrp, w.xrg, w.y, adj, f32, st, nr);
     launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, w.y, w.x, st, nr);
   }
-  // D^{-1} (adjoint D^{-H}): all pivot blocks, then the top block
-  launch_solve_diag(all_boxes, nall, rmax_all, w.x, adj, f32, st, nr);
+  // D^{-1} (adjoint D^{-H}): all pivot blocks (on the x_R buffer), then the top block
+  launch_solve_diag(all_boxes, nall, rmax_all, w.xrg, adj, f32, st, nr);
   launch_solve_top(Ainv, n0, top_dev, w.x, w.top, adj, st, nr);
-  // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse
+  // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse: x_R partials,
+  // then x_R into x and the updates of x_S
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
-    const int nb = it->box_end - it->box_begin;
     launch_solve_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st, nr);
-    launch_solve_bfin(it->dboxes, nb, w.p, w.x, w.xr, st, nr);
-    launch_solve_bt_part(it->dboxes, it->dbt, it->nbt, w.xr, w.tp, adj, f32, st, nr);
-    launch_solve_bt_fin(it->dboxes, it->dbf, it->nbf, w.tp, w.x, st, nr);
+    launch_solve_bt(it->dboxes, it->dbt, it->nbt, w.xrg, w.p, w.x, adj, f32, st, nr);
   }
   launch_permute(w.x, xc, order_dev, n, 0, st, nr, ldx, m);
 }
@@ -2657,19 +2629,9 @@ bool FactorImpl::blocked_ok() const { return (size_t)rmax_all * kSolveBlock * si
 
 void FactorImpl::ensure_block_workspace() {
   if (wsb.x) return;
-  const size_t B = kSolveBlock;
-  auto al = [&](int64_t len) { return arena.alloc_n<zd>((size_t)std::max<int64_t>(len, 1) * B); };
-  const int64_t nblk = (n0 + 255) / 256;
-  wsb.x = al(n);
-  wsb.y = al(ymax);
-  wsb.top = al((int64_t)n0 * (1 + nblk));
-  wsb.xr = al(xrmax);
-  wsb.p = al(pmax);
-  wsb.xrp = al(xrpmax);
-  wsb.yp = al(ypmax);
-  wsb.tp = al(tpmax);
-  ginb = al(n);
-  goutb = al(n);
+  alloc_ws(wsb, kSolveBlock);
+  ginb = arena.alloc_n<zd>((size_t)n * kSolveBlock);
+  goutb = arena.alloc_n<zd>((size_t)n * kSolveBlock);
 }
 
 // the blocked sweeps of one direction in a graph on the private stream (ginb -> goutb)

@@ -80,18 +80,17 @@ struct SolvePhase {
   int64_t* sc_ptr = nullptr;
   int64_t* sc_src = nullptr;
   int64_t nd = 0;
-  int64_t ylen = 0, xrlen = 0, plen = 0, xrplen = 0, yplen = 0, tplen = 0;
-  // work items: forward x_R partials, y partials, y row reductions; backward partials,
-  // T-row partials, T-row reductions
-  SweepTask *dxr = nullptr, *dyp = nullptr, *dyr = nullptr, *dbp = nullptr, *dbt = nullptr, *dbf = nullptr;
-  int nxr = 0, nyp = 0, nyr = 0, nbp = 0, nbt = 0, nbf = 0;
+  int64_t ylen = 0, plen = 0, xrplen = 0;
+  // work items: forward x_R partials, rows of y; backward x_R partials, rows of x_S
+  SweepTask *dxr = nullptr, *dy = nullptr, *dbp = nullptr, *dbt = nullptr;
+  int nxr = 0, ny = 0, nbp = 0, nbt = 0;
   int rmax = 0, smax = 0;
 };
 
 // Workspace of the sweeps for blocks of nr right-hand sides (interleaved vectors)
 struct SolveWs {
-  zd *x = nullptr, *y = nullptr, *top = nullptr, *xr = nullptr, *p = nullptr;
-  zd *xrp = nullptr, *yp = nullptr, *tp = nullptr;
+  zd *x = nullptr, *y = nullptr, *top = nullptr, *p = nullptr, *xrp = nullptr;
+  zd* xrg = nullptr;  // x_R of every box (offset dx_off): forward result, D^{-1} applied in place
 };
 
 struct FactorImpl {
@@ -109,25 +108,19 @@ struct FactorImpl {
   std::vector<int64_t> order;  // host copy
   std::vector<FactorBox> boxes;
   std::vector<SolvePhase> phases;
-  int64_t ymax = 0, xrmax = 0, pmax = 0, xrpmax = 0, ypmax = 0, tpmax = 0;
+  int64_t ymax = 0, pmax = 0, xrpmax = 0;
   SolveBox* all_boxes = nullptr;  // every factored box, for the diagonal step
   int nall = 0, rmax_all = 0;
+  int64_t dxlen = 0;  // x_R of every box in one buffer (sum of r)
   int n0 = 0;
   int32_t* top_dev = nullptr;
   zd* Ainv = nullptr;
   fmmlu_info info{};
   Profiler prof;
   // solve workspace (allocated lazily)
-  zd* wx = nullptr;
-  zd* wy = nullptr;
-  zd* wtop = nullptr;
+  SolveWs ws1{};        // single right-hand sides
   zd* wmv = nullptr;
-  zd* wxr = nullptr;
-  zd* wp = nullptr;
   zd* wpart = nullptr;  // matvec slice partials
-  zd* wxrp = nullptr;   // forward x_R partials
-  zd* wyp = nullptr;    // forward y partials
-  zd* wtp = nullptr;    // backward x_S partials
   // refinement workspace (allocated on the first refined solve)
   DeviceArena rarena{size_t(1) << 20};
   zd* rbuf = nullptr;
@@ -145,6 +138,7 @@ struct FactorImpl {
   void sweep(const SolveWs& w, int nr, const zd* b, int64_t ldb, zd* x, int64_t ldx, int m, bool adjoint,
              hipStream_t st);
   void ensure_workspace();
+  void alloc_ws(SolveWs& w, int nr);
   // blocks of kSolveBlock right-hand sides (allocated on the first multi-column solve)
   SolveWs wsb{};
   zd* ginb = nullptr;

@@ -338,23 +338,20 @@ struct SolveBox {
   const void* UpT;    // U^T with U = X_RR^{-1} X_{R (S u N)}: (s+nN) x r, ld = s+nN
   int32_t r, s, nsn;
   int32_t nks;        // chunks of kSolveK over s (forward x_R partials)
-  int32_t nkr;        // chunks of kSolveKr over r (row-GEMV partials)
-  int32_t nchunk;     // chunks of kSolveK over s + nN (backward partials)
+  int32_t nchunk;     // chunks of kSolveK over s + nN (backward x_R partials)
+  int32_t pad;
   int64_t y_off;      // this box's outputs in the forward scatter buffer
-  int64_t xr_off;     // this box's x_R copy in the phase buffer
-  int64_t p_off;      // backward partials (nchunk x r)
+  int64_t p_off;      // backward x_R partials (nchunk x r)
   int64_t xrp_off;    // forward x_R partials (nks x r)
-  int64_t yp_off;     // forward y partials (nkr x nsn)
-  int64_t tp_off;     // backward x_S partials (nkr x s)
+  int64_t dx_off;     // this box's x_R in the buffer of all boxes (sum of r)
 };
 // Work item of a sweep kernel: rows or columns [k0, k0 + kn) of box `box`; `chunk` is the
-// k-chunk (row GEMVs) and `grp` the group of kSolveOut outputs (column GEMVs).
+// k-chunk and `grp` the group of kSolveOut outputs (column GEMVs).
 struct SweepTask {
   int32_t box, k0, kn, chunk, grp, pad;
 };
-constexpr int kSolveRows = 256;  // rows per row-GEMV work item
-constexpr int kSolveKr = 64;     // k-chunk of row GEMVs (over r)
-constexpr int kSolveK = 256;     // k-chunk of column GEMVs (over s or s + nN)
+constexpr int kSolveRows = 64;   // rows per row-GEMV work item (one row per lane)
+constexpr int kSolveK = 256;     // k-chunk of column GEMVs (over s or s + nN) and of staged x_R
 constexpr int kSolveOut = 64;    // outputs per column-GEMV work item
 
 // Every solve launcher takes nr = 1 or kSolveBlock right-hand sides; vectors inside the
@@ -363,31 +360,23 @@ constexpr int kSolveBlock = 8;
 // forward: partials of op(T)^T x_S (T^T, adjoint T^H) per (box, s-chunk, output group)
 void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
                           bool f32, hipStream_t st, int nr = 1);
-// forward, per box: x_R -= sum of partials; copy to XR
-void launch_solve_xr_fin(const SolveBox* boxes, int nb, zd* x, zd* XR, const zd* Pxr, hipStream_t st, int nr = 1);
-// forward: partials of op(P) x_R (Lp, adjoint conj(Up^T)) per (box, row chunk, k-chunk)
-void launch_solve_y_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Yp, int adjoint,
-                         bool f32, hipStream_t st, int nr = 1);
-// forward: y = sum of partials per (box, row chunk)
-void launch_solve_y_red(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Yp, zd* y, hipStream_t st,
-                        int nr = 1);
+// forward, per (box, 64 rows of S u N): x_R = x[R] - sum of the partials (kept in XRg by the
+// items of rows 0..63), then y = op(P) x_R (Lp, adjoint conj(Up^T)) for those rows
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg,
+                    zd* y, int adjoint, bool f32, hipStream_t st, int nr = 1);
 // x[dst[d]] -= sum of y[src[q]] over ptr[d] <= q < ptr[d+1] (deterministic scatter)
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st, int nr = 1);
-// diagonal: x_R = Xi x_R (adjoint Xi^H x_R) for every box (rmax nr 16 bytes of LDS <= 64 KiB)
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, bool f32, hipStream_t st,
+// diagonal: x_R = Xi x_R (adjoint Xi^H x_R) in XRg for every box (rmax nr 16 bytes of LDS <= 64 KiB)
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* XRg, int adjoint, bool f32, hipStream_t st,
                        int nr = 1);
 // backward: partials of op(Q)^T x_SN (Up, adjoint Lp^H) per (box, column chunk, output group)
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
                         int adjoint, bool f32, hipStream_t st, int nr = 1);
-// backward, per box: x_R -= sum of partials; copy to XR
-void launch_solve_bfin(const SolveBox* boxes, int nb, const zd* Pbuf, zd* x, zd* XR, hipStream_t st, int nr = 1);
-// backward: partials of op(T) x_R (T, adjoint conj(T)) per (box, s-row chunk, k-chunk)
-void launch_solve_bt_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Pt, int adjoint,
-                          bool f32, hipStream_t st, int nr = 1);
-// backward: x_S -= sum of partials per (box, s-row chunk)
-void launch_solve_bt_fin(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Pt, zd* x, hipStream_t st,
-                         int nr = 1);
+// backward, per (box, 64 rows of S): x_R = XRg - sum of the partials (written to x[R] by the
+// items of rows 0..63), then x_S -= op(T) x_R (T, adjoint conj(T)) for those rows
+void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, const zd* Pbuf, zd* x,
+                     int adjoint, bool f32, hipStream_t st, int nr = 1);
 // top block: x_t = Ainv x_t (adjoint Ainv^H); tmp holds n0 (1 + nblk) nr entries
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
                       hipStream_t st, int nr = 1);

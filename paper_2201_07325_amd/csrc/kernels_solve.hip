@@ -7,6 +7,12 @@
 // colour's boxes run concurrently; their L-updates to shared near DOFs are summed by a
 // deterministic gather (scatter_sub) instead of atomics.
 //
+// Per colour phase and direction two or three launches: column products over chunks of the
+// skeleton (or S u N) into partials of x_R; then items of 64 rows that each rebuild x_R from
+// the partials while staging it in LDS and apply their rows of L or T (the four wavefronts of
+// an item split the columns, no further partials); forward, the scatter. x_R of every box
+// lives in one buffer between the forward sweep, the pivot blocks and the backward sweep.
+//
 // Every kernel works on a block of NR right-hand sides at once (NR = 1 or kSolveBlock):
 // internal vectors are interleaved, entry i of right-hand side c at [i NR + c], so each
 // factor entry is read once per block and used NR times. These kernels are HBM-bound in
@@ -78,47 +84,6 @@ __device__ inline void colgemv_group(const FT* __restrict__ A, int64_t lda, int 
   }
 }
 
-// Row GEMV partial for NR right-hand sides: acc[c] = sum_{k < kn} A[i, k]^(*) v[k][c] for
-// one row i (thread per row; rows consecutive across threads, so each k is one coalesced
-// load), eight loads in flight.
-template <class FT, int NR>
-__device__ inline void rowgemv(const FT* __restrict__ A, int64_t lda, int i, int kn, bool conjA, const zd (*v)[NR],
-                               zd (&out)[NR]) {
-  zd acc[4][NR];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int c = 0; c < NR; ++c) acc[q][c] = zd{0.0, 0.0};
-  const FT* ar = A + i;
-  int k = 0;
-  for (; k + 7 < kn; k += 8) {
-    zd a[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] = widen(ar[(int64_t)(k + q) * lda]);
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        if (conjA)
-          zfmac(acc[q & 3][c], a[q], v[k + q][c]);
-        else
-          zfma(acc[q & 3][c], a[q], v[k + q][c]);
-      }
-  }
-  for (; k < kn; ++k) {
-    const zd a = widen(ar[(int64_t)k * lda]);
-#pragma unroll
-    for (int c = 0; c < NR; ++c) {
-      if (conjA)
-        zfmac(acc[0][c], a, v[k][c]);
-      else
-        zfma(acc[0][c], a, v[k][c]);
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < NR; ++c) out[c] = zadd(zadd(acc[0][c], acc[1][c]), zadd(acc[2][c], acc[3][c]));
-}
-
 // Forward: Pxr[c-chunk][i] = sum_{k in s-chunk} op(T)[k, i] x_S[k] (T^T, adjoint T^H).
 template <class FT, int NR>
 __global__ void __launch_bounds__(256) solve_xr_part_kernel(const SolveBox* __restrict__ boxes,
@@ -136,58 +101,92 @@ __global__ void __launch_bounds__(256) solve_xr_part_kernel(const SolveBox* __re
                         [&](int i, int c, zd d) { out[(int64_t)i * NR + c] = d; });
 }
 
-// Forward, per box: x_R -= sum of the partials; the result also goes to XR.
-template <int NR>
-__global__ void __launch_bounds__(256) solve_xr_fin_kernel(const SolveBox* __restrict__ boxes, zd* x,
-                                                           zd* __restrict__ XR, const zd* __restrict__ Pxr) {
-  const SolveBox b = boxes[blockIdx.x];
-  for (int e = threadIdx.x; e < b.r * NR; e += 256) {
-    const int i = e / NR, c = e % NR;
-    const int64_t xi = (int64_t)b.R[i] * NR + c;
-    zd v = x[xi];
-    for (int ch = 0; ch < b.nks; ++ch) v = zsub(v, Pxr[(b.xrp_off + (int64_t)ch * b.r + i) * NR + c]);
-    x[xi] = v;
-    XR[(b.xr_off + i) * NR + c] = v;
+// Dot products of the rows [k0, k0 + 64) of a column-major matrix M (ld) with x_R staged in
+// LDS in chunks of kSolveK, one row per lane, the four wavefronts taking every fourth column
+// (four loads in flight each); acc holds this wavefront's share. stage(kb, kn) fills
+// xr[0, kn) with x_R[kb, kb + kn) (all threads, before the barrier).
+template <class FT, int NR, class Stage>
+__device__ inline void rows_times_xr(const FT* __restrict__ M, int64_t ld, int r, int i, bool row, bool conjM,
+                                     zd (*xr)[NR], zd (&acc)[NR], Stage stage) {
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = zd{0.0, 0.0};
+  for (int kb = 0; kb < r; kb += kSolveK) {
+    const int kn = min(kSolveK, r - kb);
+    stage(kb, kn);
+    __syncthreads();
+    if (row) {
+      const FT* col = M + i + (int64_t)kb * ld;
+      int k = wave;
+      for (; k + 12 < kn; k += 16) {
+        zd a[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[q] = widen(col[(int64_t)(k + 4 * q) * ld]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < NR; ++c) {
+            if (conjM)
+              zfmac(acc[c], a[q], xr[k + 4 * q][c]);
+            else
+              zfma(acc[c], a[q], xr[k + 4 * q][c]);
+          }
+      }
+      for (; k < kn; k += 4) {
+        const zd a = widen(col[(int64_t)k * ld]);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          if (conjM)
+            zfmac(acc[c], a, xr[k][c]);
+          else
+            zfma(acc[c], a, xr[k][c]);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Forward: Yp[k-chunk][i] = sum_{k in r-chunk} P[i, k] x_R[k], P = Lp (adjoint conj(U^T)).
-template <class FT, int NR>
-__global__ void __launch_bounds__(256) solve_y_part_kernel(const SolveBox* __restrict__ boxes,
-                                                           const SweepTask* __restrict__ tasks,
-                                                           const zd* __restrict__ XR, zd* __restrict__ Yp,
-                                                           int adjoint) {
-  const SweepTask t = tasks[blockIdx.x];
-  const SolveBox b = boxes[t.box];
-  __shared__ zd xr[kSolveKr][NR];
-  const int kb = t.chunk * kSolveKr, kn = min(kSolveKr, b.r - kb);
-  for (int e = threadIdx.x; e < kn * NR; e += 256) xr[e / NR][e % NR] = XR[(b.xr_off + kb) * NR + e];
+// the four wavefronts' sums of row `lane` side by side in LDS (xr reused; after the loop)
+template <int NR>
+__device__ inline void rows_reduce(zd (*xr)[NR], const zd (&acc)[NR]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int c = 0; c < NR; ++c) xr[wave * 64 + lane][c] = acc[c];
   __syncthreads();
-  const FT* P = static_cast<const FT*>(adjoint ? b.UpT : b.Lp) + (int64_t)kb * b.nsn;
-  zd* out = Yp + (b.yp_off + (int64_t)t.chunk * b.nsn) * NR;
-  const int i = t.k0 + threadIdx.x;
-  if (i < t.k0 + t.kn) {
-    zd r[NR];
-    rowgemv<FT, NR>(P, b.nsn, i, kn, adjoint != 0, xr, r);
-#pragma unroll
-    for (int c = 0; c < NR; ++c) out[(int64_t)i * NR + c] = r[c];
-  }
 }
 
-// Forward: y[i] = sum of the partials, rows of one (box, row chunk).
-template <int NR>
-__global__ void __launch_bounds__(256) solve_y_red_kernel(const SolveBox* __restrict__ boxes,
-                                                          const SweepTask* __restrict__ tasks,
-                                                          const zd* __restrict__ Yp, zd* __restrict__ y) {
+// Forward, per (box, 64 rows of S u N): x_R = x[R] - sum of the x_R partials, staged chunk by
+// chunk (the item of rows 0..63 also keeps it in XRg); y = op(P) x_R for the item's rows,
+// P = Lp (adjoint conj(Up^T)). A box with no S u N rows has one item without rows.
+template <class FT, int NR>
+__global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict__ boxes,
+                                                      const SweepTask* __restrict__ tasks,
+                                                      const zd* __restrict__ x, const zd* __restrict__ Pxr,
+                                                      zd* __restrict__ XRg, zd* __restrict__ y, int adjoint) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
-  const int i = t.k0 + threadIdx.x;
-  if (i >= t.k0 + t.kn) return;
+  __shared__ zd xr[kSolveK][NR];
+  const int lane = threadIdx.x & 63;
+  const int i = t.k0 + lane;
+  const bool keep = t.k0 == 0;
+  zd acc[NR];
+  rows_times_xr<FT, NR>(static_cast<const FT*>(adjoint ? b.UpT : b.Lp), b.nsn, b.r, i, lane < t.kn, adjoint != 0,
+                        xr, acc, [&](int kb, int kn) {
+                          for (int e = threadIdx.x; e < kn * NR; e += 256) {
+                            const int k = e / NR, c = e % NR;
+                            zd v = x[(int64_t)b.R[kb + k] * NR + c];
+                            for (int ch = 0; ch < b.nks; ++ch)
+                              v = zsub(v, Pxr[(b.xrp_off + (int64_t)ch * b.r + kb + k) * NR + c]);
+                            xr[k][c] = v;
+                            if (keep) XRg[(b.dx_off + kb + k) * NR + c] = v;
+                          }
+                        });
+  rows_reduce<NR>(xr, acc);
+  if (threadIdx.x < 64 && lane < t.kn) {
 #pragma unroll
-  for (int c = 0; c < NR; ++c) {
-    zd v{0.0, 0.0};
-    for (int ch = 0; ch < b.nkr; ++ch) v = zadd(v, Yp[(b.yp_off + (int64_t)ch * b.nsn + i) * NR + c]);
-    y[(b.y_off + i) * NR + c] = v;
+    for (int c = 0; c < NR; ++c)
+      y[(b.y_off + i) * NR + c] = zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c]));
   }
 }
 
@@ -207,18 +206,20 @@ __global__ void __launch_bounds__(256) scatter_sub_kernel(const int32_t* __restr
   x[xi] = zsub(x[xi], acc);
 }
 
-// Diagonal: x_R = Xi x_R (adjoint Xi^H x_R), one box per workgroup, x_R in dynamic LDS.
+// Diagonal: x_R = Xi x_R (adjoint Xi^H x_R) in place in XRg, one box per workgroup, x_R in
+// dynamic LDS.
 // Normal: lanes take rows, the four wavefronts split k, partial sums meet in LDS.
 // Adjoint: one wavefront per output, lanes over k (columns of Xi are contiguous).
 template <class FT, int NR>
-__global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restrict__ boxes, zd* x,
+__global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restrict__ boxes, zd* XRg,
                                                          int adjoint) {
   const SolveBox b = boxes[blockIdx.x];
   extern __shared__ zd xr_flat[];
   zd(*xr)[NR] = reinterpret_cast<zd(*)[NR]>(xr_flat);
   __shared__ zd part[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int e = threadIdx.x; e < b.r * NR; e += 256) xr[e / NR][e % NR] = x[(int64_t)b.R[e / NR] * NR + e % NR];
+  zd* x = XRg + b.dx_off * NR;
+  for (int e = threadIdx.x; e < b.r * NR; e += 256) xr[e / NR][e % NR] = x[e];
   __syncthreads();
   const FT* Xi = static_cast<const FT*>(b.Xi);
   const int r = b.r;
@@ -239,7 +240,7 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
         part[wave][lane] = acc[c];
         __syncthreads();
         if (wave == 0 && i < r)
-          x[(int64_t)b.R[i] * NR + c] = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
+          x[(int64_t)i * NR + c] = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
         __syncthreads();
       }
     }
@@ -258,7 +259,7 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
       for (int c = 0; c < NR; ++c) {
         acc[c].re = wave_sum(acc[c].re);
         acc[c].im = wave_sum(acc[c].im);
-        if (lane == 0) x[(int64_t)b.R[i] * NR + c] = acc[c];
+        if (lane == 0) x[(int64_t)i * NR + c] = acc[c];
       }
     }
   }
@@ -284,59 +285,39 @@ __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __rest
                         [&](int i, int c, zd d) { out[(int64_t)i * NR + c] = d; });
 }
 
-// Backward, per box: x_R -= sum of the partials; the result also goes to XR.
-template <int NR>
-__global__ void __launch_bounds__(256) solve_bfin_kernel(const SolveBox* __restrict__ boxes,
-                                                         const zd* __restrict__ Pbuf, zd* x, zd* __restrict__ XR) {
-  const SolveBox b = boxes[blockIdx.x];
-  for (int e = threadIdx.x; e < b.r * NR; e += 256) {
-    const int i = e / NR, c = e % NR;
-    const int64_t xi = (int64_t)b.R[i] * NR + c;
-    zd v = x[xi];
-    for (int ch = 0; ch < b.nchunk; ++ch) v = zsub(v, Pbuf[(b.p_off + (int64_t)ch * b.r + i) * NR + c]);
-    x[xi] = v;
-    XR[(b.xr_off + i) * NR + c] = v;
-  }
-}
-
-// Backward: Pt[k-chunk][l] = sum_{k in r-chunk} op(T)[l, k] x_R[k] (T, adjoint conj(T)), T: s x r.
+// Backward, per (box, 64 rows of S): x_R = XRg - sum of the backward partials, staged chunk by
+// chunk (the item of rows 0..63 also writes it to x[R]); x_S -= op(T) x_R for the item's rows
+// (T, adjoint conj(T)). A box with s = 0 has one item without rows.
 template <class FT, int NR>
-__global__ void __launch_bounds__(256) solve_bt_part_kernel(const SolveBox* __restrict__ boxes,
-                                                            const SweepTask* __restrict__ tasks,
-                                                            const zd* __restrict__ XR, zd* __restrict__ Pt,
-                                                            int adjoint) {
+__global__ void __launch_bounds__(256) solve_bt_kernel(const SolveBox* __restrict__ boxes,
+                                                       const SweepTask* __restrict__ tasks,
+                                                       const zd* __restrict__ XRg, const zd* __restrict__ Pbuf,
+                                                       zd* __restrict__ x, int adjoint) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
-  __shared__ zd xr[kSolveKr][NR];
-  const int kb = t.chunk * kSolveKr, kn = min(kSolveKr, b.r - kb);
-  for (int e = threadIdx.x; e < kn * NR; e += 256) xr[e / NR][e % NR] = XR[(b.xr_off + kb) * NR + e];
-  __syncthreads();
-  const FT* T = static_cast<const FT*>(b.T) + (int64_t)kb * b.s;
-  zd* out = Pt + (b.tp_off + (int64_t)t.chunk * b.s) * NR;
-  const int l = t.k0 + threadIdx.x;
-  if (l < t.k0 + t.kn) {
-    zd r[NR];
-    rowgemv<FT, NR>(T, b.s, l, kn, adjoint != 0, xr, r);
+  __shared__ zd xr[kSolveK][NR];
+  const int lane = threadIdx.x & 63;
+  const int l = t.k0 + lane;
+  const bool keep = t.k0 == 0;
+  zd acc[NR];
+  rows_times_xr<FT, NR>(static_cast<const FT*>(b.T), b.s, b.r, l, lane < t.kn, adjoint != 0, xr, acc,
+                        [&](int kb, int kn) {
+                          for (int e = threadIdx.x; e < kn * NR; e += 256) {
+                            const int k = e / NR, c = e % NR;
+                            zd v = XRg[(b.dx_off + kb + k) * NR + c];
+                            for (int ch = 0; ch < b.nchunk; ++ch)
+                              v = zsub(v, Pbuf[(b.p_off + (int64_t)ch * b.r + kb + k) * NR + c]);
+                            xr[k][c] = v;
+                            if (keep) x[(int64_t)b.R[kb + k] * NR + c] = v;
+                          }
+                        });
+  rows_reduce<NR>(xr, acc);
+  if (threadIdx.x < 64 && lane < t.kn) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) out[(int64_t)l * NR + c] = r[c];
-  }
-}
-
-// Backward: x_S -= sum of the partials, rows of one (box, s-row chunk).
-template <int NR>
-__global__ void __launch_bounds__(256) solve_bt_fin_kernel(const SolveBox* __restrict__ boxes,
-                                                           const SweepTask* __restrict__ tasks,
-                                                           const zd* __restrict__ Pt, zd* x) {
-  const SweepTask t = tasks[blockIdx.x];
-  const SolveBox b = boxes[t.box];
-  const int l = t.k0 + threadIdx.x;
-  if (l >= t.k0 + t.kn) return;
-#pragma unroll
-  for (int c = 0; c < NR; ++c) {
-    zd v{0.0, 0.0};
-    for (int ch = 0; ch < b.nkr; ++ch) v = zadd(v, Pt[(b.tp_off + (int64_t)ch * b.s + l) * NR + c]);
-    const int64_t xi = (int64_t)b.S[l] * NR + c;
-    x[xi] = zsub(x[xi], v);
+    for (int c = 0; c < NR; ++c) {
+      const int64_t xi = (int64_t)b.S[l] * NR + c;
+      x[xi] = zsub(x[xi], zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c])));
+    }
   }
 }
 
@@ -456,21 +437,10 @@ void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt,
   FMMLU_FT_NR_LAUNCH(solve_xr_part_kernel, nt, 0, boxes, tasks, x, Pxr, adjoint);
 }
 
-void launch_solve_xr_fin(const SolveBox* boxes, int nb, zd* x, zd* XR, const zd* Pxr, hipStream_t st, int nr) {
-  if (nb <= 0) return;
-  FMMLU_NR_LAUNCH(solve_xr_fin_kernel, nb, 0, boxes, x, XR, Pxr);
-}
-
-void launch_solve_y_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Yp, int adjoint,
-                         bool f32, hipStream_t st, int nr) {
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg,
+                    zd* y, int adjoint, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_NR_LAUNCH(solve_y_part_kernel, nt, 0, boxes, tasks, XR, Yp, adjoint);
-}
-
-void launch_solve_y_red(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Yp, zd* y, hipStream_t st,
-                        int nr) {
-  if (nt <= 0) return;
-  FMMLU_NR_LAUNCH(solve_y_red_kernel, nt, 0, boxes, tasks, Yp, y);
+  FMMLU_FT_NR_LAUNCH(solve_y_kernel, nt, 0, boxes, tasks, x, Pxr, XRg, y, adjoint);
 }
 
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
@@ -479,21 +449,10 @@ void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, c
   FMMLU_FT_NR_LAUNCH(solve_bpart_kernel, nt, 0, boxes, tasks, x, Pbuf, adjoint);
 }
 
-void launch_solve_bfin(const SolveBox* boxes, int nb, const zd* Pbuf, zd* x, zd* XR, hipStream_t st, int nr) {
-  if (nb <= 0) return;
-  FMMLU_NR_LAUNCH(solve_bfin_kernel, nb, 0, boxes, Pbuf, x, XR);
-}
-
-void launch_solve_bt_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XR, zd* Pt, int adjoint,
-                          bool f32, hipStream_t st, int nr) {
+void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, const zd* Pbuf, zd* x,
+                     int adjoint, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_NR_LAUNCH(solve_bt_part_kernel, nt, 0, boxes, tasks, XR, Pt, adjoint);
-}
-
-void launch_solve_bt_fin(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* Pt, zd* x, hipStream_t st,
-                         int nr) {
-  if (nt <= 0) return;
-  FMMLU_NR_LAUNCH(solve_bt_fin_kernel, nt, 0, boxes, tasks, Pt, x);
+  FMMLU_FT_NR_LAUNCH(solve_bt_kernel, nt, 0, boxes, tasks, XRg, Pbuf, x, adjoint);
 }
 
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
@@ -502,13 +461,13 @@ void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* s
   FMMLU_NR_LAUNCH(scatter_sub_kernel, (unsigned)((nd * nr + 255) / 256), 0, dst, ptr, src, nd, y, x);
 }
 
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* x, int adjoint, bool f32, hipStream_t st,
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* XRg, int adjoint, bool f32, hipStream_t st,
                        int nr) {
   if (nb <= 0) return;
   const size_t lds = (size_t)rmax * nr * sizeof(zd);
   if (lds > 65536)
     throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(rmax) + " DOFs exceeds the diagonal step's LDS bound");
-  FMMLU_FT_NR_LAUNCH(solve_diag_kernel, nb, lds, boxes, x, adjoint);
+  FMMLU_FT_NR_LAUNCH(solve_diag_kernel, nb, lds, boxes, XRg, adjoint);
 }
 
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,

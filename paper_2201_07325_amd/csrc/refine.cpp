@@ -34,8 +34,8 @@ constexpr int kRestart = 30;  // GMRES restart length
 void FactorImpl::matvec(int op, const zd* x, zd* y, hipStream_t st) {
   ensure_workspace();
   launch_permute(x, wmv, order_dev, n, 1, st);
-  launch_matvec(g, op, wmv, wx, wpart, st);
-  launch_permute(wx, y, order_dev, n, 0, st);
+  launch_matvec(g, op, wmv, ws1.x, wpart, st);
+  launch_permute(ws1.x, y, order_dev, n, 0, st);
 }
 
 bool FactorImpl::refine(const zd* b, zd* x, bool adjoint, double tol, int maxit, int* iters_out,
