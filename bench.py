@@ -386,8 +386,9 @@ def main():
     t_pair = float(np.median(times))
     solve_bytes = 2.0 * info["factor_bytes"]  # every factor byte once per sweep direction
 
-    # blocked multi-right-hand-side solves: 64 columns (8 blocks of 8) forward + adjoint
-    nrhs = 64
+    # blocked multi-right-hand-side solves: 64 columns (2 blocks of 32, matrix-core sweeps)
+    # forward + adjoint
+    nrhs, blk = 64, 32
     B = bd.reshape(n, 1).repeat(1, nrhs) * torch.exp(1j * torch.arange(nrhs, device=bd.device) * 0.1).reshape(1, nrhs)
     f.solve(B)
     f.solve_adjoint(B)
@@ -402,7 +403,8 @@ def main():
         mtimes.append(ev0.elapsed_time(ev1) / 1e3)
     t_multi = float(np.median(mtimes))
     rb = f.matvec(XB[:, nrhs - 1].contiguous(), 0) - B[:, nrhs - 1]
-    multi = {"nrhs": nrhs, "block": 8, "fwd_adj_solves_per_s": nrhs / t_multi, "ms_per_block_pair": t_multi * 1e3 / 8,
+    multi = {"nrhs": nrhs, "block": blk, "fwd_adj_solves_per_s": nrhs / t_multi,
+             "ms_per_block_pair": t_multi * 1e3 / (nrhs // blk),
              "relres_last_column": float(torch.linalg.norm(rb) / torch.linalg.norm(B[:, nrhs - 1]))}
     log(f"multi-rhs: {nrhs / t_multi:.0f} fwd+adj solves/s")
 
@@ -445,6 +447,15 @@ def main():
     roof["ms_per_step"] = d["ms"] / nsteps_d
     roof["source"] = "timed steps" if nsteps_d == args.steps else "separate fully profiled step"
     breakdown = {c: round(full[c]["ms"], 2) for c in classes}
+    # achieved rate per class: algorithmic TFLOP/s, or GB/s for the byte-counted classes
+    class_rate = {}
+    for c in classes:
+        if full[c]["ms"] <= 0:
+            continue
+        if full[c]["flops"] > 0:
+            class_rate[c] = {"TFLOP/s": round(full[c]["flops"] / (full[c]["ms"] * 1e-3) / 1e12, 2)}
+        elif full[c]["bytes"] > 0:
+            class_rate[c] = {"GB/s": round(full[c]["bytes"] / (full[c]["ms"] * 1e-3) / 1e9, 1)}
     # step-level roofline fraction: every class at its own bound (algorithmic flops at the FP64
     # peak, or algorithmic bytes at HBM bandwidth, whichever is longer) over the measured step
     ideal_ms = sum(max(full[c]["flops"] / PEAK_FP64, full[c]["bytes"] / PEAK_HBM) * 1e3 for c in classes)
@@ -475,6 +486,7 @@ def main():
         "n0": info["n0"],
         "factor_bytes": info["factor_bytes"],
         "class_ms_per_step": breakdown,
+        "class_rate": class_rate,
         "roofline": roof,
         "step_roofline": {"ideal_ms": ideal_ms, "measured_ms": dt * 1e3, "frac": ideal_ms / (dt * 1e3),
                           "note": "sum over kernel classes of max(flops / FP64 peak, bytes / HBM peak)"},

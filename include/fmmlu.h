@@ -164,6 +164,10 @@ fmmlu_status fmmlu_factor(fmmlu_tree_h t, const double* xyz, const double* norma
  * x = A_f^{-1} b with the factored inverse of Section 4.2:
  * A^{-1} ~ (W_1^{-1} ... W_M^{-1}) P_t D^{-1} P_t^T (V_M^{-1} ... V_1^{-1}).
  * b, x: device complex128, n x nrhs column-major (may alias: in-place is allowed).
+ * nrhs > 1 is applied in blocks of 32 columns (a ragged last block padded with zeros), each
+ * factor entry read once per block, on the matrix cores; a single column goes through the
+ * single-vector sweeps. The two agree to rounding (different summation order); each is
+ * deterministic run to run.
  */
 fmmlu_status fmmlu_solve(fmmlu_factor_h f, const void* b, void* x, int64_t nrhs, void* hip_stream);
 

@@ -2536,12 +2536,17 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     // top block is still running (a capture only records launches)
     {
       std::vector<SolveBox> all;
+      std::vector<SweepTask> dg;
       for (auto& fb : boxes) {
+        for (int i0 = 0; i0 < fb.r; i0 += kSolveOut)
+          dg.push_back(SweepTask{(int32_t)all.size(), i0, std::min(kSolveOut, fb.r - i0), 0, 0, 0});
         all.push_back(fb.dev);
         rmax_all = std::max(rmax_all, fb.r);
       }
       nall = (int)all.size();
       all_boxes = sg.up_to(arena, all);
+      ndg = (int)dg.size();
+      dg_tasks = sg.up_to(arena, dg);
     }
     tt[3] = Clock::now();
     if (use_graph && precapture && ActiveFactorization::count() == 1) {
@@ -2587,6 +2592,7 @@ void FactorImpl::alloc_ws(SolveWs& w, int nr) {
   w.p = al(pmax);
   w.xrp = al(xrpmax);
   w.xrg = al(dxlen);
+  w.xrd = al(dxlen);
   w.top = al((int64_t)n0 * (1 + nblk));
 }
 
@@ -2604,28 +2610,47 @@ void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) 
 void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* xc, int64_t ldx, int m,
                        bool adjoint, hipStream_t st) {
   const int adj = adjoint ? 1 : 0;
+  const bool blk = nr == kSolveBlock;
+  if (!blk && nr != 1) throw Error(FMMLU_EINVAL, "sweep of " + std::to_string(nr) + " columns");
   launch_permute(bc, w.x, order_dev, n, 1, st, nr, ldb, m);
   // V_1^{-1} ... V_M^{-1} (adjoint: W_1^{-H} ... W_M^{-H}), phase by phase: x_R partials, then
   // x_R and the updates y of S u N, then their deterministic sum into x
   for (auto& ph : phases) {
-    launch_solve_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st, nr);
-    launch_solve_y(ph.dboxes, ph.dy, ph.ny, w.x, w.xrp, w.xrg, w.y, adj, f32, st, nr);
+    if (blk) {
+      launch_blk_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st);
+      launch_blk_y(ph.dboxes, ph.dy, ph.ny, w.x, w.xrp, w.xrg, w.y, adj, f32, st);
+    } else {
+      launch_solve_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st, nr);
+      launch_solve_y(ph.dboxes, ph.dy, ph.ny, w.x, w.xrp, w.xrg, w.y, adj, f32, st, nr);
+    }
     launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, w.y, w.x, st, nr);
   }
-  // D^{-1} (adjoint D^{-H}): all pivot blocks (on the x_R buffer), then the top block
-  launch_solve_diag(all_boxes, nall, rmax_all, w.xrg, adj, f32, st, nr);
-  launch_solve_top(Ainv, n0, top_dev, w.x, w.top, adj, st, nr);
+  // D^{-1} (adjoint D^{-H}): all pivot blocks (x_R buffer to x_R buffer), then the top block
+  if (blk) {
+    launch_blk_diag(all_boxes, dg_tasks, ndg, w.xrg, w.xrd, adj, f32, st);
+    launch_solve_top_gather(n0, top_dev, w.x, w.top, st, nr);
+    launch_blk_top_part(Ainv, n0, w.top, w.top + (int64_t)n0 * nr, adj, st);
+    launch_solve_top_fin(n0, top_dev, w.top + (int64_t)n0 * nr, w.x, st, nr);
+  } else {
+    launch_solve_diag(all_boxes, nall, rmax_all, w.xrg, w.xrd, adj, f32, st, nr);
+    launch_solve_top(Ainv, n0, top_dev, w.x, w.top, adj, st, nr);
+  }
   // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse: x_R partials,
   // then x_R into x and the updates of x_S
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
-    launch_solve_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st, nr);
-    launch_solve_bt(it->dboxes, it->dbt, it->nbt, w.xrg, w.p, w.x, adj, f32, st, nr);
+    if (blk) {
+      launch_blk_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st);
+      launch_blk_bt(it->dboxes, it->dbt, it->nbt, w.xrd, w.p, w.x, adj, f32, st);
+    } else {
+      launch_solve_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st, nr);
+      launch_solve_bt(it->dboxes, it->dbt, it->nbt, w.xrd, w.p, w.x, adj, f32, st, nr);
+    }
   }
   launch_permute(w.x, xc, order_dev, n, 0, st, nr, ldx, m);
 }
 
-// the blocked sweeps keep kSolveBlock copies of the largest x_R in LDS for the diagonal step
-bool FactorImpl::blocked_ok() const { return (size_t)rmax_all * kSolveBlock * sizeof(zd) <= 65536; }
+// the blocked sweeps stage x_R in chunks: no bound on the redundant sets
+bool FactorImpl::blocked_ok() const { return true; }
 
 void FactorImpl::ensure_block_workspace() {
   if (wsb.x) return;

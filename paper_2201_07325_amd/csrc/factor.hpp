@@ -90,7 +90,8 @@ struct SolvePhase {
 // Workspace of the sweeps for blocks of nr right-hand sides (interleaved vectors)
 struct SolveWs {
   zd *x = nullptr, *y = nullptr, *top = nullptr, *p = nullptr, *xrp = nullptr;
-  zd* xrg = nullptr;  // x_R of every box (offset dx_off): forward result, D^{-1} applied in place
+  zd* xrg = nullptr;  // x_R of every box (offset dx_off) after the forward sweep
+  zd* xrd = nullptr;  // the same with D^{-1} applied
 };
 
 struct FactorImpl {
@@ -111,6 +112,8 @@ struct FactorImpl {
   int64_t ymax = 0, pmax = 0, xrpmax = 0;
   SolveBox* all_boxes = nullptr;  // every factored box, for the diagonal step
   int nall = 0, rmax_all = 0;
+  SweepTask* dg_tasks = nullptr;  // blocked diagonal step: (box of all_boxes, 64 outputs)
+  int ndg = 0;
   int64_t dxlen = 0;  // x_R of every box in one buffer (sum of r)
   int n0 = 0;
   int32_t* top_dev = nullptr;

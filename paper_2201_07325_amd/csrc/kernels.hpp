@@ -354,9 +354,11 @@ constexpr int kSolveRows = 64;   // rows per row-GEMV work item (one row per lan
 constexpr int kSolveK = 256;     // k-chunk of column GEMVs (over s or s + nN) and of staged x_R
 constexpr int kSolveOut = 64;    // outputs per column-GEMV work item
 
-// Every solve launcher takes nr = 1 or kSolveBlock right-hand sides; vectors inside the
-// sweeps are interleaved (entry i of right-hand side c at [i nr + c]).
-constexpr int kSolveBlock = 8;
+// Vectors inside the sweeps are interleaved (entry i of right-hand side c at [i nr + c]):
+// nr = 1 for the single-vector kernels below, nr = kSolveBlock for the blocked ones (matrix
+// cores, launch_blk_*); the permutations, scatter and top-block gather and sum take either.
+constexpr int kSolveBlock = 32;
+constexpr int kApplyK = 64;  // k-chunk of the staged vector block in the blocked sweeps (32 KiB)
 // forward: partials of op(T)^T x_S (T^T, adjoint T^H) per (box, s-chunk, output group)
 void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
                           bool f32, hipStream_t st, int nr = 1);
@@ -367,19 +369,36 @@ void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const
 // x[dst[d]] -= sum of y[src[q]] over ptr[d] <= q < ptr[d+1] (deterministic scatter)
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st, int nr = 1);
-// diagonal: x_R = Xi x_R (adjoint Xi^H x_R) in XRg for every box (rmax nr 16 bytes of LDS <= 64 KiB)
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* XRg, int adjoint, bool f32, hipStream_t st,
-                       int nr = 1);
+// diagonal: XRd = Xi XRg (adjoint Xi^H XRg) for every box (rmax 16 bytes of LDS <= 64 KiB)
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, const zd* XRg, zd* XRd, int adjoint, bool f32,
+                       hipStream_t st, int nr = 1);
 // backward: partials of op(Q)^T x_SN (Up, adjoint Lp^H) per (box, column chunk, output group)
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
                         int adjoint, bool f32, hipStream_t st, int nr = 1);
-// backward, per (box, 64 rows of S): x_R = XRg - sum of the partials (written to x[R] by the
+// backward, per (box, 64 rows of S): x_R = XRd - sum of the partials (written to x[R] by the
 // items of rows 0..63), then x_S -= op(T) x_R (T, adjoint conj(T)) for those rows
-void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, const zd* Pbuf, zd* x,
+void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pbuf, zd* x,
                      int adjoint, bool f32, hipStream_t st, int nr = 1);
-// top block: x_t = Ainv x_t (adjoint Ainv^H); tmp holds n0 (1 + nblk) nr entries
+// The same steps for blocks of kSolveBlock right-hand sides on the matrix cores (same work
+// items; the pivot blocks take one item per (box, 64 outputs) with box indexing the table of
+// all boxes; the top block's partials over chunks of 256 go to launch_solve_top_fin).
+void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
+                        bool f32, hipStream_t st);
+void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg, zd* y,
+                  int adjoint, bool f32, hipStream_t st);
+void launch_blk_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, zd* XRd, int adjoint,
+                     bool f32, hipStream_t st);
+void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pb, int adjoint,
+                      bool f32, hipStream_t st);
+void launch_blk_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pb, zd* x,
+                   int adjoint, bool f32, hipStream_t st);
+void launch_blk_top_part(const zd* Ainv, int n0, const zd* tmp, zd* part, int adjoint, hipStream_t st);
+// top block: x_t = Ainv x_t (adjoint Ainv^H); tmp holds n0 (1 + nblk) nr entries, nblk =
+// ceil(n0 / 256). Blocked: gather, launch_blk_top_part on (tmp, tmp + n0 nr), then the sum
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
                       hipStream_t st, int nr = 1);
+void launch_solve_top_gather(int n0, const int32_t* top, const zd* x, zd* tmp, hipStream_t st, int nr);
+void launch_solve_top_fin(int n0, const int32_t* top, const zd* part, zd* x, hipStream_t st, int nr);
 // permute between the caller's column-major vectors (ld, m <= nr active columns) and the
 // interleaved tree-order block: gather dst[i nr + c] = src[map[i] + c ld] (zero for c >= m),
 // or scatter dst[map[i] + c ld] = src[i nr + c] for c < m

@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
 // (128 x 128 blocks, one workgroup per compute unit, measured slower on the Schur updates:
 // 37.6 vs 29.4 ms.) The output rows and columns are read through the maps before the K loop,
 // and the epilogue issues all old values of C before its stores.
-template <bool SCAT, int TM>
+template <int OPA, bool SCAT, int TM>
 __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
     zgemm_lds_kernel(const GemmTask* __restrict__ tasks, int ntasks, const GemmSeg* __restrict__ segs,
                      const int32_t* __restrict__ utask) {
@@ -388,14 +388,20 @@ __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
   };
   // this lane's copies: A copy q of the wavefront is k = c / (TM / 64), rows 64 (c % (TM / 64))
   // + lane, with c = NLA wave + q; B copy q holds tile column j = 4 (NLA wave + q) + lane / 16
-  // at swizzled k = (lane % 16) ^ (j % 16)
+  // at swizzled k = (lane % 16) ^ (j % 16). A transposed (OPA 1, 2: rows of op(A) are columns
+  // of the stored matrix, contiguous in k) is copied like B: [TM rows][16 k], swizzled.
   int arow[NLA], ak[NLA], bcol[NLA], bk[NLA];
 #pragma unroll
   for (int q = 0; q < NLA; ++q) {
     const int c = NLA * wave + q;
-    ak[q] = c / (TM / 64);
-    arow[q] = min(row0 + 64 * (c % (TM / 64)) + lane, t.M - 1);
     const int j = 4 * c + (lane >> 4);
+    if (OPA == 0) {
+      ak[q] = c / (TM / 64);
+      arow[q] = min(row0 + 64 * (c % (TM / 64)) + lane, t.M - 1);
+    } else {
+      ak[q] = (lane & 15) ^ (j & 15);
+      arow[q] = min(row0 + j, t.M - 1);
+    }
     bcol[q] = min(col0 + j, t.N - 1);
     bk[q] = (lane & 15) ^ (j & 15);
   }
@@ -405,7 +411,8 @@ __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
 #pragma unroll
     for (int q = 0; q < NLA; ++q) {
       const int c = NLA * wave + q;
-      const zd* src = g.A + arow[q] + (int64_t)min(k0 + ak[q], kend - 1) * g.lda;
+      const zd* src = OPA == 0 ? g.A + arow[q] + (int64_t)min(k0 + ak[q], kend - 1) * g.lda
+                               : g.A + min(k0 + ak[q], kend - 1) + (int64_t)arow[q] * g.lda;
       __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)(la + 64 * c), 16, 0, 0);
     }
 #pragma unroll
@@ -458,8 +465,14 @@ __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
       zd av[AB], bv[BB];
 #pragma unroll
       for (int a = 0; a < AB; ++a) {
-        av[a] = As[k * TM + wr + 16 * a + cl];
-        if (!SCAT && kd >= 0 && row0 + wr + 16 * a + cl == kd + k) av[a].re -= 1.0;
+        if (OPA == 0) {
+          av[a] = As[k * TM + wr + 16 * a + cl];
+          if (!SCAT && kd >= 0 && row0 + wr + 16 * a + cl == kd + k) av[a].re -= 1.0;
+        } else {
+          const int rr = wr + 16 * a + cl;
+          av[a] = As[rr * 16 + (k ^ (rr & 15))];
+          if (OPA == 2) av[a].im = -av[a].im;
+        }
         if (!kin) av[a] = zd{0.0, 0.0};
       }
 #pragma unroll
@@ -526,13 +539,13 @@ void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, con
       hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
   } else if (opA == 0) {
     if (mapped)
-      hipLaunchKernelGGL((zgemm_lds_kernel<true, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_lds_kernel<0, true, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
     else
-      hipLaunchKernelGGL((zgemm_lds_kernel<false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+      hipLaunchKernelGGL((zgemm_lds_kernel<0, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
   } else if (opA == 1) {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<1, zd, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
+    hipLaunchKernelGGL((zgemm_lds_kernel<1, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
   } else {
-    hipLaunchKernelGGL((zgemm_mfma_kernel<2, zd, false, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
+    hipLaunchKernelGGL((zgemm_lds_kernel<2, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
   }
   FMMLU_HIP(hipGetLastError());
 }

@@ -206,20 +206,20 @@ __global__ void __launch_bounds__(256) scatter_sub_kernel(const int32_t* __restr
   x[xi] = zsub(x[xi], acc);
 }
 
-// Diagonal: x_R = Xi x_R (adjoint Xi^H x_R) in place in XRg, one box per workgroup, x_R in
-// dynamic LDS.
+// Diagonal: XRd = Xi XRg (adjoint Xi^H XRg), one box per workgroup, x_R in dynamic LDS.
 // Normal: lanes take rows, the four wavefronts split k, partial sums meet in LDS.
 // Adjoint: one wavefront per output, lanes over k (columns of Xi are contiguous).
 template <class FT, int NR>
-__global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restrict__ boxes, zd* XRg,
-                                                         int adjoint) {
+__global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restrict__ boxes, const zd* XRg,
+                                                         zd* XRd, int adjoint) {
   const SolveBox b = boxes[blockIdx.x];
   extern __shared__ zd xr_flat[];
   zd(*xr)[NR] = reinterpret_cast<zd(*)[NR]>(xr_flat);
   __shared__ zd part[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  zd* x = XRg + b.dx_off * NR;
-  for (int e = threadIdx.x; e < b.r * NR; e += 256) xr[e / NR][e % NR] = x[e];
+  const zd* xin = XRg + b.dx_off * NR;
+  zd* x = XRd + b.dx_off * NR;
+  for (int e = threadIdx.x; e < b.r * NR; e += 256) xr[e / NR][e % NR] = xin[e];
   __syncthreads();
   const FT* Xi = static_cast<const FT*>(b.Xi);
   const int r = b.r;
@@ -285,13 +285,13 @@ __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __rest
                         [&](int i, int c, zd d) { out[(int64_t)i * NR + c] = d; });
 }
 
-// Backward, per (box, 64 rows of S): x_R = XRg - sum of the backward partials, staged chunk by
+// Backward, per (box, 64 rows of S): x_R = XRd - sum of the backward partials, staged chunk by
 // chunk (the item of rows 0..63 also writes it to x[R]); x_S -= op(T) x_R for the item's rows
 // (T, adjoint conj(T)). A box with s = 0 has one item without rows.
 template <class FT, int NR>
 __global__ void __launch_bounds__(256) solve_bt_kernel(const SolveBox* __restrict__ boxes,
                                                        const SweepTask* __restrict__ tasks,
-                                                       const zd* __restrict__ XRg, const zd* __restrict__ Pbuf,
+                                                       const zd* __restrict__ XRd, const zd* __restrict__ Pbuf,
                                                        zd* __restrict__ x, int adjoint) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(256) solve_bt_kernel(const SolveBox* __restric
                         [&](int kb, int kn) {
                           for (int e = threadIdx.x; e < kn * NR; e += 256) {
                             const int k = e / NR, c = e % NR;
-                            zd v = XRg[(b.dx_off + kb + k) * NR + c];
+                            zd v = XRd[(b.dx_off + kb + k) * NR + c];
                             for (int ch = 0; ch < b.nchunk; ++ch)
                               v = zsub(v, Pbuf[(b.p_off + (int64_t)ch * b.r + kb + k) * NR + c]);
                             xr[k][c] = v;
@@ -418,16 +418,11 @@ __global__ void __launch_bounds__(256) permute_kernel(const zd* __restrict__ src
 
 #define FMMLU_FT_NR_LAUNCH(kern, grid, lds, ...)                                       \
   do {                                                                                  \
-    if (nr != 1 && nr != kSolveBlock)                                                   \
-      throw Error(FMMLU_EINVAL, "solve block of " + std::to_string(nr) + " columns");   \
-    if (f32 && nr == 1)                                                                 \
+    if (nr != 1) throw Error(FMMLU_EINVAL, "single-vector sweep kernel with " + std::to_string(nr) + " columns"); \
+    if (f32)                                                                            \
       hipLaunchKernelGGL((kern<zf, 1>), dim3(grid), dim3(256), lds, st, __VA_ARGS__);   \
-    else if (f32)                                                                       \
-      hipLaunchKernelGGL((kern<zf, kSolveBlock>), dim3(grid), dim3(256), lds, st, __VA_ARGS__); \
-    else if (nr == 1)                                                                   \
-      hipLaunchKernelGGL((kern<zd, 1>), dim3(grid), dim3(256), lds, st, __VA_ARGS__);   \
     else                                                                                \
-      hipLaunchKernelGGL((kern<zd, kSolveBlock>), dim3(grid), dim3(256), lds, st, __VA_ARGS__); \
+      hipLaunchKernelGGL((kern<zd, 1>), dim3(grid), dim3(256), lds, st, __VA_ARGS__);   \
     FMMLU_HIP(hipGetLastError());                                                       \
   } while (0)
 
@@ -449,10 +444,10 @@ void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, c
   FMMLU_FT_NR_LAUNCH(solve_bpart_kernel, nt, 0, boxes, tasks, x, Pbuf, adjoint);
 }
 
-void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, const zd* Pbuf, zd* x,
+void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pbuf, zd* x,
                      int adjoint, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_NR_LAUNCH(solve_bt_kernel, nt, 0, boxes, tasks, XRg, Pbuf, x, adjoint);
+  FMMLU_FT_NR_LAUNCH(solve_bt_kernel, nt, 0, boxes, tasks, XRd, Pbuf, x, adjoint);
 }
 
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
@@ -461,27 +456,40 @@ void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* s
   FMMLU_NR_LAUNCH(scatter_sub_kernel, (unsigned)((nd * nr + 255) / 256), 0, dst, ptr, src, nd, y, x);
 }
 
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, zd* XRg, int adjoint, bool f32, hipStream_t st,
-                       int nr) {
+void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, const zd* XRg, zd* XRd, int adjoint, bool f32,
+                       hipStream_t st, int nr) {
   if (nb <= 0) return;
   const size_t lds = (size_t)rmax * nr * sizeof(zd);
   if (lds > 65536)
     throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(rmax) + " DOFs exceeds the diagonal step's LDS bound");
-  FMMLU_FT_NR_LAUNCH(solve_diag_kernel, nb, lds, boxes, XRg, adjoint);
+  FMMLU_FT_NR_LAUNCH(solve_diag_kernel, nb, lds, boxes, XRg, XRd, adjoint);
 }
 
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
                       hipStream_t st, int nr) {
   if (n0 <= 0) return;
-  FMMLU_NR_LAUNCH(gather_top_kernel, (n0 * nr + 255) / 256, 0, top, n0, x, tmp);
+  if (nr != 1) throw Error(FMMLU_EINVAL, "single-vector top-block step with " + std::to_string(nr) + " columns");
+  hipLaunchKernelGGL(gather_top_kernel<1>, dim3((n0 + 255) / 256), dim3(256), 0, st, top, n0, x, tmp);
   if (!adjoint) {
     const int nblk = (n0 + 255) / 256;
-    zd* part = tmp + (int64_t)n0 * nr;
-    FMMLU_NR_LAUNCH(top_n_part_kernel, dim3(nblk, nblk), 0, Ainv, n0, tmp, part);
-    FMMLU_NR_LAUNCH(top_n_fin_kernel, (n0 * nr + 255) / 256, 0, n0, nblk, top, part, x);
+    zd* part = tmp + (int64_t)n0;
+    hipLaunchKernelGGL(top_n_part_kernel<1>, dim3(nblk, nblk), dim3(256), 0, st, Ainv, n0, tmp, part);
+    hipLaunchKernelGGL(top_n_fin_kernel<1>, dim3((n0 + 255) / 256), dim3(256), 0, st, n0, nblk, top, part, x);
   } else {
-    FMMLU_NR_LAUNCH(top_c_kernel, (n0 + 3) / 4, 0, Ainv, n0, top, tmp, x);
+    hipLaunchKernelGGL(top_c_kernel<1>, dim3((n0 + 3) / 4), dim3(256), 0, st, Ainv, n0, top, tmp, x);
   }
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_solve_top_gather(int n0, const int32_t* top, const zd* x, zd* tmp, hipStream_t st, int nr) {
+  if (n0 <= 0) return;
+  FMMLU_NR_LAUNCH(gather_top_kernel, (n0 * nr + 255) / 256, 0, top, n0, x, tmp);
+}
+
+void launch_solve_top_fin(int n0, const int32_t* top, const zd* part, zd* x, hipStream_t st, int nr) {
+  if (n0 <= 0) return;
+  const int nblk = (n0 + 255) / 256;
+  FMMLU_NR_LAUNCH(top_n_fin_kernel, (n0 * nr + 255) / 256, 0, n0, nblk, top, part, x);
 }
 
 void launch_permute(const zd* src, zd* dst, const int64_t* map, int64_t n, int gather,

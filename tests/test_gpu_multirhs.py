@@ -1,8 +1,8 @@
-"""Blocked multi-right-hand-side solves (blocks of 8 columns through the same sweeps) give
-the single-column results exactly: every entry of every column goes through the same
-operations in the same order. Forward and adjoint, graph and eager paths, float64 and
-float32 factors, block sizes below, at and above the block width; plus the residual of
-the blocked solution with the exact float64 matvec."""
+"""Blocked multi-right-hand-side solves (blocks of 32 columns through the matrix-core sweeps)
+against the single-column sweeps (same factors, different summation order: within 1e-11
+relative per column), run-to-run bitwise identical, forward and adjoint, graph and eager
+paths, float64 and float32 factors, block sizes below, at and above the block width; plus
+the residual of the blocked solution with the exact float64 matvec and the oracle's dense LU."""
 import sys
 
 import numpy as np
@@ -40,17 +40,20 @@ def test_blocked_solves_match_single_columns(precision):
     eps = 1e-6
     f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=eps, leaf_size=32, precision=precision)
     rng = np.random.default_rng(7)
-    for nrhs in (2, 8, 11, 17):
+    for nrhs in (2, 32, 33, 70):
         B = torch.as_tensor(rng.standard_normal((s.n, nrhs)) + 1j * rng.standard_normal((s.n, nrhs))).cuda()
         for graph in (True, False):
             f.set_solve_graph(graph)
             for adjoint in (False, True):
                 X = f.solve_adjoint(B) if adjoint else f.solve(B)
+                X2 = f.solve_adjoint(B) if adjoint else f.solve(B)
                 ref = _cols(f, B, adjoint)
                 torch.cuda.synchronize()
-                same = torch.equal(X, ref)
-                say(f"precision {precision} nrhs {nrhs} graph {graph} adjoint {adjoint}: equal {same}")
-                assert same
+                rel = float((torch.linalg.norm(X - ref, dim=0) / torch.linalg.norm(ref, dim=0)).max())
+                say(f"precision {precision} nrhs {nrhs} graph {graph} adjoint {adjoint}: "
+                    f"vs single columns {rel:.2e}, repeat equal {torch.equal(X, X2)}")
+                assert torch.equal(X, X2)
+                assert rel < 1e-11
     f.set_solve_graph(True)
     # residual of a blocked forward solve, column by column, with the exact matvec
     B = torch.as_tensor(rng.standard_normal((s.n, 9)) + 1j * rng.standard_normal((s.n, 9))).cuda()
@@ -64,14 +67,14 @@ def test_blocked_solves_match_single_columns(precision):
 
 
 def test_blocked_solves_match_oracle_dense_lu():
-    """Eleven columns (a block of eight and a ragged block of three), forward and adjoint,
+    """Thirty-five columns (a block of 32 and a ragged block of three), forward and adjoint,
     against the oracle's dense LU column by column (<= 10 eps)."""
     s = synth.unit_sphere(3000)
     f = fm.Factor(s.points, s.normals, s.weights, s.k, s.eta, eps=s.eps)
     a = dense.system_matrix(s.points, s.normals, s.weights, s.k, s.eta)
     lu = dense.DenseLU(a)
     rng = np.random.default_rng(11)
-    B = rng.standard_normal((s.n, 11)) + 1j * rng.standard_normal((s.n, 11))
+    B = rng.standard_normal((s.n, 35)) + 1j * rng.standard_normal((s.n, 35))
     B[:, 0] = np.sqrt(s.weights) * synth.point_source_data(s.points, s.k)
     Bd = torch.as_tensor(B).cuda()
     for adjoint in (False, True):
@@ -88,7 +91,8 @@ def test_blocked_solve_in_place_and_zero_columns():
     rng = np.random.default_rng(3)
     B = torch.as_tensor(rng.standard_normal((s.n, 5)) + 1j * rng.standard_normal((s.n, 5))).cuda()
     B[:, 2] = 0
-    ref = _cols(f, B, False)
+    ref = f.solve(B)
+    torch.cuda.synchronize()
     assert torch.count_nonzero(ref[:, 2]) == 0
     # column-major n x 5 in one buffer, solved in place through the C entry point
     bcol = B.t().contiguous()
