@@ -1808,9 +1808,10 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           zd* G = sg.dev.alloc_n<zd>((size_t)mm);
           bp.R = sg.dev.alloc_n<zd>((size_t)mm);
           bp.T = sg.dev.alloc_n<zd>((size_t)mm);
-          // G = M^H M is Hermitian: its lower triangle of tiles only (pchol reads no more)
+          // G = M^H M is Hermitian: its lower triangle of tiles, completed by the sum of the
+          // split-K partials (the pivoting reads rows of G as contiguous columns)
           gg.add_split(part, bp.m, bp.m, bp.m, bp.M, bp.rows, bp.M, bp.rows, bp.rows, KCH, mm, true);
-          SumTask sm{part, G, mm, mm, nsplit, 0, su};
+          SumTask sm{part, G, mm, mm, nsplit, bp.m, su};
           su += (mm + 255) / 256;
           st_.push_back(sm);
           zd* Rp = sg.dev.alloc_n<zd>((size_t)mm);
@@ -1831,7 +1832,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             t.dgs = sg.dev.alloc_n<double>((size_t)m + 1);
             t.ist = sg.dev.alloc_n<int32_t>((size_t)2 * m + 2);
             gu.add(t.G, m, m, m, nullptr, nullptr, {GemmSeg{t.Rb, t.Rb, kPcholNb, kPcholNb, kPcholNb, 0}}, -1.0, 0.0,
-                   1.0, true);
+                   1.0, false);
             gu.tasks.back().skip = t.ist + 2 * m + 1;  // no downdate once the box's pivoting stopped
           }
           gu.prepare(sg);

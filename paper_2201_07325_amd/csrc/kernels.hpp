@@ -180,11 +180,13 @@ void launch_gather_cross(const CrossTask* tasks, int ntasks, int64_t nunits, con
                          const void* pool, bool pool32, hipStream_t st);
 
 // ---- sum of split-K partials: out[e] = sum_k part[k*stride + e], e < count ----
+// herm = m > 0: out is m x m (count = m m) and only the lower triangle's partials exist; the
+// sum goes to the lower triangle and its conjugate to the upper (a full Hermitian matrix)
 struct SumTask {
   const zd* part;
   zd* out;
   int64_t count, stride;
-  int32_t nsplit, pad;
+  int32_t nsplit, herm;
   int64_t unit_begin;  // units of 256 elements
 };
 void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStream_t st);
@@ -194,7 +196,7 @@ void launch_sum_parts(const SumTask* tasks, int ntasks, int64_t nunits, hipStrea
 // Schur complement (the squared norms of the remaining columns after projection) is updated
 // exactly. Outputs as CpqrTask: perm, rank, T = R11^{-1} R12 (ld m).
 struct PcholTask {
-  zd* G;           // m x m, ld m, Hermitian, lower triangle (the blocked form overwrites it)
+  zd* G;           // m x m, ld m, Hermitian, both triangles (the blocked form overwrites it)
   zd* Rt;          // m x m scratch: rows of R by original column, Rt[l * m + c]
   zd* Rp;          // m x m scratch: R in pivoted column order, ld m
   int32_t* perm;
@@ -210,7 +212,7 @@ struct PcholTask {
 // Blocked greedy pivoted Cholesky (matrices of m <= kPcholThreadsB columns): launch block
 // b = 0, 1, ... takes pivots kPcholNb b .. kPcholNb (b + 1) - 1 left-looking within the block
 // (rows of the block in registers, one column per thread) against G, then the caller
-// downdates G -= Rb^H Rb (lower tiles) before the next block; pchol_finish writes rank,
+// downdates G -= Rb^H Rb (both triangles) before the next block; pchol_finish writes rank,
 // perm and R in pivoted order. Equal to launch_pchol's result in exact arithmetic.
 constexpr int kPcholNb = 16;
 constexpr int kPcholThreadsB = 1024;

@@ -378,9 +378,16 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restric
   const SumTask t = tasks[ti];
   const int64_t e = (u - t.unit_begin) * 256 + threadIdx.x;
   if (e >= t.count) return;
+  int64_t i = 0, j = 0;
+  if (t.herm > 0) {
+    i = e % t.herm;
+    j = e / t.herm;
+    if (i < j) return;
+  }
   zd a{0.0, 0.0};
   for (int k = 0; k < t.nsplit; ++k) a = zadd(a, t.part[(int64_t)k * t.stride + e]);
   t.out[e] = a;
+  if (t.herm > 0 && i > j) t.out[j + i * t.herm] = zconj(a);
 }
 
 // Left-looking pivoted Cholesky of the Gram matrix (greedy CPQR of M in exact arithmetic).
@@ -388,8 +395,9 @@ __global__ void __launch_bounds__(256) sum_parts_kernel(const SumTask* __restric
 // column c not yet chosen, p_k maximising the Schur-complement diagonal dg (the squared norm
 // of column c of M after projection on the chosen columns; ties to the lowest column). R is
 // kept row-major by original column (Rt[l m + c]), so the sum is one coalesced pass over the
-// previous rows (split into row slices when m is small). Only the lower triangle of G is
-// read: G[p_k, c] = conj(G[c, p_k]) for c >= p_k (contiguous), G[p_k, c] for c < p_k. Positions follow column-pivoted QR's exchange rule (step k swaps positions
+// previous rows (split into row slices when m is small). G is stored with both triangles, so
+// row p_k is read as the contiguous column, G[p_k, c] = conj(G[c, p_k]). Positions follow
+// column-pivoted QR's exchange rule (step k swaps positions
 // k and pos(p_k)). At the end R is written in pivoted column order, column-major (rows < rank,
 // upper triangle only), for the back substitution.
 // (value, index) ordering of pivot searches: larger value, ties to the smaller index
@@ -457,9 +465,9 @@ __device__ inline void pchol_write_out(const PcholTask& t, int s, const int* pv,
   }
 }
 
-// G[p, c] from the lower triangle of the Hermitian G (column-major, ld m)
+// G[p, c] of the Hermitian G (column-major, ld m, both triangles): column p, conjugated
 __device__ inline zd pchol_grow(const zd* __restrict__ G, int m, int p, int c) {
-  return c >= p ? zconj(G[c + (int64_t)p * m]) : G[p + (int64_t)c * m];
+  return zconj(G[c + (int64_t)p * m]);
 }
 
 __device__ inline bool pchol_better(double v, int c, double bv, int bc) {
