@@ -1236,7 +1236,7 @@ __global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTas
 
 // ---- stepped Gauss-Jordan: one launch per panel (see GjStepArgs)
 constexpr int kStepRpt = kGjStepMax / kGjStepThreads;  // rows per thread of workgroup 0
-constexpr int kStepCols = 16;                          // columns per updating workgroup
+constexpr int kStepCols = 8;                           // columns per updating workgroup
 
 __global__ void __launch_bounds__(kGjStepThreads) gj_step_kernel(GjStepArgs g, int j) {
   constexpr int NB = kGjStepNb, NT = kGjStepThreads, NW = NT / 64, RPT = kStepRpt;
