@@ -487,6 +487,7 @@ def main():
         "factor_bytes": info["factor_bytes"],
         "class_ms_per_step": breakdown,
         "class_rate": class_rate,
+        "gemm_autotune": fm.gemm_tuning(),
         "roofline": roof,
         "step_roofline": {"ideal_ms": ideal_ms, "measured_ms": dt * 1e3, "frac": ideal_ms / (dt * 1e3),
                           "note": "sum over kernel classes of max(flops / FP64 peak, bytes / HBM peak)"},

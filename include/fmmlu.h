@@ -98,7 +98,13 @@ typedef struct {
   const int64_t* corr_row_ptr;
   const int64_t* corr_col;
   const double* corr_a;
-  int32_t reserved[4];
+  int32_t gemm_autotune;      /* 1 (default): before the first factorization on a device, time
+                                 every kernel of the batched GEMM per use and K bucket on a
+                                 synthetic batch and use the fastest (fmmlu_gemm_tuning); 0: the
+                                 default kernels; 2, 3, 4 (testing): one kernel for every GEMM
+                                 (direct-to-LDS where it applies, register-staged with eight or
+                                 four wavefronts) */
+  int32_t reserved[3];
 } fmmlu_opts;
 
 /* Per-factorization statistics. */
@@ -355,6 +361,16 @@ fmmlu_status fmmlu_dense_inverse(const void* a, int64_t n, int64_t count, void* 
  * factorizations, not while one is running on another thread. Errors: EHIP.
  */
 fmmlu_status fmmlu_trim_caches(void);
+
+/*
+ * The GEMM autotuner's table for the current device (opts.gemm_autotune): for every use of the
+ * batched GEMM (precision, mapped output, op(A)) and K bucket, the kernel chosen and the
+ * measured milliseconds of each candidate on the synthetic batch, as a NUL-terminated JSON
+ * object. buf: host, len bytes (may be NULL with len 0); *needed (may be NULL) receives the
+ * bytes required including the NUL. ESTATE if no factorization has tuned the device yet;
+ * EINVAL if len is too small (nothing written).
+ */
+fmmlu_status fmmlu_gemm_tuning(char* buf, int64_t len, int64_t* needed);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char* fmmlu_last_error(void);

@@ -44,7 +44,7 @@ class Opts(C.Structure):
                 ("profile", C.c_int32), ("id_route", C.c_int32), ("test_zero_pivot_block", C.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("corr_row_ptr", C.c_void_p), ("corr_col", C.c_void_p), ("corr_a", C.c_void_p),
-                ("reserved", C.c_int32 * 4)]
+                ("gemm_autotune", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 def _torch_alloc(nbytes, stream, ctx):
@@ -135,6 +135,7 @@ def lib():
         "fmmlu_kernel_block": (I32, [P, P, P, I64, D, D, P, I64, P, I64, P, P]),
         "fmmlu_proxy_block": (I32, [P, P, P, I64, D, D, P, I64, PD, D, I32, P, P]),
         "fmmlu_trim_caches": (I32, []),
+        "fmmlu_gemm_tuning": (I32, [C.c_char_p, I64, C.POINTER(I64)]),
         "fmmlu_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -235,7 +236,7 @@ class Factor:
 
     def __init__(self, points, normals, weights, k, eta, eps=1e-6, leaf_size=64, tree=None,
                  proxy_radius=2.5, proxy_min_points=64, precision=0, verbose=0, mem_cap=0, profile=False,
-                 id_route=0, allocator="torch", test_zero_pivot_block=-1, corrections=None):
+                 id_route=0, allocator="torch", test_zero_pivot_block=-1, corrections=None, gemm_autotune=1):
         L = lib()
         self.points = _soa(points)
         self.n = self.points.size // 3
@@ -257,6 +258,7 @@ class Factor:
         o.profile = int(profile) if isinstance(profile, int) and not isinstance(profile, bool) else (1 if profile else 0)
         o.id_route = int(id_route)
         o.test_zero_pivot_block = int(test_zero_pivot_block)
+        o.gemm_autotune = int(gemm_autotune)
         _set_allocator(o, allocator)
         keep = None
         if corrections is not None:
@@ -443,6 +445,20 @@ def trim_caches():
     """Free the device and pinned host memory that released factorizations keep for reuse
     by later ones (call between factorizations)."""
     _check(lib().fmmlu_trim_caches())
+
+
+def gemm_tuning():
+    """The GEMM autotuner's table for the current device (dict: the kernel chosen per use and
+    K bucket, and each candidate's measured milliseconds), or None before any factorization
+    has tuned it."""
+    import json
+    need = I64(0)
+    st = lib().fmmlu_gemm_tuning(None, 0, C.byref(need))
+    if st != 0:
+        return None
+    buf = C.create_string_buffer(int(need.value))
+    _check(lib().fmmlu_gemm_tuning(buf, need.value, None))
+    return json.loads(buf.value.decode())
 
 
 def release_all():

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfmmlu.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "batch.cpp", "factor.cpp", "refine.cpp", "tree.cpp", "kernels_gen.hip", "kernels_la.hip",
+SOURCES = ["api.cpp", "batch.cpp", "factor.cpp", "refine.cpp", "tree.cpp", "tune.cpp", "kernels_gen.hip", "kernels_la.hip",
            "kernels_solve.hip", "kernels_apply.hip", "kernels_blas1.hip", "kernels_far.hip", "kernels_gemm.hip"]
 ARCH = os.environ.get("FMMLU_ARCH", "gfx950")
 

@@ -14,6 +14,7 @@
 #include "common.hpp"
 #include "batch.hpp"
 #include "factor.hpp"
+#include "tune.hpp"
 #include "kernels.hpp"
 #include "tree.hpp"
 
@@ -76,6 +77,7 @@ fmmlu_opts checked_opts(fmmlu_tree_h t, const double* xyz, const double* normals
   if (!(o.proxy_radius >= 1.5 && o.proxy_radius <= 10.0)) throw Error(FMMLU_EINVAL, "proxy_radius must be in [1.5, 10]");
   if (o.proxy_min_points < 1) throw Error(FMMLU_EINVAL, "proxy_min_points must be >= 1");
   if (o.id_route < 0 || o.id_route > 2) throw Error(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
+  if (o.gemm_autotune < 0 || o.gemm_autotune > 4) throw Error(FMMLU_EINVAL, "gemm_autotune must be in 0..4");
   if ((o.alloc == nullptr) != (o.free == nullptr))
     throw Error(FMMLU_EINVAL, "alloc and free must be given together");
   if ((o.corr_row_ptr == nullptr) != (o.corr_col == nullptr) || (o.corr_row_ptr == nullptr) != (o.corr_a == nullptr))
@@ -154,6 +156,7 @@ fmmlu_status fmmlu_default_opts(fmmlu_opts* opts) {
   opts->profile = 0;
   opts->id_route = 0;
   opts->test_zero_pivot_block = -1;
+  opts->gemm_autotune = 1;
   return FMMLU_OK;
 }
 
@@ -624,6 +627,18 @@ fmmlu_status fmmlu_proxy_block(const double* xyz, const double* nrm, const doubl
 
 fmmlu_status fmmlu_trim_caches(void) {
   return guarded([&] { trim_reuse_caches(); });
+}
+
+fmmlu_status fmmlu_gemm_tuning(char* buf, int64_t len, int64_t* needed) {
+  return guarded([&] {
+    const std::string r = gemm_tune_report();
+    if (r.empty()) throw Error(FMMLU_ESTATE, "no GEMM tuning on this device yet");
+    const int64_t need = (int64_t)r.size() + 1;
+    if (needed) *needed = need;
+    if (buf == nullptr && len == 0) return;
+    if (!buf || len < need) throw Error(FMMLU_EINVAL, "buffer too small for the tuning table");
+    std::memcpy(buf, r.c_str(), (size_t)need);
+  });
 }
 
 const char* fmmlu_last_error(void) { return g_last_error.c_str(); }

@@ -26,6 +26,7 @@
 //   5. Schur update of the near-near tiles with X_{.R} U
 // The host only plans (index lists, task descriptors) and reads back ranks and pivots.
 #include "factor.hpp"
+#include "tune.hpp"
 
 #include <algorithm>
 #include <array>
@@ -792,8 +793,15 @@ struct GemmBatch {
   void launch(Stage& sg, int opA, bool c32 = false) {
     if (tasks.empty()) return;
     bool mapped = false;
-    for (auto& t : tasks) mapped = mapped || t.rmap || t.cmap;
-    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.go(), mapped, du);
+    int64_t kmax = 0;  // longest inner dimension of one product (the autotuner's bucket)
+    for (auto& t : tasks) {
+      mapped = mapped || t.rmap || t.cmap;
+      int64_t k = 0;
+      for (int q = 0; q < t.nseg; ++q) k += segs[(size_t)t.seg_begin + q].K;
+      kmax = std::max<int64_t>(kmax, t.kchunk > 0 ? std::min<int64_t>(k, t.kchunk) : k);
+    }
+    launch_gemm(opA, dt, (int)tasks.size(), units, ds, c32, sg.go(), mapped, du,
+                gemm_tuned_kernel(c32, mapped, opA, kmax));
   }
   void run(Stage& sg, int opA) {
     prepare(sg);
@@ -1255,6 +1263,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   info.nlevels = tree.nlevels;
   info.precision = opts.precision;
   mem.configure(opts, st);
+  // measure the GEMM kernels on this device once per process (later calls return at once);
+  // 2, 3, 4 force one kernel for every GEMM of this factorization (testing)
+  struct ForceReset {
+    ~ForceReset() { gemm_force_kernel(GK_AUTO); }
+  } force_reset;
+  if (opts.gemm_autotune == 1) gemm_autotune(mem, st);
+  gemm_force_kernel(opts.gemm_autotune >= 2 ? opts.gemm_autotune - 2 : GK_AUTO);
   // whatever is released after this call (also when an error unwinds it) is ordered on the
   // null stream: the caller's stream may be gone by then
   struct StreamReset {

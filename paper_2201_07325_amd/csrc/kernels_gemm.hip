@@ -524,29 +524,52 @@ __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
 // LDS of the direct-copy kernels: two buffers of A and B (16 K steps of TM complex each)
 constexpr size_t kLdsGemmBytes64 = 2 * 32 * 64 * sizeof(zd);
 
+int gemm_default_kernel(bool c32, bool mapped, int) {
+  if (c32) return mapped ? GK_REG8 : GK_REG4;
+  return GK_LDS;
+}
+
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
-                 hipStream_t st, bool mapped, const int32_t* utask) {
+                 hipStream_t st, bool mapped, const int32_t* utask, int kernel) {
   if (ntasks <= 0 || nunits <= 0) return;
-  // eight wavefronts per block, except for the transposed-A elimination products (opA = 1),
-  // which measured faster with four
-  const dim3 g((unsigned)nunits), b4(256), b8(512);
+  if (opA < 0 || opA > 2) throw Error(FMMLU_EINVAL, "GEMM op(A) must be 0, 1 or 2");
   if (mapped && opA != 0) throw Error(FMMLU_EINVAL, "mapped GEMM takes opA = N");
+  if (c32 && opA != 0) throw Error(FMMLU_EINVAL, "float32 GEMM takes opA = N");
+  const int k = kernel == GK_AUTO ? gemm_default_kernel(c32, mapped, opA) : kernel;
+  if (k != GK_LDS && k != GK_REG8 && k != GK_REG4) throw Error(FMMLU_EINVAL, "unknown GEMM kernel");
+  if (c32 && k == GK_LDS) throw Error(FMMLU_EINVAL, "the direct-to-LDS GEMM is float64 only");
+  const dim3 g((unsigned)nunits), b4(256), b8(512);
+#define FMMLU_GEMM_REG(OP, CT, SC)                                                                     \
+  do {                                                                                                \
+    if (k == GK_REG8)                                                                                 \
+      hipLaunchKernelGGL((zgemm_mfma_kernel<OP, CT, SC, 8>), g, b8, 0, st, tasks, ntasks, segs, utask); \
+    else                                                                                              \
+      hipLaunchKernelGGL((zgemm_mfma_kernel<OP, CT, SC, 4>), g, b4, 0, st, tasks, ntasks, segs, utask); \
+  } while (0)
   if (c32) {
-    if (opA != 0) throw Error(FMMLU_EINVAL, "float32 GEMM takes opA = N");
     if (mapped)
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, true, 8>), g, b8, 0, st, tasks, ntasks, segs, utask);
+      FMMLU_GEMM_REG(0, zf, true);
     else
-      hipLaunchKernelGGL((zgemm_mfma_kernel<0, zf, false, 4>), g, b4, 0, st, tasks, ntasks, segs, utask);
-  } else if (opA == 0) {
+      FMMLU_GEMM_REG(0, zf, false);
+  } else if (k == GK_LDS) {
     if (mapped)
       hipLaunchKernelGGL((zgemm_lds_kernel<0, true, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
-    else
+    else if (opA == 0)
       hipLaunchKernelGGL((zgemm_lds_kernel<0, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+    else if (opA == 1)
+      hipLaunchKernelGGL((zgemm_lds_kernel<1, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+    else
+      hipLaunchKernelGGL((zgemm_lds_kernel<2, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+  } else if (mapped) {
+    FMMLU_GEMM_REG(0, zd, true);
+  } else if (opA == 0) {
+    FMMLU_GEMM_REG(0, zd, false);
   } else if (opA == 1) {
-    hipLaunchKernelGGL((zgemm_lds_kernel<1, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+    FMMLU_GEMM_REG(1, zd, false);
   } else {
-    hipLaunchKernelGGL((zgemm_lds_kernel<2, false, 64>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+    FMMLU_GEMM_REG(2, zd, false);
   }
+#undef FMMLU_GEMM_REG
   FMMLU_HIP(hipGetLastError());
 }
 
