@@ -120,14 +120,14 @@ __host__ __device__ inline int64_t gemm_task_tiles(int M, int N, int lower) {
   return gemm_task_tiles_t(M, N, lower, kGemmTile);
 }
 // Kernels of the batched GEMM (all 64 x 64 output blocks): operands copied straight into
-// double-buffered LDS by eight wavefronts (float64 only), or staged through registers by eight
-// or four wavefronts. GK_AUTO: the library's default for the use, gemm_default_kernel.
+// double-buffered LDS by eight wavefronts (float64 products; a float32 C gets them rounded as
+// stored), or staged through registers by eight or four wavefronts (float32 C: float32
+// products). GK_AUTO: the library's default for the use, gemm_default_kernel.
 enum GemmKernel { GK_AUTO = -1, GK_LDS = 0, GK_REG8 = 1, GK_REG4 = 2 };
 int gemm_default_kernel(bool c32, bool mapped, int opA);
 // mapped: tasks may carry rmap / cmap (a separate kernel instance); otherwise they are ignored.
 // utask (optional, nunits entries): the task of each output block, in place of a search of
-// the tasks' unit_begin prefix sums. kernel: a GemmKernel (EINVAL where it does not implement
-// the use: GK_LDS with c32).
+// the tasks' unit_begin prefix sums. kernel: a GemmKernel.
 void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, const GemmSeg* segs, bool c32,
                  hipStream_t st, bool mapped = false, const int32_t* utask = nullptr, int kernel = GK_AUTO);
 

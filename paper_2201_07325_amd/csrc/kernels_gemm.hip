@@ -1,6 +1,7 @@
-// Batched complex GEMM on the matrix cores: float64 (v_mfma_f64_16x16x4f64) for float64
-// C, float32 (v_mfma_f32_16x16x4f32, operands rounded to float32 as they are staged) for
-// float32 C. Operands A and B are complex float64 in memory.
+// Batched complex GEMM on the matrix cores. Operands A and B are complex float64 in memory.
+// The register-staged kernels compute in float64 (v_mfma_f64_16x16x4f64) for float64 C and
+// in float32 (v_mfma_f32_16x16x4f32, operands rounded as they are staged) for float32 C; the
+// direct-to-LDS kernel always computes in float64 and rounds a float32 C as it stores it.
 //
 //   C[rmap[i], cmap[j]] = beta C[...] + alpha * sum_s opA(A_s)[i, :] B_s[:, j]
 //
@@ -311,7 +312,7 @@ __global__ void __launch_bounds__(64 * NWV, NWV == 8 ? 4 : 3)
 // (128 x 128 blocks, one workgroup per compute unit, measured slower on the Schur updates:
 // 37.6 vs 29.4 ms.) The output rows and columns are read through the maps before the K loop,
 // and the epilogue issues all old values of C before its stores.
-template <int OPA, bool SCAT, int TM>
+template <int OPA, bool SCAT, int TM, class CT = zd>
 __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
     zgemm_lds_kernel(const GemmTask* __restrict__ tasks, int ntasks, const GemmSeg* __restrict__ segs,
                      const int32_t* __restrict__ utask) {
@@ -493,7 +494,7 @@ __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
     }
   }
   const zd alpha{t.alpha_re, t.alpha_im};
-  zd* Cb = static_cast<zd*>(t.C) + (int64_t)kc * t.part_stride;
+  CT* Cb = static_cast<CT*>(t.C) + (int64_t)kc * t.part_stride;
 #pragma unroll
   for (int b = 0; b < BB; ++b) {
     if (ocol[b] < 0) continue;
@@ -505,7 +506,7 @@ __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
       for (int a = 0; a < AB; ++a)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          old[a][r] = orow[a][r] >= 0 ? Cb[orow[a][r] + (int64_t)ocol[b] * t.ldc] : zd{0.0, 0.0};
+          old[a][r] = orow[a][r] >= 0 ? widen(Cb[orow[a][r] + (int64_t)ocol[b] * t.ldc]) : zd{0.0, 0.0};
     }
 #pragma unroll
     for (int a = 0; a < AB; ++a)
@@ -514,7 +515,7 @@ __global__ void __launch_bounds__(512, TM == 64 ? 4 : 2)
         if (orow[a][r] < 0) continue;
         zd v = zmul(alpha, zd{(double)cr[a][b][r], (double)ci[a][b][r]});
         if (t.beta != 0.0) v = zadd(v, zscale(old[a][r], t.beta));
-        Cb[orow[a][r] + (int64_t)ocol[b] * t.ldc] = v;
+        Cb[orow[a][r] + (int64_t)ocol[b] * t.ldc] = narrow<CT>(v);
       }
   }
 }
@@ -537,7 +538,7 @@ void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, con
   if (c32 && opA != 0) throw Error(FMMLU_EINVAL, "float32 GEMM takes opA = N");
   const int k = kernel == GK_AUTO ? gemm_default_kernel(c32, mapped, opA) : kernel;
   if (k != GK_LDS && k != GK_REG8 && k != GK_REG4) throw Error(FMMLU_EINVAL, "unknown GEMM kernel");
-  if (c32 && k == GK_LDS) throw Error(FMMLU_EINVAL, "the direct-to-LDS GEMM is float64 only");
+
   const dim3 g((unsigned)nunits), b4(256), b8(512);
 #define FMMLU_GEMM_REG(OP, CT, SC)                                                                     \
   do {                                                                                                \
@@ -546,7 +547,13 @@ void launch_gemm(int opA, const GemmTask* tasks, int ntasks, int64_t nunits, con
     else                                                                                              \
       hipLaunchKernelGGL((zgemm_mfma_kernel<OP, CT, SC, 4>), g, b4, 0, st, tasks, ntasks, segs, utask); \
   } while (0)
-  if (c32) {
+  if (c32 && k == GK_LDS) {
+    // float64 products rounded to float32 as they are stored
+    if (mapped)
+      hipLaunchKernelGGL((zgemm_lds_kernel<0, true, 64, zf>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+    else
+      hipLaunchKernelGGL((zgemm_lds_kernel<0, false, 64, zf>), g, b8, kLdsGemmBytes64, st, tasks, ntasks, segs, utask);
+  } else if (c32) {
     if (mapped)
       FMMLU_GEMM_REG(0, zf, true);
     else

@@ -32,10 +32,7 @@ const Use kUses[] = {{false, true, 0}, {false, false, 0}, {false, false, 1}, {fa
                      {true, true, 0},  {true, false, 0}};
 constexpr int kNumUses = sizeof(kUses) / sizeof(kUses[0]);
 
-std::vector<int> candidates(const Use& u) {
-  if (u.c32) return {GK_REG8, GK_REG4};
-  return {GK_LDS, GK_REG8, GK_REG4};
-}
+std::vector<int> candidates(const Use&) { return {GK_LDS, GK_REG8, GK_REG4}; }
 
 struct Table {
   bool done = false;
@@ -63,7 +60,7 @@ int gemm_bucket(int64_t k) { return k <= 32 ? 0 : k <= 512 ? 1 : 2; }
 void gemm_force_kernel(int kernel) { t_force = kernel; }
 
 int gemm_tuned_kernel(bool c32, bool mapped, int opA, int64_t kmax) {
-  if (t_force != GK_AUTO) return (c32 && t_force == GK_LDS) ? GK_AUTO : t_force;
+  if (t_force != GK_AUTO) return t_force;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return GK_AUTO;
   std::lock_guard<std::mutex> l(g_mu);

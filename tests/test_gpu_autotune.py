@@ -43,7 +43,7 @@ def test_tuning_table():
         assert c["k_bucket"] in ("<=32", "<=512", ">512")
         assert c["kernel"] in c["ms"]
         assert all(v > 0 for v in c["ms"].values())
-        assert ("lds64x8" in c["ms"]) == (c["precision"] == "c128")
+        assert set(c["ms"]) == {"lds64x8", "reg64x8", "reg64x4"}
 
 
 @pytest.mark.parametrize("precision", [0, 1])
