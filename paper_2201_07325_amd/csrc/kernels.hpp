@@ -273,7 +273,6 @@ void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int 
 // workgroups of gj_coop that can be resident at once; compute units of the device
 int gj_coop_capacity(int nmax);
 int gj_coop_cus();
-constexpr int kGjCoopThreads = 256;  // threads per cooperative Gauss-Jordan workgroup
 
 // Stepped Gauss-Jordan inversion of one matrix of kGjCoopMax < n <= kGjStepMax rows with
 // implicit pivoting, one launch per panel of kGjStepNb columns (the launch boundary is the

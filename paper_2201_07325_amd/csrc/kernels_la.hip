@@ -1037,11 +1037,10 @@ __device__ inline zd gj_mul(const zd& a, const zd& b) {
   return zd{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
 }
 
-// kGjCoopThreads threads per workgroup, RPT rows per thread (rows tid + r kGjCoopThreads),
-// panels of NB columns
-template <int RPT, int NB>
-__global__ void __launch_bounds__(kGjCoopThreads) gj_coop_kernel(const GjCoopTask* __restrict__ tasks, int ntasks) {
-  constexpr int NT = kGjCoopThreads, NW = NT / 64, NR = NT * RPT;
+// NT threads per workgroup, RPT rows per thread (rows tid + r NT), panels of NB columns
+template <int RPT, int NB, int NT>
+__global__ void __launch_bounds__(NT) gj_coop_kernel(const GjCoopTask* __restrict__ tasks, int ntasks) {
+  constexpr int NW = NT / 64, NR = NT * RPT;
   const int64_t u = blockIdx.x;
   const GjCoopTask t = tasks[find_task(tasks, ntasks, u)];
   const int w = (int)(u - t.unit_begin);
@@ -1719,21 +1718,22 @@ void launch_gj_panel(const GjTask* tasks, int ntasks, int j0, int wmax, hipStrea
   FMMLU_HIP(hipGetLastError());
 }
 
-// (rows per thread, panel width) for matrices of up to n rows
+// (rows per thread, panel width, threads) for matrices of up to nmax rows: one row per
+// thread, 256 threads up to 256 rows, 512 beyond
 template <class F>
 void gj_coop_dispatch(int nmax, F&& f) {
-  if (nmax <= kGjCoopThreads)
-    f(reinterpret_cast<const void*>(gj_coop_kernel<1, 16>));
+  if (nmax <= 256)
+    f(reinterpret_cast<const void*>(gj_coop_kernel<1, 16, 256>), 256);
   else
-    f(reinterpret_cast<const void*>(gj_coop_kernel<2, 16>));
+    f(reinterpret_cast<const void*>(gj_coop_kernel<1, 16, 512>), 512);
 }
 
 void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int nmax, hipStream_t st) {
   if (ntasks <= 0 || nwg_total <= 0) return;
   if (nmax > kGjCoopMax) throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
   void* args[] = {(void*)&tasks, (void*)&ntasks};
-  gj_coop_dispatch(nmax, [&](const void* k) {
-    coop_launch([&]() { FMMLU_HIP(hipLaunchCooperativeKernel(k, dim3((unsigned)nwg_total), dim3(kGjCoopThreads), args, 0, st)); },
+  gj_coop_dispatch(nmax, [&](const void* k, int nt) {
+    coop_launch([&]() { FMMLU_HIP(hipLaunchCooperativeKernel(k, dim3((unsigned)nwg_total), dim3(nt), args, 0, st)); },
                 st);
   });
   FMMLU_HIP(hipGetLastError());
@@ -1743,8 +1743,8 @@ int gj_coop_capacity(int nmax) {
   int dev = 0, per_cu = 0, cus = 0;
   FMMLU_HIP(hipGetDevice(&dev));
   FMMLU_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  gj_coop_dispatch(nmax, [&](const void* k) {
-    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kGjCoopThreads, 0));
+  gj_coop_dispatch(nmax, [&](const void* k, int nt) {
+    FMMLU_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, nt, 0));
   });
   return per_cu * cus;
 }
