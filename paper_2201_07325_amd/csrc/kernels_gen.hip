@@ -4,9 +4,9 @@
 // Entries follow Section 3 (eqs. disc1, disc3, comb_ref) with plain smooth weights:
 //   A~_ii = 1/2,  A~_ij = sqrt(w_i) K(x_i, x_j) sqrt(w_j),
 //   K(x, y) = e^{ik r} / (4 pi r^3) * [ (1 - ik r) (x - y).n(y) - i eta r^2 ],  r = |x - y|.
-// All generators are VALU-bound (one sincos, one sqrt and one division per entry); work is
-// split into 64x64 units so that a workgroup of 256 threads writes whole columns
-// (consecutive threads -> consecutive rows, coalesced stores).
+// All generators are VALU-bound (one sine-cosine pair and one reciprocal square root per
+// entry); work is split into 64x64 units so that a workgroup of 256 threads writes whole
+// columns (consecutive threads -> consecutive rows, coalesced stores).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,18 +21,59 @@ namespace {
 
 constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
 
+// sin x and cos x for the kernel phase x = k r (|x| < 2^20; the library's routine beyond):
+// Cody-Waite reduction by pi/2 with fused multiply-adds (x - q hi exact to one rounding, then
+// the tail lo of pi/2) to |y| <= pi/4, then the Taylor series of sin to y^15 and of cos to
+// y^16 (truncation below 7e-17 relative on that interval), and the quadrant q mod 4.
+__device__ inline void sincos_phase(double x, double* sn, double* cs) {
+  if (!(fabs(x) < 1048576.0)) {
+    sincos(x, sn, cs);
+    return;
+  }
+  constexpr double kTwoOverPi = 0.63661977236758134308;
+  constexpr double kPio2Hi = 1.5707963267948965580;   // nearest double to pi/2
+  constexpr double kPio2Lo = 6.123233995736766036e-17;  // pi/2 - kPio2Hi
+  const double q = rint(x * kTwoOverPi);
+  double y = fma(-q, kPio2Hi, x);
+  y = fma(-q, kPio2Lo, y);
+  const double z = y * y;
+  // 1/n! for n = 3, 5, ..., 15 and n = 2, 4, ..., 16
+  double ps = -7.6471637318198164759e-13;            // -1/15!
+  ps = fma(ps, z, 1.6059043836821614599e-10);        //  1/13!
+  ps = fma(ps, z, -2.5052108385441718775e-08);       // -1/11!
+  ps = fma(ps, z, 2.7557319223985890653e-06);        //  1/9!
+  ps = fma(ps, z, -1.9841269841269841270e-04);       // -1/7!
+  ps = fma(ps, z, 8.3333333333333333333e-03);        //  1/5!
+  ps = fma(ps, z, -1.6666666666666666667e-01);       // -1/3!
+  const double sy = fma(ps * z, y, y);
+  double pc = 4.7794773323873852974e-14;             //  1/16!
+  pc = fma(pc, z, -1.1470745597729724714e-11);       // -1/14!
+  pc = fma(pc, z, 2.0876756987868098979e-09);        //  1/12!
+  pc = fma(pc, z, -2.7557319223985890653e-07);       // -1/10!
+  pc = fma(pc, z, 2.4801587301587301587e-05);        //  1/8!
+  pc = fma(pc, z, -1.3888888888888888889e-03);       // -1/6!
+  pc = fma(pc, z, 4.1666666666666666667e-02);        //  1/4!
+  pc = fma(pc, z, -0.5);                             // -1/2!
+  const double cy = fma(pc, z, 1.0);
+  const int quad = (int)((int64_t)q & 3);
+  const double s0 = (quad & 1) ? cy : sy, c0 = (quad & 1) ? sy : cy;
+  *sn = (quad & 2) ? -s0 : s0;
+  *cs = ((quad + 1) & 2) ? -c0 : c0;
+}
+
 // A~[i, j] for tree positions i, j
 __device__ inline zd cfie_entry(const double* __restrict__ p, int64_t n, double k, double eta,
                                 int64_t i, int64_t j) {
   if (i == j) return zd{0.5, 0.0};
   double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
   double r2 = dx * dx + dy * dy + dz * dz;
-  double r = sqrt(r2);
+  double ir = rsqrt(r2);
+  double r = r2 * ir;
   double dn = dx * p[3 * n + j] + dy * p[4 * n + j] + dz * p[5 * n + j];
   double s, c;
-  sincos(k * r, &s, &c);
+  sincos_phase(k * r, &s, &c);
   double a = dn, b = k * r * dn + eta * r2;
-  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi / (r2 * r);
+  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi * (ir * ir * ir);
   return zd{(c * a + s * b) * f, (s * a - c * b) * f};
 }
 
@@ -42,12 +83,13 @@ __device__ inline zd cfie_entry_dk(const double* __restrict__ p, int64_t n, doub
   if (i == j) return zd{0.0, 0.0};
   double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
   double r2 = dx * dx + dy * dy + dz * dz;
-  double r = sqrt(r2);
+  double ir = rsqrt(r2);
+  double r = r2 * ir;
   double dn = dx * p[3 * n + j] + dy * p[4 * n + j] + dz * p[5 * n + j];
   double s, c;
-  sincos(k * r, &s, &c);
+  sincos_phase(k * r, &s, &c);
   // k e^{ikr} dn / (4 pi r)  +  eta r e^{ikr} / (4 pi r) = e^{ikr} (k dn + eta r) / (4 pi r)
-  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi / r;
+  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi * ir;
   double a = k * dn + eta * r;
   return zd{c * a * f, s * a * f};
 }
@@ -57,10 +99,11 @@ __device__ inline zd cfie_entry_deta(const double* __restrict__ p, int64_t n, do
                                      int64_t i, int64_t j) {
   if (i == j) return zd{0.0, 0.0};
   double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
-  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double r2 = dx * dx + dy * dy + dz * dz;
+  double ir = rsqrt(r2);
   double s, c;
-  sincos(k * r, &s, &c);
-  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi / r;
+  sincos_phase(k * (r2 * ir), &s, &c);
+  double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi * ir;
   return zd{s * f, -c * f};
 }
 
@@ -230,20 +273,21 @@ __global__ void __launch_bounds__(256) idmatrix_kernel(DevGeom g, const IdTask* 
     const int64_t q = dof[t.dof_off + j];
     const double dx = yx - p[q], dy = yy - p[n + q], dz = yz - p[2 * n + q];
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
+    const double ir = rsqrt(r2);
+    const double r = r2 * ir;
     double s, c;
-    sincos(g.k * r, &s, &c);
+    sincos_phase(g.k * r, &s, &c);
     const double sw = p[6 * n + q] * t.wgamma;
     zd v;
     if (incoming) {
       // G(x_j, y_l) sqrt(w_j)
-      const double f = sw * kInv4Pi / r;
+      const double f = sw * kInv4Pi * ir;
       v = zd{c * f, s * f};
     } else {
       // K(y_l, x_j) sqrt(w_j), source normal n_j
       const double dn = dx * p[3 * n + q] + dy * p[4 * n + q] + dz * p[5 * n + q];
       const double a = dn, b = g.k * r * dn + g.eta * r2;
-      const double f = sw * kInv4Pi / (r2 * r);
+      const double f = sw * kInv4Pi * (ir * ir * ir);
       v = zd{(c * a + s * b) * f, (s * a - c * b) * f};
     }
     out[i + (int64_t)j * t.rows] = v;
@@ -296,10 +340,10 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __rest
       }
       const double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const double r = sqrt(r2);
-      const double ir = 1.0 / r;
+      const double ir = rsqrt(r2);
+      const double r = r2 * ir;
       double s, c;
-      sincos(g.k * r, &s, &c);
+      sincos_phase(g.k * r, &s, &c);
       const double w = xi[6] * sp[6][jj] * kInv4Pi;
       double vr, vi;
       if (OP == 0) {
