@@ -1865,7 +1865,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           if (blocked) {
             const int nblk = (mmax + kPcholNb - 1) / kPcholNb;
             for (int b = 0; b < nblk; ++b) {
-              launch_pchol_block(dpt, nb, b * kPcholNb, eps, sg.go());
+              launch_pchol_block(dpt, nb, b * kPcholNb, eps, sg.go(), mmax);
               if (b + 1 < nblk) gu.launch(sg, 2);
             }
             launch_pchol_finish(dpt, nb, mmax, sg.go());

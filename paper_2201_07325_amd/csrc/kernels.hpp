@@ -223,7 +223,7 @@ struct PcholTask {
 constexpr int kPcholNb = 16;
 constexpr int kPcholThreadsB = 1024;
 constexpr int kPcholBlockedMin = 128;  // widest block of a phase from which the blocked form is used
-void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st);
+void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st, int mmax);
 void launch_pchol_finish(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st);
 void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipStream_t st);
 // after launch_pchol or launch_pchol_finish: T = R11^{-1} R12 by back substitution (rank and

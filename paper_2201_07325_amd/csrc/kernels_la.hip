@@ -590,9 +590,9 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* _
 // R is R[k, c] = (G[p_k, c] - sum_{k0 <= l < k} conj(R[l, p_k]) R[l, c]) / R[k, k]. Thread c
 // keeps column c's rows of the block in registers; the pivot column's values are broadcast
 // through LDS. State (dg, positions, k, done) lives in global memory between launches.
-__global__ void __launch_bounds__(kPcholThreadsB) pchol_block_kernel(const PcholTask* __restrict__ tasks, int k0,
-                                                                     double eps) {
-  constexpr int NB = kPcholNb, NT = kPcholThreadsB, NW = NT / 64;
+template <int NT>
+__global__ void __launch_bounds__(NT) pchol_block_kernel(const PcholTask* __restrict__ tasks, int k0, double eps) {
+  constexpr int NB = kPcholNb, NW = NT / 64;
   const PcholTask t = tasks[blockIdx.x];
   const int m = t.m;
   if (k0 >= m) return;
@@ -601,7 +601,7 @@ __global__ void __launch_bounds__(kPcholThreadsB) pchol_block_kernel(const Pchol
   int* gpos = t.ist;
   int* gpv = t.ist + m;
   int* ctl = t.ist + 2 * m;  // [0] k reached, [1] done
-  __shared__ int pos[kPcholThreadsB], pv[kPcholThreadsB];
+  __shared__ int pos[NT], pv[NT];
   __shared__ double bestv[NW];
   __shared__ int bestc[NW];
   __shared__ zd multb[NB];
@@ -1647,9 +1647,17 @@ void launch_pchol_t(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st
   FMMLU_HIP(hipGetLastError());
 }
 
-void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st) {
+void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, hipStream_t st, int mmax) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(pchol_block_kernel, dim3(ntasks), dim3(kPcholThreadsB), 0, st, tasks, k0, eps);
+  if (mmax > kPcholThreadsB) throw Error(FMMLU_EINVAL, "blocked pivoted Cholesky takes m <= 1024");
+  // one column per thread: the fewest wavefronts that cover the widest matrix (cheaper
+  // barriers and pivot searches per step)
+  if (mmax <= 256)
+    hipLaunchKernelGGL(pchol_block_kernel<256>, dim3(ntasks), dim3(256), 0, st, tasks, k0, eps);
+  else if (mmax <= 512)
+    hipLaunchKernelGGL(pchol_block_kernel<512>, dim3(ntasks), dim3(512), 0, st, tasks, k0, eps);
+  else
+    hipLaunchKernelGGL(pchol_block_kernel<1024>, dim3(ntasks), dim3(1024), 0, st, tasks, k0, eps);
   FMMLU_HIP(hipGetLastError());
 }
 
