@@ -439,25 +439,27 @@ constexpr int kPcholThreads = 1024;
 
 // rank, perm = pv, and the rows < s of R in pivoted order (column-major, ld m, upper
 // triangle) through a 32 x 32 LDS tile (part: >= 32 x 33 entries): reads along rows of Rt,
-// writes down columns. Called by all kPcholThreads threads.
+// writes down columns. Called by all NT threads.
+template <int NT>
 __device__ inline void pchol_write_out(const PcholTask& t, int s, const int* pv, zd* part) {
   const int m = t.m, tid = threadIdx.x;
   const zd* __restrict__ Rt = t.Rt;
   if (tid == 0) *t.rank = s;
-  for (int j = tid; j < m; j += kPcholThreads) t.perm[j] = pv[j];
+  for (int j = tid; j < m; j += NT) t.perm[j] = pv[j];
   zd(*tile)[33] = reinterpret_cast<zd(*)[33]>(part);
-  const int ta = tid & 31, tb = tid >> 5;
   for (int i0 = 0; i0 < s; i0 += 32) {
     for (int j0 = i0 & ~31; j0 < m; j0 += 32) {
       __syncthreads();
-      {
+      for (int e = tid; e < 1024; e += NT) {
+        const int ta = e & 31, tb = e >> 5;
         const int i = i0 + tb, j = j0 + ta;
         zd v{0.0, 0.0};
         if (i < s && j < m && j >= i) v = Rt[(int64_t)i * m + pv[j]];
         tile[tb][ta] = v;
       }
       __syncthreads();
-      {
+      for (int e = tid; e < 1024; e += NT) {
+        const int ta = e & 31, tb = e >> 5;
         const int i = i0 + ta, j = j0 + tb;
         if (i < s && j < m) t.Rp[i + (int64_t)j * m] = tile[ta][tb];
       }
@@ -474,35 +476,35 @@ __device__ inline bool pchol_better(double v, int c, double bv, int bc) {
   return c >= 0 && (bc < 0 || v > bv || (v == bv && c < bc));
 }
 
-__global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* __restrict__ tasks, double eps,
-                                                              int mult_in_lds) {
+template <int NT>
+__global__ void __launch_bounds__(NT) pchol_kernel(const PcholTask* __restrict__ tasks, double eps, int mult_in_lds) {
   const PcholTask t = tasks[blockIdx.x];
   const int m = t.m;
   const zd* __restrict__ G = t.G;
   zd* __restrict__ Rt = t.Rt;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ zd part[32 * 33];  // row-slice partial sums; 32 x 33 tile in the final pass
-  __shared__ double bestv[kPcholThreads / 64];
-  __shared__ int bestc[kPcholThreads / 64];
+  __shared__ double bestv[NT / 64];
+  __shared__ int bestc[NT / 64];
   zd* mult = mult_in_lds ? reinterpret_cast<zd*>(smem) : t.Rp;  // R[0:k, p_k]
   double* dg = reinterpret_cast<double*>(smem + (mult_in_lds ? sizeof(zd) * (size_t)m : 0));
   int* pos = reinterpret_cast<int*>(dg + m);  // column -> position
   int* pv = pos + m;                          // position -> column
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int c = tid; c < m; c += kPcholThreads) {
+  for (int c = tid; c < m; c += NT) {
     dg[c] = G[c + (int64_t)c * m].re;
     pos[c] = c;
     pv[c] = c;
   }
   __syncthreads();
   const int mpad = (m + 63) & ~63;
-  const int slices = mpad >= kPcholThreads ? 1 : kPcholThreads / mpad;
+  const int slices = mpad >= NT ? 1 : NT / mpad;
   double r00 = 0.0;
   int s = m;
   for (int k = 0; k < m; ++k) {
     double bv = -1.0;
     int bc = -1;
-    for (int c = tid; c < m; c += kPcholThreads) {
+    for (int c = tid; c < m; c += NT) {
       if (pos[c] < k) continue;
       const double v = dg[c];
       if (pchol_better(v, c, bv, bc)) {
@@ -525,7 +527,7 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* _
     __syncthreads();
     bv = -1.0;
     bc = -1;
-    for (int w = 0; w < kPcholThreads / 64; ++w)
+    for (int w = 0; w < NT / 64; ++w)
       if (pchol_better(bestv[w], bestc[w], bv, bc)) {
         bv = bestv[w];
         bc = bestc[w];
@@ -544,11 +546,11 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* _
       pos[p] = k;
       pos[ck] = q;
     }
-    for (int l = tid; l < k; l += kPcholThreads) mult[l] = Rt[(int64_t)l * m + p];
+    for (int l = tid; l < k; l += NT) mult[l] = Rt[(int64_t)l * m + p];
     __syncthreads();
     const double inv = 1.0 / rkk;
     if (slices == 1) {
-      for (int c = tid; c < m; c += kPcholThreads) {
+      for (int c = tid; c < m; c += NT) {
         if (pos[c] <= k) continue;
         zd a0{0.0, 0.0}, a1{0.0, 0.0};
         int l = 0;
@@ -582,11 +584,11 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_kernel(const PcholTask* _
     if (tid == 0) Rt[(int64_t)k * m + p] = zd{rkk, 0.0};
     __syncthreads();
   }
-  pchol_write_out(t, s, pv, part);
+  pchol_write_out<NT>(t, s, pv, part);
 }
 
 // One block of kPcholNb pivots of the blocked pivoted Cholesky (see PcholTask): G holds the
-// Schur complement of the Gram matrix after the earlier blocks (lower triangle), so row k of
+// Schur complement of the Gram matrix after the earlier blocks (both triangles), so row k of
 // R is R[k, c] = (G[p_k, c] - sum_{k0 <= l < k} conj(R[l, p_k]) R[l, c]) / R[k, k]. Thread c
 // keeps column c's rows of the block in registers; the pivot column's values are broadcast
 // through LDS. State (dg, positions, k, done) lives in global memory between launches.
@@ -733,7 +735,7 @@ __global__ void __launch_bounds__(kPcholThreads) pchol_finish_kernel(const Pchol
   extern __shared__ int pvs[];
   for (int j = threadIdx.x; j < t.m; j += kPcholThreads) pvs[j] = t.ist[t.m + j];
   __syncthreads();
-  pchol_write_out(t, t.ist[2 * t.m], pvs, part);
+  pchol_write_out<kPcholThreads>(t, t.ist[2 * t.m], pvs, part);
 }
 
 // T = R11^{-1} R12 (s x (m - s), ld m) from R in pivoted order. Each workgroup holds NC
@@ -1626,8 +1628,13 @@ void launch_pchol(const PcholTask* tasks, int ntasks, int mmax, double eps, hipS
   const size_t with_mult = (size_t)mmax * 32, without = (size_t)mmax * 16;
   if (without > kBudget) throw Error(FMMLU_EINVAL, "ID block wider than " + std::to_string(kBudget / 16));
   const int in_lds = with_mult <= kBudget ? 1 : 0;
-  hipLaunchKernelGGL(pchol_kernel, dim3(ntasks), dim3(kPcholThreads), in_lds ? with_mult : without, st, tasks, eps,
-                     in_lds);
+  // 256 threads up to 128 columns (two or more row slices per column), 1024 beyond
+  if (mmax <= 128)
+    hipLaunchKernelGGL(pchol_kernel<256>, dim3(ntasks), dim3(256), in_lds ? with_mult : without, st, tasks, eps,
+                       in_lds);
+  else
+    hipLaunchKernelGGL(pchol_kernel<kPcholThreads>, dim3(ntasks), dim3(kPcholThreads), in_lds ? with_mult : without, st,
+                       tasks, eps, in_lds);
   FMMLU_HIP(hipGetLastError());
 }
 
