@@ -960,10 +960,13 @@ void batched_inverse(Stage& sg, std::vector<GjTask>& tasks, const std::vector<zd
     // batch at one workgroup per compute unit (a matrix's time is its panel chain; fewer
     // workgroups add each one's share of the column updates to that chain, and workgroups
     // sharing a compute unit slow each other's redundant panel work).
+    // While other factorizations run concurrently, one workgroup per matrix: the launch then
+    // has no waits between workgroups and goes out as an ordinary launch, where cooperative
+    // launches would have to be serialised across the concurrent factorizations.
     auto npan_of = [NB](int n) { return (n + NB - 1) / NB; };
     const int64_t budget = std::min(cap, gj_coop_cus());
     int K = 1;
-    for (int k = 2; k <= npan_of(nmax); ++k) {
+    for (int k = 2; ActiveFactorization::count() <= 1 && k <= npan_of(nmax); ++k) {
       int64_t tot = 0;
       for (auto& c : small) tot += std::min(npan_of(c.n), k);
       if (tot > budget) break;

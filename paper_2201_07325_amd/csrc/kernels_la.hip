@@ -1747,9 +1747,14 @@ void launch_gj_coop(const GjCoopTask* tasks, int ntasks, int64_t nwg_total, int 
   if (ntasks <= 0 || nwg_total <= 0) return;
   if (nmax > kGjCoopMax) throw Error(FMMLU_EINVAL, "cooperative Gauss-Jordan takes n <= 512");
   void* args[] = {(void*)&tasks, (void*)&ntasks};
+  // one workgroup per matrix: nothing waits across workgroups, an ordinary launch suffices
+  const bool independent = nwg_total == ntasks;
   gj_coop_dispatch(nmax, [&](const void* k, int nt) {
-    coop_launch([&]() { FMMLU_HIP(hipLaunchCooperativeKernel(k, dim3((unsigned)nwg_total), dim3(nt), args, 0, st)); },
-                st);
+    if (independent)
+      FMMLU_HIP(hipLaunchKernel(k, dim3((unsigned)nwg_total), dim3(nt), args, 0, st));
+    else
+      coop_launch([&]() { FMMLU_HIP(hipLaunchCooperativeKernel(k, dim3((unsigned)nwg_total), dim3(nt), args, 0, st)); },
+                  st);
   });
   FMMLU_HIP(hipGetLastError());
 }
