@@ -1146,7 +1146,7 @@ struct PendingPhase {
   SolvePhase ph;
   std::vector<std::pair<int32_t, int64_t>> contrib;  // (destination, y index)
   std::vector<SolveBox> db;
-  std::vector<SweepTask> txr, ty, tbp, tbt;
+  std::vector<SweepTask> txr, ty, tbp, tbt, tbt16;
   std::vector<int32_t> dst;
   std::vector<int64_t> ptr, src;
 };
@@ -2324,7 +2324,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         int64_t yo = 0, po = 0, xpo = 0;
         auto& contrib = pp.contrib;
         auto& db = pp.db;
-        auto &txr = pp.txr, &ty = pp.ty, &tbp = pp.tbp, &tbt = pp.tbt;
+        auto &txr = pp.txr, &ty = pp.ty, &tbp = pp.tbp, &tbt = pp.tbt, &tbt16 = pp.tbt16;
         for (int b = ph.box_begin; b < ph.box_end; ++b) {
           FactorBox& fb = boxes[b];
           const int lb = b - ph.box_begin;
@@ -2350,6 +2350,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
               tbp.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.nsn - c * kSolveK), c, g, 0});
           for (int l0 = 0; l0 < std::max(fb.s, 1); l0 += kSolveRows)
             tbt.push_back(SweepTask{lb, l0, std::max(0, std::min(kSolveRows, fb.s - l0)), 0, 0, 0});
+          for (int l0 = 0; l0 < std::max(fb.s, 1); l0 += 16)
+            tbt16.push_back(SweepTask{lb, l0, std::max(0, std::min(16, fb.s - l0)), 0, 0, 0});
           ph.rmax = std::max(ph.rmax, fb.r);
           ph.smax = std::max(ph.smax, fb.s);
           db.push_back(d);
@@ -2544,10 +2546,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         pk.add(&ph.dy, pp.ty);
         pk.add(&ph.dbp, pp.tbp);
         pk.add(&ph.dbt, pp.tbt);
+        pk.add(&ph.dbt16, pp.tbt16);
         ph.nxr = (int)pp.txr.size();
         ph.ny = (int)pp.ty.size();
         ph.nbp = (int)pp.tbp.size();
         ph.nbt = (int)pp.tbt.size();
+        ph.nbt16 = (int)pp.tbt16.size();
       }
       sg.commit(arena, pk);
       for (auto& ph : newph) phases.push_back(ph);
@@ -2661,7 +2665,7 @@ void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* 
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
     if (blk) {
       launch_blk_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st);
-      launch_blk_bt(it->dboxes, it->dbt, it->nbt, w.xrd, w.p, w.x, adj, f32, st);
+      launch_blk_bt(it->dboxes, it->dbt16, it->nbt16, w.xrd, w.p, w.x, adj, f32, st);
     } else {
       launch_solve_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st, nr);
       launch_solve_bt(it->dboxes, it->dbt, it->nbt, w.xrd, w.p, w.x, adj, f32, st, nr);

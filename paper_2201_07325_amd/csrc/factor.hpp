@@ -83,7 +83,8 @@ struct SolvePhase {
   int64_t ylen = 0, plen = 0, xrplen = 0;
   // work items: forward x_R partials, rows of y; backward x_R partials, rows of x_S
   SweepTask *dxr = nullptr, *dy = nullptr, *dbp = nullptr, *dbt = nullptr;
-  int nxr = 0, ny = 0, nbp = 0, nbt = 0;
+  SweepTask* dbt16 = nullptr;  // blocked sweeps: rows of x_S in items of 16
+  int nxr = 0, ny = 0, nbp = 0, nbt = 0, nbt16 = 0;
   int rmax = 0, smax = 0;
 };
 

@@ -387,8 +387,9 @@ void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, c
 void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pbuf, zd* x,
                      int adjoint, bool f32, hipStream_t st, int nr = 1);
 // The same steps for blocks of kSolveBlock right-hand sides on the matrix cores (same work
-// items; the pivot blocks take one item per (box, 64 outputs) with box indexing the table of
-// all boxes; the top block's partials over chunks of 256 go to launch_solve_top_fin).
+// items, except items of 16 rows of S for launch_blk_bt; the pivot blocks take one item per
+// (box, 64 outputs) with box indexing the table of all boxes; the top block's partials over
+// chunks of 256 go to launch_solve_top_fin).
 void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
                         bool f32, hipStream_t st);
 void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg, zd* y,

@@ -151,6 +151,44 @@ __device__ inline void cols_block(const FT* __restrict__ M, int64_t ld, int i0, 
   }
 }
 
+// Rows [i0, i0 + ni) (ni <= 16) times the staged vector block over k in [0, K): the four
+// wavefronts split every staged chunk of KC = 64 columns into four runs of 16 and their 16 x NB
+// partial blocks are summed in LDS (wavefront order) at the end: four times the work items of
+// rows_block for short row ranges (the skeleton rows of a box).
+template <class FT, class Stage, class Emit>
+__device__ inline void rows_block16(const FT* __restrict__ M, int64_t ld, int i0, int ni, int K, bool conj,
+                                    zd (*sv)[NB], Stage stage, Emit emit) {
+  static_assert(KC == 64, "four runs of 16 columns per staged chunk");
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  dbl4 cr[2][NCB], ci[2][NCB];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      cr[h][cb] = dbl4{0, 0, 0, 0};
+      ci[h][cb] = dbl4{0, 0, 0, 0};
+    }
+  for (int kb = 0; kb < K; kb += KC) {
+    const int kn = min(KC, K - kb);
+    stage(kb, kn, sv);
+    __syncthreads();
+    const int k0 = 16 * wave, kw = min(16, kn - k0);
+    if (ni > 0 && kw > 0) block_mma<true, FT>(M + i0 + (int64_t)(kb + k0) * ld, ld, ni, kw, conj, sv + k0, cr, ci);
+    __syncthreads();
+  }
+  // partial blocks of the four wavefronts side by side in LDS (sv reused: 4 x 16 rows of NB)
+  zd(*red)[NB] = sv;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[16 * wave + (lane >> 4) + 4 * r][16 * cb + (lane & 15)] = dval(cr, ci, cb, r);
+  __syncthreads();
+  for (int e = threadIdx.x; e < ni * NB; e += 256) {
+    const int i = e / NB, c = e % NB;
+    emit(i0 + i, c, zadd(zadd(red[i][c], red[16 + i][c]), zadd(red[32 + i][c], red[48 + i][c])));
+  }
+}
+
 // forward: Pxr[chunk][i] = sum_{k in the s-chunk} op(T)[k, i] x_S[k] (T^T, adjoint T^H)
 template <class FT>
 __global__ void __launch_bounds__(256) blk_xr_part_kernel(const SolveBox* __restrict__ boxes,
@@ -236,8 +274,8 @@ __global__ void __launch_bounds__(256) blk_bpart_kernel(const SolveBox* __restri
                  [&](int i, int c, zd v) { out[(int64_t)i * NB + c] = v; });
 }
 
-// backward, per (box, 64 rows of S): x_R = XRd - sum of the partials (written to x[R] by the
-// item of rows 0..63), x_S -= op(T) x_R (T, adjoint conj(T)) for the item's rows
+// backward, per (box, 16 rows of S): x_R = XRd - sum of the partials (written to x[R] by the
+// item of rows 0..15), x_S -= op(T) x_R (T, adjoint conj(T)) for the item's rows
 template <class FT>
 __global__ void __launch_bounds__(256) blk_bt_kernel(const SolveBox* __restrict__ boxes,
                                                      const SweepTask* __restrict__ tasks, const zd* __restrict__ XRd,
@@ -246,7 +284,7 @@ __global__ void __launch_bounds__(256) blk_bt_kernel(const SolveBox* __restrict_
   const SolveBox b = boxes[t.box];
   __shared__ zd sv[KC][NB];
   const bool keep = t.k0 == 0;
-  rows_block<FT>(static_cast<const FT*>(b.T), b.s, t.k0, t.kn, b.r, adjoint != 0, sv,
+  rows_block16<FT>(static_cast<const FT*>(b.T), b.s, t.k0, t.kn, b.r, adjoint != 0, sv,
                  [&](int kb, int kn, zd(*s)[NB]) {
                    for (int e = threadIdx.x; e < kn * NB; e += 256) {
                      const int k = e / NB, c = e % NB;
