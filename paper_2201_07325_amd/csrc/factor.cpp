@@ -2657,7 +2657,7 @@ void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* 
     launch_blk_top_part(Ainv, n0, w.top, w.top + (int64_t)n0 * nr, adj, st);
     launch_solve_top_fin(n0, top_dev, w.top + (int64_t)n0 * nr, w.x, st, nr);
   } else {
-    launch_solve_diag(all_boxes, nall, rmax_all, w.xrg, w.xrd, adj, f32, st, nr);
+    launch_solve_diag(all_boxes, dg_tasks, ndg, rmax_all, w.xrg, w.xrd, adj, f32, st, nr);
     launch_solve_top(Ainv, n0, top_dev, w.x, w.top, adj, st, nr);
   }
   // W_M^{-1} ... W_1^{-1} (adjoint: V_M^{-H} ... V_1^{-H}), phases in reverse: x_R partials,

@@ -113,7 +113,7 @@ struct FactorImpl {
   int64_t ymax = 0, pmax = 0, xrpmax = 0;
   SolveBox* all_boxes = nullptr;  // every factored box, for the diagonal step
   int nall = 0, rmax_all = 0;
-  SweepTask* dg_tasks = nullptr;  // blocked diagonal step: (box of all_boxes, 64 outputs)
+  SweepTask* dg_tasks = nullptr;  // diagonal step: (box of all_boxes, 64 outputs)
   int ndg = 0;
   int64_t dxlen = 0;  // x_R of every box in one buffer (sum of r)
   int n0 = 0;

@@ -376,9 +376,10 @@ void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const
 // x[dst[d]] -= sum of y[src[q]] over ptr[d] <= q < ptr[d+1] (deterministic scatter)
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st, int nr = 1);
-// diagonal: XRd = Xi XRg (adjoint Xi^H XRg) for every box (rmax 16 bytes of LDS <= 64 KiB)
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, const zd* XRg, zd* XRd, int adjoint, bool f32,
-                       hipStream_t st, int nr = 1);
+// diagonal: XRd = Xi XRg (adjoint Xi^H XRg) for every box, items (box, 64 outputs) with box
+// indexing the table of all boxes (rmax 16 bytes of LDS <= 64 KiB)
+void launch_solve_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XRg, zd* XRd,
+                       int adjoint, bool f32, hipStream_t st, int nr = 1);
 // backward: partials of op(Q)^T x_SN (Up, adjoint Lp^H) per (box, column chunk, output group)
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
                         int adjoint, bool f32, hipStream_t st, int nr = 1);

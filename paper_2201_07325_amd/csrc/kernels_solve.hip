@@ -206,13 +206,16 @@ __global__ void __launch_bounds__(256) scatter_sub_kernel(const int32_t* __restr
   x[xi] = zsub(x[xi], acc);
 }
 
-// Diagonal: XRd = Xi XRg (adjoint Xi^H XRg), one box per workgroup, x_R in dynamic LDS.
+// Diagonal: XRd = Xi XRg (adjoint Xi^H XRg), one (box, 64 outputs) item per workgroup, the
+// box's x_R in dynamic LDS.
 // Normal: lanes take rows, the four wavefronts split k, partial sums meet in LDS.
 // Adjoint: one wavefront per output, lanes over k (columns of Xi are contiguous).
 template <class FT, int NR>
-__global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restrict__ boxes, const zd* XRg,
+__global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restrict__ boxes,
+                                                         const SweepTask* __restrict__ tasks, const zd* XRg,
                                                          zd* XRd, int adjoint) {
-  const SolveBox b = boxes[blockIdx.x];
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
   extern __shared__ zd xr_flat[];
   zd(*xr)[NR] = reinterpret_cast<zd(*)[NR]>(xr_flat);
   __shared__ zd part[4][64];
@@ -222,30 +225,42 @@ __global__ void __launch_bounds__(256) solve_diag_kernel(const SolveBox* __restr
   for (int e = threadIdx.x; e < b.r * NR; e += 256) xr[e / NR][e % NR] = xin[e];
   __syncthreads();
   const FT* Xi = static_cast<const FT*>(b.Xi);
-  const int r = b.r;
+  const int r = b.r, i0 = t.k0, i1 = t.k0 + t.kn;
   if (!adjoint) {
-    for (int i0 = 0; i0 < r; i0 += 64) {
-      const int i = i0 + lane;
-      zd acc[NR];
+    // the item's 64 rows, one per lane; the four wavefronts take every fourth column (four
+    // loads in flight each) and meet in LDS
+    const int i = i0 + lane;
+    zd acc[NR];
 #pragma unroll
-      for (int c = 0; c < NR; ++c) acc[c] = zd{0.0, 0.0};
-      if (i < r)
-        for (int k = wave; k < r; k += 4) {
-          const zd a = widen(Xi[i + (int64_t)k * r]);
+    for (int c = 0; c < NR; ++c) acc[c] = zd{0.0, 0.0};
+    if (i < i1) {
+      const FT* row = Xi + i;
+      int k = wave;
+      for (; k + 12 < r; k += 16) {
+        zd a[4];
 #pragma unroll
-          for (int c = 0; c < NR; ++c) zfma(acc[c], a, xr[k][c]);
-        }
-#pragma unroll 1
-      for (int c = 0; c < NR; ++c) {
-        part[wave][lane] = acc[c];
-        __syncthreads();
-        if (wave == 0 && i < r)
-          x[(int64_t)i * NR + c] = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
-        __syncthreads();
+        for (int q = 0; q < 4; ++q) a[q] = widen(row[(int64_t)(k + 4 * q) * r]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < NR; ++c) zfma(acc[c], a[q], xr[k + 4 * q][c]);
+      }
+      for (; k < r; k += 4) {
+        const zd a = widen(row[(int64_t)k * r]);
+#pragma unroll
+        for (int c = 0; c < NR; ++c) zfma(acc[c], a, xr[k][c]);
       }
     }
+#pragma unroll 1
+    for (int c = 0; c < NR; ++c) {
+      part[wave][lane] = acc[c];
+      __syncthreads();
+      if (wave == 0 && i < i1)
+        x[(int64_t)i * NR + c] = zadd(zadd(part[0][lane], part[1][lane]), zadd(part[2][lane], part[3][lane]));
+      __syncthreads();
+    }
   } else {
-    for (int i = wave; i < r; i += 4) {
+    for (int i = i0 + wave; i < i1; i += 4) {
       const FT* col = Xi + (int64_t)i * r;
       zd acc[NR];
 #pragma unroll
@@ -456,13 +471,13 @@ void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* s
   FMMLU_NR_LAUNCH(scatter_sub_kernel, (unsigned)((nd * nr + 255) / 256), 0, dst, ptr, src, nd, y, x);
 }
 
-void launch_solve_diag(const SolveBox* boxes, int nb, int rmax, const zd* XRg, zd* XRd, int adjoint, bool f32,
-                       hipStream_t st, int nr) {
-  if (nb <= 0) return;
+void launch_solve_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XRg, zd* XRd,
+                       int adjoint, bool f32, hipStream_t st, int nr) {
+  if (nt <= 0) return;
   const size_t lds = (size_t)rmax * nr * sizeof(zd);
   if (lds > 65536)
     throw Error(FMMLU_EINVAL, "redundant set of " + std::to_string(rmax) + " DOFs exceeds the diagonal step's LDS bound");
-  FMMLU_FT_NR_LAUNCH(solve_diag_kernel, nb, lds, boxes, XRg, XRd, adjoint);
+  FMMLU_FT_NR_LAUNCH(solve_diag_kernel, nt, lds, boxes, tasks, XRg, XRd, adjoint);
 }
 
 void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp, int adjoint,
