@@ -343,29 +343,28 @@ __global__ void __launch_bounds__(256) gather_top_kernel(const int32_t* __restri
   if (e < n0 * NR) tmp[e] = x[(int64_t)top[e / NR] * NR + e % NR];
 }
 
-// Top block, normal: partial[cb][i] = sum_{j in column block cb} Ainv[i, j] tmp[j]
-// (grid: row blocks of 256 x column blocks of 256), then a finish pass sums the partials.
+// Top block, normal, in items of 64 rows x 256 columns: partial[cb][i] = sum over the column
+// block cb of Ainv[i, j] tmp[j] (rows one per lane, the four wavefronts splitting the columns)
 template <int NR>
-__global__ void __launch_bounds__(256) top_n_part_kernel(const zd* __restrict__ A, int n0,
-                                                         const zd* __restrict__ tmp, zd* __restrict__ part) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int j0 = blockIdx.y * 256;
-  __shared__ zd tv[256][NR];
-  const int jn = min(256, n0 - j0);
-  for (int e = threadIdx.x; e < jn * NR; e += 256) tv[e / NR][e % NR] = tmp[(int64_t)j0 * NR + e];
-  __syncthreads();
-  if (i >= n0) return;
+__global__ void __launch_bounds__(256) top_rows_part_kernel(const zd* __restrict__ A, int n0,
+                                                            const zd* __restrict__ tmp, zd* __restrict__ part) {
+  __shared__ zd xr[kSolveK][NR];
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 64 + lane;
+  const int k0 = blockIdx.y * 256, kn = min(256, n0 - k0);
   zd acc[NR];
+  rows_times_xr<zd, NR>(A + (int64_t)k0 * n0, n0, kn, i, i < n0, false, xr, acc, [&](int kb, int kc) {
+    for (int e = threadIdx.x; e < kc * NR; e += 256) xr[e / NR][e % NR] = tmp[(int64_t)(k0 + kb) * NR + e];
+  });
+  rows_reduce<NR>(xr, acc);
+  if (threadIdx.x < 64 && i < n0) {
 #pragma unroll
-  for (int c = 0; c < NR; ++c) acc[c] = zd{0.0, 0.0};
-  for (int j = 0; j < jn; ++j) {
-    const zd a = A[i + (int64_t)(j0 + j) * n0];
-#pragma unroll
-    for (int c = 0; c < NR; ++c) zfma(acc[c], a, tv[j][c]);
+    for (int c = 0; c < NR; ++c)
+      part[((int64_t)blockIdx.y * n0 + i) * NR + c] =
+          zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c]));
   }
-#pragma unroll
-  for (int c = 0; c < NR; ++c) part[((int64_t)blockIdx.y * n0 + i) * NR + c] = acc[c];
 }
+
 template <int NR>
 __global__ void __launch_bounds__(256) top_n_fin_kernel(int n0, int nblk, const int32_t* __restrict__ top,
                                                         const zd* __restrict__ part, zd* __restrict__ x) {
@@ -488,7 +487,7 @@ void launch_solve_top(const zd* Ainv, int n0, const int32_t* top, zd* x, zd* tmp
   if (!adjoint) {
     const int nblk = (n0 + 255) / 256;
     zd* part = tmp + (int64_t)n0;
-    hipLaunchKernelGGL(top_n_part_kernel<1>, dim3(nblk, nblk), dim3(256), 0, st, Ainv, n0, tmp, part);
+    hipLaunchKernelGGL(top_rows_part_kernel<1>, dim3((n0 + 63) / 64, nblk), dim3(256), 0, st, Ainv, n0, tmp, part);
     hipLaunchKernelGGL(top_n_fin_kernel<1>, dim3((n0 + 255) / 256), dim3(256), 0, st, n0, nblk, top, part, x);
   } else {
     hipLaunchKernelGGL(top_c_kernel<1>, dim3((n0 + 3) / 4), dim3(256), 0, st, Ainv, n0, top, tmp, x);
