@@ -1147,6 +1147,8 @@ struct PendingPhase {
   std::vector<std::pair<int32_t, int64_t>> contrib;  // (destination, y index)
   std::vector<SolveBox> db;
   std::vector<SweepTask> txr, ty, tbp, tbt, tbt16;
+  std::vector<SweepTask> txr16, ty16, tbp16;  // single-vector items of 16 outputs / rows
+  std::vector<SweepTask> txs;                 // blocked: backward x_R sums, 64 entries of R
   std::vector<int32_t> dst;
   std::vector<int64_t> ptr, src;
 };
@@ -2325,6 +2327,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         auto& contrib = pp.contrib;
         auto& db = pp.db;
         auto &txr = pp.txr, &ty = pp.ty, &tbp = pp.tbp, &tbt = pp.tbt, &tbt16 = pp.tbt16;
+        auto &txr16 = pp.txr16, &ty16 = pp.ty16, &tbp16 = pp.tbp16, &txs = pp.txs;
+        double reread = 0;  // partial entries the blocked 16-row items would read, all items
         for (int b = ph.box_begin; b < ph.box_end; ++b) {
           FactorBox& fb = boxes[b];
           const int lb = b - ph.box_begin;
@@ -2337,21 +2341,32 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           d.nchunk = (fb.nsn + kSolveK - 1) / kSolveK;
           d.dx_off = dxlen;
           dxlen += fb.r;
-          const int ngrp = (fb.r + kSolveOut - 1) / kSolveOut;
-          for (int c = 0; c < d.nks; ++c)
+          const int ngrp = (fb.r + kSolveOut - 1) / kSolveOut, ngrp16 = (fb.r + 15) / 16;
+          for (int c = 0; c < d.nks; ++c) {
             for (int g = 0; g < ngrp; ++g)
               txr.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.s - c * kSolveK), c, g, 0});
+            for (int g = 0; g < ngrp16; ++g)
+              txr16.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.s - c * kSolveK), c, g, 0});
+          }
           // rows of S u N (forward) and of S (backward), 64 per item; the item of rows 0..63
           // also stores x_R, so a box without such rows still gets one (empty) item
           for (int k0 = 0; k0 < std::max(fb.nsn, 1); k0 += kSolveRows)
             ty.push_back(SweepTask{lb, k0, std::max(0, std::min(kSolveRows, fb.nsn - k0)), 0, 0, 0});
-          for (int c = 0; c < d.nchunk; ++c)
+          for (int k0 = 0; k0 < std::max(fb.nsn, 1); k0 += 16)
+            ty16.push_back(SweepTask{lb, k0, std::max(0, std::min(16, fb.nsn - k0)), 0, 0, 0});
+          for (int c = 0; c < d.nchunk; ++c) {
             for (int g = 0; g < ngrp; ++g)
               tbp.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.nsn - c * kSolveK), c, g, 0});
+            for (int g = 0; g < ngrp16; ++g)
+              tbp16.push_back(SweepTask{lb, c * kSolveK, std::min(kSolveK, fb.nsn - c * kSolveK), c, g, 0});
+          }
           for (int l0 = 0; l0 < std::max(fb.s, 1); l0 += kSolveRows)
             tbt.push_back(SweepTask{lb, l0, std::max(0, std::min(kSolveRows, fb.s - l0)), 0, 0, 0});
           for (int l0 = 0; l0 < std::max(fb.s, 1); l0 += 16)
             tbt16.push_back(SweepTask{lb, l0, std::max(0, std::min(16, fb.s - l0)), 0, 0, 0});
+          for (int k0 = 0; k0 < fb.r; k0 += kSolveRows)
+            txs.push_back(SweepTask{lb, k0, std::min(kSolveRows, fb.r - k0), 0, 0, 0});
+          reread += (double)((std::max(fb.s, 1) + 15) / 16) * fb.r * d.nchunk;
           ph.rmax = std::max(ph.rmax, fb.r);
           ph.smax = std::max(ph.smax, fb.s);
           db.push_back(d);
@@ -2359,6 +2374,9 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           po += (int64_t)d.nchunk * fb.r;
           xpo += (int64_t)d.nks * fb.r;
         }
+        // past 8 MiB of re-read partials (blocks of kSolveBlock complex128), one summing launch
+        // is cheaper than the re-reads
+        ph.blk_presum = reread * kSolveBlock * sizeof(zd) > 8.0 * (1 << 20);
         // scatter lists: every S u N position of every box of the phase, summed in box order
         for (int q = 0; q < ne; ++q) {
           ElimPlan& e = ep[q];
@@ -2547,13 +2565,41 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         pk.add(&ph.dbp, pp.tbp);
         pk.add(&ph.dbt, pp.tbt);
         pk.add(&ph.dbt16, pp.tbt16);
+        pk.add(&ph.dxs, pp.txs);
+        ph.nxs = (int)pp.txs.size();
         ph.nxr = (int)pp.txr.size();
         ph.ny = (int)pp.ty.size();
         ph.nbp = (int)pp.tbp.size();
         ph.nbt = (int)pp.tbt.size();
         ph.nbt16 = (int)pp.tbt16.size();
+        // single-vector sweeps: items of 16 outputs or rows where the items of 64 would leave
+        // most compute units idle
+        const int fine = kSolveFineBelow;
+        auto pick = [&](SweepTask** dst, int* cnt, int* gran, const std::vector<SweepTask>& coarse,
+                        const std::vector<SweepTask>& fine16, int coarse_gran) {
+          const bool f = (int)coarse.size() < fine;
+          pk.add(dst, f ? fine16 : coarse);
+          *cnt = (int)(f ? fine16 : coarse).size();
+          *gran = f ? 16 : coarse_gran;
+        };
+        pick(&ph.s1xr, &ph.n1xr, &ph.g1xr, pp.txr, pp.txr16, kSolveOut);
+        pick(&ph.s1y, &ph.n1y, &ph.g1y, pp.ty, pp.ty16, kSolveRows);
+        pick(&ph.s1bp, &ph.n1bp, &ph.g1bp, pp.tbp, pp.tbp16, kSolveOut);
+        pick(&ph.s1bt, &ph.n1bt, &ph.g1bt, pp.tbt, pp.tbt16, kSolveRows);
       }
       sg.commit(arena, pk);
+      if (opts.verbose) {
+        int nf[4] = {0, 0, 0, 0}, maxc[4] = {0, 0, 0, 0}, npre = 0;
+        for (auto& ph : newph) {
+          npre += ph.blk_presum;
+          nf[0] += ph.g1xr == 16; nf[1] += ph.g1y == 16; nf[2] += ph.g1bp == 16; nf[3] += ph.g1bt == 16;
+          maxc[0] = std::max(maxc[0], ph.nxr); maxc[1] = std::max(maxc[1], ph.ny);
+          maxc[2] = std::max(maxc[2], ph.nbp); maxc[3] = std::max(maxc[3], ph.nbt);
+        }
+        fprintf(stderr, "[fmmlu] single-vector sweeps: phases with 16-wide items (of %zu) xr %d y %d bpart %d bt %d; "
+                "most 64-wide items in a phase %d %d %d %d; blocked sweeps summing x_R per phase: %d\n", newph.size(),
+                nf[0], nf[1], nf[2], nf[3], maxc[0], maxc[1], maxc[2], maxc[3], npre);
+      }
       for (auto& ph : newph) phases.push_back(ph);
     }
     pending.clear();
@@ -2645,8 +2691,8 @@ void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* 
       launch_blk_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st);
       launch_blk_y(ph.dboxes, ph.dy, ph.ny, w.x, w.xrp, w.xrg, w.y, adj, f32, st);
     } else {
-      launch_solve_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st, nr);
-      launch_solve_y(ph.dboxes, ph.dy, ph.ny, w.x, w.xrp, w.xrg, w.y, adj, f32, st, nr);
+      launch_solve_xr_part(ph.dboxes, ph.s1xr, ph.n1xr, ph.g1xr, w.x, w.xrp, adj, f32, st, nr);
+      launch_solve_y(ph.dboxes, ph.s1y, ph.n1y, ph.g1y, w.x, w.xrp, w.xrg, w.y, adj, f32, st, nr);
     }
     launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, w.y, w.x, st, nr);
   }
@@ -2665,10 +2711,11 @@ void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* 
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
     if (blk) {
       launch_blk_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st);
-      launch_blk_bt(it->dboxes, it->dbt16, it->nbt16, w.xrd, w.p, w.x, adj, f32, st);
+      if (it->blk_presum) launch_blk_xr_sub(it->dboxes, it->dxs, it->nxs, w.xrd, w.p, w.x, st);
+      launch_blk_bt(it->dboxes, it->dbt16, it->nbt16, w.xrd, w.p, w.x, adj, it->blk_presum, f32, st);
     } else {
-      launch_solve_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st, nr);
-      launch_solve_bt(it->dboxes, it->dbt, it->nbt, w.xrd, w.p, w.x, adj, f32, st, nr);
+      launch_solve_bpart(it->dboxes, it->s1bp, it->n1bp, it->g1bp, w.x, w.p, adj, f32, st, nr);
+      launch_solve_bt(it->dboxes, it->s1bt, it->n1bt, it->g1bt, w.xrd, w.p, w.x, adj, f32, st, nr);
     }
   }
   launch_permute(w.x, xc, order_dev, n, 0, st, nr, ldx, m);

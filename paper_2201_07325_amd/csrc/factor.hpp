@@ -85,6 +85,14 @@ struct SolvePhase {
   SweepTask *dxr = nullptr, *dy = nullptr, *dbp = nullptr, *dbt = nullptr;
   SweepTask* dbt16 = nullptr;  // blocked sweeps: rows of x_S in items of 16
   int nxr = 0, ny = 0, nbp = 0, nbt = 0, nbt16 = 0;
+  // single-vector sweeps: the same steps, each in items of 64 or of 16 outputs / rows (g1*)
+  SweepTask *s1xr = nullptr, *s1y = nullptr, *s1bp = nullptr, *s1bt = nullptr;
+  int n1xr = 0, n1y = 0, n1bp = 0, n1bt = 0;
+  int g1xr = kSolveOut, g1y = kSolveRows, g1bp = kSolveOut, g1bt = kSolveRows;
+  // blocked sweeps: backward x_R summed once per phase (items of 64 entries of R) where the
+  // 16-row items would each re-read many partials
+  SweepTask* dxs = nullptr;
+  int nxs = 0, blk_presum = 0;
   int rmax = 0, smax = 0;
 };
 

@@ -360,19 +360,25 @@ struct SweepTask {
 constexpr int kSolveRows = 64;   // rows per row-GEMV work item (one row per lane)
 constexpr int kSolveK = 256;     // k-chunk of column GEMVs (over s or s + nN) and of staged x_R
 constexpr int kSolveOut = 64;    // outputs per column-GEMV work item
+// single-vector sweeps: a step whose phase has fewer items of 64 than this (two per compute
+// unit) runs in items of 16 outputs or rows instead
+constexpr int kSolveFineBelow = 512;
 
 // Vectors inside the sweeps are interleaved (entry i of right-hand side c at [i nr + c]):
 // nr = 1 for the single-vector kernels below, nr = kSolveBlock for the blocked ones (matrix
 // cores, launch_blk_*); the permutations, scatter and top-block gather and sum take either.
 constexpr int kSolveBlock = 32;
 constexpr int kApplyK = 64;  // k-chunk of the staged vector block in the blocked sweeps (32 KiB)
+// Single-vector sweep steps. Column products take output groups of gsz (64, or 16 on phases
+// with few work items: task grp g covers outputs [g gsz, (g + 1) gsz)); row products take
+// items of `rows` (64 or 16) rows.
 // forward: partials of op(T)^T x_S (T^T, adjoint T^H) per (box, s-chunk, output group)
-void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
-                          bool f32, hipStream_t st, int nr = 1);
-// forward, per (box, 64 rows of S u N): x_R = x[R] - sum of the partials (kept in XRg by the
-// items of rows 0..63), then y = op(P) x_R (Lp, adjoint conj(Up^T)) for those rows
-void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg,
-                    zd* y, int adjoint, bool f32, hipStream_t st, int nr = 1);
+void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pxr,
+                          int adjoint, bool f32, hipStream_t st, int nr = 1);
+// forward, per (box, item of rows of S u N): x_R = x[R] - sum of the partials (kept in XRg by
+// the item of the first rows), then y = op(P) x_R (Lp, adjoint conj(Up^T)) for those rows
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
+                    zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st, int nr = 1);
 // x[dst[d]] -= sum of y[src[q]] over ptr[d] <= q < ptr[d+1] (deterministic scatter)
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st, int nr = 1);
@@ -381,12 +387,12 @@ void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* s
 void launch_solve_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, int rmax, const zd* XRg, zd* XRd,
                        int adjoint, bool f32, hipStream_t st, int nr = 1);
 // backward: partials of op(Q)^T x_SN (Up, adjoint Lp^H) per (box, column chunk, output group)
-void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
+void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pbuf,
                         int adjoint, bool f32, hipStream_t st, int nr = 1);
-// backward, per (box, 64 rows of S): x_R = XRd - sum of the partials (written to x[R] by the
-// items of rows 0..63), then x_S -= op(T) x_R (T, adjoint conj(T)) for those rows
-void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pbuf, zd* x,
-                     int adjoint, bool f32, hipStream_t st, int nr = 1);
+// backward, per (box, item of rows of S): x_R = XRd - sum of the partials (written to x[R] by
+// the item of the first rows), then x_S -= op(T) x_R (T, adjoint conj(T)) for those rows
+void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* XRd,
+                     const zd* Pbuf, zd* x, int adjoint, bool f32, hipStream_t st, int nr = 1);
 // The same steps for blocks of kSolveBlock right-hand sides on the matrix cores (same work
 // items, except items of 16 rows of S for launch_blk_bt; the pivot blocks take one item per
 // (box, 64 outputs) with box indexing the table of all boxes; the top block's partials over
@@ -399,8 +405,12 @@ void launch_blk_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, cons
                      bool f32, hipStream_t st);
 void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pb, int adjoint,
                       bool f32, hipStream_t st);
+// backward x_R = XRd - sum of the partials per (box, 64 entries of R), stored back to XRd and
+// to x[R]; launch_blk_bt with presummed = 1 then stages XRd alone
+void launch_blk_xr_sub(const SolveBox* boxes, const SweepTask* tasks, int nt, zd* XRd, const zd* Pb, zd* x,
+                       hipStream_t st);
 void launch_blk_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pb, zd* x,
-                   int adjoint, bool f32, hipStream_t st);
+                   int adjoint, int presummed, bool f32, hipStream_t st);
 void launch_blk_top_part(const zd* Ainv, int n0, const zd* tmp, zd* part, int adjoint, hipStream_t st);
 // top block: x_t = Ainv x_t (adjoint Ainv^H); tmp holds n0 (1 + nblk) nr entries, nblk =
 // ceil(n0 / 256). Blocked: gather, launch_blk_top_part on (tmp, tmp + n0 nr), then the sum

@@ -274,22 +274,41 @@ __global__ void __launch_bounds__(256) blk_bpart_kernel(const SolveBox* __restri
                  [&](int i, int c, zd v) { out[(int64_t)i * NB + c] = v; });
 }
 
+// backward, per (box, 64 entries of R): x_R = XRd - sum of the partials, stored back to XRd
+// and to x[R] (phases whose row items would each re-read many partials)
+__global__ void __launch_bounds__(256) blk_xr_sub_kernel(const SolveBox* __restrict__ boxes,
+                                                         const SweepTask* __restrict__ tasks, zd* __restrict__ XRd,
+                                                         const zd* __restrict__ Pb, zd* __restrict__ x) {
+  const SweepTask t = tasks[blockIdx.x];
+  const SolveBox b = boxes[t.box];
+  for (int e = threadIdx.x; e < t.kn * NB; e += 256) {
+    const int k = t.k0 + e / NB, c = e % NB;
+    zd v = XRd[(b.dx_off + k) * NB + c];
+    for (int ch = 0; ch < b.nchunk; ++ch) v = zsub(v, Pb[(b.p_off + (int64_t)ch * b.r + k) * NB + c]);
+    XRd[(b.dx_off + k) * NB + c] = v;
+    x[(int64_t)b.R[k] * NB + c] = v;
+  }
+}
+
 // backward, per (box, 16 rows of S): x_R = XRd - sum of the partials (written to x[R] by the
-// item of rows 0..15), x_S -= op(T) x_R (T, adjoint conj(T)) for the item's rows
+// item of rows 0..15), x_S -= op(T) x_R (T, adjoint conj(T)) for the item's rows. presummed:
+// blk_xr_sub_kernel has already done the first step (x_R is XRd).
 template <class FT>
 __global__ void __launch_bounds__(256) blk_bt_kernel(const SolveBox* __restrict__ boxes,
                                                      const SweepTask* __restrict__ tasks, const zd* __restrict__ XRd,
-                                                     const zd* __restrict__ Pb, zd* __restrict__ x, int adjoint) {
+                                                     const zd* __restrict__ Pb, zd* __restrict__ x, int adjoint,
+                                                     int presummed) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd sv[KC][NB];
-  const bool keep = t.k0 == 0;
+  const bool keep = t.k0 == 0 && !presummed;
+  const int nch = presummed ? 0 : b.nchunk;
   rows_block16<FT>(static_cast<const FT*>(b.T), b.s, t.k0, t.kn, b.r, adjoint != 0, sv,
                  [&](int kb, int kn, zd(*s)[NB]) {
                    for (int e = threadIdx.x; e < kn * NB; e += 256) {
                      const int k = e / NB, c = e % NB;
                      zd v = XRd[(b.dx_off + kb + k) * NB + c];
-                     for (int ch = 0; ch < b.nchunk; ++ch)
+                     for (int ch = 0; ch < nch; ++ch)
                        v = zsub(v, Pb[(b.p_off + (int64_t)ch * b.r + kb + k) * NB + c]);
                      s[k][c] = v;
                      if (keep) x[(int64_t)b.R[kb + k] * NB + c] = v;
@@ -357,10 +376,17 @@ void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, con
   FMMLU_FT_LAUNCH(blk_bpart_kernel, nt, boxes, tasks, x, Pb, adjoint);
 }
 
-void launch_blk_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pb, zd* x,
-                   int adjoint, bool f32, hipStream_t st) {
+void launch_blk_xr_sub(const SolveBox* boxes, const SweepTask* tasks, int nt, zd* XRd, const zd* Pb, zd* x,
+                       hipStream_t st) {
   if (nt <= 0) return;
-  FMMLU_FT_LAUNCH(blk_bt_kernel, nt, boxes, tasks, XRd, Pb, x, adjoint);
+  hipLaunchKernelGGL(blk_xr_sub_kernel, dim3(nt), dim3(256), 0, st, boxes, tasks, XRd, Pb, x);
+  FMMLU_HIP(hipGetLastError());
+}
+
+void launch_blk_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pb, zd* x,
+                   int adjoint, int presummed, bool f32, hipStream_t st) {
+  if (nt <= 0) return;
+  FMMLU_FT_LAUNCH(blk_bt_kernel, nt, boxes, tasks, XRd, Pb, x, adjoint, presummed);
 }
 
 void launch_blk_top_part(const zd* Ainv, int n0, const zd* tmp, zd* part, int adjoint, hipStream_t st) {

@@ -84,19 +84,20 @@ __device__ inline void colgemv_group(const FT* __restrict__ A, int64_t lda, int 
   }
 }
 
-// Forward: Pxr[c-chunk][i] = sum_{k in s-chunk} op(T)[k, i] x_S[k] (T^T, adjoint T^H).
+// Forward: Pxr[c-chunk][i] = sum_{k in s-chunk} op(T)[k, i] x_S[k] (T^T, adjoint T^H), for the
+// gsz outputs of group t.grp (gsz = 64, or 16 on phases with few work items).
 template <class FT, int NR>
 __global__ void __launch_bounds__(256) solve_xr_part_kernel(const SolveBox* __restrict__ boxes,
                                                             const SweepTask* __restrict__ tasks,
                                                             const zd* __restrict__ x, zd* __restrict__ Pxr,
-                                                            int adjoint) {
+                                                            int adjoint, int gsz) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd xs[kSolveK][NR];
   for (int e = threadIdx.x; e < t.kn * NR; e += 256) xs[e / NR][e % NR] = x[(int64_t)b.S[t.k0 + e / NR] * NR + e % NR];
   __syncthreads();
   zd* out = Pxr + (b.xrp_off + (int64_t)(t.k0 / kSolveK) * b.r) * NR;
-  const int i0 = t.grp * kSolveOut, i1 = min(b.r, i0 + kSolveOut);
+  const int i0 = t.grp * gsz, i1 = min(b.r, i0 + gsz);
   colgemv_group<FT, NR>(static_cast<const FT*>(b.T) + t.k0, b.s, i0, i1, t.kn, adjoint != 0, xs,
                         [&](int i, int c, zd d) { out[(int64_t)i * NR + c] = d; });
 }
@@ -156,10 +157,62 @@ __device__ inline void rows_reduce(zd (*xr)[NR], const zd (&acc)[NR]) {
   __syncthreads();
 }
 
+// As rows_times_xr for items of 16 rows: lane l takes row l % 16 and, with the other lanes
+// and wavefronts, every 16th column from l / 16 + 4 wave on (eight loads in flight each); the
+// 16 partial sums of each row meet in LDS (rows16_sum).
+template <class FT, int NR, class Stage>
+__device__ inline void rows16_times_xr(const FT* __restrict__ M, int64_t ld, int r, int i, bool row, bool conjM,
+                                       zd (*xr)[NR], zd (&acc)[NR], Stage stage) {
+  const int kl = ((threadIdx.x & 63) >> 4) + 4 * (threadIdx.x >> 6);
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = zd{0.0, 0.0};
+  for (int kb = 0; kb < r; kb += kSolveK) {
+    const int kn = min(kSolveK, r - kb);
+    stage(kb, kn);
+    __syncthreads();
+    if (row) {
+      const FT* col = M + i + (int64_t)kb * ld;
+      for (int k0 = kl; k0 < kn; k0 += 128) {
+        zd a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + 16 * q;
+          a[q] = k < kn ? widen(col[(int64_t)k * ld]) : zd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + 16 * q;
+          if (k < kn) {
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+              if (conjM)
+                zfmac(acc[c], a[q], xr[k][c]);
+              else
+                zfma(acc[c], a[q], xr[k][c]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// the 16 partial sums of row `rho` (< 16) left by rows16_times_xr, in a fixed order (call
+// after every thread has stored its acc to xr[threadIdx.x] and a barrier)
+template <int NR>
+__device__ inline zd rows16_sum(zd (*xr)[NR], int rho, int c) {
+  zd v{0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v = zadd(v, xr[(j >> 2) * 64 + (j & 3) * 16 + rho][c]);
+  return v;
+}
+
 // Forward, per (box, 64 rows of S u N): x_R = x[R] - sum of the x_R partials, staged chunk by
 // chunk (the item of rows 0..63 also keeps it in XRg); y = op(P) x_R for the item's rows,
-// P = Lp (adjoint conj(Up^T)). A box with no S u N rows has one item without rows.
-template <class FT, int NR>
+// P = Lp (adjoint conj(Up^T)). A box with no S u N rows has one item without rows. RPI = 16:
+// the same in items of 16 rows (phases with few boxes).
+template <class FT, int NR, int RPI>
 __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict__ boxes,
                                                       const SweepTask* __restrict__ tasks,
                                                       const zd* __restrict__ x, const zd* __restrict__ Pxr,
@@ -168,25 +221,37 @@ __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict
   const SolveBox b = boxes[t.box];
   __shared__ zd xr[kSolveK][NR];
   const int lane = threadIdx.x & 63;
-  const int i = t.k0 + lane;
+  const int rho = RPI == 64 ? lane : (lane & 15);
+  const int i = t.k0 + rho;
   const bool keep = t.k0 == 0;
   zd acc[NR];
-  rows_times_xr<FT, NR>(static_cast<const FT*>(adjoint ? b.UpT : b.Lp), b.nsn, b.r, i, lane < t.kn, adjoint != 0,
-                        xr, acc, [&](int kb, int kn) {
-                          for (int e = threadIdx.x; e < kn * NR; e += 256) {
-                            const int k = e / NR, c = e % NR;
-                            zd v = x[(int64_t)b.R[kb + k] * NR + c];
-                            for (int ch = 0; ch < b.nks; ++ch)
-                              v = zsub(v, Pxr[(b.xrp_off + (int64_t)ch * b.r + kb + k) * NR + c]);
-                            xr[k][c] = v;
-                            if (keep) XRg[(b.dx_off + kb + k) * NR + c] = v;
-                          }
-                        });
-  rows_reduce<NR>(xr, acc);
-  if (threadIdx.x < 64 && lane < t.kn) {
+  const FT* P = static_cast<const FT*>(adjoint ? b.UpT : b.Lp);
+  auto stage = [&](int kb, int kn) {
+    for (int e = threadIdx.x; e < kn * NR; e += 256) {
+      const int k = e / NR, c = e % NR;
+      zd v = x[(int64_t)b.R[kb + k] * NR + c];
+      for (int ch = 0; ch < b.nks; ++ch)
+        v = zsub(v, Pxr[(b.xrp_off + (int64_t)ch * b.r + kb + k) * NR + c]);
+      xr[k][c] = v;
+      if (keep) XRg[(b.dx_off + kb + k) * NR + c] = v;
+    }
+  };
+  if constexpr (RPI == 64) {
+    rows_times_xr<FT, NR>(P, b.nsn, b.r, i, lane < t.kn, adjoint != 0, xr, acc, stage);
+    rows_reduce<NR>(xr, acc);
+    if (threadIdx.x < 64 && lane < t.kn) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c)
-      y[(b.y_off + i) * NR + c] = zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c]));
+      for (int c = 0; c < NR; ++c)
+        y[(b.y_off + i) * NR + c] =
+            zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c]));
+    }
+  } else {
+    rows16_times_xr<FT, NR>(P, b.nsn, b.r, i, rho < t.kn, adjoint != 0, xr, acc, stage);
+    rows_reduce<NR>(xr, acc);
+    if (threadIdx.x < 16 && rho < t.kn) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) y[(b.y_off + i) * NR + c] = rows16_sum<NR>(xr, rho, c);
+    }
   }
 }
 
@@ -286,7 +351,7 @@ template <class FT, int NR>
 __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __restrict__ boxes,
                                                           const SweepTask* __restrict__ tasks,
                                                           const zd* __restrict__ x, zd* __restrict__ Pbuf,
-                                                          int adjoint) {
+                                                          int adjoint, int gsz) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd xsn[kSolveK][NR];
@@ -295,15 +360,16 @@ __global__ void __launch_bounds__(256) solve_bpart_kernel(const SolveBox* __rest
   __syncthreads();
   zd* out = Pbuf + (b.p_off + (int64_t)t.chunk * b.r) * NR;
   const FT* Q = static_cast<const FT*>(adjoint ? b.Lp : b.UpT) + t.k0;
-  const int i0 = t.grp * kSolveOut, i1 = min(b.r, i0 + kSolveOut);
+  const int i0 = t.grp * gsz, i1 = min(b.r, i0 + gsz);
   colgemv_group<FT, NR>(Q, b.nsn, i0, i1, t.kn, adjoint != 0, xsn,
                         [&](int i, int c, zd d) { out[(int64_t)i * NR + c] = d; });
 }
 
 // Backward, per (box, 64 rows of S): x_R = XRd - sum of the backward partials, staged chunk by
 // chunk (the item of rows 0..63 also writes it to x[R]); x_S -= op(T) x_R for the item's rows
-// (T, adjoint conj(T)). A box with s = 0 has one item without rows.
-template <class FT, int NR>
+// (T, adjoint conj(T)). A box with s = 0 has one item without rows. RPI = 16: items of 16
+// rows.
+template <class FT, int NR, int RPI>
 __global__ void __launch_bounds__(256) solve_bt_kernel(const SolveBox* __restrict__ boxes,
                                                        const SweepTask* __restrict__ tasks,
                                                        const zd* __restrict__ XRd, const zd* __restrict__ Pbuf,
@@ -312,26 +378,39 @@ __global__ void __launch_bounds__(256) solve_bt_kernel(const SolveBox* __restric
   const SolveBox b = boxes[t.box];
   __shared__ zd xr[kSolveK][NR];
   const int lane = threadIdx.x & 63;
-  const int l = t.k0 + lane;
+  const int rho = RPI == 64 ? lane : (lane & 15);
+  const int l = t.k0 + rho;
   const bool keep = t.k0 == 0;
   zd acc[NR];
-  rows_times_xr<FT, NR>(static_cast<const FT*>(b.T), b.s, b.r, l, lane < t.kn, adjoint != 0, xr, acc,
-                        [&](int kb, int kn) {
-                          for (int e = threadIdx.x; e < kn * NR; e += 256) {
-                            const int k = e / NR, c = e % NR;
-                            zd v = XRd[(b.dx_off + kb + k) * NR + c];
-                            for (int ch = 0; ch < b.nchunk; ++ch)
-                              v = zsub(v, Pbuf[(b.p_off + (int64_t)ch * b.r + kb + k) * NR + c]);
-                            xr[k][c] = v;
-                            if (keep) x[(int64_t)b.R[kb + k] * NR + c] = v;
-                          }
-                        });
-  rows_reduce<NR>(xr, acc);
-  if (threadIdx.x < 64 && lane < t.kn) {
+  auto stage = [&](int kb, int kn) {
+    for (int e = threadIdx.x; e < kn * NR; e += 256) {
+      const int k = e / NR, c = e % NR;
+      zd v = XRd[(b.dx_off + kb + k) * NR + c];
+      for (int ch = 0; ch < b.nchunk; ++ch)
+        v = zsub(v, Pbuf[(b.p_off + (int64_t)ch * b.r + kb + k) * NR + c]);
+      xr[k][c] = v;
+      if (keep) x[(int64_t)b.R[kb + k] * NR + c] = v;
+    }
+  };
+  if constexpr (RPI == 64) {
+    rows_times_xr<FT, NR>(static_cast<const FT*>(b.T), b.s, b.r, l, lane < t.kn, adjoint != 0, xr, acc, stage);
+    rows_reduce<NR>(xr, acc);
+    if (threadIdx.x < 64 && lane < t.kn) {
 #pragma unroll
-    for (int c = 0; c < NR; ++c) {
-      const int64_t xi = (int64_t)b.S[l] * NR + c;
-      x[xi] = zsub(x[xi], zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c])));
+      for (int c = 0; c < NR; ++c) {
+        const int64_t xi = (int64_t)b.S[l] * NR + c;
+        x[xi] = zsub(x[xi], zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c])));
+      }
+    }
+  } else {
+    rows16_times_xr<FT, NR>(static_cast<const FT*>(b.T), b.s, b.r, l, rho < t.kn, adjoint != 0, xr, acc, stage);
+    rows_reduce<NR>(xr, acc);
+    if (threadIdx.x < 16 && rho < t.kn) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        const int64_t xi = (int64_t)b.S[l] * NR + c;
+        x[xi] = zsub(x[xi], rows16_sum<NR>(xr, rho, c));
+      }
     }
   }
 }
@@ -440,28 +519,46 @@ __global__ void __launch_bounds__(256) permute_kernel(const zd* __restrict__ src
     FMMLU_HIP(hipGetLastError());                                                       \
   } while (0)
 
-void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
-                          bool f32, hipStream_t st, int nr) {
+#define FMMLU_FT_RPI_LAUNCH(kern, grid, ...)                                                          \
+  do {                                                                                                 \
+    if (nr != 1) throw Error(FMMLU_EINVAL, "single-vector sweep kernel with " + std::to_string(nr) + " columns"); \
+    if (rows != 16 && rows != kSolveRows)                                                              \
+      throw Error(FMMLU_EINVAL, "sweep items of " + std::to_string(rows) + " rows");                   \
+    if (f32 && rows == 16)                                                                             \
+      hipLaunchKernelGGL((kern<zf, 1, 16>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);                \
+    else if (f32)                                                                                      \
+      hipLaunchKernelGGL((kern<zf, 1, kSolveRows>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);        \
+    else if (rows == 16)                                                                               \
+      hipLaunchKernelGGL((kern<zd, 1, 16>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);                \
+    else                                                                                               \
+      hipLaunchKernelGGL((kern<zd, 1, kSolveRows>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);        \
+    FMMLU_HIP(hipGetLastError());                                                                      \
+  } while (0)
+
+void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pxr,
+                          int adjoint, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_NR_LAUNCH(solve_xr_part_kernel, nt, 0, boxes, tasks, x, Pxr, adjoint);
+  if (gsz < 1 || gsz > kSolveOut) throw Error(FMMLU_EINVAL, "column-product group of " + std::to_string(gsz));
+  FMMLU_FT_NR_LAUNCH(solve_xr_part_kernel, nt, 0, boxes, tasks, x, Pxr, adjoint, gsz);
 }
 
-void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg,
-                    zd* y, int adjoint, bool f32, hipStream_t st, int nr) {
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
+                    zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_NR_LAUNCH(solve_y_kernel, nt, 0, boxes, tasks, x, Pxr, XRg, y, adjoint);
+  FMMLU_FT_RPI_LAUNCH(solve_y_kernel, nt, boxes, tasks, x, Pxr, XRg, y, adjoint);
 }
 
-void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pbuf,
+void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pbuf,
                         int adjoint, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_NR_LAUNCH(solve_bpart_kernel, nt, 0, boxes, tasks, x, Pbuf, adjoint);
+  if (gsz < 1 || gsz > kSolveOut) throw Error(FMMLU_EINVAL, "column-product group of " + std::to_string(gsz));
+  FMMLU_FT_NR_LAUNCH(solve_bpart_kernel, nt, 0, boxes, tasks, x, Pbuf, adjoint, gsz);
 }
 
-void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRd, const zd* Pbuf, zd* x,
-                     int adjoint, bool f32, hipStream_t st, int nr) {
+void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* XRd,
+                     const zd* Pbuf, zd* x, int adjoint, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_NR_LAUNCH(solve_bt_kernel, nt, 0, boxes, tasks, XRd, Pbuf, x, adjoint);
+  FMMLU_FT_RPI_LAUNCH(solve_bt_kernel, nt, boxes, tasks, XRd, Pbuf, x, adjoint);
 }
 
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
