@@ -2560,10 +2560,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         pk.add(&ph.sc_dst, pp.dst);
         pk.add(&ph.sc_ptr, pp.ptr);
         pk.add(&ph.sc_src, pp.src);
-        pk.add(&ph.dxr, pp.txr);
-        pk.add(&ph.dy, pp.ty);
-        pk.add(&ph.dbp, pp.tbp);
-        pk.add(&ph.dbt, pp.tbt);
         pk.add(&ph.dbt16, pp.tbt16);
         pk.add(&ph.dxs, pp.txs);
         ph.nxs = (int)pp.txs.size();
@@ -2572,12 +2568,10 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         ph.nbp = (int)pp.tbp.size();
         ph.nbt = (int)pp.tbt.size();
         ph.nbt16 = (int)pp.tbt16.size();
-        // single-vector sweeps: items of 16 outputs or rows where the items of 64 would leave
-        // most compute units idle
-        const int fine = kSolveFineBelow;
+        // items of 16 outputs or rows where the items of 64 would leave most compute units idle
         auto pick = [&](SweepTask** dst, int* cnt, int* gran, const std::vector<SweepTask>& coarse,
                         const std::vector<SweepTask>& fine16, int coarse_gran) {
-          const bool f = (int)coarse.size() < fine;
+          const bool f = (int)coarse.size() < kSolveFineBelow;
           pk.add(dst, f ? fine16 : coarse);
           *cnt = (int)(f ? fine16 : coarse).size();
           *gran = f ? 16 : coarse_gran;
@@ -2596,7 +2590,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           maxc[0] = std::max(maxc[0], ph.nxr); maxc[1] = std::max(maxc[1], ph.ny);
           maxc[2] = std::max(maxc[2], ph.nbp); maxc[3] = std::max(maxc[3], ph.nbt);
         }
-        fprintf(stderr, "[fmmlu] single-vector sweeps: phases with 16-wide items (of %zu) xr %d y %d bpart %d bt %d; "
+        fprintf(stderr, "[fmmlu] sweeps: phases with 16-wide items (of %zu) xr %d y %d bpart %d bt %d; "
                 "most 64-wide items in a phase %d %d %d %d; blocked sweeps summing x_R per phase: %d\n", newph.size(),
                 nf[0], nf[1], nf[2], nf[3], maxc[0], maxc[1], maxc[2], maxc[3], npre);
       }
@@ -2688,8 +2682,8 @@ void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* 
   // x_R and the updates y of S u N, then their deterministic sum into x
   for (auto& ph : phases) {
     if (blk) {
-      launch_blk_xr_part(ph.dboxes, ph.dxr, ph.nxr, w.x, w.xrp, adj, f32, st);
-      launch_blk_y(ph.dboxes, ph.dy, ph.ny, w.x, w.xrp, w.xrg, w.y, adj, f32, st);
+      launch_blk_xr_part(ph.dboxes, ph.s1xr, ph.n1xr, ph.g1xr, w.x, w.xrp, adj, f32, st);
+      launch_blk_y(ph.dboxes, ph.s1y, ph.n1y, ph.g1y, w.x, w.xrp, w.xrg, w.y, adj, f32, st);
     } else {
       launch_solve_xr_part(ph.dboxes, ph.s1xr, ph.n1xr, ph.g1xr, w.x, w.xrp, adj, f32, st, nr);
       launch_solve_y(ph.dboxes, ph.s1y, ph.n1y, ph.g1y, w.x, w.xrp, w.xrg, w.y, adj, f32, st, nr);
@@ -2710,7 +2704,7 @@ void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* 
   // then x_R into x and the updates of x_S
   for (auto it = phases.rbegin(); it != phases.rend(); ++it) {
     if (blk) {
-      launch_blk_bpart(it->dboxes, it->dbp, it->nbp, w.x, w.p, adj, f32, st);
+      launch_blk_bpart(it->dboxes, it->s1bp, it->n1bp, it->g1bp, w.x, w.p, adj, f32, st);
       if (it->blk_presum) launch_blk_xr_sub(it->dboxes, it->dxs, it->nxs, w.xrd, w.p, w.x, st);
       launch_blk_bt(it->dboxes, it->dbt16, it->nbt16, w.xrd, w.p, w.x, adj, it->blk_presum, f32, st);
     } else {

@@ -81,11 +81,13 @@ struct SolvePhase {
   int64_t* sc_src = nullptr;
   int64_t nd = 0;
   int64_t ylen = 0, plen = 0, xrplen = 0;
-  // work items: forward x_R partials, rows of y; backward x_R partials, rows of x_S
-  SweepTask *dxr = nullptr, *dy = nullptr, *dbp = nullptr, *dbt = nullptr;
+  // counts of the work items of 64 (forward x_R partials, rows of y; backward x_R partials,
+  // rows of x_S), from which each sweep picks its granularity
+  int nxr = 0, ny = 0, nbp = 0, nbt = 0;
   SweepTask* dbt16 = nullptr;  // blocked sweeps: rows of x_S in items of 16
-  int nxr = 0, ny = 0, nbp = 0, nbt = 0, nbt16 = 0;
-  // single-vector sweeps: the same steps, each in items of 64 or of 16 outputs / rows (g1*)
+  int nbt16 = 0;
+  // the same steps, each in items of 64 or of 16 outputs / rows (g1*), for the single-vector
+  // sweeps and (all but the rows of x_S) the blocked ones
   SweepTask *s1xr = nullptr, *s1y = nullptr, *s1bp = nullptr, *s1bt = nullptr;
   int n1xr = 0, n1y = 0, n1bp = 0, n1bt = 0;
   int g1xr = kSolveOut, g1y = kSolveRows, g1bp = kSolveOut, g1bt = kSolveRows;

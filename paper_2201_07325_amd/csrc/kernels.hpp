@@ -360,8 +360,8 @@ struct SweepTask {
 constexpr int kSolveRows = 64;   // rows per row-GEMV work item (one row per lane)
 constexpr int kSolveK = 256;     // k-chunk of column GEMVs (over s or s + nN) and of staged x_R
 constexpr int kSolveOut = 64;    // outputs per column-GEMV work item
-// single-vector sweeps: a step whose phase has fewer items of 64 than this (two per compute
-// unit) runs in items of 16 outputs or rows instead
+// sweeps: a step whose phase has fewer items of 64 than this (two per compute unit) runs in
+// items of 16 outputs or rows instead
 constexpr int kSolveFineBelow = 512;
 
 // Vectors inside the sweeps are interleaved (entry i of right-hand side c at [i nr + c]):
@@ -393,18 +393,19 @@ void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, i
 // the item of the first rows), then x_S -= op(T) x_R (T, adjoint conj(T)) for those rows
 void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* XRd,
                      const zd* Pbuf, zd* x, int adjoint, bool f32, hipStream_t st, int nr = 1);
-// The same steps for blocks of kSolveBlock right-hand sides on the matrix cores (same work
-// items, except items of 16 rows of S for launch_blk_bt; the pivot blocks take one item per
-// (box, 64 outputs) with box indexing the table of all boxes; the top block's partials over
-// chunks of 256 go to launch_solve_top_fin).
-void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
-                        bool f32, hipStream_t st);
-void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg, zd* y,
-                  int adjoint, bool f32, hipStream_t st);
+// The same steps for blocks of kSolveBlock right-hand sides on the matrix cores (the same work
+// items, with output groups or row items of 16 or 64 chosen per phase, and items of 16 rows of
+// S for launch_blk_bt; the pivot blocks take one item per (box, 64 outputs) with box indexing
+// the table of all boxes; the top block's partials over chunks of 256 go to
+// launch_solve_top_fin).
+void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pxr,
+                        int adjoint, bool f32, hipStream_t st);
+void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
+                  zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st);
 void launch_blk_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, zd* XRd, int adjoint,
                      bool f32, hipStream_t st);
-void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pb, int adjoint,
-                      bool f32, hipStream_t st);
+void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pb,
+                      int adjoint, bool f32, hipStream_t st);
 // backward x_R = XRd - sum of the partials per (box, 64 entries of R), stored back to XRd and
 // to x[R]; launch_blk_bt with presummed = 1 then stages XRd alone
 void launch_blk_xr_sub(const SolveBox* boxes, const SweepTask* tasks, int nt, zd* XRd, const zd* Pb, zd* x,

@@ -3,8 +3,10 @@
 // complex GEMM, computed with v_mfma_f64_16x16x4f64 (float32 factors are widened as they are
 // read). The block is interleaved as in the single-vector sweeps (entry i of right-hand side
 // c at [i NB + c]), and the work items are the same: column products over chunks of the
-// skeleton (or S u N) into partials of x_R, then items of 64 rows that rebuild x_R from the
-// partials while staging it in LDS and apply their rows of L or T.
+// skeleton (or S u N) into partials of x_R, then items of rows that rebuild x_R from the
+// partials while staging it in LDS and apply their rows of L or T (16 or 64 outputs or rows
+// per item as in the single-vector sweeps; the backward rows of T always in items of 16, with
+// x_R summed once per phase beforehand where those items would each re-read many partials).
 //
 // A workgroup of four wavefronts computes 64 outputs x kSolveBlock columns; wavefront w owns
 // outputs 16 w .. 16 w + 15 as kSolveBlock / 16 blocks of 16 x 16 of D (complex: real and
@@ -151,6 +153,23 @@ __device__ inline void cols_block(const FT* __restrict__ M, int64_t ld, int i0, 
   }
 }
 
+// The 16 x NB partial blocks of the four wavefronts (left in cr/ci) summed in LDS in
+// wavefront order; emit(i0 + i, c, value) for i < ni (sv reused: 4 x 16 rows of NB).
+template <class Emit>
+__device__ inline void sum_waves16(const dbl4 (&cr)[2][NCB], const dbl4 (&ci)[2][NCB], int i0, int ni,
+                                   zd (*sv)[NB], Emit emit) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sv[16 * wave + (lane >> 4) + 4 * r][16 * cb + (lane & 15)] = dval(cr, ci, cb, r);
+  __syncthreads();
+  for (int e = threadIdx.x; e < ni * NB; e += 256) {
+    const int i = e / NB, c = e % NB;
+    emit(i0 + i, c, zadd(zadd(sv[i][c], sv[16 + i][c]), zadd(sv[32 + i][c], sv[48 + i][c])));
+  }
+}
+
 // Rows [i0, i0 + ni) (ni <= 16) times the staged vector block over k in [0, K): the four
 // wavefronts split every staged chunk of KC = 64 columns into four runs of 16 and their 16 x NB
 // partial blocks are summed in LDS (wavefront order) at the end: four times the work items of
@@ -159,7 +178,7 @@ template <class FT, class Stage, class Emit>
 __device__ inline void rows_block16(const FT* __restrict__ M, int64_t ld, int i0, int ni, int K, bool conj,
                                     zd (*sv)[NB], Stage stage, Emit emit) {
   static_assert(KC == 64, "four runs of 16 columns per staged chunk");
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
   dbl4 cr[2][NCB], ci[2][NCB];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -176,21 +195,40 @@ __device__ inline void rows_block16(const FT* __restrict__ M, int64_t ld, int i0
     if (ni > 0 && kw > 0) block_mma<true, FT>(M + i0 + (int64_t)(kb + k0) * ld, ld, ni, kw, conj, sv + k0, cr, ci);
     __syncthreads();
   }
-  // partial blocks of the four wavefronts side by side in LDS (sv reused: 4 x 16 rows of NB)
-  zd(*red)[NB] = sv;
-#pragma unroll
-  for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) red[16 * wave + (lane >> 4) + 4 * r][16 * cb + (lane & 15)] = dval(cr, ci, cb, r);
-  __syncthreads();
-  for (int e = threadIdx.x; e < ni * NB; e += 256) {
-    const int i = e / NB, c = e % NB;
-    emit(i0 + i, c, zadd(zadd(red[i][c], red[16 + i][c]), zadd(red[32 + i][c], red[48 + i][c])));
-  }
+  sum_waves16(cr, ci, i0, ni, sv, emit);
 }
 
-// forward: Pxr[chunk][i] = sum_{k in the s-chunk} op(T)[k, i] x_S[k] (T^T, adjoint T^H)
-template <class FT>
+// Outputs [i0, i0 + ni) (ni <= 16) of cols_block: the four wavefronts split every staged chunk
+// of KC = 64 into four runs of 16 and sum their partial blocks at the end (four times the
+// work items of cols_block for phases with few boxes).
+template <class FT, class Stage, class Emit>
+__device__ inline void cols_block16(const FT* __restrict__ M, int64_t ld, int i0, int ni, int k0, int k1, bool conj,
+                                    zd (*sv)[NB], Stage stage, Emit emit) {
+  static_assert(KC == 64, "four runs of 16 columns per staged chunk");
+  const int wave = threadIdx.x >> 6;
+  dbl4 cr[2][NCB], ci[2][NCB];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      cr[h][cb] = dbl4{0, 0, 0, 0};
+      ci[h][cb] = dbl4{0, 0, 0, 0};
+    }
+  for (int kb = k0; kb < k1; kb += KC) {
+    const int kn = min(KC, k1 - kb);
+    stage(kb, kn, sv);
+    __syncthreads();
+    const int kw0 = 16 * wave, kw = min(16, kn - kw0);
+    if (ni > 0 && kw > 0)
+      block_mma<false, FT>(M + (int64_t)i0 * ld + kb + kw0, ld, ni, kw, conj, sv + kw0, cr, ci);
+    __syncthreads();
+  }
+  sum_waves16(cr, ci, i0, ni, sv, emit);
+}
+
+// forward: Pxr[chunk][i] = sum_{k in the s-chunk} op(T)[k, i] x_S[k] (T^T, adjoint T^H), for
+// the G outputs of group t.grp (G = 64, or 16 on phases with few work items)
+template <class FT, int G>
 __global__ void __launch_bounds__(256) blk_xr_part_kernel(const SolveBox* __restrict__ boxes,
                                                           const SweepTask* __restrict__ tasks,
                                                           const zd* __restrict__ x, zd* __restrict__ Pxr,
@@ -198,20 +236,23 @@ __global__ void __launch_bounds__(256) blk_xr_part_kernel(const SolveBox* __rest
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd sv[KC][NB];
-  const int i0 = t.grp * kSolveOut;
+  const int i0 = t.grp * G;
   zd* out = Pxr + (b.xrp_off + (int64_t)t.chunk * b.r) * NB;
-  cols_block<FT>(static_cast<const FT*>(b.T), b.s, i0, min(kSolveOut, b.r - i0), t.k0, t.k0 + t.kn, adjoint != 0,
-                 sv,
-                 [&](int kb, int kn, zd(*s)[NB]) {
-                   for (int e = threadIdx.x; e < kn * NB; e += 256)
-                     s[e / NB][e % NB] = x[(int64_t)b.S[kb + e / NB] * NB + e % NB];
-                 },
-                 [&](int i, int c, zd v) { out[(int64_t)i * NB + c] = v; });
+  auto stage = [&](int kb, int kn, zd(*s)[NB]) {
+    for (int e = threadIdx.x; e < kn * NB; e += 256) s[e / NB][e % NB] = x[(int64_t)b.S[kb + e / NB] * NB + e % NB];
+  };
+  auto emit = [&](int i, int c, zd v) { out[(int64_t)i * NB + c] = v; };
+  if constexpr (G == 16)
+    cols_block16<FT>(static_cast<const FT*>(b.T), b.s, i0, min(G, b.r - i0), t.k0, t.k0 + t.kn, adjoint != 0, sv,
+                     stage, emit);
+  else
+    cols_block<FT>(static_cast<const FT*>(b.T), b.s, i0, min(G, b.r - i0), t.k0, t.k0 + t.kn, adjoint != 0, sv,
+                   stage, emit);
 }
 
-// forward, per (box, 64 rows of S u N): x_R = x[R] - sum of the partials (kept in XRg by the
-// item of rows 0..63), y = op(P) x_R (Lp, adjoint conj(Up^T)) for the item's rows
-template <class FT>
+// forward, per (box, RPI rows of S u N): x_R = x[R] - sum of the partials (kept in XRg by the
+// item of the first rows), y = op(P) x_R (Lp, adjoint conj(Up^T)) for the item's rows
+template <class FT, int RPI>
 __global__ void __launch_bounds__(256) blk_y_kernel(const SolveBox* __restrict__ boxes,
                                                     const SweepTask* __restrict__ tasks, const zd* __restrict__ x,
                                                     const zd* __restrict__ Pxr, zd* __restrict__ XRg,
@@ -220,18 +261,21 @@ __global__ void __launch_bounds__(256) blk_y_kernel(const SolveBox* __restrict__
   const SolveBox b = boxes[t.box];
   __shared__ zd sv[KC][NB];
   const bool keep = t.k0 == 0;
-  rows_block<FT>(static_cast<const FT*>(adjoint ? b.UpT : b.Lp), b.nsn, t.k0, t.kn, b.r, adjoint != 0, sv,
-                 [&](int kb, int kn, zd(*s)[NB]) {
-                   for (int e = threadIdx.x; e < kn * NB; e += 256) {
-                     const int k = e / NB, c = e % NB;
-                     zd v = x[(int64_t)b.R[kb + k] * NB + c];
-                     for (int ch = 0; ch < b.nks; ++ch)
-                       v = zsub(v, Pxr[(b.xrp_off + (int64_t)ch * b.r + kb + k) * NB + c]);
-                     s[k][c] = v;
-                     if (keep) XRg[(b.dx_off + kb + k) * NB + c] = v;
-                   }
-                 },
-                 [&](int i, int c, zd v) { y[(b.y_off + i) * NB + c] = v; });
+  auto stage = [&](int kb, int kn, zd(*s)[NB]) {
+    for (int e = threadIdx.x; e < kn * NB; e += 256) {
+      const int k = e / NB, c = e % NB;
+      zd v = x[(int64_t)b.R[kb + k] * NB + c];
+      for (int ch = 0; ch < b.nks; ++ch) v = zsub(v, Pxr[(b.xrp_off + (int64_t)ch * b.r + kb + k) * NB + c]);
+      s[k][c] = v;
+      if (keep) XRg[(b.dx_off + kb + k) * NB + c] = v;
+    }
+  };
+  auto emit = [&](int i, int c, zd v) { y[(b.y_off + i) * NB + c] = v; };
+  const FT* P = static_cast<const FT*>(adjoint ? b.UpT : b.Lp);
+  if constexpr (RPI == 16)
+    rows_block16<FT>(P, b.nsn, t.k0, t.kn, b.r, adjoint != 0, sv, stage, emit);
+  else
+    rows_block<FT>(P, b.nsn, t.k0, t.kn, b.r, adjoint != 0, sv, stage, emit);
 }
 
 // pivot blocks, per (box, 64 outputs): XRd = Xi XRg (adjoint Xi^H XRg)
@@ -255,23 +299,26 @@ __global__ void __launch_bounds__(256) blk_diag_kernel(const SolveBox* __restric
     cols_block<FT>(static_cast<const FT*>(b.Xi), b.r, t.k0, t.kn, 0, b.r, true, sv, stage, emit);
 }
 
-// backward: Pb[chunk][i] = sum_{k in the chunk of S u N} op(Q)[k, i] x_SN[k] (U^T, adjoint conj(Lp))
-template <class FT>
+// backward: Pb[chunk][i] = sum_{k in the chunk of S u N} op(Q)[k, i] x_SN[k] (U^T, adjoint
+// conj(Lp)), output groups of G as in blk_xr_part_kernel
+template <class FT, int G>
 __global__ void __launch_bounds__(256) blk_bpart_kernel(const SolveBox* __restrict__ boxes,
                                                         const SweepTask* __restrict__ tasks,
                                                         const zd* __restrict__ x, zd* __restrict__ Pb, int adjoint) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd sv[KC][NB];
-  const int i0 = t.grp * kSolveOut;
+  const int i0 = t.grp * G;
   zd* out = Pb + (b.p_off + (int64_t)t.chunk * b.r) * NB;
-  cols_block<FT>(static_cast<const FT*>(adjoint ? b.Lp : b.UpT), b.nsn, i0, min(kSolveOut, b.r - i0), t.k0,
-                 t.k0 + t.kn, adjoint != 0, sv,
-                 [&](int kb, int kn, zd(*s)[NB]) {
-                   for (int e = threadIdx.x; e < kn * NB; e += 256)
-                     s[e / NB][e % NB] = x[(int64_t)b.SN[kb + e / NB] * NB + e % NB];
-                 },
-                 [&](int i, int c, zd v) { out[(int64_t)i * NB + c] = v; });
+  auto stage = [&](int kb, int kn, zd(*s)[NB]) {
+    for (int e = threadIdx.x; e < kn * NB; e += 256) s[e / NB][e % NB] = x[(int64_t)b.SN[kb + e / NB] * NB + e % NB];
+  };
+  auto emit = [&](int i, int c, zd v) { out[(int64_t)i * NB + c] = v; };
+  const FT* Q = static_cast<const FT*>(adjoint ? b.Lp : b.UpT);
+  if constexpr (G == 16)
+    cols_block16<FT>(Q, b.nsn, i0, min(G, b.r - i0), t.k0, t.k0 + t.kn, adjoint != 0, sv, stage, emit);
+  else
+    cols_block<FT>(Q, b.nsn, i0, min(G, b.r - i0), t.k0, t.k0 + t.kn, adjoint != 0, sv, stage, emit);
 }
 
 // backward, per (box, 64 entries of R): x_R = XRd - sum of the partials, stored back to XRd
@@ -352,16 +399,31 @@ __global__ void __launch_bounds__(256) blk_top_part_kernel(const zd* __restrict_
     FMMLU_HIP(hipGetLastError());                                                       \
   } while (0)
 
-void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pxr, int adjoint,
-                        bool f32, hipStream_t st) {
+// kern<FT, 16> or kern<FT, 64> by the granularity g (outputs or rows per work item)
+#define FMMLU_FT_G_LAUNCH(kern, grid, g, ...)                                                        \
+  do {                                                                                              \
+    if (g != 16 && g != 64) throw Error(FMMLU_EINVAL, "blocked sweep items of " + std::to_string(g)); \
+    if (f32 && g == 16)                                                                             \
+      hipLaunchKernelGGL((kern<zf, 16>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);                \
+    else if (f32)                                                                                   \
+      hipLaunchKernelGGL((kern<zf, 64>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);                \
+    else if (g == 16)                                                                               \
+      hipLaunchKernelGGL((kern<zd, 16>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);                \
+    else                                                                                            \
+      hipLaunchKernelGGL((kern<zd, 64>), dim3(grid), dim3(256), 0, st, __VA_ARGS__);                \
+    FMMLU_HIP(hipGetLastError());                                                                   \
+  } while (0)
+
+void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pxr,
+                        int adjoint, bool f32, hipStream_t st) {
   if (nt <= 0) return;
-  FMMLU_FT_LAUNCH(blk_xr_part_kernel, nt, boxes, tasks, x, Pxr, adjoint);
+  FMMLU_FT_G_LAUNCH(blk_xr_part_kernel, nt, gsz, boxes, tasks, x, Pxr, adjoint);
 }
 
-void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, const zd* Pxr, zd* XRg, zd* y,
-                  int adjoint, bool f32, hipStream_t st) {
+void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
+                  zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st) {
   if (nt <= 0) return;
-  FMMLU_FT_LAUNCH(blk_y_kernel, nt, boxes, tasks, x, Pxr, XRg, y, adjoint);
+  FMMLU_FT_G_LAUNCH(blk_y_kernel, nt, rows, boxes, tasks, x, Pxr, XRg, y, adjoint);
 }
 
 void launch_blk_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, zd* XRd, int adjoint,
@@ -370,10 +432,10 @@ void launch_blk_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, cons
   FMMLU_FT_LAUNCH(blk_diag_kernel, nt, boxes, tasks, XRg, XRd, adjoint);
 }
 
-void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* x, zd* Pb, int adjoint,
-                      bool f32, hipStream_t st) {
+void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pb,
+                      int adjoint, bool f32, hipStream_t st) {
   if (nt <= 0) return;
-  FMMLU_FT_LAUNCH(blk_bpart_kernel, nt, boxes, tasks, x, Pb, adjoint);
+  FMMLU_FT_G_LAUNCH(blk_bpart_kernel, nt, gsz, boxes, tasks, x, Pb, adjoint);
 }
 
 void launch_blk_xr_sub(const SolveBox* boxes, const SweepTask* tasks, int nt, zd* XRd, const zd* Pb, zd* x,

@@ -10,8 +10,11 @@
 // Per colour phase and direction two or three launches: column products over chunks of the
 // skeleton (or S u N) into partials of x_R; then items of 64 rows that each rebuild x_R from
 // the partials while staging it in LDS and apply their rows of L or T (the four wavefronts of
-// an item split the columns, no further partials); forward, the scatter. x_R of every box
-// lives in one buffer between the forward sweep, the pivot blocks and the backward sweep.
+// an item split the columns, no further partials); forward, the scatter. On phases with few
+// boxes the column products take groups of 16 outputs and the row products items of 16 rows
+// (every wavefront then takes every 16th column), so that more compute units share the phase.
+// x_R of every box lives in one buffer between the forward sweep, the pivot blocks and the
+// backward sweep.
 //
 // Every kernel works on a block of NR right-hand sides at once (NR = 1 or kSolveBlock):
 // internal vectors are interleaved, entry i of right-hand side c at [i NR + c], so each
