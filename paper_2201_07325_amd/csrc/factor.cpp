@@ -1747,6 +1747,70 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       // is what makes the buffer of the phase before last free for reuse.
       sg.flip();
       const int nb = (int)plan.size();
+      // Schur contributions of the plan's boxes (box q = plan entry q), each assumed to keep a
+      // skeleton: contributions grouped by destination tile (tiles in pair order, boxes in
+      // order within a tile); ok = false if a needed tile is not stored
+      struct Contrib {
+        int64_t toff;
+        int64_t k;     // destination pair index (tiles lie in the pool in pair order)
+        int q;         // box index
+        int32_t a, b;  // group indices (0 = the box itself, else near owner index + 1)
+      };
+      struct SchurGroups {
+        std::vector<std::vector<int>> grps;  // per box: its owner, then its near owners
+        std::vector<Contrib> cl;             // grouped by destination tile
+        std::vector<int32_t> first{0};       // tile u has cl[first[u], first[u + 1])
+        bool ok = true;
+      };
+      auto schur_groups = [&](int nq) {
+        SchurGroups G;
+        G.grps.resize(nq);
+        std::vector<std::vector<Contrib>> pcl(nq);  // per box, built on host threads
+        std::vector<int> bad(nq, 0);
+        hp.ranges(nq, 4, [&](int lo, int hi) {
+          for (int q = lo; q < hi; ++q) {
+            const BoxPlan& bp = plan[q];
+            auto& grp = G.grps[q];
+            grp.push_back(bp.oi);
+            for (int o : bp.nown_) grp.push_back(o);
+            for (size_t a = 0; a < grp.size(); ++a)
+              for (size_t b = 0; b < grp.size(); ++b) {
+                const int M = (a == 0) ? 1 : (int)own[grp[a]].live.size();
+                const int N = (b == 0) ? 1 : (int)own[grp[b]].live.size();
+                if (M == 0 || N == 0) continue;
+                const int64_t k = pidx.pos(grp[a], grp[b]);
+                if (k < 0) {
+                  bad[q] = 1;
+                  continue;
+                }
+                pcl[q].push_back(Contrib{pidx.off[k], k, q, (int32_t)a, (int32_t)b});
+              }
+          }
+        });
+        for (int q = 0; q < nq; ++q)
+          if (bad[q]) G.ok = false;
+        // group by destination tile, boxes in order within a tile: count per touched pair
+        // (kcount is all zero between uses), order the touched pairs, place stably
+        std::vector<int64_t> tk;
+        size_t ncl = 0;
+        for (auto& v : pcl) {
+          ncl += v.size();
+          for (auto& c : v)
+            if (kcount[c.k]++ == 0) tk.push_back(c.k);
+        }
+        std::sort(tk.begin(), tk.end());
+        const int ntk = (int)tk.size();
+        G.first.assign(ntk + 1, 0);
+        for (int u = 0; u < ntk; ++u) {
+          G.first[u + 1] = G.first[u] + kcount[tk[u]];
+          kcount[tk[u]] = G.first[u];  // now the fill position of pair tk[u]
+        }
+        G.cl.resize(ncl);
+        for (auto& v : pcl)
+          for (auto& c : v) G.cl[kcount[c.k]++] = c;
+        for (int u = 0; u < ntk; ++u) kcount[tk[u]] = 0;
+        return G;
+      };
       ht.mark(2);
       // ---- 1. ID matrices
       std::vector<IdTask> idt;
@@ -1916,6 +1980,11 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           launch_cpqr(dct, nb, mmax, eps, sg.go());
         }
       }
+      // ---- Schur structure of the phase, built while the device computes the IDs: for every
+      //      box the destination tiles of its contributions (its own skeleton and near owners,
+      //      pairwise), grouped by destination tile with boxes in order within a tile; after the
+      //      read-back it is restricted to the boxes that eliminate something
+      const SchurGroups sg_pre = schur_groups(nb);
       // ---- read back ranks and pivots
       std::vector<int32_t> ranks(nb);
       std::vector<std::vector<int32_t>> perms(nb);
@@ -2178,66 +2247,47 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         // 5. Schur update of near-near tiles: A[SN, SN] -= X_{SN,R} Up. One GEMM task per
         //    destination tile; contributions of several boxes are its segments, in box order.
         {
-          struct Contrib {
-            int64_t toff;
-            int64_t k;     // destination pair index (tiles lie in the pool in pair order)
-            int q;         // elimination index (box order)
-            int32_t a, b;  // group indices (0 = the box itself, else near owner index + 1)
-          };
-          std::vector<std::vector<int>> grps(ne), goffs(ne);
-          std::vector<std::vector<Contrib>> pcl(ne);  // per box, built on host threads
-          std::vector<int> bad(ne, 0);
-          hp.ranges(ne, 4, [&](int lo, int hi) {
-            for (int q = lo; q < hi; ++q) {
-              ElimPlan& e = ep[q];
-              BoxPlan& bp = plan[e.pi];
-              auto& grp = grps[q];
-              auto& goff = goffs[q];
-              grp.push_back(bp.oi);
-              goff.push_back(0);
-              int off = e.s;
-              for (int o : bp.nown_) {
-                grp.push_back(o);
-                goff.push_back(off);
-                off += (int)own[o].live.size();
+          // the grouping built while the device computed the IDs, restricted to the boxes that
+          // eliminate something (box q = elimination index) and to non-empty contributions
+          // (a box without skeleton has none to or from itself); order within tiles is kept
+          if (!sg_pre.ok) throw Error(FMMLU_EINVAL, "internal: tile of a pair that is not close");
+          std::vector<int> qof(nb, -1);
+          for (int q = 0; q < ne; ++q) qof[ep[q].pi] = q;
+          bool same = ne == nb;
+          for (int q = 0; q < ne && same; ++q) same = ep[q].s > 0;
+          std::vector<Contrib> cl_f;
+          std::vector<int32_t> first_f;
+          if (!same) {
+            first_f.push_back(0);
+            cl_f.reserve(sg_pre.cl.size());
+            for (size_t u = 0; u + 1 < sg_pre.first.size(); ++u) {
+              for (int i = sg_pre.first[u]; i < sg_pre.first[u + 1]; ++i) {
+                Contrib c = sg_pre.cl[i];
+                const int q = qof[c.q];
+                if (q < 0 || ((c.a == 0 || c.b == 0) && ep[q].s == 0)) continue;
+                c.q = q;
+                cl_f.push_back(c);
               }
-              for (size_t a = 0; a < grp.size(); ++a)
-                for (size_t b = 0; b < grp.size(); ++b) {
-                  const int M = (a == 0) ? e.s : (int)own[grp[a]].live.size();
-                  const int N = (b == 0) ? e.s : (int)own[grp[b]].live.size();
-                  if (M == 0 || N == 0) continue;
-                  const int64_t k = pidx.pos(grp[a], grp[b]);
-                  if (k < 0) {
-                    bad[q] = 1;
-                    continue;
-                  }
-                  pcl[q].push_back(Contrib{pidx.off[k], k, q, (int32_t)a, (int32_t)b});
-                }
+              if ((int32_t)cl_f.size() > first_f.back()) first_f.push_back((int32_t)cl_f.size());
             }
-          });
-          for (int q = 0; q < ne; ++q)
-            if (bad[q]) throw Error(FMMLU_EINVAL, "internal: tile of a pair that is not close");
+          }
+          std::vector<const std::vector<int>*> grps(ne);
+          for (int q = 0; q < ne; ++q) grps[q] = &sg_pre.grps[ep[q].pi];
+          const std::vector<Contrib>& cl = same ? sg_pre.cl : cl_f;
+          const std::vector<int32_t>& first = same ? sg_pre.first : first_f;
+          const int ntk = (int)first.size() - 1;
+          // column offsets of the groups in S u N (the box's own skeleton first)
+          std::vector<std::vector<int>> goffs(ne);
+          for (int q = 0; q < ne; ++q) {
+            const std::vector<int>& grp = *grps[q];
+            goffs[q].resize(grp.size());
+            int off = ep[q].s;
+            for (size_t a = 1; a < grp.size(); ++a) {
+              goffs[q][a] = off;
+              off += (int)own[grp[a]].live.size();
+            }
+          }
           ht.mark(13);
-          // group by destination tile, boxes in order within a tile: count per touched pair
-          // (kcount is all zero between phases), order the touched pairs, place stably
-          std::vector<int64_t> tk;
-          size_t ncl = 0;
-          for (auto& v : pcl) {
-            ncl += v.size();
-            for (auto& c : v)
-              if (kcount[c.k]++ == 0) tk.push_back(c.k);
-          }
-          std::sort(tk.begin(), tk.end());
-          const int ntk = (int)tk.size();
-          std::vector<int32_t> first(ntk + 1, 0);
-          for (int u = 0; u < ntk; ++u) {
-            first[u + 1] = first[u] + kcount[tk[u]];
-            kcount[tk[u]] = first[u];  // now the fill position of pair tk[u]
-          }
-          std::vector<Contrib> cl(ncl);
-          for (auto& v : pcl)
-            for (auto& c : v) cl[kcount[c.k]++] = c;
-          for (int u = 0; u < ntk; ++u) kcount[tk[u]] = 0;
           // one GEMM task per destination tile with contributions, its segments in box order
           GemmBatch gs;
           gs.tasks.resize(ntk);
@@ -2258,7 +2308,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
               const Contrib& c0 = cl[i0];
               const ElimPlan& e0 = ep[c0.q];
               const BoxPlan& bp0 = plan[e0.pi];
-              const int o1 = grps[c0.q][c0.a], o2 = grps[c0.q][c0.b];
+              const int o1 = (*grps[c0.q])[c0.a], o2 = (*grps[c0.q])[c0.b];
               GemmTask t{};
               t.C = static_cast<char*>(pool) + (size_t)c0.toff * te;
               t.ldc = (int)own[o1].act.size();
