@@ -441,13 +441,16 @@ constexpr int kPcholThreads = 1024;
 // triangle) through a 32 x 32 LDS tile (part: >= 32 x 33 entries): reads along rows of Rt,
 // writes down columns. Called by all NT threads.
 template <int NT>
-__device__ inline void pchol_write_out(const PcholTask& t, int s, const int* pv, zd* part) {
+__device__ inline void pchol_write_out(const PcholTask& t, int s, const int* pv, zd* part, int ib = 0,
+                                       int nib = 1) {
   const int m = t.m, tid = threadIdx.x;
   const zd* __restrict__ Rt = t.Rt;
-  if (tid == 0) *t.rank = s;
-  for (int j = tid; j < m; j += NT) t.perm[j] = pv[j];
+  if (ib == 0) {
+    if (tid == 0) *t.rank = s;
+    for (int j = tid; j < m; j += NT) t.perm[j] = pv[j];
+  }
   zd(*tile)[33] = reinterpret_cast<zd(*)[33]>(part);
-  for (int i0 = 0; i0 < s; i0 += 32) {
+  for (int i0 = 32 * ib; i0 < s; i0 += 32 * nib) {
     for (int j0 = i0 & ~31; j0 < m; j0 += 32) {
       __syncthreads();
       for (int e = tid; e < 1024; e += NT) {
@@ -729,18 +732,22 @@ __global__ void __launch_bounds__(NT) pchol_block_kernel(const PcholTask* __rest
 }
 
 // after the last block: rank, perm and R in pivoted order
+// one workgroup per (box, 32-row block of R): blocks at or past the rank have nothing to write
 __global__ void __launch_bounds__(kPcholThreads) pchol_finish_kernel(const PcholTask* __restrict__ tasks) {
   const PcholTask t = tasks[blockIdx.x];
+  const int s = t.ist[2 * t.m];
+  if (blockIdx.y > 0 && 32 * (int)blockIdx.y >= s) return;
   __shared__ zd part[32 * 33];
   extern __shared__ int pvs[];
   for (int j = threadIdx.x; j < t.m; j += kPcholThreads) pvs[j] = t.ist[t.m + j];
   __syncthreads();
-  pchol_write_out<kPcholThreads>(t, t.ist[2 * t.m], pvs, part);
+  pchol_write_out<kPcholThreads>(t, s, pvs, part, (int)blockIdx.y, (int)gridDim.y);
 }
 
 // T = R11^{-1} R12 (s x (m - s), ld m) from R in pivoted order. Each workgroup holds NC
 // right-hand-side columns in LDS; blocks of 16 rows are solved there (diagonal block staged
-// in LDS), then the rows above are updated in one pass over the block's 16 columns of R.
+// in LDS, one thread per column), then the rows above are updated in one pass over the
+// block's 16 columns of R.
 template <int NC>
 __global__ void __launch_bounds__(256) pchol_t_kernel(const PcholTask* __restrict__ tasks) {
   const PcholTask t = tasks[blockIdx.x];
@@ -767,15 +774,25 @@ __global__ void __launch_bounds__(256) pchol_t_kernel(const PcholTask* __restric
       if (tid < b) dinv[tid] = 1.0 / Rp[(i0 + tid) + (int64_t)(i0 + tid) * m].re;
     }
     __syncthreads();
-    for (int i = b - 1; i >= 0; --i) {
-      if (tid < NC) W[(i0 + i) * NC + tid] = zscale(W[(i0 + i) * NC + tid], dinv[i]);
-      __syncthreads();
-      if (tid < i * NC) {
-        const int r = tid / NC, j = tid - r * NC;
-        W[(i0 + r) * NC + j] = zsub(W[(i0 + r) * NC + j], zmul(Rb[r][i], W[(i0 + i) * NC + j]));
+    // the diagonal block: one thread per right-hand-side column, in registers (the same
+    // operations in the same order as a row-by-row sweep, without a barrier per row)
+    if (tid < NC) {
+      zd w[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) w[q] = q < b ? W[(i0 + q) * NC + tid] : zd{0.0, 0.0};
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        if (i < b) {
+          w[i] = zscale(w[i], dinv[i]);
+#pragma unroll
+          for (int r = 0; r < i; ++r) w[r] = zsub(w[r], zmul(Rb[r][i], w[i]));
+        }
       }
-      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (q < b) W[(i0 + q) * NC + tid] = w[q];
     }
+    __syncthreads();
     for (int r = tid; r < i0; r += 256) {
       zd a[16];
 #pragma unroll
@@ -1670,7 +1687,8 @@ void launch_pchol_block(const PcholTask* tasks, int ntasks, int k0, double eps, 
 
 void launch_pchol_finish(const PcholTask* tasks, int ntasks, int mmax, hipStream_t st) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL(pchol_finish_kernel, dim3(ntasks), dim3(kPcholThreads), (size_t)mmax * sizeof(int), st, tasks);
+  hipLaunchKernelGGL(pchol_finish_kernel, dim3(ntasks, (unsigned)std::max(1, (mmax + 31) / 32)), dim3(kPcholThreads),
+                     (size_t)mmax * sizeof(int), st, tasks);
   FMMLU_HIP(hipGetLastError());
 }
 
