@@ -104,7 +104,13 @@ typedef struct {
                                  default kernels; 2, 3, 4 (testing): one kernel for every GEMM
                                  (direct-to-LDS where it applies, register-staged with eight or
                                  four wavefronts) */
-  int32_t reserved[3];
+  int32_t pchol_blocks;       /* 0 (default): the blocked pivoted Cholesky (Gram route, wide
+                                 boxes) launches blocks of pivots up to a bound from the ranks
+                                 seen so far, and the remaining blocks only when a box's pivoting
+                                 has not stopped by then (found at the rank read-back); k > 0
+                                 (testing): at most k blocks before the first read-back. The
+                                 result is the same either way. */
+  int32_t reserved[2];
 } fmmlu_opts;
 
 /* Per-factorization statistics. */

@@ -44,7 +44,7 @@ class Opts(C.Structure):
                 ("profile", C.c_int32), ("id_route", C.c_int32), ("test_zero_pivot_block", C.c_int32),
                 ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("corr_row_ptr", C.c_void_p), ("corr_col", C.c_void_p), ("corr_a", C.c_void_p),
-                ("gemm_autotune", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("gemm_autotune", C.c_int32), ("pchol_blocks", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 def _torch_alloc(nbytes, stream, ctx):
@@ -236,7 +236,8 @@ class Factor:
 
     def __init__(self, points, normals, weights, k, eta, eps=1e-6, leaf_size=64, tree=None,
                  proxy_radius=2.5, proxy_min_points=64, precision=0, verbose=0, mem_cap=0, profile=False,
-                 id_route=0, allocator="torch", test_zero_pivot_block=-1, corrections=None, gemm_autotune=1):
+                 id_route=0, allocator="torch", test_zero_pivot_block=-1, corrections=None, gemm_autotune=1,
+                 pchol_blocks=0):
         L = lib()
         self.points = _soa(points)
         self.n = self.points.size // 3
@@ -259,6 +260,7 @@ class Factor:
         o.id_route = int(id_route)
         o.test_zero_pivot_block = int(test_zero_pivot_block)
         o.gemm_autotune = int(gemm_autotune)
+        o.pchol_blocks = int(pchol_blocks)
         _set_allocator(o, allocator)
         keep = None
         if corrections is not None:

@@ -78,6 +78,7 @@ fmmlu_opts checked_opts(fmmlu_tree_h t, const double* xyz, const double* normals
   if (o.proxy_min_points < 1) throw Error(FMMLU_EINVAL, "proxy_min_points must be >= 1");
   if (o.id_route < 0 || o.id_route > 2) throw Error(FMMLU_EINVAL, "id_route must be 0, 1 or 2");
   if (o.gemm_autotune < 0 || o.gemm_autotune > 4) throw Error(FMMLU_EINVAL, "gemm_autotune must be in 0..4");
+  if (o.pchol_blocks < 0) throw Error(FMMLU_EINVAL, "pchol_blocks must be >= 0");
   if ((o.alloc == nullptr) != (o.free == nullptr))
     throw Error(FMMLU_EINVAL, "alloc and free must be given together");
   if ((o.corr_row_ptr == nullptr) != (o.corr_col == nullptr) || (o.corr_row_ptr == nullptr) != (o.corr_a == nullptr))

@@ -1437,8 +1437,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   Background spec_worker;
 
   HostTimers ht;
+  // largest rank seen at this level and at the level before (bounds for the blocked pivoting)
+  int rank_max_level = 0, rank_max_prev = 0;
+  int pchol_continued = 0;  // phases whose blocked pivoting ran past the bound (verbose report)
   for (int lev = tree.nlevels - 1; lev >= 2; --lev) {
     const int nown = (int)own.size();
+    if (rank_max_level > 0) rank_max_prev = rank_max_level;
+    rank_max_level = 0;
     // ---- close pairs of owners and their tiles: taken from the worker's speculative lists
     // when this level's owners are the ones it assumed, else searched here
     std::vector<std::vector<int>> close;
@@ -1877,6 +1882,10 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         }
       }
       int32_t* hr = nullptr;  // host copy of ranks and pivots (set where the read-back is queued)
+      // blocked pivoted Cholesky: the blocks past the predicted bound (run only when a box's
+      // pivoting had not stopped by then), and those blocks with a second read-back
+      std::function<void()> pchol_more, pchol_rest;
+      GemmBatch gu;  // the blocked pivoting's downdates of G (used by pchol_more as well)
       const bool gram = opts.id_route == 1 || (opts.id_route == 0 && eps >= kGramEps);
       if (gram) {
         constexpr int KCH = 512;
@@ -1907,7 +1916,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         // blocks by a batched GEMM on all compute units) instead of one workgroup streaming
         // every earlier row of R at every pivot
         const bool blocked = mmax >= kPcholBlockedMin && mmax <= kPcholThreadsB;
-        GemmBatch gu;
         if (blocked) {
           for (size_t i = 0; i < plan.size(); ++i) {
             PcholTask& t = pt[i];
@@ -1932,12 +1940,31 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         {
           ProfScope ps(prof, KC_CPQR);
           if (blocked) {
+            // blocks up to a bound on the phase's ranks (from the ranks seen so far); a box
+            // whose pivoting has not stopped there gets the remaining blocks after the rank
+            // read-back (pchol_more): the same sequence of blocks either way
             const int nblk = (mmax + kPcholNb - 1) / kPcholNb;
-            for (int b = 0; b < nblk; ++b) {
+            int bound = mmax;
+            if (rank_max_level > 0)
+              bound = (5 * rank_max_level) / 4 + kPcholNb;
+            else if (rank_max_prev > 0)
+              bound = (5 * rank_max_prev) / 2 + kPcholNb;
+            int nb1 = std::min(nblk, bound / kPcholNb + 1);
+            if (opts.pchol_blocks > 0) nb1 = std::min(nb1, opts.pchol_blocks);
+            for (int b = 0; b < nb1; ++b) {
               launch_pchol_block(dpt, nb, b * kPcholNb, eps, sg.go(), mmax);
               if (b + 1 < nblk) gu.launch(sg, 2);
             }
             launch_pchol_finish(dpt, nb, mmax, sg.go());
+            if (nb1 < nblk)
+              pchol_more = [&, dpt, nb1, nblk, mmax, nb] {
+                ProfScope ps2(prof, KC_CPQR);
+                for (int b = nb1; b < nblk; ++b) {
+                  launch_pchol_block(dpt, nb, b * kPcholNb, eps, sg.go(), mmax);
+                  if (b + 1 < nblk) gu.launch(sg, 2);
+                }
+                launch_pchol_finish(dpt, nb, mmax, sg.go());
+              };
           } else {
             launch_pchol(dpt, nb, mmax, eps, sg.go());
           }
@@ -1952,6 +1979,19 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           ProfScope ps(prof, KC_CPQR);
           launch_pchol_t(dpt, nb, mmax, sg.go());
         }
+        if (pchol_more)
+          pchol_rest = [&, dpt, mmax, nb, perm_total, rank_all, perm_all] {
+            pchol_more();
+            FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
+            FMMLU_HIP(
+                hipMemcpyAsync(hr + nb, perm_all, sizeof(int32_t) * perm_total, hipMemcpyDeviceToHost, sg.go()));
+            sg.mark();
+            {
+              ProfScope ps(prof, KC_CPQR);
+              launch_pchol_t(dpt, nb, mmax, sg.go());
+            }
+            sg.wait_mark();
+          };
       } else {
         std::vector<zd*> Ms;
         std::vector<int> rws, mms;
@@ -1991,6 +2031,15 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       {
         if (hr) {
           sg.wait_mark();
+          bool open = false;
+          for (int i = 0; i < nb; ++i) open = open || hr[i] < 0;
+          if (open) {
+            ++pchol_continued;
+            if (!pchol_rest) throw Error(FMMLU_EINVAL, "internal: pivoting unfinished after every block");
+            pchol_rest();
+            for (int i = 0; i < nb; ++i)
+              if (hr[i] < 0) throw Error(FMMLU_EINVAL, "internal: pivoting unfinished after every block");
+          }
         } else {
           hr = static_cast<int32_t*>(sg.host.alloc(sizeof(int32_t) * (size_t)(nb + perm_total)));
           FMMLU_HIP(hipMemcpyAsync(hr, rank_all, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, sg.go()));
@@ -2010,6 +2059,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         double f = 0;
         for (int kk = 0; kk < ranks[i]; ++kk) f += 2.0 * (double)(plan[i].m - kk) * (plan[i].m - kk);
         prof.flops[KC_CPQR] += 8.0 * f;
+        rank_max_level = std::max(rank_max_level, ranks[i]);
       }
       ht.mark(3);
       // ---- 3. elimination plan
@@ -2695,6 +2745,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             "graph capture %.2f, final wait %.2f\n", ms(0, 1), ms(1, 2), ms(2, 3), ms(3, 4), ms(4, 5));
     fprintf(stderr, "[fmmlu] schur planning: contributions %.3f tasks %.3f launch+rest %.3f\n", ht.t[13], ht.t[14],
             ht.t[5]);
+    fprintf(stderr, "[fmmlu] blocked pivoting continued past the rank bound in %d phases\n", pchol_continued);
   }
 }
 

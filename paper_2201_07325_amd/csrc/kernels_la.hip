@@ -442,11 +442,11 @@ constexpr int kPcholThreads = 1024;
 // writes down columns. Called by all NT threads.
 template <int NT>
 __device__ inline void pchol_write_out(const PcholTask& t, int s, const int* pv, zd* part, int ib = 0,
-                                       int nib = 1) {
+                                       int nib = 1, bool stopped = true) {
   const int m = t.m, tid = threadIdx.x;
   const zd* __restrict__ Rt = t.Rt;
   if (ib == 0) {
-    if (tid == 0) *t.rank = s;
+    if (tid == 0) *t.rank = stopped ? s : -1 - s;
     for (int j = tid; j < m; j += NT) t.perm[j] = pv[j];
   }
   zd(*tile)[33] = reinterpret_cast<zd(*)[33]>(part);
@@ -732,16 +732,20 @@ __global__ void __launch_bounds__(NT) pchol_block_kernel(const PcholTask* __rest
 }
 
 // after the last block: rank, perm and R in pivoted order
-// one workgroup per (box, 32-row block of R): blocks at or past the rank have nothing to write
+// one workgroup per (box, 32-row block of R): blocks at or past the rank have nothing to write.
+// A box whose pivoting has not stopped yet (the blocks launched so far did not reach its
+// rank) gets rank -1 - (pivots so far); the caller launches the remaining blocks and this
+// kernel again.
 __global__ void __launch_bounds__(kPcholThreads) pchol_finish_kernel(const PcholTask* __restrict__ tasks) {
   const PcholTask t = tasks[blockIdx.x];
   const int s = t.ist[2 * t.m];
+  const bool stopped = t.ist[2 * t.m + 1] != 0;
   if (blockIdx.y > 0 && 32 * (int)blockIdx.y >= s) return;
   __shared__ zd part[32 * 33];
   extern __shared__ int pvs[];
   for (int j = threadIdx.x; j < t.m; j += kPcholThreads) pvs[j] = t.ist[t.m + j];
   __syncthreads();
-  pchol_write_out<kPcholThreads>(t, s, pvs, part, (int)blockIdx.y, (int)gridDim.y);
+  pchol_write_out<kPcholThreads>(t, s, pvs, part, (int)blockIdx.y, (int)gridDim.y, stopped);
 }
 
 // T = R11^{-1} R12 (s x (m - s), ld m) from R in pivoted order. Each workgroup holds NC
@@ -753,7 +757,7 @@ __global__ void __launch_bounds__(256) pchol_t_kernel(const PcholTask* __restric
   const PcholTask t = tasks[blockIdx.x];
   const int m = t.m, s = *t.rank;
   const int c0 = blockIdx.y * NC;
-  if (s == 0 || c0 >= m - s) return;
+  if (s <= 0 || c0 >= m - s) return;  // s < 0: pivoting not finished (see pchol_finish_kernel)
   const int nc = min(NC, m - s - c0);
   extern __shared__ __align__(16) unsigned char smem[];
   zd* W = reinterpret_cast<zd*>(smem);  // W[i * NC + j], i < s
