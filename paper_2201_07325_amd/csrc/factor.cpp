@@ -2526,14 +2526,13 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     ht.mark(6);
     // ---- next level's owners: merge live DOFs of level-lev owners into parents
     std::vector<Owner> next;
-    std::unordered_map<int, int> next_by_box;
+    std::vector<int32_t> next_by_box(tree.nboxes(), -1);  // box -> index in next
     for (int i = 0; i < nown; ++i) {
       Owner& o = own[i];
       if (o.live.empty()) continue;
       int target_box = o.level == lev ? tree.parent[o.box] : o.box;
-      auto it = next_by_box.find(target_box);
-      int ni;
-      if (it == next_by_box.end()) {
+      int ni = next_by_box[target_box];
+      if (ni < 0) {
         ni = (int)next.size();
         next_by_box[target_box] = ni;
         Owner no;
@@ -2544,8 +2543,6 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         no.c[2] = tree.cz[target_box];
         no.first_pos = o.act[o.live[0]];
         next.push_back(std::move(no));
-      } else {
-        ni = it->second;
       }
       Owner& no = next[ni];
       no.sub.push_back(i);
