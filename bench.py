@@ -291,8 +291,8 @@ def batched_leg(solves=20):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=50_000)
     ap.add_argument("--solves", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")

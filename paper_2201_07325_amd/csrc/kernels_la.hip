@@ -916,8 +916,9 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
         }
         __syncthreads();
         if (tid == 0) {
-          __threadfence();
-          __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          // release (a write-back, no invalidate): the slot writes above precede the count
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __hip_atomic_fetch_add(t.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const int target = t.wpt * (gc + 1);
           int64_t spins = 0;
           // relaxed polling (an acquire load would invalidate the caches at every poll); the
@@ -929,7 +930,7 @@ __global__ void __launch_bounds__(256) gj_panel_kernel(const GjTask* __restrict_
             }
             __builtin_amdgcn_s_sleep(1);
           }
-          __threadfence();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // an invalidate, no write-back
           double b = -1.0;
           int p = 0x7fffffff, pw = 0;
           for (int u = 0; u < t.wpt; ++u) {
@@ -1033,16 +1034,19 @@ __device__ inline void gj_wait_at_least(int32_t* w, int target, int32_t* info) {
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __threadfence();
+    // acquire: the signaller's writes before its release are visible to this workgroup's
+    // reads after the barrier below (an invalidate, no write-back)
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
 
 // after a workgroup barrier: thread 0 publishes the workgroup's prior memory operations
+// (callers pass a workgroup barrier first, so that every thread's writes precede the release)
 __device__ inline void gj_signal(int32_t* w) {
   if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_fetch_add(w, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // a write-back, no invalidate
+    __hip_atomic_fetch_add(w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
