@@ -2653,6 +2653,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         SolvePhase& ph = newph[i++];
         ph = pp.ph;
         ph.nd = (int64_t)pp.dst.size();
+        ph.direct = pp.src.size() == pp.dst.size();
         pk.add(&ph.dboxes, pp.db);
         pk.add(&ph.sc_dst, pp.dst);
         pk.add(&ph.sc_ptr, pp.ptr);
@@ -2681,8 +2682,10 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       sg.commit(arena, pk);
       if (opts.verbose) {
         int nf[4] = {0, 0, 0, 0}, maxc[4] = {0, 0, 0, 0}, npre = 0;
+        int ndirect = 0;
         for (auto& ph : newph) {
           npre += ph.blk_presum;
+          ndirect += ph.direct;
           nf[0] += ph.g1xr == 16; nf[1] += ph.g1y == 16; nf[2] += ph.g1bp == 16; nf[3] += ph.g1bt == 16;
           maxc[0] = std::max(maxc[0], ph.nxr); maxc[1] = std::max(maxc[1], ph.ny);
           maxc[2] = std::max(maxc[2], ph.nbp); maxc[3] = std::max(maxc[3], ph.nbt);
@@ -2690,6 +2693,7 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         fprintf(stderr, "[fmmlu] sweeps: phases with 16-wide items (of %zu) xr %d y %d bpart %d bt %d; "
                 "most 64-wide items in a phase %d %d %d %d; blocked sweeps summing x_R per phase: %d\n", newph.size(),
                 nf[0], nf[1], nf[2], nf[3], maxc[0], maxc[1], maxc[2], maxc[3], npre);
+        fprintf(stderr, "[fmmlu] sweeps: phases without a shared row of S u N (no scatter launch): %d\n", ndirect);
       }
       for (auto& ph : newph) phases.push_back(ph);
     }
@@ -2781,12 +2785,12 @@ void FactorImpl::sweep(const SolveWs& w, int nr, const zd* bc, int64_t ldb, zd* 
   for (auto& ph : phases) {
     if (blk) {
       launch_blk_xr_part(ph.dboxes, ph.s1xr, ph.n1xr, ph.g1xr, w.x, w.xrp, adj, f32, st);
-      launch_blk_y(ph.dboxes, ph.s1y, ph.n1y, ph.g1y, w.x, w.xrp, w.xrg, w.y, adj, f32, st);
+      launch_blk_y(ph.dboxes, ph.s1y, ph.n1y, ph.g1y, w.x, w.xrp, w.xrg, w.y, adj, ph.direct, f32, st);
     } else {
       launch_solve_xr_part(ph.dboxes, ph.s1xr, ph.n1xr, ph.g1xr, w.x, w.xrp, adj, f32, st, nr);
-      launch_solve_y(ph.dboxes, ph.s1y, ph.n1y, ph.g1y, w.x, w.xrp, w.xrg, w.y, adj, f32, st, nr);
+      launch_solve_y(ph.dboxes, ph.s1y, ph.n1y, ph.g1y, w.x, w.xrp, w.xrg, w.y, adj, ph.direct, f32, st, nr);
     }
-    launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, w.y, w.x, st, nr);
+    if (!ph.direct) launch_scatter_sub(ph.sc_dst, ph.sc_ptr, ph.sc_src, ph.nd, w.y, w.x, st, nr);
   }
   // D^{-1} (adjoint D^{-H}): all pivot blocks (x_R buffer to x_R buffer), then the top block
   if (blk) {

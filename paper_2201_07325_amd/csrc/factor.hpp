@@ -80,6 +80,7 @@ struct SolvePhase {
   int64_t* sc_ptr = nullptr;
   int64_t* sc_src = nullptr;
   int64_t nd = 0;
+  int direct = 0;  // every scatter destination has one contribution: y goes straight into x
   int64_t ylen = 0, plen = 0, xrplen = 0;
   // counts of the work items of 64 (forward x_R partials, rows of y; backward x_R partials,
   // rows of x_S), from which each sweep picks its granularity

@@ -377,8 +377,10 @@ void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt,
                           int adjoint, bool f32, hipStream_t st, int nr = 1);
 // forward, per (box, item of rows of S u N): x_R = x[R] - sum of the partials (kept in XRg by
 // the item of the first rows), then y = op(P) x_R (Lp, adjoint conj(Up^T)) for those rows
-void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
-                    zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st, int nr = 1);
+// (direct: no two boxes of the phase share a row of S u N; the rows are subtracted from x
+// here and the phase needs no scatter)
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, zd* x, const zd* Pxr,
+                    zd* XRg, zd* y, int adjoint, int direct, bool f32, hipStream_t st, int nr = 1);
 // x[dst[d]] -= sum of y[src[q]] over ptr[d] <= q < ptr[d+1] (deterministic scatter)
 void launch_scatter_sub(const int32_t* dst, const int64_t* ptr, const int64_t* src, int64_t nd,
                         const zd* y, zd* x, hipStream_t st, int nr = 1);
@@ -400,8 +402,8 @@ void launch_solve_bt(const SolveBox* boxes, const SweepTask* tasks, int nt, int 
 // launch_solve_top_fin).
 void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pxr,
                         int adjoint, bool f32, hipStream_t st);
-void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
-                  zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st);
+void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, zd* x, const zd* Pxr,
+                  zd* XRg, zd* y, int adjoint, int direct, bool f32, hipStream_t st);
 void launch_blk_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, zd* XRd, int adjoint,
                      bool f32, hipStream_t st);
 void launch_blk_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pb,

@@ -254,9 +254,9 @@ __global__ void __launch_bounds__(256) blk_xr_part_kernel(const SolveBox* __rest
 // item of the first rows), y = op(P) x_R (Lp, adjoint conj(Up^T)) for the item's rows
 template <class FT, int RPI>
 __global__ void __launch_bounds__(256) blk_y_kernel(const SolveBox* __restrict__ boxes,
-                                                    const SweepTask* __restrict__ tasks, const zd* __restrict__ x,
+                                                    const SweepTask* __restrict__ tasks, zd* __restrict__ x,
                                                     const zd* __restrict__ Pxr, zd* __restrict__ XRg,
-                                                    zd* __restrict__ y, int adjoint) {
+                                                    zd* __restrict__ y, int adjoint, int direct) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd sv[KC][NB];
@@ -270,7 +270,14 @@ __global__ void __launch_bounds__(256) blk_y_kernel(const SolveBox* __restrict__
       if (keep) XRg[(b.dx_off + kb + k) * NB + c] = v;
     }
   };
-  auto emit = [&](int i, int c, zd v) { y[(b.y_off + i) * NB + c] = v; };
+  auto emit = [&](int i, int c, zd v) {
+    if (direct) {  // as in the single-vector sweep: the row goes straight into x[SN]
+      const int64_t xi = (int64_t)b.SN[i] * NB + c;
+      x[xi] = zsub(x[xi], v);
+    } else {
+      y[(b.y_off + i) * NB + c] = v;
+    }
+  };
   const FT* P = static_cast<const FT*>(adjoint ? b.UpT : b.Lp);
   if constexpr (RPI == 16)
     rows_block16<FT>(P, b.nsn, t.k0, t.kn, b.r, adjoint != 0, sv, stage, emit);
@@ -420,10 +427,10 @@ void launch_blk_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt, i
   FMMLU_FT_G_LAUNCH(blk_xr_part_kernel, nt, gsz, boxes, tasks, x, Pxr, adjoint);
 }
 
-void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
-                  zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st) {
+void launch_blk_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, zd* x, const zd* Pxr,
+                  zd* XRg, zd* y, int adjoint, int direct, bool f32, hipStream_t st) {
   if (nt <= 0) return;
-  FMMLU_FT_G_LAUNCH(blk_y_kernel, nt, rows, boxes, tasks, x, Pxr, XRg, y, adjoint);
+  FMMLU_FT_G_LAUNCH(blk_y_kernel, nt, rows, boxes, tasks, x, Pxr, XRg, y, adjoint, direct);
 }
 
 void launch_blk_diag(const SolveBox* boxes, const SweepTask* tasks, int nt, const zd* XRg, zd* XRd, int adjoint,

@@ -214,12 +214,14 @@ __device__ inline zd rows16_sum(zd (*xr)[NR], int rho, int c) {
 // Forward, per (box, 64 rows of S u N): x_R = x[R] - sum of the x_R partials, staged chunk by
 // chunk (the item of rows 0..63 also keeps it in XRg); y = op(P) x_R for the item's rows,
 // P = Lp (adjoint conj(Up^T)). A box with no S u N rows has one item without rows. RPI = 16:
-// the same in items of 16 rows (phases with few boxes).
+// the same in items of 16 rows (phases with few boxes). direct: no two boxes of the phase
+// share a row of S u N, so each row is subtracted from x[SN] here (x - y, as the scatter
+// would) instead of going to y; the rows written are never the rows of R that items read.
 template <class FT, int NR, int RPI>
 __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict__ boxes,
-                                                      const SweepTask* __restrict__ tasks,
-                                                      const zd* __restrict__ x, const zd* __restrict__ Pxr,
-                                                      zd* __restrict__ XRg, zd* __restrict__ y, int adjoint) {
+                                                      const SweepTask* __restrict__ tasks, zd* __restrict__ x,
+                                                      const zd* __restrict__ Pxr, zd* __restrict__ XRg,
+                                                      zd* __restrict__ y, int adjoint, int direct) {
   const SweepTask t = tasks[blockIdx.x];
   const SolveBox b = boxes[t.box];
   __shared__ zd xr[kSolveK][NR];
@@ -244,16 +246,30 @@ __global__ void __launch_bounds__(256) solve_y_kernel(const SolveBox* __restrict
     rows_reduce<NR>(xr, acc);
     if (threadIdx.x < 64 && lane < t.kn) {
 #pragma unroll
-      for (int c = 0; c < NR; ++c)
-        y[(b.y_off + i) * NR + c] =
-            zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c]));
+      for (int c = 0; c < NR; ++c) {
+        const zd v = zadd(zadd(xr[lane][c], xr[64 + lane][c]), zadd(xr[128 + lane][c], xr[192 + lane][c]));
+        if (direct) {
+          const int64_t xi = (int64_t)b.SN[i] * NR + c;
+          x[xi] = zsub(x[xi], v);
+        } else {
+          y[(b.y_off + i) * NR + c] = v;
+        }
+      }
     }
   } else {
     rows16_times_xr<FT, NR>(P, b.nsn, b.r, i, rho < t.kn, adjoint != 0, xr, acc, stage);
     rows_reduce<NR>(xr, acc);
     if (threadIdx.x < 16 && rho < t.kn) {
 #pragma unroll
-      for (int c = 0; c < NR; ++c) y[(b.y_off + i) * NR + c] = rows16_sum<NR>(xr, rho, c);
+      for (int c = 0; c < NR; ++c) {
+        const zd v = rows16_sum<NR>(xr, rho, c);
+        if (direct) {
+          const int64_t xi = (int64_t)b.SN[i] * NR + c;
+          x[xi] = zsub(x[xi], v);
+        } else {
+          y[(b.y_off + i) * NR + c] = v;
+        }
+      }
     }
   }
 }
@@ -545,10 +561,10 @@ void launch_solve_xr_part(const SolveBox* boxes, const SweepTask* tasks, int nt,
   FMMLU_FT_NR_LAUNCH(solve_xr_part_kernel, nt, 0, boxes, tasks, x, Pxr, adjoint, gsz);
 }
 
-void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, const zd* x, const zd* Pxr,
-                    zd* XRg, zd* y, int adjoint, bool f32, hipStream_t st, int nr) {
+void launch_solve_y(const SolveBox* boxes, const SweepTask* tasks, int nt, int rows, zd* x, const zd* Pxr,
+                    zd* XRg, zd* y, int adjoint, int direct, bool f32, hipStream_t st, int nr) {
   if (nt <= 0) return;
-  FMMLU_FT_RPI_LAUNCH(solve_y_kernel, nt, boxes, tasks, x, Pxr, XRg, y, adjoint);
+  FMMLU_FT_RPI_LAUNCH(solve_y_kernel, nt, boxes, tasks, x, Pxr, XRg, y, adjoint, direct);
 }
 
 void launch_solve_bpart(const SolveBox* boxes, const SweepTask* tasks, int nt, int gsz, const zd* x, zd* Pbuf,
