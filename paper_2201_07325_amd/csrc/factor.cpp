@@ -2025,6 +2025,33 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
       //      pairwise), grouped by destination tile with boxes in order within a tile; after the
       //      read-back it is restricted to the boxes that eliminate something
       const SchurGroups sg_pre = schur_groups(nb);
+      // ---- and the rank-independent parts of the elimination plan: per box its tile (B, B),
+      //      the segments of its near owners and the N part of its S u N list (the near
+      //      owners are of other colours: their live lists do not change in this phase)
+      std::vector<int64_t> pre_tile_bb(nb);
+      std::vector<std::vector<NSeg>> pre_nseg(nb);
+      std::vector<std::vector<int32_t>> pre_nlist(nb);
+      hp.ranges(nb, 8, [&](int lo, int hi) {
+        for (int i = lo; i < hi; ++i) {
+          const BoxPlan& bp = plan[i];
+          pre_tile_bb[i] = pidx.find(bp.oi, bp.oi);
+          auto& sgs = pre_nseg[i];
+          auto& nl = pre_nlist[i];
+          nl.reserve((size_t)bp.nN);
+          int off = 0;
+          for (int o : bp.nown_) {
+            NSeg sgm{};
+            sgm.tile_nb = pidx.find(o, bp.oi);
+            sgm.tile_bn = pidx.find(bp.oi, o);
+            sgm.live = own[o].live_dev;
+            sgm.ld = (int)own[o].act.size();
+            sgm.off = off;
+            off += (int)own[o].live.size();
+            sgs.push_back(sgm);
+            for (int32_t l : own[o].live) nl.push_back((int32_t)own[o].act[l]);
+          }
+        }
+      });
       // ---- read back ranks and pivots
       std::vector<int32_t> ranks(nb);
       std::vector<std::vector<int32_t>> perms(nb);
@@ -2132,22 +2159,16 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
           CrossTask ct{};
           ct.Ccol = e.Ccol;
           ct.Crow = e.Crow;
-          ct.tile_bb = pidx.at(bp.oi, bp.oi);
+          ct.tile_bb = pre_tile_bb[e.pi];
           ct.perm = bp.perm;
           ct.m = bp.m;
           ct.nN = bp.nN;
           ct.s = e.s;
           ct.seg_off = (int64_t)nsegs.size();
-          int off = 0;
-          for (int o : bp.nown_) {
-            NSeg s{};
-            s.tile_nb = pidx.at(o, bp.oi);
-            s.tile_bn = pidx.at(bp.oi, o);
-            s.live = own[o].live_dev;
-            s.ld = (int)own[o].act.size();
-            s.off = off;
-            off += (int)own[o].live.size();
-            nsegs.push_back(s);
+          for (const NSeg& sgm : pre_nseg[e.pi]) {
+            if (sgm.tile_nb < 0 || sgm.tile_bn < 0 || ct.tile_bb < 0)
+              throw Error(FMMLU_EINVAL, "internal: tile of a pair that is not close");
+            nsegs.push_back(sgm);
           }
           ct.nseg = (int)bp.nown_.size();
           ct.unit_begin = cunits;
@@ -2168,12 +2189,12 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
             int32_t* sn = idx_cat.data() + idx_off[q][2];
             for (int j = 0; j < e.r; ++j) rl[j] = (int32_t)B.act[pv[e.s + j]];
             for (int j = 0; j < e.s; ++j) sl[j] = sn[j] = (int32_t)B.act[pv[j]];
-            int64_t c = e.s;
-            for (int o : bp.nown_)
-              for (int32_t l : own[o].live)
-                if (c < e.nsn) sn[c++] = (int32_t)own[o].act[l];
-                else short_sn[q] = 1;
-            if (c != e.nsn) short_sn[q] = 1;
+            const std::vector<int32_t>& nl = pre_nlist[e.pi];
+            if ((int64_t)e.s + (int64_t)nl.size() != e.nsn) {
+              short_sn[q] = 1;
+            } else if (!nl.empty()) {
+              std::memcpy(sn + e.s, nl.data(), sizeof(int32_t) * nl.size());
+            }
             FactorBox& fb = boxes[box_base + q];
             fb.skel_orig.resize(e.s);
             for (int j = 0; j < e.s; ++j) fb.skel_orig[j] = order[B.act[pv[j]]];
