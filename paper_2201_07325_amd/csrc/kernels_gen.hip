@@ -21,10 +21,23 @@ namespace {
 
 constexpr double kInv4Pi = 0.07957747154594767;  // 1 / (4 pi)
 
+// 1/sqrt(x) for x > 0 (every squared distance between distinct points): the hardware
+// estimate y0, then one second-order correction from the binomial series
+// 1/sqrt(1 - e) = 1 + e/2 + 3e^2/8 + ... with e = 1 - x y0^2, whose truncation (about
+// 5e^3/16) is far below a rounding error for the estimate's relative error.
+__device__ inline double rsqrt_pos(double x) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  const double e = fma(-x * y0, y0, 1.0);
+  return fma(y0 * e, fma(e, 0.375, 0.5), y0);
+}
+
 // sin x and cos x for the kernel phase x = k r (|x| < 2^20; the library's routine beyond):
 // Cody-Waite reduction by pi/2 with fused multiply-adds (x - q hi exact to one rounding, then
 // the tail lo of pi/2) to |y| <= pi/4, then the Taylor series of sin to y^15 and of cos to
 // y^16 (truncation below 7e-17 relative on that interval), and the quadrant q mod 4.
+// Both series are sums over powers of z = y^2 formed once and shared: each term is one
+// multiply-add of a coefficient and a ready power, smallest term first, so no step waits
+// on a chain of products and no coefficient has to be copied into an accumulator.
 __device__ inline void sincos_phase(double x, double* sn, double* cs) {
   if (!(fabs(x) < 1048576.0)) {
     sincos(x, sn, cs);
@@ -37,25 +50,27 @@ __device__ inline void sincos_phase(double x, double* sn, double* cs) {
   double y = fma(-q, kPio2Hi, x);
   y = fma(-q, kPio2Lo, y);
   const double z = y * y;
-  // 1/n! for n = 3, 5, ..., 15 and n = 2, 4, ..., 16
-  double ps = -7.6471637318198164759e-13;            // -1/15!
-  ps = fma(ps, z, 1.6059043836821614599e-10);        //  1/13!
-  ps = fma(ps, z, -2.5052108385441718775e-08);       // -1/11!
-  ps = fma(ps, z, 2.7557319223985890653e-06);        //  1/9!
-  ps = fma(ps, z, -1.9841269841269841270e-04);       // -1/7!
-  ps = fma(ps, z, 8.3333333333333333333e-03);        //  1/5!
-  ps = fma(ps, z, -1.6666666666666666667e-01);       // -1/3!
+  const double z2 = z * z, z3 = z2 * z, z4 = z2 * z2, z5 = z4 * z, z6 = z4 * z2, z7 = z4 * z3;
+  // sin y = y + y z (-1/3! + z/5! - ... - z^6/15!)
+  double ps = -7.6471637318198164759e-13 * z6;       // -1/15!
+  ps = fma(1.6059043836821614599e-10, z5, ps);       //  1/13!
+  ps = fma(-2.5052108385441718775e-08, z4, ps);      // -1/11!
+  ps = fma(2.7557319223985890653e-06, z3, ps);       //  1/9!
+  ps = fma(-1.9841269841269841270e-04, z2, ps);      // -1/7!
+  ps = fma(8.3333333333333333333e-03, z, ps);        //  1/5!
+  ps = ps - 1.6666666666666666667e-01;               // -1/3!
   const double sy = fma(ps * z, y, y);
-  double pc = 4.7794773323873852974e-14;             //  1/16!
-  pc = fma(pc, z, -1.1470745597729724714e-11);       // -1/14!
-  pc = fma(pc, z, 2.0876756987868098979e-09);        //  1/12!
-  pc = fma(pc, z, -2.7557319223985890653e-07);       // -1/10!
-  pc = fma(pc, z, 2.4801587301587301587e-05);        //  1/8!
-  pc = fma(pc, z, -1.3888888888888888889e-03);       // -1/6!
-  pc = fma(pc, z, 4.1666666666666666667e-02);        //  1/4!
-  pc = fma(pc, z, -0.5);                             // -1/2!
+  // cos y = 1 + z (-1/2! + z/4! - ... + z^7/16!)
+  double pc = 4.7794773323873852974e-14 * z7;        //  1/16!
+  pc = fma(-1.1470745597729724714e-11, z6, pc);      // -1/14!
+  pc = fma(2.0876756987868098979e-09, z5, pc);       //  1/12!
+  pc = fma(-2.7557319223985890653e-07, z4, pc);      // -1/10!
+  pc = fma(2.4801587301587301587e-05, z3, pc);       //  1/8!
+  pc = fma(-1.3888888888888888889e-03, z2, pc);      // -1/6!
+  pc = fma(4.1666666666666666667e-02, z, pc);        //  1/4!
+  pc = pc - 0.5;                                     // -1/2!
   const double cy = fma(pc, z, 1.0);
-  const int quad = (int)((int64_t)q & 3);
+  const int quad = (int)q & 3;  // |q| < 2^20: exact in an int
   const double s0 = (quad & 1) ? cy : sy, c0 = (quad & 1) ? sy : cy;
   *sn = (quad & 2) ? -s0 : s0;
   *cs = ((quad + 1) & 2) ? -c0 : c0;
@@ -67,7 +82,7 @@ __device__ inline zd cfie_entry(const double* __restrict__ p, int64_t n, double 
   if (i == j) return zd{0.5, 0.0};
   double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
   double r2 = dx * dx + dy * dy + dz * dz;
-  double ir = rsqrt(r2);
+  double ir = rsqrt_pos(r2);
   double r = r2 * ir;
   double dn = dx * p[3 * n + j] + dy * p[4 * n + j] + dz * p[5 * n + j];
   double s, c;
@@ -83,7 +98,7 @@ __device__ inline zd cfie_entry_dk(const double* __restrict__ p, int64_t n, doub
   if (i == j) return zd{0.0, 0.0};
   double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
   double r2 = dx * dx + dy * dy + dz * dz;
-  double ir = rsqrt(r2);
+  double ir = rsqrt_pos(r2);
   double r = r2 * ir;
   double dn = dx * p[3 * n + j] + dy * p[4 * n + j] + dz * p[5 * n + j];
   double s, c;
@@ -100,7 +115,7 @@ __device__ inline zd cfie_entry_deta(const double* __restrict__ p, int64_t n, do
   if (i == j) return zd{0.0, 0.0};
   double dx = p[i] - p[j], dy = p[n + i] - p[n + j], dz = p[2 * n + i] - p[2 * n + j];
   double r2 = dx * dx + dy * dy + dz * dz;
-  double ir = rsqrt(r2);
+  double ir = rsqrt_pos(r2);
   double s, c;
   sincos_phase(k * (r2 * ir), &s, &c);
   double f = p[6 * n + i] * p[6 * n + j] * kInv4Pi * ir;
@@ -273,7 +288,7 @@ __global__ void __launch_bounds__(256) idmatrix_kernel(DevGeom g, const IdTask* 
     const int64_t q = dof[t.dof_off + j];
     const double dx = yx - p[q], dy = yy - p[n + q], dz = yz - p[2 * n + q];
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double ir = rsqrt(r2);
+    const double ir = rsqrt_pos(r2);
     const double r = r2 * ir;
     double s, c;
     sincos_phase(g.k * r, &s, &c);
@@ -340,7 +355,7 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __rest
       }
       const double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
       const double r2 = dx * dx + dy * dy + dz * dz;
-      const double ir = rsqrt(r2);
+      const double ir = rsqrt_pos(r2);
       const double r = r2 * ir;
       double s, c;
       sincos_phase(g.k * r, &s, &c);
