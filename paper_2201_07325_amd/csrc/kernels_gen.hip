@@ -320,9 +320,59 @@ __global__ void __launch_bounds__(256) block_kernel(DevGeom g, const int64_t* __
 }
 
 // ---------------------------------------------------------------------------------------
+// One source j of the exact matvec for the thread's target i, added to (are, aim) without the
+// target's weight sqrt(w_i), which the caller applies once to the sum. sp holds the sources'
+// coordinates, normals and sqrt(w_j) / (4 pi); the entry is (A + iB) f, and x_j f is formed
+// first so that the complex product accumulates in four multiply-adds.
+template <int OP>
+__device__ inline void matvec_pair(const DevGeom& g, const double (&xi)[6], const double (*sp)[256],
+                                   const zd* sx, int jj, double& are, double& aim) {
+  const double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir = rsqrt_pos(r2);
+  const double r = r2 * ir;
+  const double kr = g.k * r;
+  double s, c;
+  sincos_phase(kr, &s, &c);
+  double A, B, f;
+  if (OP == 0) {
+    const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
+    const double b = kr * dn + g.eta * r2;
+    f = sp[6][jj] * (ir * ir * ir);
+    A = c * dn + s * b;
+    B = s * dn - c * b;
+  } else if (OP == 1) {
+    // conj(A~[j, i]): target j, source i with normal n_i; d = x_j - x_i = -(dx, dy, dz)
+    const double dn = -(dx * xi[3] + dy * xi[4] + dz * xi[5]);
+    const double b = kr * dn + g.eta * r2;
+    f = sp[6][jj] * (ir * ir * ir);
+    A = c * dn + s * b;
+    B = c * b - s * dn;
+  } else if (OP == 2) {
+    const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
+    const double a = g.k * dn + g.eta * r;
+    f = sp[6][jj] * ir;
+    A = c * a;
+    B = s * a;
+  } else {
+    f = sp[6][jj] * ir;
+    A = s;
+    B = -c;
+  }
+  const zd xv = sx[jj];
+  const double xr = xv.re * f, xm = xv.im * f;
+  are = fma(A, xr, are);
+  are = fma(-B, xm, are);
+  aim = fma(A, xm, aim);
+  aim = fma(B, xr, aim);
+}
+
 // Exact matvec: each workgroup owns 256 target rows and streams one slice of the sources
 // through LDS; slices (grid.y) write partial sums that a second pass adds in a fixed order.
 // op 0: y = A~ x; 1: y = A~^H x; 2: y = dA~/dk x; 3: y = dA~/deta x. Vectors in tree order.
+// Source tiles start at multiples of 256 (the slice length is one), so the diagonal entry of
+// every target of the workgroup lies in the one tile that starts at the workgroup's first
+// target, at position threadIdx.x; only that tile's loop tests for it.
 template <int OP>
 __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __restrict__ x, zd* __restrict__ part,
                                                      int64_t slice) {
@@ -330,67 +380,39 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __rest
   __shared__ zd sx[256];
   const int64_t n = g.n;
   const double* p = g.p;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t ib = (int64_t)blockIdx.x * 256, i = ib + threadIdx.x;
   const bool live = i < n;
-  double xi[7];
-  for (int a = 0; a < 7; ++a) xi[a] = live ? p[a * n + i] : 0.0;
-  double are = 0.0, aim = 0.0;
+  double xi[6];
+  for (int a = 0; a < 6; ++a) xi[a] = live ? p[a * n + i] : 0.0;
+  const double wi = live ? p[6 * n + i] : 0.0;
+  double are = 0.0, aim = 0.0, dre = 0.0, dim = 0.0;
   const int64_t jbeg = (int64_t)blockIdx.y * slice, jend = min(n, jbeg + slice);
   for (int64_t j0 = jbeg; j0 < jend; j0 += 256) {
     __syncthreads();
     const int64_t jl = j0 + threadIdx.x;
-    for (int a = 0; a < 7; ++a) sp[a][threadIdx.x] = jl < jend ? p[a * n + jl] : 0.0;
+    for (int a = 0; a < 6; ++a) sp[a][threadIdx.x] = jl < jend ? p[a * n + jl] : 0.0;
+    sp[6][threadIdx.x] = jl < jend ? p[6 * n + jl] * kInv4Pi : 0.0;
     sx[threadIdx.x] = jl < jend ? x[jl] : zd{0.0, 0.0};
     __syncthreads();
     const int cnt = (int)min<int64_t>(256, jend - j0);
     if (!live) continue;
-    for (int jj = 0; jj < cnt; ++jj) {
-      const int64_t j = j0 + jj;
-      if (j == i) {
-        if (OP <= 1) {
-          are += 0.5 * sx[jj].re;
-          aim += 0.5 * sx[jj].im;
+    if (j0 == ib) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        if (jj == (int)threadIdx.x) {
+          if (OP <= 1) {
+            dre = 0.5 * sx[jj].re;
+            dim = 0.5 * sx[jj].im;
+          }
+          continue;
         }
-        continue;
+        matvec_pair<OP>(g, xi, sp, sx, jj, are, aim);
       }
-      const double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      const double ir = rsqrt_pos(r2);
-      const double r = r2 * ir;
-      double s, c;
-      sincos_phase(g.k * r, &s, &c);
-      const double w = xi[6] * sp[6][jj] * kInv4Pi;
-      double vr, vi;
-      if (OP == 0) {
-        const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
-        const double a = dn, b = g.k * r * dn + g.eta * r2;
-        const double f = w * ir * ir * ir;
-        vr = (c * a + s * b) * f;
-        vi = (s * a - c * b) * f;
-      } else if (OP == 1) {
-        // conj(A~[j, i]): target j, source i with normal n_i; d = x_j - x_i = -(dx, dy, dz)
-        const double dn = -(dx * xi[3] + dy * xi[4] + dz * xi[5]);
-        const double a = dn, b = g.k * r * dn + g.eta * r2;
-        const double f = w * ir * ir * ir;
-        vr = (c * a + s * b) * f;
-        vi = -(s * a - c * b) * f;
-      } else if (OP == 2) {
-        const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
-        const double a = g.k * dn + g.eta * r;
-        const double f = w * ir;
-        vr = c * a * f;
-        vi = s * a * f;
-      } else {
-        const double f = w * ir;
-        vr = s * f;
-        vi = -c * f;
-      }
-      const zd xv = sx[jj];
-      are += vr * xv.re - vi * xv.im;
-      aim += vr * xv.im + vi * xv.re;
+    } else {
+#pragma unroll 2
+      for (int jj = 0; jj < cnt; ++jj) matvec_pair<OP>(g, xi, sp, sx, jj, are, aim);
     }
   }
-  if (live) part[(int64_t)blockIdx.y * n + i] = zd{are, aim};
+  if (live) part[(int64_t)blockIdx.y * n + i] = zd{fma(wi, are, dre), fma(wi, aim, dim)};
 }
 
 // The corrections' share of the exact product: the listed entries beyond their kernel value,
