@@ -1308,6 +1308,19 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     order_dev = sg.up_to(arena, order);
   }
   g = DevGeom{geom, n, k, eta};
+  if (n > 0) {
+    // k times the bounding box's diagonal bounds the phase k r of every pair of points
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      double lo = xyz[a * n], hi = lo;
+      for (int64_t p = 1; p < n; ++p) {
+        lo = std::min(lo, xyz[a * n + p]);
+        hi = std::max(hi, xyz[a * n + p]);
+      }
+      d2 += (hi - lo) * (hi - lo);
+    }
+    g.kr_max = k * std::sqrt(d2) * (1.0 + 1e-12);
+  }
   // ---- quadrature corrections (Section 5.3): tree-order CSR by row and by column on the
   // device; on the host, every position's partners (either direction) for the spill-over rule
   std::vector<int64_t> adj_ptr;

@@ -32,6 +32,7 @@ struct DevGeom {
   int64_t n;
   double k, eta;
   DevCorr corr;
+  double kr_max = __builtin_inf();  // upper bound of k |x_i - x_j| over the points (inf: unknown)
 };
 
 // ---- tile assembly: out block = copy from old tiles where stored, else kernel entries ----

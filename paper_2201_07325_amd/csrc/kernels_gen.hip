@@ -38,11 +38,9 @@ __device__ inline double rsqrt_pos(double x) {
 // Both series are sums over powers of z = y^2 formed once and shared: each term is one
 // multiply-add of a coefficient and a ready power, smallest term first, so no step waits
 // on a chain of products and no coefficient has to be copied into an accumulator.
-__device__ inline void sincos_phase(double x, double* sn, double* cs) {
-  if (!(fabs(x) < 1048576.0)) {
-    sincos(x, sn, cs);
-    return;
-  }
+constexpr double kPhaseFast = 1048576.0;  // |x| below which the reduction below is used
+
+__device__ inline void sincos_phase_reduced(double x, double* sn, double* cs) {
   constexpr double kTwoOverPi = 0.63661977236758134308;
   constexpr double kPio2Hi = 1.5707963267948965580;   // nearest double to pi/2
   constexpr double kPio2Lo = 6.123233995736766036e-17;  // pi/2 - kPio2Hi
@@ -74,6 +72,14 @@ __device__ inline void sincos_phase(double x, double* sn, double* cs) {
   const double s0 = (quad & 1) ? cy : sy, c0 = (quad & 1) ? sy : cy;
   *sn = (quad & 2) ? -s0 : s0;
   *cs = ((quad + 1) & 2) ? -c0 : c0;
+}
+
+__device__ inline void sincos_phase(double x, double* sn, double* cs) {
+  if (!(fabs(x) < kPhaseFast)) {
+    sincos(x, sn, cs);
+    return;
+  }
+  sincos_phase_reduced(x, sn, cs);
 }
 
 // A~[i, j] for tree positions i, j
@@ -324,7 +330,7 @@ __global__ void __launch_bounds__(256) block_kernel(DevGeom g, const int64_t* __
 // target's weight sqrt(w_i), which the caller applies once to the sum. sp holds the sources'
 // coordinates, normals and sqrt(w_j) / (4 pi); the entry is (A + iB) f, and x_j f is formed
 // first so that the complex product accumulates in four multiply-adds.
-template <int OP>
+template <int OP, bool FAST>
 __device__ inline void matvec_pair(const DevGeom& g, const double (&xi)[6], const double (*sp)[256],
                                    const zd* sx, int jj, double& are, double& aim) {
   const double dx = xi[0] - sp[0][jj], dy = xi[1] - sp[1][jj], dz = xi[2] - sp[2][jj];
@@ -333,7 +339,10 @@ __device__ inline void matvec_pair(const DevGeom& g, const double (&xi)[6], cons
   const double r = r2 * ir;
   const double kr = g.k * r;
   double s, c;
-  sincos_phase(kr, &s, &c);
+  if (FAST)
+    sincos_phase_reduced(kr, &s, &c);
+  else
+    sincos_phase(kr, &s, &c);
   double A, B, f;
   if (OP == 0) {
     const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
@@ -372,8 +381,9 @@ __device__ inline void matvec_pair(const DevGeom& g, const double (&xi)[6], cons
 // op 0: y = A~ x; 1: y = A~^H x; 2: y = dA~/dk x; 3: y = dA~/deta x. Vectors in tree order.
 // Source tiles start at multiples of 256 (the slice length is one), so the diagonal entry of
 // every target of the workgroup lies in the one tile that starts at the workgroup's first
-// target, at position threadIdx.x; only that tile's loop tests for it.
-template <int OP>
+// target, at position threadIdx.x; only that tile's loop tests for it. FAST: every phase
+// k r of the launch is known to lie below kPhaseFast (no per-entry range test).
+template <int OP, bool FAST>
 __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __restrict__ x, zd* __restrict__ part,
                                                      int64_t slice) {
   __shared__ double sp[7][256];
@@ -405,11 +415,11 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __rest
           }
           continue;
         }
-        matvec_pair<OP>(g, xi, sp, sx, jj, are, aim);
+        matvec_pair<OP, FAST>(g, xi, sp, sx, jj, are, aim);
       }
     } else {
 #pragma unroll 2
-      for (int jj = 0; jj < cnt; ++jj) matvec_pair<OP>(g, xi, sp, sx, jj, are, aim);
+      for (int jj = 0; jj < cnt; ++jj) matvec_pair<OP, FAST>(g, xi, sp, sx, jj, are, aim);
     }
   }
   if (live) part[(int64_t)blockIdx.y * n + i] = zd{fma(wi, are, dre), fma(wi, aim, dim)};
@@ -504,14 +514,23 @@ void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipSt
   const int ns = matvec_slices(g.n);
   const int64_t slice = ((g.n + ns - 1) / ns + 255) / 256 * 256;
   const dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)ns), b(256);
+  const bool fast = g.kr_max < kPhaseFast;
+#define FMMLU_MATVEC_LAUNCH(OPV)                                                              \
+  do {                                                                                        \
+    if (fast)                                                                                 \
+      hipLaunchKernelGGL((matvec_kernel<OPV, true>), grid, b, 0, st, g, x, part, slice);     \
+    else                                                                                      \
+      hipLaunchKernelGGL((matvec_kernel<OPV, false>), grid, b, 0, st, g, x, part, slice);    \
+  } while (0)
   if (op == 0)
-    hipLaunchKernelGGL(matvec_kernel<0>, grid, b, 0, st, g, x, part, slice);
+    FMMLU_MATVEC_LAUNCH(0);
   else if (op == 1)
-    hipLaunchKernelGGL(matvec_kernel<1>, grid, b, 0, st, g, x, part, slice);
+    FMMLU_MATVEC_LAUNCH(1);
   else if (op == 2)
-    hipLaunchKernelGGL(matvec_kernel<2>, grid, b, 0, st, g, x, part, slice);
+    FMMLU_MATVEC_LAUNCH(2);
   else
-    hipLaunchKernelGGL(matvec_kernel<3>, grid, b, 0, st, g, x, part, slice);
+    FMMLU_MATVEC_LAUNCH(3);
+#undef FMMLU_MATVEC_LAUNCH
   FMMLU_HIP(hipGetLastError());
   hipLaunchKernelGGL(matvec_sum_kernel, dim3((unsigned)((g.n + 255) / 256)), b, 0, st, part, g.n, ns, y);
   FMMLU_HIP(hipGetLastError());
