@@ -210,10 +210,10 @@ fmmlu_status fmmlu_matvec(fmmlu_factor_h f, int32_t op, const void* x, void* y, 
  * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
  * Same operation, arguments and kernels as fmmlu_matvec, but its scratch (the permuted
  * input, the tree-order result and the source-slice partial sums: (2 + s) * n complex128
- * entries, s <= 16 slices) lives in a static device array of 64 MiB that the library holds
- * on each GPU it runs on until the process ends; nothing is allocated or freed. n up to
- * about 400,000 fits at any slice count (n = 1,000,000 uses one slice: 48 MB); a larger
- * need returns FMMLU_EINVAL. The current device must be the factor's device (EINVAL
+ * entries, 1 <= s <= 16 slices) lives in a static device array of 64 MiB (4,194,304
+ * entries) that the library holds on each GPU it runs on until the process ends; nothing
+ * is allocated or freed. The slice count is limited so that the scratch fits, which it does
+ * for n up to 1,398,101 (one slice); a larger n returns FMMLU_EINVAL. The current device must be the factor's device (EINVAL
  * otherwise). Asynchronous on hip_stream (no synchronisation). Every call on one GPU
  * shares that GPU's array: calls that overlap in time on one GPU (different streams or
  * host threads) race and must be serialised by the caller.

@@ -401,7 +401,7 @@ fmmlu_status fmmlu_matvec_noalloc(fmmlu_factor_h f, int32_t op, const void* x, v
     zd* yt = ws + F.n;
     zd* part = ws + 2 * F.n;
     launch_permute(static_cast<const zd*>(x), xt, F.order_dev, F.n, 1, st);
-    launch_matvec(F.g, op, xt, yt, part, st);
+    launch_matvec(F.g, op, xt, yt, part, matvec_noalloc_part_entries(F.n), st);
     launch_permute(yt, static_cast<zd*>(y), F.order_dev, F.n, 0, st);
   });
 }

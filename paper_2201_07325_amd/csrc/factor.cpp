@@ -2801,7 +2801,8 @@ void FactorImpl::ensure_workspace() {
   if (ws1.x) return;
   alloc_ws(ws1, 1);
   wmv = arena.alloc_n<zd>((size_t)n);
-  wpart = arena.alloc_n<zd>((size_t)matvec_slices(n) * (size_t)n);
+  wpart_entries = (int64_t)matvec_slices(n) * n;
+  wpart = arena.alloc_n<zd>((size_t)wpart_entries);
 }
 
 void FactorImpl::solve_core(const zd* bc, zd* xc, bool adjoint, hipStream_t st) {

@@ -136,6 +136,7 @@ struct FactorImpl {
   SolveWs ws1{};        // single right-hand sides
   zd* wmv = nullptr;
   zd* wpart = nullptr;  // matvec slice partials
+  int64_t wpart_entries = 0;
   // refinement workspace (allocated on the first refined solve)
   DeviceArena rarena{size_t(1) << 20};
   zd* rbuf = nullptr;

@@ -448,15 +448,21 @@ void launch_farfield(const DevGeom& g, int op, const double* dirs, int64_t ndir,
                      const zd* in, zd* out, zd* part, hipStream_t st);
 
 // ---- exact matvec on the fly ----
-// part: matvec_slices(n) * n scratch entries (partial sums of source slices)
+// part: part_entries scratch entries for the partial sums of the source slices, at least
+// matvec_slices(n, part_entries) * n. The slice count (at most kMatvecMaxSlices and
+// max_entries / n) is the one whose workgroups fill the current device's resident slots best,
+// fixed per device and n.
 constexpr int kMatvecMaxSlices = 16;
-int matvec_slices(int64_t n);
-void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipStream_t st);
+int matvec_slices(int64_t n, int64_t max_entries = INT64_MAX);
+void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, int64_t part_entries,
+                   hipStream_t st);
 
 // ---- allocation-free exact matvec ----
 // One file-scope device array per GPU (kNoallocScratchBytes) holds the permuted input, the
-// tree-order result and the slice partials: (2 + matvec_slices(n)) * n entries.
+// tree-order result and the slice partials: (2 + matvec_slices(n, matvec_noalloc_part_entries(n)))
+// * n entries.
 constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+int64_t matvec_noalloc_part_entries(int64_t n);  // room left for the partials after 2 n entries
 int64_t matvec_noalloc_entries(int64_t n);
 // device address of the current device's array (hipGetSymbolAddress on first use per device)
 zd* noalloc_scratch();

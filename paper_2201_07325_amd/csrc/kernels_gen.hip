@@ -10,7 +10,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <queue>
+#include <tuple>
+#include <vector>
 #include <string>
 
 #include "kernels.hpp"
@@ -504,16 +508,76 @@ void launch_block(const DevGeom& g, const int64_t* rows, int64_t nr, const int64
   FMMLU_HIP(hipGetLastError());
 }
 
-int matvec_slices(int64_t n) {
-  const int64_t nbt = (n + 255) / 256;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMatvecMaxSlices, 2048 / std::max<int64_t>(nbt, 1)));
+namespace {
+
+// Modelled duration of a matvec launch over nt tiles of 256 targets and nt of 256 sources in
+// ns source slices on a device of ncu compute units. The kernel is bound by instruction issue,
+// which a compute unit shares among its resident workgroups, so each unit is modelled as
+// working through the workgroups it is given one after another: workgroups go out in
+// dispatch order (target block fastest) to the unit that frees up first, each taking its
+// slice's tile count plus half a tile (loading its targets, writing its partial sums).
+double matvec_makespan(int64_t nt, int64_t ns, int64_t ncu) {
+  const int64_t L = (nt + ns - 1) / ns;
+  std::priority_queue<double, std::vector<double>, std::greater<double>> busy;  // finish times
+  double end = 0.0;
+  for (int64_t y = 0; y < ns; ++y) {
+    const double d = (double)std::max<int64_t>(0, std::min(L, nt - y * L)) + 0.5;
+    for (int64_t x = 0; x < nt; ++x) {
+      double start = 0.0;
+      if ((int64_t)busy.size() >= ncu) {
+        start = busy.top();
+        busy.pop();
+      }
+      busy.push(start + d);
+      end = std::max(end, start + d);
+    }
+  }
+  return end;
 }
 
-void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipStream_t st) {
+}  // namespace
+
+int matvec_slices(int64_t n, int64_t max_entries) {
+  if (n <= 0) return 1;
+  const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(kMatvecMaxSlices, max_entries / n));
+  int dev = 0;
+  FMMLU_HIP(hipGetDevice(&dev));
+  static std::mutex mu;
+  static std::map<std::tuple<int, int64_t, int64_t>, int> memo;
+  const auto key = std::make_tuple(dev, n, cap);
+  {
+    std::lock_guard<std::mutex> l(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
+  }
+  // at least seven workgroups per compute unit (enough resident waves to keep issue busy),
+  // then the fewest slices whose modelled duration is within 2% of the best
+  int ncu = 0;
+  FMMLU_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  ncu = std::max(ncu, 1);
+  const int64_t nt = (n + 255) / 256;
+  const int64_t smin = std::min(cap, std::max<int64_t>(1, (7 * (int64_t)ncu + nt - 1) / nt));
+  std::vector<double> t((size_t)cap + 1, 0.0);
+  double best = -1.0;
+  for (int64_t s = smin; s <= cap; ++s) {
+    t[(size_t)s] = matvec_makespan(nt, s, ncu);
+    best = best < 0.0 ? t[(size_t)s] : std::min(best, t[(size_t)s]);
+  }
+  int ns = (int)smin;
+  while (t[(size_t)ns] > best * 1.02) ++ns;
+  std::lock_guard<std::mutex> l(mu);
+  memo[key] = ns;
+  return ns;
+}
+
+void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, int64_t part_entries,
+                   hipStream_t st) {
   if (g.n <= 0) return;
-  const int ns = matvec_slices(g.n);
-  const int64_t slice = ((g.n + ns - 1) / ns + 255) / 256 * 256;
-  const dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)ns), b(256);
+  const int ns = matvec_slices(g.n, part_entries);
+  if ((int64_t)ns * g.n > part_entries) throw Error(FMMLU_EINVAL, "internal: matvec partials exceed their buffer");
+  const int64_t nt = (g.n + 255) / 256;
+  const int64_t slice = (nt + ns - 1) / ns * 256;
+  const dim3 grid((unsigned)nt, (unsigned)ns), b(256);
   const bool fast = g.kr_max < kPhaseFast;
 #define FMMLU_MATVEC_LAUNCH(OPV)                                                              \
   do {                                                                                        \
@@ -554,7 +618,11 @@ void launch_matvec(const DevGeom& g, int op, const zd* x, zd* y, zd* part, hipSt
 // comes from hipGetSymbolAddress, taken once per device with that device current.
 static __device__ __align__(256) zd scratch[kNoallocScratchBytes / sizeof(zd)];
 
-int64_t matvec_noalloc_entries(int64_t n) { return (2 + (int64_t)matvec_slices(n)) * n; }
+int64_t matvec_noalloc_part_entries(int64_t n) { return (int64_t)(kNoallocScratchBytes / sizeof(zd)) - 2 * n; }
+
+int64_t matvec_noalloc_entries(int64_t n) {
+  return (2 + (int64_t)matvec_slices(n, matvec_noalloc_part_entries(n))) * n;
+}
 
 zd* noalloc_scratch() {
   constexpr int kMaxDev = 64;

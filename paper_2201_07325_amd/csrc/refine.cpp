@@ -34,7 +34,7 @@ constexpr int kRestart = 30;  // GMRES restart length
 void FactorImpl::matvec(int op, const zd* x, zd* y, hipStream_t st) {
   ensure_workspace();
   launch_permute(x, wmv, order_dev, n, 1, st);
-  launch_matvec(g, op, wmv, ws1.x, wpart, st);
+  launch_matvec(g, op, wmv, ws1.x, wpart, wpart_entries, st);
   launch_permute(ws1.x, y, order_dev, n, 0, st);
 }
 
