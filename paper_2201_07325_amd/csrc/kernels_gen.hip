@@ -44,7 +44,9 @@ __device__ inline double rsqrt_pos(double x) {
 // on a chain of products and no coefficient has to be copied into an accumulator.
 constexpr double kPhaseFast = 1048576.0;  // |x| below which the reduction below is used
 
-__device__ inline void sincos_phase_reduced(double x, double* sn, double* cs) {
+// sin y and cos y of the reduced argument y = x - q pi/2, |y| <= pi/4, and q mod 4 (returned),
+// so that e^{ix} = i^q (cos y + i sin y).
+__device__ inline int sincos_phase_quadrant(double x, double* sy_out, double* cy_out) {
   constexpr double kTwoOverPi = 0.63661977236758134308;
   constexpr double kPio2Hi = 1.5707963267948965580;   // nearest double to pi/2
   constexpr double kPio2Lo = 6.123233995736766036e-17;  // pi/2 - kPio2Hi
@@ -72,10 +74,28 @@ __device__ inline void sincos_phase_reduced(double x, double* sn, double* cs) {
   pc = fma(4.1666666666666666667e-02, z, pc);        //  1/4!
   pc = pc - 0.5;                                     // -1/2!
   const double cy = fma(pc, z, 1.0);
-  const int quad = (int)q & 3;  // |q| < 2^20: exact in an int
+  *sy_out = sy;
+  *cy_out = cy;
+  return (int)q & 3;  // |q| < 2^20: exact in an int
+}
+
+__device__ inline void sincos_phase_reduced(double x, double* sn, double* cs) {
+  double sy, cy;
+  const int quad = sincos_phase_quadrant(x, &sy, &cy);
   const double s0 = (quad & 1) ? cy : sy, c0 = (quad & 1) ? sy : cy;
   *sn = (quad & 2) ? -s0 : s0;
   *cs = ((quad + 1) & 2) ? -c0 : c0;
+}
+
+// (u + i v) i^q for q in 0..3
+__device__ inline void rotate_quadrant(int q, double& u, double& v) {
+  const double u0 = u;
+  u = (q & 1) ? -v : u;
+  v = (q & 1) ? u0 : v;
+  if (q & 2) {
+    u = -u;
+    v = -v;
+  }
 }
 
 __device__ inline void sincos_phase(double x, double* sn, double* cs) {
@@ -332,8 +352,10 @@ __global__ void __launch_bounds__(256) block_kernel(DevGeom g, const int64_t* __
 // ---------------------------------------------------------------------------------------
 // One source j of the exact matvec for the thread's target i, added to (are, aim) without the
 // target's weight sqrt(w_i), which the caller applies once to the sum. sp holds the sources'
-// coordinates, normals and sqrt(w_j) / (4 pi); the entry is (A + iB) f, and x_j f is formed
-// first so that the complex product accumulates in four multiply-adds.
+// coordinates and normals, sx the sources' x_j sqrt(w_j) / (4 pi); the entry over those
+// weights is (A + iB) f. FAST (every phase below kPhaseFast): A + iB is formed from the
+// reduced sine and cosine and turned by the phase's quadrant once, instead of selecting and
+// negating sine and cosine.
 template <int OP, bool FAST>
 __device__ inline void matvec_pair(const DevGeom& g, const double (&xi)[6], const double (*sp)[256],
                                    const zd* sx, int jj, double& are, double& aim) {
@@ -343,35 +365,42 @@ __device__ inline void matvec_pair(const DevGeom& g, const double (&xi)[6], cons
   const double r = r2 * ir;
   const double kr = g.k * r;
   double s, c;
+  int quad = 0;
   if (FAST)
-    sincos_phase_reduced(kr, &s, &c);
+    quad = sincos_phase_quadrant(kr, &s, &c);
   else
     sincos_phase(kr, &s, &c);
   double A, B, f;
   if (OP == 0) {
+    // e^{ikr} (dn - i b)
     const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
     const double b = kr * dn + g.eta * r2;
-    f = sp[6][jj] * (ir * ir * ir);
+    f = ir * ir * ir;
     A = c * dn + s * b;
     B = s * dn - c * b;
   } else if (OP == 1) {
-    // conj(A~[j, i]): target j, source i with normal n_i; d = x_j - x_i = -(dx, dy, dz)
+    // conj(A~[j, i]) = e^{-ikr} (dn + i b): target j, source i with normal n_i;
+    // d = x_j - x_i = -(dx, dy, dz)
     const double dn = -(dx * xi[3] + dy * xi[4] + dz * xi[5]);
     const double b = kr * dn + g.eta * r2;
-    f = sp[6][jj] * (ir * ir * ir);
+    f = ir * ir * ir;
     A = c * dn + s * b;
     B = c * b - s * dn;
+    quad = (4 - quad) & 3;
   } else if (OP == 2) {
+    // e^{ikr} a
     const double dn = dx * sp[3][jj] + dy * sp[4][jj] + dz * sp[5][jj];
     const double a = g.k * dn + g.eta * r;
-    f = sp[6][jj] * ir;
+    f = ir;
     A = c * a;
     B = s * a;
   } else {
-    f = sp[6][jj] * ir;
+    // -i e^{ikr}
+    f = ir;
     A = s;
     B = -c;
   }
+  if (FAST) rotate_quadrant(quad, A, B);
   const zd xv = sx[jj];
   const double xr = xv.re * f, xm = xv.im * f;
   are = fma(A, xr, are);
@@ -390,7 +419,7 @@ __device__ inline void matvec_pair(const DevGeom& g, const double (&xi)[6], cons
 template <int OP, bool FAST>
 __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __restrict__ x, zd* __restrict__ part,
                                                      int64_t slice) {
-  __shared__ double sp[7][256];
+  __shared__ double sp[6][256];
   __shared__ zd sx[256];
   const int64_t n = g.n;
   const double* p = g.p;
@@ -405,8 +434,13 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __rest
     __syncthreads();
     const int64_t jl = j0 + threadIdx.x;
     for (int a = 0; a < 6; ++a) sp[a][threadIdx.x] = jl < jend ? p[a * n + jl] : 0.0;
-    sp[6][threadIdx.x] = jl < jend ? p[6 * n + jl] * kInv4Pi : 0.0;
-    sx[threadIdx.x] = jl < jend ? x[jl] : zd{0.0, 0.0};
+    if (jl < jend) {
+      const zd xj = x[jl];
+      const double wj = p[6 * n + jl] * kInv4Pi;
+      sx[threadIdx.x] = zd{xj.re * wj, xj.im * wj};
+    } else {
+      sx[threadIdx.x] = zd{0.0, 0.0};
+    }
     __syncthreads();
     const int cnt = (int)min<int64_t>(256, jend - j0);
     if (!live) continue;
@@ -414,8 +448,9 @@ __global__ void __launch_bounds__(256) matvec_kernel(DevGeom g, const zd* __rest
       for (int jj = 0; jj < cnt; ++jj) {
         if (jj == (int)threadIdx.x) {
           if (OP <= 1) {
-            dre = 0.5 * sx[jj].re;
-            dim = 0.5 * sx[jj].im;
+            const zd xd = x[i];  // sx holds the weighted values
+            dre = 0.5 * xd.re;
+            dim = 0.5 * xd.im;
           }
           continue;
         }
