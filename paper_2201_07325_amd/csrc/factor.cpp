@@ -29,6 +29,7 @@
 #include "tune.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -1328,43 +1329,80 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
   if (opts.corr_row_ptr) {
     std::vector<int64_t> pos(n);
     for (int64_t p = 0; p < n; ++p) pos[order[p]] = p;
-    std::vector<std::vector<std::pair<int32_t, double>>> byrow(n), bycol(n);
+    // tree-order CSR by row and by column: counts, offsets, one scatter, then every segment
+    // sorted on the host workers; a position's partners merge its two sorted segments
+    std::vector<int64_t> rptr(n + 1, 0), cptr(n + 1, 0);
     for (int64_t i = 0; i < n; ++i)
       for (int64_t e = opts.corr_row_ptr[i]; e < opts.corr_row_ptr[i + 1]; ++e) {
         const int64_t j = opts.corr_col[e];
         if (j == i) continue;  // the diagonal is 1/2, not a quadrature entry
-        byrow[pos[i]].emplace_back((int32_t)pos[j], opts.corr_a[e]);
-        bycol[pos[j]].emplace_back((int32_t)pos[i], opts.corr_a[e]);
+        ++rptr[pos[i] + 1];
+        ++cptr[pos[j] + 1];
       }
-    std::vector<int64_t> rptr(n + 1, 0), cptr(n + 1, 0);
-    std::vector<int32_t> rcol, crow;
-    std::vector<double> ra, ca;
-    adj_ptr.assign(n + 1, 0);
     for (int64_t p = 0; p < n; ++p) {
-      auto& r = byrow[p];
-      std::sort(r.begin(), r.end());
-      for (size_t q = 0; q < r.size(); ++q) {
-        if (q > 0 && r[q].first == r[q - 1].first)
-          throw Error(FMMLU_EINVAL, "correction table lists a pair twice");
-        rcol.push_back(r[q].first);
-        ra.push_back(r[q].second);
-      }
-      rptr[p + 1] = (int64_t)rcol.size();
-      auto& c = bycol[p];
-      std::sort(c.begin(), c.end());
-      for (auto& v : c) {
-        crow.push_back(v.first);
-        ca.push_back(v.second);
-      }
-      cptr[p + 1] = (int64_t)crow.size();
-      std::vector<int32_t> part;
-      for (auto& v : r) part.push_back(v.first);
-      for (auto& v : c) part.push_back(v.first);
-      std::sort(part.begin(), part.end());
-      part.erase(std::unique(part.begin(), part.end()), part.end());
-      adj.insert(adj.end(), part.begin(), part.end());
-      adj_ptr[p + 1] = (int64_t)adj.size();
+      rptr[p + 1] += rptr[p];
+      cptr[p + 1] += cptr[p];
     }
+    const int64_t nnz = rptr[n];
+    std::vector<std::pair<int32_t, double>> rv((size_t)nnz), cv((size_t)nnz);
+    {
+      std::vector<int64_t> rf(rptr.begin(), rptr.end() - 1), cf(cptr.begin(), cptr.end() - 1);
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t pi = pos[i];
+        for (int64_t e = opts.corr_row_ptr[i]; e < opts.corr_row_ptr[i + 1]; ++e) {
+          const int64_t j = opts.corr_col[e];
+          if (j == i) continue;
+          const int64_t pj = pos[j];
+          rv[(size_t)rf[pi]++] = {(int32_t)pj, opts.corr_a[e]};
+          cv[(size_t)cf[pj]++] = {(int32_t)pi, opts.corr_a[e]};
+        }
+      }
+    }
+    std::vector<int32_t> rcol((size_t)nnz), crow((size_t)nnz);
+    std::vector<double> ra((size_t)nnz), ca((size_t)nnz);
+    adj_ptr.assign(n + 1, 0);
+    std::atomic<bool> twice{false};
+    // position p's partners in either direction, ascending without repeats (counted only
+    // when out is null)
+    auto partners = [&](int64_t p, int32_t* out) {
+      auto r = rv.cbegin() + rptr[p], re = rv.cbegin() + rptr[p + 1];
+      auto c = cv.cbegin() + cptr[p], ce = cv.cbegin() + cptr[p + 1];
+      int64_t k = 0;
+      int32_t last = -1;
+      while (r != re || c != ce) {
+        const int32_t v = (c == ce || (r != re && r->first <= c->first)) ? (r++)->first : (c++)->first;
+        if (k == 0 || v != last) {
+          if (out) out[k] = v;
+          ++k;
+          last = v;
+        }
+      }
+      return k;
+    };
+    hp.ranges((int)n, 512, [&](int lo, int hi) {
+      for (int64_t p = lo; p < hi; ++p) {
+        const auto rb = rv.begin() + rptr[p], re = rv.begin() + rptr[p + 1];
+        const auto cb = cv.begin() + cptr[p], ce = cv.begin() + cptr[p + 1];
+        std::sort(rb, re);
+        std::sort(cb, ce);
+        for (auto it = rb; it != re; ++it) {
+          if (it != rb && it->first == (it - 1)->first) twice = true;
+          rcol[(size_t)(it - rv.begin())] = it->first;
+          ra[(size_t)(it - rv.begin())] = it->second;
+        }
+        for (auto it = cb; it != ce; ++it) {
+          crow[(size_t)(it - cv.begin())] = it->first;
+          ca[(size_t)(it - cv.begin())] = it->second;
+        }
+        adj_ptr[p + 1] = partners(p, nullptr);
+      }
+    });
+    if (twice) throw Error(FMMLU_EINVAL, "correction table lists a pair twice");
+    for (int64_t p = 0; p < n; ++p) adj_ptr[p + 1] += adj_ptr[p];
+    adj.resize((size_t)adj_ptr[n]);
+    hp.ranges((int)n, 512, [&](int lo, int hi) {
+      for (int64_t p = lo; p < hi; ++p) partners(p, adj.data() + adj_ptr[p]);
+    });
     g.corr.rptr = sg.up_to(arena, rptr);
     g.corr.rcol = sg.up_to(arena, rcol);
     g.corr.ra = sg.up_to(arena, ra);
