@@ -1700,10 +1700,30 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
     int64_t* act_dev = sg.up_to(level_arena, act_cat);
     // owner of every position active at this level (spill-over rule)
     std::vector<int32_t> owner_of;
+    // spill-over candidates of each owner processed at this level: (owner q, position p) for
+    // every partner p of one of its positions whose owner q lies beyond the stored pairs
+    // (gap of two units or more). Owners, their positions and their boxes stay fixed through
+    // the level; whether p is still active is decided when the owner's phase is planned.
+    std::vector<std::vector<std::pair<int, int32_t>>> spill_cand;
     if (!adj_ptr.empty()) {
       owner_of.assign((size_t)n, -1);
       for (int i = 0; i < nown; ++i)
         for (int64_t a : own[i].act) owner_of[(size_t)a] = i;
+      spill_cand.assign((size_t)nown, {});
+      hp.ranges(nown, 16, [&](int lo, int hi) {
+        for (int i = lo; i < hi; ++i) {
+          const Owner& B = own[i];
+          if (B.level != lev) continue;
+          auto& out = spill_cand[(size_t)i];
+          for (int64_t a : B.act)
+            for (int64_t e = adj_ptr[a]; e < adj_ptr[a + 1]; ++e) {
+              const int32_t p = adj[e];
+              const int q = owner_of[p];
+              if (q < 0 || q == i) continue;
+              if (gap_units(B, own[q]) >= 2) out.emplace_back(q, p);
+            }
+        }
+      });
     }
 
     // ---- processed boxes by colour, Morton order within a colour
@@ -1763,13 +1783,8 @@ void FactorImpl::factor(const Octree& tree, const double* xyz, const double* nrm
         // quadrature correction joins Q; its rows are generated (corrected kernel values)
         if (!adj_ptr.empty()) {
           std::vector<int> sp;
-          for (int64_t a : B.act)
-            for (int64_t e = adj_ptr[a]; e < adj_ptr[a + 1]; ++e) {
-              const int32_t p = adj[e];
-              const int q = owner_of[p];
-              if (q < 0 || q == oi || !pos_live[p]) continue;
-              if (gap_units(B, own[q]) >= 2) sp.push_back(q);
-            }
+          for (const auto& cq : spill_cand[(size_t)oi])
+            if (pos_live[(size_t)cq.second]) sp.push_back(cq.first);
           std::sort(sp.begin(), sp.end());
           sp.erase(std::unique(sp.begin(), sp.end()), sp.end());
           for (int q : sp) {
