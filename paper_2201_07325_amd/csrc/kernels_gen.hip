@@ -35,17 +35,18 @@ __device__ inline double rsqrt_pos(double x) {
   return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
-// sin x and cos x for the kernel phase x = k r (|x| < 2^20; the library's routine beyond):
-// Cody-Waite reduction by pi/2 with fused multiply-adds (x - q hi exact to one rounding, then
-// the tail lo of pi/2) to |y| <= pi/4, then the Taylor series of sin to y^15 and of cos to
-// y^16 (truncation below 7e-17 relative on that interval), and the quadrant q mod 4.
-// Both series are sums over powers of z = y^2 formed once and shared: each term is one
-// multiply-add of a coefficient and a ready power, smallest term first, so no step waits
-// on a chain of products and no coefficient has to be copied into an accumulator.
-constexpr double kPhaseFast = 1048576.0;  // |x| below which the reduction below is used
+// Sine and cosine of the kernel phase x = k r. Below kPhaseFast: Cody-Waite reduction by
+// pi/2 with fused multiply-adds (x - q hi exact to one rounding, then the tail lo of pi/2) to
+// |y| <= pi/4, the Taylor series of sin to y^15 and of cos to y^16 (truncation below 7e-17
+// relative on that interval), and the quadrant q mod 4. Both series are sums over the powers
+// of z = y^2, formed once and shared: each term is one multiply-add of a coefficient and a
+// ready power, smallest term first, so no coefficient has to be copied into an accumulator
+// register first (as the addend of a Horner step would be). At or beyond kPhaseFast
+// sincos_phase calls the library's routine.
+constexpr double kPhaseFast = 1048576.0;
 
-// sin y and cos y of the reduced argument y = x - q pi/2, |y| <= pi/4, and q mod 4 (returned),
-// so that e^{ix} = i^q (cos y + i sin y).
+// sin y and cos y of the reduced argument y = x - q pi/2, and q mod 4 (returned), so that
+// e^{ix} = i^q (cos y + i sin y); |x| < kPhaseFast.
 __device__ inline int sincos_phase_quadrant(double x, double* sy_out, double* cy_out) {
   constexpr double kTwoOverPi = 0.63661977236758134308;
   constexpr double kPio2Hi = 1.5707963267948965580;   // nearest double to pi/2
@@ -79,6 +80,7 @@ __device__ inline int sincos_phase_quadrant(double x, double* sy_out, double* cy
   return (int)q & 3;  // |q| < 2^20: exact in an int
 }
 
+// sin x and cos x for |x| < kPhaseFast
 __device__ inline void sincos_phase_reduced(double x, double* sn, double* cs) {
   double sy, cy;
   const int quad = sincos_phase_quadrant(x, &sy, &cy);
